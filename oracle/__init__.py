@@ -1,0 +1,184 @@
+"""FP64 CPU oracle for the forward lensing model -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package. The product library never calls it and shares no code
+with it.
+
+Functions follow Tessore, Bellagamba & Metcalf (MNRAS 2016):
+lens equation Sec. 2.1 Eq. (1); surface brightness Eq. (2); pixel luminosity
+Eq. (3) by midpoint subsampling (Sec. 3.1 Eq. (14), Sec. 4.5 "subN" rules);
+PSF convolution with replicate padding Sec. 3.1 Eq. (15); log-likelihood
+Sec. 3.2 Eq. (17); Sersic profile Sec. 4.1 Eqs. (22)-(23); SIE lens Sec. 4.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB, build
+
+NPAR = 17
+
+_lib = None
+
+
+class LoSystem(ctypes.Structure):
+    _fields_ = [
+        ("height", ctypes.c_int32), ("width", ctypes.c_int32),
+        ("pixscale", ctypes.c_double),
+        ("center_x", ctypes.c_double), ("center_y", ctypes.c_double),
+        ("nsub", ctypes.c_int32),
+        ("psf_h", ctypes.c_int32), ("psf_w", ctypes.c_int32),
+        ("psf", ctypes.POINTER(ctypes.c_double)),
+        ("data", ctypes.POINTER(ctypes.c_double)),
+        ("weight", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        d, i, dp = ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+        sp = ctypes.POINTER(LoSystem)
+        for name, res, args in [
+            ("lo_param_count", i, []),
+            ("lo_digamma", d, [d]),
+            ("lo_gamma_p", d, [d, d]),
+            ("lo_bn", d, [d]),
+            ("lo_bn_deriv", d, [d]),
+            ("lo_sie_deflection", None, [d, d, d, d, d, dp, dp]),
+            ("lo_shear_deflection", None, [d, d, d, d, dp, dp]),
+            ("lo_sersic", d, [d] * 9),
+            ("lo_surface_brightness", d, [dp, d, d]),
+            ("lo_surface_brightness_grad", d, [dp, d, d, dp]),
+            ("lo_sum_compensated", d, [dp, ctypes.c_int64]),
+            ("lo_render", i, [sp, dp, i, dp]),
+            ("lo_psf_convolve", i, [i, i, dp, i, i, dp, dp]),
+            ("lo_loglike", d, [sp, dp]),
+            ("lo_loglike_grad", d, [sp, dp, dp]),
+        ]:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class System:
+    """Host-side description of one observation for the oracle.
+
+    All arrays are converted to float64 copies; values the GPU sees in float32
+    should be passed already rounded to float32 so both sides read the same numbers.
+    """
+
+    def __init__(self, height, width, pixscale, nsub, psf, data=None, weight=None,
+                 center_x=0.0, center_y=0.0):
+        self.height, self.width = int(height), int(width)
+        self.pixscale = float(pixscale)
+        self.center_x, self.center_y = float(center_x), float(center_y)
+        self.nsub = int(nsub)
+        self.psf = np.ascontiguousarray(np.asarray(psf, dtype=np.float64))
+        n = self.height * self.width
+        self.data = np.ascontiguousarray(np.zeros(n) if data is None else np.asarray(data, np.float64).reshape(-1))
+        self.weight = np.ascontiguousarray(np.ones(n) if weight is None else np.asarray(weight, np.float64).reshape(-1))
+        self._s = LoSystem(self.height, self.width, self.pixscale, self.center_x, self.center_y,
+                           self.nsub, self.psf.shape[0], self.psf.shape[1],
+                           _dp(self.psf), _dp(self.data), _dp(self.weight))
+
+    @property
+    def ptr(self):
+        return ctypes.byref(self._s)
+
+
+def _theta(theta):
+    t = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+    assert t.size == NPAR
+    return t
+
+
+def bn(n):
+    """b_n with P(2n, b_n) = 1/2 (half-light normalisation of Eq. 22)."""
+    return lib().lo_bn(float(n))
+
+
+def bn_deriv(n):
+    return lib().lo_bn_deriv(float(n))
+
+
+def digamma(z):
+    return lib().lo_digamma(float(z))
+
+
+def gamma_p(a, x):
+    return lib().lo_gamma_p(float(a), float(x))
+
+
+def sie_deflection(theta_e, q, phi, x, y):
+    ax, ay = ctypes.c_double(), ctypes.c_double()
+    lib().lo_sie_deflection(theta_e, q, phi, x, y, ctypes.byref(ax), ctypes.byref(ay))
+    return ax.value, ay.value
+
+
+def shear_deflection(gamma, phi, x, y):
+    ax, ay = ctypes.c_double(), ctypes.c_double()
+    lib().lo_shear_deflection(gamma, phi, x, y, ctypes.byref(ax), ctypes.byref(ay))
+    return ax.value, ay.value
+
+
+def sersic(x, y, x0, y0, Ie, Re, n, q, phi):
+    return lib().lo_sersic(x, y, x0, y0, Ie, Re, n, q, phi)
+
+
+def surface_brightness(theta, x, y):
+    t = _theta(theta)
+    return lib().lo_surface_brightness(_dp(t), float(x), float(y))
+
+
+def surface_brightness_grad(theta, x, y):
+    t = _theta(theta)
+    g = np.zeros(NPAR)
+    v = lib().lo_surface_brightness_grad(_dp(t), float(x), float(y), _dp(g))
+    return v, g
+
+
+def sum_compensated(x):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+    return lib().lo_sum_compensated(_dp(a), a.size)
+
+
+def render(system, theta, apply_psf=True):
+    t = _theta(theta)
+    out = np.empty(system.height * system.width)
+    rc = lib().lo_render(system.ptr, _dp(t), int(bool(apply_psf)), _dp(out))
+    if rc != 0:
+        raise ValueError("oracle render: invalid system")
+    return out.reshape(system.height, system.width)
+
+
+def psf_convolve(image, psf):
+    img = np.ascontiguousarray(np.asarray(image, dtype=np.float64))
+    F = np.ascontiguousarray(np.asarray(psf, dtype=np.float64))
+    out = np.empty_like(img)
+    rc = lib().lo_psf_convolve(img.shape[0], img.shape[1], _dp(img), F.shape[0], F.shape[1], _dp(F), _dp(out))
+    if rc != 0:
+        raise ValueError("oracle psf_convolve: invalid arguments")
+    return out
+
+
+def loglike(system, theta):
+    t = _theta(theta)
+    return lib().lo_loglike(system.ptr, _dp(t))
+
+
+def loglike_grad(system, theta):
+    t = _theta(theta)
+    g = np.zeros(NPAR)
+    v = lib().lo_loglike_grad(system.ptr, _dp(t), _dp(g))
+    return v, g

@@ -1,0 +1,455 @@
+// lensed_oracle.cpp -- TEST INFRASTRUCTURE, not part of the product.
+//
+// A plain, serial, double-precision CPU implementation of the forward model and
+// likelihood of Tessore, Bellagamba & Metcalf, "LENSED: a code for the forward
+// reconstruction of lenses and sources from strong lensing observations"
+// (MNRAS 2016). It exists only to check the GPU library: the test-suite, the
+// smoke check and the CPU-baseline leg of the benchmark may load it; nothing in
+// the product path may. It shares no code with the GPU library.
+//
+// Every step is written as its definition, with no blocking, fusion or reordering:
+//   lens equation                      Sec. 2.1, Eq. (1)
+//   image-plane surface brightness     Sec. 2.1, Eq. (2)
+//   pixel luminosity and quadrature    Sec. 2.1 Eq. (3), Sec. 3.1 Eq. (14); N x N
+//                                      midpoint subsampling (the "subN" rules, Sec. 4.5)
+//   PSF convolution, replicate padding Sec. 3.1, Eq. (15)
+//   log-likelihood with weights        Sec. 3.2, Eq. (17)
+//   Sersic profile, geometric radius   Sec. 4.1, Eqs. (22)-(23)
+//   singular isothermal ellipsoid      Sec. 4 (Kormann et al. 1994; formula not printed
+//                                      in the paper, area-preserving convention)
+//   external shear                     Sec. 5 / Table 4 (formula not printed)
+//
+// The gradient of the log-likelihood is obtained by running the very same
+// templated code on forward-mode dual numbers carrying 17 partial derivatives.
+//
+// Parameter vector (17 values), lens centred on the coordinate origin:
+//   0 theta_E  1 q_L  2 phi_L  3 gamma  4 phi_gamma
+//   5 I_H  6 R_H  7 n_H  8 q_H  9 phi_H                       (lens light at the origin)
+//  10 x_S 11 y_S 12 I_S 13 R_S 14 n_S 15 q_S 16 phi_S          (source)
+// Angles are counter-clockwise from +x to the major axis (Sec. 4).
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+namespace {
+
+constexpr int NPAR = 17;
+constexpr double PI = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Forward-mode dual number: value and the 17 partial derivatives.
+// ---------------------------------------------------------------------------
+struct Dual {
+  double v;
+  double d[NPAR];
+  Dual() : v(0) { for (int i = 0; i < NPAR; ++i) d[i] = 0; }
+  Dual(double x) : v(x) { for (int i = 0; i < NPAR; ++i) d[i] = 0; }
+  static Dual var(double x, int k) { Dual r(x); r.d[k] = 1; return r; }
+};
+
+inline double value(double x) { return x; }
+inline double value(const Dual& x) { return x.v; }
+
+// chain rule helper: f(a) with f'(a) = fp
+inline Dual chain(const Dual& a, double f, double fp) {
+  Dual r(f);
+  for (int i = 0; i < NPAR; ++i) r.d[i] = fp * a.d[i];
+  return r;
+}
+
+inline Dual operator+(const Dual& a, const Dual& b) {
+  Dual r(a.v + b.v); for (int i = 0; i < NPAR; ++i) r.d[i] = a.d[i] + b.d[i]; return r;
+}
+inline Dual operator-(const Dual& a, const Dual& b) {
+  Dual r(a.v - b.v); for (int i = 0; i < NPAR; ++i) r.d[i] = a.d[i] - b.d[i]; return r;
+}
+inline Dual operator-(const Dual& a) {
+  Dual r(-a.v); for (int i = 0; i < NPAR; ++i) r.d[i] = -a.d[i]; return r;
+}
+inline Dual operator*(const Dual& a, const Dual& b) {
+  Dual r(a.v * b.v); for (int i = 0; i < NPAR; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i]; return r;
+}
+inline Dual operator/(const Dual& a, const Dual& b) {
+  Dual r(a.v / b.v);
+  for (int i = 0; i < NPAR; ++i) r.d[i] = (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v);
+  return r;
+}
+inline Dual operator+(const Dual& a, double b) { return a + Dual(b); }
+inline Dual operator+(double a, const Dual& b) { return Dual(a) + b; }
+inline Dual operator-(const Dual& a, double b) { return a - Dual(b); }
+inline Dual operator-(double a, const Dual& b) { return Dual(a) - b; }
+inline Dual operator*(const Dual& a, double b) { return a * Dual(b); }
+inline Dual operator*(double a, const Dual& b) { return Dual(a) * b; }
+inline Dual operator/(const Dual& a, double b) { return a / Dual(b); }
+inline Dual operator/(double a, const Dual& b) { return Dual(a) / b; }
+
+inline Dual sqrt(const Dual& a) { double s = std::sqrt(a.v); return chain(a, s, 0.5 / s); }
+inline Dual exp(const Dual& a) { double e = std::exp(a.v); return chain(a, e, e); }
+inline Dual log(const Dual& a) { return chain(a, std::log(a.v), 1.0 / a.v); }
+inline Dual sin(const Dual& a) { return chain(a, std::sin(a.v), std::cos(a.v)); }
+inline Dual cos(const Dual& a) { return chain(a, std::cos(a.v), -std::sin(a.v)); }
+inline Dual atan(const Dual& a) { return chain(a, std::atan(a.v), 1.0 / (1.0 + a.v * a.v)); }
+inline Dual atanh(const Dual& a) { return chain(a, std::atanh(a.v), 1.0 / (1.0 - a.v * a.v)); }
+
+// ---------------------------------------------------------------------------
+// Special functions used by the Sersic normalisation b_n.
+// ---------------------------------------------------------------------------
+
+// Digamma psi(z), z > 0: upward recurrence psi(z) = psi(z+1) - 1/z until z >= 10,
+// then the asymptotic series of Abramowitz & Stegun 6.3.18.
+double digamma(double z) {
+  double acc = 0.0;
+  while (z < 10.0) { acc -= 1.0 / z; z += 1.0; }
+  const double z2 = 1.0 / (z * z);
+  // B2/2 = 1/12, B4/4 = -1/120, B6/6 = 1/252, B8/8 = -1/240, B10/10 = 1/132, B12/12 = -691/32760
+  const double series = z2 * (1.0 / 12 - z2 * (1.0 / 120 - z2 * (1.0 / 252 - z2 * (1.0 / 240 - z2 * (1.0 / 132 - z2 * (691.0 / 32760))))));
+  return acc + std::log(z) - 0.5 / z - series;
+}
+
+// Regularised lower incomplete gamma function P(a, x) by its power series
+//   P(a,x) = e^{-x} x^a / Gamma(a+1) * sum_{k>=0} x^k / ((a+1)(a+2)...(a+k)).
+// Also returns dP/da through the term-wise derivative
+//   d/da log(term_k) = log x - psi(a+1) - sum_{j=1..k} 1/(a+j).
+double gamma_p_series(double a, double x, double* dP_da) {
+  if (x <= 0.0) { if (dP_da) *dP_da = 0.0; return 0.0; }
+  const double pref = std::exp(-x + a * std::log(x) - std::lgamma(a + 1.0));
+  const double lx = std::log(x), psi1 = digamma(a + 1.0);
+  double term = 1.0, sum = 1.0;          // term_k / pref
+  double hsum = 0.0;                     // sum_{j=1..k} 1/(a+j)
+  double dsum = (lx - psi1);             // sum_k term_k * dlog(term_k)/da
+  for (int k = 1; k < 100000; ++k) {
+    term *= x / (a + k);
+    hsum += 1.0 / (a + k);
+    sum += term;
+    dsum += term * (lx - psi1 - hsum);
+    if (term < 1e-18 * sum) break;
+  }
+  if (dP_da) *dP_da = pref * dsum;
+  return pref * sum;
+}
+
+// b_n: the root of P(2n, b) = 1/2, i.e. the constant that makes R_e the
+// half-light radius of the Sersic profile (Sec. 4.1, Eq. 22). Newton's method on
+// the series above, safeguarded by bisection, started from the leading terms of
+// the Ciotti & Bertin (1999) asymptotic expansion.
+double bn_exact(double n) {
+  const double a = 2.0 * n;
+  double lo = 0.0, hi = a + 20.0 + 10.0 * std::sqrt(a);
+  double b = 2.0 * n - 1.0 / 3.0 + 4.0 / (405.0 * n) + 46.0 / (25515.0 * n * n);
+  if (!(b > lo && b < hi)) b = 0.5 * (lo + hi);
+  for (int it = 0; it < 200; ++it) {
+    const double f = gamma_p_series(a, b, nullptr) - 0.5;
+    if (f < 0) lo = b; else hi = b;
+    const double fp = std::exp((a - 1.0) * std::log(b) - b - std::lgamma(a));
+    double bn = b - f / fp;
+    if (!(bn > lo && bn < hi)) bn = 0.5 * (lo + hi);
+    const double step = std::fabs(bn - b);
+    b = bn;
+    if (step <= 1e-15 * b) break;
+  }
+  return b;
+}
+
+// db_n/dn by implicit differentiation of P(2n, b_n) = 1/2:
+//   2 dP/da + dP/dx * db/dn = 0,  dP/dx = x^{a-1} e^{-x} / Gamma(a).
+double bn_derivative(double n, double b) {
+  const double a = 2.0 * n;
+  double dPda = 0.0;
+  gamma_p_series(a, b, &dPda);
+  const double dPdx = std::exp((a - 1.0) * std::log(b) - b - std::lgamma(a));
+  return -2.0 * dPda / dPdx;
+}
+
+inline double bn_of(double n) { return bn_exact(n); }
+inline Dual bn_of(const Dual& n) {
+  const double b = bn_exact(n.v);
+  return chain(n, b, bn_derivative(n.v, b));
+}
+
+// ---------------------------------------------------------------------------
+// Model components.
+// ---------------------------------------------------------------------------
+
+// atan(sqrt(s) u)/sqrt(s) and atanh(sqrt(s) v)/sqrt(s) with s = q'^2 = 1 - q^2.
+// For small s the Taylor series in s is used, which is smooth through s = 0 (the
+// singular isothermal sphere); the two forms agree to rounding at the switch.
+template <class T> T atan_over(T s, T u) {
+  using std::atan; using std::sqrt;
+  if (value(s) >= 1e-4) { T r = sqrt(s); return atan(r * u) / r; }
+  T z = s * u * u, acc = T(0.0), pw = T(1.0);
+  for (int k = 0; k < 12; ++k) { acc = acc + pw / double(2 * k + 1); pw = pw * (-1.0) * z; }
+  return u * acc;
+}
+template <class T> T atanh_over(T s, T v) {
+  using std::atanh; using std::sqrt;
+  if (value(s) >= 1e-4) { T r = sqrt(s); return atanh(r * v) / r; }
+  T z = s * v * v, acc = T(0.0), pw = T(1.0);
+  for (int k = 0; k < 12; ++k) { acc = acc + pw / double(2 * k + 1); pw = pw * z; }
+  return v * acc;
+}
+
+// Deflection of a singular isothermal ellipsoid centred on the origin, with
+// convergence kappa = theta_E / (2 sqrt(q x'^2 + y'^2/q)) in the frame rotated by
+// phi (counter-clockwise from +x to the major axis):
+//   psi = sqrt(q^2 x'^2 + y'^2),  q' = sqrt(1 - q^2)
+//   alpha'_x = theta_E sqrt(q)/q' atan(q' x'/psi),  alpha'_y = theta_E sqrt(q)/q' atanh(q' y'/psi)
+// rotated back to the image frame. At psi = 0 the deflection is set to zero.
+template <class T> void sie_deflection(T te, T q, T phi, T x, T y, T& ax, T& ay) {
+  using std::cos; using std::sin; using std::sqrt;
+  const T c = cos(phi), s = sin(phi);
+  const T xp = c * x + s * y, yp = -s * x + c * y;
+  const T psi = sqrt(q * q * xp * xp + yp * yp);
+  if (value(psi) == 0.0) { ax = T(0.0); ay = T(0.0); return; }
+  const T s2 = 1.0 - q * q;
+  const T k = te * sqrt(q);
+  const T axp = k * atan_over(s2, xp / psi);
+  const T ayp = k * atanh_over(s2, yp / psi);
+  ax = c * axp - s * ayp;
+  ay = s * axp + c * ayp;
+}
+
+// External shear about the lens centre: gamma_1 = gamma cos(2 phi), gamma_2 = gamma sin(2 phi),
+// alpha = (gamma_1 x + gamma_2 y, gamma_2 x - gamma_1 y).
+template <class T> void shear_deflection(T g, T phi, T x, T y, T& ax, T& ay) {
+  using std::cos; using std::sin;
+  const T g1 = g * cos(2.0 * phi), g2 = g * sin(2.0 * phi);
+  ax = g1 * x + g2 * y;
+  ay = g2 * x - g1 * y;
+}
+
+// Elliptical Sersic profile (Sec. 4.1, Eqs. 22-23), amplitude I_e at the
+// half-light "radius" R_e, centred on (x0, y0) and rotated by phi:
+//   R = sqrt(q x'^2 + y'^2/q),  I = I_e exp(-b_n [(R/R_e)^{1/n} - 1]).
+template <class T> T sersic(T x, T y, T x0, T y0, T Ie, T Re, T n, T q, T phi) {
+  using std::cos; using std::sin; using std::sqrt; using std::exp; using std::log;
+  const T dx = x - x0, dy = y - y0;
+  const T c = cos(phi), s = sin(phi);
+  const T xp = c * dx + s * dy, yp = -s * dx + c * dy;
+  const T R2 = q * xp * xp + yp * yp / q;
+  const T b = bn_of(n);
+  if (value(R2) == 0.0) return Ie * exp(b);
+  const T R = sqrt(R2);
+  const T t = exp(log(R / Re) / n);   // (R/R_e)^{1/n}
+  return Ie * exp(-b * (t - 1.0));
+}
+
+template <class T> struct Params {
+  T p[NPAR];
+};
+
+// Surface brightness of the image plane at x (Eq. 2): lens light at x plus the
+// source at the position given by the lens equation (Eq. 1).
+template <class T> T surface_brightness(const Params<T>& P, T x, T y) {
+  const T* p = P.p;
+  T ax, ay, gx, gy;
+  sie_deflection(p[0], p[1], p[2], x, y, ax, ay);
+  shear_deflection(p[3], p[4], x, y, gx, gy);
+  const T bx = x - ax - gx, by = y - ay - gy;
+  const T zero(0.0);
+  const T lens = sersic(x, y, zero, zero, p[5], p[6], p[7], p[8], p[9]);
+  const T src = sersic(bx, by, p[10], p[11], p[12], p[13], p[14], p[15], p[16]);
+  return lens + src;
+}
+
+bool params_valid(const double* th) {
+  for (int i = 0; i < NPAR; ++i) if (!std::isfinite(th[i])) return false;
+  const double qs[3] = {th[1], th[8], th[15]};
+  for (double q : qs) if (!(q > 0.0 && q <= 1.0)) return false;
+  if (!(th[6] > 0.0) || !(th[13] > 0.0)) return false;
+  if (!(th[7] >= 0.2 && th[7] <= 10.0) || !(th[14] >= 0.2 && th[14] <= 10.0)) return false;
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI for the Python tests.
+// ---------------------------------------------------------------------------
+extern "C" {
+
+typedef struct {
+  int32_t height, width;     // pixels; row-major [height][width], row 0 = smallest y
+  double pixscale;           // arcsec per pixel
+  double center_x, center_y; // image-plane coordinates of the grid centre
+  int32_t nsub;              // N of the N x N midpoint rule
+  int32_t psf_h, psf_w;      // odd PSF dimensions
+  const double* psf;         // [psf_h * psf_w], normalised here to unit sum
+  const double* data;        // [height * width]
+  const double* weight;      // [height * width], 1/s^2, 0 = masked
+} lo_system;
+
+int lo_param_count(void) { return NPAR; }
+double lo_digamma(double z) { return digamma(z); }
+double lo_gamma_p(double a, double x) { return gamma_p_series(a, x, nullptr); }
+double lo_bn(double n) { return bn_exact(n); }
+double lo_bn_deriv(double n) { return bn_derivative(n, bn_exact(n)); }
+
+void lo_sie_deflection(double te, double q, double phi, double x, double y, double* ax, double* ay) {
+  sie_deflection<double>(te, q, phi, x, y, *ax, *ay);
+}
+void lo_shear_deflection(double g, double phi, double x, double y, double* ax, double* ay) {
+  shear_deflection<double>(g, phi, x, y, *ax, *ay);
+}
+double lo_sersic(double x, double y, double x0, double y0, double Ie, double Re, double n, double q, double phi) {
+  return sersic<double>(x, y, x0, y0, Ie, Re, n, q, phi);
+}
+double lo_surface_brightness(const double* theta, double x, double y) {
+  if (!params_valid(theta)) return std::numeric_limits<double>::quiet_NaN();
+  Params<double> P; for (int i = 0; i < NPAR; ++i) P.p[i] = theta[i];
+  return surface_brightness(P, x, y);
+}
+
+// Neumaier's compensated summation.
+double lo_sum_compensated(const double* x, int64_t n) {
+  double s = 0.0, c = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double t = s + x[i];
+    if (std::fabs(s) >= std::fabs(x[i])) c += (s - t) + x[i]; else c += (x[i] - t) + s;
+    s = t;
+  }
+  return s + c;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Pixel luminosities (Eq. 3) by the N x N midpoint product rule (Eq. 14): the
+// abscissae of pixel (r, c) are
+//   x = center_x + (c - (W-1)/2 + (kx + 1/2)/N - 1/2) * pixscale,
+//   y = center_y + (r - (H-1)/2 + (ky + 1/2)/N - 1/2) * pixscale,
+// each with weight pixscale^2 / N^2.
+template <class T> void render_unconvolved(const lo_system& S, const Params<T>& P, std::vector<T>& L) {
+  const int H = S.height, W = S.width, N = S.nsub;
+  const double d = S.pixscale, wk = d * d / double(N * N);
+  L.assign(size_t(H) * W, T(0.0));
+  for (int r = 0; r < H; ++r)
+    for (int c = 0; c < W; ++c) {
+      T acc(0.0);
+      for (int ky = 0; ky < N; ++ky)
+        for (int kx = 0; kx < N; ++kx) {
+          const double x = S.center_x + (c - 0.5 * (W - 1) + (kx + 0.5) / N - 0.5) * d;
+          const double y = S.center_y + (r - 0.5 * (H - 1) + (ky + 0.5) / N - 0.5) * d;
+          acc = acc + surface_brightness(P, T(x), T(y));
+        }
+      L[size_t(r) * W + c] = acc * wk;
+    }
+}
+
+// Discrete PSF convolution (Eq. 15) with the kernel normalised to unit sum and
+// the image padded by repeating the closest pixel:
+//   L*_ij = sum_{k=-p..p} sum_{l=-q..q} F_{-k,-l} L_{clamp(i+k), clamp(j+l)},
+// F_{a,b} being the element at row offset a and column offset b from the centre.
+template <class T> void psf_convolve(int H, int W, const std::vector<T>& L, int ph, int pw, const double* psf,
+                                     std::vector<T>& out) {
+  const int p = ph / 2, q = pw / 2;
+  double tot = 0.0;
+  for (int i = 0; i < ph * pw; ++i) tot += psf[i];
+  out.assign(size_t(H) * W, T(0.0));
+  for (int i = 0; i < H; ++i)
+    for (int j = 0; j < W; ++j) {
+      T acc(0.0);
+      for (int k = -p; k <= p; ++k)
+        for (int l = -q; l <= q; ++l) {
+          const double F = psf[size_t(-k + p) * pw + (-l + q)] / tot;
+          const int ii = std::min(std::max(i + k, 0), H - 1);
+          const int jj = std::min(std::max(j + l, 0), W - 1);
+          acc = acc + F * L[size_t(ii) * W + jj];
+        }
+      out[size_t(i) * W + j] = acc;
+    }
+}
+
+bool system_valid(const lo_system* S) {
+  if (!S || S->height <= 0 || S->width <= 0 || S->nsub < 1) return false;
+  if (S->psf_h < 1 || S->psf_w < 1 || S->psf_h % 2 == 0 || S->psf_w % 2 == 0) return false;
+  return true;
+}
+
+template <class T> void model_image(const lo_system& S, const Params<T>& P, int apply_psf, std::vector<T>& out) {
+  std::vector<T> L;
+  render_unconvolved(S, P, L);
+  if (apply_psf && S.psf) psf_convolve(S.height, S.width, L, S.psf_h, S.psf_w, S.psf, out);
+  else out.swap(L);
+}
+
+}  // namespace
+
+extern "C" {
+
+// Model image: unconvolved pixel luminosities (apply_psf = 0) or their PSF
+// convolution (apply_psf != 0). Returns 0, or 1 for an invalid system; invalid
+// parameters fill the image with NaN.
+int lo_render(const lo_system* S, const double* theta, int apply_psf, double* out) {
+  if (!system_valid(S) || !theta || !out) return 1;
+  const size_t n = size_t(S->height) * S->width;
+  if (!params_valid(theta)) {
+    for (size_t i = 0; i < n; ++i) out[i] = std::numeric_limits<double>::quiet_NaN();
+    return 0;
+  }
+  Params<double> P; for (int i = 0; i < NPAR; ++i) P.p[i] = theta[i];
+  std::vector<double> img;
+  model_image(*S, P, apply_psf, img);
+  std::memcpy(out, img.data(), n * sizeof(double));
+  return 0;
+}
+
+// PSF convolution alone (Eq. 15), for pins of the stencil.
+int lo_psf_convolve(int H, int W, const double* L, int ph, int pw, const double* psf, double* out) {
+  if (H <= 0 || W <= 0 || ph % 2 == 0 || pw % 2 == 0 || ph < 1 || pw < 1) return 1;
+  std::vector<double> in(L, L + size_t(H) * W), res;
+  psf_convolve(H, W, in, ph, pw, psf, res);
+  std::memcpy(out, res.data(), res.size() * sizeof(double));
+  return 0;
+}
+
+// chi^2 = sum_i w_i (d_i - L*_i)^2 summed with compensation; log L = -chi^2 / 2 (Eq. 17).
+double lo_loglike(const lo_system* S, const double* theta) {
+  if (!system_valid(S) || !theta || !S->data || !S->weight) return std::numeric_limits<double>::quiet_NaN();
+  if (!params_valid(theta)) return std::numeric_limits<double>::quiet_NaN();
+  Params<double> P; for (int i = 0; i < NPAR; ++i) P.p[i] = theta[i];
+  std::vector<double> img;
+  model_image(*S, P, 1, img);
+  std::vector<double> terms(img.size());
+  for (size_t i = 0; i < img.size(); ++i) {
+    const double r = S->data[i] - img[i];
+    terms[i] = S->weight[i] * r * r;
+  }
+  return -0.5 * lo_sum_compensated(terms.data(), int64_t(terms.size()));
+}
+
+// log L and its gradient with respect to the 17 parameters, by forward-mode
+// differentiation of the same computation.
+double lo_loglike_grad(const lo_system* S, const double* theta, double* grad) {
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  if (!system_valid(S) || !theta || !grad || !S->data || !S->weight) return nan;
+  if (!params_valid(theta)) { for (int i = 0; i < NPAR; ++i) grad[i] = nan; return nan; }
+  Params<Dual> P; for (int i = 0; i < NPAR; ++i) P.p[i] = Dual::var(theta[i], i);
+  std::vector<Dual> img;
+  model_image(*S, P, 1, img);
+  std::vector<double> terms(img.size());
+  double g[NPAR] = {0};
+  for (size_t i = 0; i < img.size(); ++i) {
+    const double r = S->data[i] - img[i].v;
+    terms[i] = S->weight[i] * r * r;
+    for (int k = 0; k < NPAR; ++k) g[k] += S->weight[i] * r * img[i].d[k];
+  }
+  for (int k = 0; k < NPAR; ++k) grad[k] = g[k];
+  return -0.5 * lo_sum_compensated(terms.data(), int64_t(terms.size()));
+}
+
+// Surface brightness and its 17 partial derivatives at one image-plane point.
+double lo_surface_brightness_grad(const double* theta, double x, double y, double* grad) {
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  if (!params_valid(theta)) { for (int i = 0; i < NPAR; ++i) grad[i] = nan; return nan; }
+  Params<Dual> P; for (int i = 0; i < NPAR; ++i) P.p[i] = Dual::var(theta[i], i);
+  const Dual I = surface_brightness(P, Dual(x), Dual(y));
+  for (int i = 0; i < NPAR; ++i) grad[i] = I.d[i];
+  return I.v;
+}
+
+}  // extern "C"
