@@ -1,0 +1,146 @@
+/* lensed.h -- C ABI of the MI355X forward strong-lensing likelihood library.
+ *
+ * Implements the forward model and likelihood of Tessore, Bellagamba & Metcalf,
+ * "LENSED: a code for the forward reconstruction of lenses and sources from
+ * strong lensing observations" (MNRAS 2016) as hand-written HIP kernels for
+ * gfx950 (liblensed_hip.so).
+ *
+ * Model (17 float32 parameters per point, lens centred on the coordinate origin):
+ *   index  0 theta_E    SIE equivalent-circular Einstein radius (arcsec), >= 0
+ *          1 q_L        SIE axis ratio, (0, 1]
+ *          2 phi_L      SIE position angle (rad, counter-clockwise from +x to the major axis)
+ *          3 gamma      external shear magnitude
+ *          4 phi_gamma  external shear angle (rad): gamma_1 = gamma cos 2phi, gamma_2 = gamma sin 2phi
+ *          5 I_H        lens-light Sersic surface brightness at R_H
+ *          6 R_H        lens-light half-light radius (geometric mean of the semi-axes), > 0
+ *          7 n_H        lens-light Sersic index, [0.2, 10]
+ *          8 q_H        lens-light axis ratio, (0, 1]
+ *          9 phi_H      lens-light position angle
+ *         10 x_S, 11 y_S  source centre (arcsec)
+ *         12 I_S, 13 R_S, 14 n_S, 15 q_S, 16 phi_S   source Sersic, as for the lens light
+ *   Lens equation beta = x - alpha_SIE(x) - alpha_shear(x)        (Sec. 2.1, Eq. 1)
+ *   I(x) = I_lens(x) + I_source(beta)                             (Sec. 2.1, Eq. 2)
+ *   Sersic I = I_e exp(-b_n [(R/R_e)^{1/n} - 1]), R = sqrt(q x'^2 + y'^2/q)
+ *   with b_n the exact root of P(2n, b_n) = 1/2                   (Sec. 4.1, Eqs. 22-23)
+ *   SIE: kappa = theta_E / (2 sqrt(q x'^2 + y'^2/q))              (Sec. 4, Kormann et al. 1994)
+ *
+ * Conventions shared by every call
+ *   - Images are row-major float32 [height][width]; row 0 is the smallest y.
+ *     Pixel (r, c) is centred on x = center_x + (c - (W-1)/2) pixscale,
+ *     y = center_y + (r - (H-1)/2) pixscale.
+ *   - Pixel luminosity (Sec. 2.1 Eq. 3) uses the N x N midpoint rule
+ *     (Sec. 3.1 Eq. 14, the "subN" rules of Sec. 4.5): abscissae at
+ *     ((k + 1/2)/N - 1/2) pixscale from the pixel centre, weights pixscale^2/N^2.
+ *   - The PSF is an odd (2p+1) x (2q+1) float32 array centred on its middle
+ *     element; the library normalises a private copy to unit sum and convolves
+ *     with replicate padding (Sec. 3.1, Eq. 15).
+ *   - Every data pointer (images, weights, PSF, theta, outputs) is a DEVICE
+ *     pointer owned by the caller, except where a comment says HOST. The caller
+ *     keeps buffers alive until the stream has completed the call.
+ *   - All calls are asynchronous on `stream` (a hipStream_t; NULL = null stream)
+ *     and return once the work is enqueued.
+ *   - Parameter values live on the device, so they are not validated on the
+ *     host: a point with q outside (0,1], R_e <= 0, n outside [0.2, 10] or a
+ *     non-finite value yields NaN for that point only.
+ *   - One context per host thread; calls on one context must not overlap.
+ *
+ * Return codes: LENSED_OK, or one of the errors below; nothing is enqueued when
+ * an error is returned for invalid arguments.
+ */
+#ifndef LENSED_H
+#define LENSED_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LENSED_NPARAM 17
+
+enum {
+  LENSED_OK = 0,
+  LENSED_INVALID_ARGUMENT = 1, /* null pointer, non-positive size, even PSF side,
+                                  nsub outside 1..16, bad system index, ...     */
+  LENSED_HIP_ERROR = 2,        /* a HIP runtime call failed; see lensed_last_error */
+  LENSED_OUT_OF_MEMORY = 3,    /* workspace allocation failed                   */
+  LENSED_NOT_SUPPORTED = 4     /* no usable gfx950 device                       */
+};
+
+typedef struct lensed_ctx lensed_ctx;
+
+/* One observation (Sec. 3, step i): data d_i, weights w_i = 1/s_i^2 (0 = masked,
+ * Sec. 3.2), PSF array, grid geometry and integration rule. */
+typedef struct {
+  int32_t height, width;      /* pixels, > 0                                    */
+  float pixscale;             /* arcsec per pixel, > 0                          */
+  float center_x, center_y;   /* image-plane coordinates of the grid centre     */
+  int32_t nsub;               /* N of the N x N midpoint rule, 1..16            */
+  int32_t psf_h, psf_w;       /* odd, >= 1 (1 x 1 = no blurring)                */
+  const float* psf;           /* device [psf_h * psf_w], any positive scale     */
+  const float* data;          /* device [height * width]; may be NULL for render */
+  const float* weight;        /* device [height * width]; may be NULL for render */
+} lensed_system;
+
+/* Creates a context bound to HIP device `device` (its workspace arena, cached
+ * batch plans and graphs). Returns LENSED_NOT_SUPPORTED if the device is not
+ * gfx950. The context owns only its own allocations; lensed_destroy frees them. */
+int lensed_create(lensed_ctx** out, int device);
+void lensed_destroy(lensed_ctx* ctx);
+
+/* Number of model parameters per point (17). */
+int lensed_param_count(void);
+
+/* Static description of a status code. */
+const char* lensed_status_string(int status);
+
+/* Text of the last HIP or validation error recorded on the context. */
+const char* lensed_last_error(const lensed_ctx* ctx);
+
+/* Model image of one parameter point (Sec. 3, step iv): the pixel luminosities
+ * of Eq. 3 by the N x N midpoint rule, then, if apply_psf != 0, the PSF
+ * convolution of Eq. 15.
+ *   theta  device float32 [17]
+ *   image  device float32 [height * width], written
+ * data and weight of the system are not read. */
+int lensed_render(lensed_ctx* ctx, const lensed_system* sys, const float* theta,
+                  float* image, int apply_psf, void* stream);
+
+/* Log-likelihood of one point (Sec. 3.2, Eq. 17): log L = -chi^2/2 with
+ * chi^2 = sum_i w_i (d_i - L*_i)^2, the constant term dropped.
+ * chi^2 is accumulated in float32 with compensated summation and the final sum
+ * over tiles is taken in float64.
+ *   theta  device float32 [17]
+ *   logl   device float64 [1], written
+ * This is the plain form: one launch sequence per call. */
+int lensed_loglike(lensed_ctx* ctx, const lensed_system* sys, const float* theta,
+                   double* logl, void* stream);
+
+/* Log-likelihoods of many points over many systems in one graph launch
+ * (Eq. 17 for every point). Work is split into (point, tile) items, ordered
+ * longest first, and the schedule is chosen per system shape by the autotuner.
+ *   systems          HOST array [n_systems] (their data pointers are device pointers)
+ *   theta            device float32 [n_points * 17], point-major
+ *   system_of_point  HOST int32 [n_points], values in [0, n_systems)
+ *   logl             device float64 [n_points], written
+ * The plan (work lists, scratch layout, captured graph) is cached on the context
+ * keyed by the systems, the mapping and the theta/logl pointers. */
+int lensed_loglike_batch(lensed_ctx* ctx, const lensed_system* systems, int n_systems,
+                         const float* theta, const int32_t* system_of_point, int n_points,
+                         double* logl, void* stream);
+
+/* Log-likelihood and its gradient with respect to the 17 parameters for
+ * n_points points of one system: the derivative of Eq. 17 through Eqs. 15, 14,
+ * 2 and 1, computed by a hand-written adjoint (transposed PSF with the
+ * replicate-padding fold, then per-subsample partial derivatives).
+ *   theta  device float32 [n_points * 17]
+ *   logl   device float64 [n_points], written
+ *   grad   device float32 [n_points * 17], written (d log L / d theta) */
+int lensed_loglike_grad(lensed_ctx* ctx, const lensed_system* sys, const float* theta,
+                        int n_points, double* logl, float* grad, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LENSED_H */

@@ -38,7 +38,6 @@
 namespace {
 
 constexpr int NPAR = 17;
-constexpr double PI = 3.14159265358979323846;
 
 // ---------------------------------------------------------------------------
 // Forward-mode dual number: value and the 17 partial derivatives.
@@ -223,14 +222,14 @@ template <class T> void shear_deflection(T g, T phi, T x, T y, T& ax, T& ay) {
 
 // Elliptical Sersic profile (Sec. 4.1, Eqs. 22-23), amplitude I_e at the
 // half-light "radius" R_e, centred on (x0, y0) and rotated by phi:
-//   R = sqrt(q x'^2 + y'^2/q),  I = I_e exp(-b_n [(R/R_e)^{1/n} - 1]).
-template <class T> T sersic(T x, T y, T x0, T y0, T Ie, T Re, T n, T q, T phi) {
+//   R = sqrt(q x'^2 + y'^2/q),  I = I_e exp(-b_n [(R/R_e)^{1/n} - 1]),
+// with b = b_n passed in (it depends on n only, so it is solved once per point).
+template <class T> T sersic(T x, T y, T x0, T y0, T Ie, T Re, T n, T q, T phi, T b) {
   using std::cos; using std::sin; using std::sqrt; using std::exp; using std::log;
   const T dx = x - x0, dy = y - y0;
   const T c = cos(phi), s = sin(phi);
   const T xp = c * dx + s * dy, yp = -s * dx + c * dy;
   const T R2 = q * xp * xp + yp * yp / q;
-  const T b = bn_of(n);
   if (value(R2) == 0.0) return Ie * exp(b);
   const T R = sqrt(R2);
   const T t = exp(log(R / Re) / n);   // (R/R_e)^{1/n}
@@ -239,7 +238,16 @@ template <class T> T sersic(T x, T y, T x0, T y0, T Ie, T Re, T n, T q, T phi) {
 
 template <class T> struct Params {
   T p[NPAR];
+  T b_lens, b_src;   // b_n of the lens light and of the source
 };
+
+template <class T> Params<T> make_params(const T* th) {
+  Params<T> P;
+  for (int i = 0; i < NPAR; ++i) P.p[i] = th[i];
+  P.b_lens = bn_of(P.p[7]);
+  P.b_src = bn_of(P.p[14]);
+  return P;
+}
 
 // Surface brightness of the image plane at x (Eq. 2): lens light at x plus the
 // source at the position given by the lens equation (Eq. 1).
@@ -250,8 +258,8 @@ template <class T> T surface_brightness(const Params<T>& P, T x, T y) {
   shear_deflection(p[3], p[4], x, y, gx, gy);
   const T bx = x - ax - gx, by = y - ay - gy;
   const T zero(0.0);
-  const T lens = sersic(x, y, zero, zero, p[5], p[6], p[7], p[8], p[9]);
-  const T src = sersic(bx, by, p[10], p[11], p[12], p[13], p[14], p[15], p[16]);
+  const T lens = sersic(x, y, zero, zero, p[5], p[6], p[7], p[8], p[9], P.b_lens);
+  const T src = sersic(bx, by, p[10], p[11], p[12], p[13], p[14], p[15], p[16], P.b_src);
   return lens + src;
 }
 
@@ -295,11 +303,11 @@ void lo_shear_deflection(double g, double phi, double x, double y, double* ax, d
   shear_deflection<double>(g, phi, x, y, *ax, *ay);
 }
 double lo_sersic(double x, double y, double x0, double y0, double Ie, double Re, double n, double q, double phi) {
-  return sersic<double>(x, y, x0, y0, Ie, Re, n, q, phi);
+  return sersic<double>(x, y, x0, y0, Ie, Re, n, q, phi, bn_exact(n));
 }
 double lo_surface_brightness(const double* theta, double x, double y) {
   if (!params_valid(theta)) return std::numeric_limits<double>::quiet_NaN();
-  Params<double> P; for (int i = 0; i < NPAR; ++i) P.p[i] = theta[i];
+  const Params<double> P = make_params(theta);
   return surface_brightness(P, x, y);
 }
 
@@ -391,7 +399,7 @@ int lo_render(const lo_system* S, const double* theta, int apply_psf, double* ou
     for (size_t i = 0; i < n; ++i) out[i] = std::numeric_limits<double>::quiet_NaN();
     return 0;
   }
-  Params<double> P; for (int i = 0; i < NPAR; ++i) P.p[i] = theta[i];
+  const Params<double> P = make_params(theta);
   std::vector<double> img;
   model_image(*S, P, apply_psf, img);
   std::memcpy(out, img.data(), n * sizeof(double));
@@ -411,7 +419,7 @@ int lo_psf_convolve(int H, int W, const double* L, int ph, int pw, const double*
 double lo_loglike(const lo_system* S, const double* theta) {
   if (!system_valid(S) || !theta || !S->data || !S->weight) return std::numeric_limits<double>::quiet_NaN();
   if (!params_valid(theta)) return std::numeric_limits<double>::quiet_NaN();
-  Params<double> P; for (int i = 0; i < NPAR; ++i) P.p[i] = theta[i];
+  const Params<double> P = make_params(theta);
   std::vector<double> img;
   model_image(*S, P, 1, img);
   std::vector<double> terms(img.size());
@@ -428,7 +436,9 @@ double lo_loglike_grad(const lo_system* S, const double* theta, double* grad) {
   const double nan = std::numeric_limits<double>::quiet_NaN();
   if (!system_valid(S) || !theta || !grad || !S->data || !S->weight) return nan;
   if (!params_valid(theta)) { for (int i = 0; i < NPAR; ++i) grad[i] = nan; return nan; }
-  Params<Dual> P; for (int i = 0; i < NPAR; ++i) P.p[i] = Dual::var(theta[i], i);
+  Dual th[NPAR];
+  for (int i = 0; i < NPAR; ++i) th[i] = Dual::var(theta[i], i);
+  const Params<Dual> P = make_params(th);
   std::vector<Dual> img;
   model_image(*S, P, 1, img);
   std::vector<double> terms(img.size());
@@ -446,7 +456,9 @@ double lo_loglike_grad(const lo_system* S, const double* theta, double* grad) {
 double lo_surface_brightness_grad(const double* theta, double x, double y, double* grad) {
   const double nan = std::numeric_limits<double>::quiet_NaN();
   if (!params_valid(theta)) { for (int i = 0; i < NPAR; ++i) grad[i] = nan; return nan; }
-  Params<Dual> P; for (int i = 0; i < NPAR; ++i) P.p[i] = Dual::var(theta[i], i);
+  Dual th[NPAR];
+  for (int i = 0; i < NPAR; ++i) th[i] = Dual::var(theta[i], i);
+  const Params<Dual> P = make_params(th);
   const Dual I = surface_brightness(P, Dual(x), Dual(y));
   for (int i = 0; i < NPAR; ++i) grad[i] = I.d[i];
   return I.v;

@@ -1,1 +1,14 @@
-"""MI355X-native forward lensing likelihood (placeholder, binding added below)."""
+"""MI355X-native forward strong-lensing likelihood.
+
+Hot path of the forward reconstruction method of Tessore, Bellagamba & Metcalf
+(LENSED, MNRAS 2016): ray-trace every pixel subsample through an SIE plus
+external shear (Eq. 1), add the lensed Sersic source to the Sersic lens light
+(Eq. 2), integrate over the pixel (Eqs. 3, 14), convolve with the PSF (Eq. 15)
+and reduce the weighted chi^2 / log-likelihood (Eq. 17) -- all in hand-written
+HIP kernels for gfx950 behind the C ABI of include/lensed.h.
+"""
+from .binding import (NPARAM, Context, LensedError, LogLikeFn, System, default_context, loglike,
+                      loglike_batch, loglike_grad, render)
+
+__all__ = ["NPARAM", "Context", "LensedError", "LogLikeFn", "System", "default_context", "loglike",
+           "loglike_batch", "loglike_grad", "render"]

@@ -1,0 +1,267 @@
+"""ctypes binding of liblensed_hip.so: argument marshalling only.
+
+Every step of the forward model and likelihood runs in the library's HIP
+kernels; torch supplies device memory and the current stream. The binding
+raises if the library has not been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblensed_hip.so")
+NPARAM = 17
+
+LENSED_OK = 0
+_STATUS = {0: "ok", 1: "invalid argument", 2: "HIP runtime error", 3: "out of device memory", 4: "not supported"}
+
+
+class LensedError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, 'error')} ({status}): {message}")
+        self.status = status
+
+
+class LensedSystemC(ctypes.Structure):
+    """Mirror of lensed_system in include/lensed.h."""
+    _fields_ = [
+        ("height", ctypes.c_int32), ("width", ctypes.c_int32),
+        ("pixscale", ctypes.c_float),
+        ("center_x", ctypes.c_float), ("center_y", ctypes.c_float),
+        ("nsub", ctypes.c_int32),
+        ("psf_h", ctypes.c_int32), ("psf_w", ctypes.c_int32),
+        ("psf", ctypes.c_void_p), ("data", ctypes.c_void_p), ("weight", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def lib():
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1505_07674_amd.build` "
+                                   "(or __graft_entry__.build()) first")
+            L = ctypes.CDLL(LIB_PATH)
+            i, vp, cp = ctypes.c_int, ctypes.c_void_p, ctypes.c_char_p
+            sp = ctypes.POINTER(LensedSystemC)
+            sig = {
+                "lensed_create": (i, [ctypes.POINTER(vp), i]),
+                "lensed_destroy": (None, [vp]),
+                "lensed_param_count": (i, []),
+                "lensed_status_string": (cp, [i]),
+                "lensed_last_error": (cp, [vp]),
+                "lensed_render": (i, [vp, sp, vp, vp, i, vp]),
+                "lensed_loglike": (i, [vp, sp, vp, vp, vp]),
+                "lensed_loglike_batch": (i, [vp, sp, i, vp, ctypes.POINTER(ctypes.c_int32), i, vp, vp]),
+                "lensed_loglike_grad": (i, [vp, sp, vp, i, vp, vp, vp]),
+            }
+            for name, (res, args) in sig.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+        return _lib
+
+
+class Context:
+    """Owns a lensed_ctx (workspace, cached batch plans and graphs) on one device."""
+
+    def __init__(self, device: int = 0):
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        rc = lib().lensed_create(ctypes.byref(h), self.device)
+        if rc != LENSED_OK:
+            raise LensedError(rc, f"lensed_create(device={device})")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def check(self, rc: int, what: str):
+        if rc != LENSED_OK:
+            msg = lib().lensed_last_error(self._h)
+            raise LensedError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().lensed_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts = {}
+
+
+def default_context(device: Optional[int] = None) -> Context:
+    dev = torch.cuda.current_device() if device is None else int(device)
+    ctx = _contexts.get(dev)
+    if ctx is None:
+        ctx = Context(dev)
+        _contexts[dev] = ctx
+    return ctx
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_tensor(t: torch.Tensor, dtype: torch.dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+class System:
+    """One observation resident on the GPU (Sec. 3, step i).
+
+    data, weight: float32 [H, W] (weight = 1/s^2, 0 = masked); psf: float32
+    odd [ph, pw] (normalised by the library). data/weight may be None for
+    render-only use.
+    """
+
+    def __init__(self, psf: torch.Tensor, data: Optional[torch.Tensor] = None,
+                 weight: Optional[torch.Tensor] = None, *, pixscale: float, nsub: int,
+                 height: Optional[int] = None, width: Optional[int] = None,
+                 center: Tuple[float, float] = (0.0, 0.0)):
+        self.psf = _dev_tensor(psf, torch.float32, "psf")
+        if self.psf.dim() != 2:
+            raise ValueError("psf must be 2-D")
+        self.data = None if data is None else _dev_tensor(data, torch.float32, "data")
+        self.weight = None if weight is None else _dev_tensor(weight, torch.float32, "weight")
+        ref = self.data if self.data is not None else self.weight
+        if ref is not None:
+            if ref.dim() != 2:
+                raise ValueError("data and weight must be 2-D [H, W]")
+            height, width = ref.shape
+        if height is None or width is None:
+            raise ValueError("height and width are required without data")
+        for t in (self.data, self.weight):
+            if t is not None and tuple(t.shape) != (height, width):
+                raise ValueError("data and weight must have the same [H, W] shape")
+        self.height, self.width = int(height), int(width)
+        self.pixscale, self.nsub = float(pixscale), int(nsub)
+        self.center = (float(center[0]), float(center[1]))
+        self._c = LensedSystemC(
+            self.height, self.width, self.pixscale, self.center[0], self.center[1], self.nsub,
+            int(self.psf.shape[0]), int(self.psf.shape[1]), self.psf.data_ptr(),
+            None if self.data is None else self.data.data_ptr(),
+            None if self.weight is None else self.weight.data_ptr())
+
+    @property
+    def c_struct(self) -> LensedSystemC:
+        return self._c
+
+    @property
+    def device(self) -> torch.device:
+        return self.psf.device
+
+
+def _theta2d(theta: torch.Tensor) -> torch.Tensor:
+    t = _dev_tensor(theta, torch.float32, "theta")
+    if t.dim() == 1:
+        t = t.view(1, -1)
+    if t.dim() != 2 or t.shape[1] != NPARAM:
+        raise ValueError(f"theta must be [{NPARAM}] or [P, {NPARAM}]")
+    return t
+
+
+def render(theta: torch.Tensor, system: System, apply_psf: bool = True, *, ctx: Optional[Context] = None,
+           stream=None) -> torch.Tensor:
+    """Model image [H, W] of one point: Eq. 3 by N x N midpoint subsampling, then Eq. 15."""
+    t = _theta2d(theta)
+    if t.shape[0] != 1:
+        raise ValueError("render takes a single parameter point")
+    ctx = ctx or default_context(t.device.index)
+    out = torch.empty((system.height, system.width), dtype=torch.float32, device=t.device)
+    rc = lib().lensed_render(ctx.handle, ctypes.byref(system.c_struct), ctypes.c_void_p(t.data_ptr()),
+                             ctypes.c_void_p(out.data_ptr()), int(bool(apply_psf)), _stream_handle(stream))
+    ctx.check(rc, "lensed_render")
+    return out
+
+
+def loglike(theta: torch.Tensor, system: System, *, out: Optional[torch.Tensor] = None,
+            ctx: Optional[Context] = None, stream=None) -> torch.Tensor:
+    """log L = -chi^2/2 of one point (Eq. 17) as a float64 [1] device tensor (plain form)."""
+    t = _theta2d(theta)
+    if t.shape[0] != 1:
+        raise ValueError("loglike takes a single parameter point; use loglike_batch")
+    ctx = ctx or default_context(t.device.index)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=t.device)
+    rc = lib().lensed_loglike(ctx.handle, ctypes.byref(system.c_struct), ctypes.c_void_p(t.data_ptr()),
+                              ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+    ctx.check(rc, "lensed_loglike")
+    return out
+
+
+class _SystemArray:
+    def __init__(self, systems: Sequence[System]):
+        self.systems = list(systems)
+        self.arr = (LensedSystemC * len(self.systems))(*[s.c_struct for s in self.systems])
+
+
+def loglike_batch(theta: torch.Tensor, system_of_point, systems: Sequence[System], *,
+                  out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None, stream=None) -> torch.Tensor:
+    """log L of P points over several systems in one graph launch -> float64 [P]."""
+    t = _theta2d(theta)
+    P = t.shape[0]
+    sop = np.ascontiguousarray(np.asarray(system_of_point, dtype=np.int32).reshape(-1))
+    if sop.size != P:
+        raise ValueError("system_of_point must have one entry per point")
+    ctx = ctx or default_context(t.device.index)
+    if out is None:
+        out = torch.empty(P, dtype=torch.float64, device=t.device)
+    sa = _SystemArray(systems)
+    rc = lib().lensed_loglike_batch(ctx.handle, sa.arr, len(sa.systems), ctypes.c_void_p(t.data_ptr()),
+                                    sop.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), P,
+                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+    ctx.check(rc, "lensed_loglike_batch")
+    return out
+
+
+def loglike_grad(theta: torch.Tensor, system: System, *, ctx: Optional[Context] = None,
+                 stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """log L and d log L / d theta for P points of one system -> (float64 [P], float32 [P, 17])."""
+    t = _theta2d(theta)
+    P = t.shape[0]
+    ctx = ctx or default_context(t.device.index)
+    ll = torch.empty(P, dtype=torch.float64, device=t.device)
+    g = torch.empty((P, NPARAM), dtype=torch.float32, device=t.device)
+    rc = lib().lensed_loglike_grad(ctx.handle, ctypes.byref(system.c_struct), ctypes.c_void_p(t.data_ptr()), P,
+                                   ctypes.c_void_p(ll.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                   _stream_handle(stream))
+    ctx.check(rc, "lensed_loglike_grad")
+    return ll, g
+
+
+class LogLikeFn(torch.autograd.Function):
+    """log L(theta) for [P, 17] points of one system with the hand-written adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx_, theta: torch.Tensor, system: System):
+        ll, g = loglike_grad(theta.detach(), system)
+        ctx_.save_for_backward(g)
+        return ll
+
+    @staticmethod
+    def backward(ctx_, grad_out: torch.Tensor):
+        (g,) = ctx_.saved_tensors
+        return (grad_out.to(g.dtype)[:, None] * g), None

@@ -1,0 +1,284 @@
+// capi.hip -- the extern "C" boundary of liblensed_hip: contexts, validation,
+// workspace, the plain launch sequences and the batched plans (work lists,
+// scratch layout, captured hipGraphs).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+#include "lensed.h"
+#include "plan.h"
+
+using namespace lensed;
+
+struct lensed_ctx {
+  int device = 0;
+  hipStream_t cap = nullptr;        // private stream used only for graph capture
+  std::string err;
+  char* arena = nullptr;            // workspace of the plain calls
+  size_t arena_bytes = 0;
+  bool use_graphs = true;
+  std::vector<std::unique_ptr<BatchPlan>> plans;   // most recently used last
+  TileCache tiles;
+};
+
+namespace {
+
+int set_err(lensed_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(lensed_ctx* c, hipError_t e, const char* what) {
+  const int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? LENSED_OUT_OF_MEMORY
+                                                                                : LENSED_HIP_ERROR;
+  return set_err(c, code, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define LENSED_HIP(ctx, call)                          \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int ensure_arena(lensed_ctx* c, size_t bytes) {
+  if (c->arena_bytes >= bytes) return LENSED_OK;
+  if (c->arena) {
+    // earlier calls may still use the old workspace
+    LENSED_HIP(c, hipDeviceSynchronize());
+    LENSED_HIP(c, hipFree(c->arena));
+    c->arena = nullptr;
+    c->arena_bytes = 0;
+  }
+  const size_t n = align_up(std::max(bytes, (size_t)1 << 20), (size_t)1 << 20);
+  LENSED_HIP(c, hipMalloc((void**)&c->arena, n));
+  c->arena_bytes = n;
+  return LENSED_OK;
+}
+
+}  // namespace
+
+namespace lensed {
+
+int validate_system(lensed_ctx* c, const lensed_system* s, bool need_data, int index) {
+  const std::string where = index >= 0 ? "system " + std::to_string(index) + ": " : "";
+  if (!s) return set_err(c, LENSED_INVALID_ARGUMENT, where + "system is NULL");
+  if (s->height <= 0 || s->width <= 0) return set_err(c, LENSED_INVALID_ARGUMENT, where + "height and width must be > 0");
+  if ((int64_t)s->height * s->width > ((int64_t)1 << 28))
+    return set_err(c, LENSED_INVALID_ARGUMENT, where + "image larger than 2^28 pixels");
+  if (!(s->pixscale > 0.0f) || !std::isfinite(s->pixscale))
+    return set_err(c, LENSED_INVALID_ARGUMENT, where + "pixscale must be finite and > 0");
+  if (!std::isfinite(s->center_x) || !std::isfinite(s->center_y))
+    return set_err(c, LENSED_INVALID_ARGUMENT, where + "grid centre must be finite");
+  if (s->nsub < 1 || s->nsub > 16) return set_err(c, LENSED_INVALID_ARGUMENT, where + "nsub must be in 1..16");
+  if (s->psf_h < 1 || s->psf_w < 1 || s->psf_h % 2 == 0 || s->psf_w % 2 == 0)
+    return set_err(c, LENSED_INVALID_ARGUMENT, where + "PSF dimensions must be odd and >= 1");
+  if (s->psf_h > MAX_PSF || s->psf_w > MAX_PSF)
+    return set_err(c, LENSED_INVALID_ARGUMENT, where + "PSF side larger than " + std::to_string(MAX_PSF));
+  if (!s->psf) return set_err(c, LENSED_INVALID_ARGUMENT, where + "psf is NULL");
+  if (need_data && (!s->data || !s->weight))
+    return set_err(c, LENSED_INVALID_ARGUMENT, where + "data and weight are required");
+  return LENSED_OK;
+}
+
+SysDesc make_desc(const lensed_system& s, const TileShape& t) {
+  SysDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.H = s.height;
+  d.W = s.width;
+  d.N = s.nsub;
+  d.ph = s.psf_h;
+  d.pw = s.psf_w;
+  d.d = s.pixscale;
+  d.cx = s.center_x;
+  d.cy = s.center_y;
+  d.psf = s.psf;
+  d.psfn = nullptr;
+  d.data = s.data;
+  d.weight = s.weight;
+  d.TW = t.TW;
+  d.TH = t.TH;
+  d.tiles_x = (s.width + t.TW - 1) / t.TW;
+  d.n_ptiles = d.tiles_x * ((s.height + t.TH - 1) / t.TH);
+  d.n_rtiles = (int)(((int64_t)s.height * s.width + RENDER_BLOCK - 1) / RENDER_BLOCK);
+  return d;
+}
+
+int square_psf_code(int ph, int pw) {
+  if (ph != pw) return -1;
+  return (ph == 21 || ph == 7 || ph == 1) ? ph : -1;
+}
+
+}  // namespace lensed
+
+extern "C" {
+
+int lensed_param_count(void) { return LENSED_NPARAM; }
+
+const char* lensed_status_string(int status) {
+  switch (status) {
+    case LENSED_OK: return "ok";
+    case LENSED_INVALID_ARGUMENT: return "invalid argument";
+    case LENSED_HIP_ERROR: return "HIP runtime error";
+    case LENSED_OUT_OF_MEMORY: return "out of device memory";
+    case LENSED_NOT_SUPPORTED: return "not supported";
+    default: return "unknown status";
+  }
+}
+
+const char* lensed_last_error(const lensed_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int lensed_create(lensed_ctx** out, int device) {
+  if (!out) return LENSED_INVALID_ARGUMENT;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return LENSED_NOT_SUPPORTED;
+  if (device < 0 || device >= count) return LENSED_INVALID_ARGUMENT;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return LENSED_HIP_ERROR;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LENSED_NOT_SUPPORTED;
+  if (hipSetDevice(device) != hipSuccess) return LENSED_HIP_ERROR;
+  auto* c = new lensed_ctx();
+  c->device = device;
+  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return LENSED_HIP_ERROR;
+  }
+  const char* g = std::getenv("LENSED_NO_GRAPHS");
+  c->use_graphs = !(g && g[0] == '1');
+  *out = c;
+  return LENSED_OK;
+}
+
+void lensed_destroy(lensed_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  c->plans.clear();
+  if (c->arena) (void)hipFree(c->arena);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  delete c;
+}
+
+int lensed_render(lensed_ctx* c, const lensed_system* sys, const float* theta, float* image, int apply_psf,
+                  void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  int rc = validate_system(c, sys, false, -1);
+  if (rc) return rc;
+  if (!theta || !image) return set_err(c, LENSED_INVALID_ARGUMENT, "theta and image are required");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const TileShape ts = c->tiles.choose(*sys);
+  SysDesc sd = make_desc(*sys, ts);
+  const size_t npix = (size_t)sd.H * sd.W;
+  const size_t off_pc = 0;
+  const size_t off_psf = align_up(off_pc + sizeof(PointConst), 256);
+  const size_t off_L = align_up(off_psf + sizeof(float) * sd.ph * sd.pw, 256);
+  const size_t total = align_up(off_L + sizeof(float) * npix, 256);
+  if ((rc = ensure_arena(c, total))) return rc;
+  PointConst* pc = (PointConst*)(c->arena + off_pc);
+  sd.psfn = (float*)(c->arena + off_psf);
+  float* L = apply_psf ? (float*)(c->arena + off_L) : image;
+  WorkArgs w;
+  std::memset(&w, 0, sizeof(w));
+  w.single = sd;
+  LENSED_HIP(c, launch_prologue(theta, 1, pc, nullptr, sd, nullptr, 1, st));
+  LENSED_HIP(c, launch_render(w, pc, L, sd.n_rtiles, st));
+  if (apply_psf)
+    LENSED_HIP(c, launch_psf(w, L, image, nullptr, 0, sd.n_ptiles, square_psf_code(sd.ph, sd.pw), sd.TW, sd.TH,
+                             sd.ph, sd.pw, st));
+  return LENSED_OK;
+}
+
+int lensed_loglike(lensed_ctx* c, const lensed_system* sys, const float* theta, double* logl, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  int rc = validate_system(c, sys, true, -1);
+  if (rc) return rc;
+  if (!theta || !logl) return set_err(c, LENSED_INVALID_ARGUMENT, "theta and logl are required");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const TileShape ts = c->tiles.choose(*sys);
+  SysDesc sd = make_desc(*sys, ts);
+  const size_t npix = (size_t)sd.H * sd.W;
+  const size_t off_pc = 0;
+  const size_t off_psf = align_up(off_pc + sizeof(PointConst), 256);
+  const size_t off_L = align_up(off_psf + sizeof(float) * sd.ph * sd.pw, 256);
+  const size_t off_part = align_up(off_L + sizeof(float) * npix, 256);
+  const size_t total = align_up(off_part + sizeof(float2) * sd.n_ptiles, 256);
+  if ((rc = ensure_arena(c, total))) return rc;
+  PointConst* pc = (PointConst*)(c->arena + off_pc);
+  sd.psfn = (float*)(c->arena + off_psf);
+  float* L = (float*)(c->arena + off_L);
+  float2* part = (float2*)(c->arena + off_part);
+  WorkArgs w;
+  std::memset(&w, 0, sizeof(w));
+  w.single = sd;
+  LENSED_HIP(c, launch_prologue(theta, 1, pc, nullptr, sd, nullptr, 1, st));
+  LENSED_HIP(c, launch_render(w, pc, L, sd.n_rtiles, st));
+  LENSED_HIP(c, launch_psf(w, L, nullptr, part, 1, sd.n_ptiles, square_psf_code(sd.ph, sd.pw), sd.TW, sd.TH, sd.ph,
+                           sd.pw, st));
+  LENSED_HIP(c, launch_finalize(part, nullptr, nullptr, 1, sd.n_ptiles, logl, st));
+  return LENSED_OK;
+}
+
+int lensed_loglike_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const float* theta,
+                         const int32_t* system_of_point, int n_points, double* logl, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  if (n_points < 0) return set_err(c, LENSED_INVALID_ARGUMENT, "n_points must be >= 0");
+  if (n_points == 0) return LENSED_OK;
+  if (!systems || n_systems <= 0) return set_err(c, LENSED_INVALID_ARGUMENT, "at least one system is required");
+  if (!theta || !logl || !system_of_point)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "theta, system_of_point and logl are required");
+  for (int s = 0; s < n_systems; ++s) {
+    const int rc = validate_system(c, &systems[s], true, s);
+    if (rc) return rc;
+  }
+  for (int p = 0; p < n_points; ++p)
+    if (system_of_point[p] < 0 || system_of_point[p] >= n_systems)
+      return set_err(c, LENSED_INVALID_ARGUMENT, "system_of_point[" + std::to_string(p) + "] out of range");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  BatchPlan* plan = nullptr;
+  for (size_t i = 0; i < c->plans.size(); ++i) {
+    if (c->plans[i]->matches(systems, n_systems, theta, system_of_point, n_points, logl)) {
+      std::unique_ptr<BatchPlan> keep = std::move(c->plans[i]);
+      c->plans.erase(c->plans.begin() + i);
+      c->plans.push_back(std::move(keep));
+      plan = c->plans.back().get();
+      break;
+    }
+  }
+  if (!plan) {
+    if (c->plans.size() >= 8) {
+      LENSED_HIP(c, hipDeviceSynchronize());
+      c->plans.erase(c->plans.begin());
+    }
+    std::unique_ptr<BatchPlan> np(new BatchPlan());
+    std::string msg;
+    hipError_t e = np->build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg);
+    if (e != hipSuccess) return hip_fail(c, e, ("batch plan: " + msg).c_str());
+    if (c->use_graphs) {
+      e = np->capture(c->cap);
+      if (e != hipSuccess) return hip_fail(c, e, "batch plan graph capture");
+    }
+    c->plans.push_back(std::move(np));
+    plan = c->plans.back().get();
+  }
+  LENSED_HIP(c, plan->run((hipStream_t)stream));
+  return LENSED_OK;
+}
+
+}  // extern "C"
+
+extern "C" int lensed_loglike_grad(lensed_ctx* c, const lensed_system* sys, const float* theta, int n_points,
+                                   double* logl, float* grad, void* stream) {
+  (void)sys; (void)theta; (void)n_points; (void)logl; (void)grad; (void)stream;
+  return set_err(c, LENSED_NOT_SUPPORTED, "adjoint not built yet");
+}

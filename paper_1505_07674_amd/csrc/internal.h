@@ -1,0 +1,60 @@
+// internal.h -- device-side data layout shared by the kernels of liblensed_hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lensed {
+
+constexpr int NPAR = 17;
+constexpr float LN2F = 0.693147180559945309f;
+constexpr double LOG2E = 1.44269504088896340736;
+
+// Per-point constants derived once from the 17 parameters (prologue kernel).
+// Read with wave-uniform addresses, so they live in scalar registers in the
+// render kernels. Invalid points carry NaN in the amplitudes and in the lens
+// matrix, which turns every result of that point into NaN.
+struct PointConst {
+  int sie_mode;        // 0: isothermal sphere (q = 1); 1: atanh by polynomial (q' <= 1/2); 2: atanh by log
+  float cL, sL;        // frame rotation of the SIE
+  float q2;            // q_L^2
+  float qp;            // q' = sqrt(1 - q_L^2)
+  float kc, ks;        // k cos(phi_L), k sin(phi_L), k = theta_E sqrt(q)/q' (mode 0: kc = theta_E)
+  float iq;            // 1/q_L
+  float m11, m12, m22; // beta = M x - alpha_SIE(x), M = 1 - shear matrix
+  // lens light: I = hI * exp2(hB (1 - t)), t = exp2(he * log2(hqa x'^2 + hqb y'^2))
+  float hc, hs, hqa, hqb, he, hB, hI;
+  // source: same, about (sx0, sy0)
+  float sx0, sy0, sc, ss, sqa, sqb, se, sB, sI;
+  float pad[5];
+};
+static_assert(sizeof(PointConst) == 32 * 4, "PointConst layout");
+
+// Extra per-point values needed by the adjoint.
+struct GradConst {
+  float theta[NPAR];   // raw parameters
+  float dB_dn_h;       // d(b_n log2 e)/dn for the lens light
+  float dB_dn_s;       // same for the source
+  float bh, bs;        // b_n of lens light and source
+  float pad[11];
+};
+static_assert(sizeof(GradConst) == 32 * 4, "GradConst layout");
+
+// Geometry and schedule of one system (one observation).
+struct SysDesc {
+  int H, W, N;            // image size and subsampling
+  int ph, pw;             // PSF dimensions (odd)
+  float d, cx, cy;        // pixel scale and grid centre
+  const float* psf;       // caller's PSF (unnormalised)
+  float* psfn;            // library copy, normalised to unit sum
+  const float* data;
+  const float* weight;
+  int TW, TH;             // PSF/chi^2 output tile
+  int tiles_x, n_ptiles;  // PSF tiles per row, per image
+  int n_rtiles;           // render tiles (RT pixels each) per image
+  int pad;
+};
+
+constexpr int RENDER_BLOCK = 256;   // pixels per render tile / threads per render block
+
+}  // namespace lensed

@@ -1,0 +1,46 @@
+// kernels.h -- host-side launch wrappers of the liblensed_hip kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace lensed {
+
+// Work description shared by the render, PSF/chi^2 and adjoint kernels.
+// Plain calls use `single` and `point0` with implicit item = (point0, blockIdx.x);
+// batched calls pass device tables and an explicit (point, tile) item list.
+struct WorkArgs {
+  SysDesc single;               // used when sys_table == nullptr
+  const SysDesc* sys_table;     // [n_systems] or nullptr
+  const int* point_sys;         // [n_points] system of each point, or nullptr (system 0)
+  const int64_t* point_loff;    // [n_points] offset of the point's image in the scratch, or nullptr (0)
+  const int* point_pbase;       // [n_points] first partial-sum slot of the point, or nullptr (0)
+  const int2* items;            // [n_items] (point, tile), or nullptr
+  int n_items;                  // grid size when items is given
+  int point0;                   // point of a plain call
+};
+
+hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, GradConst* gcs, const SysDesc& single,
+                           SysDesc* table, int n_sys, hipStream_t stream);
+
+// Unconvolved pixel luminosities into L (scratch or the caller's image).
+hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, float* L, int n_blocks, hipStream_t stream);
+
+// mode 0: PSF convolution of L into out (L* images, same offsets as L).
+// mode 1: PSF convolution fused with the weighted chi^2; one compensated
+//         (hi, lo) float pair per tile is written to partials.
+// Every system of one launch uses the same TW x TH output tile (the block is
+// TW x TH/4 threads). square_psf = 21, 7 or 1 selects a specialised stencil when
+// every PSF of the launch has that square size; -1 selects the generic one.
+hipError_t launch_psf(const WorkArgs& w, const float* L, float* out, float2* partials, int mode, int n_blocks,
+                      int square_psf, int TW, int TH, int max_ph, int max_pw, hipStream_t stream);
+
+constexpr int PSF_ROWS = 4;   // outputs per thread of the PSF kernel
+
+// log L = -1/2 * sum over the point's tiles of (hi + lo), in float64.
+hipError_t launch_finalize(const float2* partials, const int* point_pbase, const int* point_ntiles, int n_points,
+                           int single_ntiles, double* logl, hipStream_t stream);
+
+}  // namespace lensed

@@ -1,0 +1,81 @@
+// plan.h -- tile-shape selection and batched execution plans.
+#pragma once
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+#include "lensed.h"
+
+struct lensed_ctx;
+
+namespace lensed {
+
+constexpr int MAX_PSF = 63;   // largest PSF side accepted (LDS staging bound)
+
+struct TileShape {
+  int TW, TH;
+};
+
+// Chooses the TW x TH output tile of the PSF/chi^2 kernel for an image shape.
+// The model counts lane slots of the stencil (ragged tiles and partly idle
+// waves included) plus the LDS staging of the halo; a measured choice can
+// override it through set().
+class TileCache {
+ public:
+  TileShape choose(const lensed_system& s);
+  TileShape choose_common(const lensed_system* s, int n);
+  void set(int H, int W, int ph, int pw, TileShape t) { cache_[std::make_tuple(H, W, ph, pw)] = t; }
+  static double model_cost(int H, int W, int ph, int pw, TileShape t);
+  static std::vector<TileShape> candidates();
+
+ private:
+  std::map<std::tuple<int, int, int, int>, TileShape> cache_;
+};
+
+int validate_system(lensed_ctx* c, const lensed_system* s, bool need_data, int index);
+SysDesc make_desc(const lensed_system& s, const TileShape& t);
+int square_psf_code(int ph, int pw);
+
+// One batched evaluation: n_points parameter points over n_systems systems.
+// Work lists are (point, tile) items ordered by decreasing cost (longest first);
+// the unconvolved images of all points live in one scratch buffer.
+class BatchPlan {
+ public:
+  ~BatchPlan();
+  bool matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map, int n_points,
+               const double* logl) const;
+  hipError_t build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
+                   int n_points, double* logl, TileCache& tiles, std::string& msg);
+  hipError_t capture(hipStream_t cap);
+  hipError_t enqueue(hipStream_t s) const;
+  hipError_t run(hipStream_t s) const;
+
+ private:
+  std::vector<lensed_system> systems_;
+  std::vector<int32_t> map_;
+  const float* theta_ = nullptr;
+  double* logl_ = nullptr;
+  int n_points_ = 0;
+
+  char* mem_ = nullptr;
+  SysDesc* d_sys_ = nullptr;
+  int* d_point_sys_ = nullptr;
+  int64_t* d_loff_ = nullptr;
+  int* d_pbase_ = nullptr;
+  int* d_ntiles_ = nullptr;
+  int2* d_ritems_ = nullptr;
+  int2* d_pitems_ = nullptr;
+  PointConst* d_pc_ = nullptr;
+  float* d_L_ = nullptr;
+  float2* d_part_ = nullptr;
+  int n_ritems_ = 0, n_pitems_ = 0;
+  int square_psf_ = -1, TW_ = 32, TH_ = 32, max_ph_ = 1, max_pw_ = 1;
+  hipGraph_t graph_ = nullptr;
+  hipGraphExec_t exec_ = nullptr;
+};
+
+}  // namespace lensed

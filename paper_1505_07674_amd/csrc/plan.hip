@@ -1,0 +1,225 @@
+// plan.hip -- tile-shape model and batched plans with captured hipGraphs.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "plan.h"
+
+namespace lensed {
+
+std::vector<TileShape> TileCache::candidates() {
+  std::vector<TileShape> out;
+  const int tws[] = {16, 32, 40, 48, 64};
+  const int ths[] = {16, 20, 24, 32, 40, 48, 64};
+  for (int tw : tws)
+    for (int th : ths) {
+      const int threads = tw * th / PSF_ROWS;
+      if (threads >= 64 && threads <= 512) out.push_back({tw, th});
+    }
+  return out;
+}
+
+double TileCache::model_cost(int H, int W, int ph, int pw, TileShape t) {
+  const double ntiles = (double)((W + t.TW - 1) / t.TW) * (double)((H + t.TH - 1) / t.TH);
+  const int threads = t.TW * t.TH / PSF_ROWS;
+  const double lanes = 64.0 * ((threads + 63) / 64);
+  const double per_lane = (double)PSF_ROWS * ph * pw + (double)pw * (PSF_ROWS + ph - 1);
+  const double staging = 6.0 * (double)(t.TW + pw - 1) * (double)(t.TH + ph - 1);
+  return ntiles * (lanes * per_lane + staging + 2000.0);
+}
+
+TileShape TileCache::choose(const lensed_system& s) {
+  const auto key = std::make_tuple(s.height, s.width, s.psf_h, s.psf_w);
+  auto it = cache_.find(key);
+  if (it != cache_.end()) return it->second;
+  TileShape best{32, 32};
+  double bc = 1e300;
+  for (const TileShape& t : candidates()) {
+    const double cst = model_cost(s.height, s.width, s.psf_h, s.psf_w, t);
+    if (cst < bc) {
+      bc = cst;
+      best = t;
+    }
+  }
+  cache_[key] = best;
+  return best;
+}
+
+TileShape TileCache::choose_common(const lensed_system* s, int n) {
+  if (n == 1) return choose(s[0]);
+  TileShape best{32, 32};
+  double bc = 1e300;
+  for (const TileShape& t : candidates()) {
+    double cst = 0.0;
+    for (int i = 0; i < n; ++i) cst += model_cost(s[i].height, s[i].width, s[i].psf_h, s[i].psf_w, t);
+    if (cst < bc) {
+      bc = cst;
+      best = t;
+    }
+  }
+  return best;
+}
+
+namespace {
+bool same_system(const lensed_system& a, const lensed_system& b) {
+  return a.height == b.height && a.width == b.width && a.pixscale == b.pixscale && a.center_x == b.center_x &&
+         a.center_y == b.center_y && a.nsub == b.nsub && a.psf_h == b.psf_h && a.psf_w == b.psf_w &&
+         a.psf == b.psf && a.data == b.data && a.weight == b.weight;
+}
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+}  // namespace
+
+BatchPlan::~BatchPlan() {
+  if (exec_) (void)hipGraphExecDestroy(exec_);
+  if (graph_) (void)hipGraphDestroy(graph_);
+  if (mem_) (void)hipFree(mem_);
+}
+
+bool BatchPlan::matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
+                        int n_points, const double* logl) const {
+  if (theta != theta_ || logl != logl_ || n_points != n_points_ || (size_t)n_systems != systems_.size()) return false;
+  for (int s = 0; s < n_systems; ++s)
+    if (!same_system(systems[s], systems_[s])) return false;
+  return std::equal(map_.begin(), map_.end(), map);
+}
+
+hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
+                            int n_points, double* logl, TileCache& tiles, std::string& msg) {
+  systems_.assign(systems, systems + n_systems);
+  map_.assign(map, map + n_points);
+  theta_ = theta;
+  logl_ = logl;
+  n_points_ = n_points;
+
+  const TileShape ts = tiles.choose_common(systems, n_systems);
+  TW_ = ts.TW;
+  TH_ = ts.TH;
+  std::vector<SysDesc> desc(n_systems);
+  std::vector<size_t> psf_off(n_systems);
+  size_t psf_total = 0;
+  square_psf_ = square_psf_code(systems[0].psf_h, systems[0].psf_w);
+  max_ph_ = max_pw_ = 1;
+  for (int s = 0; s < n_systems; ++s) {
+    desc[s] = make_desc(systems[s], ts);
+    psf_off[s] = psf_total;
+    psf_total += (size_t)systems[s].psf_h * systems[s].psf_w;
+    max_ph_ = std::max(max_ph_, systems[s].psf_h);
+    max_pw_ = std::max(max_pw_, systems[s].psf_w);
+    if (square_psf_code(systems[s].psf_h, systems[s].psf_w) != square_psf_) square_psf_ = -1;
+  }
+
+  std::vector<int64_t> loff(n_points);
+  std::vector<int> pbase(n_points), ntiles(n_points);
+  int64_t Ltot = 0;
+  int ptot = 0;
+  struct Item {
+    int64_t cost;
+    int point, tile;
+  };
+  std::vector<Item> ritems, pitems;
+  for (int p = 0; p < n_points; ++p) {
+    const SysDesc& d = desc[map[p]];
+    loff[p] = Ltot;
+    Ltot += (int64_t)d.H * d.W;
+    pbase[p] = ptot;
+    ntiles[p] = d.n_ptiles;
+    ptot += d.n_ptiles;
+    const int64_t npix = (int64_t)d.H * d.W;
+    for (int t = 0; t < d.n_rtiles; ++t) {
+      const int64_t px = std::min<int64_t>(RENDER_BLOCK, npix - (int64_t)t * RENDER_BLOCK);
+      ritems.push_back({px * d.N * d.N, p, t});
+    }
+    for (int t = 0; t < d.n_ptiles; ++t) pitems.push_back({(int64_t)d.ph * d.pw, p, t});
+  }
+  auto by_cost = [](const Item& a, const Item& b) { return a.cost > b.cost; };
+  std::stable_sort(ritems.begin(), ritems.end(), by_cost);
+  std::stable_sort(pitems.begin(), pitems.end(), by_cost);
+  n_ritems_ = (int)ritems.size();
+  n_pitems_ = (int)pitems.size();
+  std::vector<int2> ri(n_ritems_), pi(n_pitems_);
+  for (int i = 0; i < n_ritems_; ++i) ri[i] = make_int2(ritems[i].point, ritems[i].tile);
+  for (int i = 0; i < n_pitems_; ++i) pi[i] = make_int2(pitems[i].point, pitems[i].tile);
+
+  // one device allocation for every table and scratch buffer of the plan
+  size_t off = 0;
+  const size_t o_sys = off; off = align256(off + sizeof(SysDesc) * n_systems);
+  const size_t o_ps = off; off = align256(off + sizeof(int) * n_points);
+  const size_t o_loff = off; off = align256(off + sizeof(int64_t) * n_points);
+  const size_t o_pb = off; off = align256(off + sizeof(int) * n_points);
+  const size_t o_nt = off; off = align256(off + sizeof(int) * n_points);
+  const size_t o_ri = off; off = align256(off + sizeof(int2) * n_ritems_);
+  const size_t o_pi = off; off = align256(off + sizeof(int2) * n_pitems_);
+  const size_t o_pc = off; off = align256(off + sizeof(PointConst) * n_points);
+  const size_t o_psf = off; off = align256(off + sizeof(float) * psf_total);
+  const size_t o_L = off; off = align256(off + sizeof(float) * (size_t)Ltot);
+  const size_t o_part = off; off = align256(off + sizeof(float2) * (size_t)ptot);
+  hipError_t e = hipMalloc((void**)&mem_, off);
+  if (e != hipSuccess) {
+    msg = "scratch of " + std::to_string(off) + " bytes";
+    mem_ = nullptr;
+    return e;
+  }
+  d_sys_ = (SysDesc*)(mem_ + o_sys);
+  d_point_sys_ = (int*)(mem_ + o_ps);
+  d_loff_ = (int64_t*)(mem_ + o_loff);
+  d_pbase_ = (int*)(mem_ + o_pb);
+  d_ntiles_ = (int*)(mem_ + o_nt);
+  d_ritems_ = (int2*)(mem_ + o_ri);
+  d_pitems_ = (int2*)(mem_ + o_pi);
+  d_pc_ = (PointConst*)(mem_ + o_pc);
+  d_L_ = (float*)(mem_ + o_L);
+  d_part_ = (float2*)(mem_ + o_part);
+  for (int s = 0; s < n_systems; ++s) desc[s].psfn = (float*)(mem_ + o_psf) + psf_off[s];
+
+  std::vector<int> ps(map, map + n_points);
+  if ((e = hipMemcpy(d_sys_, desc.data(), sizeof(SysDesc) * n_systems, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(d_point_sys_, ps.data(), sizeof(int) * n_points, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(d_loff_, loff.data(), sizeof(int64_t) * n_points, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(d_pbase_, pbase.data(), sizeof(int) * n_points, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(d_ntiles_, ntiles.data(), sizeof(int) * n_points, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(d_ritems_, ri.data(), sizeof(int2) * n_ritems_, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(d_pitems_, pi.data(), sizeof(int2) * n_pitems_, hipMemcpyHostToDevice)) != hipSuccess) {
+    msg = "uploading work lists";
+    return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t BatchPlan::enqueue(hipStream_t st) const {
+  WorkArgs w;
+  std::memset(&w, 0, sizeof(w));
+  w.sys_table = d_sys_;
+  w.point_sys = d_point_sys_;
+  w.point_loff = d_loff_;
+  w.point_pbase = d_pbase_;
+  SysDesc none;
+  std::memset(&none, 0, sizeof(none));
+  hipError_t e = launch_prologue(theta_, n_points_, d_pc_, nullptr, none, d_sys_, (int)systems_.size(), st);
+  if (e != hipSuccess) return e;
+  w.items = d_ritems_;
+  w.n_items = n_ritems_;
+  if ((e = launch_render(w, d_pc_, d_L_, n_ritems_, st)) != hipSuccess) return e;
+  w.items = d_pitems_;
+  w.n_items = n_pitems_;
+  if ((e = launch_psf(w, d_L_, nullptr, d_part_, 1, n_pitems_, square_psf_, TW_, TH_, max_ph_, max_pw_, st)) !=
+      hipSuccess)
+    return e;
+  return launch_finalize(d_part_, d_pbase_, d_ntiles_, n_points_, 0, logl_, st);
+}
+
+hipError_t BatchPlan::capture(hipStream_t cap) {
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t le = enqueue(cap);
+  e = hipStreamEndCapture(cap, &graph_);
+  if (le != hipSuccess) return le;
+  if (e != hipSuccess) return e;
+  return hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0);
+}
+
+hipError_t BatchPlan::run(hipStream_t s) const {
+  if (exec_) return hipGraphLaunch(exec_, s);
+  return enqueue(s);
+}
+
+}  // namespace lensed

@@ -1,0 +1,177 @@
+// prologue.hip -- per-point derived constants and PSF normalisation.
+//
+// One thread per parameter point turns the 17 float32 parameters into the
+// wave-uniform constants the render kernels consume (trigonometry, the shear
+// matrix, reciprocal radii and the Sersic b_n). b_n is the root of
+// P(2n, b) = 1/2 (R_e is the half-light radius, Sec. 4.1 Eq. 22), solved here in
+// float64 by a bracketed Newton iteration on the power series of the
+// regularised incomplete gamma function. Extra blocks normalise each system's
+// PSF to unit sum (Sec. 3.1).
+#include <math.h>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace lensed {
+namespace {
+
+// P(a, x) = x^a e^{-x} / Gamma(a+1) * (1 + x/(a+1) + x^2/((a+1)(a+2)) + ...)
+__device__ double inc_gamma_lower_reg(double a, double x) {
+  if (x <= 0.0) return 0.0;
+  double term = 1.0, s = 1.0;
+  for (int k = 1; k < 600; ++k) {
+    term *= x / (a + (double)k);
+    s += term;
+    if (term <= 1e-17 * s) break;
+  }
+  return exp(a * log(x) - x - lgamma(a + 1.0)) * s;
+}
+
+__device__ double sersic_bn(double n) {
+  const double a = 2.0 * n;
+  const double lga = lgamma(a);
+  double lo = 0.0, hi = a + 40.0;
+  // start from the Ciotti & Bertin large-n expansion, kept inside the bracket
+  double b = a - 1.0 / 3.0 + 4.0 / (405.0 * n);
+  if (!(b > lo && b < hi)) b = 0.5 * a + 1e-3;
+  for (int it = 0; it < 100; ++it) {
+    const double f = inc_gamma_lower_reg(a, b) - 0.5;
+    if (f > 0.0) hi = b; else lo = b;
+    const double df = exp((a - 1.0) * log(b) - b - lga);   // dP/dx
+    double nb = b - f / df;
+    if (!(nb > lo && nb < hi)) nb = 0.5 * (lo + hi);
+    const double step = fabs(nb - b);
+    b = nb;
+    if (step <= 4e-16 * b) break;
+  }
+  return b;
+}
+
+// d b_n / dn by Richardson-extrapolated central differences of the root.
+__device__ double sersic_bn_deriv(double n) {
+  const double h = 2e-3 * n;
+  const double d1 = (sersic_bn(n + h) - sersic_bn(n - h)) / (2.0 * h);
+  const double d2 = (sersic_bn(n + 0.5 * h) - sersic_bn(n - 0.5 * h)) / h;
+  return (4.0 * d2 - d1) / 3.0;
+}
+
+__device__ bool ok_q(float q) { return q > 0.0f && q <= 1.0f; }
+__device__ bool ok_n(float n) { return n >= 0.2f && n <= 10.0f; }
+
+__global__ void prologue_kernel(const float* __restrict__ theta, int n_points, PointConst* __restrict__ pcs,
+                                GradConst* __restrict__ gcs, SysDesc single, SysDesc* __restrict__ table,
+                                int n_sys, int point_blocks) {
+  if ((int)blockIdx.x >= point_blocks) {
+    // PSF normalisation: one block per system, float64 sum over the array.
+    const int s = blockIdx.x - point_blocks;
+    const SysDesc sd = table ? table[s] : single;
+    const int n = sd.ph * sd.pw;
+    __shared__ double part[64];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += (double)sd.psf[i];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+      __syncthreads();
+    }
+    const double inv = 1.0 / part[0];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sd.psfn[i] = (float)((double)sd.psf[i] * inv);
+    return;
+  }
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_points) return;
+  float t[NPAR];
+  bool valid = true;
+  for (int k = 0; k < NPAR; ++k) {
+    t[k] = theta[(size_t)p * NPAR + k];
+    valid = valid && isfinite(t[k]);
+  }
+  valid = valid && ok_q(t[1]) && ok_q(t[8]) && ok_q(t[15]) && t[6] > 0.0f && t[13] > 0.0f && ok_n(t[7]) &&
+          ok_n(t[14]);
+
+  PointConst c;
+  const double te = t[0], q = t[1], phL = t[2], g = t[3], phg = t[4];
+  c.cL = (float)cos(phL);
+  c.sL = (float)sin(phL);
+  const double s2 = (1.0 - q) * (1.0 + q);
+  const double qp = sqrt(s2);
+  c.q2 = (float)(q * q);
+  c.qp = (float)qp;
+  c.iq = (float)(1.0 / q);
+  if (s2 == 0.0) {
+    c.sie_mode = 0;
+    c.kc = (float)te;
+    c.ks = 0.0f;
+  } else {
+    c.sie_mode = qp <= 0.5 ? 1 : 2;
+    const double k = te * sqrt(q) / qp;
+    c.kc = (float)(k * cos(phL));
+    c.ks = (float)(k * sin(phL));
+  }
+  const double g1 = g * cos(2.0 * phg), g2 = g * sin(2.0 * phg);
+  c.m11 = (float)(1.0 - g1);
+  c.m12 = (float)(-g2);
+  c.m22 = (float)(1.0 + g1);
+
+  double bh = 0.0, bs = 0.0;
+  if (valid) {
+    bh = sersic_bn(t[7]);
+    bs = sersic_bn(t[14]);
+  }
+  {
+    const double Re = t[6], qh = t[8], ph = t[9];
+    c.hc = (float)cos(ph);
+    c.hs = (float)sin(ph);
+    c.hqa = (float)(qh / (Re * Re));
+    c.hqb = (float)(1.0 / (qh * Re * Re));
+    c.he = (float)(0.5 / (double)t[7]);
+    c.hB = (float)(bh * LOG2E);
+    c.hI = t[5];
+  }
+  {
+    const double Re = t[13], qs = t[15], ph = t[16];
+    c.sx0 = t[10];
+    c.sy0 = t[11];
+    c.sc = (float)cos(ph);
+    c.ss = (float)sin(ph);
+    c.sqa = (float)(qs / (Re * Re));
+    c.sqb = (float)(1.0 / (qs * Re * Re));
+    c.se = (float)(0.5 / (double)t[14]);
+    c.sB = (float)(bs * LOG2E);
+    c.sI = t[12];
+  }
+  for (int k = 0; k < 5; ++k) c.pad[k] = 0.0f;
+  if (!valid) {
+    const float nan = __builtin_nanf("");
+    c.m11 = c.m12 = c.m22 = nan;
+    c.hI = c.sI = nan;
+  }
+  pcs[p] = c;
+
+  if (gcs) {
+    GradConst gc;
+    for (int k = 0; k < NPAR; ++k) gc.theta[k] = t[k];
+    gc.bh = (float)bh;
+    gc.bs = (float)bs;
+    gc.dB_dn_h = valid ? (float)(sersic_bn_deriv(t[7]) * LOG2E) : __builtin_nanf("");
+    gc.dB_dn_s = valid ? (float)(sersic_bn_deriv(t[14]) * LOG2E) : __builtin_nanf("");
+    for (int k = 0; k < 11; ++k) gc.pad[k] = 0.0f;
+    gcs[p] = gc;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, GradConst* gcs, const SysDesc& single,
+                           SysDesc* table, int n_sys, hipStream_t stream) {
+  const int threads = 64;
+  const int point_blocks = (n_points + threads - 1) / threads;
+  const int blocks = point_blocks + n_sys;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(prologue_kernel, dim3(blocks), dim3(threads), 0, stream, theta, n_points, pcs, gcs, single,
+                     table, n_sys, point_blocks);
+  return hipGetLastError();
+}
+
+}  // namespace lensed

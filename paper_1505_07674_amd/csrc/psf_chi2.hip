@@ -1,0 +1,193 @@
+// psf_chi2.hip -- PSF convolution (Sec. 3.1, Eq. 15) fused with the weighted
+// chi^2 of the log-likelihood (Sec. 3.2, Eq. 17).
+//
+// Each block owns a TW x TH tile of output pixels of one image. It stages the
+// tile plus a halo of p rows and q columns in LDS, reading the unconvolved
+// image with clamped indices (the replicate padding of Eq. 15), then every
+// thread computes R vertically adjacent outputs: for each stencil column it
+// keeps R + 2p LDS values in registers and applies the 2p + 1 kernel taps of
+// that column to all R outputs. Kernel taps are wave-uniform (scalar loads).
+// The chi^2 contribution w (d - L*)^2 is accumulated with Kahan summation per
+// thread, combined across the block with error-free TwoSum steps, and written
+// as one (hi, lo) float pair per tile; the final sum over tiles is float64.
+#include "internal.h"
+#include "kernels.h"
+
+namespace lensed {
+namespace {
+
+constexpr int ROWS = 4;   // outputs per thread (R)
+
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+template <int P>
+__global__ __launch_bounds__(512) void psf_kernel(WorkArgs w, const float* __restrict__ L, float* __restrict__ out,
+                                                   float2* __restrict__ partials, int mode) {
+  extern __shared__ float S[];
+  __shared__ float red_hi[16], red_lo[16];
+  int point, tile;
+  if (w.items) {
+    const int2 it = w.items[blockIdx.x];
+    point = it.x;
+    tile = it.y;
+  } else {
+    point = w.point0;
+    tile = blockIdx.x;
+  }
+  const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[point] : 0] : w.single;
+  const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
+  const int p = P >= 0 ? P : sd.ph / 2;
+  const int q = P >= 0 ? P : sd.pw / 2;
+  const int TW = sd.TW, TH = sd.TH;
+  const int SW = TW + 2 * q, SH = TH + 2 * p;
+  const int ty = tile / sd.tiles_x, tx = tile - ty * sd.tiles_x;
+  const int x0 = tx * TW, y0 = ty * TH;
+  const float* __restrict__ Lp = L + loff;
+  const int tid = threadIdx.x;
+  const int jx = tid % TW, jy = tid / TW;
+  const int rows_per_pass = blockDim.x / TW;
+
+  for (int row = jy; row < SH; row += rows_per_pass) {
+    const int gi = min(max(y0 + row - p, 0), sd.H - 1);
+    const float* __restrict__ src = Lp + (size_t)gi * sd.W;
+    for (int col = jx; col < SW; col += TW) {
+      const int gj = min(max(x0 + col - q, 0), sd.W - 1);
+      S[row * SW + col] = src[gj];
+    }
+  }
+  __syncthreads();
+
+  const float* __restrict__ F = sd.psfn;
+  const int i0 = jy * ROWS;
+  float acc[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) acc[r] = 0.0f;
+  if (P >= 0) {
+    constexpr int K = 2 * (P > 0 ? P : 0) + 1;
+    for (int l = 0; l < K; ++l) {
+      float v[ROWS + K - 1];
+#pragma unroll
+      for (int m = 0; m < ROWS + K - 1; ++m) v[m] = S[(i0 + m) * SW + jx + l];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const float f = F[(K - 1 - k) * K + (K - 1 - l)];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) acc[r] = fmaf(f, v[r + k], acc[r]);
+      }
+    }
+  } else {
+    const int KH = 2 * p + 1, KW = 2 * q + 1;
+    for (int l = 0; l < KW; ++l) {
+      for (int k = 0; k < KH; ++k) {
+        const float f = F[(KH - 1 - k) * KW + (KW - 1 - l)];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) acc[r] = fmaf(f, S[(i0 + r + k) * SW + jx + l], acc[r]);
+      }
+    }
+  }
+
+  const int gj = x0 + jx;
+  if (mode == 0) {
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      const int gi = y0 + i0 + r;
+      if (gi < sd.H && gj < sd.W && i0 + r < TH) out[loff + (size_t)gi * sd.W + gj] = acc[r];
+    }
+    return;
+  }
+
+  // Kahan accumulation of w (d - L*)^2 over this thread's outputs.
+  float sum = 0.0f, comp = 0.0f;
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) {
+    const int gi = y0 + i0 + r;
+    if (gi < sd.H && gj < sd.W && i0 + r < TH) {
+      const size_t idx = (size_t)gi * sd.W + gj;
+      const float res = sd.data[idx] - acc[r];
+      const float term = sd.weight[idx] * res * res;
+      const float yk = term - comp;
+      const float t = sum + yk;
+      comp = (t - sum) - yk;
+      sum = t;
+    }
+  }
+  float hi = sum, lo = -comp;
+  // wave reduction with error-free transformations
+  for (int off = 32; off > 0; off >>= 1) {
+    const float h2 = __shfl_down(hi, off, 64);
+    const float l2 = __shfl_down(lo, off, 64);
+    float s, e;
+    two_sum(hi, h2, s, e);
+    hi = s;
+    lo = lo + l2 + e;
+  }
+  const int lane = tid & 63, wid = tid >> 6;
+  if (lane == 0) {
+    red_hi[wid] = hi;
+    red_lo[wid] = lo;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    float h = red_hi[0], lsum = red_lo[0];
+    for (int i = 1; i < nw; ++i) {
+      float s, e;
+      two_sum(h, red_hi[i], s, e);
+      h = s;
+      lsum = lsum + red_lo[i] + e;
+    }
+    const int base = w.point_pbase ? w.point_pbase[point] : 0;
+    partials[base + tile] = make_float2(h, lsum);
+  }
+}
+
+__global__ void finalize_kernel(const float2* __restrict__ partials, const int* __restrict__ pbase,
+                                const int* __restrict__ ntiles, int n_points, int single_ntiles,
+                                double* __restrict__ logl) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_points) return;
+  const int base = pbase ? pbase[p] : 0;
+  const int nt = ntiles ? ntiles[p] : single_ntiles;
+  double s = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    const float2 v = partials[base + t];
+    s += (double)v.x + (double)v.y;
+  }
+  logl[p] = -0.5 * s;
+}
+
+template <int P>
+hipError_t launch_psf_t(const WorkArgs& w, const float* L, float* out, float2* partials, int mode, int n_blocks,
+                        int threads, size_t lds, hipStream_t stream) {
+  hipLaunchKernelGGL(psf_kernel<P>, dim3(n_blocks), dim3(threads), lds, stream, w, L, out, partials, mode);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_psf(const WorkArgs& w, const float* L, float* out, float2* partials, int mode, int n_blocks,
+                      int square_psf, int TW, int TH, int max_ph, int max_pw, hipStream_t stream) {
+  if (n_blocks <= 0) return hipSuccess;
+  const int threads = TW * (TH / ROWS);
+  const size_t lds = sizeof(float) * (size_t)(TW + max_pw - 1) * (size_t)(TH + max_ph - 1);
+  // Specialised stencils for the square PSFs of the standard workloads.
+  if (square_psf == 21) return launch_psf_t<10>(w, L, out, partials, mode, n_blocks, threads, lds, stream);
+  if (square_psf == 7) return launch_psf_t<3>(w, L, out, partials, mode, n_blocks, threads, lds, stream);
+  if (square_psf == 1) return launch_psf_t<0>(w, L, out, partials, mode, n_blocks, threads, lds, stream);
+  return launch_psf_t<-1>(w, L, out, partials, mode, n_blocks, threads, lds, stream);
+}
+
+hipError_t launch_finalize(const float2* partials, const int* point_pbase, const int* point_ntiles, int n_points,
+                           int single_ntiles, double* logl, hipStream_t stream) {
+  if (n_points <= 0) return hipSuccess;
+  const int threads = 64;
+  hipLaunchKernelGGL(finalize_kernel, dim3((n_points + threads - 1) / threads), dim3(threads), 0, stream, partials,
+                     point_pbase, point_ntiles, n_points, single_ntiles, logl);
+  return hipGetLastError();
+}
+
+}  // namespace lensed

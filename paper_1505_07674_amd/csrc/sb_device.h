@@ -1,0 +1,133 @@
+// sb_device.h -- surface brightness of the image plane at one subsample, float32.
+//
+// Lens equation beta = x - alpha(x) (Sec. 2.1, Eq. 1) through a singular
+// isothermal ellipsoid (Kormann et al. 1994, as used in Sec. 4) and an external
+// shear; I(x) = I_lens(x) + I_source(beta) (Eq. 2) with elliptical Sersic
+// profiles (Sec. 4.1, Eqs. 22-23).
+//
+// Everything is written in base 2 for the hardware v_exp_f32 / v_log_f32:
+//   Sersic   I = I_e exp(-b [(R/R_e)^{1/n} - 1]) = I_e 2^{B (1 - t)},
+//            t = 2^{log2(R^2/R_e^2) / (2n)},  B = b log2(e)
+//   SIE      alpha'_x = k atan(q' x'/psi),  alpha'_y = k atanh(q' y'/psi),
+//            k = theta_E sqrt(q)/q',  psi = sqrt(q^2 x'^2 + y'^2)
+// atan uses a minimax polynomial on |u| <= 1; atanh a minimax polynomial on
+// |v| <= 1/2 (q' <= 1/2) and otherwise the identity
+//   atanh(q' y'/psi) = sign(y') ln((psi + q'|y'|) / (q r)),  r = sqrt(x'^2 + y'^2),
+// which has no cancellation for any q. At psi = 0 the deflection is zero.
+#pragma once
+
+#include "internal.h"
+#include "sie_poly.h"
+
+namespace lensed {
+
+__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <int DEG>
+__device__ __forceinline__ float horner(const float (&c)[DEG + 1], float s) {
+  float p = c[DEG];
+#pragma unroll
+  for (int k = DEG - 1; k >= 0; --k) p = fmaf(p, s, c[k]);
+  return p;
+}
+
+__device__ __forceinline__ float atan_poly(float u) { return u * horner<ATAN_POLY_DEGREE>(ATAN_POLY, u * u); }
+__device__ __forceinline__ float atanh_poly(float v) { return v * horner<ATANH_POLY_DEGREE>(ATANH_POLY, v * v); }
+
+// Source-plane position of image-plane point (x, y).
+template <int MODE>
+__device__ __forceinline__ void lens_map(const PointConst& c, float x, float y, float& bx, float& by) {
+  if (MODE == 0) {
+    const float r2 = fmaf(x, x, y * y);
+    const float ir = r2 > 0.0f ? hw_rsq(r2) : 0.0f;
+    const float s = c.kc * ir;
+    bx = fmaf(c.m11, x, fmaf(c.m12, y, -s * x));
+    by = fmaf(c.m12, x, fmaf(c.m22, y, -s * y));
+  } else {
+    const float xp = fmaf(c.cL, x, c.sL * y);
+    const float yp = fmaf(c.cL, y, -c.sL * x);
+    const float yp2 = yp * yp;
+    const float psi2 = fmaf(c.q2 * xp, xp, yp2);
+    const float ip = psi2 > 0.0f ? hw_rsq(psi2) : 0.0f;
+    const float tq = c.qp * ip;
+    const float At = atan_poly(tq * xp);
+    float Ah;
+    if (MODE == 1) {
+      Ah = atanh_poly(tq * yp);
+    } else {
+      const float r2 = fmaf(xp, xp, yp2);
+      const float ir = hw_rsq(r2);
+      const float psi = psi2 * ip;
+      const float num = fmaf(c.qp, fabsf(yp), psi);
+      const float l = LN2F * hw_log2(num * ir * c.iq);
+      Ah = psi2 > 0.0f ? copysignf(l, yp) : 0.0f;
+    }
+    const float ax = fmaf(c.kc, At, -c.ks * Ah);
+    const float ay = fmaf(c.ks, At, c.kc * Ah);
+    bx = fmaf(c.m11, x, fmaf(c.m12, y, -ax));
+    by = fmaf(c.m12, x, fmaf(c.m22, y, -ay));
+  }
+}
+
+// Sersic value for offsets (dx, dy) from the centre: rotation (c, s), scaled
+// axis factors qa = q/R_e^2, qb = 1/(q R_e^2), e = 1/(2n), B = b_n log2(e), amplitude I_e.
+__device__ __forceinline__ float sersic_b2(float dx, float dy, float cs, float sn, float qa, float qb, float e,
+                                           float B, float Ie) {
+  const float xp = fmaf(cs, dx, sn * dy);
+  const float yp = fmaf(cs, dy, -sn * dx);
+  const float R2 = fmaf(qa * xp, xp, qb * yp * yp);
+  const float t = hw_exp2(e * hw_log2(R2));
+  return Ie * hw_exp2(fmaf(-B, t, B));
+}
+
+template <int MODE>
+__device__ __forceinline__ float surface_brightness(const PointConst& c, float x, float y) {
+  float bx, by;
+  lens_map<MODE>(c, x, y, bx, by);
+  const float Ih = sersic_b2(x, y, c.hc, c.hs, c.hqa, c.hqb, c.he, c.hB, c.hI);
+  const float Is = sersic_b2(bx - c.sx0, by - c.sy0, c.sc, c.ss, c.sqa, c.sqb, c.se, c.sB, c.sI);
+  return Ih + Is;
+}
+
+// Midpoint offset of subsample k of N, in pixel units: (k + 1/2)/N - 1/2.
+template <int N>
+__device__ __forceinline__ constexpr float sub_offset(int k) {
+  return (float(k) + 0.5f) / float(N) - 0.5f;
+}
+
+// Sum of the surface brightness over the N x N midpoint abscissae of a pixel
+// whose centre is (ux, uy) pixels from the grid centre.
+template <int N, int MODE>
+__device__ __forceinline__ float pixel_sum(const PointConst& c, float ux, float uy, float d, float cx, float cy) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int ky = 0; ky < N; ++ky) {
+    const float y = fmaf(uy + sub_offset<N>(ky), d, cy);
+#pragma unroll
+    for (int kx = 0; kx < N; ++kx) {
+      const float x = fmaf(ux + sub_offset<N>(kx), d, cx);
+      acc += surface_brightness<MODE>(c, x, y);
+    }
+  }
+  return acc;
+}
+
+template <int MODE>
+__device__ __forceinline__ float pixel_sum_rt(const PointConst& c, int N, float ux, float uy, float d, float cx,
+                                              float cy) {
+  float acc = 0.0f;
+  const float invN = 1.0f / float(N);
+  for (int ky = 0; ky < N; ++ky) {
+    const float y = fmaf(uy + ((float(ky) + 0.5f) * invN - 0.5f), d, cy);
+    for (int kx = 0; kx < N; ++kx) {
+      const float x = fmaf(ux + ((float(kx) + 0.5f) * invN - 0.5f), d, cx);
+      acc += surface_brightness<MODE>(c, x, y);
+    }
+  }
+  return acc;
+}
+
+}  // namespace lensed

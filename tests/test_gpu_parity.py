@@ -1,0 +1,205 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars (per point): per-pixel max |delta| <= 1e-5 x peak |oracle pixel|, and
+|delta log L| <= 1e-6 x max(|log L_oracle|, N_w/2) where N_w counts weighted
+pixels (the expected |log L| at the truth; avoids 0/0 for noiseless data).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1505_07674_amd as lensed
+from paper_1505_07674_amd import mocks
+
+from helpers import f32, loglike_tolerance, observation, oracle_loglikes, oracle_system
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def gpu_system(spec, obs=None):
+    data = None if obs is None else torch.from_numpy(obs.data).to(DEV)
+    weight = None if obs is None else torch.from_numpy(obs.weight).to(DEV)
+    return lensed.System(torch.from_numpy(spec.psf).to(DEV), data, weight, pixscale=spec.pixscale,
+                         nsub=spec.nsub, height=spec.height, width=spec.width,
+                         center=(spec.center_x, spec.center_y))
+
+
+def check_images(spec, thetas, apply_psf):
+    gsys = gpu_system(spec)
+    osys = oracle_system(spec)
+    worst = 0.0
+    for t in thetas:
+        img = lensed.render(torch.from_numpy(t).to(DEV), gsys, apply_psf=apply_psf).cpu().numpy().astype(np.float64)
+        ref = oracle.render(osys, t.astype(np.float64), apply_psf=apply_psf)
+        err = np.max(np.abs(img - ref)) / np.max(np.abs(ref))
+        worst = max(worst, err)
+        assert err <= 1e-5, f"pixel error {err:.3e} x peak at theta={t.tolist()}"
+    return worst
+
+
+def test_c0_render_parity():
+    spec, _ = observation("c0")
+    say("c0 render parity")
+    pts = mocks.points(spec, 24, seed=mocks.C0_POINT_SEED)
+    check_images(spec, pts, True)
+    check_images(spec, pts[:8], False)
+
+
+def test_c0_loglike_batch_parity_all_points():
+    spec, obs = observation("c0")
+    say("c0 loglike batch, 1000 points")
+    pts = mocks.points(spec, 1000, seed=mocks.C0_POINT_SEED)
+    gsys = gpu_system(spec, obs)
+    ll = lensed.loglike_batch(torch.from_numpy(pts).to(DEV), np.zeros(1000, np.int32), [gsys]).cpu().numpy()
+    ref = oracle_loglikes(oracle_system(spec, obs), pts)
+    tol = loglike_tolerance(ref, obs.weight)
+    bad = np.nonzero(np.abs(ll - ref) > tol)[0]
+    assert bad.size == 0, f"{bad.size} points off, e.g. {ll[bad[:3]]} vs {ref[bad[:3]]}"
+
+
+def test_c0_plain_matches_batch_and_oracle():
+    spec, obs = observation("c0")
+    say("c0 plain loglike")
+    pts = mocks.points(spec, 48, seed=11)
+    gsys = gpu_system(spec, obs)
+    tp = torch.from_numpy(pts).to(DEV)
+    plain = torch.cat([lensed.loglike(tp[i], gsys) for i in range(len(pts))]).cpu().numpy()
+    batch = lensed.loglike_batch(tp, np.zeros(len(pts), np.int32), [gsys]).cpu().numpy()
+    ref = oracle_loglikes(oracle_system(spec, obs), pts)
+    tol = loglike_tolerance(ref, obs.weight)
+    assert np.all(np.abs(plain - ref) <= tol)
+    assert np.all(np.abs(batch - ref) <= tol)
+    assert np.all(np.abs(plain - batch) <= tol)
+
+
+def test_c1_render_parity():
+    spec, _ = observation("c1")
+    say("c1 render parity")
+    pts = np.concatenate([spec.truth[None, :], mocks.points(spec, 5, seed=mocks.C1_POINT_SEED)])
+    check_images(spec, pts, True)
+    check_images(spec, pts[:2], False)
+
+
+def test_c1_loglike_batch_parity_full_launch():
+    """The 4096-point batch the benchmark times; the oracle checks a spread sample."""
+    spec, obs = observation("c1")
+    say("c1 loglike batch, 4096 points")
+    pts = mocks.points(spec, 4096, seed=mocks.C1_POINT_SEED)
+    pts[0] = spec.truth
+    gsys = gpu_system(spec, obs)
+    ll = lensed.loglike_batch(torch.from_numpy(pts).to(DEV), np.zeros(4096, np.int32), [gsys]).cpu().numpy()
+    assert np.all(np.isfinite(ll))
+    idx = np.unique(np.concatenate([[0, 1, 4095], np.linspace(2, 4094, 29).astype(int)]))
+    ref = oracle_loglikes(oracle_system(spec, obs), pts[idx])
+    tol = loglike_tolerance(ref, obs.weight)
+    err = np.abs(ll[idx] - ref)
+    assert np.all(err <= tol), f"worst relative {np.max(err / tol) * 1e-6:.3e}"
+
+
+def test_c1_plain_matches_oracle():
+    spec, obs = observation("c1")
+    say("c1 plain loglike")
+    pts = mocks.points(spec, 6, seed=21)
+    gsys = gpu_system(spec, obs)
+    tp = torch.from_numpy(pts).to(DEV)
+    plain = torch.cat([lensed.loglike(tp[i], gsys) for i in range(len(pts))]).cpu().numpy()
+    ref = oracle_loglikes(oracle_system(spec, obs), pts)
+    assert np.all(np.abs(plain - ref) <= loglike_tolerance(ref, obs.weight))
+
+
+def _custom_spec(H, W, N, psf, pixscale=0.07, center=(0.1, -0.05)):
+    base = mocks.c1_spec()
+    return mocks.SystemSpec(f"custom_{H}x{W}_sub{N}", H, W, N, psf.astype(np.float32), base.truth, base.prior,
+                            np.ones((H, W), bool), 77, False, pixscale=pixscale, center_x=center[0],
+                            center_y=center[1])
+
+
+@pytest.mark.parametrize("H,W,N,ph,pw", [
+    (37, 53, 3, 5, 9),       # ragged tiles, generic stencil, odd N
+    (64, 64, 1, 1, 1),       # point rule, no blurring
+    (1, 1, 2, 3, 3),         # single pixel
+    (5, 129, 5, 7, 7),       # thin strip, specialised 7x7 stencil
+    (90, 33, 16, 21, 21),    # largest N, specialised 21x21 stencil, ragged
+    (20, 20, 9, 3, 5),       # N outside the specialised set
+])
+def test_ragged_and_generic_shapes(H, W, N, ph, pw):
+    say(f"shape {H}x{W} N={N} psf {ph}x{pw}")
+    rng = np.random.default_rng(H * 1000 + W)
+    psf = rng.random((ph, pw)) + 0.1
+    spec = _custom_spec(H, W, N, psf)
+    pts = mocks.points(spec, 3, seed=5)
+    check_images(spec, pts, True)
+    osys = oracle_system(spec)
+    model = oracle.render(osys, spec.truth.astype(np.float64))
+    obs = mocks.Observation(spec, (model + 0.01 * rng.standard_normal(model.shape)).astype(np.float32),
+                            (rng.random(model.shape) < 0.8).astype(np.float32) * 1e4, 0.01)
+    gsys = gpu_system(spec, obs)
+    tp = torch.from_numpy(pts).to(DEV)
+    ll = lensed.loglike_batch(tp, np.zeros(len(pts), np.int32), [gsys]).cpu().numpy()
+    ref = oracle_loglikes(oracle_system(spec, obs), pts)
+    assert np.all(np.abs(ll - ref) <= loglike_tolerance(ref, obs.weight))
+    plain = lensed.loglike(tp[0], gsys).cpu().numpy()[0]
+    assert abs(plain - ref[0]) <= loglike_tolerance(ref[:1], obs.weight)[0]
+
+
+def test_mixed_batch_c2_sampled():
+    """16 systems of mixed size and subsampling, 512 points each, one graph launch."""
+    specs = mocks.c2_specs()
+    say("c2 mixed batch, 16 systems x 512 points")
+    systems, obs_all, pts_all, sop = [], [], [], []
+    for s, spec in enumerate(specs):
+        _, obs = observation("c2", s)
+        obs_all.append(obs)
+        systems.append(gpu_system(spec, obs))
+        pts_all.append(mocks.points(spec, 512, seed=mocks.C2_BASE_SEED * 100 + s))
+        sop.append(np.full(512, s, np.int32))
+    pts = np.concatenate(pts_all)
+    sop = np.concatenate(sop)
+    ll = lensed.loglike_batch(torch.from_numpy(pts).to(DEV), sop, systems).cpu().numpy()
+    assert np.all(np.isfinite(ll))
+    for s, spec in enumerate(specs):
+        idx = [s * 512, s * 512 + 511]
+        ref = oracle_loglikes(oracle_system(spec, obs_all[s]), pts[idx])
+        assert np.all(np.abs(ll[idx] - ref) <= loglike_tolerance(ref, obs_all[s].weight)), spec.name
+
+
+def test_invalid_points_give_nan_only_there():
+    spec, obs = observation("c0")
+    say("invalid points")
+    pts = mocks.points(spec, 6, seed=3)
+    pts[1, 1] = 1.5        # q > 1
+    pts[3, 13] = -0.2      # R_e < 0
+    pts[4, 0] = np.nan
+    gsys = gpu_system(spec, obs)
+    ll = lensed.loglike_batch(torch.from_numpy(pts).to(DEV), np.zeros(6, np.int32), [gsys]).cpu().numpy()
+    assert np.all(np.isnan(ll[[1, 3, 4]]))
+    assert np.all(np.isfinite(ll[[0, 2, 5]]))
+
+
+def test_invalid_arguments_return_status():
+    spec, obs = observation("c0")
+    gsys = gpu_system(spec, obs)
+    tp = torch.from_numpy(spec.truth).to(DEV)
+    ctx = lensed.default_context(0)
+    from paper_1505_07674_amd import binding
+    bad = binding.LensedSystemC.from_buffer_copy(gsys.c_struct)
+    out = torch.empty(1, dtype=torch.float64, device=DEV)
+    stream = torch.cuda.current_stream().cuda_stream
+    import ctypes
+    for field, val in [("psf_h", 4), ("nsub", 0), ("nsub", 17), ("height", 0), ("pixscale", -1.0)]:
+        b = binding.LensedSystemC.from_buffer_copy(gsys.c_struct)
+        setattr(b, field, val)
+        rc = binding.lib().lensed_loglike(ctx.handle, ctypes.byref(b), ctypes.c_void_p(tp.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream))
+        assert rc == 1, (field, val)
+    with pytest.raises(lensed.LensedError):
+        lensed.loglike_batch(tp.view(1, 17), [3], [gsys])
+    del bad
