@@ -1,0 +1,187 @@
+"""Throughput of the batched forward-lensing log-likelihood on one MI355X.
+
+A step is one batched evaluation of the whole hot path (per-point prologue,
+subsample ray-tracing render, PSF + chi^2, float64 finalise) for 4096 parameter
+points of the 200x200, 4x4-subsampled, 21x21-Moffat SIE + shear + Sersic model,
+with every input resident in HBM. Prints ONE JSON line (rank 0).
+
+Also reported: the plain one-point-per-launch form on the same points, the
+roofline of the dominant kernel (render) from per-stage hipEvents, and the FP64
+oracle timed on the host cores on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic work per unit (add, mul, fma, div, sqrt and each elementary
+# function counted as one op): 84 per subsample of the model, 2 per PSF tap and
+# 5 per pixel for the chi^2.
+OPS_PER_SUBSAMPLE = 84
+FP32_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--points", type=int, default=4096)
+    ap.add_argument("--plain-points", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-points-per-core", type=int, default=4)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(spec, thetas, per_core):
+    """FP64 oracle log L on the host cores: one serial point per thread."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    from paper_1505_07674_amd import mocks
+
+    px = float(np.float32(spec.pixscale))
+    osys = oracle.System(spec.height, spec.width, px, spec.nsub, spec.psf.astype(np.float64))
+    obs = mocks.make_observation(spec, lambda t: oracle.render(osys, np.asarray(t, np.float64)))
+    osys = oracle.System(spec.height, spec.width, px, spec.nsub, spec.psf.astype(np.float64),
+                         obs.data.astype(np.float64), obs.weight.astype(np.float64))
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    n = cores * per_core
+    sample = [np.asarray(t, np.float64) for t in thetas[:n]]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        vals = list(ex.map(lambda t: oracle.loglike(osys, t), sample))
+    dt = time.perf_counter() - t0
+    assert all(math.isfinite(v) for v in vals)
+    return {"value": n / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} points of the same 4096-point C1 workload, {per_core} per thread, "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the path shards by points across GPUs, but no multi-GPU run is part of it)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1505_07674_amd as lensed
+    from paper_1505_07674_amd import mocks
+
+    dev = torch.device("cuda:0")
+    spec = mocks.c1_spec()
+    psf = torch.from_numpy(spec.psf).to(dev)
+    rsys = lensed.System(psf, pixscale=spec.pixscale, nsub=spec.nsub, height=spec.height, width=spec.width)
+    # synthetic mock rendered by the library itself (inputs only; no parity claim here)
+    obs = mocks.make_observation(
+        spec, lambda t: lensed.render(torch.from_numpy(np.asarray(t, np.float32)).to(dev), rsys).cpu().numpy())
+    gsys = lensed.System(psf, torch.from_numpy(obs.data).to(dev), torch.from_numpy(obs.weight).to(dev),
+                         pixscale=spec.pixscale, nsub=spec.nsub)
+    P = args.points
+    pts = mocks.points(spec, P, seed=mocks.C1_POINT_SEED)
+    theta = torch.from_numpy(pts).to(dev)
+    sop = np.zeros(P, np.int32)
+    out = torch.empty(P, dtype=torch.float64, device=dev)
+    ctx = lensed.default_context(0)
+    stream = torch.cuda.current_stream()
+
+    log(f"batched: {P} points, warmup {args.warmup}")
+    for _ in range(args.warmup):
+        lensed.loglike_batch(theta, sop, [gsys], out=out, ctx=ctx)
+    torch.cuda.synchronize()
+    log(f"batched: timing {args.steps} steps")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        lensed.loglike_batch(theta, sop, [gsys], out=out, ctx=ctx)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    value = P * args.steps / (ms_total / 1e3)
+    assert torch.isfinite(out).all().item(), "non-finite log L in the timed batch"
+
+    # per-stage kernel durations over an equal number of profiled steps
+    log("batched: per-stage hipEvent timing")
+    ctx.set_profiling(True)
+    ctx.stage_times()
+    for _ in range(args.steps):
+        lensed.loglike_batch(theta, sop, [gsys], out=out, ctx=ctx)
+    stages, calls = ctx.stage_times()
+    ctx.set_profiling(False)
+    stage_ms = {k: v / calls for k, v in stages.items()}
+    subs = spec.height * spec.width * spec.nsub ** 2
+    render_flops = OPS_PER_SUBSAMPLE * subs * P
+    achieved = render_flops / (stage_ms["render"] * 1e-3) / 1e12
+    taps = spec.psf.shape[0] * spec.psf.shape[1]
+    psf_flops = (2 * taps + 5) * spec.height * spec.width * P
+    psf_tflops = psf_flops / (stage_ms["psf_chi2"] * 1e-3) / 1e12
+
+    # plain form: one launch sequence per point, back-to-back, one sync at the end
+    n_plain = min(args.plain_points, P)
+    log(f"plain: {n_plain} points")
+    outs = torch.empty(n_plain, dtype=torch.float64, device=dev)
+    for i in range(min(8, n_plain)):
+        lensed.loglike(theta[i], gsys, out=outs[i:i + 1], ctx=ctx)
+    torch.cuda.synchronize()
+    p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    p0.record(stream)
+    for i in range(n_plain):
+        lensed.loglike(theta[i], gsys, out=outs[i:i + 1], ctx=ctx)
+    p1.record(stream)
+    torch.cuda.synchronize()
+    plain_value = n_plain / (p0.elapsed_time(p1) / 1e3)
+    rel = (outs - out[:n_plain]).abs() / out[:n_plain].abs().clamp_min(1.0)
+    assert rel.max().item() < 1e-5, "plain and batched log L disagree"
+
+    result = {
+        "metric": "log-likelihood evals/sec at 200x200, 4x4 subsample (batched)",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c1_200x200_sie_shear_sersic_sub4_moffat21_batch4096",
+                   "points_per_step": P, "image": [spec.height, spec.width], "nsub": spec.nsub,
+                   "psf": "21x21 Moffat beta=3 FWHM 0.1 arcsec", "params": 17,
+                   "mask": "annulus 0.3-3.0 arcsec (all pixels rendered)"},
+        "plain": {"value": plain_value, "unit": "evals/s", "points": n_plain,
+                  "form": "one prologue/render/psf/finalize launch sequence per point, one sync"},
+        "batched_over_plain": value / plain_value,
+        "stage_ms_per_step": stage_ms,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "render", "ops_per_subsample": OPS_PER_SUBSAMPLE,
+                     "subsamples_per_launch": subs * P},
+        "psf_chi2_tflops": psf_tflops,
+        "wall_s_timed": wall,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on host cores")
+        result["cpu_baseline"] = cpu_baseline(spec, pts, args.cpu_points_per_core)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

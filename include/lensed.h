@@ -139,6 +139,17 @@ int lensed_loglike_batch(lensed_ctx* ctx, const lensed_system* systems, int n_sy
 int lensed_loglike_grad(lensed_ctx* ctx, const lensed_system* sys, const float* theta,
                         int n_points, double* logl, float* grad, void* stream);
 
+/* Instrumentation. With profiling enabled, lensed_loglike_batch runs its stages
+ * without the captured graph and records a hipEvent between consecutive stages
+ * on `stream`. lensed_stage_times waits for the recorded events and returns,
+ * summed over the profiled calls since the previous query, the milliseconds of
+ *   ms[0] prologue, ms[1] render, ms[2] PSF + chi^2, ms[3] finalize
+ * (ms is a HOST array of at least LENSED_NSTAGES doubles; *calls, if not NULL,
+ * receives the number of calls summed), then resets the sums. */
+#define LENSED_NSTAGES 4
+int lensed_set_profiling(lensed_ctx* ctx, int enable);
+int lensed_stage_times(lensed_ctx* ctx, double* ms, int n, int* calls);
+
 #ifdef __cplusplus
 }
 #endif

@@ -63,6 +63,8 @@ def lib():
                 "lensed_loglike": (i, [vp, sp, vp, vp, vp]),
                 "lensed_loglike_batch": (i, [vp, sp, i, vp, ctypes.POINTER(ctypes.c_int32), i, vp, vp]),
                 "lensed_loglike_grad": (i, [vp, sp, vp, i, vp, vp, vp]),
+                "lensed_set_profiling": (i, [vp, i]),
+                "lensed_stage_times": (i, [vp, ctypes.POINTER(ctypes.c_double), i, ctypes.POINTER(ctypes.c_int)]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)
@@ -91,6 +93,20 @@ class Context:
         if rc != LENSED_OK:
             msg = lib().lensed_last_error(self._h)
             raise LensedError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    STAGES = ("prologue", "render", "psf_chi2", "finalize")
+
+    def set_profiling(self, enable: bool):
+        """Run batched calls stage by stage with hipEvents between the stages (no graph)."""
+        self.check(lib().lensed_set_profiling(self._h, int(bool(enable))), "lensed_set_profiling")
+
+    def stage_times(self):
+        """Summed per-stage milliseconds of the profiled calls since the last query, and their count."""
+        ms = (ctypes.c_double * len(self.STAGES))()
+        calls = ctypes.c_int()
+        self.check(lib().lensed_stage_times(self._h, ms, len(self.STAGES), ctypes.byref(calls)),
+                   "lensed_stage_times")
+        return dict(zip(self.STAGES, list(ms))), calls.value
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -26,6 +26,10 @@ struct lensed_ctx {
   bool use_graphs = true;
   std::vector<std::unique_ptr<BatchPlan>> plans;   // most recently used last
   TileCache tiles;
+  bool profiling = false;                          // per-stage hipEvents, no graphs
+  std::vector<std::vector<hipEvent_t>> pending;    // event sets of profiled calls
+  double stage_ms[LENSED_NSTAGES] = {0};
+  int stage_calls = 0;
 };
 
 namespace {
@@ -163,6 +167,8 @@ void lensed_destroy(lensed_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   c->plans.clear();
+  for (auto& ev : c->pending)
+    for (auto& e : ev) (void)hipEventDestroy(e);
   if (c->arena) (void)hipFree(c->arena);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
@@ -271,7 +277,41 @@ int lensed_loglike_batch(lensed_ctx* c, const lensed_system* systems, int n_syst
     c->plans.push_back(std::move(np));
     plan = c->plans.back().get();
   }
+  if (c->profiling) {
+    std::vector<hipEvent_t> ev(LENSED_NSTAGES + 1);
+    for (auto& e : ev) LENSED_HIP(c, hipEventCreate(&e));
+    LENSED_HIP(c, plan->enqueue((hipStream_t)stream, ev.data()));
+    c->pending.push_back(std::move(ev));
+    return LENSED_OK;
+  }
   LENSED_HIP(c, plan->run((hipStream_t)stream));
+  return LENSED_OK;
+}
+
+int lensed_set_profiling(lensed_ctx* c, int enable) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  c->profiling = enable != 0;
+  return LENSED_OK;
+}
+
+int lensed_stage_times(lensed_ctx* c, double* ms, int n, int* calls) {
+  if (!c || !ms || n < LENSED_NSTAGES) return set_err(c, LENSED_INVALID_ARGUMENT, "ms needs LENSED_NSTAGES slots");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  for (auto& ev : c->pending) {
+    LENSED_HIP(c, hipEventSynchronize(ev.back()));
+    for (int k = 0; k < LENSED_NSTAGES; ++k) {
+      float t = 0.0f;
+      LENSED_HIP(c, hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+      c->stage_ms[k] += t;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    c->stage_calls += 1;
+  }
+  c->pending.clear();
+  for (int k = 0; k < LENSED_NSTAGES; ++k) ms[k] = c->stage_ms[k];
+  if (calls) *calls = c->stage_calls;
+  for (int k = 0; k < LENSED_NSTAGES; ++k) c->stage_ms[k] = 0.0;
+  c->stage_calls = 0;
   return LENSED_OK;
 }
 

@@ -51,7 +51,9 @@ class BatchPlan {
   hipError_t build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
                    int n_points, double* logl, TileCache& tiles, std::string& msg);
   hipError_t capture(hipStream_t cap);
-  hipError_t enqueue(hipStream_t s) const;
+  // events, when given, are 5 events recorded around the 4 stages
+  // (prologue, render, PSF + chi^2, finalize)
+  hipError_t enqueue(hipStream_t s, hipEvent_t* events = nullptr) const;
   hipError_t run(hipStream_t s) const;
 
  private:

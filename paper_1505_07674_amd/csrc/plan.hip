@@ -185,7 +185,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   return hipSuccess;
 }
 
-hipError_t BatchPlan::enqueue(hipStream_t st) const {
+hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
   WorkArgs w;
   std::memset(&w, 0, sizeof(w));
   w.sys_table = d_sys_;
@@ -194,17 +194,24 @@ hipError_t BatchPlan::enqueue(hipStream_t st) const {
   w.point_pbase = d_pbase_;
   SysDesc none;
   std::memset(&none, 0, sizeof(none));
-  hipError_t e = launch_prologue(theta_, n_points_, d_pc_, nullptr, none, d_sys_, (int)systems_.size(), st);
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
+  if ((e = launch_prologue(theta_, n_points_, d_pc_, nullptr, none, d_sys_, (int)systems_.size(), st)) != hipSuccess)
+    return e;
+  if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
   w.items = d_ritems_;
   w.n_items = n_ritems_;
   if ((e = launch_render(w, d_pc_, d_L_, n_ritems_, st)) != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
   w.items = d_pitems_;
   w.n_items = n_pitems_;
   if ((e = launch_psf(w, d_L_, nullptr, d_part_, 1, n_pitems_, square_psf_, TW_, TH_, max_ph_, max_pw_, st)) !=
       hipSuccess)
     return e;
-  return launch_finalize(d_part_, d_pbase_, d_ntiles_, n_points_, 0, logl_, st);
+  if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
+  if ((e = launch_finalize(d_part_, d_pbase_, d_ntiles_, n_points_, 0, logl_, st)) != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[4], st)) != hipSuccess) return e;
+  return hipSuccess;
 }
 
 hipError_t BatchPlan::capture(hipStream_t cap) {

