@@ -113,6 +113,7 @@ SysDesc make_desc(const lensed_system& s, const TileShape& t) {
   d.tiles_x = (s.width + t.TW - 1) / t.TW;
   d.n_ptiles = d.tiles_x * ((s.height + t.TH - 1) / t.TH);
   d.n_rtiles = (int)(((int64_t)s.height * s.width + RENDER_BLOCK - 1) / RENDER_BLOCK);
+  d.wgt = (double)s.pixscale * (double)s.pixscale / ((double)s.nsub * (double)s.nsub);
   return d;
 }
 
@@ -186,18 +187,23 @@ int lensed_render(lensed_ctx* c, const lensed_system* sys, const float* theta, f
   SysDesc sd = make_desc(*sys, ts);
   const size_t npix = (size_t)sd.H * sd.W;
   const size_t off_pc = 0;
-  const size_t off_psf = align_up(off_pc + sizeof(PointConst), 256);
-  const size_t off_L = align_up(off_psf + sizeof(float) * sd.ph * sd.pw, 256);
+  const size_t off_p64 = align_up(off_pc + sizeof(PointConst), 256);
+  const size_t off_psf = align_up(off_p64 + sizeof(PointConst64), 256);
+  const size_t off_cc = align_up(off_psf + sizeof(float) * sd.ph * sd.pw, 256);
+  const size_t off_ce = align_up(off_cc + sizeof(int), 256);
+  const size_t off_L = align_up(off_ce + sizeof(CuspEntry) * (size_t)sd.n_rtiles * (RENDER_BLOCK / 64), 256);
   const size_t total = align_up(off_L + sizeof(float) * npix, 256);
   if ((rc = ensure_arena(c, total))) return rc;
   PointConst* pc = (PointConst*)(c->arena + off_pc);
+  PointConst64* p64 = (PointConst64*)(c->arena + off_p64);
+  CuspList cl{(CuspEntry*)(c->arena + off_ce), (int*)(c->arena + off_cc)};
   sd.psfn = (float*)(c->arena + off_psf);
   float* L = apply_psf ? (float*)(c->arena + off_L) : image;
   WorkArgs w;
   std::memset(&w, 0, sizeof(w));
   w.single = sd;
-  LENSED_HIP(c, launch_prologue(theta, 1, pc, nullptr, sd, nullptr, 1, st));
-  LENSED_HIP(c, launch_render(w, pc, L, sd.n_rtiles, st));
+  LENSED_HIP(c, launch_prologue(theta, 1, pc, p64, nullptr, sd, nullptr, 1, cl.count, st));
+  LENSED_HIP(c, launch_render(w, pc, p64, L, sd.n_rtiles, cl, st));
   if (apply_psf)
     LENSED_HIP(c, launch_psf(w, L, image, nullptr, 0, sd.n_ptiles, square_psf_code(sd.ph, sd.pw), sd.TW, sd.TH,
                              sd.ph, sd.pw, st));
@@ -215,20 +221,25 @@ int lensed_loglike(lensed_ctx* c, const lensed_system* sys, const float* theta, 
   SysDesc sd = make_desc(*sys, ts);
   const size_t npix = (size_t)sd.H * sd.W;
   const size_t off_pc = 0;
-  const size_t off_psf = align_up(off_pc + sizeof(PointConst), 256);
-  const size_t off_L = align_up(off_psf + sizeof(float) * sd.ph * sd.pw, 256);
+  const size_t off_p64 = align_up(off_pc + sizeof(PointConst), 256);
+  const size_t off_psf = align_up(off_p64 + sizeof(PointConst64), 256);
+  const size_t off_cc = align_up(off_psf + sizeof(float) * sd.ph * sd.pw, 256);
+  const size_t off_ce = align_up(off_cc + sizeof(int), 256);
+  const size_t off_L = align_up(off_ce + sizeof(CuspEntry) * (size_t)sd.n_rtiles * (RENDER_BLOCK / 64), 256);
   const size_t off_part = align_up(off_L + sizeof(float) * npix, 256);
   const size_t total = align_up(off_part + sizeof(float2) * sd.n_ptiles, 256);
   if ((rc = ensure_arena(c, total))) return rc;
   PointConst* pc = (PointConst*)(c->arena + off_pc);
+  PointConst64* p64 = (PointConst64*)(c->arena + off_p64);
+  CuspList cl{(CuspEntry*)(c->arena + off_ce), (int*)(c->arena + off_cc)};
   sd.psfn = (float*)(c->arena + off_psf);
   float* L = (float*)(c->arena + off_L);
   float2* part = (float2*)(c->arena + off_part);
   WorkArgs w;
   std::memset(&w, 0, sizeof(w));
   w.single = sd;
-  LENSED_HIP(c, launch_prologue(theta, 1, pc, nullptr, sd, nullptr, 1, st));
-  LENSED_HIP(c, launch_render(w, pc, L, sd.n_rtiles, st));
+  LENSED_HIP(c, launch_prologue(theta, 1, pc, p64, nullptr, sd, nullptr, 1, cl.count, st));
+  LENSED_HIP(c, launch_render(w, pc, p64, L, sd.n_rtiles, cl, st));
   LENSED_HIP(c, launch_psf(w, L, nullptr, part, 1, sd.n_ptiles, square_psf_code(sd.ph, sd.pw), sd.TW, sd.TH, sd.ph,
                            sd.pw, st));
   LENSED_HIP(c, launch_finalize(part, nullptr, nullptr, 1, sd.n_ptiles, logl, st));

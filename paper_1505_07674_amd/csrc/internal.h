@@ -9,6 +9,9 @@ namespace lensed {
 constexpr int NPAR = 17;
 constexpr float LN2F = 0.693147180559945309f;
 constexpr double LOG2E = 1.44269504088896340736;
+// Source-plane radius around a cuspy source centre inside which subsamples are
+// re-traced in float64 (the float32 ray position carries ~1e-7 arcsec of rounding).
+constexpr double CUSP_RADIUS_ARCSEC = 0.03;
 
 // Per-point constants derived once from the 17 parameters (prologue kernel).
 // Read with wave-uniform addresses, so they live in scalar registers in the
@@ -26,9 +29,24 @@ struct PointConst {
   float hc, hs, hqa, hqb, he, hB, hI;
   // source: same, about (sx0, sy0)
   float sx0, sy0, sc, ss, sqa, sqb, se, sB, sI;
-  float pad[5];
+  // source subsamples with R^2/R_e^2 below this are re-traced in float64 (0 = never)
+  float cusp_r2;
+  float pad[4];
 };
 static_assert(sizeof(PointConst) == 32 * 4, "PointConst layout");
+
+// Float64 lens constants for the rare re-tracing of subsamples that land next
+// to the centre of a cuspy (n > 1) source, where the float32 rounding of the
+// ray position (~1e-7 arcsec) is amplified by the steep profile.
+struct PointConst64 {
+  double cL, sL, q2, qp, k, te;   // SIE frame, k = theta_E sqrt(q)/q'
+  double m11, m12, m22;           // 1 - shear matrix
+  double sx0, sy0;                // source centre
+  int mode;                       // 0: isothermal sphere
+  int pad0;
+  double pad[4];
+};
+static_assert(sizeof(PointConst64) == 16 * 8, "PointConst64 layout");
 
 // Extra per-point values needed by the adjoint.
 struct GradConst {
@@ -51,10 +69,25 @@ struct SysDesc {
   const float* weight;
   int TW, TH;             // PSF/chi^2 output tile
   int tiles_x, n_ptiles;  // PSF tiles per row, per image
-  int n_rtiles;           // render tiles (RT pixels each) per image
+  int n_rtiles;           // render tiles (RENDER_BLOCK pixels each) per image
   int pad;
+  double wgt;             // quadrature weight pixscale^2 / N^2, in float64
 };
 
-constexpr int RENDER_BLOCK = 256;   // pixels per render tile / threads per render block
+constexpr int RENDER_BLOCK = 256;
+
+// A wave of the render kernel with pixels next to a cuspy source centre: the
+// point, the first pixel of the wave and the lane mask of flagged pixels.
+struct CuspEntry {
+  int point;
+  int pix0;
+  unsigned long long mask;
+};
+
+// Correction work list filled by the render kernel (count reset by the prologue).
+struct CuspList {
+  CuspEntry* entries;   // capacity: one entry per render wave of the launch
+  int* count;
+};   // pixels per render tile / threads per render block
 
 }  // namespace lensed

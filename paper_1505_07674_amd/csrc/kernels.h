@@ -22,11 +22,16 @@ struct WorkArgs {
   int point0;                   // point of a plain call
 };
 
-hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, GradConst* gcs, const SysDesc& single,
-                           SysDesc* table, int n_sys, hipStream_t stream);
+// Also clears *cusp_count (may be nullptr).
+hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, PointConst64* p64s, GradConst* gcs,
+                           const SysDesc& single, SysDesc* table, int n_sys, int* cusp_count, hipStream_t stream);
 
-// Unconvolved pixel luminosities into L (scratch or the caller's image).
-hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, float* L, int n_blocks, hipStream_t stream);
+// Unconvolved pixel luminosities into L (scratch or the caller's image): the
+// float32 render kernel, then the float64 cusp corrections of the pixels it
+// flagged. cl.entries needs one slot per render wave (n_blocks * 4); cl.count
+// must be zero when the render kernel starts (the prologue clears it).
+hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L, int n_blocks,
+                         const CuspList& cl, hipStream_t stream);
 
 // mode 0: PSF convolution of L into out (L* images, same offsets as L).
 // mode 1: PSF convolution fused with the weighted chi^2; one compensated

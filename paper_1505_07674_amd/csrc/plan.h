@@ -72,6 +72,8 @@ class BatchPlan {
   int2* d_ritems_ = nullptr;
   int2* d_pitems_ = nullptr;
   PointConst* d_pc_ = nullptr;
+  PointConst64* d_p64_ = nullptr;
+  CuspList cusp_{nullptr, nullptr};
   float* d_L_ = nullptr;
   float2* d_part_ = nullptr;
   int n_ritems_ = 0, n_pitems_ = 0;

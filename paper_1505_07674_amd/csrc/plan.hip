@@ -150,7 +150,10 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   const size_t o_ri = off; off = align256(off + sizeof(int2) * n_ritems_);
   const size_t o_pi = off; off = align256(off + sizeof(int2) * n_pitems_);
   const size_t o_pc = off; off = align256(off + sizeof(PointConst) * n_points);
+  const size_t o_p64 = off; off = align256(off + sizeof(PointConst64) * n_points);
   const size_t o_psf = off; off = align256(off + sizeof(float) * psf_total);
+  const size_t o_cc = off; off = align256(off + sizeof(int));
+  const size_t o_ce = off; off = align256(off + sizeof(CuspEntry) * (size_t)n_ritems_ * (RENDER_BLOCK / 64));
   const size_t o_L = off; off = align256(off + sizeof(float) * (size_t)Ltot);
   const size_t o_part = off; off = align256(off + sizeof(float2) * (size_t)ptot);
   hipError_t e = hipMalloc((void**)&mem_, off);
@@ -167,6 +170,9 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   d_ritems_ = (int2*)(mem_ + o_ri);
   d_pitems_ = (int2*)(mem_ + o_pi);
   d_pc_ = (PointConst*)(mem_ + o_pc);
+  d_p64_ = (PointConst64*)(mem_ + o_p64);
+  cusp_.count = (int*)(mem_ + o_cc);
+  cusp_.entries = (CuspEntry*)(mem_ + o_ce);
   d_L_ = (float*)(mem_ + o_L);
   d_part_ = (float2*)(mem_ + o_part);
   for (int s = 0; s < n_systems; ++s) desc[s].psfn = (float*)(mem_ + o_psf) + psf_off[s];
@@ -196,12 +202,12 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
   std::memset(&none, 0, sizeof(none));
   hipError_t e;
   if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
-  if ((e = launch_prologue(theta_, n_points_, d_pc_, nullptr, none, d_sys_, (int)systems_.size(), st)) != hipSuccess)
+  if ((e = launch_prologue(theta_, n_points_, d_pc_, d_p64_, nullptr, none, d_sys_, (int)systems_.size(), cusp_.count, st)) != hipSuccess)
     return e;
   if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
   w.items = d_ritems_;
   w.n_items = n_ritems_;
-  if ((e = launch_render(w, d_pc_, d_L_, n_ritems_, st)) != hipSuccess) return e;
+  if ((e = launch_render(w, d_pc_, d_p64_, d_L_, n_ritems_, cusp_, st)) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
   w.items = d_pitems_;
   w.n_items = n_pitems_;

@@ -59,8 +59,9 @@ __device__ bool ok_q(float q) { return q > 0.0f && q <= 1.0f; }
 __device__ bool ok_n(float n) { return n >= 0.2f && n <= 10.0f; }
 
 __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, PointConst* __restrict__ pcs,
-                                GradConst* __restrict__ gcs, SysDesc single, SysDesc* __restrict__ table,
-                                int n_sys, int point_blocks) {
+                                PointConst64* __restrict__ p64s, GradConst* __restrict__ gcs, SysDesc single,
+                                SysDesc* __restrict__ table, int n_sys, int point_blocks, int* __restrict__ cusp_count) {
+  if (cusp_count && blockIdx.x == 0 && threadIdx.x == 0) *cusp_count = 0;
   if ((int)blockIdx.x >= point_blocks) {
     // PSF normalisation: one block per system, float64 sum over the array.
     const int s = blockIdx.x - point_blocks;
@@ -141,13 +142,37 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
     c.sB = (float)(bs * LOG2E);
     c.sI = t[12];
   }
-  for (int k = 0; k < 5; ++k) c.pad[k] = 0.0f;
+  // re-trace in float64 within 0.03 arcsec (source plane) of a cuspy (n > 1) source centre
+  {
+    const double Re = t[13], rc = CUSP_RADIUS_ARCSEC / Re;
+    c.cusp_r2 = t[14] > 1.0f ? (float)(rc * rc) : 0.0f;
+  }
+  for (int k = 0; k < 4; ++k) c.pad[k] = 0.0f;
   if (!valid) {
     const float nan = __builtin_nanf("");
     c.m11 = c.m12 = c.m22 = nan;
     c.hI = c.sI = nan;
   }
   pcs[p] = c;
+  if (p64s) {
+    PointConst64 e;
+    e.cL = cos(phL);
+    e.sL = sin(phL);
+    e.q2 = q * q;
+    e.qp = qp;
+    e.te = te;
+    e.k = s2 == 0.0 ? te : te * sqrt(q) / qp;
+    e.mode = s2 == 0.0 ? 0 : 1;
+    e.pad0 = 0;
+    e.m11 = 1.0 - g1;
+    e.m12 = -g2;
+    e.m22 = 1.0 + g1;
+    e.sx0 = t[10];
+    e.sy0 = t[11];
+    for (int k = 0; k < 4; ++k) e.pad[k] = 0.0;
+    if (!valid) e.m11 = e.m12 = e.m22 = __builtin_nan("");
+    p64s[p] = e;
+  }
 
   if (gcs) {
     GradConst gc;
@@ -163,14 +188,14 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
 
 }  // namespace
 
-hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, GradConst* gcs, const SysDesc& single,
-                           SysDesc* table, int n_sys, hipStream_t stream) {
+hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, PointConst64* p64s, GradConst* gcs,
+                           const SysDesc& single, SysDesc* table, int n_sys, int* cusp_count, hipStream_t stream) {
   const int threads = 64;
   const int point_blocks = (n_points + threads - 1) / threads;
   const int blocks = point_blocks + n_sys;
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(prologue_kernel, dim3(blocks), dim3(threads), 0, stream, theta, n_points, pcs, gcs, single,
-                     table, n_sys, point_blocks);
+  hipLaunchKernelGGL(prologue_kernel, dim3(blocks), dim3(threads), 0, stream, theta, n_points, pcs, p64s, gcs,
+                     single, table, n_sys, point_blocks, cusp_count);
   return hipGetLastError();
 }
 

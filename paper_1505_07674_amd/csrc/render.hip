@@ -15,23 +15,21 @@ namespace lensed {
 namespace {
 
 template <int MODE>
-__device__ float pixel_sum_dispatch(const PointConst& c, int N, float ux, float uy, float d, float cx, float cy) {
+__device__ float pixel_sum_dispatch(const PointConst& c, int N, const PixelGeom& g, bool& cusp) {
   switch (N) {
-    case 1: return pixel_sum<1, MODE>(c, ux, uy, d, cx, cy);
-    case 2: return pixel_sum<2, MODE>(c, ux, uy, d, cx, cy);
-    case 3: return pixel_sum<3, MODE>(c, ux, uy, d, cx, cy);
-    case 4: return pixel_sum<4, MODE>(c, ux, uy, d, cx, cy);
-    case 5: return pixel_sum<5, MODE>(c, ux, uy, d, cx, cy);
-    case 6: return pixel_sum<6, MODE>(c, ux, uy, d, cx, cy);
-    case 7: return pixel_sum<7, MODE>(c, ux, uy, d, cx, cy);
-    case 8: return pixel_sum<8, MODE>(c, ux, uy, d, cx, cy);
-    default: return pixel_sum_rt<MODE>(c, N, ux, uy, d, cx, cy);
+    case 1: return pixel_sum<1, MODE>(c, g, cusp);
+    case 2: return pixel_sum<2, MODE>(c, g, cusp);
+    case 3: return pixel_sum<3, MODE>(c, g, cusp);
+    case 4: return pixel_sum<4, MODE>(c, g, cusp);
+    case 5: return pixel_sum<5, MODE>(c, g, cusp);
+    case 6: return pixel_sum<6, MODE>(c, g, cusp);
+    case 7: return pixel_sum<7, MODE>(c, g, cusp);
+    case 8: return pixel_sum<8, MODE>(c, g, cusp);
+    default: return pixel_sum_rt<MODE>(c, N, g, cusp);
   }
 }
 
-__global__ __launch_bounds__(RENDER_BLOCK) void render_kernel(WorkArgs w, const PointConst* __restrict__ pcs,
-                                                               float* __restrict__ L) {
-  int point, tile;
+__device__ __forceinline__ void resolve_item(const WorkArgs& w, int& point, int& tile) {
   if (w.items) {
     const int2 it = w.items[blockIdx.x];
     point = it.x;
@@ -40,30 +38,94 @@ __global__ __launch_bounds__(RENDER_BLOCK) void render_kernel(WorkArgs w, const 
     point = w.point0;
     tile = blockIdx.x;
   }
+}
+
+__device__ __forceinline__ PixelGeom pixel_geom(const SysDesc& sd, int pix) {
+  const int r = pix / sd.W;
+  const int col = pix - r * sd.W;
+  PixelGeom g;
+  g.ux = (float)col - 0.5f * (float)(sd.W - 1);
+  g.uy = (float)r - 0.5f * (float)(sd.H - 1);
+  g.d = sd.d;
+  g.cx = sd.cx;
+  g.cy = sd.cy;
+  return g;
+}
+
+__global__ __launch_bounds__(RENDER_BLOCK) void render_kernel(WorkArgs w, const PointConst* __restrict__ pcs,
+                                                               float* __restrict__ L, CuspList cl) {
+  int point, tile;
+  resolve_item(w, point, tile);
   const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[point] : 0] : w.single;
   const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
   const int pix = tile * RENDER_BLOCK + (int)threadIdx.x;
-  if (pix >= sd.H * sd.W) return;
-  const int r = pix / sd.W;
-  const int col = pix - r * sd.W;
-  const float ux = (float)col - 0.5f * (float)(sd.W - 1);
-  const float uy = (float)r - 0.5f * (float)(sd.H - 1);
-  const PointConst& c = pcs[point];
-  float acc;
-  switch (c.sie_mode) {
-    case 0: acc = pixel_sum_dispatch<0>(c, sd.N, ux, uy, sd.d, sd.cx, sd.cy); break;
-    case 1: acc = pixel_sum_dispatch<1>(c, sd.N, ux, uy, sd.d, sd.cx, sd.cy); break;
-    default: acc = pixel_sum_dispatch<2>(c, sd.N, ux, uy, sd.d, sd.cx, sd.cy); break;
+  const bool active = pix < sd.H * sd.W;
+  bool cusp = false;
+  if (active) {
+    const PixelGeom g = pixel_geom(sd, pix);
+    const PointConst& c = pcs[point];
+    float acc;
+    switch (c.sie_mode) {
+      case 0: acc = pixel_sum_dispatch<0>(c, sd.N, g, cusp); break;
+      case 1: acc = pixel_sum_dispatch<1>(c, sd.N, g, cusp); break;
+      default: acc = pixel_sum_dispatch<2>(c, sd.N, g, cusp); break;
+    }
+    L[loff + pix] = (float)((double)acc * sd.wgt);
   }
-  const float wgt = sd.d * sd.d / (float)(sd.N * sd.N);
-  L[loff + pix] = acc * wgt;
+  // one list entry per wave that has pixels next to a cuspy source centre
+  const unsigned long long mask = __ballot(cusp);
+  if (mask != 0ull && (threadIdx.x & 63) == 0) {
+    const int slot = atomicAdd(cl.count, 1);
+    CuspEntry e;
+    e.point = point;
+    e.pix0 = pix;
+    e.mask = mask;
+    cl.entries[slot] = e;
+  }
+}
+
+// Adds the float64 cusp corrections to the flagged pixels; a fixed grid of
+// waves walks the list written by render_kernel (each pixel appears at most
+// once), one entry per wave at a time.
+constexpr int CUSP_WAVES = 4;
+constexpr int CUSP_BLOCKS = 2048;
+
+__global__ __launch_bounds__(64 * CUSP_WAVES) void cusp_kernel(WorkArgs w, const PointConst* __restrict__ pcs,
+                                                               const PointConst64* __restrict__ p64s,
+                                                               float* __restrict__ L, CuspList cl) {
+  const int n = *cl.count;
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * CUSP_WAVES + (threadIdx.x >> 6);
+  for (int i = wave; i < n; i += gridDim.x * CUSP_WAVES) {
+    const CuspEntry e = cl.entries[i];
+    if (!((e.mask >> lane) & 1ull)) continue;
+    const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[e.point] : 0] : w.single;
+    const int64_t loff = w.point_loff ? w.point_loff[e.point] : 0;
+    const int pix = e.pix0 + lane;
+    const PixelGeom g = pixel_geom(sd, pix);
+    const PointConst& c = pcs[e.point];
+    float corr;
+    switch (c.sie_mode) {
+      case 0: corr = cusp_correction<0>(c, p64s[e.point], sd.N, g); break;
+      case 1: corr = cusp_correction<1>(c, p64s[e.point], sd.N, g); break;
+      default: corr = cusp_correction<2>(c, p64s[e.point], sd.N, g); break;
+    }
+    L[loff + pix] = (float)((double)L[loff + pix] + (double)corr * sd.wgt);
+  }
 }
 
 }  // namespace
 
-hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, float* L, int n_blocks, hipStream_t stream) {
+hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L, int n_blocks,
+                         const CuspList& cl, hipStream_t stream) {
   if (n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(render_kernel, dim3(n_blocks), dim3(RENDER_BLOCK), 0, stream, w, pcs, L);
+  hipLaunchKernelGGL(render_kernel, dim3(n_blocks), dim3(RENDER_BLOCK), 0, stream, w, pcs, L, cl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int waves = n_blocks * (RENDER_BLOCK / 64);   // list capacity
+  int grid = (waves + CUSP_WAVES - 1) / CUSP_WAVES;
+  if (grid > CUSP_BLOCKS) grid = CUSP_BLOCKS;
+  hipLaunchKernelGGL(cusp_kernel, dim3(grid), dim3(64 * CUSP_WAVES), 0, stream, w, pcs, p64s, L, cl);
   return hipGetLastError();
 }
 

@@ -79,24 +79,17 @@ __device__ __forceinline__ void lens_map(const PointConst& c, float x, float y, 
   }
 }
 
-// Sersic value for offsets (dx, dy) from the centre: rotation (c, s), scaled
-// axis factors qa = q/R_e^2, qb = 1/(q R_e^2), e = 1/(2n), B = b_n log2(e), amplitude I_e.
-__device__ __forceinline__ float sersic_b2(float dx, float dy, float cs, float sn, float qa, float qb, float e,
-                                           float B, float Ie) {
+// Elliptical Sersic profile in two steps: the scaled squared radius
+// R^2/R_e^2 = qa x'^2 + qb y'^2 (rotation (cs, sn), qa = q/R_e^2, qb = 1/(q R_e^2)),
+// then I = I_e 2^{B (1 - t)} with t = (R^2/R_e^2)^{e}, e = 1/(2n), B = b_n log2(e).
+__device__ __forceinline__ float sersic_r2(float dx, float dy, float cs, float sn, float qa, float qb) {
   const float xp = fmaf(cs, dx, sn * dy);
   const float yp = fmaf(cs, dy, -sn * dx);
-  const float R2 = fmaf(qa * xp, xp, qb * yp * yp);
+  return fmaf(qa * xp, xp, qb * yp * yp);
+}
+__device__ __forceinline__ float sersic_from_r2(float R2, float e, float B, float Ie) {
   const float t = hw_exp2(e * hw_log2(R2));
   return Ie * hw_exp2(fmaf(-B, t, B));
-}
-
-template <int MODE>
-__device__ __forceinline__ float surface_brightness(const PointConst& c, float x, float y) {
-  float bx, by;
-  lens_map<MODE>(c, x, y, bx, by);
-  const float Ih = sersic_b2(x, y, c.hc, c.hs, c.hqa, c.hqb, c.he, c.hB, c.hI);
-  const float Is = sersic_b2(bx - c.sx0, by - c.sy0, c.sc, c.ss, c.sqa, c.sqb, c.se, c.sB, c.sI);
-  return Ih + Is;
 }
 
 // Midpoint offset of subsample k of N, in pixel units: (k + 1/2)/N - 1/2.
@@ -104,34 +97,105 @@ template <int N>
 __device__ __forceinline__ constexpr float sub_offset(int k) {
   return (float(k) + 0.5f) / float(N) - 0.5f;
 }
+__device__ __forceinline__ float sub_offset_rt(int k, int N) { return (float(k) + 0.5f) / float(N) - 0.5f; }
 
-// Sum of the surface brightness over the N x N midpoint abscissae of a pixel
-// whose centre is (ux, uy) pixels from the grid centre.
+// Where the pixel's subsamples sit: centre (ux, uy) in pixels from the grid
+// centre (exact half-integers), pixel scale d, grid centre (cx, cy).
+struct PixelGeom {
+  float ux, uy, d, cx, cy;
+};
+
+// Float64 re-tracing of one subsample: exact abscissa (as the rule defines it),
+// SIE + shear lens equation in float64, offset from the source centre.
+__device__ __forceinline__ void source_offset_f64(const PointConst64& e, const PixelGeom& g, int kx, int ky, int N,
+                                                  float& dx, float& dy) {
+  const double x = (double)g.cx + ((double)g.ux + (((double)kx + 0.5) / N - 0.5)) * (double)g.d;
+  const double y = (double)g.cy + ((double)g.uy + (((double)ky + 0.5) / N - 0.5)) * (double)g.d;
+  double ax = 0.0, ay = 0.0;
+  if (e.mode == 0) {
+    const double r = sqrt(x * x + y * y);
+    if (r > 0.0) {
+      ax = e.te * x / r;
+      ay = e.te * y / r;
+    }
+  } else {
+    const double xp = e.cL * x + e.sL * y, yp = -e.sL * x + e.cL * y;
+    const double psi = sqrt(e.q2 * xp * xp + yp * yp);
+    if (psi > 0.0) {
+      const double a1 = e.k * atan(e.qp * xp / psi), a2 = e.k * atanh(e.qp * yp / psi);
+      ax = e.cL * a1 - e.sL * a2;
+      ay = e.sL * a1 + e.cL * a2;
+    }
+  }
+  dx = (float)(e.m11 * x + e.m12 * y - ax - e.sx0);
+  dy = (float)(e.m12 * x + e.m22 * y - ay - e.sy0);
+}
+
+// Scaled squared source radius of subsample (x, y), float32 path.
+template <int MODE>
+__device__ __forceinline__ float source_r2(const PointConst& c, float x, float y) {
+  float bx, by;
+  lens_map<MODE>(c, x, y, bx, by);
+  return sersic_r2(bx - c.sx0, by - c.sy0, c.sc, c.ss, c.sqa, c.sqb);
+}
+
+// Surface brightness at one subsample; `cusp` is raised when the float32 source
+// radius falls inside the cusp zone, where a correction kernel later replaces
+// this subsample's source light by its float64 re-traced value.
+template <int MODE>
+__device__ __forceinline__ float surface_brightness(const PointConst& c, float x, float y, bool& cusp) {
+  const float Ih = sersic_from_r2(sersic_r2(x, y, c.hc, c.hs, c.hqa, c.hqb), c.he, c.hB, c.hI);
+  const float sR2 = source_r2<MODE>(c, x, y);
+  cusp = cusp || (sR2 < c.cusp_r2);
+  return Ih + sersic_from_r2(sR2, c.se, c.sB, c.sI);
+}
+
+// Sum of the surface brightness over the N x N midpoint abscissae of a pixel.
 template <int N, int MODE>
-__device__ __forceinline__ float pixel_sum(const PointConst& c, float ux, float uy, float d, float cx, float cy) {
+__device__ __forceinline__ float pixel_sum(const PointConst& c, const PixelGeom& g, bool& cusp) {
   float acc = 0.0f;
 #pragma unroll
   for (int ky = 0; ky < N; ++ky) {
-    const float y = fmaf(uy + sub_offset<N>(ky), d, cy);
+    const float y = fmaf(g.uy + sub_offset<N>(ky), g.d, g.cy);
 #pragma unroll
     for (int kx = 0; kx < N; ++kx) {
-      const float x = fmaf(ux + sub_offset<N>(kx), d, cx);
-      acc += surface_brightness<MODE>(c, x, y);
+      const float x = fmaf(g.ux + sub_offset<N>(kx), g.d, g.cx);
+      acc += surface_brightness<MODE>(c, x, y, cusp);
     }
   }
   return acc;
 }
 
 template <int MODE>
-__device__ __forceinline__ float pixel_sum_rt(const PointConst& c, int N, float ux, float uy, float d, float cx,
-                                              float cy) {
+__device__ __forceinline__ float pixel_sum_rt(const PointConst& c, int N, const PixelGeom& g, bool& cusp) {
   float acc = 0.0f;
-  const float invN = 1.0f / float(N);
   for (int ky = 0; ky < N; ++ky) {
-    const float y = fmaf(uy + ((float(ky) + 0.5f) * invN - 0.5f), d, cy);
+    const float y = fmaf(g.uy + sub_offset_rt(ky, N), g.d, g.cy);
     for (int kx = 0; kx < N; ++kx) {
-      const float x = fmaf(ux + ((float(kx) + 0.5f) * invN - 0.5f), d, cx);
-      acc += surface_brightness<MODE>(c, x, y);
+      const float x = fmaf(g.ux + sub_offset_rt(kx, N), g.d, g.cx);
+      acc += surface_brightness<MODE>(c, x, y, cusp);
+    }
+  }
+  return acc;
+}
+
+// Correction for one flagged pixel: for every subsample in the cusp zone, the
+// source light at the float64 re-traced offset minus its float32 value.
+template <int MODE>
+__device__ __forceinline__ float cusp_correction(const PointConst& c, const PointConst64& c64, int N,
+                                                 const PixelGeom& g) {
+  float acc = 0.0f;
+  for (int ky = 0; ky < N; ++ky) {
+    const float y = fmaf(g.uy + sub_offset_rt(ky, N), g.d, g.cy);
+    for (int kx = 0; kx < N; ++kx) {
+      const float x = fmaf(g.ux + sub_offset_rt(kx, N), g.d, g.cx);
+      const float sR2 = source_r2<MODE>(c, x, y);
+      if (sR2 < c.cusp_r2) {
+        float dx, dy;
+        source_offset_f64(c64, g, kx, ky, N, dx, dy);
+        const float exact = sersic_from_r2(sersic_r2(dx, dy, c.sc, c.ss, c.sqa, c.sqb), c.se, c.sB, c.sI);
+        acc += exact - sersic_from_r2(sR2, c.se, c.sB, c.sI);
+      }
     }
   }
   return acc;

@@ -208,3 +208,19 @@ def test_invalid_arguments_return_status():
     with pytest.raises(lensed.LensedError):
         lensed.loglike_batch(tp.view(1, 17), [3], [gsys])
     del bad
+
+
+def test_subsample_on_the_image_of_a_cuspy_source_centre():
+    """SIS with theta_E = 0.8 and an n = 4 source centred at (0.2, 0): its centre is
+    imaged at x = 1.0 on the axis, exactly where a subsample of the 63x63, N = 3
+    grid sits (y = 0 is the middle subsample of the middle row). The float64
+    cusp correction must keep the cusp pixel within the bars."""
+    say("cusp subsample")
+    base = mocks.c1_spec()
+    spec = mocks.SystemSpec("cusp_63x63_sub3", 63, 63, 3, mocks.moffat_psf(11, 0.1, 3.0), base.truth,
+                            base.prior, np.ones((63, 63), bool), 5, False)
+    t = np.array([0.8, 1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0, 0.0,
+                  0.2, 0.0, 1.0, 0.05, 4.0, 0.8, 0.3], np.float32)
+    t2 = t.copy(); t2[1], t2[2], t2[14] = 0.7, 0.4, 3.0     # elliptical lens, same source
+    check_images(spec, np.stack([t, t2]), True)
+    check_images(spec, np.stack([t, t2]), False)
