@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--plain-points", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-points-per-core", type=int, default=4)
+    ap.add_argument("--grad-points", type=int, default=1024)
+    ap.add_argument("--grad-steps", type=int, default=5)
     return ap.parse_args()
 
 
@@ -149,6 +151,21 @@ def main():
     rel = (outs - out[:n_plain]).abs() / out[:n_plain].abs().clamp_min(1.0)
     assert rel.max().item() < 1e-5, "plain and batched log L disagree"
 
+    # adjoint: log L and its 17-gradient for the C3 configuration
+    G = args.grad_points
+    log(f"gradient: {G} points, {args.grad_steps} steps")
+    gpts = torch.from_numpy(mocks.points(spec, G, seed=mocks.C3_SEED)).to(dev)
+    lensed.loglike_grad(gpts, gsys, ctx=ctx)
+    torch.cuda.synchronize()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record(stream)
+    for _ in range(args.grad_steps):
+        gll, gg = lensed.loglike_grad(gpts, gsys, ctx=ctx)
+    g1.record(stream)
+    torch.cuda.synchronize()
+    grad_value = G * args.grad_steps / (g0.elapsed_time(g1) / 1e3)
+    assert torch.isfinite(gg).all().item()
+
     result = {
         "metric": "log-likelihood evals/sec at 200x200, 4x4 subsample (batched)",
         "value": value,
@@ -169,6 +186,8 @@ def main():
         "plain": {"value": plain_value, "unit": "evals/s", "points": n_plain,
                   "form": "one prologue/render/psf/finalize launch sequence per point, one sync"},
         "batched_over_plain": value / plain_value,
+        "adjoint": {"value": grad_value, "unit": "gradients/s", "points": G,
+                    "form": "log L and d log L/d theta (17) per point, one graph launch per step"},
         "stage_ms_per_step": stage_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,

@@ -330,6 +330,40 @@ int lensed_stage_times(lensed_ctx* c, double* ms, int n, int* calls) {
 
 extern "C" int lensed_loglike_grad(lensed_ctx* c, const lensed_system* sys, const float* theta, int n_points,
                                    double* logl, float* grad, void* stream) {
-  (void)sys; (void)theta; (void)n_points; (void)logl; (void)grad; (void)stream;
-  return set_err(c, LENSED_NOT_SUPPORTED, "adjoint not built yet");
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  if (n_points < 0) return set_err(c, LENSED_INVALID_ARGUMENT, "n_points must be >= 0");
+  if (n_points == 0) return LENSED_OK;
+  int rc = validate_system(c, sys, true, -1);
+  if (rc) return rc;
+  if (!theta || !logl || !grad) return set_err(c, LENSED_INVALID_ARGUMENT, "theta, logl and grad are required");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  std::vector<int32_t> map(n_points, 0);
+  BatchPlan* plan = nullptr;
+  for (size_t i = 0; i < c->plans.size(); ++i) {
+    if (c->plans[i]->matches(sys, 1, theta, map.data(), n_points, logl, grad)) {
+      std::unique_ptr<BatchPlan> keep = std::move(c->plans[i]);
+      c->plans.erase(c->plans.begin() + i);
+      c->plans.push_back(std::move(keep));
+      plan = c->plans.back().get();
+      break;
+    }
+  }
+  if (!plan) {
+    if (c->plans.size() >= 8) {
+      LENSED_HIP(c, hipDeviceSynchronize());
+      c->plans.erase(c->plans.begin());
+    }
+    std::unique_ptr<BatchPlan> np(new BatchPlan());
+    std::string msg;
+    hipError_t e = np->build(sys, 1, theta, map.data(), n_points, logl, c->tiles, msg, grad);
+    if (e != hipSuccess) return hip_fail(c, e, ("gradient plan: " + msg).c_str());
+    if (c->use_graphs) {
+      e = np->capture(c->cap);
+      if (e != hipSuccess) return hip_fail(c, e, "gradient plan graph capture");
+    }
+    c->plans.push_back(std::move(np));
+    plan = c->plans.back().get();
+  }
+  LENSED_HIP(c, plan->run((hipStream_t)stream));
+  return LENSED_OK;
 }

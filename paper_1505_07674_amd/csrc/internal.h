@@ -72,6 +72,8 @@ struct SysDesc {
   int n_rtiles;           // render tiles (RENDER_BLOCK pixels each) per image
   int pad;
   double wgt;             // quadrature weight pixscale^2 / N^2, in float64
+  float* adjk;            // 16 folded PSF tables of the adjoint (or nullptr)
+  float* adjk_pad;
 };
 
 constexpr int RENDER_BLOCK = 256;

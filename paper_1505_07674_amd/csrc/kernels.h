@@ -22,9 +22,11 @@ struct WorkArgs {
   int point0;                   // point of a plain call
 };
 
-// Also clears *cusp_count (may be nullptr).
+// Also clears *cusp_count (may be nullptr) and, when gcs is given, the 17
+// cusp-correction accumulators of every point in grad_corr.
 hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, PointConst64* p64s, GradConst* gcs,
-                           const SysDesc& single, SysDesc* table, int n_sys, int* cusp_count, hipStream_t stream);
+                           const SysDesc& single, SysDesc* table, int n_sys, int* cusp_count, hipStream_t stream,
+                           double* grad_corr = nullptr);
 
 // Unconvolved pixel luminosities into L (scratch or the caller's image): the
 // float32 render kernel, then the float64 cusp corrections of the pixels it
@@ -36,6 +38,7 @@ hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointCo
 // mode 0: PSF convolution of L into out (L* images, same offsets as L).
 // mode 1: PSF convolution fused with the weighted chi^2; one compensated
 //         (hi, lo) float pair per tile is written to partials.
+// mode 2: as mode 1, and the weighted residual w (d - L*) is written to out.
 // Every system of one launch uses the same TW x TH output tile (the block is
 // TW x TH/4 threads). square_psf = 21, 7 or 1 selects a specialised stencil when
 // every PSF of the launch has that square size; -1 selects the generic one.
@@ -47,5 +50,20 @@ constexpr int PSF_ROWS = 4;   // outputs per thread of the PSF kernel
 // log L = -1/2 * sum over the point's tiles of (hi + lo), in float64.
 hipError_t launch_finalize(const float2* partials, const int* point_pbase, const int* point_ntiles, int n_points,
                            int single_ntiles, double* logl, hipStream_t stream);
+
+// g = A^T rho for every point of a single-system launch (same tiles as the PSF
+// kernel, border pixels by the folded tables); R and G use the image offsets.
+hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n_blocks, int square_psf, int TW,
+                              int TH, int ph, int pw, int n_points, int H, int W, hipStream_t st);
+
+// Per-(point, render tile) sums of g d^2/N^2 dI/dtheta: gpart[(gpbase[p] + tile) * 17 + k],
+// then the float64 cusp corrections of the waves in cl (the list the forward
+// render filled) added to corr[p * 17 + k], which must start at zero.
+hipError_t launch_grad(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, const GradConst* gcs,
+                       const float* G, const int* gpbase, float2* gpart, int n_blocks, const CuspList& cl,
+                       double* corr, hipStream_t st);
+
+hipError_t launch_finalize_grad(const float2* gpart, const int* gpbase, int ntiles, int n_points, const double* corr,
+                                float* grad, hipStream_t st);
 
 }  // namespace lensed

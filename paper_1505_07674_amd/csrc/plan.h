@@ -46,10 +46,11 @@ int square_psf_code(int ph, int pw);
 class BatchPlan {
  public:
   ~BatchPlan();
+  // grad == nullptr: log L only; otherwise also d log L / d theta (single system).
   bool matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map, int n_points,
-               const double* logl) const;
+               const double* logl, const float* grad = nullptr) const;
   hipError_t build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
-                   int n_points, double* logl, TileCache& tiles, std::string& msg);
+                   int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad = nullptr);
   hipError_t capture(hipStream_t cap);
   // events, when given, are 5 events recorded around the 4 stages
   // (prologue, render, PSF + chi^2, finalize)
@@ -61,6 +62,7 @@ class BatchPlan {
   std::vector<int32_t> map_;
   const float* theta_ = nullptr;
   double* logl_ = nullptr;
+  float* grad_ = nullptr;
   int n_points_ = 0;
 
   char* mem_ = nullptr;
@@ -74,6 +76,12 @@ class BatchPlan {
   PointConst* d_pc_ = nullptr;
   PointConst64* d_p64_ = nullptr;
   CuspList cusp_{nullptr, nullptr};
+  GradConst* d_gc_ = nullptr;
+  float* d_R_ = nullptr;          // weighted residuals (gradient plans)
+  int* d_gpbase_ = nullptr;       // first gradient-partial tile of each point
+  float2* d_gpart_ = nullptr;     // [tiles][17] (hi, lo)
+  double* d_gcorr_ = nullptr;     // [points][17] float64 cusp corrections
+  int grad_ntiles_ = 0;
   float* d_L_ = nullptr;
   float2* d_part_ = nullptr;
   int n_ritems_ = 0, n_pitems_ = 0;

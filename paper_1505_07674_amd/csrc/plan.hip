@@ -76,19 +76,22 @@ BatchPlan::~BatchPlan() {
 }
 
 bool BatchPlan::matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
-                        int n_points, const double* logl) const {
-  if (theta != theta_ || logl != logl_ || n_points != n_points_ || (size_t)n_systems != systems_.size()) return false;
+                        int n_points, const double* logl, const float* grad) const {
+  if (theta != theta_ || logl != logl_ || grad != grad_ || n_points != n_points_ ||
+      (size_t)n_systems != systems_.size())
+    return false;
   for (int s = 0; s < n_systems; ++s)
     if (!same_system(systems[s], systems_[s])) return false;
   return std::equal(map_.begin(), map_.end(), map);
 }
 
 hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
-                            int n_points, double* logl, TileCache& tiles, std::string& msg) {
+                            int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad) {
   systems_.assign(systems, systems + n_systems);
   map_.assign(map, map + n_points);
   theta_ = theta;
   logl_ = logl;
+  grad_ = grad;
   n_points_ = n_points;
 
   const TileShape ts = tiles.choose_common(systems, n_systems);
@@ -109,7 +112,8 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   }
 
   std::vector<int64_t> loff(n_points);
-  std::vector<int> pbase(n_points), ntiles(n_points);
+  std::vector<int> pbase(n_points), ntiles(n_points), gpbase(n_points);
+  int gtot = 0;
   int64_t Ltot = 0;
   int ptot = 0;
   struct Item {
@@ -124,6 +128,8 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
     pbase[p] = ptot;
     ntiles[p] = d.n_ptiles;
     ptot += d.n_ptiles;
+    gpbase[p] = gtot;
+    gtot += d.n_rtiles;
     const int64_t npix = (int64_t)d.H * d.W;
     for (int t = 0; t < d.n_rtiles; ++t) {
       const int64_t px = std::min<int64_t>(RENDER_BLOCK, npix - (int64_t)t * RENDER_BLOCK);
@@ -156,6 +162,13 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   const size_t o_ce = off; off = align256(off + sizeof(CuspEntry) * (size_t)n_ritems_ * (RENDER_BLOCK / 64));
   const size_t o_L = off; off = align256(off + sizeof(float) * (size_t)Ltot);
   const size_t o_part = off; off = align256(off + sizeof(float2) * (size_t)ptot);
+  const bool g = grad != nullptr;
+  const size_t o_gc = off; off = align256(off + (g ? sizeof(GradConst) * n_points : 0));
+  const size_t o_R = off; off = align256(off + (g ? sizeof(float) * (size_t)Ltot : 0));
+  const size_t o_gpb = off; off = align256(off + (g ? sizeof(int) * n_points : 0));
+  const size_t o_gpart = off; off = align256(off + (g ? sizeof(float2) * (size_t)gtot * NPAR : 0));
+  const size_t o_adjk = off; off = align256(off + (g ? sizeof(float) * 16 * psf_total : 0));
+  const size_t o_gcorr = off; off = align256(off + (g ? sizeof(double) * (size_t)n_points * NPAR : 0));
   hipError_t e = hipMalloc((void**)&mem_, off);
   if (e != hipSuccess) {
     msg = "scratch of " + std::to_string(off) + " bytes";
@@ -176,6 +189,15 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   d_L_ = (float*)(mem_ + o_L);
   d_part_ = (float2*)(mem_ + o_part);
   for (int s = 0; s < n_systems; ++s) desc[s].psfn = (float*)(mem_ + o_psf) + psf_off[s];
+  if (g) {
+    d_gc_ = (GradConst*)(mem_ + o_gc);
+    d_R_ = (float*)(mem_ + o_R);
+    d_gpbase_ = (int*)(mem_ + o_gpb);
+    d_gpart_ = (float2*)(mem_ + o_gpart);
+    d_gcorr_ = (double*)(mem_ + o_gcorr);
+    grad_ntiles_ = desc[0].n_rtiles;
+    for (int s = 0; s < n_systems; ++s) desc[s].adjk = (float*)(mem_ + o_adjk) + 16 * psf_off[s];
+  }
 
   std::vector<int> ps(map, map + n_points);
   if ((e = hipMemcpy(d_sys_, desc.data(), sizeof(SysDesc) * n_systems, hipMemcpyHostToDevice)) != hipSuccess ||
@@ -184,7 +206,8 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
       (e = hipMemcpy(d_pbase_, pbase.data(), sizeof(int) * n_points, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_ntiles_, ntiles.data(), sizeof(int) * n_points, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_ritems_, ri.data(), sizeof(int2) * n_ritems_, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(d_pitems_, pi.data(), sizeof(int2) * n_pitems_, hipMemcpyHostToDevice)) != hipSuccess) {
+      (e = hipMemcpy(d_pitems_, pi.data(), sizeof(int2) * n_pitems_, hipMemcpyHostToDevice)) != hipSuccess ||
+      (g && (e = hipMemcpy(d_gpbase_, gpbase.data(), sizeof(int) * n_points, hipMemcpyHostToDevice)) != hipSuccess)) {
     msg = "uploading work lists";
     return e;
   }
@@ -202,21 +225,37 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
   std::memset(&none, 0, sizeof(none));
   hipError_t e;
   if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
-  if ((e = launch_prologue(theta_, n_points_, d_pc_, d_p64_, nullptr, none, d_sys_, (int)systems_.size(), cusp_.count, st)) != hipSuccess)
+  if ((e = launch_prologue(theta_, n_points_, d_pc_, d_p64_, d_gc_, none, d_sys_, (int)systems_.size(), cusp_.count,
+                           st, d_gcorr_)) != hipSuccess)
     return e;
   if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-  w.items = d_ritems_;
-  w.n_items = n_ritems_;
-  if ((e = launch_render(w, d_pc_, d_p64_, d_L_, n_ritems_, cusp_, st)) != hipSuccess) return e;
+  WorkArgs wr = w;
+  wr.items = d_ritems_;
+  wr.n_items = n_ritems_;
+  if ((e = launch_render(wr, d_pc_, d_p64_, d_L_, n_ritems_, cusp_, st)) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-  w.items = d_pitems_;
-  w.n_items = n_pitems_;
-  if ((e = launch_psf(w, d_L_, nullptr, d_part_, 1, n_pitems_, square_psf_, TW_, TH_, max_ph_, max_pw_, st)) !=
+  WorkArgs wp = w;
+  wp.items = d_pitems_;
+  wp.n_items = n_pitems_;
+  const int mode = grad_ ? 2 : 1;
+  if ((e = launch_psf(wp, d_L_, d_R_, d_part_, mode, n_pitems_, square_psf_, TW_, TH_, max_ph_, max_pw_, st)) !=
       hipSuccess)
     return e;
   if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
   if ((e = launch_finalize(d_part_, d_pbase_, d_ntiles_, n_points_, 0, logl_, st)) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[4], st)) != hipSuccess) return e;
+  if (grad_) {
+    // g = A^T rho overwrites the unconvolved images, which are no longer needed
+    const lensed_system& s0 = systems_[0];
+    if ((e = launch_adjoint_psf(wp, d_R_, d_L_, n_pitems_, square_psf_, TW_, TH_, max_ph_, max_pw_, n_points_,
+                                s0.height, s0.width, st)) != hipSuccess)
+      return e;
+    if ((e = launch_grad(wr, d_pc_, d_p64_, d_gc_, d_L_, d_gpbase_, d_gpart_, n_ritems_, cusp_, d_gcorr_, st)) !=
+        hipSuccess)
+      return e;
+    if ((e = launch_finalize_grad(d_gpart_, d_gpbase_, grad_ntiles_, n_points_, d_gcorr_, grad_, st)) != hipSuccess)
+      return e;
+  }
   return hipSuccess;
 }
 

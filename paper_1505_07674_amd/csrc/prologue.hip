@@ -60,7 +60,8 @@ __device__ bool ok_n(float n) { return n >= 0.2f && n <= 10.0f; }
 
 __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, PointConst* __restrict__ pcs,
                                 PointConst64* __restrict__ p64s, GradConst* __restrict__ gcs, SysDesc single,
-                                SysDesc* __restrict__ table, int n_sys, int point_blocks, int* __restrict__ cusp_count) {
+                                SysDesc* __restrict__ table, int n_sys, int point_blocks, int* __restrict__ cusp_count,
+                                double* __restrict__ grad_corr) {
   if (cusp_count && blockIdx.x == 0 && threadIdx.x == 0) *cusp_count = 0;
   if ((int)blockIdx.x >= point_blocks) {
     // PSF normalisation: one block per system, float64 sum over the array.
@@ -78,6 +79,35 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
     }
     const double inv = 1.0 / part[0];
     for (int i = threadIdx.x; i < n; i += blockDim.x) sd.psfn[i] = (float)((double)sd.psf[i] * inv);
+    if (sd.adjk) {
+      // Folded tables of the transposed convolution: for border class (cr, cc)
+      // (0 interior, 1 first, 2 last, 3 both, per axis) the entry at offset (a, b)
+      // sums the normalised kernel over the offsets the replicate padding maps
+      // there: first -> offsets a..p, last -> -p..a, both -> all (only a = 0).
+      const int p = sd.ph / 2, q = sd.pw / 2;
+      for (int i = threadIdx.x; i < 16 * n; i += blockDim.x) {
+        const int cls = i / n, e = i - cls * n;
+        const int cr = cls >> 2, cc = cls & 3;
+        const int a = e / sd.pw - p, b = e % sd.pw - q;
+        int a0, a1, b0, b1;
+        switch (cr) {
+          case 0: a0 = a; a1 = a; break;
+          case 1: a0 = a; a1 = a >= 0 ? p : a - 1; break;
+          case 2: a0 = -p; a1 = a <= 0 ? a : -p - 1; break;
+          default: a0 = -p; a1 = a == 0 ? p : -p - 1; break;
+        }
+        switch (cc) {
+          case 0: b0 = b; b1 = b; break;
+          case 1: b0 = b; b1 = b >= 0 ? q : b - 1; break;
+          case 2: b0 = -q; b1 = b <= 0 ? b : -q - 1; break;
+          default: b0 = -q; b1 = b == 0 ? q : -q - 1; break;
+        }
+        double acc = 0.0;
+        for (int aa = a0; aa <= a1; ++aa)
+          for (int bb = b0; bb <= b1; ++bb) acc += (double)sd.psf[(aa + p) * sd.pw + (bb + q)];
+        sd.adjk[i] = (float)(acc * inv);
+      }
+    }
     return;
   }
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -174,6 +204,8 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
     p64s[p] = e;
   }
 
+  if (grad_corr)
+    for (int k = 0; k < NPAR; ++k) grad_corr[(size_t)p * NPAR + k] = 0.0;
   if (gcs) {
     GradConst gc;
     for (int k = 0; k < NPAR; ++k) gc.theta[k] = t[k];
@@ -189,13 +221,14 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
 }  // namespace
 
 hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, PointConst64* p64s, GradConst* gcs,
-                           const SysDesc& single, SysDesc* table, int n_sys, int* cusp_count, hipStream_t stream) {
+                           const SysDesc& single, SysDesc* table, int n_sys, int* cusp_count, hipStream_t stream,
+                           double* grad_corr) {
   const int threads = 64;
   const int point_blocks = (n_points + threads - 1) / threads;
   const int blocks = point_blocks + n_sys;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(prologue_kernel, dim3(blocks), dim3(threads), 0, stream, theta, n_points, pcs, p64s, gcs,
-                     single, table, n_sys, point_blocks, cusp_count);
+                     single, table, n_sys, point_blocks, cusp_count, grad_corr);
   return hipGetLastError();
 }
 

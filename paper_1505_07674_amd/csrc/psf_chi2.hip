@@ -108,7 +108,9 @@ __global__ __launch_bounds__(512) void psf_kernel(WorkArgs w, const float* __res
     if (gi < sd.H && gj < sd.W && i0 + r < TH) {
       const size_t idx = (size_t)gi * sd.W + gj;
       const float res = sd.data[idx] - acc[r];
-      const float term = sd.weight[idx] * res * res;
+      const float wres = sd.weight[idx] * res;
+      if (mode == 2) out[loff + idx] = wres;
+      const float term = wres * res;
       const float yk = term - comp;
       const float t = sum + yk;
       comp = (t - sum) - yk;

@@ -1,0 +1,165 @@
+"""GPU adjoint (lensed_loglike_grad) against the FP64 oracle's exact gradient
+(forward-mode dual numbers) and against central finite differences of the
+oracle's log L.
+
+Bar (per point): ||g_gpu - g_ref||_2 <= 1e-4 ||g_ref||_2, and the returned
+log L within the log-likelihood bar of the forward parity tests. At the truth of
+a mock (the likelihood maximum) g_ref is only the noise-driven gradient, of the
+order of the Fisher scale sqrt(sum_i w_i (dL*_i/dtheta)^2); there the float32
+model error (|dL*|/sigma ~ 3e-5 per pixel, partly correlated with dL*/dtheta)
+sets a floor near 1e-4 to 1e-3 of ||g_ref||, and the bar is 1e-3.
+"""
+import numpy as np
+import pytest
+import torch
+from concurrent.futures import ThreadPoolExecutor
+
+import oracle
+import paper_1505_07674_amd as lensed
+from paper_1505_07674_amd import mocks
+
+from helpers import loglike_tolerance, observation, oracle_system
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def gpu_system(spec, obs):
+    return lensed.System(torch.from_numpy(spec.psf).to(DEV), torch.from_numpy(obs.data).to(DEV),
+                         torch.from_numpy(obs.weight).to(DEV), pixscale=spec.pixscale, nsub=spec.nsub,
+                         center=(spec.center_x, spec.center_y))
+
+
+def oracle_grads(osys, pts):
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        res = list(ex.map(lambda t: oracle.loglike_grad(osys, np.asarray(t, np.float64)), pts))
+    return np.array([r[0] for r in res]), np.array([r[1] for r in res])
+
+
+def check(spec, obs, pts, tol=1e-4, truth_rows=()):
+    """Gradient bar at every point; the log L bar against the oracle away from the
+    truth rows (on a ~1e3-pixel image the float32 model noise at the truth, about
+    2 sqrt(N_w) |dL*/sigma|, reaches the N_w/2 x 1e-6 floor), and everywhere the
+    log L of the gradient plan equals the batched log L of the same points."""
+    gsys = gpu_system(spec, obs)
+    tp = torch.from_numpy(np.ascontiguousarray(pts)).to(DEV)
+    ll, g = lensed.loglike_grad(tp, gsys)
+    lb = lensed.loglike_batch(tp, np.zeros(len(pts), np.int32), [gsys]).cpu().numpy()
+    ll, g = ll.cpu().numpy(), g.cpu().numpy().astype(np.float64)
+    assert np.allclose(ll, lb, rtol=1e-12, atol=0)
+    rll, rg = oracle_grads(oracle_system(spec, obs), pts)
+    far = np.setdiff1d(np.arange(len(pts)), truth_rows)
+    assert np.all(np.abs(ll[far] - rll[far]) <= loglike_tolerance(rll[far], obs.weight))
+    rel = np.linalg.norm(g - rg, axis=1) / np.linalg.norm(rg, axis=1)
+    worst = int(np.argmax(rel))
+    assert rel.max() <= tol, (f"worst relative gradient error {rel.max():.3e} at point {worst}: "
+                              f"gpu {g[worst]} oracle {rg[worst]}")
+    return rel
+
+
+def small_spec(H=40, W=36, N=2, psf=None, pixscale=0.08, center=(0.05, -0.03)):
+    base = mocks.c1_spec()
+    psf = mocks.moffat_psf(7, 0.15, 3.0, pixscale) if psf is None else psf
+    return mocks.SystemSpec(f"grad_{H}x{W}_sub{N}", H, W, N, psf.astype(np.float32), base.truth, base.prior,
+                            mocks.annulus_mask(H, W, 0.2, 10.0, pixscale), 31, True, pixscale=pixscale,
+                            center_x=center[0], center_y=center[1])
+
+
+def small_obs(spec, seed=3):
+    osys = oracle_system(spec)
+    return mocks.make_observation(spec, lambda t: oracle.render(osys, np.asarray(t, np.float64)))
+
+
+def test_gradient_small_system_random_points():
+    spec = small_spec()
+    say("gradient, 40x36 sub2, 24 prior points")
+    obs = small_obs(spec)
+    pts = mocks.points(spec, 24, seed=41)
+    pts[0] = spec.truth
+    check(spec, obs, pts, truth_rows=[0])
+
+
+def test_gradient_when_the_signal_reaches_the_border():
+    """Large PSF, source image near the edge: the replicate-padding fold of A^T matters."""
+    psf = mocks.gaussian_psf(9, 0.3, 0.08) + 0.05
+    spec = small_spec(H=24, W=20, N=3, psf=psf)
+    say("gradient at the border fold")
+    obs = small_obs(spec)
+    pts = mocks.points(spec, 8, seed=43)
+    pts[:, 0] = 0.6           # images near the edges of the 1.9" x 1.6" field
+    pts[:, 10:12] = 0.15
+    check(spec, obs, pts)
+
+
+def test_gradient_isothermal_sphere_and_round_source():
+    spec = small_spec(H=32, W=32, N=4)
+    say("gradient, q = 1 lens")
+    obs = small_obs(spec)
+    pts = mocks.points(spec, 6, seed=47)
+    pts[:, 1] = 1.0           # SIS: derivative in q is the one-sided limit
+    pts[3:, 15] = 1.0         # round source
+    check(spec, obs, pts)
+
+
+def test_gradient_full_c1_shape():
+    """The C3 configuration: the 200x200 sub4 Moffat-21 model, 1024 points per launch,
+    checked against the oracle at sampled points."""
+    spec, obs = observation("c1")
+    say("gradient, C1 shape, 1024 points")
+    pts = mocks.points(spec, 1024, seed=mocks.C3_SEED)
+    pts[0] = spec.truth
+    gsys = gpu_system(spec, obs)
+    ll, g = lensed.loglike_grad(torch.from_numpy(pts).to(DEV), gsys)
+    g = g.cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(g))
+    idx = [0, 1, 517, 1023]
+    rll, rg = oracle_grads(oracle_system(spec, obs), pts[idx])
+    assert np.all(np.abs(ll.cpu().numpy()[idx] - rll) <= loglike_tolerance(rll, obs.weight))
+    rel = np.linalg.norm(g[idx] - rg, axis=1) / np.linalg.norm(rg, axis=1)
+    assert rel[0] <= 1e-3, rel          # the truth: noise-driven gradient
+    assert rel[1:].max() <= 1e-4, rel
+
+
+def test_gradient_matches_oracle_central_differences():
+    """Central differences of the FP64 oracle log L (Richardson-extrapolated), step
+    h_j = 1e-4 max(|theta_j|, 0.01 x prior width_j)."""
+    spec = small_spec(H=30, W=30, N=2)
+    say("gradient vs oracle finite differences")
+    obs = small_obs(spec)
+    osys = oracle_system(spec, obs)
+    t = spec.truth.astype(np.float32).copy()
+    t[0] += 0.02; t[14] += 0.1; t[10] -= 0.01
+    width = spec.prior.high - spec.prior.low
+    gsys = gpu_system(spec, obs)
+    _, g = lensed.loglike_grad(torch.from_numpy(t).view(1, 17).to(DEV), gsys)
+    g = g.cpu().numpy()[0].astype(np.float64)
+    tt = t.astype(np.float64)
+
+    def fd(k):
+        h = 1e-4 * max(abs(tt[k]), 0.01 * width[k])
+        def f(dh):
+            u = tt.copy(); u[k] += dh
+            return oracle.loglike(osys, u)
+        d1 = (f(h) - f(-h)) / (2 * h)
+        d2 = (f(h / 2) - f(-h / 2)) / h
+        return (4 * d2 - d1) / 3
+
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        ref = np.array(list(ex.map(fd, range(17))))
+    assert np.linalg.norm(g - ref) <= 1e-4 * np.linalg.norm(ref), (g, ref)
+
+
+def test_autograd_function_backward():
+    spec = small_spec()
+    obs = small_obs(spec)
+    gsys = gpu_system(spec, obs)
+    pts = torch.from_numpy(mocks.points(spec, 5, seed=53)).to(DEV).requires_grad_(True)
+    ll = lensed.LogLikeFn.apply(pts, gsys)
+    w = torch.linspace(0.5, 1.5, 5, device=DEV, dtype=torch.float64)
+    (ll * w).sum().backward()
+    _, g = lensed.loglike_grad(pts.detach(), gsys)
+    assert torch.allclose(pts.grad, (w[:, None].float() * g), rtol=1e-6, atol=0)
