@@ -139,6 +139,44 @@ int lensed_loglike_batch(lensed_ctx* ctx, const lensed_system* systems, int n_sy
 int lensed_loglike_grad(lensed_ctx* ctx, const lensed_system* sys, const float* theta,
                         int n_points, double* logl, float* grad, void* stream);
 
+/* ---- Surrogate network of log L ------------------------------------------
+ * A multilayer perceptron 17 -> 256 -> 256 -> 256 -> 1 with SiLU activations,
+ * run on the matrix cores with bfloat16 operands and float32 accumulation. It
+ * is trained on (theta, log L) pairs that the exact likelihood produces during
+ * a nested-sampling run and used to screen constrained draws; every accepted
+ * point is still evaluated exactly (not part of the paper's method: a training
+ * pattern added to its sampling loop, Sec. 3.2).
+ *   params  device float32 [LENSED_MLP_NPARAM], caller-owned master weights,
+ *           layout W1 [256][17], b1 [256], W2 [256][256], b2, W3 [256][256], b3,
+ *           W4 [1][256], b4 [1]; converted to bfloat16 on every call
+ *   norm    device float32 [36]: x_shift [17], x_scale [17], y_shift, y_scale;
+ *           the network sees (x - x_shift) * x_scale and outputs
+ *           y_shift + y_scale * net(...)
+ *   x       device float32 [batch][17]; y device float32 [batch]
+ *   batch   0..65536 rows
+ * The context owns the scratch (grown on demand); calls on one context must not
+ * overlap. */
+#define LENSED_MLP_NPARAM 136449
+int lensed_mlp_param_count(void);
+
+/* y = network(x). */
+int lensed_mlp_forward(lensed_ctx* ctx, const float* params, const float* norm, const float* x, float* y,
+                       int batch, void* stream);
+
+/* Mean squared error in normalised target units, loss = mean((out - (y - y_shift)/y_scale)^2)
+ * (device float32 [1]), and its gradient with respect to params (device float32 [LENSED_MLP_NPARAM]). */
+int lensed_mlp_grad(lensed_ctx* ctx, const float* params, const float* norm, const float* x, const float* y,
+                    int batch, float* grad, float* loss, void* stream);
+
+/* One Adam update (Kingma & Ba 2015) with bias correction for step >= 1:
+ * m, v device float32 [LENSED_MLP_NPARAM] moments (start at zero). */
+int lensed_mlp_adam(lensed_ctx* ctx, float* params, const float* grad, float* m, float* v, int step, float lr,
+                    float beta1, float beta2, float eps, void* stream);
+
+/* lensed_mlp_grad then lensed_mlp_adam with beta1 = 0.9, beta2 = 0.999, eps = 1e-8. */
+int lensed_mlp_train_step(lensed_ctx* ctx, float* params, float* m, float* v, int step, const float* norm,
+                          const float* x, const float* y, int batch, float lr, float* loss, void* stream);
+
 /* Instrumentation. With profiling enabled, lensed_loglike_batch runs its stages
  * without the captured graph and records a hipEvent between consecutive stages
  * on `stream`. lensed_stage_times waits for the recorded events and returns,

@@ -7,8 +7,8 @@ external shear (Eq. 1), add the lensed Sersic source to the Sersic lens light
 and reduce the weighted chi^2 / log-likelihood (Eq. 17) -- all in hand-written
 HIP kernels for gfx950 behind the C ABI of include/lensed.h.
 """
-from .binding import (NPARAM, Context, LensedError, LogLikeFn, System, default_context, loglike,
-                      loglike_batch, loglike_grad, render)
+from .binding import (MLP_NPARAM, NPARAM, Context, LensedError, LogLikeFn, System, default_context, loglike,
+                      loglike_batch, loglike_grad, mlp_adam, mlp_forward, mlp_grad, mlp_train_step, render)
 
-__all__ = ["NPARAM", "Context", "LensedError", "LogLikeFn", "System", "default_context", "loglike",
-           "loglike_batch", "loglike_grad", "render"]
+__all__ = ["MLP_NPARAM", "NPARAM", "Context", "LensedError", "LogLikeFn", "System", "default_context", "loglike",
+           "loglike_batch", "loglike_grad", "mlp_adam", "mlp_forward", "mlp_grad", "mlp_train_step", "render"]

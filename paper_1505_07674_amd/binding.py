@@ -64,6 +64,12 @@ def lib():
                 "lensed_loglike_batch": (i, [vp, sp, i, vp, ctypes.POINTER(ctypes.c_int32), i, vp, vp]),
                 "lensed_loglike_grad": (i, [vp, sp, vp, i, vp, vp, vp]),
                 "lensed_set_profiling": (i, [vp, i]),
+                "lensed_mlp_param_count": (i, []),
+                "lensed_mlp_forward": (i, [vp, vp, vp, vp, vp, i, vp]),
+                "lensed_mlp_grad": (i, [vp, vp, vp, vp, vp, i, vp, vp, vp]),
+                "lensed_mlp_adam": (i, [vp, vp, vp, vp, vp, i, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_float, vp]),
+                "lensed_mlp_train_step": (i, [vp, vp, vp, vp, i, vp, vp, vp, i, ctypes.c_float, vp, vp]),
                 "lensed_stage_times": (i, [vp, ctypes.POINTER(ctypes.c_double), i, ctypes.POINTER(ctypes.c_int)]),
             }
             for name, (res, args) in sig.items():
@@ -266,6 +272,70 @@ def loglike_grad(theta: torch.Tensor, system: System, *, ctx: Optional[Context] 
                                    _stream_handle(stream))
     ctx.check(rc, "lensed_loglike_grad")
     return ll, g
+
+
+MLP_NPARAM = 136449
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mlp_forward(params: torch.Tensor, norm: torch.Tensor, x: torch.Tensor, *, out: Optional[torch.Tensor] = None,
+                ctx: Optional[Context] = None, stream=None) -> torch.Tensor:
+    """Surrogate prediction y [B] for inputs x [B, 17] (bfloat16 MFMA kernels)."""
+    params = _dev_tensor(params, torch.float32, "params")
+    norm = _dev_tensor(norm, torch.float32, "norm")
+    x = _dev_tensor(x, torch.float32, "x")
+    if params.numel() != MLP_NPARAM or norm.numel() != 36 or x.dim() != 2 or x.shape[1] != NPARAM:
+        raise ValueError("params [136449], norm [36] and x [B, 17] expected")
+    ctx = ctx or default_context(x.device.index)
+    B = x.shape[0]
+    if out is None:
+        out = torch.empty(B, dtype=torch.float32, device=x.device)
+    rc = lib().lensed_mlp_forward(ctx.handle, _ptr(params), _ptr(norm), _ptr(x), _ptr(out), B,
+                                  _stream_handle(stream))
+    ctx.check(rc, "lensed_mlp_forward")
+    return out
+
+
+def mlp_grad(params: torch.Tensor, norm: torch.Tensor, x: torch.Tensor, y: torch.Tensor, *,
+             ctx: Optional[Context] = None, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """(loss [1], gradient [136449]) of the mean squared error in normalised target units."""
+    params = _dev_tensor(params, torch.float32, "params")
+    norm = _dev_tensor(norm, torch.float32, "norm")
+    x = _dev_tensor(x, torch.float32, "x")
+    y = _dev_tensor(y, torch.float32, "y")
+    ctx = ctx or default_context(x.device.index)
+    g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    rc = lib().lensed_mlp_grad(ctx.handle, _ptr(params), _ptr(norm), _ptr(x), _ptr(y), x.shape[0], _ptr(g),
+                               _ptr(loss), _stream_handle(stream))
+    ctx.check(rc, "lensed_mlp_grad")
+    return loss, g
+
+
+def mlp_adam(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
+             beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, *, ctx: Optional[Context] = None,
+             stream=None) -> None:
+    """In-place Adam update of params, m, v."""
+    ctx = ctx or default_context(params.device.index)
+    rc = lib().lensed_mlp_adam(ctx.handle, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
+                               float(beta1), float(beta2), float(eps), _stream_handle(stream))
+    ctx.check(rc, "lensed_mlp_adam")
+
+
+def mlp_train_step(params: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, norm: torch.Tensor,
+                   x: torch.Tensor, y: torch.Tensor, lr: float, *, loss: Optional[torch.Tensor] = None,
+                   ctx: Optional[Context] = None, stream=None) -> torch.Tensor:
+    """Gradient and Adam step in one call; returns the loss tensor [1] (before the step)."""
+    ctx = ctx or default_context(params.device.index)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    rc = lib().lensed_mlp_train_step(ctx.handle, _ptr(params), _ptr(m), _ptr(v), int(step), _ptr(norm), _ptr(x),
+                                     _ptr(y), x.shape[0], float(lr), _ptr(loss), _stream_handle(stream))
+    ctx.check(rc, "lensed_mlp_train_step")
+    return loss
 
 
 class LogLikeFn(torch.autograd.Function):

@@ -13,6 +13,7 @@
 #include "internal.h"
 #include "kernels.h"
 #include "lensed.h"
+#include "mlp.h"
 #include "plan.h"
 
 using namespace lensed;
@@ -30,6 +31,8 @@ struct lensed_ctx {
   std::vector<std::vector<hipEvent_t>> pending;    // event sets of profiled calls
   double stage_ms[LENSED_NSTAGES] = {0};
   int stage_calls = 0;
+  char* mlp_mem = nullptr;                          // surrogate scratch
+  MlpScratch mlp;
 };
 
 namespace {
@@ -65,6 +68,55 @@ int ensure_arena(lensed_ctx* c, size_t bytes) {
   const size_t n = align_up(std::max(bytes, (size_t)1 << 20), (size_t)1 << 20);
   LENSED_HIP(c, hipMalloc((void**)&c->arena, n));
   c->arena_bytes = n;
+  return LENSED_OK;
+}
+
+int ensure_mlp(lensed_ctx* c, int rows) {
+  if (c->mlp.cap >= rows) return LENSED_OK;
+  if (c->mlp_mem) {
+    LENSED_HIP(c, hipDeviceSynchronize());
+    LENSED_HIP(c, hipFree(c->mlp_mem));
+    c->mlp_mem = nullptr;
+    c->mlp = MlpScratch();
+  }
+  const size_t R = (size_t)std::max(rows, 256);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes, 256); return o; };
+  const size_t o_wb = take(sizeof(uint16_t) * MLP_WB_SIZE);
+  const size_t o_x0 = take(sizeof(uint16_t) * R * MLP_KPAD);
+  size_t o_z[3], o_h[3];
+  for (int l = 0; l < 3; ++l) {
+    o_z[l] = take(sizeof(float) * R * MLP_H);
+    o_h[l] = take(sizeof(uint16_t) * R * MLP_H);
+  }
+  const size_t o_d = take(sizeof(float) * R), o_sq = take(sizeof(float) * R);
+  const size_t o_dz = take(sizeof(float) * R * MLP_H), o_dz2 = take(sizeof(float) * R * MLP_H);
+  const size_t o_dzb = take(sizeof(uint16_t) * R * MLP_H), o_dzb2 = take(sizeof(uint16_t) * R * MLP_H);
+  const size_t o_g = take(sizeof(float) * MLP_NPARAM);
+  LENSED_HIP(c, hipMalloc((void**)&c->mlp_mem, off));
+  char* b = c->mlp_mem;
+  c->mlp.cap = (int)R;
+  c->mlp.wb = (uint16_t*)(b + o_wb);
+  c->mlp.X0 = (uint16_t*)(b + o_x0);
+  for (int l = 0; l < 3; ++l) {
+    c->mlp.Z[l] = (float*)(b + o_z[l]);
+    c->mlp.H[l] = (uint16_t*)(b + o_h[l]);
+  }
+  c->mlp.d = (float*)(b + o_d);
+  c->mlp.sq = (float*)(b + o_sq);
+  c->mlp.dZ = (float*)(b + o_dz);
+  c->mlp.dZ2 = (float*)(b + o_dz2);
+  c->mlp.dZb = (uint16_t*)(b + o_dzb);
+  c->mlp.dZb2 = (uint16_t*)(b + o_dzb2);
+  c->mlp.grad = (float*)(b + o_g);
+  return LENSED_OK;
+}
+
+constexpr int MLP_MAX_BATCH = 1 << 16;
+
+int check_mlp_batch(lensed_ctx* c, int batch) {
+  if (batch < 0 || batch > MLP_MAX_BATCH)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "batch must be in 0.." + std::to_string(MLP_MAX_BATCH));
   return LENSED_OK;
 }
 
@@ -171,6 +223,7 @@ void lensed_destroy(lensed_ctx* c) {
   for (auto& ev : c->pending)
     for (auto& e : ev) (void)hipEventDestroy(e);
   if (c->arena) (void)hipFree(c->arena);
+  if (c->mlp_mem) (void)hipFree(c->mlp_mem);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
 }
@@ -367,3 +420,65 @@ extern "C" int lensed_loglike_grad(lensed_ctx* c, const lensed_system* sys, cons
   LENSED_HIP(c, plan->run((hipStream_t)stream));
   return LENSED_OK;
 }
+
+extern "C" {
+
+int lensed_mlp_param_count(void) { return MLP_NPARAM; }
+
+int lensed_mlp_forward(lensed_ctx* c, const float* params, const float* norm, const float* x, float* y, int batch,
+                       void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  int rc = check_mlp_batch(c, batch);
+  if (rc) return rc;
+  if (batch == 0) return LENSED_OK;
+  if (!params || !norm || !x || !y) return set_err(c, LENSED_INVALID_ARGUMENT, "params, norm, x and y are required");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  if ((rc = ensure_mlp(c, batch))) return rc;
+  LENSED_HIP(c, mlp_forward(params, norm, x, y, batch, c->mlp, (hipStream_t)stream));
+  return LENSED_OK;
+}
+
+int lensed_mlp_grad(lensed_ctx* c, const float* params, const float* norm, const float* x, const float* y, int batch,
+                    float* grad, float* loss, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  int rc = check_mlp_batch(c, batch);
+  if (rc) return rc;
+  if (batch == 0) return set_err(c, LENSED_INVALID_ARGUMENT, "the loss needs at least one row");
+  if (!params || !norm || !x || !y || !grad || !loss)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "params, norm, x, y, grad and loss are required");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  if ((rc = ensure_mlp(c, batch))) return rc;
+  LENSED_HIP(c, mlp_grad(params, norm, x, y, batch, grad, loss, c->mlp, (hipStream_t)stream));
+  return LENSED_OK;
+}
+
+int lensed_mlp_adam(lensed_ctx* c, float* params, const float* grad, float* m, float* v, int step, float lr,
+                    float beta1, float beta2, float eps, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  if (!params || !grad || !m || !v) return set_err(c, LENSED_INVALID_ARGUMENT, "params, grad, m and v are required");
+  if (step < 1 || !std::isfinite(lr) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+      !(eps > 0.0f))
+    return set_err(c, LENSED_INVALID_ARGUMENT, "step >= 1, finite lr, betas in [0,1) and eps > 0 are required");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  LENSED_HIP(c, mlp_adam(params, grad, m, v, MLP_NPARAM, step, lr, beta1, beta2, eps, (hipStream_t)stream));
+  return LENSED_OK;
+}
+
+int lensed_mlp_train_step(lensed_ctx* c, float* params, float* m, float* v, int step, const float* norm,
+                          const float* x, const float* y, int batch, float lr, float* loss, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  int rc = check_mlp_batch(c, batch);
+  if (rc) return rc;
+  if (batch == 0) return set_err(c, LENSED_INVALID_ARGUMENT, "the loss needs at least one row");
+  if (!params || !m || !v || !norm || !x || !y || !loss)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "params, m, v, norm, x, y and loss are required");
+  if (step < 1 || !std::isfinite(lr)) return set_err(c, LENSED_INVALID_ARGUMENT, "step >= 1 and finite lr required");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  if ((rc = ensure_mlp(c, batch))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  LENSED_HIP(c, mlp_grad(params, norm, x, y, batch, c->mlp.grad, loss, c->mlp, st));
+  LENSED_HIP(c, mlp_adam(params, c->mlp.grad, m, v, MLP_NPARAM, step, lr, 0.9f, 0.999f, 1e-8f, st));
+  return LENSED_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,242 @@
+"""Nested sampling with and without the learned screen, on the GPU likelihood.
+
+``GpuLogLike`` turns unit-cube points of the free parameters into float64 log L
+through the batched library path (one graph launch per call). It pads every
+call up to a power-of-two bucket so that the library's cached launch plans are
+reused instead of rebuilt for each new batch size; padding rows are copies of
+the first point and are not counted as evaluations.
+
+``SurrogateScreen`` wraps a trained ``Surrogate`` as the sampler's screen. Its
+margin starts from the held-out residuals and is recalibrated as the run goes:
+every candidate that passes the screen is evaluated exactly, and its residual
+(prediction minus exact log L) joins the calibration set. The margin at a
+threshold L_min is ``sigmas`` times the root-mean-square residual of the
+calibration pairs whose exact log L is nearest L_min. The run's own residuals
+are kept for the most recent ``keep`` evaluations: the threshold only rises, so
+older pairs lie below it.
+
+``compare_runs`` is the end-to-end experiment: a plain run that records every
+exact (theta, log L) pair, a second plain run with another seed (the null
+spread of the sampler itself), the surrogate trained on the first run's pairs,
+and a screened run; it reports exact renders per accepted point and the
+posterior mean shifts in units of the plain posterior standard deviation.
+"""
+from __future__ import annotations
+
+import math
+import time
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+from . import binding
+from .mocks import Observation, SystemSpec
+from .sampler import NestedSampler, NSResult, Screen
+from .surrogate import Surrogate
+
+
+class GpuLogLike:
+    def __init__(self, spec: SystemSpec, obs: Observation, device: torch.device, min_bucket: int = 64,
+                 ctx: Optional[binding.Context] = None):
+        self.spec = spec
+        self.device = device
+        self.free = spec.prior.free
+        self.ctx = ctx or binding.Context(device.index or 0)
+        self.system = binding.System(torch.from_numpy(spec.psf).to(device), torch.from_numpy(obs.data).to(device),
+                                     torch.from_numpy(obs.weight).to(device), pixscale=spec.pixscale,
+                                     nsub=spec.nsub, center=(spec.center_x, spec.center_y))
+        self.min_bucket = min_bucket
+        self.buffers: Dict[int, tuple] = {}
+        self.n_calls = 0
+        self.n_points = 0
+        self.gpu_s = 0.0
+
+    def theta(self, u: np.ndarray) -> np.ndarray:
+        lo, hi = self.spec.prior.low, self.spec.prior.high
+        full = np.tile(lo, (len(u), 1))
+        full[:, self.free] = lo[self.free] + np.asarray(u) * (hi - lo)[self.free]
+        return full.astype(np.float32)
+
+    def __call__(self, u: np.ndarray) -> np.ndarray:
+        u = np.atleast_2d(np.asarray(u))
+        n = len(u)
+        if n == 0:
+            return np.zeros(0)
+        cap = max(self.min_bucket, 1 << (n - 1).bit_length())
+        if cap not in self.buffers:
+            self.buffers[cap] = (torch.empty((cap, 17), dtype=torch.float32, device=self.device),
+                                 torch.empty(cap, dtype=torch.float64, device=self.device),
+                                 np.zeros(cap, np.int32))
+        tb, lb, sop = self.buffers[cap]
+        th = self.theta(u)
+        if n < cap:
+            th = np.concatenate([th, np.repeat(th[:1], cap - n, axis=0)])
+        t0 = time.perf_counter()
+        tb.copy_(torch.from_numpy(th))
+        binding.loglike_batch(tb, sop, [self.system], out=lb, ctx=self.ctx)
+        out = lb[:n].cpu().numpy().copy()
+        self.gpu_s += time.perf_counter() - t0
+        self.n_calls += 1
+        self.n_points += n
+        return out
+
+
+class SurrogateScreen(Screen):
+    def __init__(self, surrogate: Surrogate, sigmas: float = 3.0, window: int = 200, floor: float = 1.0,
+                 max_skips: int = 2000, keep: int = 8192):
+        self.surrogate = surrogate
+        self.sigmas = sigmas
+        self.window = window
+        self.floor = floor
+        self.max_skips = max_skips
+        self.keep = keep
+        self.held_l, self.held_r = (np.asarray(a, np.float64) for a in surrogate.margin_table)
+        self.run_l = np.zeros(0)
+        self.run_r = np.zeros(0)
+        self._sorted = None
+        self.n_predicted = 0
+
+    def predict(self, u: np.ndarray) -> np.ndarray:
+        self.n_predicted += len(u)
+        return self.surrogate.predict(u)
+
+    def observe(self, u: np.ndarray, exact: np.ndarray) -> None:
+        """Add the residuals of exactly evaluated points to the calibration set."""
+        ok = np.isfinite(exact)
+        if not ok.any():
+            return
+        pred = self.surrogate.predict(np.asarray(u)[ok])
+        ex = np.asarray(exact, np.float64)[ok]
+        self.run_l = np.concatenate([self.run_l, ex])[-self.keep:]
+        self.run_r = np.concatenate([self.run_r, pred - ex])[-self.keep:]
+        self._sorted = None
+
+    def margin(self, lmin: float) -> float:
+        if self._sorted is None:
+            ll = np.concatenate([self.held_l, self.run_l])
+            order = np.argsort(ll)
+            self._sorted = (ll[order], np.concatenate([self.held_r, self.run_r])[order])
+        ll, res = self._sorted
+        i = int(np.searchsorted(ll, lmin))
+        lo, hi = max(0, i - self.window // 2), min(len(ll), i + self.window // 2)
+        w = res[lo:hi] if hi > lo else res
+        return max(self.sigmas * float(np.sqrt(np.mean(w * w))), self.floor)
+
+
+class _Observed:
+    """The likelihood callable of a screened run: also feeds residuals back to the screen."""
+
+    def __init__(self, loglike, screen: SurrogateScreen):
+        self.loglike = loglike
+        self.screen = screen
+
+    def __call__(self, u):
+        ll = self.loglike(u)
+        self.screen.observe(u, ll)
+        return ll
+
+
+def _summary(res: NSResult, wall: float) -> dict:
+    return {"logz": res.logz, "logz_err": res.logz_err, "n_exact": res.n_exact, "n_accepted": res.n_accepted,
+            "n_iter": res.n_iter, "renders_per_accepted": res.renders_per_accepted,
+            "n_screened_out": res.n_screened_out, "wall_s": wall}
+
+
+def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, n_live: int = 400, k_replace: int = 40,
+                 seeds=(5, 6, 7), dlogz: float = 0.5, max_iter: int = 5000, train_epochs: int = 60,
+                 train_batch: int = 1024, sigmas: float = 3.0, log=print, log_every: int = 100) -> dict:
+    """Plain run A (recorded), plain run B (null), surrogate fit on A, screened run C."""
+    ll = GpuLogLike(spec, obs, device)
+    ndim = len(ll.free)
+    out = {"system": spec.name, "n_live": n_live, "k_replace": k_replace, "ndim": ndim, "free": ll.free.tolist()}
+
+    def run(seed, screen=None, record=False, fn=None):
+        s = NestedSampler(fn or ll, ndim, n_live=n_live, k_replace=k_replace, dlogz=dlogz, seed=seed,
+                          max_iter=max_iter, record=record)
+        t0 = time.perf_counter()
+        r = s.run(screen=screen, log=log, log_every=log_every)
+        return r, time.perf_counter() - t0
+
+    log(f"plain run, seed {seeds[0]} (recording pairs)")
+    ra, wa = run(seeds[0], record=True)
+    log(f"  {ra.n_exact} exact evaluations, {ra.n_iter} iterations, log Z {ra.logz:.2f}, {wa:.1f} s")
+    log(f"plain run, seed {seeds[1]}")
+    rb, wb = run(seeds[1])
+    log(f"  {rb.n_exact} exact evaluations, {rb.n_iter} iterations, log Z {rb.logz:.2f}, {wb:.1f} s")
+
+    sur = Surrogate(device, seed=seeds[0], free=ll.free)
+    t0 = time.perf_counter()
+    fit = sur.fit(ra.evaluated_u, ra.evaluated_logl, epochs=train_epochs, batch=train_batch)
+    torch.cuda.synchronize(device)
+    fit["wall_s"] = time.perf_counter() - t0
+    log(f"surrogate trained on {fit['n_train']} pairs in {fit['wall_s']:.1f} s, held-out rmse(log -logL) "
+        f"{fit['rmse_logy']:.4f}")
+    screen = SurrogateScreen(sur, sigmas=sigmas)
+    log(f"screened run, seed {seeds[2]}")
+    rc, wc = run(seeds[2], screen=screen, fn=_Observed(ll, screen))
+    log(f"  {rc.n_exact} exact evaluations, {rc.n_screened_out} screened out, log Z {rc.logz:.2f}, {wc:.1f} s")
+
+    to_theta = lambda u: ll.theta(u)[:, ll.free].astype(np.float64)
+    ma, sa = ra.posterior_moments(to_theta)
+    mb, sb = rb.posterior_moments(to_theta)
+    mc, sc = rc.posterior_moments(to_theta)
+    out.update({
+        "plain": _summary(ra, wa), "plain_null": _summary(rb, wb), "screened": _summary(rc, wc), "fit": fit,
+        "renders_per_accepted_ratio": ra.renders_per_accepted / rc.renders_per_accepted,
+        "posterior_mean_plain": ma.tolist(), "posterior_std_plain": sa.tolist(),
+        "posterior_mean_null": mb.tolist(), "posterior_std_null": sb.tolist(),
+        "posterior_mean_screened": mc.tolist(), "posterior_std_screened": sc.tolist(),
+        "shift_screened_sigma": (np.abs(mc - ma) / sa).tolist(),
+        "shift_null_sigma": (np.abs(mb - ma) / sa).tolist(),
+    })
+    out["max_shift_screened_sigma"] = float(np.max(out["shift_screened_sigma"]))
+    out["max_shift_null_sigma"] = float(np.max(out["shift_null_sigma"]))
+    return out
+
+
+def library_mock(spec: SystemSpec, device: torch.device) -> Observation:
+    """A mock observation of spec whose noiseless image the library itself renders."""
+    from .mocks import make_observation
+    psf = torch.from_numpy(spec.psf).to(device)
+    rsys = binding.System(psf, pixscale=spec.pixscale, nsub=spec.nsub, height=spec.height, width=spec.width,
+                          center=(spec.center_x, spec.center_y))
+    return make_observation(
+        spec, lambda t: binding.render(torch.from_numpy(np.asarray(t, np.float32)).to(device), rsys).cpu().numpy())
+
+
+def main(argv=None) -> int:
+    import argparse
+    import json
+    import sys
+
+    from . import mocks
+    ap = argparse.ArgumentParser(description="nested sampling with and without the learned screen")
+    ap.add_argument("--system", choices=["64x64", "200x200"], default="200x200")
+    ap.add_argument("--n-live", type=int, default=400)
+    ap.add_argument("--k-replace", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--sigmas", type=float, default=3.0)
+    ap.add_argument("--max-iter", type=int, default=5000)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    if not torch.cuda.is_available():
+        print("a GPU is required", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda:0")
+    spec = mocks.c0_spec() if a.system == "64x64" else mocks.c1_spec()
+    obs = library_mock(spec, dev)
+    log = lambda m: print(m, flush=True)
+    res = compare_runs(spec, obs, dev, n_live=a.n_live, k_replace=a.k_replace, train_epochs=a.epochs,
+                       sigmas=a.sigmas, max_iter=a.max_iter, seeds=(mocks.C4_SEED, mocks.C4_SEED + 1,
+                                                                    mocks.C4_SEED + 2), log=log)
+    text = json.dumps(res)
+    print(text, flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text + "\n")
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
