@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--cpu-points-per-core", type=int, default=4)
     ap.add_argument("--grad-points", type=int, default=1024)
     ap.add_argument("--grad-steps", type=int, default=5)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before timing, copy a MIB-MiB device buffer once (a plain copy of known size that scales "
+                         "hardware byte counters taken over the same run)")
     return ap.parse_args()
 
 
@@ -99,6 +102,16 @@ def main():
     out = torch.empty(P, dtype=torch.float64, device=dev)
     ctx = lensed.default_context(0)
     stream = torch.cuda.current_stream()
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
+        del src, dst
 
     log(f"batched: {P} points, warmup {args.warmup}")
     for _ in range(args.warmup):

@@ -169,13 +169,16 @@ int lensed_mlp_grad(lensed_ctx* ctx, const float* params, const float* norm, con
                     int batch, float* grad, float* loss, void* stream);
 
 /* One Adam update (Kingma & Ba 2015) with bias correction for step >= 1:
- * m, v device float32 [LENSED_MLP_NPARAM] moments (start at zero). */
-int lensed_mlp_adam(lensed_ctx* ctx, float* params, const float* grad, float* m, float* v, int step, float lr,
-                    float beta1, float beta2, float eps, void* stream);
+ * m, v device float32 [LENSED_MLP_NPARAM] moments (start at zero). The
+ * hyperparameters are float64 so that 1 - beta and the bias corrections
+ * 1 - beta^step are formed exactly before rounding to float32. Invalid
+ * arguments: step < 1, non-finite lr, beta outside [0, 1), eps <= 0. */
+int lensed_mlp_adam(lensed_ctx* ctx, float* params, const float* grad, float* m, float* v, int step, double lr,
+                    double beta1, double beta2, double eps, void* stream);
 
 /* lensed_mlp_grad then lensed_mlp_adam with beta1 = 0.9, beta2 = 0.999, eps = 1e-8. */
 int lensed_mlp_train_step(lensed_ctx* ctx, float* params, float* m, float* v, int step, const float* norm,
-                          const float* x, const float* y, int batch, float lr, float* loss, void* stream);
+                          const float* x, const float* y, int batch, double lr, float* loss, void* stream);
 
 /* Instrumentation. With profiling enabled, lensed_loglike_batch runs its stages
  * without the captured graph and records a hipEvent between consecutive stages

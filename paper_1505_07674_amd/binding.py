@@ -67,9 +67,9 @@ def lib():
                 "lensed_mlp_param_count": (i, []),
                 "lensed_mlp_forward": (i, [vp, vp, vp, vp, vp, i, vp]),
                 "lensed_mlp_grad": (i, [vp, vp, vp, vp, vp, i, vp, vp, vp]),
-                "lensed_mlp_adam": (i, [vp, vp, vp, vp, vp, i, ctypes.c_float, ctypes.c_float, ctypes.c_float,
-                                        ctypes.c_float, vp]),
-                "lensed_mlp_train_step": (i, [vp, vp, vp, vp, i, vp, vp, vp, i, ctypes.c_float, vp, vp]),
+                "lensed_mlp_adam": (i, [vp, vp, vp, vp, vp, i, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, vp]),
+                "lensed_mlp_train_step": (i, [vp, vp, vp, vp, i, vp, vp, vp, i, ctypes.c_double, vp, vp]),
                 "lensed_stage_times": (i, [vp, ctypes.POINTER(ctypes.c_double), i, ctypes.POINTER(ctypes.c_int)]),
             }
             for name, (res, args) in sig.items():

@@ -18,6 +18,7 @@
 #include "internal.h"
 #include "kernels.h"
 #include "sb_device.h"
+#include "stencil.h"
 
 namespace lensed {
 namespace {
@@ -42,7 +43,7 @@ __device__ __forceinline__ void resolve(const WorkArgs& w, int& point, int& tile
 // ---------------------------------------------------------------------------
 // g = A^T rho, interior pixels: g[u][v] = sum_{a,b} rho0[u+a][v+b] F[a][b].
 // ---------------------------------------------------------------------------
-template <int P>
+template <int P, int TWc, int ROWS>
 __global__ __launch_bounds__(512) void adj_psf_kernel(WorkArgs w, const float* __restrict__ R, float* __restrict__ G) {
   extern __shared__ float S[];
   int point, tile;
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(512) void adj_psf_kernel(WorkArgs w, const float* _
   const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
   const int p = P >= 0 ? P : sd.ph / 2;
   const int q = P >= 0 ? P : sd.pw / 2;
-  const int TW = sd.TW, TH = sd.TH;
+  const int TW = P >= 0 ? TWc : sd.TW, TH = sd.TH;
   const int SW = TW + 2 * q, SH = TH + 2 * p;
   const int ty = tile / sd.tiles_x, tx = tile - ty * sd.tiles_x;
   const int x0 = tx * TW, y0 = ty * TH;
@@ -67,36 +68,28 @@ __global__ __launch_bounds__(512) void adj_psf_kernel(WorkArgs w, const float* _
     }
   }
   __syncthreads();
-  const float* __restrict__ F = sd.psfn;
-  const int i0 = jy * PSF_ROWS;
-  float acc[PSF_ROWS];
+  const int i0 = jy * ROWS;
+  float acc[ROWS];
 #pragma unroll
-  for (int r = 0; r < PSF_ROWS; ++r) acc[r] = 0.0f;
+  for (int r = 0; r < ROWS; ++r) acc[r] = 0.0f;
   if (P >= 0) {
     constexpr int K = 2 * (P > 0 ? P : 0) + 1;
-    for (int l = 0; l < K; ++l) {
-      float v[PSF_ROWS + K - 1];
-#pragma unroll
-      for (int m = 0; m < PSF_ROWS + K - 1; ++m) v[m] = S[(i0 + m) * SW + jx + l];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const float f = F[k * K + l];
-#pragma unroll
-        for (int r = 0; r < PSF_ROWS; ++r) acc[r] = fmaf(f, v[r + k], acc[r]);
-      }
-    }
+    constexpr int SWc = (TWc > 0 ? TWc : 1) + K - 1;
+    // taps F[k][l] of stencil column l, contiguous in k
+    stencil_columns<K, SWc, ROWS>(S + i0 * SWc + jx, uniform_const(sd.psfn + 2 * K * K), acc);
   } else {
+    const float* __restrict__ F = sd.psfn;
     const int KH = 2 * p + 1, KW = 2 * q + 1;
     for (int l = 0; l < KW; ++l)
       for (int k = 0; k < KH; ++k) {
         const float f = F[k * KW + l];
 #pragma unroll
-        for (int r = 0; r < PSF_ROWS; ++r) acc[r] = fmaf(f, S[(i0 + r + k) * SW + jx + l], acc[r]);
+        for (int r = 0; r < ROWS; ++r) acc[r] = fmaf(f, S[(i0 + r + k) * SW + jx + l], acc[r]);
       }
   }
   const int gj = x0 + jx;
 #pragma unroll
-  for (int r = 0; r < PSF_ROWS; ++r) {
+  for (int r = 0; r < ROWS; ++r) {
     const int gi = y0 + i0 + r;
     const bool border = gi == 0 || gi == sd.H - 1 || gj == 0 || gj == sd.W - 1;
     if (gi < sd.H && gj < sd.W && i0 + r < TH && !border) G[loff + (size_t)gi * sd.W + gj] = acc[r];
@@ -457,12 +450,7 @@ __global__ __launch_bounds__(64 * GCUSP_WAVES) void grad_cusp_kernel(WorkArgs w,
         const float y = fmaf(geo.uy + sub_offset_rt(ky, N), geo.d, geo.cy);
         for (int kx = 0; kx < N; ++kx) {
           const float x = fmaf(geo.ux + sub_offset_rt(kx, N), geo.d, geo.cx);
-          float sR2;
-          switch (c.sie_mode) {
-            case 0: sR2 = source_r2<0>(c, x, y); break;
-            case 1: sR2 = source_r2<1>(c, x, y); break;
-            default: sR2 = source_r2<2>(c, x, y); break;
-          }
+          const float sR2 = render_source_R2(c, x, y);
           if (sR2 < c.cusp_r2) {
             float dx, dy;
             source_offset_f64(p64s[e.point], geo, kx, ky, N, dx, dy);
@@ -504,11 +492,18 @@ __global__ void finalize_grad_kernel(const float2* __restrict__ gpart, const int
   grad[t] = (float)s;
 }
 
-template <int P>
-hipError_t launch_adj_t(const WorkArgs& w, const float* R, float* G, int n_blocks, int threads, size_t lds,
+template <int P, int TWc, int R>
+hipError_t launch_adj_t(const WorkArgs& w, const float* R_, float* G, int n_blocks, int threads, size_t lds,
                         hipStream_t st) {
-  hipLaunchKernelGGL(adj_psf_kernel<P>, dim3(n_blocks), dim3(threads), lds, st, w, R, G);
+  hipLaunchKernelGGL((adj_psf_kernel<P, TWc, R>), dim3(n_blocks), dim3(threads), lds, st, w, R_, G);
   return hipGetLastError();
+}
+
+template <int P, int R>
+hipError_t launch_adj_w(int TW, const WorkArgs& w, const float* R_, float* G, int n_blocks, int threads, size_t lds,
+                        hipStream_t st) {
+  if (TW == 64) return launch_adj_t<P, 64, R>(w, R_, G, n_blocks, threads, lds, st);
+  return launch_adj_t<P, 32, R>(w, R_, G, n_blocks, threads, lds, st);
 }
 
 }  // namespace
@@ -516,13 +511,18 @@ hipError_t launch_adj_t(const WorkArgs& w, const float* R, float* G, int n_block
 hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n_blocks, int square_psf, int TW,
                               int TH, int ph, int pw, int n_points, int H, int W, hipStream_t st) {
   if (n_blocks <= 0) return hipSuccess;
-  const int threads = TW * (TH / PSF_ROWS);
+  const int Rr = psf_rows(square_psf, TW, TH);
+  const int threads = TW * (TH / Rr);
   const size_t lds = sizeof(float) * (size_t)(TW + pw - 1) * (size_t)(TH + ph - 1);
   hipError_t e;
-  if (square_psf == 21) e = launch_adj_t<10>(w, R, G, n_blocks, threads, lds, st);
-  else if (square_psf == 7) e = launch_adj_t<3>(w, R, G, n_blocks, threads, lds, st);
-  else if (square_psf == 1) e = launch_adj_t<0>(w, R, G, n_blocks, threads, lds, st);
-  else e = launch_adj_t<-1>(w, R, G, n_blocks, threads, lds, st);
+  if (psf_specialised(square_psf, TW)) {
+    if (square_psf == 21) e = Rr == 8 ? launch_adj_w<10, 8>(TW, w, R, G, n_blocks, threads, lds, st)
+                                      : launch_adj_w<10, 4>(TW, w, R, G, n_blocks, threads, lds, st);
+    else if (square_psf == 7) e = launch_adj_w<3, 4>(TW, w, R, G, n_blocks, threads, lds, st);
+    else e = launch_adj_w<0, 4>(TW, w, R, G, n_blocks, threads, lds, st);
+  } else {
+    e = launch_adj_t<-1, 0, 4>(w, R, G, n_blocks, threads, lds, st);
+  }
   if (e != hipSuccess) return e;
   const int nb = (H <= 2 || W <= 2) ? H * W : 2 * W + 2 * (H - 2);
   hipLaunchKernelGGL(adj_border_kernel, dim3((nb + 63) / 64, n_points), dim3(64), 0, st, w, R, G, nb);

@@ -242,7 +242,7 @@ int lensed_render(lensed_ctx* c, const lensed_system* sys, const float* theta, f
   const size_t off_pc = 0;
   const size_t off_p64 = align_up(off_pc + sizeof(PointConst), 256);
   const size_t off_psf = align_up(off_p64 + sizeof(PointConst64), 256);
-  const size_t off_cc = align_up(off_psf + sizeof(float) * sd.ph * sd.pw, 256);
+  const size_t off_cc = align_up(off_psf + 3 * sizeof(float) * sd.ph * sd.pw, 256);
   const size_t off_ce = align_up(off_cc + sizeof(int), 256);
   const size_t off_L = align_up(off_ce + sizeof(CuspEntry) * (size_t)sd.n_rtiles * (RENDER_BLOCK / 64), 256);
   const size_t total = align_up(off_L + sizeof(float) * npix, 256);
@@ -276,7 +276,7 @@ int lensed_loglike(lensed_ctx* c, const lensed_system* sys, const float* theta, 
   const size_t off_pc = 0;
   const size_t off_p64 = align_up(off_pc + sizeof(PointConst), 256);
   const size_t off_psf = align_up(off_p64 + sizeof(PointConst64), 256);
-  const size_t off_cc = align_up(off_psf + sizeof(float) * sd.ph * sd.pw, 256);
+  const size_t off_cc = align_up(off_psf + 3 * sizeof(float) * sd.ph * sd.pw, 256);
   const size_t off_ce = align_up(off_cc + sizeof(int), 256);
   const size_t off_L = align_up(off_ce + sizeof(CuspEntry) * (size_t)sd.n_rtiles * (RENDER_BLOCK / 64), 256);
   const size_t off_part = align_up(off_L + sizeof(float) * npix, 256);
@@ -452,12 +452,12 @@ int lensed_mlp_grad(lensed_ctx* c, const float* params, const float* norm, const
   return LENSED_OK;
 }
 
-int lensed_mlp_adam(lensed_ctx* c, float* params, const float* grad, float* m, float* v, int step, float lr,
-                    float beta1, float beta2, float eps, void* stream) {
+int lensed_mlp_adam(lensed_ctx* c, float* params, const float* grad, float* m, float* v, int step, double lr,
+                    double beta1, double beta2, double eps, void* stream) {
   if (!c) return LENSED_INVALID_ARGUMENT;
   if (!params || !grad || !m || !v) return set_err(c, LENSED_INVALID_ARGUMENT, "params, grad, m and v are required");
-  if (step < 1 || !std::isfinite(lr) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
-      !(eps > 0.0f))
+  if (step < 1 || !std::isfinite(lr) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+      !(eps > 0.0))
     return set_err(c, LENSED_INVALID_ARGUMENT, "step >= 1, finite lr, betas in [0,1) and eps > 0 are required");
   LENSED_HIP(c, hipSetDevice(c->device));
   LENSED_HIP(c, mlp_adam(params, grad, m, v, MLP_NPARAM, step, lr, beta1, beta2, eps, (hipStream_t)stream));
@@ -465,7 +465,7 @@ int lensed_mlp_adam(lensed_ctx* c, float* params, const float* grad, float* m, f
 }
 
 int lensed_mlp_train_step(lensed_ctx* c, float* params, float* m, float* v, int step, const float* norm,
-                          const float* x, const float* y, int batch, float lr, float* loss, void* stream) {
+                          const float* x, const float* y, int batch, double lr, float* loss, void* stream) {
   if (!c) return LENSED_INVALID_ARGUMENT;
   int rc = check_mlp_batch(c, batch);
   if (rc) return rc;
@@ -477,7 +477,7 @@ int lensed_mlp_train_step(lensed_ctx* c, float* params, float* m, float* v, int 
   if ((rc = ensure_mlp(c, batch))) return rc;
   hipStream_t st = (hipStream_t)stream;
   LENSED_HIP(c, mlp_grad(params, norm, x, y, batch, c->mlp.grad, loss, c->mlp, st));
-  LENSED_HIP(c, mlp_adam(params, c->mlp.grad, m, v, MLP_NPARAM, step, lr, 0.9f, 0.999f, 1e-8f, st));
+  LENSED_HIP(c, mlp_adam(params, c->mlp.grad, m, v, MLP_NPARAM, step, lr, 0.9, 0.999, 1e-8, st));
   return LENSED_OK;
 }
 

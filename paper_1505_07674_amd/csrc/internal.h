@@ -32,8 +32,25 @@ struct PointConst {
   // source subsamples with R^2/R_e^2 below this are re-traced in float64 (0 = never)
   float cusp_r2;
   float pad[4];
+  // ---- folded forms used by the forward render (the adjoint uses the fields above)
+  // rmode: 0 sphere, 1 polynomials (q' <= 1/2), 2 log + half-angle atan with
+  // argument <= 1/sqrt(3) (q >= 1/2), 3 log + half-angle atan on [0, 1] (q < 1/2).
+  int rmode;
+  // alpha_x = tac At - ths Ah, alpha_y = tas At + thc Ah, with the factors 2
+  // (half angle) and ln 2 (log2) of modes 2 and 3 folded in; mode 0: tac = theta_E.
+  float tac, tas, thc, ths;
+  // scaled frame of the Sersic profiles: (R/R_e)^2 = X^2 + Y^2,
+  // X = a11 dx + a12 dy, Y = a21 dx + a22 dy (sqrt(q)/R_e and 1/(sqrt(q) R_e) folded in)
+  float h11, h12, h21, h22;
+  float s11, s12, s21, s22;
+  // the source frame of beta - (x_S, y_S) in one step: with S = (s11 s12; s21 s22),
+  // X = A1 x + (B1 y + C1) + cXt At + cXh Ah, Y = A2 x + (B2 y + C2) + cYt At + cYh Ah,
+  // (A1 A2) = S (m11 m12), (B1 B2) = S (m12 m22), (C1 C2) = -S (x_S y_S),
+  // cXt = -(s11 tac + s12 tas), cXh = s11 ths - s12 thc, and the same with s21, s22.
+  float A1, A2, B1, B2, C1, C2, cXt, cXh, cYt, cYh;
+  float pad2[9];
 };
-static_assert(sizeof(PointConst) == 32 * 4, "PointConst layout");
+static_assert(sizeof(PointConst) == 64 * 4, "PointConst layout");
 
 // Float64 lens constants for the rare re-tracing of subsamples that land next
 // to the centre of a cuspy (n > 1) source, where the float32 rounding of the
@@ -64,7 +81,8 @@ struct SysDesc {
   int ph, pw;             // PSF dimensions (odd)
   float d, cx, cy;        // pixel scale and grid centre
   const float* psf;       // caller's PSF (unnormalised)
-  float* psfn;            // library copy, normalised to unit sum
+  float* psfn;            // library copies normalised to unit sum: row-major, column-major flipped,
+                          // column-major (3 ph pw floats)
   const float* data;
   const float* weight;
   int TW, TH;             // PSF/chi^2 output tile

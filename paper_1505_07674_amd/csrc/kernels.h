@@ -40,12 +40,12 @@ hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointCo
 //         (hi, lo) float pair per tile is written to partials.
 // mode 2: as mode 1, and the weighted residual w (d - L*) is written to out.
 // Every system of one launch uses the same TW x TH output tile (the block is
-// TW x TH/4 threads). square_psf = 21, 7 or 1 selects a specialised stencil when
-// every PSF of the launch has that square size; -1 selects the generic one.
+// TW x TH/R threads, R = psf_rows()). square_psf = 21, 7 or 1 with TW = 32 or 64
+// selects a specialised stencil when every PSF of the launch has that square
+// size; anything else runs the generic one.
 hipError_t launch_psf(const WorkArgs& w, const float* L, float* out, float2* partials, int mode, int n_blocks,
                       int square_psf, int TW, int TH, int max_ph, int max_pw, hipStream_t stream);
 
-constexpr int PSF_ROWS = 4;   // outputs per thread of the PSF kernel
 
 // log L = -1/2 * sum over the point's tiles of (hi + lo), in float64.
 hipError_t launch_finalize(const float2* partials, const int* point_pbase, const int* point_ntiles, int n_points,

@@ -44,7 +44,7 @@ hipError_t mlp_forward(const float* params, const float* norm, const float* x, f
                        hipStream_t st);
 hipError_t mlp_grad(const float* params, const float* norm, const float* x, const float* yt, int B, float* grad,
                     float* loss, const MlpScratch& s, hipStream_t st);
-hipError_t mlp_adam(float* params, const float* grad, float* m, float* v, int n, int step, float lr, float beta1,
-                    float beta2, float eps, hipStream_t st);
+hipError_t mlp_adam(float* params, const float* grad, float* m, float* v, int n, int step, double lr, double beta1,
+                    double beta2, double eps, hipStream_t st);
 
 }  // namespace lensed

@@ -15,6 +15,8 @@
 // x_scale [17], y_shift, y_scale.
 #include <stdint.h>
 
+#include <cmath>
+
 #include "internal.h"
 #include "kernels.h"
 #include "mlp.h"
@@ -227,15 +229,18 @@ __global__ __launch_bounds__(256) void mean_kernel(const float* __restrict__ x, 
   if (threadIdx.x == 0) out[0] = red[0] / (float)n;
 }
 
-// Adam (Kingma & Ba 2015) with bias corrections bc1 = 1 - beta1^t, bc2 = 1 - beta2^t.
+// Adam (Kingma & Ba 2015): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// p -= lr (m / bc1) / (sqrt(v / bc2) + eps), bc = 1 - b^t. The factors 1 - b
+// and the bias corrections come from the host in float64 (1 - b2 rounded from a
+// float b2 would carry a 1e-5 relative error).
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                            float* __restrict__ v, int n, float lr, float beta1, float beta2, float eps, float bc1,
-                            float bc2) {
+                            float* __restrict__ v, int n, float lr, float beta1, float omb1, float beta2, float omb2,
+                            float eps, float bc1, float bc2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
-  const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
-  const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+  const float mi = fmaf(beta1, m[i], omb1 * gi);
+  const float vi = fmaf(beta2, v[i], omb2 * gi * gi);
   m[i] = mi;
   v[i] = vi;
   p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
@@ -340,11 +345,12 @@ hipError_t mlp_grad(const float* params, const float* norm, const float* x, cons
   return hipSuccess;
 }
 
-hipError_t mlp_adam(float* params, const float* grad, float* m, float* v, int n, int step, float lr, float beta1,
-                    float beta2, float eps, hipStream_t st) {
-  const float bc1 = 1.0f - powf(beta1, (float)step), bc2 = 1.0f - powf(beta2, (float)step);
-  hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, st, params, grad, m, v, n, lr, beta1, beta2,
-                     eps, bc1, bc2);
+hipError_t mlp_adam(float* params, const float* grad, float* m, float* v, int n, int step, double lr, double beta1,
+                    double beta2, double eps, hipStream_t st) {
+  const double bc1 = 1.0 - std::pow(beta1, (double)step), bc2 = 1.0 - std::pow(beta2, (double)step);
+  hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, st, params, grad, m, v, n, (float)lr,
+                     (float)beta1, (float)(1.0 - beta1), (float)beta2, (float)(1.0 - beta2), (float)eps, (float)bc1,
+                     (float)bc2);
   return hipGetLastError();
 }
 

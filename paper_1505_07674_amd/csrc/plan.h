@@ -29,8 +29,8 @@ class TileCache {
   TileShape choose(const lensed_system& s);
   TileShape choose_common(const lensed_system* s, int n);
   void set(int H, int W, int ph, int pw, TileShape t) { cache_[std::make_tuple(H, W, ph, pw)] = t; }
-  static double model_cost(int H, int W, int ph, int pw, TileShape t);
-  static std::vector<TileShape> candidates();
+  static double model_cost(int H, int W, int ph, int pw, TileShape t, int sq);
+  static std::vector<TileShape> candidates(int sq);
 
  private:
   std::map<std::tuple<int, int, int, int>, TileShape> cache_;

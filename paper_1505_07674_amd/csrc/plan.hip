@@ -4,26 +4,35 @@
 #include <numeric>
 
 #include "plan.h"
+#include "stencil.h"
 
 namespace lensed {
 
-std::vector<TileShape> TileCache::candidates() {
+std::vector<TileShape> TileCache::candidates(int sq) {
   std::vector<TileShape> out;
   const int tws[] = {16, 32, 40, 48, 64};
   const int ths[] = {16, 20, 24, 32, 40, 48, 64};
   for (int tw : tws)
     for (int th : ths) {
-      const int threads = tw * th / PSF_ROWS;
+      const int threads = tw * th / psf_rows(sq, tw, th);
       if (threads >= 64 && threads <= 512) out.push_back({tw, th});
     }
   return out;
 }
 
-double TileCache::model_cost(int H, int W, int ph, int pw, TileShape t) {
+// Lane slots of one launch: per tile, the block's lanes (whole waves) times the
+// per-thread work of R outputs (R ph pw FMAs and pw (R + ph - 1) LDS reads),
+// plus the LDS staging of the tile and its halo and a fixed block cost. The
+// generic stencil (runtime sizes, taps by vector loads) costs twice as much
+// per tap as the specialised ones. sq is the square-PSF code of the launch
+// (-1 when its systems differ), which decides the kernel and R.
+double TileCache::model_cost(int H, int W, int ph, int pw, TileShape t, int sq) {
+  const int R = psf_rows(sq, t.TW, t.TH);
   const double ntiles = (double)((W + t.TW - 1) / t.TW) * (double)((H + t.TH - 1) / t.TH);
-  const int threads = t.TW * t.TH / PSF_ROWS;
+  const int threads = t.TW * t.TH / R;
   const double lanes = 64.0 * ((threads + 63) / 64);
-  const double per_lane = (double)PSF_ROWS * ph * pw + (double)pw * (PSF_ROWS + ph - 1);
+  const double tap = psf_specialised(sq, t.TW) ? 1.0 : 2.0;
+  const double per_lane = tap * (double)R * ph * pw + 0.5 * (double)pw * (R + ph - 1);
   const double staging = 6.0 * (double)(t.TW + pw - 1) * (double)(t.TH + ph - 1);
   return ntiles * (lanes * per_lane + staging + 2000.0);
 }
@@ -34,8 +43,9 @@ TileShape TileCache::choose(const lensed_system& s) {
   if (it != cache_.end()) return it->second;
   TileShape best{32, 32};
   double bc = 1e300;
-  for (const TileShape& t : candidates()) {
-    const double cst = model_cost(s.height, s.width, s.psf_h, s.psf_w, t);
+  const int sq = square_psf_code(s.psf_h, s.psf_w);
+  for (const TileShape& t : candidates(sq)) {
+    const double cst = model_cost(s.height, s.width, s.psf_h, s.psf_w, t, sq);
     if (cst < bc) {
       bc = cst;
       best = t;
@@ -49,9 +59,12 @@ TileShape TileCache::choose_common(const lensed_system* s, int n) {
   if (n == 1) return choose(s[0]);
   TileShape best{32, 32};
   double bc = 1e300;
-  for (const TileShape& t : candidates()) {
+  int sq = square_psf_code(s[0].psf_h, s[0].psf_w);
+  for (int i = 1; i < n; ++i)
+    if (square_psf_code(s[i].psf_h, s[i].psf_w) != sq) sq = -1;
+  for (const TileShape& t : candidates(sq)) {
     double cst = 0.0;
-    for (int i = 0; i < n; ++i) cst += model_cost(s[i].height, s[i].width, s[i].psf_h, s[i].psf_w, t);
+    for (int i = 0; i < n; ++i) cst += model_cost(s[i].height, s[i].width, s[i].psf_h, s[i].psf_w, t, sq);
     if (cst < bc) {
       bc = cst;
       best = t;
@@ -157,7 +170,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   const size_t o_pi = off; off = align256(off + sizeof(int2) * n_pitems_);
   const size_t o_pc = off; off = align256(off + sizeof(PointConst) * n_points);
   const size_t o_p64 = off; off = align256(off + sizeof(PointConst64) * n_points);
-  const size_t o_psf = off; off = align256(off + sizeof(float) * psf_total);
+  const size_t o_psf = off; off = align256(off + 3 * sizeof(float) * psf_total);
   const size_t o_cc = off; off = align256(off + sizeof(int));
   const size_t o_ce = off; off = align256(off + sizeof(CuspEntry) * (size_t)n_ritems_ * (RENDER_BLOCK / 64));
   const size_t o_L = off; off = align256(off + sizeof(float) * (size_t)Ltot);
@@ -188,7 +201,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   cusp_.entries = (CuspEntry*)(mem_ + o_ce);
   d_L_ = (float*)(mem_ + o_L);
   d_part_ = (float2*)(mem_ + o_part);
-  for (int s = 0; s < n_systems; ++s) desc[s].psfn = (float*)(mem_ + o_psf) + psf_off[s];
+  for (int s = 0; s < n_systems; ++s) desc[s].psfn = (float*)(mem_ + o_psf) + 3 * psf_off[s];
   if (g) {
     d_gc_ = (GradConst*)(mem_ + o_gc);
     d_R_ = (float*)(mem_ + o_R);

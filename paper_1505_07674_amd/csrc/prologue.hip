@@ -82,7 +82,14 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
       __syncthreads();
     }
     const double inv = 1.0 / part[0];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) sd.psfn[i] = (float)((double)sd.psf[i] * inv);
+    // three copies: row-major; column-major flipped (the convolution's taps, column
+    // l = KW-1-b, row k = KH-1-a for entry (a, b)); column-major (the transpose's taps)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      sd.psfn[i] = (float)((double)sd.psf[i] * inv);
+      const int l = i / sd.ph, k = i - l * sd.ph;
+      sd.psfn[n + i] = (float)((double)sd.psf[(sd.ph - 1 - k) * sd.pw + (sd.pw - 1 - l)] * inv);
+      sd.psfn[2 * n + i] = (float)((double)sd.psf[k * sd.pw + l] * inv);
+    }
     if (sd.adjk) {
       // Folded tables of the transposed convolution: for border class (cr, cc)
       // (0 interior, 1 first, 2 last, 3 both, per axis) the entry at offset (a, b)
@@ -182,10 +189,57 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
     c.cusp_r2 = t[14] > 1.0f ? (float)(rc * rc) : 0.0f;
   }
   for (int k = 0; k < 4; ++k) c.pad[k] = 0.0f;
+  // folded constants of the forward render
+  double tac = te, tas = 0.0, thc = 0.0, ths = 0.0;
+  c.rmode = 0;
+  if (s2 != 0.0) {
+    const double k = te * sqrt(q) / qp;
+    const double fa = qp <= 0.5 ? 1.0 : 2.0, fh = qp <= 0.5 ? 1.0 : 0.693147180559945309417;
+    c.rmode = qp <= 0.5 ? 1 : (q >= 0.5 ? 2 : 3);
+    tac = fa * k * cos(phL);
+    tas = fa * k * sin(phL);
+    thc = fh * k * cos(phL);
+    ths = fh * k * sin(phL);
+  }
+  c.tac = (float)tac;
+  c.tas = (float)tas;
+  c.thc = (float)thc;
+  c.ths = (float)ths;
+  {
+    const double Re = t[6], qh = t[8], ph = t[9];
+    const double a = sqrt(qh) / Re, b = 1.0 / (sqrt(qh) * Re), cs = cos(ph), sn = sin(ph);
+    c.h11 = (float)(a * cs);
+    c.h12 = (float)(a * sn);
+    c.h21 = (float)(-b * sn);
+    c.h22 = (float)(b * cs);
+  }
+  {
+    const double Re = t[13], qs = t[15], ph = t[16];
+    const double a = sqrt(qs) / Re, b = 1.0 / (sqrt(qs) * Re), cs = cos(ph), sn = sin(ph);
+    const double s11 = a * cs, s12 = a * sn, s21 = -b * sn, s22 = b * cs;
+    c.s11 = (float)s11;
+    c.s12 = (float)s12;
+    c.s21 = (float)s21;
+    c.s22 = (float)s22;
+    // the source frame of the lens equation in one step (float64 products, one rounding each)
+    const double m11 = 1.0 - g1, m12 = -g2, m22 = 1.0 + g1, xs = t[10], ys = t[11];
+    c.A1 = (float)(s11 * m11 + s12 * m12);
+    c.A2 = (float)(s21 * m11 + s22 * m12);
+    c.B1 = (float)(s11 * m12 + s12 * m22);
+    c.B2 = (float)(s21 * m12 + s22 * m22);
+    c.C1 = (float)(-(s11 * xs + s12 * ys));
+    c.C2 = (float)(-(s21 * xs + s22 * ys));
+    c.cXt = (float)(-(s11 * tac + s12 * tas));
+    c.cXh = (float)(s11 * ths - s12 * thc);
+    c.cYt = (float)(-(s21 * tac + s22 * tas));
+    c.cYh = (float)(s21 * ths - s22 * thc);
+  }
+  for (int k = 0; k < 9; ++k) c.pad2[k] = 0.0f;
   if (!valid) {
     const float nan = __builtin_nanf("");
     c.m11 = c.m12 = c.m22 = nan;
     c.hI = c.sI = nan;
+    c.A1 = c.A2 = nan;
   }
   pcs[p] = c;
   if (p64s) {

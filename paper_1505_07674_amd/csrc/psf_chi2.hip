@@ -6,17 +6,17 @@
 // image with clamped indices (the replicate padding of Eq. 15), then every
 // thread computes R vertically adjacent outputs: for each stencil column it
 // keeps R + 2p LDS values in registers and applies the 2p + 1 kernel taps of
-// that column to all R outputs. Kernel taps are wave-uniform (scalar loads).
+// that column to all R outputs. Kernel taps are wave-uniform scalar loads from
+// a column-major copy of the flipped kernel written by the prologue.
 // The chi^2 contribution w (d - L*)^2 is accumulated with Kahan summation per
 // thread, combined across the block with error-free TwoSum steps, and written
 // as one (hi, lo) float pair per tile; the final sum over tiles is float64.
 #include "internal.h"
 #include "kernels.h"
+#include "stencil.h"
 
 namespace lensed {
 namespace {
-
-constexpr int ROWS = 4;   // outputs per thread (R)
 
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   s = a + b;
@@ -24,7 +24,9 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   e = (a - (s - bb)) + (b - bb);
 }
 
-template <int P>
+// P >= 0: square (2P+1)^2 PSF, tile width TWc, ROWS outputs per thread.
+// P = -1: any PSF and tile width, ROWS = 4.
+template <int P, int TWc, int ROWS>
 __global__ __launch_bounds__(512) void psf_kernel(WorkArgs w, const float* __restrict__ L, float* __restrict__ out,
                                                    float2* __restrict__ partials, int mode) {
   extern __shared__ float S[];
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(512) void psf_kernel(WorkArgs w, const float* __res
   const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
   const int p = P >= 0 ? P : sd.ph / 2;
   const int q = P >= 0 ? P : sd.pw / 2;
-  const int TW = sd.TW, TH = sd.TH;
+  const int TW = P >= 0 ? TWc : sd.TW, TH = sd.TH;
   const int SW = TW + 2 * q, SH = TH + 2 * p;
   const int ty = tile / sd.tiles_x, tx = tile - ty * sd.tiles_x;
   const int x0 = tx * TW, y0 = ty * TH;
@@ -61,26 +63,18 @@ __global__ __launch_bounds__(512) void psf_kernel(WorkArgs w, const float* __res
   }
   __syncthreads();
 
-  const float* __restrict__ F = sd.psfn;
   const int i0 = jy * ROWS;
   float acc[ROWS];
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) acc[r] = 0.0f;
   if (P >= 0) {
     constexpr int K = 2 * (P > 0 ? P : 0) + 1;
-    for (int l = 0; l < K; ++l) {
-      float v[ROWS + K - 1];
-#pragma unroll
-      for (int m = 0; m < ROWS + K - 1; ++m) v[m] = S[(i0 + m) * SW + jx + l];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const float f = F[(K - 1 - k) * K + (K - 1 - l)];
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) acc[r] = fmaf(f, v[r + k], acc[r]);
-      }
-    }
+    constexpr int SWc = (TWc > 0 ? TWc : 1) + K - 1;
+    // taps F[K-1-k][K-1-l] of stencil column l, contiguous in k
+    stencil_columns<K, SWc, ROWS>(S + i0 * SWc + jx, uniform_const(sd.psfn + K * K), acc);
   } else {
     const int KH = 2 * p + 1, KW = 2 * q + 1;
+    const float* __restrict__ F = sd.psfn;
     for (int l = 0; l < KW; ++l) {
       for (int k = 0; k < KH; ++k) {
         const float f = F[(KH - 1 - k) * KW + (KW - 1 - l)];
@@ -162,11 +156,18 @@ __global__ void finalize_kernel(const float2* __restrict__ partials, const int* 
   logl[p] = -0.5 * s;
 }
 
-template <int P>
+template <int P, int TWc, int R>
 hipError_t launch_psf_t(const WorkArgs& w, const float* L, float* out, float2* partials, int mode, int n_blocks,
                         int threads, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL(psf_kernel<P>, dim3(n_blocks), dim3(threads), lds, stream, w, L, out, partials, mode);
+  hipLaunchKernelGGL((psf_kernel<P, TWc, R>), dim3(n_blocks), dim3(threads), lds, stream, w, L, out, partials, mode);
   return hipGetLastError();
+}
+
+template <int P, int R>
+hipError_t launch_psf_w(int TW, const WorkArgs& w, const float* L, float* out, float2* partials, int mode,
+                        int n_blocks, int threads, size_t lds, hipStream_t stream) {
+  if (TW == 64) return launch_psf_t<P, 64, R>(w, L, out, partials, mode, n_blocks, threads, lds, stream);
+  return launch_psf_t<P, 32, R>(w, L, out, partials, mode, n_blocks, threads, lds, stream);
 }
 
 }  // namespace
@@ -174,13 +175,19 @@ hipError_t launch_psf_t(const WorkArgs& w, const float* L, float* out, float2* p
 hipError_t launch_psf(const WorkArgs& w, const float* L, float* out, float2* partials, int mode, int n_blocks,
                       int square_psf, int TW, int TH, int max_ph, int max_pw, hipStream_t stream) {
   if (n_blocks <= 0) return hipSuccess;
-  const int threads = TW * (TH / ROWS);
+  const int R = psf_rows(square_psf, TW, TH);
+  const int threads = TW * (TH / R);
   const size_t lds = sizeof(float) * (size_t)(TW + max_pw - 1) * (size_t)(TH + max_ph - 1);
   // Specialised stencils for the square PSFs of the standard workloads.
-  if (square_psf == 21) return launch_psf_t<10>(w, L, out, partials, mode, n_blocks, threads, lds, stream);
-  if (square_psf == 7) return launch_psf_t<3>(w, L, out, partials, mode, n_blocks, threads, lds, stream);
-  if (square_psf == 1) return launch_psf_t<0>(w, L, out, partials, mode, n_blocks, threads, lds, stream);
-  return launch_psf_t<-1>(w, L, out, partials, mode, n_blocks, threads, lds, stream);
+  if (psf_specialised(square_psf, TW)) {
+    if (square_psf == 21) {
+      if (R == 8) return launch_psf_w<10, 8>(TW, w, L, out, partials, mode, n_blocks, threads, lds, stream);
+      return launch_psf_w<10, 4>(TW, w, L, out, partials, mode, n_blocks, threads, lds, stream);
+    }
+    if (square_psf == 7) return launch_psf_w<3, 4>(TW, w, L, out, partials, mode, n_blocks, threads, lds, stream);
+    return launch_psf_w<0, 4>(TW, w, L, out, partials, mode, n_blocks, threads, lds, stream);
+  }
+  return launch_psf_t<-1, 0, 4>(w, L, out, partials, mode, n_blocks, threads, lds, stream);
 }
 
 hipError_t launch_finalize(const float2* partials, const int* point_pbase, const int* point_ntiles, int n_points,

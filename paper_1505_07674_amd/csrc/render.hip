@@ -6,7 +6,8 @@
 // consecutive pixels of one image in row-major order, so stores are coalesced
 // and only the last block of an image is ragged. The per-point constants are
 // read through wave-uniform addresses (scalar loads), and the integration rule
-// and the SIE branch are resolved once per block.
+// and the SIE branch are resolved once per block. The lens light and the
+// source light are summed separately and signed once per pixel.
 #include "internal.h"
 #include "kernels.h"
 #include "sb_device.h"
@@ -65,10 +66,11 @@ __global__ __launch_bounds__(RENDER_BLOCK) void render_kernel(WorkArgs w, const 
     const PixelGeom g = pixel_geom(sd, pix);
     const PointConst& c = pcs[point];
     float acc;
-    switch (c.sie_mode) {
+    switch (c.rmode) {
       case 0: acc = pixel_sum_dispatch<0>(c, sd.N, g, cusp); break;
       case 1: acc = pixel_sum_dispatch<1>(c, sd.N, g, cusp); break;
-      default: acc = pixel_sum_dispatch<2>(c, sd.N, g, cusp); break;
+      case 2: acc = pixel_sum_dispatch<2>(c, sd.N, g, cusp); break;
+      default: acc = pixel_sum_dispatch<3>(c, sd.N, g, cusp); break;
     }
     L[loff + pix] = (float)((double)acc * sd.wgt);
   }
@@ -104,12 +106,7 @@ __global__ __launch_bounds__(64 * CUSP_WAVES) void cusp_kernel(WorkArgs w, const
     const int pix = e.pix0 + lane;
     const PixelGeom g = pixel_geom(sd, pix);
     const PointConst& c = pcs[e.point];
-    float corr;
-    switch (c.sie_mode) {
-      case 0: corr = cusp_correction<0>(c, p64s[e.point], sd.N, g); break;
-      case 1: corr = cusp_correction<1>(c, p64s[e.point], sd.N, g); break;
-      default: corr = cusp_correction<2>(c, p64s[e.point], sd.N, g); break;
-    }
+    const float corr = cusp_correction(c, p64s[e.point], sd.N, g);
     L[loff + pix] = (float)((double)L[loff + pix] + (double)corr * sd.wgt);
   }
 }

@@ -41,57 +41,6 @@ __device__ __forceinline__ float atan_small(float u) {
 __device__ __forceinline__ float atan_unit(float u) { return u * horner<ATAN_UNIT_POLY_DEGREE>(ATAN_UNIT_POLY, u * u); }
 __device__ __forceinline__ float atanh_poly(float v) { return v * horner<ATANH_POLY_DEGREE>(ATANH_POLY, v * v); }
 
-// Source-plane position of image-plane point (x, y).
-template <int MODE>
-__device__ __forceinline__ void lens_map(const PointConst& c, float x, float y, float& bx, float& by) {
-  if (MODE == 0) {
-    const float r2 = fmaf(x, x, y * y);
-    const float ir = r2 > 0.0f ? hw_rsq(r2) : 0.0f;
-    const float s = c.kc * ir;
-    bx = fmaf(c.m11, x, fmaf(c.m12, y, -s * x));
-    by = fmaf(c.m12, x, fmaf(c.m22, y, -s * y));
-  } else {
-    const float xp = fmaf(c.cL, x, c.sL * y);
-    const float yp = fmaf(c.cL, y, -c.sL * x);
-    const float yp2 = yp * yp;
-    const float psi2 = fmaf(c.q2 * xp, xp, yp2);
-    const float ip = psi2 > 0.0f ? hw_rsq(psi2) : 0.0f;
-    float At, Ah;
-    if (MODE == 1) {
-      const float tq = c.qp * ip;
-      At = atan_small(tq * xp);
-      Ah = atanh_poly(tq * yp);
-    } else {
-      const float r2 = fmaf(xp, xp, yp2);
-      const float ir = hw_rsq(r2);
-      const float psi = psi2 * ip;
-      const float r = r2 * ir;
-      At = 2.0f * atan_unit(c.qp * xp * hw_rcp(psi + r));
-      const float num = fmaf(c.qp, fabsf(yp), psi);
-      const float l = LN2F * hw_log2(num * ir * c.iq);
-      At = psi2 > 0.0f ? At : 0.0f;
-      Ah = psi2 > 0.0f ? copysignf(l, yp) : 0.0f;
-    }
-    const float ax = fmaf(c.kc, At, -c.ks * Ah);
-    const float ay = fmaf(c.ks, At, c.kc * Ah);
-    bx = fmaf(c.m11, x, fmaf(c.m12, y, -ax));
-    by = fmaf(c.m12, x, fmaf(c.m22, y, -ay));
-  }
-}
-
-// Elliptical Sersic profile in two steps: the scaled squared radius
-// R^2/R_e^2 = qa x'^2 + qb y'^2 (rotation (cs, sn), qa = q/R_e^2, qb = 1/(q R_e^2)),
-// then I = I_e 2^{B (1 - t)} with t = (R^2/R_e^2)^{e}, e = 1/(2n), B = b_n log2(e).
-__device__ __forceinline__ float sersic_r2(float dx, float dy, float cs, float sn, float qa, float qb) {
-  const float xp = fmaf(cs, dx, sn * dy);
-  const float yp = fmaf(cs, dy, -sn * dx);
-  return fmaf(qa * xp, xp, qb * yp * yp);
-}
-__device__ __forceinline__ float sersic_from_r2(float R2, float e, float B, float Ie) {
-  const float t = hw_exp2(e * hw_log2(R2));
-  return Ie * hw_exp2(fmaf(-B, t, B));
-}
-
 // Midpoint offset of subsample k of N, in pixel units: (k + 1/2)/N - 1/2.
 template <int N>
 __device__ __forceinline__ constexpr float sub_offset(int k) {
@@ -131,57 +80,160 @@ __device__ __forceinline__ void source_offset_f64(const PointConst64& e, const P
   dy = (float)(e.m12 * x + e.m22 * y - ay - e.sy0);
 }
 
-// Scaled squared source radius of subsample (x, y), float32 path.
-template <int MODE>
-__device__ __forceinline__ float source_r2(const PointConst& c, float x, float y) {
-  float bx, by;
-  lens_map<MODE>(c, x, y, bx, by);
-  return sersic_r2(bx - c.sx0, by - c.sy0, c.sc, c.ss, c.sqa, c.sqb);
+// ---------------------------------------------------------------------------
+// Forward render, float32, with the folded constants of PointConst (rmode,
+// tac, h11..h22, s11..s22, A1..cYh). Every product and sum is written out
+// with explicit fmaf so that the render kernel and the cusp correction, which
+// must reproduce the render's float32 value of a subsample, round identically.
+// ---------------------------------------------------------------------------
+
+// Terms of the subsample grid that depend on the row (y) only.
+constexpr float SIE_TINY = 1e-30f;
+
+struct RowTerms {
+  float y, y2t;       // y and y^2 + SIE_TINY (sphere)
+  float sLy, cLy;     // SIE frame: x' = cL x + sL y, y' = cL y - sL x
+  float rX, rY;       // B1 y + C1, B2 y + C2: row part of the source frame of beta
+  float s12y, s22y;   // sphere: s12 y, s22 y
+  float hx, hy;       // lens-light frame: h12 y, h22 y
+};
+
+__device__ __forceinline__ RowTerms row_terms(const PointConst& c, float y) {
+  RowTerms r;
+  r.y = y;
+  r.y2t = fmaf(y, y, SIE_TINY);
+  r.sLy = c.sL * y;
+  r.cLy = c.cL * y;
+  r.rX = fmaf(c.B1, y, c.C1);
+  r.rY = fmaf(c.B2, y, c.C2);
+  r.s12y = c.s12 * y;
+  r.s22y = c.s22 * y;
+  r.hx = c.h12 * y;
+  r.hy = c.h22 * y;
+  return r;
 }
 
-// Surface brightness at one subsample; `cusp` is raised when the float32 source
-// radius falls inside the cusp zone, where a correction kernel later replaces
-// this subsample's source light by its float64 re-traced value.
-template <int MODE>
-__device__ __forceinline__ float surface_brightness(const PointConst& c, float x, float y, bool& cusp) {
-  const float Ih = sersic_from_r2(sersic_r2(x, y, c.hc, c.hs, c.hqa, c.hqb), c.he, c.hB, c.hI);
-  const float sR2 = source_r2<MODE>(c, x, y);
+// Source-frame coordinates (X, Y) of beta - (x_S, y_S), (R/R_e)^2 = X^2 + Y^2,
+// for the image-plane subsample (x, row y): Eq. 1 with the SIE + external shear,
+// the shear matrix, the source centre and the source ellipse folded into
+// per-point constants.
+//
+// The lens centre needs no branch: x'^2 carries SIE_TINY (arcsec^2), so that at
+// x' = y' = 0 exactly psi = q sqrt(SIE_TINY), r = sqrt(SIE_TINY), the atan argument
+// is 0 and the atanh log argument is psi/(q r) = 1: the deflection there is 0
+// (to rounding), the value the method takes at its singular point. Elsewhere
+// the offset changes x'^2 by a relative 1e-30 / x'^2, below float32 resolution
+// for any |x'| above 1e-11 arcsec.
+template <int RM>
+__device__ __forceinline__ void source_frame(const PointConst& c, const RowTerms& r, float x, float& X, float& Y) {
+  const float lX = fmaf(c.A1, x, r.rX);
+  const float lY = fmaf(c.A2, x, r.rY);
+  if (RM == 0) {
+    const float s = c.tac * hw_rsq(fmaf(x, x, r.y2t));   // alpha = s (x, y)
+    X = fmaf(-s, fmaf(c.s11, x, r.s12y), lX);
+    Y = fmaf(-s, fmaf(c.s21, x, r.s22y), lY);
+    return;
+  }
+  const float xp = fmaf(c.cL, x, r.sLy);
+  const float yp = fmaf(-c.sL, x, r.cLy);
+  const float yp2 = yp * yp;
+  const float x2t = fmaf(xp, xp, SIE_TINY);
+  const float psi2 = fmaf(c.q2, x2t, yp2);
+  float At, Ah;
+  if (RM == 1) {
+    const float tq = c.qp * hw_rsq(psi2);
+    At = atan_small(tq * xp);
+    Ah = atanh_poly(tq * yp);
+  } else {
+    const float r2 = x2t + yp2;
+    const float psi = __builtin_amdgcn_sqrtf(psi2);
+    const float ir = hw_rsq(r2);
+    const float u = c.qp * xp * hw_rcp(fmaf(r2, ir, psi));
+    At = RM == 2 ? atan_small(u) : atan_unit(u);
+    Ah = copysignf(hw_log2(fmaf(c.qp, fabsf(yp), psi) * ir * c.iq), yp);
+  }
+  X = fmaf(c.cXt, At, fmaf(c.cXh, Ah, lX));
+  Y = fmaf(c.cYt, At, fmaf(c.cYh, Ah, lY));
+}
+
+// (R/R_e)^2 of the source at offset (dx, dy) from its centre.
+__device__ __forceinline__ float source_R2(const PointConst& c, float dx, float dy) {
+  const float X = fmaf(c.s11, dx, c.s12 * dy);
+  const float Y = fmaf(c.s21, dx, c.s22 * dy);
+  return fmaf(X, X, Y * Y);
+}
+
+// Sersic shape I / I_e = exp2(B (1 - t)), t = (R^2/R_e^2)^e; the amplitude I_e is
+// a per-point factor and multiplies the pixel sums instead of every subsample.
+__device__ __forceinline__ float sersic_shape(float R2, float e, float B) {
+  return hw_exp2(fmaf(-B, hw_exp2(e * hw_log2(R2)), B));
+}
+
+// Lens-light and source shapes at one subsample, and the cusp flag.
+template <int RM>
+__device__ __forceinline__ void subsample_light(const PointConst& c, const RowTerms& r, float x, float& h, float& s,
+                                                bool& cusp) {
+  const float X = fmaf(c.h11, x, r.hx);
+  const float Y = fmaf(c.h21, x, r.hy);
+  h = sersic_shape(fmaf(X, X, Y * Y), c.he, c.hB);
+  float sX, sY;
+  source_frame<RM>(c, r, x, sX, sY);
+  const float sR2 = fmaf(sX, sX, sY * sY);
   cusp = cusp || (sR2 < c.cusp_r2);
-  return Ih + sersic_from_r2(sR2, c.se, c.sB, c.sI);
+  s = sersic_shape(sR2, c.se, c.sB);
 }
 
 // Sum of the surface brightness over the N x N midpoint abscissae of a pixel.
-template <int N, int MODE>
+template <int N, int RM>
 __device__ __forceinline__ float pixel_sum(const PointConst& c, const PixelGeom& g, bool& cusp) {
-  float acc = 0.0f;
+  float sh = 0.0f, ss = 0.0f;
+  float xs[N];
+#pragma unroll
+  for (int kx = 0; kx < N; ++kx) xs[kx] = fmaf(g.ux + sub_offset<N>(kx), g.d, g.cx);
 #pragma unroll
   for (int ky = 0; ky < N; ++ky) {
-    const float y = fmaf(g.uy + sub_offset<N>(ky), g.d, g.cy);
+    const RowTerms r = row_terms(c, fmaf(g.uy + sub_offset<N>(ky), g.d, g.cy));
 #pragma unroll
     for (int kx = 0; kx < N; ++kx) {
-      const float x = fmaf(g.ux + sub_offset<N>(kx), g.d, g.cx);
-      acc += surface_brightness<MODE>(c, x, y, cusp);
+      float h, s;
+      subsample_light<RM>(c, r, xs[kx], h, s, cusp);
+      sh += h;
+      ss += s;
     }
   }
-  return acc;
+  return fmaf(c.hI, sh, c.sI * ss);
 }
 
-template <int MODE>
+template <int RM>
 __device__ __forceinline__ float pixel_sum_rt(const PointConst& c, int N, const PixelGeom& g, bool& cusp) {
-  float acc = 0.0f;
+  float sh = 0.0f, ss = 0.0f;
   for (int ky = 0; ky < N; ++ky) {
-    const float y = fmaf(g.uy + sub_offset_rt(ky, N), g.d, g.cy);
+    const RowTerms r = row_terms(c, fmaf(g.uy + sub_offset_rt(ky, N), g.d, g.cy));
     for (int kx = 0; kx < N; ++kx) {
-      const float x = fmaf(g.ux + sub_offset_rt(kx, N), g.d, g.cx);
-      acc += surface_brightness<MODE>(c, x, y, cusp);
+      float h, s;
+      subsample_light<RM>(c, r, fmaf(g.ux + sub_offset_rt(kx, N), g.d, g.cx), h, s, cusp);
+      sh += h;
+      ss += s;
     }
   }
-  return acc;
+  return fmaf(c.hI, sh, c.sI * ss);
+}
+
+// (R/R_e)^2 of the source seen by the float32 render at subsample (x, y).
+__device__ __forceinline__ float render_source_R2(const PointConst& c, float x, float y) {
+  const RowTerms r = row_terms(c, y);
+  float X, Y;
+  switch (c.rmode) {
+    case 0: source_frame<0>(c, r, x, X, Y); break;
+    case 1: source_frame<1>(c, r, x, X, Y); break;
+    case 2: source_frame<2>(c, r, x, X, Y); break;
+    default: source_frame<3>(c, r, x, X, Y); break;
+  }
+  return fmaf(X, X, Y * Y);
 }
 
 // Correction for one flagged pixel: for every subsample in the cusp zone, the
-// source light at the float64 re-traced offset minus its float32 value.
-template <int MODE>
+// source light at the float64 re-traced offset minus the render's float32 value.
 __device__ __forceinline__ float cusp_correction(const PointConst& c, const PointConst64& c64, int N,
                                                  const PixelGeom& g) {
   float acc = 0.0f;
@@ -189,16 +241,16 @@ __device__ __forceinline__ float cusp_correction(const PointConst& c, const Poin
     const float y = fmaf(g.uy + sub_offset_rt(ky, N), g.d, g.cy);
     for (int kx = 0; kx < N; ++kx) {
       const float x = fmaf(g.ux + sub_offset_rt(kx, N), g.d, g.cx);
-      const float sR2 = source_r2<MODE>(c, x, y);
+      const float sR2 = render_source_R2(c, x, y);
       if (sR2 < c.cusp_r2) {
         float dx, dy;
         source_offset_f64(c64, g, kx, ky, N, dx, dy);
-        const float exact = sersic_from_r2(sersic_r2(dx, dy, c.sc, c.ss, c.sqa, c.sqb), c.se, c.sB, c.sI);
-        acc += exact - sersic_from_r2(sR2, c.se, c.sB, c.sI);
+        const float exact = sersic_shape(source_R2(c, dx, dy), c.se, c.sB);
+        acc += exact - sersic_shape(sR2, c.se, c.sB);
       }
     }
   }
-  return acc;
+  return c.sI * acc;
 }
 
 }  // namespace lensed

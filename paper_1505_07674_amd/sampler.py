@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import math
 import pickle
+import time
 from dataclasses import dataclass, field
 from typing import Callable, List, Optional
 
@@ -39,7 +40,16 @@ def _logaddexp(a, b):
 
 
 class Ellipsoid:
-    """Bounding ellipsoid of a point set, enlarged by a volume factor."""
+    """Bounding ellipsoid of a point set, enlarged by a volume factor.
+
+    ``sample_in_cube`` draws uniformly from the part of the ellipsoid inside the
+    unit cube by whichever of two rejection schemes accepts more often: draws in
+    the ellipsoid kept when inside the cube, or draws in the ellipsoid's bounding
+    box (clipped to the cube) kept when inside the ellipsoid. Both give the same
+    distribution; in many dimensions an ellipsoid that still spans the cube has a
+    volume far larger than the cube, and one inside it a volume far smaller than
+    its box, so neither scheme alone is efficient through a whole run.
+    """
 
     def __init__(self, pts: np.ndarray, enlarge: float = 1.25):
         d = pts.shape[1]
@@ -50,14 +60,42 @@ class Ellipsoid:
         r2 = np.einsum("ij,jk,ik->i", delta, inv, delta).max()
         # scale so every point is inside, then enlarge the volume
         self.cov = cov * r2 * enlarge ** (2.0 / d)
+        self.inv = np.linalg.inv(self.cov)
         self.chol = np.linalg.cholesky(self.cov)
         self.d = d
+        half = np.sqrt(np.diag(self.cov))
+        self.lo = np.clip(self.center - half, 0.0, 1.0)
+        self.hi = np.clip(self.center + half, 0.0, 1.0)
+        self._scheme = None
 
     def sample(self, rng: np.random.Generator, n: int) -> np.ndarray:
         z = rng.standard_normal((n, self.d))
         z /= np.linalg.norm(z, axis=1, keepdims=True)
         r = rng.random(n) ** (1.0 / self.d)
         return self.center + (z * r[:, None]) @ self.chol.T
+
+    def contains(self, x: np.ndarray) -> np.ndarray:
+        dlt = x - self.center
+        return np.einsum("ij,jk,ik->i", dlt, self.inv, dlt) <= 1.0
+
+    def _from_ellipsoid(self, rng, n):
+        c = self.sample(rng, n)
+        return c[np.all((c > 0.0) & (c < 1.0), axis=1)]
+
+    def _from_box(self, rng, n):
+        c = self.lo + rng.random((n, self.d)) * (self.hi - self.lo)
+        return c[self.contains(c) & np.all(c > 0.0, axis=1)]
+
+    def sample_in_cube(self, rng: np.random.Generator, n: int) -> np.ndarray:
+        """Up to about n uniform draws from ellipsoid and cube (possibly fewer, never 0 twice in a row)."""
+        if self._scheme is None:
+            probe = 4096
+            pa = len(self._from_ellipsoid(rng, probe)) / probe
+            pb = len(self._from_box(rng, probe)) / probe
+            self._scheme = (self._from_ellipsoid, max(pa, 1e-6)) if pa >= pb else (self._from_box, max(pb, 1e-6))
+        fn, p = self._scheme
+        m = int(min(max(n / p, n), 1 << 20))
+        return fn(rng, m)
 
 
 @dataclass
@@ -80,6 +118,8 @@ class NSResult:
     n_accepted: int                 # replacements accepted
     n_iter: int
     n_screened_out: int = 0
+    n_audit: int = 0                # screened-out draws evaluated exactly to check the screen
+    n_false_reject: int = 0         # of those, how many had log L above the threshold
     history: List[tuple] = field(default_factory=list)   # (n_exact, n_accepted) per iteration
     evaluated_u: Optional[np.ndarray] = None             # every exactly evaluated point
     evaluated_logl: Optional[np.ndarray] = None
@@ -98,7 +138,7 @@ class NSResult:
 class NestedSampler:
     def __init__(self, loglike: LogLikeFn, ndim: int, n_live: int = 400, k_replace: int = 40,
                  enlarge: float = 1.25, dlogz: float = 0.5, seed: int = 0, max_iter: int = 100000,
-                 candidates_per_call: int = 256, record: bool = False):
+                 candidates_per_call: int = 256, record: bool = False, audit: float = 0.0, audit_seed: int = 0):
         if not (1 <= k_replace < n_live):
             raise ValueError("need 1 <= k_replace < n_live")
         self.loglike = loglike
@@ -111,6 +151,10 @@ class NestedSampler:
         self.max_iter = max_iter
         self.cand = candidates_per_call
         self.record = record
+        # audit: this fraction of screened-out draws is also evaluated exactly (not
+        # accepted, not counted in n_exact) to measure false rejections
+        self.audit = audit
+        self.audit_rng = np.random.default_rng(audit_seed)
         self.state = None
 
     # -- checkpointing -------------------------------------------------------
@@ -130,7 +174,7 @@ class NestedSampler:
             "live_u": u, "live_logl": logl, "dead_u": [], "dead_logl": [], "dead_logw": [],
             "logx": 0.0, "logz": -np.inf, "h": 0.0, "n_exact": self.n_live, "n_accepted": 0, "it": 0,
             "n_screened": 0, "history": [], "eval_u": [u] if self.record else [], "eval_l": [logl] if self.record else [],
-            "rate": 0.5, "skips": 0,
+            "rate": 0.5, "skips": 0, "audit_u": [], "n_audit": 0, "n_false_reject": 0,
         }
 
     def _draw(self, ell: Ellipsoid, m: int, lmin: float, screen: Optional[Screen]) -> np.ndarray:
@@ -138,8 +182,7 @@ class NestedSampler:
         st = self.state
         pool, have = [], 0
         while have < m:
-            c = ell.sample(self.rng, max(2 * m, 64))
-            c = c[np.all((c > 0.0) & (c < 1.0), axis=1)]
+            c = ell.sample_in_cube(self.rng, max(2 * m, 64))
             if len(c) == 0:
                 continue
             if screen is not None and st["skips"] < screen.max_skips:
@@ -147,7 +190,12 @@ class NestedSampler:
                 # draws after the last kept one are not yet looked at: count discards up to it
                 last = np.nonzero(keep)[0]
                 looked = (last[-1] + 1) if len(last) else len(c)
-                st["n_screened"] += int((~keep[:looked]).sum())
+                dropped = np.nonzero(~keep[:looked])[0]
+                st["n_screened"] += len(dropped)
+                if self.audit > 0 and len(dropped):
+                    pick = dropped[self.audit_rng.random(len(dropped)) < self.audit]
+                    if len(pick):
+                        st["audit_u"].append(c[pick])
                 st["skips"] = 0 if len(last) else st["skips"] + len(c)
                 c = c[keep]
             else:
@@ -166,6 +214,12 @@ class NestedSampler:
             m = min(self.cand * 16, int(math.ceil(1.1 * need / max(st["rate"], 1e-3))) + 1)
             c = self._draw(ell, m, lmin, screen)
             logl = np.asarray(self.loglike(c), dtype=np.float64)
+            if st["audit_u"]:
+                au = np.concatenate(st["audit_u"])
+                st["audit_u"] = []
+                al = np.asarray(self.loglike(au), dtype=np.float64)
+                st["n_audit"] += len(au)
+                st["n_false_reject"] += int(np.count_nonzero(al > lmin))
             st["n_exact"] += len(c)
             if self.record:
                 st["eval_u"].append(c)
@@ -180,15 +234,18 @@ class NestedSampler:
         return np.array(new_u), np.array(new_l)
 
     def run(self, screen: Optional[Screen] = None, max_iter: Optional[int] = None,
-            log: Optional[Callable[[str], None]] = None, log_every: int = 50) -> NSResult:
+            log: Optional[Callable[[str], None]] = None, log_every: int = 50,
+            log_seconds: float = 20.0) -> NSResult:
         """Iterate until the stopping rule (or max_iter more iterations). ``log``
-        receives a progress line every ``log_every`` iterations: iteration, L_min,
-        log Z, exact evaluations, acceptance rate and screened-out draws."""
+        receives a progress line every ``log_every`` iterations or ``log_seconds``
+        seconds: iteration, L_min, log Z, exact evaluations, acceptance rate and
+        screened-out draws."""
         if self.state is None:
             self._init_state()
         st = self.state
         n = self.n_live
         stop_at = st["it"] + (max_iter if max_iter is not None else self.max_iter)
+        last_log = time.monotonic()
         while st["it"] < stop_at:
             order = np.argsort(st["live_logl"])
             worst = order[:self.k]
@@ -213,7 +270,8 @@ class NestedSampler:
             st["live_logl"][worst] = new_l
             st["it"] += 1
             st["history"].append((st["n_exact"], st["n_accepted"]))
-            if log is not None and st["it"] % log_every == 0:
+            if log is not None and (st["it"] % log_every == 0 or time.monotonic() - last_log > log_seconds):
+                last_log = time.monotonic()
                 log(f"it {st['it']} lmin {lmin:.6g} logz {st['logz']:.6g} exact {st['n_exact']} "
                     f"accepted {st['n_accepted']} rate {st['rate']:.3g} screened {st['n_screened']}")
             # stop when the live points can add at most dlogz to log Z:
@@ -238,7 +296,8 @@ class NestedSampler:
         h = max(st["h"], 0.0)
         res = NSResult(logz=logz, logz_err=math.sqrt(h / n), samples=samples, logl=logl, weights=w,
                        n_exact=st["n_exact"], n_accepted=st["n_accepted"], n_iter=st["it"],
-                       n_screened_out=st["n_screened"], history=list(st["history"]))
+                       n_screened_out=st["n_screened"], history=list(st["history"]),
+                       n_audit=st["n_audit"], n_false_reject=st["n_false_reject"])
         if self.record and st["eval_u"]:
             res.evaluated_u = np.concatenate(st["eval_u"])
             res.evaluated_logl = np.concatenate(st["eval_l"])

@@ -170,8 +170,8 @@ def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, n_liv
     fit = sur.fit(ra.evaluated_u, ra.evaluated_logl, epochs=train_epochs, batch=train_batch)
     torch.cuda.synchronize(device)
     fit["wall_s"] = time.perf_counter() - t0
-    log(f"surrogate trained on {fit['n_train']} pairs in {fit['wall_s']:.1f} s, held-out rmse(log -logL) "
-        f"{fit['rmse_logy']:.4f}")
+    log(f"surrogate trained on {fit['n_train']} pairs in {fit['wall_s']:.1f} s, held-out rmse(y) "
+        f"{fit['rmse_y']:.4f}")
     screen = SurrogateScreen(sur, sigmas=sigmas)
     log(f"screened run, seed {seeds[2]}")
     rc, wc = run(seeds[2], screen=screen, fn=_Observed(ll, screen))

@@ -3,8 +3,11 @@
 A multilayer perceptron 17 -> 256 -> 256 -> 256 -> 1 (SiLU), run and trained by
 the library's bfloat16-MFMA kernels, is fitted to (theta, log L) pairs that the
 exact likelihood produced during a nested-sampling run. It predicts
-y = log(-log L) (log L < 0 here: it is -chi^2/2), which spreads the targets from
-the prior (|log L| ~ 1e8) to the posterior (|log L| ~ 1e4) evenly. The screen
+y = log(1 + L_ref - log L), the logarithm of the deficit from the best log L of
+the training pairs (L_ref): the targets span the prior (deficit ~ 1e8) to the
+posterior (deficit ~ 1-100) evenly, and a fixed error in y is a fixed
+*relative* error of the deficit, so the network resolves a few nats near the
+posterior where the screen needs them. The screen
 discards a candidate when the predicted log L is below the current threshold by
 more than a margin: three times the held-out root-mean-square error, in log L
 units, of the held-out pairs whose log L is nearest the threshold. Every point
@@ -46,6 +49,7 @@ class Surrogate:
         self.free = None if free is None else np.asarray(free)
         self.params = torch.from_numpy(init_params(seed)).to(device)
         self.norm = None
+        self.l_ref = 0.0
         self.margin_table = None      # (sorted held-out log L, running RMSE) for the margin
         self.history = []
 
@@ -61,9 +65,10 @@ class Surrogate:
     def fit(self, u: np.ndarray, logl: np.ndarray, epochs: int = 60, batch: int = 1024, lr: float = 2e-3,
             holdout: float = 0.1, seed: int = 0) -> dict:
         logl = np.asarray(logl, np.float64)
-        ok = np.isfinite(logl) & (logl < 0)
+        ok = np.isfinite(logl)
         u, logl = np.asarray(u)[ok], logl[ok]
-        y = np.log(-logl)
+        self.l_ref = float(logl.max())
+        y = np.log1p(self.l_ref - logl)
         rng = np.random.default_rng(seed)
         perm = rng.permutation(len(y))
         n_hold = max(int(holdout * len(y)), 1)
@@ -97,15 +102,16 @@ class Surrogate:
         res = pred - logl[hold]
         order = np.argsort(logl[hold])
         self.margin_table = (logl[hold][order], res[order])
-        rmse_y = float(np.sqrt(np.mean((np.log(-np.minimum(pred, -1e-30)) - y[hold]) ** 2)))
-        return {"n_train": len(train), "n_holdout": n_hold, "final_loss": self.history[-1][1], "rmse_logy": rmse_y}
+        rmse_y = float(np.sqrt(np.mean((np.log1p(np.maximum(self.l_ref - pred, -0.999)) - y[hold]) ** 2)))
+        return {"n_train": len(train), "n_holdout": n_hold, "final_loss": self.history[-1][1], "rmse_y": rmse_y,
+                "l_ref": self.l_ref}
 
     def predict(self, u: np.ndarray) -> np.ndarray:
         """Predicted log L for unit-cube points."""
         if len(u) == 0:
             return np.zeros(0)
         y = binding.mlp_forward(self.params, self.norm, self._x(u)).double().cpu().numpy()
-        return -np.exp(y)
+        return self.l_ref - np.expm1(y)
 
     def margin(self, lmin: float, k: int = 200, sigmas: float = 3.0, floor: float = 1.0) -> float:
         """sigmas x RMSE of the held-out residuals whose log L is nearest lmin."""

@@ -79,4 +79,24 @@ def test_training_reduces_the_loss():
         if first is None:
             first = float(loss.cpu())
     final = float(lensed.mlp_grad(p, dev(norm), X, Y)[0].cpu())
-    assert final < 0.05 * first, (first, final)
+    assert final < 0.15 * first, (first, final)
+
+
+def test_training_tracks_the_reference_optimiser():
+    """40 Adam steps on the GPU and in the FP64 reference (same mini-batches, same
+    bfloat16 rounding points) reach the same full-batch loss within 10 %."""
+    theta, norm, x, y = problem(1024)
+    p, m, v = dev(theta), torch.zeros(ref.NPARAM, device=DEV), torch.zeros(ref.NPARAM, device=DEV)
+    X, Y = dev(x), dev(y)
+    rp, rm, rv = theta.astype(np.float64), np.zeros(ref.NPARAM), np.zeros(ref.NPARAM)
+    for step in range(1, 41):
+        i = (step - 1) % 4
+        sl = slice(i * 256, (i + 1) * 256)
+        lensed.mlp_train_step(p, m, v, step, dev(norm), X[sl], Y[sl], 2e-3)
+        _, g = ref.loss_and_grad(rp, norm, x[sl], y[sl], emulate_bf16=True)
+        rp, rm, rv = ref.adam_step(rp, g, rm, rv, step, 2e-3)
+    l_gpu = ref.loss_and_grad(p.cpu().numpy().astype(np.float64), norm, x, y, emulate_bf16=True)[0]
+    l_ref = ref.loss_and_grad(rp, norm, x, y, emulate_bf16=True)[0]
+    l0 = ref.loss_and_grad(theta.astype(np.float64), norm, x, y, emulate_bf16=True)[0]
+    assert l_ref < 0.5 * l0, (l0, l_ref)
+    assert abs(l_gpu - l_ref) <= 0.1 * l_ref, (l0, l_gpu, l_ref)

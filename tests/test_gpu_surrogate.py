@@ -46,7 +46,7 @@ def test_surrogate_fits_loglike_pairs():
     say("fitting 20000 prior pairs")
     fit = sur.fit(u, y, epochs=20, batch=512)
     assert fit["final_loss"] < 0.05, fit
-    assert fit["rmse_logy"] < 0.2, fit
+    assert fit["rmse_y"] < 0.2, fit
 
 
 def test_screen_cuts_exact_renders_and_keeps_the_posterior():
