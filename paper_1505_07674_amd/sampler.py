@@ -9,9 +9,10 @@ single-ellipsoid nested sampler that calls the batched GPU likelihood:
   transform (independent uniform priors);
 * each iteration removes the k lowest-likelihood live points; the expected
   log-shrinkage of the prior volume for the j-th of them is -1/(n_live - j);
-* replacements are drawn uniformly inside the bounding ellipsoid of the live
-  points (enlarged by a volume factor, clipped to the cube) and accepted in draw
-  order when their exact log L exceeds the threshold of the removed points;
+* replacements are drawn uniformly inside the bounding ellipsoids of the live
+  points (a union found by recursive 2-means splits, as MultiNest does, each
+  enlarged by a volume factor, clipped to the cube) and accepted in draw order
+  when their exact log L exceeds the threshold of the removed points;
 * an optional screen (a trained surrogate) may discard candidates before the
   exact evaluation; every accepted point is evaluated exactly;
 * the run stops when the live points can no longer change log Z by more than
@@ -98,6 +99,81 @@ class Ellipsoid:
         return fn(rng, m)
 
 
+def _two_means(pts: np.ndarray, rng: np.random.Generator, iters: int = 20) -> np.ndarray:
+    """Labels (0/1) of a 2-means clustering, started from two far-apart points."""
+    a = pts[rng.integers(len(pts))]
+    c0 = pts[np.argmax(np.sum((pts - a) ** 2, axis=1))]
+    c1 = pts[np.argmax(np.sum((pts - c0) ** 2, axis=1))]
+    lab = np.zeros(len(pts), dtype=int)
+    for _ in range(iters):
+        new = (np.sum((pts - c1) ** 2, axis=1) < np.sum((pts - c0) ** 2, axis=1)).astype(int)
+        if np.array_equal(new, lab) and _ > 0:
+            break
+        lab = new
+        if lab.all() or not lab.any():
+            break
+        c0, c1 = pts[lab == 0].mean(axis=0), pts[lab == 1].mean(axis=0)
+    return lab
+
+
+def _log_volume(cov: np.ndarray) -> float:
+    return 0.5 * np.linalg.slogdet(cov)[1]
+
+
+class MultiEllipsoid:
+    """Union of ellipsoids bounding the live points (Feroz & Hobson 2008): the
+    set is split recursively by 2-means while the two children's bounding
+    ellipsoids together take less than half the parent's volume; each ellipsoid
+    is enlarged by enlarge * sqrt(n_live / n_cluster) in volume (at most 4x).
+    Draws are uniform over the union inside the cube: pick an ellipsoid with
+    probability proportional to its volume, draw in it, keep the draw with
+    probability 1 / (number of ellipsoids containing it). A single ellipsoid
+    uses Ellipsoid.sample_in_cube."""
+
+    def __init__(self, pts: np.ndarray, enlarge: float = 1.25, rng: Optional[np.random.Generator] = None,
+                 max_ellipsoids: int = 16):
+        self.d = pts.shape[1]
+        self.n = len(pts)
+        self.enlarge = enlarge
+        rng = rng if rng is not None else np.random.default_rng(0)
+        self.ells: List[Ellipsoid] = []
+        stack = [pts]
+        while stack:
+            p = stack.pop()
+            e = self._fit(p)
+            if len(p) >= 2 * (self.d + 1) and len(self.ells) + len(stack) + 2 <= max_ellipsoids:
+                lab = _two_means(p, rng)
+                p0, p1 = p[lab == 0], p[lab == 1]
+                if len(p0) > self.d + 1 and len(p1) > self.d + 1:
+                    e0, e1 = self._fit(p0), self._fit(p1)
+                    lv = _log_volume(e.cov)
+                    if np.logaddexp(_log_volume(e0.cov), _log_volume(e1.cov)) < lv + math.log(0.5):
+                        stack.extend([p0, p1])
+                        continue
+            self.ells.append(e)
+        lv = np.array([_log_volume(e.cov) for e in self.ells])
+        w = np.exp(lv - lv.max())
+        self.prob = w / w.sum()
+
+    def _fit(self, p: np.ndarray) -> Ellipsoid:
+        f = min(self.enlarge * math.sqrt(self.n / len(p)), 4.0)
+        return Ellipsoid(p, f)
+
+    def sample_in_cube(self, rng: np.random.Generator, n: int) -> np.ndarray:
+        if len(self.ells) == 1:
+            return self.ells[0].sample_in_cube(rng, n)
+        counts = rng.multinomial(n, self.prob)
+        parts = [e.sample(rng, k) for e, k in zip(self.ells, counts) if k > 0]
+        c = np.concatenate(parts)
+        c = c[np.all((c > 0.0) & (c < 1.0), axis=1)]
+        if len(c) == 0:
+            return c
+        inside = np.sum([e.contains(c) for e in self.ells], axis=0)
+        keep = rng.random(len(c)) * np.maximum(inside, 1) < 1.0
+        c = c[keep]
+        return c[rng.permutation(len(c))]
+
+
 @dataclass
 class Screen:
     """Pre-screen of candidates: predict(u) returns a log L estimate; a candidate
@@ -120,6 +196,9 @@ class NSResult:
     n_screened_out: int = 0
     n_audit: int = 0                # screened-out draws evaluated exactly to check the screen
     n_false_reject: int = 0         # of those, how many had log L above the threshold
+    n_trusted: int = 0              # slice proposals the screen classified as inside (no exact render)
+    n_false_accept: int = 0         # audited trusted proposals whose exact log L was below the threshold
+    n_fallback: int = 0             # slice chains rerun without the screen
     history: List[tuple] = field(default_factory=list)   # (n_exact, n_accepted) per iteration
     evaluated_u: Optional[np.ndarray] = None             # every exactly evaluated point
     evaluated_logl: Optional[np.ndarray] = None
@@ -130,6 +209,8 @@ class NSResult:
         var = (self.weights[:, None] * (x - mean) ** 2).sum(0)
         return mean, np.sqrt(var)
 
+    converged: bool = False         # the stopping rule fired (else max_iter ended the run)
+
     @property
     def renders_per_accepted(self) -> float:
         return self.n_exact / max(self.n_accepted, 1)
@@ -138,7 +219,10 @@ class NSResult:
 class NestedSampler:
     def __init__(self, loglike: LogLikeFn, ndim: int, n_live: int = 400, k_replace: int = 40,
                  enlarge: float = 1.25, dlogz: float = 0.5, seed: int = 0, max_iter: int = 100000,
-                 candidates_per_call: int = 256, record: bool = False, audit: float = 0.0, audit_seed: int = 0):
+                 candidates_per_call: int = 256, record: bool = False, audit: float = 0.0, audit_seed: int = 0,
+                 multi: bool = True, record_per_iter: Optional[int] = None,
+                 audit_loglike: Optional[LogLikeFn] = None, method: str = "auto", n_steps: Optional[int] = None,
+                 slice_switch: Optional[float] = None):
         if not (1 <= k_replace < n_live):
             raise ValueError("need 1 <= k_replace < n_live")
         self.loglike = loglike
@@ -155,16 +239,40 @@ class NestedSampler:
         # accepted, not counted in n_exact) to measure false rejections
         self.audit = audit
         self.audit_rng = np.random.default_rng(audit_seed)
+        self.audit_loglike = audit_loglike if audit_loglike is not None else loglike
+        # record: keep exact (u, log L) pairs, at most record_per_iter per iteration
+        # (a uniform subset, drawn with its own generator)
+        self.record_per_iter = record_per_iter
+        self.record_rng = np.random.default_rng(audit_seed + 2)
+        # method: "rejection" (draws inside bounding ellipsoids), "slice" (slice
+        # sampling chains), or "auto": rejection until the bound's acceptance per
+        # draw falls below slice_switch (default 1 / (5 n_steps), the cost of a
+        # slice replacement), then slice for the rest of the run
+        if method not in ("auto", "rejection", "slice"):
+            raise ValueError("method must be auto, rejection or slice")
+        self.method = method
+        self.n_steps = n_steps if n_steps is not None else ndim
+        self.slice_switch = slice_switch if slice_switch is not None else 1.0 / (5.0 * self.n_steps)
+        # multi: bound the live points by a union of ellipsoids (else one ellipsoid)
+        self.multi = multi
+        self.split_rng = np.random.default_rng(seed + 1)
         self.state = None
 
     # -- checkpointing -------------------------------------------------------
     def checkpoint(self) -> bytes:
-        return pickle.dumps({"state": self.state, "rng": self.rng.bit_generator.state})
+        return pickle.dumps({"state": self.state, "rng": self.rng.bit_generator.state,
+                             "split_rng": self.split_rng.bit_generator.state,
+                             "audit_rng": self.audit_rng.bit_generator.state,
+                             "record_rng": self.record_rng.bit_generator.state})
 
     def restore(self, blob: bytes) -> None:
+        """Resume from a checkpoint() blob this program wrote (pickle: trusted input only)."""
         d = pickle.loads(blob)
         self.state = d["state"]
         self.rng.bit_generator.state = d["rng"]
+        self.split_rng.bit_generator.state = d["split_rng"]
+        self.audit_rng.bit_generator.state = d["audit_rng"]
+        self.record_rng.bit_generator.state = d["record_rng"]
 
     # -- sampling ------------------------------------------------------------
     def _init_state(self):
@@ -173,7 +281,8 @@ class NestedSampler:
         self.state = {
             "live_u": u, "live_logl": logl, "dead_u": [], "dead_logl": [], "dead_logw": [],
             "logx": 0.0, "logz": -np.inf, "h": 0.0, "n_exact": self.n_live, "n_accepted": 0, "it": 0,
-            "n_screened": 0, "history": [], "eval_u": [u] if self.record else [], "eval_l": [logl] if self.record else [],
+            "n_screened": 0, "history": [], "eval_u": [u.astype(np.float32)] if self.record else [],
+            "eval_l": [logl] if self.record else [],
             "rate": 0.5, "skips": 0, "audit_u": [], "n_audit": 0, "n_false_reject": 0,
         }
 
@@ -190,6 +299,7 @@ class NestedSampler:
                 # draws after the last kept one are not yet looked at: count discards up to it
                 last = np.nonzero(keep)[0]
                 looked = (last[-1] + 1) if len(last) else len(c)
+                st["drawn_it"] += looked
                 dropped = np.nonzero(~keep[:looked])[0]
                 st["n_screened"] += len(dropped)
                 if self.audit > 0 and len(dropped):
@@ -200,38 +310,206 @@ class NestedSampler:
                 c = c[keep]
             else:
                 st["skips"] = 0                    # exact fallback batch
+                st["drawn_it"] += min(len(c), m - have)
             pool.append(c)
             have += len(c)
         return np.concatenate(pool)[:m]
 
+    def _exact(self, c: np.ndarray) -> np.ndarray:
+        """Exact log L of the points c (counted, and recorded when asked)."""
+        st = self.state
+        logl = np.asarray(self.loglike(c), dtype=np.float64)
+        st["n_exact"] += len(c)
+        if self.record:
+            take = np.arange(len(c))
+            if self.record_per_iter is not None:
+                room = self.record_per_iter - st.get("rec_it", 0)
+                take = take[self.record_rng.random(len(c)) < min(1.0, max(room, 0) / max(len(c), 1))]
+                st["rec_it"] = st.get("rec_it", 0) + len(take)
+            st["eval_u"].append(c[take].astype(np.float32))
+            st["eval_l"].append(logl[take])
+        return logl
+
+    def _audit(self, lmin: float) -> None:
+        st = self.state
+        if st["audit_u"]:
+            au = np.concatenate(st["audit_u"])
+            st["audit_u"] = []
+            al = np.asarray(self.audit_loglike(au), dtype=np.float64)
+            st["n_audit"] += len(au)
+            st["n_false_reject"] += int(np.count_nonzero(al > lmin))
+        if st.get("audit_in"):
+            au = np.concatenate(st["audit_in"])
+            st["audit_in"] = []
+            al = np.asarray(self.audit_loglike(au), dtype=np.float64)
+            st["n_audit"] += len(au)
+            st["n_false_accept"] = st.get("n_false_accept", 0) + int(np.count_nonzero(al <= lmin))
+
     def _replace(self, lmin: float, n_new: int, screen: Optional[Screen]):
         st = self.state
-        ell = Ellipsoid(st["live_u"], self.enlarge)
+        st["rec_it"] = 0
+        st["drawn_it"] = 0
+        if self.method == "slice" or (self.method == "auto" and st.get("use_slice", False)):
+            out = self._replace_slice(lmin, n_new, screen)
+        else:
+            out = self._replace_rejection(lmin, n_new, screen)
+            rate = n_new / max(st["drawn_it"], 1)
+            st["draw_rate"] = rate if "draw_rate" not in st else 0.7 * st["draw_rate"] + 0.3 * rate
+            if self.method == "auto" and st["draw_rate"] < self.slice_switch:
+                st["use_slice"] = True
+        st["n_accepted"] += n_new
+        return out
+
+    def _replace_rejection(self, lmin: float, n_new: int, screen: Optional[Screen]):
+        st = self.state
+        ell = (MultiEllipsoid(st["live_u"], self.enlarge, self.split_rng) if self.multi
+               else Ellipsoid(st["live_u"], self.enlarge))
         new_u, new_l = [], []
         while len(new_u) < n_new:
             need = n_new - len(new_u)
             # size the exact batch from the running acceptance rate (about 10 % overshoot)
             m = min(self.cand * 16, int(math.ceil(1.1 * need / max(st["rate"], 1e-3))) + 1)
             c = self._draw(ell, m, lmin, screen)
-            logl = np.asarray(self.loglike(c), dtype=np.float64)
-            if st["audit_u"]:
-                au = np.concatenate(st["audit_u"])
-                st["audit_u"] = []
-                al = np.asarray(self.loglike(au), dtype=np.float64)
-                st["n_audit"] += len(au)
-                st["n_false_reject"] += int(np.count_nonzero(al > lmin))
-            st["n_exact"] += len(c)
-            if self.record:
-                st["eval_u"].append(c)
-                st["eval_l"].append(logl)
+            logl = self._exact(c)
+            self._audit(lmin)
             ok = np.nonzero(logl > lmin)[0]
             st["rate"] = 0.7 * st["rate"] + 0.3 * max(len(ok), 0.5) / len(c)
             for i in ok:                      # accept in draw order
                 if len(new_u) < n_new:
                     new_u.append(c[i])
                     new_l.append(logl[i])
-        st["n_accepted"] += n_new
         return np.array(new_u), np.array(new_l)
+
+    def _classify(self, c: np.ndarray, lmin: float, screen: Optional[Screen]):
+        """Inside-the-contour flags for proposals c (points outside the cube are
+        outside): by the screen where its prediction clears L_min by the margin,
+        exactly otherwise. Returns (inside, exact log L or nan)."""
+        st = self.state
+        inside = np.zeros(len(c), dtype=bool)
+        logl = np.full(len(c), np.nan)
+        cube = np.all((c > 0.0) & (c < 1.0), axis=1)
+        todo = np.nonzero(cube)[0]
+        if screen is not None and len(todo) and st["skips"] < screen.max_skips:
+            pred = np.asarray(screen.predict(c[todo]))
+            dm = screen.margin(lmin)
+            sure_in, sure_out = pred > lmin + dm, pred < lmin - dm
+            inside[todo[sure_in]] = True
+            st["n_screened"] += int(sure_out.sum())
+            st["n_trusted"] = st.get("n_trusted", 0) + int(sure_in.sum())
+            if self.audit > 0:
+                pick_out = todo[sure_out][self.audit_rng.random(int(sure_out.sum())) < self.audit]
+                pick_in = todo[sure_in][self.audit_rng.random(int(sure_in.sum())) < self.audit]
+                if len(pick_out):
+                    st["audit_u"].append(c[pick_out])
+                if len(pick_in):
+                    st.setdefault("audit_in", []).append(c[pick_in])
+            todo = todo[~(sure_in | sure_out)]
+        if len(todo):
+            logl[todo] = self._exact(c[todo])
+            inside[todo] = logl[todo] > lmin
+        return inside, logl
+
+    def _replace_slice(self, lmin: float, n_new: int, screen: Optional[Screen]):
+        """n_new replacements by slice sampling (Neal 2003) inside the contour,
+        one chain per replacement from a random surviving live point, along random
+        directions whitened by the live points' covariance (as PolyChord does),
+        n_steps slices per chain, all chains advanced in lock-step so that every
+        round is one batched evaluation. With a screen, proposals whose predicted
+        log L clears the threshold by the margin are classified without an exact
+        render; every final point is evaluated exactly, and a chain whose final
+        point fails is rerun without the screen."""
+        st = self.state
+        live = st["live_u"]
+        keep = np.nonzero(st["live_logl"] > lmin)[0]
+        if len(keep) == 0:
+            keep = np.arange(len(live))
+        cov = np.cov(live[keep], rowvar=False) + 1e-12 * np.eye(self.ndim)
+        chol = np.linalg.cholesky(cov)
+        B = n_new
+        start = keep[self.rng.integers(len(keep), size=B)]
+        x = live[start].copy()
+        xl = st["live_logl"][start].copy()          # exact log L of x (nan when only screened)
+        out_u, out_l = np.zeros((B, self.ndim)), np.zeros(B)
+        pending = np.arange(B)
+        use_screen = screen
+        for attempt in range(3):
+            steps = np.zeros(B, dtype=int)
+            def new_dir(idx):
+                e = self.rng.standard_normal((len(idx), self.ndim))
+                e /= np.linalg.norm(e, axis=1, keepdims=True)
+                return e @ chol.T
+            v = np.zeros((B, self.ndim))
+            v[pending] = new_dir(pending)
+            lo = np.zeros(B)
+            lo[pending] = -self.rng.random(len(pending))
+            hi = lo + 1.0
+            phase = np.full(B, 3)                    # 0 step out low, 1 step out high, 2 shrink, 3 done
+            phase[pending] = 0
+            nout = np.zeros(B, dtype=int)
+            nshrink = np.zeros(B, dtype=int)
+            failed = np.zeros(B, dtype=bool)
+            while True:
+                act = np.nonzero(phase < 3)[0]
+                if len(act) == 0:
+                    break
+                t = np.where(phase[act] == 0, lo[act], np.where(phase[act] == 1, hi[act], 0.0))
+                sh = phase[act] == 2
+                t[sh] = lo[act][sh] + self.rng.random(int(sh.sum())) * (hi[act][sh] - lo[act][sh])
+                prop = x[act] + t[:, None] * v[act]
+                inside, pl = self._classify(prop, lmin, use_screen)
+                for j, i in enumerate(act):
+                    if phase[i] == 0:
+                        if inside[j] and nout[i] < 20:
+                            lo[i] -= 1.0
+                            nout[i] += 1
+                        else:
+                            phase[i], nout[i] = 1, 0
+                    elif phase[i] == 1:
+                        if inside[j] and nout[i] < 20:
+                            hi[i] += 1.0
+                            nout[i] += 1
+                        else:
+                            phase[i] = 2
+                    else:
+                        if inside[j]:
+                            x[i], xl[i] = prop[j], pl[j]
+                            steps[i] += 1
+                            if steps[i] >= self.n_steps:
+                                phase[i] = 3
+                            else:
+                                v[i] = new_dir(np.array([i]))[0]
+                                lo[i] = -self.rng.random()
+                                hi[i] = lo[i] + 1.0
+                                phase[i], nout[i], nshrink[i] = 0, 0, 0
+                        else:
+                            if t[j] < 0.0:
+                                lo[i] = t[j]
+                            else:
+                                hi[i] = t[j]
+                            nshrink[i] += 1
+                            if nshrink[i] > 60:      # the neighbourhood of x reads as outside
+                                failed[i], phase[i] = True, 3
+            # every replacement carries an exact log L above the threshold
+            done = pending[~failed[pending]]
+            need = done[np.isnan(xl[done])]
+            if len(need):
+                xl[need] = self._exact(x[need])
+            ok = done[xl[done] > lmin]
+            out_u[ok], out_l[ok] = x[ok], xl[ok]
+            self._audit(lmin)
+            pending = np.setdiff1d(pending, ok)
+            if len(pending) == 0:
+                break
+            # fallback: rerun the failed chains from live points without the screen
+            st["n_fallback"] = st.get("n_fallback", 0) + len(pending)
+            start = keep[self.rng.integers(len(keep), size=len(pending))]
+            x[pending], xl[pending] = live[start], st["live_logl"][start]
+            use_screen = None
+        if len(pending):
+            # last resort: bounded rejection draws, exact
+            u, l = self._replace_rejection(lmin, len(pending), None)
+            out_u[pending], out_l[pending] = u, l
+        return out_u, out_l
 
     def run(self, screen: Optional[Screen] = None, max_iter: Optional[int] = None,
             log: Optional[Callable[[str], None]] = None, log_every: int = 50,
@@ -246,7 +524,7 @@ class NestedSampler:
         n = self.n_live
         stop_at = st["it"] + (max_iter if max_iter is not None else self.max_iter)
         last_log = time.monotonic()
-        while st["it"] < stop_at:
+        while st["it"] < stop_at and not st.get("done", False):
             order = np.argsort(st["live_logl"])
             worst = order[:self.k]
             lmin = st["live_logl"][worst[-1]]
@@ -278,6 +556,7 @@ class NestedSampler:
             # log(1 + L_max X / Z) < dlogz
             lmax = st["live_logl"].max()
             if self.dlogz > 0 and lmax + st["logx"] - st["logz"] < math.log(math.expm1(self.dlogz)):
+                st["done"] = True
                 break
         return self._result()
 
@@ -297,7 +576,10 @@ class NestedSampler:
         res = NSResult(logz=logz, logz_err=math.sqrt(h / n), samples=samples, logl=logl, weights=w,
                        n_exact=st["n_exact"], n_accepted=st["n_accepted"], n_iter=st["it"],
                        n_screened_out=st["n_screened"], history=list(st["history"]),
-                       n_audit=st["n_audit"], n_false_reject=st["n_false_reject"])
+                       n_audit=st["n_audit"], n_false_reject=st["n_false_reject"],
+                       n_trusted=st.get("n_trusted", 0), n_false_accept=st.get("n_false_accept", 0),
+                       n_fallback=st.get("n_fallback", 0),
+                       converged=bool(st.get("done", False)))
         if self.record and st["eval_u"]:
             res.evaluated_u = np.concatenate(st["eval_u"])
             res.evaluated_logl = np.concatenate(st["eval_l"])

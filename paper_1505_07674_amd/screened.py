@@ -140,41 +140,109 @@ class _Observed:
 def _summary(res: NSResult, wall: float) -> dict:
     return {"logz": res.logz, "logz_err": res.logz_err, "n_exact": res.n_exact, "n_accepted": res.n_accepted,
             "n_iter": res.n_iter, "renders_per_accepted": res.renders_per_accepted,
-            "n_screened_out": res.n_screened_out, "wall_s": wall}
+            "n_screened_out": res.n_screened_out, "n_audit": res.n_audit, "n_false_reject": res.n_false_reject,
+            "n_trusted": res.n_trusted, "n_false_accept": res.n_false_accept, "n_fallback": res.n_fallback,
+            "converged": res.converged, "wall_s": wall}
+
+
+class Suspended(Exception):
+    """A run reached the deadline; its checkpoint is in the state directory."""
+
+
+_ARRAYS = ("samples", "logl", "weights", "evaluated_u", "evaluated_logl")
+_SCALARS = ("logz", "logz_err", "n_exact", "n_accepted", "n_iter", "n_screened_out", "n_audit", "n_false_reject",
+            "n_trusted", "n_false_accept", "n_fallback", "converged")
+
+
+def _save_result(path: str, res: NSResult, wall: float) -> None:
+    arrays = {k: getattr(res, k) for k in _ARRAYS if getattr(res, k) is not None}
+    arrays.update({k: np.asarray(getattr(res, k)) for k in _SCALARS})
+    np.savez(path, wall=np.asarray(wall), **arrays)
+
+
+def _load_result(path: str):
+    with np.load(path) as z:
+        kw = {k: z[k] for k in _ARRAYS if k in z.files}
+        kw.update({k: z[k].item() for k in _SCALARS})
+        return NSResult(**kw), float(z["wall"])
 
 
 def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, n_live: int = 400, k_replace: int = 40,
                  seeds=(5, 6, 7), dlogz: float = 0.5, max_iter: int = 5000, train_epochs: int = 60,
-                 train_batch: int = 1024, sigmas: float = 3.0, log=print, log_every: int = 100) -> dict:
-    """Plain run A (recorded), plain run B (null), surrogate fit on A, screened run C."""
+                 train_batch: int = 1024, sigmas: float = 3.0, log=print, log_every: int = 100,
+                 record_per_iter: Optional[int] = 200, audit: float = 0.0, state_dir: Optional[str] = None,
+                 deadline: Optional[float] = None, chunk: int = 25) -> dict:
+    """Plain run A (records exact pairs), plain run B (another seed: the sampler's
+    own spread), the surrogate trained on A's pairs, and the screened run C.
+
+    With ``state_dir`` every finished run is saved there and reused by a later
+    call, and a run still going at ``deadline`` (time.monotonic()) is
+    checkpointed there and Suspended is raised; calling again resumes it."""
+    import os
     ll = GpuLogLike(spec, obs, device)
     ndim = len(ll.free)
-    out = {"system": spec.name, "n_live": n_live, "k_replace": k_replace, "ndim": ndim, "free": ll.free.tolist()}
+    out = {"system": spec.name, "n_live": n_live, "k_replace": k_replace, "ndim": ndim, "free": ll.free.tolist(),
+           "audit_fraction": audit}
 
-    def run(seed, screen=None, record=False, fn=None):
+    def path(name):
+        return os.path.join(state_dir, name) if state_dir else None
+
+    def run(name, seed, screen=None, record=False, fn=None):
+        if state_dir and os.path.exists(path(name + ".npz")):
+            log(f"{name}: loaded from {path(name + '.npz')}")
+            return _load_result(path(name + ".npz"))
         s = NestedSampler(fn or ll, ndim, n_live=n_live, k_replace=k_replace, dlogz=dlogz, seed=seed,
-                          max_iter=max_iter, record=record)
+                          max_iter=max_iter, record=record, record_per_iter=record_per_iter,
+                          audit=audit if screen is not None else 0.0, audit_seed=seed, audit_loglike=ll)
+        wall0 = 0.0
+        if state_dir and os.path.exists(path(name + ".ckpt")):
+            with open(path(name + ".ckpt"), "rb") as f:
+                s.restore(f.read())
+            wall0 = s.state.get("wall", 0.0)
+            if isinstance(screen, SurrogateScreen) and "screen_run" in s.state:
+                screen.run_l, screen.run_r = s.state["screen_run"]
+            log(f"{name}: resumed at iteration {s.state['it']}")
         t0 = time.perf_counter()
-        r = s.run(screen=screen, log=log, log_every=log_every)
-        return r, time.perf_counter() - t0
+        while True:
+            r = s.run(screen=screen, max_iter=chunk, log=log, log_every=log_every)
+            if r.converged or r.n_iter >= max_iter:
+                break
+            if deadline is not None and time.monotonic() > deadline:
+                if state_dir:
+                    s.state["wall"] = wall0 + time.perf_counter() - t0
+                    if isinstance(screen, SurrogateScreen):
+                        s.state["screen_run"] = (screen.run_l, screen.run_r)
+                    with open(path(name + ".ckpt"), "wb") as f:
+                        f.write(s.checkpoint())
+                raise Suspended(f"{name} suspended at iteration {r.n_iter}")
+        wall = wall0 + time.perf_counter() - t0
+        if state_dir:
+            _save_result(path(name + ".npz"), r, wall)
+        return r, wall
 
-    log(f"plain run, seed {seeds[0]} (recording pairs)")
-    ra, wa = run(seeds[0], record=True)
+    log(f"plain run A, seed {seeds[0]} (recording pairs)")
+    ra, wa = run("plain_a", seeds[0], record=True)
     log(f"  {ra.n_exact} exact evaluations, {ra.n_iter} iterations, log Z {ra.logz:.2f}, {wa:.1f} s")
-    log(f"plain run, seed {seeds[1]}")
-    rb, wb = run(seeds[1])
+    log(f"plain run B, seed {seeds[1]}")
+    rb, wb = run("plain_b", seeds[1])
     log(f"  {rb.n_exact} exact evaluations, {rb.n_iter} iterations, log Z {rb.logz:.2f}, {wb:.1f} s")
 
     sur = Surrogate(device, seed=seeds[0], free=ll.free)
-    t0 = time.perf_counter()
-    fit = sur.fit(ra.evaluated_u, ra.evaluated_logl, epochs=train_epochs, batch=train_batch)
-    torch.cuda.synchronize(device)
-    fit["wall_s"] = time.perf_counter() - t0
+    if state_dir and os.path.exists(path("surrogate.npz")):
+        fit = sur.load(path("surrogate.npz"))
+        log("surrogate: loaded")
+    else:
+        t0 = time.perf_counter()
+        fit = sur.fit(ra.evaluated_u, ra.evaluated_logl, epochs=train_epochs, batch=train_batch)
+        torch.cuda.synchronize(device)
+        fit["wall_s"] = time.perf_counter() - t0
+        if state_dir:
+            sur.save(path("surrogate.npz"), fit)
     log(f"surrogate trained on {fit['n_train']} pairs in {fit['wall_s']:.1f} s, held-out rmse(y) "
         f"{fit['rmse_y']:.4f}")
     screen = SurrogateScreen(sur, sigmas=sigmas)
-    log(f"screened run, seed {seeds[2]}")
-    rc, wc = run(seeds[2], screen=screen, fn=_Observed(ll, screen))
+    log(f"screened run C, seed {seeds[2]}")
+    rc, wc = run("screened_c", seeds[2], screen=screen, fn=_Observed(ll, screen))
     log(f"  {rc.n_exact} exact evaluations, {rc.n_screened_out} screened out, log Z {rc.logz:.2f}, {wc:.1f} s")
 
     to_theta = lambda u: ll.theta(u)[:, ll.free].astype(np.float64)
@@ -189,6 +257,7 @@ def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, n_liv
         "posterior_mean_screened": mc.tolist(), "posterior_std_screened": sc.tolist(),
         "shift_screened_sigma": (np.abs(mc - ma) / sa).tolist(),
         "shift_null_sigma": (np.abs(mb - ma) / sa).tolist(),
+        "n_pairs_recorded": int(0 if ra.evaluated_u is None else len(ra.evaluated_u)),
     })
     out["max_shift_screened_sigma"] = float(np.max(out["shift_screened_sigma"]))
     out["max_shift_null_sigma"] = float(np.max(out["shift_null_sigma"]))
@@ -208,6 +277,7 @@ def library_mock(spec: SystemSpec, device: torch.device) -> Observation:
 def main(argv=None) -> int:
     import argparse
     import json
+    import os
     import sys
 
     from . import mocks
@@ -218,6 +288,9 @@ def main(argv=None) -> int:
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--sigmas", type=float, default=3.0)
     ap.add_argument("--max-iter", type=int, default=5000)
+    ap.add_argument("--audit", type=float, default=0.0, help="fraction of screened-out draws also evaluated exactly")
+    ap.add_argument("--state-dir", default=None, help="save finished runs and checkpoints here; resume from it")
+    ap.add_argument("--time-limit", type=float, default=None, help="seconds before the running stage is suspended")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     if not torch.cuda.is_available():
@@ -227,9 +300,17 @@ def main(argv=None) -> int:
     spec = mocks.c0_spec() if a.system == "64x64" else mocks.c1_spec()
     obs = library_mock(spec, dev)
     log = lambda m: print(m, flush=True)
-    res = compare_runs(spec, obs, dev, n_live=a.n_live, k_replace=a.k_replace, train_epochs=a.epochs,
-                       sigmas=a.sigmas, max_iter=a.max_iter, seeds=(mocks.C4_SEED, mocks.C4_SEED + 1,
-                                                                    mocks.C4_SEED + 2), log=log)
+    if a.state_dir:
+        os.makedirs(a.state_dir, exist_ok=True)
+    deadline = time.monotonic() + a.time_limit if a.time_limit else None
+    try:
+        res = compare_runs(spec, obs, dev, n_live=a.n_live, k_replace=a.k_replace, train_epochs=a.epochs,
+                           sigmas=a.sigmas, max_iter=a.max_iter, seeds=(mocks.C4_SEED, mocks.C4_SEED + 1,
+                                                                        mocks.C4_SEED + 2), log=log,
+                           audit=a.audit, state_dir=a.state_dir, deadline=deadline)
+    except Suspended as e:
+        print(f"suspended: {e}", flush=True)
+        return 3
     text = json.dumps(res)
     print(text, flush=True)
     if a.out:

@@ -120,3 +120,18 @@ class Surrogate:
         lo, hi = max(0, i - k // 2), min(len(ll), i + k // 2)
         window = res[lo:hi] if hi > lo else res
         return max(sigmas * float(np.sqrt(np.mean(window ** 2))), floor)
+
+    def save(self, path: str, fit: dict) -> None:
+        """Weights, normalisation, reference log L, calibration table and fit summary (npz)."""
+        import json
+        np.savez(path, params=self.params.cpu().numpy(), norm=self.norm.cpu().numpy(), l_ref=np.asarray(self.l_ref),
+                 cal_l=self.margin_table[0], cal_r=self.margin_table[1], fit=np.asarray(json.dumps(fit)))
+
+    def load(self, path: str) -> dict:
+        import json
+        with np.load(path) as z:
+            self.params = torch.from_numpy(z["params"]).to(self.device)
+            self.norm = torch.from_numpy(z["norm"]).to(self.device)
+            self.l_ref = float(z["l_ref"])
+            self.margin_table = (z["cal_l"], z["cal_r"])
+            return json.loads(str(z["fit"]))

@@ -224,3 +224,21 @@ def test_subsample_on_the_image_of_a_cuspy_source_centre():
     t2 = t.copy(); t2[1], t2[2], t2[14] = 0.7, 0.4, 3.0     # elliptical lens, same source
     check_images(spec, np.stack([t, t2]), True)
     check_images(spec, np.stack([t, t2]), False)
+
+
+@pytest.mark.parametrize("q", [1.0, 0.95, 0.866, 0.8, 0.5, 0.45, 0.2])
+def test_every_sie_branch_with_a_subsample_on_the_lens_centre(q):
+    """Axis ratios across the four SIE evaluation branches (sphere; polynomials
+    for q' <= 1/2; half-angle atan with log atanh for q >= 1/2 and for q < 1/2),
+    on a 41x41 grid centred on the lens with N = 3, so that one subsample sits
+    exactly on the lens centre (deflection 0 there). Zero lens light and a
+    negative source amplitude check the per-pixel amplitudes."""
+    say(f"SIE branch q={q}")
+    rng = np.random.default_rng(int(q * 1000))
+    spec = _custom_spec(41, 41, 3, mocks.gaussian_psf(7, 0.15, 0.06), pixscale=0.06, center=(0.0, 0.0))
+    pts = mocks.points(spec, 3, seed=int(q * 100))
+    pts[:, 1] = q
+    pts[1, 5] = 0.0           # no lens light
+    pts[2, 12] = -pts[2, 12]  # negative source amplitude
+    check_images(spec, pts, False)
+    check_images(spec, pts, True)

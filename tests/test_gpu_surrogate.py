@@ -1,11 +1,12 @@
-"""The learned screen end to end on the GPU: nested sampling on the 64x64 mock
-with and without the surrogate network, which is trained on the plain run's
-exact (theta, log L) pairs by the library's own kernels.
+"""The learned screen end to end on the GPU: nested sampling with and without
+the surrogate network, which is trained on the plain run's exact (theta, log L)
+pairs by the library's own kernels.
 
 What the network gains over the method without it: exact renders per accepted
-point drop by at least 2x at this small size (the 200x200 experiment is run by
-``python -m paper_1505_07674_amd.screened``), while the posterior means move
-by no more than the sampler's own seed-to-seed spread allows.
+point drop by at least 2x over the first iterations of a short run on the
+200x200 mock (the full runs with 400 live points and the posterior comparison
+are made by ``python -m paper_1505_07674_amd.screened``), and an exact audit of
+screened-out draws finds (almost) no draw the screen should have kept.
 """
 import numpy as np
 import pytest
@@ -49,16 +50,21 @@ def test_surrogate_fits_loglike_pairs():
     assert fit["rmse_y"] < 0.2, fit
 
 
-def test_screen_cuts_exact_renders_and_keeps_the_posterior():
-    spec, obs = observation("c0")
-    res = compare_runs(spec, obs, DEV, n_live=100, k_replace=10, seeds=(mocks.C4_SEED, mocks.C4_SEED + 1,
-                                                                        mocks.C4_SEED + 2),
-                       train_epochs=30, train_batch=512, log=say, log_every=100)
+def test_screen_cuts_exact_renders_without_false_rejections():
+    """The 200x200 SIE + shear + Sersic mock, 100 live points, the first 100
+    iterations: the plain run's exact pairs train the network, and the screened
+    run needs far fewer exact renders per accepted point. A fifth of the
+    screened-out draws are also evaluated exactly (an audit that does not change
+    the run): almost none of them would have been accepted."""
+    spec, obs = observation("c1")
+    res = compare_runs(spec, obs, DEV, n_live=100, k_replace=10, max_iter=100,
+                       seeds=(mocks.C4_SEED, mocks.C4_SEED + 1, mocks.C4_SEED + 2), train_epochs=150,
+                       train_batch=512, record_per_iter=None, audit=0.2, log=say, log_every=25)
+    sc = res["screened"]
     say(f"renders/accepted plain {res['plain']['renders_per_accepted']:.2f} "
-        f"screened {res['screened']['renders_per_accepted']:.2f}; max shift {res['max_shift_screened_sigma']:.3f} "
-        f"sigma (null {res['max_shift_null_sigma']:.3f})")
+        f"screened {sc['renders_per_accepted']:.2f} (x{res['renders_per_accepted_ratio']:.2f}); "
+        f"audit {sc['n_audit']} draws, {sc['n_false_reject']} false rejections, {sc['n_false_accept']} false "
+        f"acceptances; fit {res['fit']}; plain {res['plain']}; screened {sc}")
     assert res["renders_per_accepted_ratio"] >= 2.0, res
-    # every accepted point is exact, so only a biased screen could move the posterior
-    assert res["max_shift_screened_sigma"] <= max(0.5, 2.0 * res["max_shift_null_sigma"]), res
-    assert abs(res["screened"]["logz"] - res["plain"]["logz"]) <= 3 * np.hypot(res["plain"]["logz_err"],
-                                                                              res["screened"]["logz_err"]) + 0.5
+    assert sc["n_audit"] > 100
+    assert sc["n_false_reject"] + sc["n_false_accept"] <= max(2, 0.01 * sc["n_audit"]), sc
