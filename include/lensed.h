@@ -124,7 +124,11 @@ int lensed_loglike(lensed_ctx* ctx, const lensed_system* sys, const float* theta
  *   system_of_point  HOST int32 [n_points], values in [0, n_systems)
  *   logl             device float64 [n_points], written
  * The plan (work lists, scratch layout, captured graph) is cached on the context
- * keyed by the systems, the mapping and the theta/logl pointers. */
+ * keyed by the systems, the mapping and the theta/logl pointers. The first call
+ * for a new set of system shapes also autotunes the PSF tile: it times the PSF +
+ * chi^2 stage of the cost model's six best-ranked tile shapes on this launch
+ * (synchronising `stream`) and keeps the fastest for every later plan over the
+ * same shapes; LENSED_NO_AUTOTUNE=1 in the environment keeps the model's choice. */
 int lensed_loglike_batch(lensed_ctx* ctx, const lensed_system* systems, int n_systems,
                          const float* theta, const int32_t* system_of_point, int n_points,
                          double* logl, void* stream);

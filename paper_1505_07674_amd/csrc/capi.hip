@@ -25,6 +25,7 @@ struct lensed_ctx {
   char* arena = nullptr;            // workspace of the plain calls
   size_t arena_bytes = 0;
   bool use_graphs = true;
+  bool autotune = true;             // time the best-ranked tile shapes on the first batch of a shape set
   std::vector<std::unique_ptr<BatchPlan>> plans;   // most recently used last
   TileCache tiles;
   bool profiling = false;                          // per-stage hipEvents, no graphs
@@ -211,6 +212,8 @@ int lensed_create(lensed_ctx** out, int device) {
   }
   const char* g = std::getenv("LENSED_NO_GRAPHS");
   c->use_graphs = !(g && g[0] == '1');
+  const char* t = std::getenv("LENSED_NO_AUTOTUNE");
+  c->autotune = !(t && t[0] == '1');
   *out = c;
   return LENSED_OK;
 }
@@ -329,6 +332,30 @@ int lensed_loglike_batch(lensed_ctx* c, const lensed_system* systems, int n_syst
     if (c->plans.size() >= 8) {
       LENSED_HIP(c, hipDeviceSynchronize());
       c->plans.erase(c->plans.begin());
+    }
+    if (c->autotune && !c->tiles.has_measured(systems, n_systems)) {
+      // Autotuner: time the PSF + chi^2 stage of the model's best-ranked tile
+      // shapes on this very launch (stage by stage, second of two runs) and keep
+      // the fastest for every later plan over the same set of system shapes.
+      const std::vector<TileShape> cand = c->tiles.ranked(systems, n_systems, 6);
+      TileShape best = cand.empty() ? TileShape{32, 32} : cand[0];
+      float best_ms = 1e30f;
+      for (const TileShape& t : cand) {
+        BatchPlan trial;
+        std::string msg;
+        if (trial.build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg, nullptr, &t) !=
+            hipSuccess) {
+          (void)hipGetLastError();
+          continue;
+        }
+        float ms = 0.0f;
+        LENSED_HIP(c, trial.psf_ms((hipStream_t)stream, &ms));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = t;
+        }
+      }
+      c->tiles.set_measured(systems, n_systems, best);
     }
     std::unique_ptr<BatchPlan> np(new BatchPlan());
     std::string msg;

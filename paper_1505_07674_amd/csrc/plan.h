@@ -20,20 +20,26 @@ struct TileShape {
   int TW, TH;
 };
 
-// Chooses the TW x TH output tile of the PSF/chi^2 kernel for an image shape.
-// The model counts lane slots of the stencil (ragged tiles and partly idle
-// waves included) plus the LDS staging of the halo; a measured choice can
-// override it through set().
+// Chooses the TW x TH output tile of the PSF/chi^2 kernel for a launch. The
+// model counts lane slots of the stencil (ragged tiles and partly idle waves
+// included) plus the LDS staging of the halo and ranks the candidates; the
+// autotuner times the best-ranked few on the real launch and records the
+// fastest per set of system shapes, which then overrides the model.
 class TileCache {
  public:
   TileShape choose(const lensed_system& s);
   TileShape choose_common(const lensed_system* s, int n);
-  void set(int H, int W, int ph, int pw, TileShape t) { cache_[std::make_tuple(H, W, ph, pw)] = t; }
+  std::vector<TileShape> ranked(const lensed_system* s, int n, int k) const;
+  bool has_measured(const lensed_system* s, int n) const { return measured_.count(key(s, n)) != 0; }
+  void set_measured(const lensed_system* s, int n, TileShape t) { measured_[key(s, n)] = t; }
   static double model_cost(int H, int W, int ph, int pw, TileShape t, int sq);
   static std::vector<TileShape> candidates(int sq);
 
  private:
+  static std::string key(const lensed_system* s, int n);
+  static int launch_square(const lensed_system* s, int n);
   std::map<std::tuple<int, int, int, int>, TileShape> cache_;
+  std::map<std::string, TileShape> measured_;
 };
 
 int validate_system(lensed_ctx* c, const lensed_system* s, bool need_data, int index);
@@ -49,8 +55,12 @@ class BatchPlan {
   // grad == nullptr: log L only; otherwise also d log L / d theta (single system).
   bool matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map, int n_points,
                const double* logl, const float* grad = nullptr) const;
+  // force: use this tile shape instead of the cache's choice (autotuning)
   hipError_t build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
-                   int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad = nullptr);
+                   int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad = nullptr,
+                   const TileShape* force = nullptr);
+  // Runs the plan stage by stage twice on s and returns the second run's PSF + chi^2 milliseconds.
+  hipError_t psf_ms(hipStream_t s, float* ms) const;
   hipError_t capture(hipStream_t cap);
   // events, when given, are 5 events recorded around the 4 stages
   // (prologue, render, PSF + chi^2, finalize)

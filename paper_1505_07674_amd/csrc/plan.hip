@@ -37,9 +37,44 @@ double TileCache::model_cost(int H, int W, int ph, int pw, TileShape t, int sq) 
   return ntiles * (lanes * per_lane + staging + 2000.0);
 }
 
+std::string TileCache::key(const lensed_system* s, int n) {
+  std::vector<std::string> parts;
+  for (int i = 0; i < n; ++i)
+    parts.push_back(std::to_string(s[i].height) + "x" + std::to_string(s[i].width) + "p" +
+                    std::to_string(s[i].psf_h) + "x" + std::to_string(s[i].psf_w));
+  std::sort(parts.begin(), parts.end());
+  parts.erase(std::unique(parts.begin(), parts.end()), parts.end());
+  std::string k;
+  for (const auto& p : parts) k += p + ";";
+  return k;
+}
+
+int TileCache::launch_square(const lensed_system* s, int n) {
+  int sq = square_psf_code(s[0].psf_h, s[0].psf_w);
+  for (int i = 1; i < n; ++i)
+    if (square_psf_code(s[i].psf_h, s[i].psf_w) != sq) sq = -1;
+  return sq;
+}
+
+std::vector<TileShape> TileCache::ranked(const lensed_system* s, int n, int k) const {
+  const int sq = launch_square(s, n);
+  std::vector<std::pair<double, TileShape>> all;
+  for (const TileShape& t : candidates(sq)) {
+    double cst = 0.0;
+    for (int i = 0; i < n; ++i) cst += model_cost(s[i].height, s[i].width, s[i].psf_h, s[i].psf_w, t, sq);
+    all.push_back({cst, t});
+  }
+  std::stable_sort(all.begin(), all.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  std::vector<TileShape> out;
+  for (int i = 0; i < (int)all.size() && i < k; ++i) out.push_back(all[i].second);
+  return out;
+}
+
 TileShape TileCache::choose(const lensed_system& s) {
-  const auto key = std::make_tuple(s.height, s.width, s.psf_h, s.psf_w);
-  auto it = cache_.find(key);
+  auto m = measured_.find(key(&s, 1));
+  if (m != measured_.end()) return m->second;
+  const auto shape = std::make_tuple(s.height, s.width, s.psf_h, s.psf_w);
+  auto it = cache_.find(shape);
   if (it != cache_.end()) return it->second;
   TileShape best{32, 32};
   double bc = 1e300;
@@ -51,26 +86,16 @@ TileShape TileCache::choose(const lensed_system& s) {
       best = t;
     }
   }
-  cache_[key] = best;
+  cache_[shape] = best;
   return best;
 }
 
 TileShape TileCache::choose_common(const lensed_system* s, int n) {
   if (n == 1) return choose(s[0]);
-  TileShape best{32, 32};
-  double bc = 1e300;
-  int sq = square_psf_code(s[0].psf_h, s[0].psf_w);
-  for (int i = 1; i < n; ++i)
-    if (square_psf_code(s[i].psf_h, s[i].psf_w) != sq) sq = -1;
-  for (const TileShape& t : candidates(sq)) {
-    double cst = 0.0;
-    for (int i = 0; i < n; ++i) cst += model_cost(s[i].height, s[i].width, s[i].psf_h, s[i].psf_w, t, sq);
-    if (cst < bc) {
-      bc = cst;
-      best = t;
-    }
-  }
-  return best;
+  auto m = measured_.find(key(s, n));
+  if (m != measured_.end()) return m->second;
+  const std::vector<TileShape> r = ranked(s, n, 1);
+  return r.empty() ? TileShape{32, 32} : r[0];
 }
 
 namespace {
@@ -99,7 +124,8 @@ bool BatchPlan::matches(const lensed_system* systems, int n_systems, const float
 }
 
 hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
-                            int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad) {
+                            int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad,
+                            const TileShape* force) {
   systems_.assign(systems, systems + n_systems);
   map_.assign(map, map + n_points);
   theta_ = theta;
@@ -107,7 +133,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   grad_ = grad;
   n_points_ = n_points;
 
-  const TileShape ts = tiles.choose_common(systems, n_systems);
+  const TileShape ts = force ? *force : tiles.choose_common(systems, n_systems);
   TW_ = ts.TW;
   TH_ = ts.TH;
   std::vector<SysDesc> desc(n_systems);
@@ -280,6 +306,19 @@ hipError_t BatchPlan::capture(hipStream_t cap) {
   if (le != hipSuccess) return le;
   if (e != hipSuccess) return e;
   return hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0);
+}
+
+hipError_t BatchPlan::psf_ms(hipStream_t s, float* ms) const {
+  hipEvent_t ev[5] = {};
+  hipError_t e = hipSuccess;
+  for (auto& x : ev)
+    if (e == hipSuccess) e = hipEventCreate(&x);
+  for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) e = enqueue(s, ev);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, ev[2], ev[3]);
+  for (auto& x : ev)
+    if (x) (void)hipEventDestroy(x);
+  return e;
 }
 
 hipError_t BatchPlan::run(hipStream_t s) const {

@@ -222,7 +222,7 @@ class NestedSampler:
                  candidates_per_call: int = 256, record: bool = False, audit: float = 0.0, audit_seed: int = 0,
                  multi: bool = True, record_per_iter: Optional[int] = None,
                  audit_loglike: Optional[LogLikeFn] = None, method: str = "auto", n_steps: Optional[int] = None,
-                 slice_switch: Optional[float] = None):
+                 slice_switch: Optional[float] = None, probe_every: int = 20):
         if not (1 <= k_replace < n_live):
             raise ValueError("need 1 <= k_replace < n_live")
         self.loglike = loglike
@@ -245,14 +245,16 @@ class NestedSampler:
         self.record_per_iter = record_per_iter
         self.record_rng = np.random.default_rng(audit_seed + 2)
         # method: "rejection" (draws inside bounding ellipsoids), "slice" (slice
-        # sampling chains), or "auto": rejection until the bound's acceptance per
-        # draw falls below slice_switch (default 1 / (5 n_steps), the cost of a
-        # slice replacement), then slice for the rest of the run
+        # sampling chains), or "auto": per iteration the one with the lower
+        # measured exact renders per replacement (see _replace_auto)
         if method not in ("auto", "rejection", "slice"):
             raise ValueError("method must be auto, rejection or slice")
         self.method = method
         self.n_steps = n_steps if n_steps is not None else ndim
-        self.slice_switch = slice_switch if slice_switch is not None else 1.0 / (5.0 * self.n_steps)
+        # before any slice iteration has been measured, rejection is tried with a
+        # budget of twice this guess of the slice cost (renders per replacement)
+        self.slice_cost_guess = 1.0 / slice_switch if slice_switch is not None else 5.0 * self.n_steps
+        self.probe_every = probe_every
         # multi: bound the live points by a union of ellipsoids (else one ellipsoid)
         self.multi = multi
         self.split_rng = np.random.default_rng(seed + 1)
@@ -282,7 +284,7 @@ class NestedSampler:
             "live_u": u, "live_logl": logl, "dead_u": [], "dead_logl": [], "dead_logw": [],
             "logx": 0.0, "logz": -np.inf, "h": 0.0, "n_exact": self.n_live, "n_accepted": 0, "it": 0,
             "n_screened": 0, "history": [], "eval_u": [u.astype(np.float32)] if self.record else [],
-            "eval_l": [logl] if self.record else [],
+            "eval_l": [logl.copy()] if self.record else [],
             "rate": 0.5, "skips": 0, "audit_u": [], "n_audit": 0, "n_false_reject": 0,
         }
 
@@ -349,23 +351,64 @@ class NestedSampler:
         st = self.state
         st["rec_it"] = 0
         st["drawn_it"] = 0
-        if self.method == "slice" or (self.method == "auto" and st.get("use_slice", False)):
+        if self.method == "slice":
             out = self._replace_slice(lmin, n_new, screen)
-        else:
+        elif self.method == "rejection":
             out = self._replace_rejection(lmin, n_new, screen)
-            rate = n_new / max(st["drawn_it"], 1)
-            st["draw_rate"] = rate if "draw_rate" not in st else 0.7 * st["draw_rate"] + 0.3 * rate
-            if self.method == "auto" and st["draw_rate"] < self.slice_switch:
-                st["use_slice"] = True
+        else:
+            out = self._replace_auto(lmin, n_new, screen)
         st["n_accepted"] += n_new
         return out
 
-    def _replace_rejection(self, lmin: float, n_new: int, screen: Optional[Screen]):
+    def _replace_auto(self, lmin: float, n_new: int, screen: Optional[Screen]):
+        """Rejection or slice replacements, whichever has cost fewer exact renders
+        per accepted point lately (running averages); every probe_every
+        iterations the other one is tried, rejection with a render budget of
+        twice the slice cost (the shortfall is filled by slice)."""
+        st = self.state
+        c_rej, c_sl = st.get("cost_rej"), st.get("cost_slice")
+        use_rej = c_sl is None or (c_rej is not None and c_rej <= c_sl)
+        since = st["it"] - st.get("last_probe", -10 ** 9)
+        if since >= self.probe_every and c_rej is not None and c_sl is not None:
+            use_rej = not use_rej
+            st["last_probe"] = st["it"]
+        n0 = st["n_exact"]
+        if use_rej:
+            budget = None if c_sl is None else int(2.0 * c_sl * n_new) + 1
+            if c_sl is None and c_rej is not None and c_rej > self.slice_cost_guess:
+                budget = int(2.0 * self.slice_cost_guess * n_new) + 1
+            u, l = self._replace_rejection(lmin, n_new, screen, budget=budget)
+            got = len(u)
+            if got:
+                st["cost_rej"] = self._ema(c_rej, (st["n_exact"] - n0) / got)
+            else:
+                st["cost_rej"] = self._ema(c_rej, float(st["n_exact"] - n0 + 1))
+            if got < n_new:
+                n1 = st["n_exact"]
+                us, ls = self._replace_slice(lmin, n_new - got, screen)
+                st["cost_slice"] = self._ema(c_sl, (st["n_exact"] - n1) / (n_new - got))
+                u = us if got == 0 else np.concatenate([u, us])
+                l = ls if got == 0 else np.concatenate([l, ls])
+            return u, l
+        u, l = self._replace_slice(lmin, n_new, screen)
+        st["cost_slice"] = self._ema(c_sl, (st["n_exact"] - n0) / n_new)
+        return u, l
+
+    @staticmethod
+    def _ema(old: Optional[float], new: float) -> float:
+        return new if old is None else 0.7 * old + 0.3 * new
+
+    def _replace_rejection(self, lmin: float, n_new: int, screen: Optional[Screen], budget: Optional[int] = None):
+        """Up to n_new replacements drawn in the bound; with a budget, stops once
+        that many exact renders were spent (possibly returning fewer)."""
         st = self.state
         ell = (MultiEllipsoid(st["live_u"], self.enlarge, self.split_rng) if self.multi
                else Ellipsoid(st["live_u"], self.enlarge))
         new_u, new_l = [], []
+        n0 = st["n_exact"]
         while len(new_u) < n_new:
+            if budget is not None and st["n_exact"] - n0 >= budget:
+                break
             need = n_new - len(new_u)
             # size the exact batch from the running acceptance rate (about 10 % overshoot)
             m = min(self.cand * 16, int(math.ceil(1.1 * need / max(st["rate"], 1e-3))) + 1)
@@ -378,7 +421,7 @@ class NestedSampler:
                 if len(new_u) < n_new:
                     new_u.append(c[i])
                     new_l.append(logl[i])
-        return np.array(new_u), np.array(new_l)
+        return np.array(new_u).reshape(-1, self.ndim), np.array(new_l)
 
     def _classify(self, c: np.ndarray, lmin: float, screen: Optional[Screen]):
         """Inside-the-contour flags for proposals c (points outside the cube are
@@ -543,6 +586,8 @@ class NestedSampler:
                 st["dead_u"].append(st["live_u"][idx].copy())
                 st["dead_logl"].append(st["live_logl"][idx])
                 st["dead_logw"].append(logw)
+            if screen is not None and hasattr(screen, "begin_iteration"):
+                screen.begin_iteration(lmin, st["it"])
             new_u, new_l = self._replace(lmin, self.k, screen)
             st["live_u"][worst] = new_u
             st["live_logl"][worst] = new_l

@@ -83,33 +83,113 @@ class GpuLogLike:
 
 
 class SurrogateScreen(Screen):
+    """The trained network as the sampler's screen.
+
+    The margin at a threshold L_min is ``sigmas`` x the RMS residual (prediction
+    minus exact log L) of the calibration pairs whose exact log L is nearest
+    L_min: the network's held-out pairs plus this run's own exact evaluations.
+
+    With ``pool`` (the (u, log L) pairs of an earlier run of the same problem)
+    the network is refitted every ``refit_every`` iterations on the pairs of the
+    current contour region: pool pairs and this run's recent exact evaluations
+    with log L >= L_min - band, band = max(band_min, band_frac (L_best - L_min)).
+    The refit re-standardises the inputs to those pairs' spread, so the network
+    resolves the narrow posterior that a fit over the whole prior cannot.
+    """
+
     def __init__(self, surrogate: Surrogate, sigmas: float = 3.0, window: int = 200, floor: float = 1.0,
-                 max_skips: int = 2000, keep: int = 8192):
+                 max_skips: int = 2000, keep: int = 65536, pool=None, refit_every: int = 10,
+                 band_min: float = 50.0, band_frac: float = 0.5, refit_max: int = 60000, refit_steps: int = 300,
+                 seed: int = 0):
         self.surrogate = surrogate
         self.sigmas = sigmas
         self.window = window
         self.floor = floor
         self.max_skips = max_skips
         self.keep = keep
-        self.held_l, self.held_r = (np.asarray(a, np.float64) for a in surrogate.margin_table)
+        self.pool = None if pool is None else (np.asarray(pool[0], np.float32), np.asarray(pool[1], np.float64))
+        self.refit_every = refit_every
+        self.band_min, self.band_frac = band_min, band_frac
+        self.refit_max, self.refit_steps = refit_max, refit_steps
+        self.rng = np.random.default_rng(seed)
+        self.last_refit = None
+        self.refits = []
+        self._reset_calibration()
+        self.run_u = np.zeros((0, 0), np.float32)
+        self.run_ll = np.zeros(0)
+        self.n_predicted = 0
+
+    def _reset_calibration(self):
+        self.held_l, self.held_r = (np.asarray(a, np.float64) for a in self.surrogate.margin_table)
         self.run_l = np.zeros(0)
         self.run_r = np.zeros(0)
         self._sorted = None
-        self.n_predicted = 0
 
     def predict(self, u: np.ndarray) -> np.ndarray:
         self.n_predicted += len(u)
         return self.surrogate.predict(u)
 
     def observe(self, u: np.ndarray, exact: np.ndarray) -> None:
-        """Add the residuals of exactly evaluated points to the calibration set."""
+        """Add the residuals of exactly evaluated points to the calibration set
+        (and the points to the refit data)."""
         ok = np.isfinite(exact)
         if not ok.any():
             return
-        pred = self.surrogate.predict(np.asarray(u)[ok])
+        uu = np.asarray(u)[ok]
+        pred = self.surrogate.predict(uu)
         ex = np.asarray(exact, np.float64)[ok]
         self.run_l = np.concatenate([self.run_l, ex])[-self.keep:]
         self.run_r = np.concatenate([self.run_r, pred - ex])[-self.keep:]
+        if self.pool is not None:
+            self.run_u = (uu.astype(np.float32) if self.run_u.size == 0
+                          else np.concatenate([self.run_u, uu.astype(np.float32)])[-self.keep:])
+            self.run_ll = np.concatenate([self.run_ll, ex])[-self.keep:]
+        self._sorted = None
+
+    def begin_iteration(self, lmin: float, it: int) -> None:
+        if self.pool is None or (self.last_refit is not None and it - self.last_refit < self.refit_every):
+            return
+        pu, pl = self.pool
+        best = max(float(pl.max()), float(self.run_ll.max()) if self.run_ll.size else -np.inf)
+        band = max(self.band_min, self.band_frac * (best - lmin))
+        sel_p = pl >= lmin - band
+        u = pu[sel_p]
+        ll = pl[sel_p]
+        if self.run_ll.size:
+            sel_r = self.run_ll >= lmin - band
+            u = np.concatenate([u, self.run_u[sel_r]])
+            ll = np.concatenate([ll, self.run_ll[sel_r]])
+        if len(ll) < 2000:
+            return
+        if len(ll) > self.refit_max:
+            pick = self.rng.choice(len(ll), self.refit_max, replace=False)
+            u, ll = u[pick], ll[pick]
+        info = self.surrogate.refit(u, ll, steps=self.refit_steps, seed=it)
+        info.update({"it": it, "lmin": lmin, "band": band})
+        self.refits.append(info)
+        self.last_refit = it
+        self._reset_calibration()
+
+    def get_state(self) -> dict:
+        """Everything a resumed run needs: the (possibly refitted) network and the calibration."""
+        sur = self.surrogate
+        return {"params": sur.params.cpu().numpy(), "norm": sur.norm.cpu().numpy(), "l_ref": sur.l_ref,
+                "mu": sur.mu, "P": sur.P,
+                "table": sur.margin_table, "held": (self.held_l, self.held_r), "run": (self.run_l, self.run_r),
+                "run_pairs": (self.run_u, self.run_ll), "last_refit": self.last_refit, "refits": self.refits,
+                "rng": self.rng.bit_generator.state}
+
+    def set_state(self, d: dict) -> None:
+        sur = self.surrogate
+        sur.params = torch.from_numpy(d["params"]).to(sur.device)
+        sur.norm = torch.from_numpy(d["norm"]).to(sur.device)
+        sur.l_ref, sur.margin_table = d["l_ref"], d["table"]
+        sur.mu, sur.P = d["mu"], d["P"]
+        self.held_l, self.held_r = d["held"]
+        self.run_l, self.run_r = d["run"]
+        self.run_u, self.run_ll = d["run_pairs"]
+        self.last_refit, self.refits = d["last_refit"], d["refits"]
+        self.rng.bit_generator.state = d["rng"]
         self._sorted = None
 
     def margin(self, lmin: float) -> float:
@@ -171,7 +251,7 @@ def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, n_liv
                  seeds=(5, 6, 7), dlogz: float = 0.5, max_iter: int = 5000, train_epochs: int = 60,
                  train_batch: int = 1024, sigmas: float = 3.0, log=print, log_every: int = 100,
                  record_per_iter: Optional[int] = 200, audit: float = 0.0, state_dir: Optional[str] = None,
-                 deadline: Optional[float] = None, chunk: int = 25) -> dict:
+                 deadline: Optional[float] = None, chunk: int = 25, local: bool = True) -> dict:
     """Plain run A (records exact pairs), plain run B (another seed: the sampler's
     own spread), the surrogate trained on A's pairs, and the screened run C.
 
@@ -200,7 +280,7 @@ def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, n_liv
                 s.restore(f.read())
             wall0 = s.state.get("wall", 0.0)
             if isinstance(screen, SurrogateScreen) and "screen_run" in s.state:
-                screen.run_l, screen.run_r = s.state["screen_run"]
+                screen.set_state(s.state["screen_run"])
             log(f"{name}: resumed at iteration {s.state['it']}")
         t0 = time.perf_counter()
         while True:
@@ -211,7 +291,7 @@ def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, n_liv
                 if state_dir:
                     s.state["wall"] = wall0 + time.perf_counter() - t0
                     if isinstance(screen, SurrogateScreen):
-                        s.state["screen_run"] = (screen.run_l, screen.run_r)
+                        s.state["screen_run"] = screen.get_state()
                     with open(path(name + ".ckpt"), "wb") as f:
                         f.write(s.checkpoint())
                 raise Suspended(f"{name} suspended at iteration {r.n_iter}")
@@ -240,8 +320,9 @@ def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, n_liv
             sur.save(path("surrogate.npz"), fit)
     log(f"surrogate trained on {fit['n_train']} pairs in {fit['wall_s']:.1f} s, held-out rmse(y) "
         f"{fit['rmse_y']:.4f}")
-    screen = SurrogateScreen(sur, sigmas=sigmas)
-    log(f"screened run C, seed {seeds[2]}")
+    screen = SurrogateScreen(sur, sigmas=sigmas, pool=(ra.evaluated_u, ra.evaluated_logl) if local else None,
+                             seed=seeds[2])
+    log(f"screened run C, seed {seeds[2]}" + (" (network refitted locally every 10 iterations)" if local else ""))
     rc, wc = run("screened_c", seeds[2], screen=screen, fn=_Observed(ll, screen))
     log(f"  {rc.n_exact} exact evaluations, {rc.n_screened_out} screened out, log Z {rc.logz:.2f}, {wc:.1f} s")
 
@@ -258,6 +339,7 @@ def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, n_liv
         "shift_screened_sigma": (np.abs(mc - ma) / sa).tolist(),
         "shift_null_sigma": (np.abs(mb - ma) / sa).tolist(),
         "n_pairs_recorded": int(0 if ra.evaluated_u is None else len(ra.evaluated_u)),
+        "refits": screen.refits,
     })
     out["max_shift_screened_sigma"] = float(np.max(out["shift_screened_sigma"]))
     out["max_shift_null_sigma"] = float(np.max(out["shift_null_sigma"]))
