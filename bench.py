@@ -37,7 +37,8 @@ def parse():
     ap.add_argument("--points", type=int, default=4096)
     ap.add_argument("--plain-points", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-points-per-core", type=int, default=4)
+    ap.add_argument("--cpu-points-per-core", type=int, default=10)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the 16-system mixed batch line")
     ap.add_argument("--grad-points", type=int, default=1024)
     ap.add_argument("--grad-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -70,9 +71,66 @@ def cpu_baseline(spec, thetas, per_core):
         vals = list(ex.map(lambda t: oracle.loglike(osys, t), sample))
     dt = time.perf_counter() - t0
     assert all(math.isfinite(v) for v in vals)
+    n1 = max(per_core, 4)
+    t1 = time.perf_counter()
+    for t in sample[:n1]:
+        oracle.loglike(osys, t)
+    dt1 = time.perf_counter() - t1
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} points of the same 4096-point C1 workload, {per_core} per thread, "
-                      f"{dt:.1f} s wall"}
+                      f"{dt:.1f} s wall ({cores * dt:.0f} thread-s)",
+            "one_core": {"value": n1 / dt1, "unit": "evals/s", "points": n1},
+            "cpu_model": cpu}
+
+
+def mixed_batch(lensed, mocks, dev, stream, c1_ms_per_subsample, steps=5):
+    """16 systems of mixed size (64..300 px) and subsampling (N = 2..8), 512 points
+    each, in one graph launch: evals/s, subsample-evals/s, and the render stage's
+    time per subsample relative to the uniform 200x200 batch (1 = no imbalance cost)."""
+    import torch
+    specs = mocks.c2_specs()
+    systems, thetas, sop = [], [], []
+    for s_i, sp in enumerate(specs):
+        psf = torch.from_numpy(sp.psf).to(dev)
+        rs = lensed.System(psf, pixscale=sp.pixscale, nsub=sp.nsub, height=sp.height, width=sp.width)
+        ob = mocks.make_observation(
+            sp, lambda t: lensed.render(torch.from_numpy(np.asarray(t, np.float32)).to(dev), rs).cpu().numpy())
+        systems.append(lensed.System(psf, torch.from_numpy(ob.data).to(dev), torch.from_numpy(ob.weight).to(dev),
+                                     pixscale=sp.pixscale, nsub=sp.nsub))
+        thetas.append(mocks.points(sp, 512, seed=mocks.C2_BASE_SEED + 100 + s_i))
+        sop += [s_i] * 512
+    th = torch.from_numpy(np.concatenate(thetas)).to(dev)
+    sop = np.asarray(sop, np.int32)
+    out = torch.empty(len(sop), dtype=torch.float64, device=dev)
+    ctx = lensed.Context(0)
+    log(f"mixed batch: {len(specs)} systems, {len(sop)} points")
+    lensed.loglike_batch(th, sop, systems, out=out, ctx=ctx)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        lensed.loglike_batch(th, sop, systems, out=out, ctx=ctx)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ctx.set_profiling(True)
+    ctx.stage_times()
+    lensed.loglike_batch(th, sop, systems, out=out, ctx=ctx)
+    stages, calls = ctx.stage_times()
+    ctx.set_profiling(False)
+    subs = sum(sp.height * sp.width * sp.nsub ** 2 * 512 for sp in specs)
+    assert torch.isfinite(out).all().item()
+    return {"value": len(sop) / (ms / 1e3), "unit": "evals/s", "points": len(sop), "systems": len(specs),
+            "subsamples_per_launch": subs, "subsample_evals_per_s": subs / (ms / 1e3),
+            "render_ms": stages["render"] / calls, "psf_chi2_ms": stages["psf_chi2"] / calls,
+            "render_time_per_subsample_vs_uniform": (stages["render"] / calls) / subs / c1_ms_per_subsample,
+            "shapes": [f"{sp.height}x{sp.width} N={sp.nsub}" for sp in specs]}
 
 
 def main():
@@ -164,6 +222,13 @@ def main():
     plain_value = n_plain / (p0.elapsed_time(p1) / 1e3)
     rel = (outs - out[:n_plain]).abs() / out[:n_plain].abs().clamp_min(1.0)
     assert rel.max().item() < 1e-5, "plain and batched log L disagree"
+    # plain with a host sync per point, as a sampler calling one point at a time would
+    n_sync = min(256, n_plain)
+    ts = time.perf_counter()
+    for i in range(n_sync):
+        lensed.loglike(theta[i], gsys, out=outs[i:i + 1], ctx=ctx)
+        outs[i].item()
+    plain_sync_value = n_sync / (time.perf_counter() - ts)
 
     # adjoint: log L and its 17-gradient for the C3 configuration
     G = args.grad_points
@@ -179,6 +244,10 @@ def main():
     torch.cuda.synchronize()
     grad_value = G * args.grad_steps / (g0.elapsed_time(g1) / 1e3)
     assert torch.isfinite(gg).all().item()
+
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_batch(lensed, mocks, dev, stream, stage_ms["render"] / (subs * P))
 
     result = {
         "metric": "log-likelihood evals/sec at 200x200, 4x4 subsample (batched)",
@@ -199,6 +268,8 @@ def main():
                    "mask": "annulus 0.3-3.0 arcsec (all pixels rendered)"},
         "plain": {"value": plain_value, "unit": "evals/s", "points": n_plain,
                   "form": "one prologue/render/psf/finalize launch sequence per point, one sync"},
+        "plain_host_sync": {"value": plain_sync_value, "unit": "evals/s", "points": n_sync,
+                            "form": "one point per call, host sync after each (not used for the ratio)"},
         "batched_over_plain": value / plain_value,
         "adjoint": {"value": grad_value, "unit": "gradients/s", "points": G,
                     "form": "log L and d log L/d theta (17) per point, one graph launch per step"},
@@ -208,6 +279,7 @@ def main():
                      "kernel": "render", "ops_per_subsample": OPS_PER_SUBSAMPLE,
                      "subsamples_per_launch": subs * P},
         "psf_chi2_tflops": psf_tflops,
+        "mixed_batch": mixed,
         "wall_s_timed": wall,
     }
     if not args.no_cpu_baseline:

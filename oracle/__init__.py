@@ -32,6 +32,9 @@ class LoSystem(ctypes.Structure):
         ("psf", ctypes.POINTER(ctypes.c_double)),
         ("data", ctypes.POINTER(ctypes.c_double)),
         ("weight", ctypes.POINTER(ctypes.c_double)),
+        ("rule_n", ctypes.c_int32),
+        ("rule_x", ctypes.POINTER(ctypes.c_double)),
+        ("rule_w", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -60,6 +63,7 @@ def lib():
             ("lo_surface_brightness_grad", d, [dp, d, d, dp]),
             ("lo_sum_compensated", d, [dp, ctypes.c_int64]),
             ("lo_render", i, [sp, dp, i, dp]),
+            ("lo_render_error", i, [sp, dp, dp, dp]),
             ("lo_psf_convolve", i, [i, i, dp, i, i, dp, dp]),
             ("lo_loglike", d, [sp, dp]),
             ("lo_loglike_grad", d, [sp, dp, dp]),
@@ -79,7 +83,9 @@ class System:
     """
 
     def __init__(self, height, width, pixscale, nsub, psf, data=None, weight=None,
-                 center_x=0.0, center_y=0.0):
+                 center_x=0.0, center_y=0.0, rule=None):
+        """rule: None for the nsub x nsub midpoint rule, or a name accepted by
+        oracle.quadrature.pixel_rule ('subN', 'point', 'g3k7', 'g5k11', 'g7k15')."""
         self.height, self.width = int(height), int(width)
         self.pixscale = float(pixscale)
         self.center_x, self.center_y = float(center_x), float(center_y)
@@ -88,9 +94,18 @@ class System:
         n = self.height * self.width
         self.data = np.ascontiguousarray(np.zeros(n) if data is None else np.asarray(data, np.float64).reshape(-1))
         self.weight = np.ascontiguousarray(np.ones(n) if weight is None else np.asarray(weight, np.float64).reshape(-1))
+        self.rule = rule
+        self.rule_x = self.rule_w = self.rule_g = None
+        rn, rx, rw = 0, None, None
+        if rule is not None:
+            from .quadrature import pixel_rule
+            x, w, g = pixel_rule(rule)
+            self.rule_x, self.rule_w = np.ascontiguousarray(x), np.ascontiguousarray(w)
+            self.rule_g = None if g is None else np.ascontiguousarray(g)
+            rn, rx, rw = len(x), _dp(self.rule_x), _dp(self.rule_w)
         self._s = LoSystem(self.height, self.width, self.pixscale, self.center_x, self.center_y,
                            self.nsub, self.psf.shape[0], self.psf.shape[1],
-                           _dp(self.psf), _dp(self.data), _dp(self.weight))
+                           _dp(self.psf), _dp(self.data), _dp(self.weight), rn, rx, rw)
 
     @property
     def ptr(self):
@@ -159,6 +174,18 @@ def render(system, theta, apply_psf=True):
     rc = lib().lo_render(system.ptr, _dp(t), int(bool(apply_psf)), _dp(out))
     if rc != 0:
         raise ValueError("oracle render: invalid system")
+    return out.reshape(system.height, system.width)
+
+
+def render_error(system, theta):
+    """|Kronrod - embedded Gauss| per pixel (before the PSF) for a system built
+    with a Gauss-Kronrod rule."""
+    if system.rule_g is None:
+        raise ValueError("render_error needs a Gauss-Kronrod rule")
+    t = _theta(theta)
+    out = np.empty(system.height * system.width)
+    if lib().lo_render_error(system.ptr, _dp(t), _dp(system.rule_g), _dp(out)) != 0:
+        raise ValueError("oracle render_error: invalid system")
     return out.reshape(system.height, system.width)
 
 
