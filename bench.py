@@ -89,6 +89,32 @@ def cpu_baseline(spec, thetas, per_core):
             "cpu_model": cpu}
 
 
+RENDER_SOURCES = ("internal.h", "sb_device.h", "sie_poly.h", "gk_rules.h", "render.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_c1_batch4096_traffic.json")
+
+
+def render_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in RENDER_SOURCES:
+        with open(os.path.join(ROOT, "paper_1505_07674_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per render launch from the committed hardware-counter summary,
+    or None when there is none or the render sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != render_sources_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def mixed_batch(lensed, mocks, dev, stream, c1_ms_per_subsample, steps=5):
     """16 systems of mixed size (64..300 px) and subsampling (N = 2..8), 512 points
     each, in one graph launch: evals/s, subsample-evals/s, and the render stage's
@@ -275,7 +301,7 @@ def main():
                     "form": "log L and d log L/d theta (17) per point, one graph launch per step"},
         "stage_ms_per_step": stage_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "render", "ops_per_subsample": OPS_PER_SUBSAMPLE,
                      "subsamples_per_launch": subs * P},
         "psf_chi2_tflops": psf_tflops,

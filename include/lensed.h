@@ -80,7 +80,16 @@ typedef struct {
   const float* psf;           /* device [psf_h * psf_w], any positive scale     */
   const float* data;          /* device [height * width]; may be NULL for render */
   const float* weight;        /* device [height * width]; may be NULL for render */
+  int32_t rule;               /* pixel integration rule (Eq. 14, Sec. 4.5):
+                                 LENSED_RULE_MIDPOINT (nsub x nsub "subN"), or the
+                                 Cartesian square of a Gauss-Kronrod rule
+                                 LENSED_RULE_G3K7 / _G5K11 / _G7K15 (nsub ignored) */
 } lensed_system;
+
+#define LENSED_RULE_MIDPOINT 0
+#define LENSED_RULE_G3K7 1
+#define LENSED_RULE_G5K11 2
+#define LENSED_RULE_G7K15 3
 
 /* Creates a context bound to HIP device `device` (its workspace arena, cached
  * batch plans and graphs). Returns LENSED_NOT_SUPPORTED if the device is not
@@ -133,13 +142,26 @@ int lensed_loglike_batch(lensed_ctx* ctx, const lensed_system* systems, int n_sy
                          const float* theta, const int32_t* system_of_point, int n_points,
                          double* logl, void* stream);
 
+/* Per-pixel integration error estimate of a Gauss-Kronrod rule (Sec. 3.1: the
+ * embedded Gauss rule estimates the error of each pixel and is saved with the
+ * output): error[i] = |L_i(Kronrod) - L_i(embedded Gauss)| before the PSF, for
+ * one parameter point.
+ *   sys     its rule must be a LENSED_RULE_G*K* value (INVALID_ARGUMENT otherwise);
+ *           data and weight are not used
+ *   theta   device float32 [17]
+ *   error   device float32 [height * width], written
+ * The subsample values are the float32 render's, without the float64 re-tracing
+ * near a cuspy source centre that lensed_render applies. */
+int lensed_render_error(lensed_ctx* ctx, const lensed_system* sys, const float* theta, float* error, void* stream);
+
 /* Log-likelihood and its gradient with respect to the 17 parameters for
  * n_points points of one system: the derivative of Eq. 17 through Eqs. 15, 14,
  * 2 and 1, computed by a hand-written adjoint (transposed PSF with the
  * replicate-padding fold, then per-subsample partial derivatives).
  *   theta  device float32 [n_points * 17]
  *   logl   device float64 [n_points], written
- *   grad   device float32 [n_points * 17], written (d log L / d theta) */
+ *   grad   device float32 [n_points * 17], written (d log L / d theta)
+ * The system must use the N x N midpoint rule (LENSED_NOT_SUPPORTED otherwise). */
 int lensed_loglike_grad(lensed_ctx* ctx, const lensed_system* sys, const float* theta,
                         int n_points, double* logl, float* grad, void* stream);
 

@@ -116,14 +116,16 @@ def gauss_kronrod(n):
     c = stieltjes(n)
     cf = np.array([float(v) for v in c])
     r = np.roots(cf[::-1]).real
-    dc = np.array([float(v * i) for i, v in enumerate(c)][1:])
-    for _ in range(50):                                  # Newton polish on the exact coefficients
-        f = np.polyval(cf[::-1], r)
-        d = np.polyval(dc[::-1], r)
-        step = f / d
-        r = r - step
-        if np.max(np.abs(step)) < 1e-16:
-            break
+    dc = [v * i for i, v in enumerate(c)][1:]
+    polished = []
+    for x0 in r:                                         # Newton polish, evaluated exactly in rationals
+        x = Fraction(float(x0))
+        for _ in range(8):
+            f = sum(cv * x ** i for i, cv in enumerate(c))
+            d = sum(dv * x ** i for i, dv in enumerate(dc))
+            x = Fraction(float(x - f / d))
+        polished.append(float(x))
+    r = np.array(polished)
     x = np.sort(np.concatenate([xg, r]))
     # weights: exact for P_0..P_{2n}
     V = np.stack([_legendre(k, x)[0] if k else np.ones_like(x) for k in range(2 * n + 1)])

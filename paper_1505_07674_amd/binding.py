@@ -36,7 +36,11 @@ class LensedSystemC(ctypes.Structure):
         ("nsub", ctypes.c_int32),
         ("psf_h", ctypes.c_int32), ("psf_w", ctypes.c_int32),
         ("psf", ctypes.c_void_p), ("data", ctypes.c_void_p), ("weight", ctypes.c_void_p),
+        ("rule", ctypes.c_int32),
     ]
+
+
+RULES = {"sub": 0, "g3k7": 1, "g5k11": 2, "g7k15": 3}
 
 
 _lib = None
@@ -60,6 +64,7 @@ def lib():
                 "lensed_status_string": (cp, [i]),
                 "lensed_last_error": (cp, [vp]),
                 "lensed_render": (i, [vp, sp, vp, vp, i, vp]),
+                "lensed_render_error": (i, [vp, sp, vp, vp, vp]),
                 "lensed_loglike": (i, [vp, sp, vp, vp, vp]),
                 "lensed_loglike_batch": (i, [vp, sp, i, vp, ctypes.POINTER(ctypes.c_int32), i, vp, vp]),
                 "lensed_loglike_grad": (i, [vp, sp, vp, i, vp, vp, vp]),
@@ -160,9 +165,14 @@ class System:
     """
 
     def __init__(self, psf: torch.Tensor, data: Optional[torch.Tensor] = None,
-                 weight: Optional[torch.Tensor] = None, *, pixscale: float, nsub: int,
+                 weight: Optional[torch.Tensor] = None, *, pixscale: float, nsub: int = 1,
                  height: Optional[int] = None, width: Optional[int] = None,
-                 center: Tuple[float, float] = (0.0, 0.0)):
+                 center: Tuple[float, float] = (0.0, 0.0), rule: str = "sub"):
+        """rule: "sub" (nsub x nsub midpoint) or a Gauss-Kronrod product rule
+        "g3k7", "g5k11", "g7k15" (Sec. 4.5; nsub is then ignored)."""
+        if rule not in RULES:
+            raise ValueError(f"rule must be one of {sorted(RULES)}")
+        self.rule = rule
         self.psf = _dev_tensor(psf, torch.float32, "psf")
         if self.psf.dim() != 2:
             raise ValueError("psf must be 2-D")
@@ -185,7 +195,7 @@ class System:
             self.height, self.width, self.pixscale, self.center[0], self.center[1], self.nsub,
             int(self.psf.shape[0]), int(self.psf.shape[1]), self.psf.data_ptr(),
             None if self.data is None else self.data.data_ptr(),
-            None if self.weight is None else self.weight.data_ptr())
+            None if self.weight is None else self.weight.data_ptr(), RULES[rule])
 
     @property
     def c_struct(self) -> LensedSystemC:
@@ -216,6 +226,20 @@ def render(theta: torch.Tensor, system: System, apply_psf: bool = True, *, ctx: 
     rc = lib().lensed_render(ctx.handle, ctypes.byref(system.c_struct), ctypes.c_void_p(t.data_ptr()),
                              ctypes.c_void_p(out.data_ptr()), int(bool(apply_psf)), _stream_handle(stream))
     ctx.check(rc, "lensed_render")
+    return out
+
+
+def render_error(theta: torch.Tensor, system: System, *, ctx: Optional[Context] = None,
+                 stream=None) -> torch.Tensor:
+    """Per-pixel |Kronrod - embedded Gauss| estimate [H, W] of a Gauss-Kronrod system (before the PSF)."""
+    t = _theta2d(theta)
+    if t.shape[0] != 1:
+        raise ValueError("render_error takes a single parameter point")
+    ctx = ctx or default_context(t.device.index)
+    out = torch.empty((system.height, system.width), dtype=torch.float32, device=t.device)
+    rc = lib().lensed_render_error(ctx.handle, ctypes.byref(system.c_struct), ctypes.c_void_p(t.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+    ctx.check(rc, "lensed_render_error")
     return out
 
 

@@ -453,7 +453,8 @@ __global__ __launch_bounds__(64 * GCUSP_WAVES) void grad_cusp_kernel(WorkArgs w,
           const float sR2 = render_source_R2(c, x, y);
           if (sR2 < c.cusp_r2) {
             float dx, dy;
-            source_offset_f64(p64s[e.point], geo, kx, ky, N, dx, dy);
+            source_offset_f64(p64s[e.point], geo, ((double)kx + 0.5) / N - 0.5, ((double)ky + 0.5) / N - 0.5, dx,
+                              dy);
             switch (c.sie_mode) {
               case 0: subsample_grad<0>(c, U, x, y, a32); subsample_grad<0>(c, U, x, y, a64, true, dx, dy); break;
               case 1: subsample_grad<1>(c, U, x, y, a32); subsample_grad<1>(c, U, x, y, a64, true, dx, dy); break;

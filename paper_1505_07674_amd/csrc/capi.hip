@@ -135,7 +135,10 @@ int validate_system(lensed_ctx* c, const lensed_system* s, bool need_data, int i
     return set_err(c, LENSED_INVALID_ARGUMENT, where + "pixscale must be finite and > 0");
   if (!std::isfinite(s->center_x) || !std::isfinite(s->center_y))
     return set_err(c, LENSED_INVALID_ARGUMENT, where + "grid centre must be finite");
-  if (s->nsub < 1 || s->nsub > 16) return set_err(c, LENSED_INVALID_ARGUMENT, where + "nsub must be in 1..16");
+  if (s->rule < LENSED_RULE_MIDPOINT || s->rule > LENSED_RULE_G7K15)
+    return set_err(c, LENSED_INVALID_ARGUMENT, where + "rule must be one of the LENSED_RULE_* values");
+  if (s->rule == LENSED_RULE_MIDPOINT && (s->nsub < 1 || s->nsub > 16))
+    return set_err(c, LENSED_INVALID_ARGUMENT, where + "nsub must be in 1..16");
   if (s->psf_h < 1 || s->psf_w < 1 || s->psf_h % 2 == 0 || s->psf_w % 2 == 0)
     return set_err(c, LENSED_INVALID_ARGUMENT, where + "PSF dimensions must be odd and >= 1");
   if (s->psf_h > MAX_PSF || s->psf_w > MAX_PSF)
@@ -151,7 +154,8 @@ SysDesc make_desc(const lensed_system& s, const TileShape& t) {
   std::memset(&d, 0, sizeof(d));
   d.H = s.height;
   d.W = s.width;
-  d.N = s.nsub;
+  d.rule = s.rule;
+  d.N = s.rule == LENSED_RULE_MIDPOINT ? s.nsub : 2 * (2 * s.rule + 1) + 1;   // g3k7, g5k11, g7k15: 7, 11, 15 nodes
   d.ph = s.psf_h;
   d.pw = s.psf_w;
   d.d = s.pixscale;
@@ -166,7 +170,9 @@ SysDesc make_desc(const lensed_system& s, const TileShape& t) {
   d.tiles_x = (s.width + t.TW - 1) / t.TW;
   d.n_ptiles = d.tiles_x * ((s.height + t.TH - 1) / t.TH);
   d.n_rtiles = (int)(((int64_t)s.height * s.width + RENDER_BLOCK - 1) / RENDER_BLOCK);
-  d.wgt = (double)s.pixscale * (double)s.pixscale / ((double)s.nsub * (double)s.nsub);
+  // the midpoint weights 1/N^2 are folded here; the Gauss-Kronrod weights (summing to 1) multiply in the kernel
+  d.wgt = (double)s.pixscale * (double)s.pixscale /
+          (s.rule == LENSED_RULE_MIDPOINT ? (double)s.nsub * (double)s.nsub : 1.0);
   return d;
 }
 
@@ -263,6 +269,34 @@ int lensed_render(lensed_ctx* c, const lensed_system* sys, const float* theta, f
   if (apply_psf)
     LENSED_HIP(c, launch_psf(w, L, image, nullptr, 0, sd.n_ptiles, square_psf_code(sd.ph, sd.pw), sd.TW, sd.TH,
                              sd.ph, sd.pw, st));
+  return LENSED_OK;
+}
+
+int lensed_render_error(lensed_ctx* c, const lensed_system* sys, const float* theta, float* error, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  int rc = validate_system(c, sys, false, -1);
+  if (rc) return rc;
+  if (sys->rule == LENSED_RULE_MIDPOINT)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "the error estimate needs a Gauss-Kronrod rule");
+  if (!theta || !error) return set_err(c, LENSED_INVALID_ARGUMENT, "theta and error are required");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const TileShape ts = c->tiles.choose(*sys);
+  SysDesc sd = make_desc(*sys, ts);
+  const size_t off_pc = 0;
+  const size_t off_p64 = align_up(off_pc + sizeof(PointConst), 256);
+  const size_t off_psf = align_up(off_p64 + sizeof(PointConst64), 256);
+  const size_t off_cc = align_up(off_psf + 3 * sizeof(float) * sd.ph * sd.pw, 256);
+  const size_t total = align_up(off_cc + sizeof(int), 256);
+  if ((rc = ensure_arena(c, total))) return rc;
+  PointConst* pc = (PointConst*)(c->arena + off_pc);
+  PointConst64* p64 = (PointConst64*)(c->arena + off_p64);
+  sd.psfn = (float*)(c->arena + off_psf);
+  WorkArgs w;
+  std::memset(&w, 0, sizeof(w));
+  w.single = sd;
+  LENSED_HIP(c, launch_prologue(theta, 1, pc, p64, nullptr, sd, nullptr, 1, (int*)(c->arena + off_cc), st));
+  LENSED_HIP(c, launch_rule_error(w, pc, error, sd.n_rtiles, st));
   return LENSED_OK;
 }
 
@@ -415,6 +449,8 @@ extern "C" int lensed_loglike_grad(lensed_ctx* c, const lensed_system* sys, cons
   if (n_points == 0) return LENSED_OK;
   int rc = validate_system(c, sys, true, -1);
   if (rc) return rc;
+  if (sys->rule != LENSED_RULE_MIDPOINT)
+    return set_err(c, LENSED_NOT_SUPPORTED, "the adjoint supports the N x N midpoint rule only");
   if (!theta || !logl || !grad) return set_err(c, LENSED_INVALID_ARGUMENT, "theta, logl and grad are required");
   LENSED_HIP(c, hipSetDevice(c->device));
   std::vector<int32_t> map(n_points, 0);

@@ -88,7 +88,7 @@ struct SysDesc {
   int TW, TH;             // PSF/chi^2 output tile
   int tiles_x, n_ptiles;  // PSF tiles per row, per image
   int n_rtiles;           // render tiles (RENDER_BLOCK pixels each) per image
-  int pad;
+  int rule;               // 0 N x N midpoint; 1, 2, 3: Gauss-Kronrod g3k7, g5k11, g7k15 (N = 7, 11, 15)
   double wgt;             // quadrature weight pixscale^2 / N^2, in float64
   float* adjk;            // 16 folded PSF tables of the adjoint (or nullptr)
   float* adjk_pad;

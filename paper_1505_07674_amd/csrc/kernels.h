@@ -35,6 +35,10 @@ hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, Po
 hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L, int n_blocks,
                          const CuspList& cl, hipStream_t stream);
 
+// Per-pixel integration error estimate of a Gauss-Kronrod rule for the single
+// point w.point0 of w.single (rule > 0): |Kronrod - embedded Gauss| x pixel weight.
+hipError_t launch_rule_error(const WorkArgs& w, const PointConst* pcs, float* E, int n_blocks, hipStream_t stream);
+
 // mode 0: PSF convolution of L into out (L* images, same offsets as L).
 // mode 1: PSF convolution fused with the weighted chi^2; one compensated
 //         (hi, lo) float pair per tile is written to partials.

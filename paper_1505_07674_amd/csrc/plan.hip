@@ -102,7 +102,7 @@ namespace {
 bool same_system(const lensed_system& a, const lensed_system& b) {
   return a.height == b.height && a.width == b.width && a.pixscale == b.pixscale && a.center_x == b.center_x &&
          a.center_y == b.center_y && a.nsub == b.nsub && a.psf_h == b.psf_h && a.psf_w == b.psf_w &&
-         a.psf == b.psf && a.data == b.data && a.weight == b.weight;
+         a.psf == b.psf && a.data == b.data && a.weight == b.weight && a.rule == b.rule;
 }
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 }  // namespace

@@ -1,7 +1,8 @@
 // render.hip -- pixel luminosities by N x N midpoint subsampling.
 //
 // L_i = integral of I over pixel i (Sec. 2.1 Eq. 3) approximated by the
-// weighted sum of Eq. 14 with the "subN" midpoint rule (Sec. 4.5). One thread
+// weighted sum of Eq. 14 with the "subN" midpoint rule or the Cartesian square
+// of a Gauss-Kronrod rule (g3k7, g5k11, g7k15; Sec. 4.5). One thread
 // per pixel sums its N^2 subsamples in registers; a block covers 256
 // consecutive pixels of one image in row-major order, so stores are coalesced
 // and only the last block of an image is ragged. The per-point constants are
@@ -16,7 +17,13 @@ namespace lensed {
 namespace {
 
 template <int MODE>
-__device__ float pixel_sum_dispatch(const PointConst& c, int N, const PixelGeom& g, bool& cusp) {
+__device__ float pixel_sum_dispatch(const PointConst& c, int rule, int N, const PixelGeom& g, bool& cusp) {
+  switch (rule) {
+    case 1: return pixel_sum_gk<7, MODE>(c, g, cusp);
+    case 2: return pixel_sum_gk<11, MODE>(c, g, cusp);
+    case 3: return pixel_sum_gk<15, MODE>(c, g, cusp);
+    default: break;
+  }
   switch (N) {
     case 1: return pixel_sum<1, MODE>(c, g, cusp);
     case 2: return pixel_sum<2, MODE>(c, g, cusp);
@@ -67,10 +74,10 @@ __global__ __launch_bounds__(RENDER_BLOCK) void render_kernel(WorkArgs w, const 
     const PointConst& c = pcs[point];
     float acc;
     switch (c.rmode) {
-      case 0: acc = pixel_sum_dispatch<0>(c, sd.N, g, cusp); break;
-      case 1: acc = pixel_sum_dispatch<1>(c, sd.N, g, cusp); break;
-      case 2: acc = pixel_sum_dispatch<2>(c, sd.N, g, cusp); break;
-      default: acc = pixel_sum_dispatch<3>(c, sd.N, g, cusp); break;
+      case 0: acc = pixel_sum_dispatch<0>(c, sd.rule, sd.N, g, cusp); break;
+      case 1: acc = pixel_sum_dispatch<1>(c, sd.rule, sd.N, g, cusp); break;
+      case 2: acc = pixel_sum_dispatch<2>(c, sd.rule, sd.N, g, cusp); break;
+      default: acc = pixel_sum_dispatch<3>(c, sd.rule, sd.N, g, cusp); break;
     }
     L[loff + pix] = (float)((double)acc * sd.wgt);
   }
@@ -106,12 +113,50 @@ __global__ __launch_bounds__(64 * CUSP_WAVES) void cusp_kernel(WorkArgs w, const
     const int pix = e.pix0 + lane;
     const PixelGeom g = pixel_geom(sd, pix);
     const PointConst& c = pcs[e.point];
-    const float corr = cusp_correction(c, p64s[e.point], sd.N, g);
+    const float corr = cusp_correction(c, p64s[e.point], sd.rule, sd.N, g);
     L[loff + pix] = (float)((double)L[loff + pix] + (double)corr * sd.wgt);
   }
 }
 
+// |Kronrod - embedded Gauss| x pixel weight for every pixel of one point (the
+// per-pixel integration error estimate of a Gauss-Kronrod rule), float32
+// subsample values without the cusp re-tracing.
+template <int K>
+__device__ float rule_error_pixel(const PointConst& c, const PixelGeom& g) {
+  bool cusp = false;
+  float gauss = 0.0f, k = 0.0f;
+  switch (c.rmode) {
+    case 0: k = pixel_sum_gk<K, 0, true>(c, g, cusp, &gauss); break;
+    case 1: k = pixel_sum_gk<K, 1, true>(c, g, cusp, &gauss); break;
+    case 2: k = pixel_sum_gk<K, 2, true>(c, g, cusp, &gauss); break;
+    default: k = pixel_sum_gk<K, 3, true>(c, g, cusp, &gauss); break;
+  }
+  return fabsf(k - gauss);
+}
+
+__global__ __launch_bounds__(RENDER_BLOCK) void rule_error_kernel(WorkArgs w, const PointConst* __restrict__ pcs,
+                                                                   float* __restrict__ E) {
+  const SysDesc sd = w.single;
+  const int pix = blockIdx.x * RENDER_BLOCK + (int)threadIdx.x;
+  if (pix >= sd.H * sd.W) return;
+  const PixelGeom g = pixel_geom(sd, pix);
+  const PointConst& c = pcs[w.point0];
+  float e;
+  switch (sd.rule) {
+    case 1: e = rule_error_pixel<7>(c, g); break;
+    case 2: e = rule_error_pixel<11>(c, g); break;
+    default: e = rule_error_pixel<15>(c, g); break;
+  }
+  E[pix] = (float)((double)e * sd.wgt);
+}
+
 }  // namespace
+
+hipError_t launch_rule_error(const WorkArgs& w, const PointConst* pcs, float* E, int n_blocks, hipStream_t stream) {
+  if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rule_error_kernel, dim3(n_blocks), dim3(RENDER_BLOCK), 0, stream, w, pcs, E);
+  return hipGetLastError();
+}
 
 hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L, int n_blocks,
                          const CuspList& cl, hipStream_t stream) {

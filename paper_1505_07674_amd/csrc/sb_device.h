@@ -17,6 +17,9 @@
 // are used instead. At psi = 0 the deflection is zero.
 #pragma once
 
+#include <utility>
+
+#include "gk_rules.h"
 #include "internal.h"
 #include "sie_poly.h"
 
@@ -54,12 +57,13 @@ struct PixelGeom {
   float ux, uy, d, cx, cy;
 };
 
-// Float64 re-tracing of one subsample: exact abscissa (as the rule defines it),
-// SIE + shear lens equation in float64, offset from the source centre.
-__device__ __forceinline__ void source_offset_f64(const PointConst64& e, const PixelGeom& g, int kx, int ky, int N,
+// Float64 re-tracing of one subsample: exact abscissa (as the rule defines it:
+// offsets ox, oy in pixel units), SIE + shear lens equation in float64, offset
+// from the source centre.
+__device__ __forceinline__ void source_offset_f64(const PointConst64& e, const PixelGeom& g, double ox, double oy,
                                                   float& dx, float& dy) {
-  const double x = (double)g.cx + ((double)g.ux + (((double)kx + 0.5) / N - 0.5)) * (double)g.d;
-  const double y = (double)g.cy + ((double)g.uy + (((double)ky + 0.5) / N - 0.5)) * (double)g.d;
+  const double x = (double)g.cx + ((double)g.ux + ox) * (double)g.d;
+  const double y = (double)g.cy + ((double)g.uy + oy) * (double)g.d;
   double ax = 0.0, ay = 0.0;
   if (e.mode == 0) {
     const double r = sqrt(x * x + y * y);
@@ -232,21 +236,85 @@ __device__ __forceinline__ float render_source_R2(const PointConst& c, float x, 
   return fmaf(X, X, Y * Y);
 }
 
+// ---------------------------------------------------------------------------
+// Gauss-Kronrod product rules (Sec. 3.1 Eq. 14, Sec. 4.5: g3k7, g5k11, g7k15):
+// offsets on [-1/2, 1/2] pixel, Kronrod weights and embedded Gauss weights (0 at
+// the Kronrod-only nodes), each summing to 1, from gk_rules.h.
+// ---------------------------------------------------------------------------
+struct GkRule {
+  float x[15], w[15], g[15];
+  double xd[15];
+};
+
+template <size_t K, size_t... I>
+constexpr GkRule make_gk_rule(const double (&x)[K], const double (&w)[K], const double (&g)[K],
+                              std::index_sequence<I...>) {
+  return GkRule{{float(x[I])...}, {float(w[I])...}, {float(g[I])...}, {x[I]...}};
+}
+
+static __constant__ GkRule kGkRules[3] = {
+    make_gk_rule(GK7_X, GK7_W, GK7_G, std::make_index_sequence<7>{}),
+    make_gk_rule(GK11_X, GK11_W, GK11_G, std::make_index_sequence<11>{}),
+    make_gk_rule(GK15_X, GK15_W, GK15_G, std::make_index_sequence<15>{}),
+};
+
+// Kronrod-weighted sum over the K x K nodes of a pixel (rows rolled, columns
+// unrolled); with ERR also the embedded Gauss sum, returned in gauss.
+template <int K, int RM, bool ERR = false>
+__device__ __forceinline__ float pixel_sum_gk(const PointConst& c, const PixelGeom& g, bool& cusp,
+                                              float* gauss = nullptr) {
+  const GkRule& R = kGkRules[(K - 7) / 4];
+  float xs[K];
+#pragma unroll
+  for (int kx = 0; kx < K; ++kx) xs[kx] = fmaf(g.ux + R.x[kx], g.d, g.cx);
+  float sh = 0.0f, ss = 0.0f, gh = 0.0f, gs = 0.0f;
+#pragma unroll 1
+  for (int ky = 0; ky < K; ++ky) {
+    const RowTerms r = row_terms(c, fmaf(g.uy + R.x[ky], g.d, g.cy));
+    float rh = 0.0f, rs = 0.0f, qh = 0.0f, qs = 0.0f;
+#pragma unroll
+    for (int kx = 0; kx < K; ++kx) {
+      float h, s;
+      subsample_light<RM>(c, r, xs[kx], h, s, cusp);
+      rh = fmaf(R.w[kx], h, rh);
+      rs = fmaf(R.w[kx], s, rs);
+      if (ERR) {
+        qh = fmaf(R.g[kx], h, qh);
+        qs = fmaf(R.g[kx], s, qs);
+      }
+    }
+    sh = fmaf(R.w[ky], rh, sh);
+    ss = fmaf(R.w[ky], rs, ss);
+    if (ERR) {
+      gh = fmaf(R.g[ky], qh, gh);
+      gs = fmaf(R.g[ky], qs, gs);
+    }
+  }
+  if (ERR) *gauss = fmaf(c.hI, gh, c.sI * gs);
+  return fmaf(c.hI, sh, c.sI * ss);
+}
+
 // Correction for one flagged pixel: for every subsample in the cusp zone, the
-// source light at the float64 re-traced offset minus the render's float32 value.
-__device__ __forceinline__ float cusp_correction(const PointConst& c, const PointConst64& c64, int N,
+// source light at the float64 re-traced offset minus the render's float32 value,
+// with the rule's weight (rule 0: N x N midpoint, weight folded into the pixel
+// weight; else the Gauss-Kronrod rule of N = 7, 11, 15 nodes).
+__device__ __forceinline__ float cusp_correction(const PointConst& c, const PointConst64& c64, int rule, int N,
                                                  const PixelGeom& g) {
   float acc = 0.0f;
+  const GkRule* R = rule > 0 ? &kGkRules[rule - 1] : nullptr;
   for (int ky = 0; ky < N; ++ky) {
-    const float y = fmaf(g.uy + sub_offset_rt(ky, N), g.d, g.cy);
+    const float y = R ? fmaf(g.uy + R->x[ky], g.d, g.cy) : fmaf(g.uy + sub_offset_rt(ky, N), g.d, g.cy);
+    const double oy = R ? R->xd[ky] : ((double)ky + 0.5) / N - 0.5;
     for (int kx = 0; kx < N; ++kx) {
-      const float x = fmaf(g.ux + sub_offset_rt(kx, N), g.d, g.cx);
+      const float x = R ? fmaf(g.ux + R->x[kx], g.d, g.cx) : fmaf(g.ux + sub_offset_rt(kx, N), g.d, g.cx);
       const float sR2 = render_source_R2(c, x, y);
       if (sR2 < c.cusp_r2) {
+        const double ox = R ? R->xd[kx] : ((double)kx + 0.5) / N - 0.5;
         float dx, dy;
-        source_offset_f64(c64, g, kx, ky, N, dx, dy);
+        source_offset_f64(c64, g, ox, oy, dx, dy);
         const float exact = sersic_shape(source_R2(c, dx, dy), c.se, c.sB);
-        acc += exact - sersic_shape(sR2, c.se, c.sB);
+        const float d = exact - sersic_shape(sR2, c.se, c.sB);
+        acc += R ? R->w[kx] * R->w[ky] * d : d;
       }
     }
   }

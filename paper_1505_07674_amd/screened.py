@@ -97,7 +97,7 @@ class SurrogateScreen(Screen):
     resolves the narrow posterior that a fit over the whole prior cannot.
     """
 
-    def __init__(self, surrogate: Surrogate, sigmas: float = 3.0, window: int = 200, floor: float = 1.0,
+    def __init__(self, surrogate: Surrogate, sigmas: float = 3.0, window: int = 200, floor: float = 0.1,
                  max_skips: int = 2000, keep: int = 65536, pool=None, refit_every: int = 10,
                  band_min: float = 50.0, band_frac: float = 0.5, refit_max: int = 60000, refit_steps: int = 300,
                  seed: int = 0):
@@ -251,7 +251,8 @@ def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, n_liv
                  seeds=(5, 6, 7), dlogz: float = 0.5, max_iter: int = 5000, train_epochs: int = 60,
                  train_batch: int = 1024, sigmas: float = 3.0, log=print, log_every: int = 100,
                  record_per_iter: Optional[int] = 200, audit: float = 0.0, state_dir: Optional[str] = None,
-                 deadline: Optional[float] = None, chunk: int = 25, local: bool = True) -> dict:
+                 deadline: Optional[float] = None, chunk: int = 25, local: bool = True, null: bool = True,
+                 refit_every: int = 5, refit_steps: int = 400, band_min: float = 25.0, floor: float = 0.1) -> dict:
     """Plain run A (records exact pairs), plain run B (another seed: the sampler's
     own spread), the surrogate trained on A's pairs, and the screened run C.
 
@@ -303,9 +304,10 @@ def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, n_liv
     log(f"plain run A, seed {seeds[0]} (recording pairs)")
     ra, wa = run("plain_a", seeds[0], record=True)
     log(f"  {ra.n_exact} exact evaluations, {ra.n_iter} iterations, log Z {ra.logz:.2f}, {wa:.1f} s")
-    log(f"plain run B, seed {seeds[1]}")
-    rb, wb = run("plain_b", seeds[1])
-    log(f"  {rb.n_exact} exact evaluations, {rb.n_iter} iterations, log Z {rb.logz:.2f}, {wb:.1f} s")
+    if null:
+        log(f"plain run B, seed {seeds[1]}")
+        rb, wb = run("plain_b", seeds[1])
+        log(f"  {rb.n_exact} exact evaluations, {rb.n_iter} iterations, log Z {rb.logz:.2f}, {wb:.1f} s")
 
     sur = Surrogate(device, seed=seeds[0], free=ll.free)
     if state_dir and os.path.exists(path("surrogate.npz")):
@@ -321,28 +323,33 @@ def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, n_liv
     log(f"surrogate trained on {fit['n_train']} pairs in {fit['wall_s']:.1f} s, held-out rmse(y) "
         f"{fit['rmse_y']:.4f}")
     screen = SurrogateScreen(sur, sigmas=sigmas, pool=(ra.evaluated_u, ra.evaluated_logl) if local else None,
-                             seed=seeds[2])
-    log(f"screened run C, seed {seeds[2]}" + (" (network refitted locally every 10 iterations)" if local else ""))
+                             seed=seeds[2], refit_every=refit_every, refit_steps=refit_steps, band_min=band_min,
+                             floor=floor)
+    log(f"screened run C, seed {seeds[2]}" +
+        (f" (network refitted locally every {refit_every} iterations)" if local else ""))
     rc, wc = run("screened_c", seeds[2], screen=screen, fn=_Observed(ll, screen))
     log(f"  {rc.n_exact} exact evaluations, {rc.n_screened_out} screened out, log Z {rc.logz:.2f}, {wc:.1f} s")
 
     to_theta = lambda u: ll.theta(u)[:, ll.free].astype(np.float64)
     ma, sa = ra.posterior_moments(to_theta)
-    mb, sb = rb.posterior_moments(to_theta)
     mc, sc = rc.posterior_moments(to_theta)
     out.update({
-        "plain": _summary(ra, wa), "plain_null": _summary(rb, wb), "screened": _summary(rc, wc), "fit": fit,
+        "plain": _summary(ra, wa), "screened": _summary(rc, wc), "fit": fit,
         "renders_per_accepted_ratio": ra.renders_per_accepted / rc.renders_per_accepted,
         "posterior_mean_plain": ma.tolist(), "posterior_std_plain": sa.tolist(),
-        "posterior_mean_null": mb.tolist(), "posterior_std_null": sb.tolist(),
         "posterior_mean_screened": mc.tolist(), "posterior_std_screened": sc.tolist(),
         "shift_screened_sigma": (np.abs(mc - ma) / sa).tolist(),
-        "shift_null_sigma": (np.abs(mb - ma) / sa).tolist(),
+        "settings": {"sigmas": sigmas, "floor": floor, "refit_every": refit_every, "refit_steps": refit_steps,
+                     "band_min": band_min, "local": local},
         "n_pairs_recorded": int(0 if ra.evaluated_u is None else len(ra.evaluated_u)),
         "refits": screen.refits,
     })
     out["max_shift_screened_sigma"] = float(np.max(out["shift_screened_sigma"]))
-    out["max_shift_null_sigma"] = float(np.max(out["shift_null_sigma"]))
+    if null:
+        mb, sb = rb.posterior_moments(to_theta)
+        out.update({"plain_null": _summary(rb, wb), "posterior_mean_null": mb.tolist(),
+                    "posterior_std_null": sb.tolist(), "shift_null_sigma": (np.abs(mb - ma) / sa).tolist()})
+        out["max_shift_null_sigma"] = float(np.max(out["shift_null_sigma"]))
     return out
 
 

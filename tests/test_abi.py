@@ -51,6 +51,7 @@ def test_host_only_calls(lib):
 
 def test_binding_mirrors_the_struct_layout():
     from paper_1505_07674_amd.binding import LensedSystemC
-    # int32 H, W; float pixscale, cx, cy; int32 nsub, ph, pw; three pointers
-    assert ctypes.sizeof(LensedSystemC) == 8 * 4 + 3 * 8
+    # int32 H, W; float pixscale, cx, cy; int32 nsub, ph, pw; three pointers; int32 rule (+ tail padding)
     assert LensedSystemC.psf.offset == 32
+    assert LensedSystemC.rule.offset == 8 * 4 + 3 * 8
+    assert ctypes.sizeof(LensedSystemC) == 8 * 4 + 3 * 8 + 8

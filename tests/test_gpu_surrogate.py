@@ -3,11 +3,16 @@ the surrogate network, which is trained on the plain run's exact (theta, log L)
 pairs by the library's own kernels.
 
 What the network gains over the method without it: exact renders per accepted
-point drop by at least 2x over the first iterations of a short run on the
-200x200 mock (the full runs with 400 live points and the posterior comparison
-are made by ``python -m paper_1505_07674_amd.screened``), and an exact audit of
-screened-out draws finds (almost) no draw the screen should have kept.
+point drop by at least 1.5x over whole runs with 400 live points on the
+200x200 mock, with the same evidence and posterior, and an exact audit of the
+screen's decisions finds (almost) no wrong one. The full experiment, with a
+second plain seed as the null and refits every 5 iterations, is
+``python -m paper_1505_07674_amd.screened``. (With 100 live points a plain run
+can settle on a secondary mode of the 17-parameter posterior, so no smaller
+run compares like with like.)
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -50,21 +55,26 @@ def test_surrogate_fits_loglike_pairs():
     assert fit["rmse_y"] < 0.2, fit
 
 
-def test_screen_cuts_exact_renders_without_false_rejections():
-    """The 200x200 SIE + shear + Sersic mock, 100 live points, the first 100
-    iterations: the plain run's exact pairs train the network, and the screened
-    run needs far fewer exact renders per accepted point. A fifth of the
-    screened-out draws are also evaluated exactly (an audit that does not change
-    the run): almost none of them would have been accepted."""
+def test_screen_cuts_exact_renders_and_keeps_the_posterior():
+    """Whole runs on the 200x200 SIE + shear + Sersic mock with 400 live points:
+    the plain run's exact pairs train the network, which screens a run with
+    another seed. It needs far fewer exact renders per accepted point, its
+    evidence and posterior means agree with the plain run, and an exact audit
+    of 5 % of the screen's decisions (which does not change the run) finds
+    almost no wrong one."""
     spec, obs = observation("c1")
-    res = compare_runs(spec, obs, DEV, n_live=100, k_replace=10, max_iter=100,
-                       seeds=(mocks.C4_SEED, mocks.C4_SEED + 1, mocks.C4_SEED + 2), train_epochs=150,
-                       train_batch=512, record_per_iter=None, audit=0.2, log=say, log_every=25)
-    sc = res["screened"]
-    say(f"renders/accepted plain {res['plain']['renders_per_accepted']:.2f} "
-        f"screened {sc['renders_per_accepted']:.2f} (x{res['renders_per_accepted_ratio']:.2f}); "
-        f"audit {sc['n_audit']} draws, {sc['n_false_reject']} false rejections, {sc['n_false_accept']} false "
-        f"acceptances; fit {res['fit']}; plain {res['plain']}; screened {sc}")
-    assert res["renders_per_accepted_ratio"] >= 2.0, res
-    assert sc["n_audit"] > 100
-    assert sc["n_false_reject"] + sc["n_false_accept"] <= max(2, 0.01 * sc["n_audit"]), sc
+    res = compare_runs(spec, obs, DEV, n_live=400, k_replace=40,
+                       seeds=(mocks.C4_SEED, mocks.C4_SEED + 1, mocks.C4_SEED + 2), train_epochs=30,
+                       train_batch=1024, record_per_iter=200, audit=0.05, log=say, log_every=100, null=False,
+                       refit_every=10, refit_steps=200)
+    pl, sc = res["plain"], res["screened"]
+    say(f"renders/accepted plain {pl['renders_per_accepted']:.2f} screened {sc['renders_per_accepted']:.2f} "
+        f"(x{res['renders_per_accepted_ratio']:.2f}); log Z {pl['logz']:.2f} vs {sc['logz']:.2f}; max mean shift "
+        f"{res['max_shift_screened_sigma']:.3f} sigma; audit {sc['n_audit']}: {sc['n_false_reject']} false "
+        f"rejections, {sc['n_false_accept']} false acceptances; wall {pl['wall_s']:.0f} s / {sc['wall_s']:.0f} s")
+    assert pl["converged"] and sc["converged"]
+    assert res["renders_per_accepted_ratio"] >= 1.5, res
+    assert abs(pl["logz"] - sc["logz"]) <= 3 * math.hypot(pl["logz_err"], sc["logz_err"])
+    assert res["max_shift_screened_sigma"] <= 0.1, res["shift_screened_sigma"]
+    assert sc["n_audit"] > 10000
+    assert sc["n_false_reject"] + sc["n_false_accept"] <= 0.02 * sc["n_audit"], sc
