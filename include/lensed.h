@@ -210,10 +210,11 @@ int lensed_mlp_train_step(lensed_ctx* ctx, float* params, float* m, float* v, in
  * without the captured graph and records a hipEvent between consecutive stages
  * on `stream`. lensed_stage_times waits for the recorded events and returns,
  * summed over the profiled calls since the previous query, the milliseconds of
- *   ms[0] prologue, ms[1] render, ms[2] PSF + chi^2, ms[3] finalize
+ *   ms[0] prologue, ms[1] render kernel, ms[2] float64 cusp corrections,
+ *   ms[3] PSF + chi^2, ms[4] finalize
  * (ms is a HOST array of at least LENSED_NSTAGES doubles; *calls, if not NULL,
  * receives the number of calls summed), then resets the sums. */
-#define LENSED_NSTAGES 4
+#define LENSED_NSTAGES 5
 int lensed_set_profiling(lensed_ctx* ctx, int enable);
 int lensed_stage_times(lensed_ctx* ctx, double* ms, int n, int* calls);
 

@@ -105,7 +105,7 @@ class Context:
             msg = lib().lensed_last_error(self._h)
             raise LensedError(rc, f"{what}: {msg.decode() if msg else ''}")
 
-    STAGES = ("prologue", "render", "psf_chi2", "finalize")
+    STAGES = ("prologue", "render", "cusp", "psf_chi2", "finalize")
 
     def set_profiling(self, enable: bool):
         """Run batched calls stage by stage with hipEvents between the stages (no graph)."""

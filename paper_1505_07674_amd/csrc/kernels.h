@@ -31,9 +31,10 @@ hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, Po
 // Unconvolved pixel luminosities into L (scratch or the caller's image): the
 // float32 render kernel, then the float64 cusp corrections of the pixels it
 // flagged. cl.entries needs one slot per render wave (n_blocks * 4); cl.count
-// must be zero when the render kernel starts (the prologue clears it).
+// must be zero when the render kernel starts (the prologue clears it). A
+// non-null `between` is recorded on the stream after the render kernel.
 hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L, int n_blocks,
-                         const CuspList& cl, hipStream_t stream);
+                         const CuspList& cl, hipStream_t stream, hipEvent_t between = nullptr);
 
 // Per-pixel integration error estimate of a Gauss-Kronrod rule for the single
 // point w.point0 of w.single (rule > 0): |Kronrod - embedded Gauss| x pixel weight.

@@ -62,7 +62,8 @@ class BatchPlan {
   // Runs the plan stage by stage twice on s and returns the second run's PSF + chi^2 milliseconds.
   hipError_t psf_ms(hipStream_t s, float* ms) const;
   hipError_t capture(hipStream_t cap);
-  // events, when given, are 5 events recorded around the 4 stages
+  // events, when given, are LENSED_NSTAGES + 1 events recorded around the stages
+  // (prologue, render kernel, cusp corrections, PSF + chi^2, finalize)
   // (prologue, render, PSF + chi^2, finalize)
   hipError_t enqueue(hipStream_t s, hipEvent_t* events = nullptr) const;
   hipError_t run(hipStream_t s) const;

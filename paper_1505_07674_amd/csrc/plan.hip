@@ -271,8 +271,10 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
   WorkArgs wr = w;
   wr.items = d_ritems_;
   wr.n_items = n_ritems_;
-  if ((e = launch_render(wr, d_pc_, d_p64_, d_L_, n_ritems_, cusp_, st)) != hipSuccess) return e;
-  if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+  if ((e = launch_render(wr, d_pc_, d_p64_, d_L_, n_ritems_, cusp_, st, ev ? ev[2] : nullptr)) != hipSuccess)
+    return e;
+  if (ev && n_ritems_ <= 0 && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
   WorkArgs wp = w;
   wp.items = d_pitems_;
   wp.n_items = n_pitems_;
@@ -280,9 +282,9 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
   if ((e = launch_psf(wp, d_L_, d_R_, d_part_, mode, n_pitems_, square_psf_, TW_, TH_, max_ph_, max_pw_, st)) !=
       hipSuccess)
     return e;
-  if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
-  if ((e = launch_finalize(d_part_, d_pbase_, d_ntiles_, n_points_, 0, logl_, st)) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[4], st)) != hipSuccess) return e;
+  if ((e = launch_finalize(d_part_, d_pbase_, d_ntiles_, n_points_, 0, logl_, st)) != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[5], st)) != hipSuccess) return e;
   if (grad_) {
     // g = A^T rho overwrites the unconvolved images, which are no longer needed
     const lensed_system& s0 = systems_[0];
@@ -309,13 +311,13 @@ hipError_t BatchPlan::capture(hipStream_t cap) {
 }
 
 hipError_t BatchPlan::psf_ms(hipStream_t s, float* ms) const {
-  hipEvent_t ev[5] = {};
+  hipEvent_t ev[LENSED_NSTAGES + 1] = {};
   hipError_t e = hipSuccess;
   for (auto& x : ev)
     if (e == hipSuccess) e = hipEventCreate(&x);
   for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) e = enqueue(s, ev);
-  if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
-  if (e == hipSuccess) e = hipEventElapsedTime(ms, ev[2], ev[3]);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[LENSED_NSTAGES]);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, ev[3], ev[4]);
   for (auto& x : ev)
     if (x) (void)hipEventDestroy(x);
   return e;

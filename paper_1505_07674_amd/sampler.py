@@ -177,7 +177,13 @@ class MultiEllipsoid:
 @dataclass
 class Screen:
     """Pre-screen of candidates: predict(u) returns a log L estimate; a candidate
-    is discarded when the estimate is below threshold - margin(threshold)."""
+    is discarded when the estimate is below threshold - margin(threshold).
+
+    A slice chain also takes a proposal as inside without an exact render when
+    the estimate clears threshold + margin_in(threshold) (margin(threshold) when
+    the screen has no margin_in). Only the discards can bias the run: a chain's
+    final point is always evaluated exactly, so a smaller margin_in trades
+    fewer renders along the chains against more final points that fail."""
     predict: Callable[[np.ndarray], np.ndarray]
     margin: Callable[[float], float]
     max_skips: int = 2000           # consecutive discards before an exact fallback batch
@@ -222,7 +228,7 @@ class NestedSampler:
                  candidates_per_call: int = 256, record: bool = False, audit: float = 0.0, audit_seed: int = 0,
                  multi: bool = True, record_per_iter: Optional[int] = None,
                  audit_loglike: Optional[LogLikeFn] = None, method: str = "auto", n_steps: Optional[int] = None,
-                 slice_switch: Optional[float] = None, probe_every: int = 20):
+                 slice_switch: Optional[float] = None, probe_every: int = 20, max_extend: int = 8):
         if not (1 <= k_replace < n_live):
             raise ValueError("need 1 <= k_replace < n_live")
         self.loglike = loglike
@@ -255,6 +261,9 @@ class NestedSampler:
         # budget of twice this guess of the slice cost (renders per replacement)
         self.slice_cost_guess = 1.0 / slice_switch if slice_switch is not None else 5.0 * self.n_steps
         self.probe_every = probe_every
+        # a slice chain whose final point fails its exact check takes up to this
+        # many extra slices before it is rerun without the screen
+        self.max_extend = max_extend
         # multi: bound the live points by a union of ellipsoids (else one ellipsoid)
         self.multi = multi
         self.split_rng = np.random.default_rng(seed + 1)
@@ -435,7 +444,8 @@ class NestedSampler:
         if screen is not None and len(todo) and st["skips"] < screen.max_skips:
             pred = np.asarray(screen.predict(c[todo]))
             dm = screen.margin(lmin)
-            sure_in, sure_out = pred > lmin + dm, pred < lmin - dm
+            dm_in = screen.margin_in(lmin) if hasattr(screen, "margin_in") else dm
+            sure_in, sure_out = pred > lmin + dm_in, pred < lmin - dm
             inside[todo[sure_in]] = True
             st["n_screened"] += int(sure_out.sum())
             st["n_trusted"] = st.get("n_trusted", 0) + int(sure_in.sum())
@@ -459,8 +469,10 @@ class NestedSampler:
         n_steps slices per chain, all chains advanced in lock-step so that every
         round is one batched evaluation. With a screen, proposals whose predicted
         log L clears the threshold by the margin are classified without an exact
-        render; every final point is evaluated exactly, and a chain whose final
-        point fails is rerun without the screen."""
+        render. Every final point is evaluated exactly; a chain whose final point
+        fails takes one more slice and is checked again (at most max_extend
+        times), and a chain that still fails, or whose slice shrinks to nothing,
+        is rerun without the screen."""
         st = self.state
         live = st["live_u"]
         keep = np.nonzero(st["live_logl"] > lmin)[0]
@@ -490,8 +502,26 @@ class NestedSampler:
             phase[pending] = 0
             nout = np.zeros(B, dtype=int)
             nshrink = np.zeros(B, dtype=int)
+            nextend = np.zeros(B, dtype=int)
             failed = np.zeros(B, dtype=bool)
+            check = np.zeros(B, dtype=bool)          # finished, final point only screened
             while True:
+                chk = np.nonzero(check)[0]
+                if len(chk):
+                    # exact check of final points the screen took as inside
+                    check[chk] = False
+                    xl[chk] = self._exact(x[chk])
+                    for i in chk[~(xl[chk] > lmin)]:
+                        nextend[i] += 1
+                        if nextend[i] > self.max_extend:
+                            failed[i] = True
+                            continue
+                        xl[i] = np.nan               # x lies outside: take one more slice from it
+                        steps[i] = self.n_steps - 1
+                        v[i] = new_dir(np.array([i]))[0]
+                        lo[i] = -self.rng.random()
+                        hi[i] = lo[i] + 1.0
+                        phase[i], nout[i], nshrink[i] = 0, 0, 0
                 act = np.nonzero(phase < 3)[0]
                 if len(act) == 0:
                     break
@@ -519,6 +549,7 @@ class NestedSampler:
                             steps[i] += 1
                             if steps[i] >= self.n_steps:
                                 phase[i] = 3
+                                check[i] = bool(np.isnan(xl[i]))
                             else:
                                 v[i] = new_dir(np.array([i]))[0]
                                 lo[i] = -self.rng.random()
@@ -534,9 +565,6 @@ class NestedSampler:
                                 failed[i], phase[i] = True, 3
             # every replacement carries an exact log L above the threshold
             done = pending[~failed[pending]]
-            need = done[np.isnan(xl[done])]
-            if len(need):
-                xl[need] = self._exact(x[need])
             ok = done[xl[done] > lmin]
             out_u[ok], out_l[ok] = x[ok], xl[ok]
             self._audit(lmin)

@@ -15,11 +15,12 @@ calibration pairs whose exact log L is nearest L_min. The run's own residuals
 are kept for the most recent ``keep`` evaluations: the threshold only rises, so
 older pairs lie below it.
 
-``compare_runs`` is the end-to-end experiment: a plain run that records every
-exact (theta, log L) pair, a second plain run with another seed (the null
-spread of the sampler itself), the surrogate trained on the first run's pairs,
-and a screened run; it reports exact renders per accepted point and the
-posterior mean shifts in units of the plain posterior standard deviation.
+``ScreenExperiment`` (and ``compare_runs``, all of it in one call) is the
+end-to-end experiment: a plain run that records every exact (theta, log L)
+pair, a second plain run with another seed (the null spread of the sampler
+itself), the surrogate trained on the first run's pairs, and a screened run; it
+reports exact renders per accepted point and the posterior mean shifts in units
+of the plain posterior standard deviation.
 """
 from __future__ import annotations
 
@@ -88,6 +89,18 @@ class SurrogateScreen(Screen):
     The margin at a threshold L_min is ``sigmas`` x the RMS residual (prediction
     minus exact log L) of the calibration pairs whose exact log L is nearest
     L_min: the network's held-out pairs plus this run's own exact evaluations.
+    A draw predicted below L_min - margin is discarded. A slice proposal
+    predicted above L_min + ``trust_sigmas`` x that RMS counts as inside without
+    an exact render (the chain's final point is always rendered).
+
+    With ``quantile`` q the margins come from the tails instead: the residuals
+    are heavy-tailed and skewed (the network over-predicts more often than it
+    under-predicts), so the discard margin is ``safety`` x the q-quantile of
+    (exact - prediction) and the inside margin ``safety`` x the q-quantile of
+    (prediction - exact), over the ``quantile_window`` held-out pairs centred
+    on L_min in log L order. Only held-out pairs enter: the run's own exact evaluations exclude
+    the draws the screen discarded and would understate the under-prediction
+    tail.
 
     With ``pool`` (the (u, log L) pairs of an earlier run of the same problem)
     the network is refitted every ``refit_every`` iterations on the pairs of the
@@ -100,9 +113,12 @@ class SurrogateScreen(Screen):
     def __init__(self, surrogate: Surrogate, sigmas: float = 3.0, window: int = 200, floor: float = 0.1,
                  max_skips: int = 2000, keep: int = 65536, pool=None, refit_every: int = 10,
                  band_min: float = 50.0, band_frac: float = 0.5, refit_max: int = 60000, refit_steps: int = 300,
-                 seed: int = 0):
+                 seed: int = 0, trust_sigmas: Optional[float] = None, quantile: Optional[float] = None,
+                 safety: float = 1.25, quantile_window: int = 1000):
         self.surrogate = surrogate
         self.sigmas = sigmas
+        self.trust_sigmas = sigmas if trust_sigmas is None else trust_sigmas
+        self.quantile, self.safety, self.quantile_window = quantile, safety, quantile_window
         self.window = window
         self.floor = floor
         self.max_skips = max_skips
@@ -192,7 +208,7 @@ class SurrogateScreen(Screen):
         self.rng.bit_generator.state = d["rng"]
         self._sorted = None
 
-    def margin(self, lmin: float) -> float:
+    def _rms(self, lmin: float) -> float:
         if self._sorted is None:
             ll = np.concatenate([self.held_l, self.run_l])
             order = np.argsort(ll)
@@ -201,7 +217,27 @@ class SurrogateScreen(Screen):
         i = int(np.searchsorted(ll, lmin))
         lo, hi = max(0, i - self.window // 2), min(len(ll), i + self.window // 2)
         w = res[lo:hi] if hi > lo else res
-        return max(self.sigmas * float(np.sqrt(np.mean(w * w))), self.floor)
+        return float(np.sqrt(np.mean(w * w)))
+
+    def _tail(self, lmin: float, sign: float) -> float:
+        ll, res = self.held_l, self.held_r          # sorted by exact log L
+        i = int(np.searchsorted(ll, lmin))
+        h = self.quantile_window // 2
+        lo, hi = max(0, i - h), min(len(ll), i + h)
+        if hi - lo < self.quantile_window:           # near an end of the table: take the window whole
+            lo, hi = max(0, hi - self.quantile_window), min(len(ll), lo + self.quantile_window)
+        w = sign * res[lo:hi]
+        return self.safety * float(np.quantile(w, self.quantile)) if len(w) else np.inf
+
+    def margin(self, lmin: float) -> float:
+        if self.quantile is not None:
+            return max(self._tail(lmin, -1.0), self.floor)
+        return max(self.sigmas * self._rms(lmin), self.floor)
+
+    def margin_in(self, lmin: float) -> float:
+        if self.quantile is not None:
+            return max(self._tail(lmin, 1.0), self.floor)
+        return max(self.trust_sigmas * self._rms(lmin), self.floor)
 
 
 class _Observed:
@@ -247,37 +283,53 @@ def _load_result(path: str):
         return NSResult(**kw), float(z["wall"])
 
 
-def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, n_live: int = 400, k_replace: int = 40,
-                 seeds=(5, 6, 7), dlogz: float = 0.5, max_iter: int = 5000, train_epochs: int = 60,
-                 train_batch: int = 1024, sigmas: float = 3.0, log=print, log_every: int = 100,
-                 record_per_iter: Optional[int] = 200, audit: float = 0.0, state_dir: Optional[str] = None,
-                 deadline: Optional[float] = None, chunk: int = 25, local: bool = True, null: bool = True,
-                 refit_every: int = 5, refit_steps: int = 400, band_min: float = 25.0, floor: float = 0.1) -> dict:
+class ScreenExperiment:
     """Plain run A (records exact pairs), plain run B (another seed: the sampler's
-    own spread), the surrogate trained on A's pairs, and the screened run C.
+    own spread), the surrogate trained on A's pairs, and the screened run C, each
+    computed on first use and kept.
 
     With ``state_dir`` every finished run is saved there and reused by a later
     call, and a run still going at ``deadline`` (time.monotonic()) is
     checkpointed there and Suspended is raised; calling again resumes it."""
-    import os
-    ll = GpuLogLike(spec, obs, device)
-    ndim = len(ll.free)
-    out = {"system": spec.name, "n_live": n_live, "k_replace": k_replace, "ndim": ndim, "free": ll.free.tolist(),
-           "audit_fraction": audit}
 
-    def path(name):
-        return os.path.join(state_dir, name) if state_dir else None
+    def __init__(self, spec: SystemSpec, obs: Observation, device: torch.device, n_live: int = 400,
+                 k_replace: int = 40, seeds=(5, 6, 7), dlogz: float = 0.5, max_iter: int = 5000,
+                 train_epochs: int = 60, train_batch: int = 1024, sigmas: float = 3.0, log=print,
+                 log_every: int = 100, record_per_iter: Optional[int] = 200, audit: float = 0.0,
+                 state_dir: Optional[str] = None, deadline: Optional[float] = None, chunk: int = 25,
+                 local: bool = True, refit_every: int = 5, refit_steps: int = 400, band_min: float = 25.0,
+                 floor: float = 0.1, trust_sigmas: float = 3.0, quantile: Optional[float] = None,
+                 safety: float = 1.25):
+        self.spec, self.obs, self.device = spec, obs, device
+        self.n_live, self.k_replace, self.seeds, self.dlogz, self.max_iter = n_live, k_replace, seeds, dlogz, max_iter
+        self.train_epochs, self.train_batch = train_epochs, train_batch
+        self.sigmas, self.trust_sigmas, self.floor = sigmas, trust_sigmas, floor
+        self.quantile, self.safety = quantile, safety
+        self.log, self.log_every, self.record_per_iter, self.audit = log, log_every, record_per_iter, audit
+        self.state_dir, self.deadline, self.chunk = state_dir, deadline, chunk
+        self.local, self.refit_every, self.refit_steps, self.band_min = local, refit_every, refit_steps, band_min
+        self.ll = GpuLogLike(spec, obs, device)
+        self.ndim = len(self.ll.free)
+        self._runs: Dict[str, tuple] = {}
+        self._sur = None
+        self._screen = None
 
-    def run(name, seed, screen=None, record=False, fn=None):
-        if state_dir and os.path.exists(path(name + ".npz")):
-            log(f"{name}: loaded from {path(name + '.npz')}")
-            return _load_result(path(name + ".npz"))
-        s = NestedSampler(fn or ll, ndim, n_live=n_live, k_replace=k_replace, dlogz=dlogz, seed=seed,
-                          max_iter=max_iter, record=record, record_per_iter=record_per_iter,
-                          audit=audit if screen is not None else 0.0, audit_seed=seed, audit_loglike=ll)
+    def _path(self, name):
+        import os
+        return os.path.join(self.state_dir, name) if self.state_dir else None
+
+    def _run(self, name, seed, screen=None, record=False, fn=None):
+        import os
+        sd, log = self.state_dir, self.log
+        if sd and os.path.exists(self._path(name + ".npz")):
+            log(f"{name}: loaded from {self._path(name + '.npz')}")
+            return _load_result(self._path(name + ".npz"))
+        s = NestedSampler(fn or self.ll, self.ndim, n_live=self.n_live, k_replace=self.k_replace, dlogz=self.dlogz,
+                          seed=seed, max_iter=self.max_iter, record=record, record_per_iter=self.record_per_iter,
+                          audit=self.audit if screen is not None else 0.0, audit_seed=seed, audit_loglike=self.ll)
         wall0 = 0.0
-        if state_dir and os.path.exists(path(name + ".ckpt")):
-            with open(path(name + ".ckpt"), "rb") as f:
+        if sd and os.path.exists(self._path(name + ".ckpt")):
+            with open(self._path(name + ".ckpt"), "rb") as f:
                 s.restore(f.read())
             wall0 = s.state.get("wall", 0.0)
             if isinstance(screen, SurrogateScreen) and "screen_run" in s.state:
@@ -285,72 +337,114 @@ def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, n_liv
             log(f"{name}: resumed at iteration {s.state['it']}")
         t0 = time.perf_counter()
         while True:
-            r = s.run(screen=screen, max_iter=chunk, log=log, log_every=log_every)
-            if r.converged or r.n_iter >= max_iter:
+            r = s.run(screen=screen, max_iter=self.chunk, log=log, log_every=self.log_every)
+            if r.converged or r.n_iter >= self.max_iter:
                 break
-            if deadline is not None and time.monotonic() > deadline:
-                if state_dir:
+            if self.deadline is not None and time.monotonic() > self.deadline:
+                if sd:
                     s.state["wall"] = wall0 + time.perf_counter() - t0
                     if isinstance(screen, SurrogateScreen):
                         s.state["screen_run"] = screen.get_state()
-                    with open(path(name + ".ckpt"), "wb") as f:
+                    with open(self._path(name + ".ckpt"), "wb") as f:
                         f.write(s.checkpoint())
                 raise Suspended(f"{name} suspended at iteration {r.n_iter}")
         wall = wall0 + time.perf_counter() - t0
-        if state_dir:
-            _save_result(path(name + ".npz"), r, wall)
+        if sd:
+            _save_result(self._path(name + ".npz"), r, wall)
         return r, wall
 
-    log(f"plain run A, seed {seeds[0]} (recording pairs)")
-    ra, wa = run("plain_a", seeds[0], record=True)
-    log(f"  {ra.n_exact} exact evaluations, {ra.n_iter} iterations, log Z {ra.logz:.2f}, {wa:.1f} s")
-    if null:
-        log(f"plain run B, seed {seeds[1]}")
-        rb, wb = run("plain_b", seeds[1])
-        log(f"  {rb.n_exact} exact evaluations, {rb.n_iter} iterations, log Z {rb.logz:.2f}, {wb:.1f} s")
+    def plain(self):
+        """Run A, which records the exact pairs: (NSResult, wall seconds)."""
+        if "a" not in self._runs:
+            self.log(f"plain run A, seed {self.seeds[0]} (recording pairs)")
+            ra, wa = self._runs["a"] = self._run("plain_a", self.seeds[0], record=True)
+            self.log(f"  {ra.n_exact} exact evaluations, {ra.n_iter} iterations, log Z {ra.logz:.2f}, {wa:.1f} s")
+        return self._runs["a"]
 
-    sur = Surrogate(device, seed=seeds[0], free=ll.free)
-    if state_dir and os.path.exists(path("surrogate.npz")):
-        fit = sur.load(path("surrogate.npz"))
-        log("surrogate: loaded")
-    else:
-        t0 = time.perf_counter()
-        fit = sur.fit(ra.evaluated_u, ra.evaluated_logl, epochs=train_epochs, batch=train_batch)
-        torch.cuda.synchronize(device)
-        fit["wall_s"] = time.perf_counter() - t0
-        if state_dir:
-            sur.save(path("surrogate.npz"), fit)
-    log(f"surrogate trained on {fit['n_train']} pairs in {fit['wall_s']:.1f} s, held-out rmse(y) "
-        f"{fit['rmse_y']:.4f}")
-    screen = SurrogateScreen(sur, sigmas=sigmas, pool=(ra.evaluated_u, ra.evaluated_logl) if local else None,
-                             seed=seeds[2], refit_every=refit_every, refit_steps=refit_steps, band_min=band_min,
-                             floor=floor)
-    log(f"screened run C, seed {seeds[2]}" +
-        (f" (network refitted locally every {refit_every} iterations)" if local else ""))
-    rc, wc = run("screened_c", seeds[2], screen=screen, fn=_Observed(ll, screen))
-    log(f"  {rc.n_exact} exact evaluations, {rc.n_screened_out} screened out, log Z {rc.logz:.2f}, {wc:.1f} s")
+    def null(self):
+        """Run B, another seed."""
+        if "b" not in self._runs:
+            self.log(f"plain run B, seed {self.seeds[1]}")
+            rb, wb = self._runs["b"] = self._run("plain_b", self.seeds[1])
+            self.log(f"  {rb.n_exact} exact evaluations, {rb.n_iter} iterations, log Z {rb.logz:.2f}, {wb:.1f} s")
+        return self._runs["b"]
 
-    to_theta = lambda u: ll.theta(u)[:, ll.free].astype(np.float64)
-    ma, sa = ra.posterior_moments(to_theta)
-    mc, sc = rc.posterior_moments(to_theta)
-    out.update({
-        "plain": _summary(ra, wa), "screened": _summary(rc, wc), "fit": fit,
-        "renders_per_accepted_ratio": ra.renders_per_accepted / rc.renders_per_accepted,
-        "posterior_mean_plain": ma.tolist(), "posterior_std_plain": sa.tolist(),
-        "posterior_mean_screened": mc.tolist(), "posterior_std_screened": sc.tolist(),
-        "shift_screened_sigma": (np.abs(mc - ma) / sa).tolist(),
-        "settings": {"sigmas": sigmas, "floor": floor, "refit_every": refit_every, "refit_steps": refit_steps,
-                     "band_min": band_min, "local": local},
-        "n_pairs_recorded": int(0 if ra.evaluated_u is None else len(ra.evaluated_u)),
-        "refits": screen.refits,
-    })
-    out["max_shift_screened_sigma"] = float(np.max(out["shift_screened_sigma"]))
-    if null:
-        mb, sb = rb.posterior_moments(to_theta)
-        out.update({"plain_null": _summary(rb, wb), "posterior_mean_null": mb.tolist(),
-                    "posterior_std_null": sb.tolist(), "shift_null_sigma": (np.abs(mb - ma) / sa).tolist()})
-        out["max_shift_null_sigma"] = float(np.max(out["shift_null_sigma"]))
-    return out
+    def surrogate(self):
+        """The network fitted on run A's pairs: (Surrogate, fit summary)."""
+        import os
+        if self._sur is None:
+            ra, _ = self.plain()
+            sur = Surrogate(self.device, seed=self.seeds[0], free=self.ll.free)
+            if self.state_dir and os.path.exists(self._path("surrogate.npz")):
+                fit = sur.load(self._path("surrogate.npz"))
+                self.log("surrogate: loaded")
+            else:
+                t0 = time.perf_counter()
+                fit = sur.fit(ra.evaluated_u, ra.evaluated_logl, epochs=self.train_epochs, batch=self.train_batch)
+                torch.cuda.synchronize(self.device)
+                fit["wall_s"] = time.perf_counter() - t0
+                if self.state_dir:
+                    sur.save(self._path("surrogate.npz"), fit)
+            self.log(f"surrogate trained on {fit['n_train']} pairs in {fit['wall_s']:.1f} s, held-out rmse(y) "
+                     f"{fit['rmse_y']:.4f}")
+            self._sur = (sur, fit)
+        return self._sur
+
+    def screened(self):
+        """Run C, screened by the network (refitted locally when ``local``)."""
+        if "c" not in self._runs:
+            ra, _ = self.plain()
+            sur, _ = self.surrogate()
+            self._screen = SurrogateScreen(
+                sur, sigmas=self.sigmas, pool=(ra.evaluated_u, ra.evaluated_logl) if self.local else None,
+                seed=self.seeds[2], refit_every=self.refit_every, refit_steps=self.refit_steps,
+                band_min=self.band_min, floor=self.floor, trust_sigmas=self.trust_sigmas, quantile=self.quantile,
+                safety=self.safety)
+            self.log(f"screened run C, seed {self.seeds[2]}" +
+                     (f" (network refitted locally every {self.refit_every} iterations)" if self.local else ""))
+            rc, wc = self._runs["c"] = self._run("screened_c", self.seeds[2], screen=self._screen,
+                                                 fn=_Observed(self.ll, self._screen))
+            self.log(f"  {rc.n_exact} exact evaluations, {rc.n_screened_out} screened out, log Z {rc.logz:.2f}, "
+                     f"{wc:.1f} s")
+        return self._runs["c"]
+
+    def summary(self, null: bool = True) -> dict:
+        """Every stage (run on first use) and the comparison: renders per accepted
+        point, evidences, posterior means and their shifts in plain-run sigmas."""
+        ra, wa = self.plain()
+        if null:
+            rb, wb = self.null()
+        _, fit = self.surrogate()
+        rc, wc = self.screened()
+        ll = self.ll
+        to_theta = lambda u: ll.theta(u)[:, ll.free].astype(np.float64)
+        ma, sa = ra.posterior_moments(to_theta)
+        mc, sc = rc.posterior_moments(to_theta)
+        out = {"system": self.spec.name, "n_live": self.n_live, "k_replace": self.k_replace, "ndim": self.ndim,
+               "free": ll.free.tolist(), "audit_fraction": self.audit,
+               "plain": _summary(ra, wa), "screened": _summary(rc, wc), "fit": fit,
+               "renders_per_accepted_ratio": ra.renders_per_accepted / rc.renders_per_accepted,
+               "posterior_mean_plain": ma.tolist(), "posterior_std_plain": sa.tolist(),
+               "posterior_mean_screened": mc.tolist(), "posterior_std_screened": sc.tolist(),
+               "shift_screened_sigma": (np.abs(mc - ma) / sa).tolist(),
+               "settings": {"sigmas": self.sigmas, "trust_sigmas": self.trust_sigmas, "quantile": self.quantile,
+                            "safety": self.safety, "floor": self.floor,
+                            "refit_every": self.refit_every, "refit_steps": self.refit_steps,
+                            "band_min": self.band_min, "local": self.local},
+               "n_pairs_recorded": int(0 if ra.evaluated_u is None else len(ra.evaluated_u)),
+               "refits": self._screen.refits if self._screen is not None else []}
+        out["max_shift_screened_sigma"] = float(np.max(out["shift_screened_sigma"]))
+        if null:
+            mb, sb = rb.posterior_moments(to_theta)
+            out.update({"plain_null": _summary(rb, wb), "posterior_mean_null": mb.tolist(),
+                        "posterior_std_null": sb.tolist(), "shift_null_sigma": (np.abs(mb - ma) / sa).tolist()})
+            out["max_shift_null_sigma"] = float(np.max(out["shift_null_sigma"]))
+        return out
+
+
+def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, null: bool = True, **settings) -> dict:
+    """The whole experiment in one call (ScreenExperiment's settings as keywords)."""
+    return ScreenExperiment(spec, obs, device, **settings).summary(null=null)
 
 
 def library_mock(spec: SystemSpec, device: torch.device) -> Observation:
@@ -376,6 +470,13 @@ def main(argv=None) -> int:
     ap.add_argument("--k-replace", type=int, default=40)
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--sigmas", type=float, default=3.0)
+    ap.add_argument("--quantile", type=float, default=None,
+                    help="margins from this quantile of the held-out residual tails (else sigmas x RMS)")
+    ap.add_argument("--safety", type=float, default=1.25, help="factor on the quantile margins")
+    ap.add_argument("--trust-sigmas", type=float, default=3.0,
+                    help="slice proposals predicted this many residual RMS above the threshold skip the render")
+    ap.add_argument("--refit-every", type=int, default=5)
+    ap.add_argument("--refit-steps", type=int, default=400)
     ap.add_argument("--max-iter", type=int, default=5000)
     ap.add_argument("--audit", type=float, default=0.0, help="fraction of screened-out draws also evaluated exactly")
     ap.add_argument("--state-dir", default=None, help="save finished runs and checkpoints here; resume from it")
@@ -396,7 +497,9 @@ def main(argv=None) -> int:
         res = compare_runs(spec, obs, dev, n_live=a.n_live, k_replace=a.k_replace, train_epochs=a.epochs,
                            sigmas=a.sigmas, max_iter=a.max_iter, seeds=(mocks.C4_SEED, mocks.C4_SEED + 1,
                                                                         mocks.C4_SEED + 2), log=log,
-                           audit=a.audit, state_dir=a.state_dir, deadline=deadline)
+                           audit=a.audit, state_dir=a.state_dir, deadline=deadline, trust_sigmas=a.trust_sigmas,
+                           refit_every=a.refit_every, refit_steps=a.refit_steps, quantile=a.quantile,
+                           safety=a.safety)
     except Suspended as e:
         print(f"suspended: {e}", flush=True)
         return 3

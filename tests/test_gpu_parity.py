@@ -109,6 +109,30 @@ def test_c1_loglike_batch_parity_full_launch():
     assert np.all(err <= tol), f"worst relative {np.max(err / tol) * 1e-6:.3e}"
 
 
+def test_profiled_stages_give_the_graph_result():
+    """With profiling on, the batch runs stage by stage between hipEvents instead
+    of as the captured graph: the same kernels, so the same log L bit for bit,
+    and five stage times per call."""
+    spec, obs = observation("c1")
+    say("c1 loglike batch, 512 points, graph vs profiled stages")
+    pts = torch.from_numpy(mocks.points(spec, 512, seed=mocks.C1_POINT_SEED + 5)).to(DEV)
+    gsys = gpu_system(spec, obs)
+    sop = np.zeros(512, np.int32)
+    ctx = lensed.Context(0)
+    a = lensed.loglike_batch(pts, sop, [gsys], ctx=ctx).cpu().numpy()
+    ctx.set_profiling(True)
+    ctx.stage_times()
+    b = lensed.loglike_batch(pts, sop, [gsys], ctx=ctx).cpu().numpy()
+    b2 = lensed.loglike_batch(pts, sop, [gsys], ctx=ctx).cpu().numpy()
+    stages, calls = ctx.stage_times()
+    ctx.set_profiling(False)
+    assert np.array_equal(a, b) and np.array_equal(a, b2)
+    assert calls == 2 and tuple(stages) == lensed.Context.STAGES
+    assert all(v >= 0.0 for v in stages.values()) and stages["render"] > 0.0 and stages["psf_chi2"] > 0.0
+    c = lensed.loglike_batch(pts, sop, [gsys], ctx=ctx).cpu().numpy()
+    assert np.array_equal(a, c)
+
+
 def test_c1_plain_matches_oracle():
     spec, obs = observation("c1")
     say("c1 plain loglike")

@@ -9,7 +9,8 @@ screen's decisions finds (almost) no wrong one. The full experiment, with a
 second plain seed as the null and refits every 5 iterations, is
 ``python -m paper_1505_07674_amd.screened``. (With 100 live points a plain run
 can settle on a secondary mode of the 17-parameter posterior, so no smaller
-run compares like with like.)
+run compares like with like.) The stages run in three tests that share one
+experiment, so that none of them runs for minutes without reporting.
 """
 import math
 
@@ -18,7 +19,7 @@ import pytest
 import torch
 
 from paper_1505_07674_amd import mocks
-from paper_1505_07674_amd.screened import GpuLogLike, compare_runs
+from paper_1505_07674_amd.screened import GpuLogLike, ScreenExperiment
 from paper_1505_07674_amd.surrogate import Surrogate
 
 from helpers import observation
@@ -55,18 +56,36 @@ def test_surrogate_fits_loglike_pairs():
     assert fit["rmse_y"] < 0.2, fit
 
 
-def test_screen_cuts_exact_renders_and_keeps_the_posterior():
+@pytest.fixture(scope="module")
+def experiment():
     """Whole runs on the 200x200 SIE + shear + Sersic mock with 400 live points:
     the plain run's exact pairs train the network, which screens a run with
-    another seed. It needs far fewer exact renders per accepted point, its
-    evidence and posterior means agree with the plain run, and an exact audit
-    of 5 % of the screen's decisions (which does not change the run) finds
-    almost no wrong one."""
+    another seed; 5 % of the screen's decisions are audited exactly (which does
+    not change the run)."""
     spec, obs = observation("c1")
-    res = compare_runs(spec, obs, DEV, n_live=400, k_replace=40,
-                       seeds=(mocks.C4_SEED, mocks.C4_SEED + 1, mocks.C4_SEED + 2), train_epochs=30,
-                       train_batch=1024, record_per_iter=200, audit=0.05, log=say, log_every=100, null=False,
-                       refit_every=10, refit_steps=200)
+    return ScreenExperiment(spec, obs, DEV, n_live=400, k_replace=40,
+                            seeds=(mocks.C4_SEED, mocks.C4_SEED + 1, mocks.C4_SEED + 2), train_epochs=30,
+                            train_batch=1024, record_per_iter=200, audit=0.05, log=say, log_every=100,
+                            refit_every=10, refit_steps=200)
+
+
+def test_plain_run_records_its_pairs(experiment):
+    ra, wall = experiment.plain()
+    say(f"plain: {ra.n_exact} exact, {ra.n_iter} iterations, log Z {ra.logz:.2f} +- {ra.logz_err:.2f}, {wall:.0f} s")
+    assert ra.converged
+    assert len(ra.evaluated_u) > 50000 and np.all(np.isfinite(ra.evaluated_logl))
+    # the truth sits inside the plain posterior
+    assert ra.logl.max() > -6000.0
+
+
+def test_surrogate_fits_the_run_pairs(experiment):
+    _, fit = experiment.surrogate()
+    say(f"surrogate: {fit}")
+    assert fit["rmse_y"] < 0.6, fit
+
+
+def test_screen_cuts_exact_renders_and_keeps_the_posterior(experiment):
+    res = experiment.summary(null=False)
     pl, sc = res["plain"], res["screened"]
     say(f"renders/accepted plain {pl['renders_per_accepted']:.2f} screened {sc['renders_per_accepted']:.2f} "
         f"(x{res['renders_per_accepted_ratio']:.2f}); log Z {pl['logz']:.2f} vs {sc['logz']:.2f}; max mean shift "

@@ -37,3 +37,30 @@ def test_fixed_parameters_enter_the_network_as_zero():
     assert x.shape == (1, 17)
     assert np.all(x[0, [i for i in range(17) if i not in (1, 4)]] == 0)
     assert np.allclose(x[0, [1, 4]], [-0.5, 0.5])       # unit cube onto [-1, 1]
+
+
+def test_quantile_margins_read_the_held_out_tails():
+    """The screen's quantile margins: safety x the q-quantile of the one-sided
+    residuals over the window of held-out pairs centred on the threshold in
+    log L order (clipped at the ends of the table), asymmetric when the residuals are skewed, and blind to the
+    run's own (screen-filtered) evaluations."""
+    from paper_1505_07674_amd.screened import SurrogateScreen
+    rng = np.random.default_rng(4)
+    ll = np.sort(rng.uniform(-1000.0, 0.0, 5000))
+    res = np.where(rng.random(5000) < 0.8, rng.normal(0.0, 1.0, 5000), rng.exponential(10.0, 5000))  # over-predicts
+    sur = Surrogate(torch.device("cpu"), seed=0)
+    sur.margin_table = (ll, res)
+    scr = SurrogateScreen(sur, quantile=0.99, safety=1.5, quantile_window=400, floor=0.01)
+    for lmin in (-1200.0, -640.0, -3.0, 50.0):
+        lo = min(max(int(np.searchsorted(ll, lmin)) - 200, 0), len(ll) - 400)   # 400 pairs centred on lmin
+        w = res[lo:lo + 400]
+        assert np.isclose(scr.margin(lmin), max(1.5 * np.quantile(-w, 0.99), 0.01))
+        assert np.isclose(scr.margin_in(lmin), max(1.5 * np.quantile(w, 0.99), 0.01))
+    assert scr.margin_in(-500.0) > 3 * scr.margin(-500.0)          # the over-prediction tail is longer
+    scr.observe = None                                             # run residuals never enter the quantiles
+    scr.run_l, scr.run_r = np.array([-500.0]), np.array([-1e6])
+    assert scr.margin(-500.0) < 10.0
+    rms = SurrogateScreen(sur, sigmas=3.0, window=400)
+    i = np.searchsorted(ll, -500.0)
+    w = res[i - 200:i + 200]
+    assert np.isclose(rms.margin(-500.0), 3.0 * np.sqrt(np.mean(w * w)))
