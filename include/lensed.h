@@ -11,13 +11,15 @@
  *          2 phi_L      SIE position angle (rad, counter-clockwise from +x to the major axis)
  *          3 gamma      external shear magnitude
  *          4 phi_gamma  external shear angle (rad): gamma_1 = gamma cos 2phi, gamma_2 = gamma sin 2phi
- *          5 I_H        lens-light Sersic surface brightness at R_H
+ *          5 I_H        lens-light Sersic surface brightness at R_H (or its total
+ *                       magnitude, when the system's amplitude is LENSED_AMP_MAGNITUDE)
  *          6 R_H        lens-light half-light radius (geometric mean of the semi-axes), > 0
  *          7 n_H        lens-light Sersic index, [0.2, 10]
  *          8 q_H        lens-light axis ratio, (0, 1]
  *          9 phi_H      lens-light position angle
  *         10 x_S, 11 y_S  source centre (arcsec)
  *         12 I_S, 13 R_S, 14 n_S, 15 q_S, 16 phi_S   source Sersic, as for the lens light
+ *                       (I_S likewise a total magnitude in magnitude mode)
  *   Lens equation beta = x - alpha_SIE(x) - alpha_shear(x)        (Sec. 2.1, Eq. 1)
  *   I(x) = I_lens(x) + I_source(beta)                             (Sec. 2.1, Eq. 2)
  *   Sersic I = I_e exp(-b_n [(R/R_e)^{1/n} - 1]), R = sqrt(q x'^2 + y'^2/q)
@@ -70,7 +72,8 @@ enum {
 typedef struct lensed_ctx lensed_ctx;
 
 /* One observation (Sec. 3, step i): data d_i, weights w_i = 1/s_i^2 (0 = masked,
- * Sec. 3.2), PSF array, grid geometry and integration rule. */
+ * Sec. 3.2), PSF array, grid geometry, integration rule and the meaning of the
+ * two Sersic amplitude parameters and of the source position. */
 typedef struct {
   int32_t height, width;      /* pixels, > 0                                    */
   float pixscale;             /* arcsec per pixel, > 0                          */
@@ -84,12 +87,30 @@ typedef struct {
                                  LENSED_RULE_MIDPOINT (nsub x nsub "subN"), or the
                                  Cartesian square of a Gauss-Kronrod rule
                                  LENSED_RULE_G3K7 / _G5K11 / _G7K15 (nsub ignored) */
+  int32_t amplitude;          /* theta[5] and theta[12] (Sec. 4.1):
+                                 LENSED_AMP_INTENSITY: I_e, the surface brightness
+                                 at R_e; LENSED_AMP_MAGNITUDE: the component's total
+                                 magnitude m, with I_e set so that its total flux is
+                                 10^(-0.4 (m - zero_point)) in data units x arcsec^2 */
+  float zero_point;           /* magnitude of unit total flux (finite)          */
+  int32_t source_position;    /* theta[10], theta[11] (Sec. 5):
+                                 LENSED_SOURCE_PLANE: the source centre;
+                                 LENSED_IMAGE_PLANE: a point x_I of the image plane,
+                                 the source centre being its image under the lens
+                                 equation, beta = x_I - alpha(x_I) (Eq. 1, float64);
+                                 the gradient is then with respect to x_I        */
 } lensed_system;
 
 #define LENSED_RULE_MIDPOINT 0
 #define LENSED_RULE_G3K7 1
 #define LENSED_RULE_G5K11 2
 #define LENSED_RULE_G7K15 3
+
+#define LENSED_AMP_INTENSITY 0
+#define LENSED_AMP_MAGNITUDE 1
+
+#define LENSED_SOURCE_PLANE 0
+#define LENSED_IMAGE_PLANE 1
 
 /* Creates a context bound to HIP device `device` (its workspace arena, cached
  * batch plans and graphs). Returns LENSED_NOT_SUPPORTED if the device is not
@@ -154,6 +175,26 @@ int lensed_loglike_batch(lensed_ctx* ctx, const lensed_system* systems, int n_sy
  * near a cuspy source centre that lensed_render applies. */
 int lensed_render_error(lensed_ctx* ctx, const lensed_system* sys, const float* theta, float* error, void* stream);
 
+/* Weights of an observation that comes without a variance map (Sec. 3.3,
+ * Eqs. 18-21). The photon counts k_i = g_i (d_i + b_i) (effective gain g_i =
+ * electronic gain x exposure time; offset b_i = whatever was subtracted from
+ * the data, e.g. the sky) are taken as Poisson, Var k_i = k_i, so the data
+ * variance is s_i^2 = (d_i + b_i) / g_i and the weight is
+ *   w_i = e_i / s_i^2 = e_i g_i / (d_i + b_i),
+ * with e_i the optional multiplicative extra weight factor (e_i = 0 masks the
+ * pixel). Pixels with k_i <= 0 get w_i = 0.
+ *   data        device float32 [n]
+ *   gain_map    device float32 [n], or NULL: `gain` for every pixel (finite, > 0)
+ *   offset_map  device float32 [n], or NULL: `offset` for every pixel (finite)
+ *   extra       device float32 [n], or NULL: 1
+ *   weight      device float32 [n], written (usable as lensed_system.weight)
+ * Arithmetic in float64, rounded once. n == 0 does nothing. Errors:
+ * LENSED_INVALID_ARGUMENT for n < 0, NULL data or weight with n > 0, or a bad
+ * scalar gain or offset. */
+int lensed_weights_from_data(lensed_ctx* ctx, const float* data, int64_t n, double gain, const float* gain_map,
+                             double offset, const float* offset_map, const float* extra, float* weight,
+                             void* stream);
+
 /* Log-likelihood and its gradient with respect to the 17 parameters for
  * n_points points of one system: the derivative of Eq. 17 through Eqs. 15, 14,
  * 2 and 1, computed by a hand-written adjoint (transposed PSF with the
@@ -161,7 +202,8 @@ int lensed_render_error(lensed_ctx* ctx, const lensed_system* sys, const float* 
  *   theta  device float32 [n_points * 17]
  *   logl   device float64 [n_points], written
  *   grad   device float32 [n_points * 17], written (d log L / d theta)
- * The system must use the N x N midpoint rule (LENSED_NOT_SUPPORTED otherwise). */
+ * Any integration rule of the system (midpoint or Gauss-Kronrod) and either
+ * amplitude parametrisation (the entries 5 and 12 are then d/dm). */
 int lensed_loglike_grad(lensed_ctx* ctx, const lensed_system* sys, const float* theta,
                         int n_points, double* logl, float* grad, void* stream);
 

@@ -8,7 +8,9 @@ Functions follow Tessore, Bellagamba & Metcalf (MNRAS 2016):
 lens equation Sec. 2.1 Eq. (1); surface brightness Eq. (2); pixel luminosity
 Eq. (3) by midpoint subsampling (Sec. 3.1 Eq. (14), Sec. 4.5 "subN" rules);
 PSF convolution with replicate padding Sec. 3.1 Eq. (15); log-likelihood
-Sec. 3.2 Eq. (17); Sersic profile Sec. 4.1 Eqs. (22)-(23); SIE lens Sec. 4.
+Sec. 3.2 Eq. (17); Sersic profile Sec. 4.1 Eqs. (22)-(23), optionally with its
+amplitude set by a total magnitude (Sec. 4.1); SIE lens Sec. 4; image-plane
+source positions (Sec. 5).
 """
 import ctypes
 import os
@@ -35,6 +37,9 @@ class LoSystem(ctypes.Structure):
         ("rule_n", ctypes.c_int32),
         ("rule_x", ctypes.POINTER(ctypes.c_double)),
         ("rule_w", ctypes.POINTER(ctypes.c_double)),
+        ("amplitude", ctypes.c_int32),
+        ("zero_point", ctypes.c_double),
+        ("source_position", ctypes.c_int32),
     ]
 
 
@@ -56,6 +61,7 @@ def lib():
             ("lo_gamma_p", d, [d, d]),
             ("lo_bn", d, [d]),
             ("lo_bn_deriv", d, [d]),
+            ("lo_intensity_from_magnitude", d, [d, d, d, d]),
             ("lo_sie_deflection", None, [d, d, d, d, d, dp, dp]),
             ("lo_shear_deflection", None, [d, d, d, d, dp, dp]),
             ("lo_sersic", d, [d] * 9),
@@ -83,9 +89,21 @@ class System:
     """
 
     def __init__(self, height, width, pixscale, nsub, psf, data=None, weight=None,
-                 center_x=0.0, center_y=0.0, rule=None):
+                 center_x=0.0, center_y=0.0, rule=None, amplitude="intensity", zero_point=0.0,
+                 source_position="source"):
         """rule: None for the nsub x nsub midpoint rule, or a name accepted by
-        oracle.quadrature.pixel_rule ('subN', 'point', 'g3k7', 'g5k11', 'g7k15')."""
+        oracle.quadrature.pixel_rule ('subN', 'point', 'g3k7', 'g5k11', 'g7k15').
+        amplitude: 'intensity' (theta[5], theta[12] are I_e) or 'magnitude'
+        (they are total magnitudes with the given zero point, Sec. 4.1).
+        source_position: 'source' (theta[10], theta[11] are the source centre) or
+        'image' (they are an image-plane point that the lens equation maps to
+        the source centre, Sec. 5)."""
+        if source_position not in ("source", "image"):
+            raise ValueError("source_position must be 'source' or 'image'")
+        self.source_position = source_position
+        if amplitude not in ("intensity", "magnitude"):
+            raise ValueError("amplitude must be 'intensity' or 'magnitude'")
+        self.amplitude, self.zero_point = amplitude, float(zero_point)
         self.height, self.width = int(height), int(width)
         self.pixscale = float(pixscale)
         self.center_x, self.center_y = float(center_x), float(center_y)
@@ -105,7 +123,9 @@ class System:
             rn, rx, rw = len(x), _dp(self.rule_x), _dp(self.rule_w)
         self._s = LoSystem(self.height, self.width, self.pixscale, self.center_x, self.center_y,
                            self.nsub, self.psf.shape[0], self.psf.shape[1],
-                           _dp(self.psf), _dp(self.data), _dp(self.weight), rn, rx, rw)
+                           _dp(self.psf), _dp(self.data), _dp(self.weight), rn, rx, rw,
+                           1 if amplitude == "magnitude" else 0, self.zero_point,
+                           1 if source_position == "image" else 0)
 
     @property
     def ptr(self):
@@ -125,6 +145,12 @@ def bn(n):
 
 def bn_deriv(n):
     return lib().lo_bn_deriv(float(n))
+
+
+def intensity_from_magnitude(m, Re, n, zero_point=0.0):
+    """I_e of a Sersic component of total magnitude m (Sec. 4.1): total flux
+    10^(-0.4 (m - zero_point)) = 2 pi n R_e^2 I_e e^(b_n) Gamma(2n) / b_n^(2n)."""
+    return lib().lo_intensity_from_magnitude(float(m), float(Re), float(n), float(zero_point))
 
 
 def digamma(z):

@@ -18,6 +18,9 @@
 //   singular isothermal ellipsoid      Sec. 4 (Kormann et al. 1994; formula not printed
 //                                      in the paper, area-preserving convention)
 //   external shear                     Sec. 5 / Table 4 (formula not printed)
+//   amplitude from a total magnitude   Sec. 4.1 (I_0 set by the total magnitude)
+//   image-plane source position        Sec. 5 (a position on the image plane mapped
+//                                      to the source plane by the lens equation)
 //
 // The gradient of the log-likelihood is obtained by running the very same
 // templated code on forward-mode dual numbers carrying 17 partial derivatives.
@@ -93,6 +96,9 @@ inline Dual sin(const Dual& a) { return chain(a, std::sin(a.v), std::cos(a.v)); 
 inline Dual cos(const Dual& a) { return chain(a, std::cos(a.v), -std::sin(a.v)); }
 inline Dual atan(const Dual& a) { return chain(a, std::atan(a.v), 1.0 / (1.0 + a.v * a.v)); }
 inline Dual atanh(const Dual& a) { return chain(a, std::atanh(a.v), 1.0 / (1.0 - a.v * a.v)); }
+double digamma(double z);
+inline double lgamma_of(double a) { return std::lgamma(a); }
+inline Dual lgamma_of(const Dual& a) { return chain(a, std::lgamma(a.v), digamma(a.v)); }
 
 // ---------------------------------------------------------------------------
 // Special functions used by the Sersic normalisation b_n.
@@ -241,11 +247,40 @@ template <class T> struct Params {
   T b_lens, b_src;   // b_n of the lens light and of the source
 };
 
-template <class T> Params<T> make_params(const T* th) {
+// Amplitude I_e of a Sersic component of total magnitude m (zero point zp: a
+// component of magnitude zp has unit total flux). The map (x', y') ->
+// (sqrt(q) x', y'/sqrt(q)) has unit Jacobian, so the elliptical profile has the
+// flux of the circular one: F = int_0^inf I(R) 2 pi R dR
+//   = 2 pi n R_e^2 I_e e^{b_n} Gamma(2n) / b_n^{2n}   (Sec. 4.1, Eq. 22),
+// and F = 10^{-0.4 (m - zp)}. Written as one exponential of the logarithms.
+template <class T> T intensity_from_magnitude(T m, T Re, T n, T b, double zp) {
+  using std::exp; using std::log;
+  const double pi = 3.14159265358979323846;
+  const T lnF = (m - zp) * (-0.4 * std::log(10.0));
+  return exp(lnF + 2.0 * n * log(b) - std::log(2.0 * pi) - log(n) - 2.0 * log(Re) - b - lgamma_of(2.0 * n));
+}
+
+// Parameters of a point; with magnitudes (amplitude != 0) the two amplitude
+// slots 5 and 12 hold total magnitudes and are replaced by I_e; with an
+// image-plane source position (srcpos != 0) slots 10 and 11 hold a point x_I of
+// the image plane, and the source centre is its image under the lens equation,
+// beta = x_I - alpha_SIE(x_I) - alpha_shear(x_I) (Eq. 1).
+template <class T> Params<T> make_params(const T* th, int amplitude = 0, double zp = 0.0, int srcpos = 0) {
   Params<T> P;
   for (int i = 0; i < NPAR; ++i) P.p[i] = th[i];
   P.b_lens = bn_of(P.p[7]);
   P.b_src = bn_of(P.p[14]);
+  if (amplitude) {
+    P.p[5] = intensity_from_magnitude(th[5], th[6], th[7], P.b_lens, zp);
+    P.p[12] = intensity_from_magnitude(th[12], th[13], th[14], P.b_src, zp);
+  }
+  if (srcpos) {
+    T ax, ay, gx, gy;
+    sie_deflection(th[0], th[1], th[2], th[10], th[11], ax, ay);
+    shear_deflection(th[3], th[4], th[10], th[11], gx, gy);
+    P.p[10] = th[10] - ax - gx;
+    P.p[11] = th[11] - ay - gy;
+  }
   return P;
 }
 
@@ -295,6 +330,13 @@ typedef struct {
   int32_t rule_n;
   const double* rule_x;
   const double* rule_w;
+  // Amplitude parametrisation: 0 = theta[5], theta[12] are I_e; 1 = they are
+  // total magnitudes with zero point zero_point (Sec. 4.1).
+  int32_t amplitude;
+  double zero_point;
+  // Source position: 0 = theta[10], theta[11] are the source centre; 1 = they
+  // are a point of the image plane that the source centre is mapped from.
+  int32_t source_position;
 } lo_system;
 
 int lo_param_count(void) { return NPAR; }
@@ -302,6 +344,9 @@ double lo_digamma(double z) { return digamma(z); }
 double lo_gamma_p(double a, double x) { return gamma_p_series(a, x, nullptr); }
 double lo_bn(double n) { return bn_exact(n); }
 double lo_bn_deriv(double n) { return bn_derivative(n, bn_exact(n)); }
+double lo_intensity_from_magnitude(double m, double Re, double n, double zp) {
+  return intensity_from_magnitude(m, Re, n, bn_exact(n), zp);
+}
 
 void lo_sie_deflection(double te, double q, double phi, double x, double y, double* ax, double* ay) {
   sie_deflection<double>(te, q, phi, x, y, *ax, *ay);
@@ -405,6 +450,8 @@ template <class T> void psf_convolve(int H, int W, const std::vector<T>& L, int 
 
 bool system_valid(const lo_system* S) {
   if (!S || S->height <= 0 || S->width <= 0 || S->nsub < 1) return false;
+  if (S->amplitude < 0 || S->amplitude > 1 || !std::isfinite(S->zero_point)) return false;
+  if (S->source_position < 0 || S->source_position > 1) return false;
   if (S->rule_n < 0 || (S->rule_n > 0 && (!S->rule_x || !S->rule_w))) return false;
   if (S->psf_h < 1 || S->psf_w < 1 || S->psf_h % 2 == 0 || S->psf_w % 2 == 0) return false;
   return true;
@@ -431,7 +478,7 @@ int lo_render(const lo_system* S, const double* theta, int apply_psf, double* ou
     for (size_t i = 0; i < n; ++i) out[i] = std::numeric_limits<double>::quiet_NaN();
     return 0;
   }
-  const Params<double> P = make_params(theta);
+  const Params<double> P = make_params(theta, S->amplitude, S->zero_point, S->source_position);
   std::vector<double> img;
   model_image(*S, P, apply_psf, img);
   std::memcpy(out, img.data(), n * sizeof(double));
@@ -449,7 +496,7 @@ int lo_render_error(const lo_system* S, const double* theta, const double* gw, d
     for (size_t i = 0; i < n; ++i) out[i] = std::numeric_limits<double>::quiet_NaN();
     return 0;
   }
-  const Params<double> P = make_params(theta);
+  const Params<double> P = make_params(theta, S->amplitude, S->zero_point, S->source_position);
   std::vector<double> K, G;
   render_rule(*S, P, S->rule_n, S->rule_x, S->rule_w, K);
   render_rule(*S, P, S->rule_n, S->rule_x, gw, G);
@@ -470,7 +517,7 @@ int lo_psf_convolve(int H, int W, const double* L, int ph, int pw, const double*
 double lo_loglike(const lo_system* S, const double* theta) {
   if (!system_valid(S) || !theta || !S->data || !S->weight) return std::numeric_limits<double>::quiet_NaN();
   if (!params_valid(theta)) return std::numeric_limits<double>::quiet_NaN();
-  const Params<double> P = make_params(theta);
+  const Params<double> P = make_params(theta, S->amplitude, S->zero_point, S->source_position);
   std::vector<double> img;
   model_image(*S, P, 1, img);
   std::vector<double> terms(img.size());
@@ -489,7 +536,7 @@ double lo_loglike_grad(const lo_system* S, const double* theta, double* grad) {
   if (!params_valid(theta)) { for (int i = 0; i < NPAR; ++i) grad[i] = nan; return nan; }
   Dual th[NPAR];
   for (int i = 0; i < NPAR; ++i) th[i] = Dual::var(theta[i], i);
-  const Params<Dual> P = make_params(th);
+  const Params<Dual> P = make_params(th, S->amplitude, S->zero_point, S->source_position);
   std::vector<Dual> img;
   model_image(*S, P, 1, img);
   std::vector<double> terms(img.size());

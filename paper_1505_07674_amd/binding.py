@@ -37,10 +37,15 @@ class LensedSystemC(ctypes.Structure):
         ("psf_h", ctypes.c_int32), ("psf_w", ctypes.c_int32),
         ("psf", ctypes.c_void_p), ("data", ctypes.c_void_p), ("weight", ctypes.c_void_p),
         ("rule", ctypes.c_int32),
+        ("amplitude", ctypes.c_int32),
+        ("zero_point", ctypes.c_float),
+        ("source_position", ctypes.c_int32),
     ]
 
 
 RULES = {"sub": 0, "g3k7": 1, "g5k11": 2, "g7k15": 3}
+AMPLITUDES = {"intensity": 0, "magnitude": 1}
+SOURCE_POSITIONS = {"source": 0, "image": 1}
 
 
 _lib = None
@@ -65,6 +70,8 @@ def lib():
                 "lensed_last_error": (cp, [vp]),
                 "lensed_render": (i, [vp, sp, vp, vp, i, vp]),
                 "lensed_render_error": (i, [vp, sp, vp, vp, vp]),
+                "lensed_weights_from_data": (i, [vp, vp, ctypes.c_int64, ctypes.c_double, vp, ctypes.c_double, vp, vp,
+                                                 vp, vp]),
                 "lensed_loglike": (i, [vp, sp, vp, vp, vp]),
                 "lensed_loglike_batch": (i, [vp, sp, i, vp, ctypes.POINTER(ctypes.c_int32), i, vp, vp]),
                 "lensed_loglike_grad": (i, [vp, sp, vp, i, vp, vp, vp]),
@@ -167,12 +174,23 @@ class System:
     def __init__(self, psf: torch.Tensor, data: Optional[torch.Tensor] = None,
                  weight: Optional[torch.Tensor] = None, *, pixscale: float, nsub: int = 1,
                  height: Optional[int] = None, width: Optional[int] = None,
-                 center: Tuple[float, float] = (0.0, 0.0), rule: str = "sub"):
+                 center: Tuple[float, float] = (0.0, 0.0), rule: str = "sub", amplitude: str = "intensity",
+                 zero_point: float = 0.0, source_position: str = "source"):
         """rule: "sub" (nsub x nsub midpoint) or a Gauss-Kronrod product rule
-        "g3k7", "g5k11", "g7k15" (Sec. 4.5; nsub is then ignored)."""
+        "g3k7", "g5k11", "g7k15" (Sec. 4.5; nsub is then ignored).
+        amplitude: "intensity" (theta[5], theta[12] are I_e) or "magnitude"
+        (they are total magnitudes with the given zero point, Sec. 4.1).
+        source_position: "source" (theta[10], theta[11] are the source centre)
+        or "image" (an image-plane point mapped to the source centre by the lens
+        equation, Sec. 5)."""
         if rule not in RULES:
             raise ValueError(f"rule must be one of {sorted(RULES)}")
-        self.rule = rule
+        if amplitude not in AMPLITUDES:
+            raise ValueError(f"amplitude must be one of {sorted(AMPLITUDES)}")
+        if source_position not in SOURCE_POSITIONS:
+            raise ValueError(f"source_position must be one of {sorted(SOURCE_POSITIONS)}")
+        self.source_position = source_position
+        self.rule, self.amplitude, self.zero_point = rule, amplitude, float(zero_point)
         self.psf = _dev_tensor(psf, torch.float32, "psf")
         if self.psf.dim() != 2:
             raise ValueError("psf must be 2-D")
@@ -195,7 +213,8 @@ class System:
             self.height, self.width, self.pixscale, self.center[0], self.center[1], self.nsub,
             int(self.psf.shape[0]), int(self.psf.shape[1]), self.psf.data_ptr(),
             None if self.data is None else self.data.data_ptr(),
-            None if self.weight is None else self.weight.data_ptr(), RULES[rule])
+            None if self.weight is None else self.weight.data_ptr(), RULES[rule], AMPLITUDES[amplitude],
+            self.zero_point, SOURCE_POSITIONS[source_position])
 
     @property
     def c_struct(self) -> LensedSystemC:
@@ -240,6 +259,39 @@ def render_error(theta: torch.Tensor, system: System, *, ctx: Optional[Context] 
     rc = lib().lensed_render_error(ctx.handle, ctypes.byref(system.c_struct), ctypes.c_void_p(t.data_ptr()),
                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
     ctx.check(rc, "lensed_render_error")
+    return out
+
+
+def weights_from_data(data: torch.Tensor, gain, offset=0.0, extra: Optional[torch.Tensor] = None, *,
+                      out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None,
+                      stream=None) -> torch.Tensor:
+    """Weights w = extra * g / (d + b) of an observation without a variance map
+    (Sec. 3.3, Eqs. 18-21); 0 where the counts g (d + b) are not positive. gain
+    and offset are numbers or float32 device tensors of the data's shape."""
+    if data.dtype != torch.float32 or not data.is_cuda:
+        raise ValueError("data must be a float32 device tensor")
+    d = data.contiguous()
+    ctx = ctx or default_context(d.device.index)
+
+    def as_map(v, what):
+        if isinstance(v, torch.Tensor):
+            if v.dtype != torch.float32 or v.device != d.device or v.shape != d.shape:
+                raise ValueError(f"{what} map must be float32 on the data's device with the data's shape")
+            return 0.0, v.contiguous()
+        return float(v), None
+    g, gmap = as_map(gain, "gain")
+    b, bmap = as_map(offset, "offset")
+    e = None
+    if extra is not None:
+        _, e = as_map(extra, "extra")
+    if out is None:
+        out = torch.empty_like(d)
+    elif out.dtype != torch.float32 or out.device != d.device or out.shape != d.shape or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor of the data's shape on its device")
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    rc = lib().lensed_weights_from_data(ctx.handle, ptr(d), d.numel(), g, ptr(gmap), b, ptr(bmap), ptr(e), ptr(out),
+                                        _stream_handle(stream))
+    ctx.check(rc, "lensed_weights_from_data")
     return out
 
 

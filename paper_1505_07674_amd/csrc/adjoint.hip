@@ -98,8 +98,8 @@ __global__ __launch_bounds__(512) void adj_psf_kernel(WorkArgs w, const float* _
 
 // Border pixels of g with the folded tables; blockIdx.y is the point.
 __global__ __launch_bounds__(64) void adj_border_kernel(WorkArgs w, const float* __restrict__ R, float* __restrict__ G,
-                                                         int n_border) {
-  const int point = blockIdx.y;
+                                                         int n_border, int point_base) {
+  const int point = point_base + (int)blockIdx.y;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_border) return;
   const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[point] : 0] : w.single;
@@ -191,13 +191,14 @@ __device__ __forceinline__ float datanh_ds_series(float s, float v) {
 
 constexpr float S_SERIES = 0.0625f;   // use the series for 1 - q^2 below this
 
-// Adds the 17 partial derivatives of I at subsample (x, y) to acc. With
-// `override`, the offset of beta from the source centre is (odx, ody) instead of
-// the float32 lens equation (the float64 re-traced value near a cuspy source).
-template <int MODE>
+// Adds the 17 partial derivatives of I at subsample (x, y) to acc, times the
+// quadrature weight sw when WT (a Gauss-Kronrod node). With `override`, the
+// offset of beta from the source centre is (odx, ody) instead of the float32
+// lens equation (the float64 re-traced value near a cuspy source).
+template <int MODE, bool WT = false>
 __device__ __forceinline__ void subsample_grad(const PointConst& c, const GradUniform& U, float x, float y,
                                                float (&acc)[NPAR], bool override = false, float odx = 0.0f,
-                                               float ody = 0.0f) {
+                                               float ody = 0.0f, float sw = 1.0f) {
   // ---- SIE in its own frame
   const float xp = fmaf(c.cL, x, c.sL * y);
   const float yp = fmaf(c.cL, y, -c.sL * x);
@@ -250,7 +251,12 @@ __device__ __forceinline__ void subsample_grad(const PointConst& c, const GradUn
   const float sxp = fmaf(c.sc, dx, c.ss * dy);
   const float syp = fmaf(c.sc, dy, -c.ss * dx);
   const float srho2 = fmaf(c.sqa * sxp, sxp, c.sqb * syp * syp);
-  const SersicD Sd = sersic_d(srho2, c.se, c.sB, c.sI, U.bS, U.dbS);
+  SersicD Sd = sersic_d(srho2, c.se, c.sB, c.sI, U.bS, U.dbS);
+  if (WT) {
+    Sd.E *= sw;
+    Sd.D *= sw;
+    Sd.dn *= sw;
+  }
   const float gxp = 2.0f * c.sqa * sxp, gyp = 2.0f * c.sqb * syp;   // d rho2 / d(x', y') of the source frame
   const float Gx = Sd.D * fmaf(gxp, c.sc, -gyp * c.ss);
   const float Gy = Sd.D * fmaf(gxp, c.ss, gyp * c.sc);
@@ -258,7 +264,12 @@ __device__ __forceinline__ void subsample_grad(const PointConst& c, const GradUn
   const float hxp = fmaf(c.hc, x, c.hs * y);
   const float hyp = fmaf(c.hc, y, -c.hs * x);
   const float hrho2 = fmaf(c.hqa * hxp, hxp, c.hqb * hyp * hyp);
-  const SersicD Hd = sersic_d(hrho2, c.he, c.hB, c.hI, U.bH, U.dbH);
+  SersicD Hd = sersic_d(hrho2, c.he, c.hB, c.hI, U.bH, U.dbH);
+  if (WT) {
+    Hd.E *= sw;
+    Hd.D *= sw;
+    Hd.dn *= sw;
+  }
   // ---- accumulate
   acc[0] -= Gx * rot_x(dte_x, dte_y) + Gy * rot_y(dte_x, dte_y);
   acc[1] -= Gx * rot_x(dq_x, dq_y) + Gy * rot_y(dq_x, dq_y);
@@ -287,6 +298,21 @@ __device__ __forceinline__ void pixel_grad(const PointConst& c, const GradUnifor
     for (int kx = 0; kx < N; ++kx) {
       const float x = fmaf(g.ux + sub_offset_rt(kx, N), g.d, g.cx);
       subsample_grad<MODE>(c, U, x, y, acc);
+    }
+  }
+}
+
+// The same over the Cartesian square of a Gauss-Kronrod rule (K nodes), each
+// subsample weighted by w_i w_j (the pixel weight d^2 multiplies later).
+template <int MODE>
+__device__ __forceinline__ void pixel_grad_gk(const PointConst& c, const GradUniform& U, int rule, int K,
+                                              const PixelGeom& g, float (&acc)[NPAR]) {
+  const GkRule& R = kGkRules[rule - 1];
+  for (int ky = 0; ky < K; ++ky) {
+    const float y = fmaf(g.uy + R.x[ky], g.d, g.cy);
+    for (int kx = 0; kx < K; ++kx) {
+      const float x = fmaf(g.ux + R.x[kx], g.d, g.cx);
+      subsample_grad<MODE, true>(c, U, x, y, acc, false, 0.0f, 0.0f, R.w[kx] * R.w[ky]);
     }
   }
 }
@@ -340,10 +366,18 @@ __global__ __launch_bounds__(RENDER_BLOCK) void grad_kernel(WorkArgs w, const Po
       geo.d = sd.d;
       geo.cx = sd.cx;
       geo.cy = sd.cy;
-      switch (c.sie_mode) {
-        case 0: pixel_grad<0>(c, U, sd.N, geo, acc); break;
-        case 1: pixel_grad<1>(c, U, sd.N, geo, acc); break;
-        default: pixel_grad<2>(c, U, sd.N, geo, acc); break;
+      if (sd.rule == 0) {
+        switch (c.sie_mode) {
+          case 0: pixel_grad<0>(c, U, sd.N, geo, acc); break;
+          case 1: pixel_grad<1>(c, U, sd.N, geo, acc); break;
+          default: pixel_grad<2>(c, U, sd.N, geo, acc); break;
+        }
+      } else {
+        switch (c.sie_mode) {
+          case 0: pixel_grad_gk<0>(c, U, sd.rule, sd.N, geo, acc); break;
+          case 1: pixel_grad_gk<1>(c, U, sd.rule, sd.N, geo, acc); break;
+          default: pixel_grad_gk<2>(c, U, sd.rule, sd.N, geo, acc); break;
+        }
       }
       const float wgt = (float)sd.wgt * gp;
 #pragma unroll
@@ -391,7 +425,8 @@ __global__ __launch_bounds__(RENDER_BLOCK) void grad_kernel(WorkArgs w, const Po
 // Cusp correction of the gradient: the waves the forward render flagged (same
 // pixels, same float32 test) get, for each subsample in the cusp zone, the
 // partials at the float64 re-traced source offset minus the float32 ones,
-// weighted by g d^2/N^2 and added to corr[point][k] in float64.
+// weighted by g d^2/N^2 (midpoint rule) or g d^2 w_i w_j (Gauss-Kronrod) and
+// added to corr[point][k] in float64.
 constexpr int GCUSP_WAVES = 4;
 constexpr int GCUSP_BLOCKS = 1024;
 
@@ -443,22 +478,34 @@ __global__ __launch_bounds__(64 * GCUSP_WAVES) void grad_cusp_kernel(WorkArgs w,
       geo.cx = sd.cx;
       geo.cy = sd.cy;
       const int N = sd.N;
+      const GkRule* Rg = sd.rule > 0 ? &kGkRules[sd.rule - 1] : nullptr;
       float a64[NPAR], a32[NPAR];
 #pragma unroll
       for (int k = 0; k < NPAR; ++k) a64[k] = a32[k] = 0.0f;
       for (int ky = 0; ky < N; ++ky) {
-        const float y = fmaf(geo.uy + sub_offset_rt(ky, N), geo.d, geo.cy);
+        const float y = fmaf(geo.uy + (Rg ? Rg->x[ky] : sub_offset_rt(ky, N)), geo.d, geo.cy);
+        const double oy = Rg ? Rg->xd[ky] : ((double)ky + 0.5) / N - 0.5;
         for (int kx = 0; kx < N; ++kx) {
-          const float x = fmaf(geo.ux + sub_offset_rt(kx, N), geo.d, geo.cx);
+          const float x = fmaf(geo.ux + (Rg ? Rg->x[kx] : sub_offset_rt(kx, N)), geo.d, geo.cx);
           const float sR2 = render_source_R2(c, x, y);
           if (sR2 < c.cusp_r2) {
+            const double ox = Rg ? Rg->xd[kx] : ((double)kx + 0.5) / N - 0.5;
+            const float sw = Rg ? Rg->w[kx] * Rg->w[ky] : 1.0f;
             float dx, dy;
-            source_offset_f64(p64s[e.point], geo, ((double)kx + 0.5) / N - 0.5, ((double)ky + 0.5) / N - 0.5, dx,
-                              dy);
+            source_offset_f64(p64s[e.point], geo, ox, oy, dx, dy);
             switch (c.sie_mode) {
-              case 0: subsample_grad<0>(c, U, x, y, a32); subsample_grad<0>(c, U, x, y, a64, true, dx, dy); break;
-              case 1: subsample_grad<1>(c, U, x, y, a32); subsample_grad<1>(c, U, x, y, a64, true, dx, dy); break;
-              default: subsample_grad<2>(c, U, x, y, a32); subsample_grad<2>(c, U, x, y, a64, true, dx, dy); break;
+              case 0:
+                subsample_grad<0, true>(c, U, x, y, a32, false, 0.0f, 0.0f, sw);
+                subsample_grad<0, true>(c, U, x, y, a64, true, dx, dy, sw);
+                break;
+              case 1:
+                subsample_grad<1, true>(c, U, x, y, a32, false, 0.0f, 0.0f, sw);
+                subsample_grad<1, true>(c, U, x, y, a64, true, dx, dy, sw);
+                break;
+              default:
+                subsample_grad<2, true>(c, U, x, y, a32, false, 0.0f, 0.0f, sw);
+                subsample_grad<2, true>(c, U, x, y, a64, true, dx, dy, sw);
+                break;
             }
           }
         }
@@ -479,16 +526,49 @@ __global__ __launch_bounds__(64 * GCUSP_WAVES) void grad_cusp_kernel(WorkArgs w,
 
 // grad[p][k] = sum over the point's render tiles of (hi + lo) plus the cusp
 // correction, in float64.
+// Sum of one gradient entry k of point p over its tiles (and its cusp term).
+__device__ double grad_entry(const float2* __restrict__ gpart, int base, int ntiles, const double* __restrict__ corr,
+                             int p, int k) {
+  double s = corr ? corr[(size_t)p * NPAR + k] : 0.0;
+  for (int i = 0; i < ntiles; ++i) {
+    const float2 v = gpart[(size_t)(base + i) * NPAR + k];
+    s += (double)v.x + (double)v.y;
+  }
+  return s;
+}
+
+// With magnitudes, slots 5 and 12 of the sums hold d log L / d I_e and slots
+// 6, 7 and 13, 14 the derivatives at fixed I_e; the chain rule through
+// I_e(m, R_e, n) gives d/dm = g_I I_e dlnI/dm and adds g_I I_e dlnI/dR_e and
+// g_I I_e dlnI/dn to the radius and index entries. With an image-plane source
+// position, slots 10 and 11 hold d log L / d beta; the chain rule through
+// beta(x_I, y_I, theta_E, q_L, phi_L, gamma, phi_gamma) gives d/dx_I, d/dy_I and
+// adds g_beta . d beta / d theta_k to the five lens entries.
 __global__ void finalize_grad_kernel(const float2* __restrict__ gpart, const int* __restrict__ gpbase, int ntiles,
-                                     int n_points, const double* __restrict__ corr, float* __restrict__ grad) {
+                                     int n_points, const double* __restrict__ corr,
+                                     const GradConst* __restrict__ gcs, float* __restrict__ grad) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_points * NPAR) return;
   const int p = t / NPAR, k = t - p * NPAR;
   const int base = gpbase ? gpbase[p] : 0;
-  double s = corr ? corr[t] : 0.0;
-  for (int i = 0; i < ntiles; ++i) {
-    const float2 v = gpart[(size_t)(base + i) * NPAR + k];
-    s += (double)v.x + (double)v.y;
+  double s = grad_entry(gpart, base, ntiles, corr, p, k);
+  if (gcs && gcs[p].srcpos && (k <= 4 || k == 10 || k == 11)) {
+    const float* J = gcs[p].src_jac;
+    const double gx = k == 10 ? s : grad_entry(gpart, base, ntiles, corr, p, 10);
+    const double gy = k == 11 ? s : grad_entry(gpart, base, ntiles, corr, p, 11);
+    const int col = k <= 4 ? k + 2 : k - 10;
+    const double chain = gx * (double)J[col] + gy * (double)J[7 + col];
+    s = k <= 4 ? s + chain : chain;
+  }
+  if (gcs && gcs[p].amp) {
+    const GradConst& gc = gcs[p];
+    if (k >= 5 && k <= 7) {
+      const double gI = k == 5 ? s : grad_entry(gpart, base, ntiles, corr, p, 5);
+      s = k == 5 ? gI * (double)gc.amp_chain[0] : s + gI * (double)gc.amp_chain[k - 5];
+    } else if (k >= 12 && k <= 14) {
+      const double gI = k == 12 ? s : grad_entry(gpart, base, ntiles, corr, p, 12);
+      s = k == 12 ? gI * (double)gc.amp_chain[3] : s + gI * (double)gc.amp_chain[k - 9];
+    }
   }
   grad[t] = (float)s;
 }
@@ -496,8 +576,10 @@ __global__ void finalize_grad_kernel(const float2* __restrict__ gpart, const int
 template <int P, int TWc, int R>
 hipError_t launch_adj_t(const WorkArgs& w, const float* R_, float* G, int n_blocks, int threads, size_t lds,
                         hipStream_t st) {
-  hipLaunchKernelGGL((adj_psf_kernel<P, TWc, R>), dim3(n_blocks), dim3(threads), lds, st, w, R_, G);
-  return hipGetLastError();
+  return for_item_parts(w, n_blocks, [&](const WorkArgs& part, int n) {
+    hipLaunchKernelGGL((adj_psf_kernel<P, TWc, R>), dim3(n), dim3(threads), lds, st, part, R_, G);
+    return hipGetLastError();
+  });
 }
 
 template <int P, int R>
@@ -526,16 +608,24 @@ hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n
   }
   if (e != hipSuccess) return e;
   const int nb = (H <= 2 || W <= 2) ? H * W : 2 * W + 2 * (H - 2);
-  hipLaunchKernelGGL(adj_border_kernel, dim3((nb + 63) / 64, n_points), dim3(64), 0, st, w, R, G, nb);
-  return hipGetLastError();
+  // one grid row per point, at most 65535 rows per launch
+  for (int p0 = 0; p0 < n_points; p0 += 65535) {
+    const int np = n_points - p0 < 65535 ? n_points - p0 : 65535;
+    hipLaunchKernelGGL(adj_border_kernel, dim3((nb + 63) / 64, np), dim3(64), 0, st, w, R, G, nb, p0);
+    const hipError_t le = hipGetLastError();
+    if (le != hipSuccess) return le;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_grad(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, const GradConst* gcs,
                        const float* G, const int* gpbase, float2* gpart, int n_blocks, const CuspList& cl,
                        double* corr, hipStream_t st) {
   if (n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(grad_kernel, dim3(n_blocks), dim3(RENDER_BLOCK), 0, st, w, pcs, gcs, G, gpbase, gpart);
-  hipError_t e = hipGetLastError();
+  hipError_t e = for_item_parts(w, n_blocks, [&](const WorkArgs& part, int n) {
+    hipLaunchKernelGGL(grad_kernel, dim3(n), dim3(RENDER_BLOCK), 0, st, part, pcs, gcs, G, gpbase, gpart);
+    return hipGetLastError();
+  });
   if (e != hipSuccess) return e;
   const int waves = n_blocks * (RENDER_BLOCK / 64);
   int grid = (waves + GCUSP_WAVES - 1) / GCUSP_WAVES;
@@ -545,11 +635,11 @@ hipError_t launch_grad(const WorkArgs& w, const PointConst* pcs, const PointCons
 }
 
 hipError_t launch_finalize_grad(const float2* gpart, const int* gpbase, int ntiles, int n_points, const double* corr,
-                                float* grad, hipStream_t st) {
+                                const GradConst* gcs, float* grad, hipStream_t st) {
   if (n_points <= 0) return hipSuccess;
   const int n = n_points * NPAR;
   hipLaunchKernelGGL(finalize_grad_kernel, dim3((n + 127) / 128), dim3(128), 0, st, gpart, gpbase, ntiles, n_points,
-                     corr, grad);
+                     corr, gcs, grad);
   return hipGetLastError();
 }
 

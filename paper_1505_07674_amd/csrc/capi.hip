@@ -3,6 +3,7 @@
 // scratch layout, captured hipGraphs).
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -17,6 +18,12 @@
 #include "plan.h"
 
 using namespace lensed;
+
+// The layout the Python binding mirrors (LensedSystemC).
+static_assert(offsetof(lensed_system, psf) == 32 && offsetof(lensed_system, rule) == 56 &&
+                  offsetof(lensed_system, amplitude) == 60 && offsetof(lensed_system, zero_point) == 64 &&
+                  offsetof(lensed_system, source_position) == 68 && sizeof(lensed_system) == 72,
+              "lensed_system layout");
 
 struct lensed_ctx {
   int device = 0;
@@ -144,6 +151,12 @@ int validate_system(lensed_ctx* c, const lensed_system* s, bool need_data, int i
   if (s->psf_h > MAX_PSF || s->psf_w > MAX_PSF)
     return set_err(c, LENSED_INVALID_ARGUMENT, where + "PSF side larger than " + std::to_string(MAX_PSF));
   if (!s->psf) return set_err(c, LENSED_INVALID_ARGUMENT, where + "psf is NULL");
+  if (s->amplitude != LENSED_AMP_INTENSITY && s->amplitude != LENSED_AMP_MAGNITUDE)
+    return set_err(c, LENSED_INVALID_ARGUMENT, where + "amplitude must be LENSED_AMP_INTENSITY or LENSED_AMP_MAGNITUDE");
+  if (!std::isfinite(s->zero_point)) return set_err(c, LENSED_INVALID_ARGUMENT, where + "zero_point must be finite");
+  if (s->source_position != LENSED_SOURCE_PLANE && s->source_position != LENSED_IMAGE_PLANE)
+    return set_err(c, LENSED_INVALID_ARGUMENT,
+                   where + "source_position must be LENSED_SOURCE_PLANE or LENSED_IMAGE_PLANE");
   if (need_data && (!s->data || !s->weight))
     return set_err(c, LENSED_INVALID_ARGUMENT, where + "data and weight are required");
   return LENSED_OK;
@@ -155,6 +168,9 @@ SysDesc make_desc(const lensed_system& s, const TileShape& t) {
   d.H = s.height;
   d.W = s.width;
   d.rule = s.rule;
+  d.amp = s.amplitude;
+  d.zp = s.zero_point;
+  d.srcpos = s.source_position;
   d.N = s.rule == LENSED_RULE_MIDPOINT ? s.nsub : 2 * (2 * s.rule + 1) + 1;   // g3k7, g5k11, g7k15: 7, 11, 15 nodes
   d.ph = s.psf_h;
   d.pw = s.psf_w;
@@ -297,6 +313,21 @@ int lensed_render_error(lensed_ctx* c, const lensed_system* sys, const float* th
   w.single = sd;
   LENSED_HIP(c, launch_prologue(theta, 1, pc, p64, nullptr, sd, nullptr, 1, (int*)(c->arena + off_cc), st));
   LENSED_HIP(c, launch_rule_error(w, pc, error, sd.n_rtiles, st));
+  return LENSED_OK;
+}
+
+int lensed_weights_from_data(lensed_ctx* c, const float* data, int64_t n, double gain, const float* gain_map,
+                             double offset, const float* offset_map, const float* extra, float* weight,
+                             void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  if (n < 0) return set_err(c, LENSED_INVALID_ARGUMENT, "n must be >= 0");
+  if (n > 0 && (!data || !weight)) return set_err(c, LENSED_INVALID_ARGUMENT, "data and weight are required");
+  if (!gain_map && !(std::isfinite(gain) && gain > 0.0))
+    return set_err(c, LENSED_INVALID_ARGUMENT, "gain must be finite and > 0");
+  if (!offset_map && !std::isfinite(offset)) return set_err(c, LENSED_INVALID_ARGUMENT, "offset must be finite");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  LENSED_HIP(c, launch_weights_from_data(data, n, gain, gain_map, offset, offset_map, extra, weight,
+                                         (hipStream_t)stream));
   return LENSED_OK;
 }
 
@@ -449,8 +480,6 @@ extern "C" int lensed_loglike_grad(lensed_ctx* c, const lensed_system* sys, cons
   if (n_points == 0) return LENSED_OK;
   int rc = validate_system(c, sys, true, -1);
   if (rc) return rc;
-  if (sys->rule != LENSED_RULE_MIDPOINT)
-    return set_err(c, LENSED_NOT_SUPPORTED, "the adjoint supports the N x N midpoint rule only");
   if (!theta || !logl || !grad) return set_err(c, LENSED_INVALID_ARGUMENT, "theta, logl and grad are required");
   LENSED_HIP(c, hipSetDevice(c->device));
   std::vector<int32_t> map(n_points, 0);

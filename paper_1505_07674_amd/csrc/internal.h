@@ -48,7 +48,11 @@ struct PointConst {
   // (A1 A2) = S (m11 m12), (B1 B2) = S (m12 m22), (C1 C2) = -S (x_S y_S),
   // cXt = -(s11 tac + s12 tas), cXh = s11 ths - s12 thc, and the same with s21, s22.
   float A1, A2, B1, B2, C1, C2, cXt, cXh, cYt, cYh;
-  float pad2[9];
+  // low parts of the two amplitudes (I_e - float(I_e)), non-zero only when I_e
+  // is derived in float64 from a magnitude: they keep the float32 rounding of
+  // the amplitude from scaling every pixel of a component the same way
+  float hIlo, sIlo;
+  float pad2[7];
 };
 static_assert(sizeof(PointConst) == 64 * 4, "PointConst layout");
 
@@ -71,9 +75,20 @@ struct GradConst {
   float dB_dn_h;       // d(b_n log2 e)/dn for the lens light
   float dB_dn_s;       // same for the source
   float bh, bs;        // b_n of lens light and source
-  float pad[11];
+  // Magnitude parametrisation (amp != 0): theta[5] and theta[12] are total
+  // magnitudes; I_e * d ln I_e / d(m, R_e, n) of the lens light [0..2] and of
+  // the source [3..5], which carry d log L / d I_e over to the parameters.
+  float amp_chain[6];
+  int amp;
+  // Image-plane source position (srcpos != 0): theta[10], theta[11] are an
+  // image-plane point x_I and the source centre is beta(x_I). Jacobian of beta
+  // (row 0: x, row 1: y) with respect to (x_I, y_I, theta_E, q_L, phi_L, gamma,
+  // phi_gamma), row-major.
+  float src_jac[14];
+  int srcpos;
+  float pad[5];
 };
-static_assert(sizeof(GradConst) == 32 * 4, "GradConst layout");
+static_assert(sizeof(GradConst) == 48 * 4, "GradConst layout");
 
 // Geometry and schedule of one system (one observation).
 struct SysDesc {
@@ -89,6 +104,9 @@ struct SysDesc {
   int tiles_x, n_ptiles;  // PSF tiles per row, per image
   int n_rtiles;           // render tiles (RENDER_BLOCK pixels each) per image
   int rule;               // 0 N x N midpoint; 1, 2, 3: Gauss-Kronrod g3k7, g5k11, g7k15 (N = 7, 11, 15)
+  int amp;                // 0: theta[5], theta[12] are I_e; 1: total magnitudes with zero point zp
+  float zp;
+  int srcpos;             // 0: theta[10], theta[11] are the source centre; 1: an image-plane point
   double wgt;             // quadrature weight pixscale^2 / N^2, in float64
   float* adjk;            // 16 folded PSF tables of the adjoint (or nullptr)
   float* adjk_pad;

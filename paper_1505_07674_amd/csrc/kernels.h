@@ -22,11 +22,33 @@ struct WorkArgs {
   int point0;                   // point of a plain call
 };
 
+// Item lists longer than this are launched in several parts: every grid
+// dimension must stay below 2^32 work-items (2^22 blocks of at most 512).
+constexpr int MAX_ITEM_BLOCKS = 1 << 22;
+
+// Calls launch(part, n) for consecutive parts of w's item list (w.items advanced,
+// n <= MAX_ITEM_BLOCKS blocks each); a plain call (no item list) goes out whole.
+template <class F>
+hipError_t for_item_parts(const WorkArgs& w, int n_blocks, F launch) {
+  if (!w.items) return launch(w, n_blocks);
+  for (int off = 0; off < n_blocks; off += MAX_ITEM_BLOCKS) {
+    WorkArgs part = w;
+    part.items = w.items + off;
+    part.n_items = n_blocks - off < MAX_ITEM_BLOCKS ? n_blocks - off : MAX_ITEM_BLOCKS;
+    const hipError_t e = launch(part, part.n_items);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Also clears *cusp_count (may be nullptr) and, when gcs is given, the 17
-// cusp-correction accumulators of every point in grad_corr.
+// cusp-correction accumulators of every point in grad_corr. The system of
+// point p is table[point_sys[p]] (table[0] without point_sys; single without
+// table); its amplitude mode decides whether theta[5] and theta[12] are I_e or
+// total magnitudes.
 hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, PointConst64* p64s, GradConst* gcs,
                            const SysDesc& single, SysDesc* table, int n_sys, int* cusp_count, hipStream_t stream,
-                           double* grad_corr = nullptr);
+                           double* grad_corr = nullptr, const int* point_sys = nullptr);
 
 // Unconvolved pixel luminosities into L (scratch or the caller's image): the
 // float32 render kernel, then the float64 cusp corrections of the pixels it
@@ -35,6 +57,11 @@ hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, Po
 // non-null `between` is recorded on the stream after the render kernel.
 hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L, int n_blocks,
                          const CuspList& cl, hipStream_t stream, hipEvent_t between = nullptr);
+
+// Weights from the data (Sec. 3.3): w = extra * g / (d + b) where g (d + b) > 0, else 0.
+// gain_map / offset_map / extra may be nullptr (scalar gain, scalar offset, 1).
+hipError_t launch_weights_from_data(const float* data, int64_t n, double gain, const float* gain_map, double offset,
+                                    const float* offset_map, const float* extra, float* weight, hipStream_t stream);
 
 // Per-pixel integration error estimate of a Gauss-Kronrod rule for the single
 // point w.point0 of w.single (rule > 0): |Kronrod - embedded Gauss| x pixel weight.
@@ -68,7 +95,9 @@ hipError_t launch_grad(const WorkArgs& w, const PointConst* pcs, const PointCons
                        const float* G, const int* gpbase, float2* gpart, int n_blocks, const CuspList& cl,
                        double* corr, hipStream_t st);
 
+// Sums the gradient partials of every point; for points of a system with
+// magnitudes, carries d log L / d I_e over to d/dm, d/dR_e and d/dn (gcs).
 hipError_t launch_finalize_grad(const float2* gpart, const int* gpbase, int ntiles, int n_points, const double* corr,
-                                float* grad, hipStream_t st);
+                                const GradConst* gcs, float* grad, hipStream_t st);
 
 }  // namespace lensed

@@ -102,7 +102,8 @@ namespace {
 bool same_system(const lensed_system& a, const lensed_system& b) {
   return a.height == b.height && a.width == b.width && a.pixscale == b.pixscale && a.center_x == b.center_x &&
          a.center_y == b.center_y && a.nsub == b.nsub && a.psf_h == b.psf_h && a.psf_w == b.psf_w &&
-         a.psf == b.psf && a.data == b.data && a.weight == b.weight && a.rule == b.rule;
+         a.psf == b.psf && a.data == b.data && a.weight == b.weight && a.rule == b.rule &&
+         a.amplitude == b.amplitude && a.zero_point == b.zero_point && a.source_position == b.source_position;
 }
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 }  // namespace
@@ -265,7 +266,7 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
   hipError_t e;
   if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
   if ((e = launch_prologue(theta_, n_points_, d_pc_, d_p64_, d_gc_, none, d_sys_, (int)systems_.size(), cusp_.count,
-                           st, d_gcorr_)) != hipSuccess)
+                           st, d_gcorr_, d_point_sys_)) != hipSuccess)
     return e;
   if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
   WorkArgs wr = w;
@@ -294,7 +295,8 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
     if ((e = launch_grad(wr, d_pc_, d_p64_, d_gc_, d_L_, d_gpbase_, d_gpart_, n_ritems_, cusp_, d_gcorr_, st)) !=
         hipSuccess)
       return e;
-    if ((e = launch_finalize_grad(d_gpart_, d_gpbase_, grad_ntiles_, n_points_, d_gcorr_, grad_, st)) != hipSuccess)
+    if ((e = launch_finalize_grad(d_gpart_, d_gpbase_, grad_ntiles_, n_points_, d_gcorr_, d_gc_, grad_, st)) !=
+        hipSuccess)
       return e;
   }
   return hipSuccess;

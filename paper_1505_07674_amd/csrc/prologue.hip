@@ -59,13 +59,110 @@ __device__ double sersic_bn_deriv(double n, double b) {
   return (gamma_median(2.0 * (n + h), b + 2.0 * h) - gamma_median(2.0 * (n - h), b - 2.0 * h)) / (2.0 * h);
 }
 
+// Digamma psi(z), z > 0: psi(z) = psi(z + 1) - 1/z up to z >= 8, then the
+// asymptotic expansion psi(z) ~ ln z - 1/(2z) - sum_k B_2k / (2k z^2k)
+// (Abramowitz & Stegun 6.3.18) to z^-12, below 1e-15 relative there.
+__device__ double digamma_d(double z) {
+  double shift = 0.0;
+  while (z < 8.0) {
+    shift += 1.0 / z;
+    z += 1.0;
+  }
+  const double w = 1.0 / (z * z);
+  const double tail =
+      w * (1.0 / 12.0 + w * (-1.0 / 120.0 + w * (1.0 / 252.0 + w * (-1.0 / 240.0 + w * (1.0 / 132.0 + w * (-691.0 / 32760.0))))));
+  return log(z) - 0.5 / z - tail - shift;
+}
+
+// Sersic amplitude from a total magnitude (Sec. 4.1: the amplitude is set by
+// the total magnitude). The elliptical profile with the geometric-mean radius
+// has the circular profile's flux F = 2 pi n R_e^2 I_e e^{b} Gamma(2n) / b^{2n},
+// and F = 10^{-0.4 (m - zp)}, so
+//   ln I_e = -0.4 ln 10 (m - zp) + 2n ln b - ln(2 pi n R_e^2) - b - ln Gamma(2n),
+// and with b = b_n(n):
+//   d ln I_e/dm = -0.4 ln 10,  d ln I_e/dR_e = -2/R_e,
+//   d ln I_e/dn = 2 ln b + (2n/b - 1) db/dn - 1/n - 2 psi(2n).
+struct AmpFromMag {
+  double I;          // I_e
+  double dm, dR, dn; // I_e times the three logarithmic derivatives
+};
+__device__ AmpFromMag amplitude_from_magnitude(double m, double Re, double n, double b, double db_dn, double zp) {
+  const double ln10 = 2.302585092994045684;
+  const double two_pi = 6.283185307179586477;
+  const double lnI = -0.4 * ln10 * (m - zp) + 2.0 * n * log(b) - log(two_pi * n * Re * Re) - b - lgamma(2.0 * n);
+  AmpFromMag a;
+  a.I = exp(lnI);
+  a.dm = a.I * (-0.4 * ln10);
+  a.dR = a.I * (-2.0 / Re);
+  a.dn = a.I * (2.0 * log(b) + (2.0 * n / b - 1.0) * db_dn - 1.0 / n - 2.0 * digamma_d(2.0 * n));
+  return a;
+}
+
+// Lens equation in float64 (Eq. 1): beta = x - alpha_SIE(x) - alpha_shear(x),
+// SIE in the area-preserving convention about the origin (alpha = 0 at its
+// centre), external shear about the same centre.
+__device__ void lens_map_f64(const double (&v)[7], double& bx, double& by) {
+  const double x = v[0], y = v[1], te = v[2], q = v[3], ph = v[4], g = v[5], phg = v[6];
+  const double c = cos(ph), s = sin(ph);
+  const double xp = c * x + s * y, yp = c * y - s * x;
+  const double psi = sqrt(q * q * xp * xp + yp * yp);
+  double axp = 0.0, ayp = 0.0;
+  if (psi > 0.0) {
+    const double s2 = (1.0 - q) * (1.0 + q);
+    if (s2 > 0.0) {
+      const double qp = sqrt(s2), k = te * sqrt(q) / qp;
+      axp = k * atan(qp * xp / psi);
+      ayp = k * atanh(qp * yp / psi);
+    } else {
+      axp = te * xp / psi;
+      ayp = te * yp / psi;
+    }
+  }
+  const double g1 = g * cos(2.0 * phg), g2 = g * sin(2.0 * phg);
+  bx = x - (c * axp - s * ayp) - (g1 * x + g2 * y);
+  by = y - (s * axp + c * ayp) - (g2 * x - g1 * y);
+}
+
+// d beta / d v by central differences in float64 (step 1e-6 of the scale: error
+// ~1e-10 relative); q_L steps backwards with a second-order stencil where a
+// forward step would leave q <= 1.
+__device__ void lens_map_jacobian(const double (&v)[7], float (&jac)[14]) {
+  for (int j = 0; j < 7; ++j) {
+    const double h = 1e-6 * fmax(fabs(v[j]), 1.0) * (j == 3 ? 0.25 : 1.0);
+    double a[7], b[7], bxa, bya, bxb, byb;
+    for (int i = 0; i < 7; ++i) a[i] = b[i] = v[i];
+    double dx, dy;
+    if (j == 3 && v[3] + h > 1.0) {
+      double c2[7];
+      for (int i = 0; i < 7; ++i) c2[i] = v[i];
+      a[3] = v[3] - h;
+      c2[3] = v[3] - 2.0 * h;
+      double bx0, by0, bx2, by2;
+      lens_map_f64(v, bx0, by0);
+      lens_map_f64(a, bxa, bya);
+      lens_map_f64(c2, bx2, by2);
+      dx = (3.0 * bx0 - 4.0 * bxa + bx2) / (2.0 * h);
+      dy = (3.0 * by0 - 4.0 * bya + by2) / (2.0 * h);
+    } else {
+      a[j] = v[j] + h;
+      b[j] = v[j] - h;
+      lens_map_f64(a, bxa, bya);
+      lens_map_f64(b, bxb, byb);
+      dx = (bxa - bxb) / (2.0 * h);
+      dy = (bya - byb) / (2.0 * h);
+    }
+    jac[j] = (float)dx;
+    jac[7 + j] = (float)dy;
+  }
+}
+
 __device__ bool ok_q(float q) { return q > 0.0f && q <= 1.0f; }
 __device__ bool ok_n(float n) { return n >= 0.2f && n <= 10.0f; }
 
 __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, PointConst* __restrict__ pcs,
                                 PointConst64* __restrict__ p64s, GradConst* __restrict__ gcs, SysDesc single,
                                 SysDesc* __restrict__ table, int n_sys, int point_blocks, int* __restrict__ cusp_count,
-                                double* __restrict__ grad_corr) {
+                                double* __restrict__ grad_corr, const int* __restrict__ point_sys) {
   if (cusp_count && blockIdx.x == 0 && threadIdx.x == 0) *cusp_count = 0;
   if ((int)blockIdx.x >= point_blocks) {
     // PSF normalisation: one block per system, float64 sum over the array.
@@ -161,6 +258,31 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
     bh = sersic_bn(t[7]);
     bs = sersic_bn(t[14]);
   }
+  // amplitudes: I_e given, or from total magnitudes (the point's system decides)
+  const SysDesc* own = table ? &table[point_sys ? point_sys[p] : 0] : &single;
+  const int amp = own->amp;
+  double Ih = t[5], Is = t[12];
+  AmpFromMag ah = {0.0, 0.0, 0.0, 0.0}, as = {0.0, 0.0, 0.0, 0.0};
+  double dbh = 0.0, dbs = 0.0;
+  if (valid && gcs) {
+    dbh = sersic_bn_deriv(t[7], bh);
+    dbs = sersic_bn_deriv(t[14], bs);
+  }
+  if (valid && amp) {
+    ah = amplitude_from_magnitude(t[5], t[6], t[7], bh, dbh, own->zp);
+    as = amplitude_from_magnitude(t[12], t[13], t[14], bs, dbs, own->zp);
+    Ih = ah.I;
+    Is = as.I;
+  }
+  // source centre: given, or the image of an image-plane point (Sec. 5)
+  const int srcpos = own->srcpos;
+  double xs = t[10], ys = t[11];
+  float jac[14] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  if (valid && srcpos) {
+    const double v[7] = {t[10], t[11], t[0], t[1], t[2], t[3], t[4]};
+    lens_map_f64(v, xs, ys);
+    if (gcs) lens_map_jacobian(v, jac);
+  }
   {
     const double Re = t[6], qh = t[8], ph = t[9];
     c.hc = (float)cos(ph);
@@ -169,19 +291,19 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
     c.hqb = (float)(1.0 / (qh * Re * Re));
     c.he = (float)(0.5 / (double)t[7]);
     c.hB = (float)(bh * LOG2E);
-    c.hI = t[5];
+    c.hI = (float)Ih;
   }
   {
     const double Re = t[13], qs = t[15], ph = t[16];
-    c.sx0 = t[10];
-    c.sy0 = t[11];
+    c.sx0 = (float)xs;
+    c.sy0 = (float)ys;
     c.sc = (float)cos(ph);
     c.ss = (float)sin(ph);
     c.sqa = (float)(qs / (Re * Re));
     c.sqb = (float)(1.0 / (qs * Re * Re));
     c.se = (float)(0.5 / (double)t[14]);
     c.sB = (float)(bs * LOG2E);
-    c.sI = t[12];
+    c.sI = (float)Is;
   }
   // re-trace in float64 within 0.03 arcsec (source plane) of a cuspy (n > 1) source centre
   {
@@ -222,7 +344,7 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
     c.s21 = (float)s21;
     c.s22 = (float)s22;
     // the source frame of the lens equation in one step (float64 products, one rounding each)
-    const double m11 = 1.0 - g1, m12 = -g2, m22 = 1.0 + g1, xs = t[10], ys = t[11];
+    const double m11 = 1.0 - g1, m12 = -g2, m22 = 1.0 + g1;
     c.A1 = (float)(s11 * m11 + s12 * m12);
     c.A2 = (float)(s21 * m11 + s22 * m12);
     c.B1 = (float)(s11 * m12 + s12 * m22);
@@ -234,7 +356,9 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
     c.cYt = (float)(-(s21 * tac + s22 * tas));
     c.cYh = (float)(s21 * ths - s22 * thc);
   }
-  for (int k = 0; k < 9; ++k) c.pad2[k] = 0.0f;
+  c.hIlo = (float)(Ih - (double)c.hI);
+  c.sIlo = (float)(Is - (double)c.sI);
+  for (int k = 0; k < 7; ++k) c.pad2[k] = 0.0f;
   if (!valid) {
     const float nan = __builtin_nanf("");
     c.m11 = c.m12 = c.m22 = nan;
@@ -255,8 +379,8 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
     e.m11 = 1.0 - g1;
     e.m12 = -g2;
     e.m22 = 1.0 + g1;
-    e.sx0 = t[10];
-    e.sy0 = t[11];
+    e.sx0 = xs;
+    e.sy0 = ys;
     for (int k = 0; k < 4; ++k) e.pad[k] = 0.0;
     if (!valid) e.m11 = e.m12 = e.m22 = __builtin_nan("");
     p64s[p] = e;
@@ -269,9 +393,18 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
     for (int k = 0; k < NPAR; ++k) gc.theta[k] = t[k];
     gc.bh = (float)bh;
     gc.bs = (float)bs;
-    gc.dB_dn_h = valid ? (float)(sersic_bn_deriv(t[7], bh) * LOG2E) : __builtin_nanf("");
-    gc.dB_dn_s = valid ? (float)(sersic_bn_deriv(t[14], bs) * LOG2E) : __builtin_nanf("");
-    for (int k = 0; k < 11; ++k) gc.pad[k] = 0.0f;
+    gc.dB_dn_h = valid ? (float)(dbh * LOG2E) : __builtin_nanf("");
+    gc.dB_dn_s = valid ? (float)(dbs * LOG2E) : __builtin_nanf("");
+    gc.amp_chain[0] = (float)ah.dm;
+    gc.amp_chain[1] = (float)ah.dR;
+    gc.amp_chain[2] = (float)ah.dn;
+    gc.amp_chain[3] = (float)as.dm;
+    gc.amp_chain[4] = (float)as.dR;
+    gc.amp_chain[5] = (float)as.dn;
+    gc.amp = amp;
+    for (int k = 0; k < 14; ++k) gc.src_jac[k] = jac[k];
+    gc.srcpos = srcpos;
+    for (int k = 0; k < 5; ++k) gc.pad[k] = 0.0f;
     gcs[p] = gc;
   }
 }
@@ -280,13 +413,13 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
 
 hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, PointConst64* p64s, GradConst* gcs,
                            const SysDesc& single, SysDesc* table, int n_sys, int* cusp_count, hipStream_t stream,
-                           double* grad_corr) {
+                           double* grad_corr, const int* point_sys) {
   const int threads = 64;
   const int point_blocks = (n_points + threads - 1) / threads;
   const int blocks = point_blocks + n_sys;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(prologue_kernel, dim3(blocks), dim3(threads), 0, stream, theta, n_points, pcs, p64s, gcs,
-                     single, table, n_sys, point_blocks, cusp_count, grad_corr);
+                     single, table, n_sys, point_blocks, cusp_count, grad_corr, point_sys);
   return hipGetLastError();
 }
 

@@ -159,8 +159,10 @@ __global__ void finalize_kernel(const float2* __restrict__ partials, const int* 
 template <int P, int TWc, int R>
 hipError_t launch_psf_t(const WorkArgs& w, const float* L, float* out, float2* partials, int mode, int n_blocks,
                         int threads, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL((psf_kernel<P, TWc, R>), dim3(n_blocks), dim3(threads), lds, stream, w, L, out, partials, mode);
-  return hipGetLastError();
+  return for_item_parts(w, n_blocks, [&](const WorkArgs& part, int n) {
+    hipLaunchKernelGGL((psf_kernel<P, TWc, R>), dim3(n), dim3(threads), lds, stream, part, L, out, partials, mode);
+    return hipGetLastError();
+  });
 }
 
 template <int P, int R>

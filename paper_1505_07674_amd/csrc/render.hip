@@ -161,8 +161,10 @@ hipError_t launch_rule_error(const WorkArgs& w, const PointConst* pcs, float* E,
 hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L, int n_blocks,
                          const CuspList& cl, hipStream_t stream, hipEvent_t between) {
   if (n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(render_kernel, dim3(n_blocks), dim3(RENDER_BLOCK), 0, stream, w, pcs, L, cl);
-  hipError_t e = hipGetLastError();
+  hipError_t e = for_item_parts(w, n_blocks, [&](const WorkArgs& part, int n) {
+    hipLaunchKernelGGL(render_kernel, dim3(n), dim3(RENDER_BLOCK), 0, stream, part, pcs, L, cl);
+    return hipGetLastError();
+  });
   if (e != hipSuccess) return e;
   if (between && (e = hipEventRecord(between, stream)) != hipSuccess) return e;
   const int waves = n_blocks * (RENDER_BLOCK / 64);   // list capacity

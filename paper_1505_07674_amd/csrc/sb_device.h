@@ -187,6 +187,13 @@ __device__ __forceinline__ void subsample_light(const PointConst& c, const RowTe
   s = sersic_shape(sR2, c.se, c.sB);
 }
 
+// Lens-light and source sums times their amplitudes, the low parts first (they
+// are zero unless an amplitude was derived from a magnitude).
+__device__ __forceinline__ float amplitudes(const PointConst& c, float sh, float ss) {
+  const float lo = fmaf(c.hIlo, sh, c.sIlo * ss);
+  return fmaf(c.hI, sh, fmaf(c.sI, ss, lo));
+}
+
 // Sum of the surface brightness over the N x N midpoint abscissae of a pixel.
 template <int N, int RM>
 __device__ __forceinline__ float pixel_sum(const PointConst& c, const PixelGeom& g, bool& cusp) {
@@ -205,7 +212,7 @@ __device__ __forceinline__ float pixel_sum(const PointConst& c, const PixelGeom&
       ss += s;
     }
   }
-  return fmaf(c.hI, sh, c.sI * ss);
+  return amplitudes(c, sh, ss);
 }
 
 template <int RM>
@@ -220,7 +227,7 @@ __device__ __forceinline__ float pixel_sum_rt(const PointConst& c, int N, const 
       ss += s;
     }
   }
-  return fmaf(c.hI, sh, c.sI * ss);
+  return amplitudes(c, sh, ss);
 }
 
 // (R/R_e)^2 of the source seen by the float32 render at subsample (x, y).
@@ -290,8 +297,8 @@ __device__ __forceinline__ float pixel_sum_gk(const PointConst& c, const PixelGe
       gs = fmaf(R.g[ky], qs, gs);
     }
   }
-  if (ERR) *gauss = fmaf(c.hI, gh, c.sI * gs);
-  return fmaf(c.hI, sh, c.sI * ss);
+  if (ERR) *gauss = amplitudes(c, gh, gs);
+  return amplitudes(c, sh, ss);
 }
 
 // Correction for one flagged pixel: for every subsample in the cusp zone, the

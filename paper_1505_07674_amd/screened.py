@@ -1,10 +1,11 @@
 """Nested sampling with and without the learned screen, on the GPU likelihood.
 
 ``GpuLogLike`` turns unit-cube points of the free parameters into float64 log L
-through the batched library path (one graph launch per call). It pads every
-call up to a power-of-two bucket so that the library's cached launch plans are
-reused instead of rebuilt for each new batch size; padding rows are copies of
-the first point and are not counted as evaluations.
+through the batched library path (one graph launch per call of at most
+``max_batch`` points; longer calls are split). It pads every call up to a
+power-of-two bucket so that the library's cached launch plans are reused
+instead of rebuilt for each new batch size; padding rows are copies of the
+first point and are not counted as evaluations.
 
 ``SurrogateScreen`` wraps a trained ``Surrogate`` as the sampler's screen. Its
 margin starts from the held-out residuals and is recalibrated as the run goes:
@@ -39,7 +40,7 @@ from .surrogate import Surrogate
 
 class GpuLogLike:
     def __init__(self, spec: SystemSpec, obs: Observation, device: torch.device, min_bucket: int = 64,
-                 ctx: Optional[binding.Context] = None):
+                 ctx: Optional[binding.Context] = None, max_batch: int = 16384):
         self.spec = spec
         self.device = device
         self.free = spec.prior.free
@@ -47,7 +48,7 @@ class GpuLogLike:
         self.system = binding.System(torch.from_numpy(spec.psf).to(device), torch.from_numpy(obs.data).to(device),
                                      torch.from_numpy(obs.weight).to(device), pixscale=spec.pixscale,
                                      nsub=spec.nsub, center=(spec.center_x, spec.center_y))
-        self.min_bucket = min_bucket
+        self.min_bucket, self.max_batch = min_bucket, max_batch
         self.buffers: Dict[int, tuple] = {}
         self.n_calls = 0
         self.n_points = 0
@@ -64,6 +65,8 @@ class GpuLogLike:
         n = len(u)
         if n == 0:
             return np.zeros(0)
+        if n > self.max_batch:                     # bounded scratch and plan sizes
+            return np.concatenate([self(u[i:i + self.max_batch]) for i in range(0, n, self.max_batch)])
         cap = max(self.min_bucket, 1 << (n - 1).bit_length())
         if cap not in self.buffers:
             self.buffers[cap] = (torch.empty((cap, 17), dtype=torch.float32, device=self.device),
@@ -114,7 +117,7 @@ class SurrogateScreen(Screen):
                  max_skips: int = 2000, keep: int = 65536, pool=None, refit_every: int = 10,
                  band_min: float = 50.0, band_frac: float = 0.5, refit_max: int = 60000, refit_steps: int = 300,
                  seed: int = 0, trust_sigmas: Optional[float] = None, quantile: Optional[float] = None,
-                 safety: float = 1.25, quantile_window: int = 1000):
+                 safety: float = 1.25, quantile_window: int = 1000, refit_batch: int = 1024):
         self.surrogate = surrogate
         self.sigmas = sigmas
         self.trust_sigmas = sigmas if trust_sigmas is None else trust_sigmas
@@ -126,7 +129,7 @@ class SurrogateScreen(Screen):
         self.pool = None if pool is None else (np.asarray(pool[0], np.float32), np.asarray(pool[1], np.float64))
         self.refit_every = refit_every
         self.band_min, self.band_frac = band_min, band_frac
-        self.refit_max, self.refit_steps = refit_max, refit_steps
+        self.refit_max, self.refit_steps, self.refit_batch = refit_max, refit_steps, refit_batch
         self.rng = np.random.default_rng(seed)
         self.last_refit = None
         self.refits = []
@@ -180,7 +183,7 @@ class SurrogateScreen(Screen):
         if len(ll) > self.refit_max:
             pick = self.rng.choice(len(ll), self.refit_max, replace=False)
             u, ll = u[pick], ll[pick]
-        info = self.surrogate.refit(u, ll, steps=self.refit_steps, seed=it)
+        info = self.surrogate.refit(u, ll, steps=self.refit_steps, batch=self.refit_batch, seed=it)
         info.update({"it": it, "lmin": lmin, "band": band})
         self.refits.append(info)
         self.last_refit = it
@@ -299,12 +302,12 @@ class ScreenExperiment:
                  state_dir: Optional[str] = None, deadline: Optional[float] = None, chunk: int = 25,
                  local: bool = True, refit_every: int = 5, refit_steps: int = 400, band_min: float = 25.0,
                  floor: float = 0.1, trust_sigmas: float = 3.0, quantile: Optional[float] = None,
-                 safety: float = 1.25):
+                 safety: float = 1.25, refit_batch: int = 1024):
         self.spec, self.obs, self.device = spec, obs, device
         self.n_live, self.k_replace, self.seeds, self.dlogz, self.max_iter = n_live, k_replace, seeds, dlogz, max_iter
         self.train_epochs, self.train_batch = train_epochs, train_batch
         self.sigmas, self.trust_sigmas, self.floor = sigmas, trust_sigmas, floor
-        self.quantile, self.safety = quantile, safety
+        self.quantile, self.safety, self.refit_batch = quantile, safety, refit_batch
         self.log, self.log_every, self.record_per_iter, self.audit = log, log_every, record_per_iter, audit
         self.state_dir, self.deadline, self.chunk = state_dir, deadline, chunk
         self.local, self.refit_every, self.refit_steps, self.band_min = local, refit_every, refit_steps, band_min
@@ -399,7 +402,7 @@ class ScreenExperiment:
                 sur, sigmas=self.sigmas, pool=(ra.evaluated_u, ra.evaluated_logl) if self.local else None,
                 seed=self.seeds[2], refit_every=self.refit_every, refit_steps=self.refit_steps,
                 band_min=self.band_min, floor=self.floor, trust_sigmas=self.trust_sigmas, quantile=self.quantile,
-                safety=self.safety)
+                safety=self.safety, refit_batch=self.refit_batch)
             self.log(f"screened run C, seed {self.seeds[2]}" +
                      (f" (network refitted locally every {self.refit_every} iterations)" if self.local else ""))
             rc, wc = self._runs["c"] = self._run("screened_c", self.seeds[2], screen=self._screen,
@@ -430,6 +433,7 @@ class ScreenExperiment:
                "settings": {"sigmas": self.sigmas, "trust_sigmas": self.trust_sigmas, "quantile": self.quantile,
                             "safety": self.safety, "floor": self.floor,
                             "refit_every": self.refit_every, "refit_steps": self.refit_steps,
+                            "refit_batch": self.refit_batch,
                             "band_min": self.band_min, "local": self.local},
                "n_pairs_recorded": int(0 if ra.evaluated_u is None else len(ra.evaluated_u)),
                "refits": self._screen.refits if self._screen is not None else []}
@@ -477,6 +481,7 @@ def main(argv=None) -> int:
                     help="slice proposals predicted this many residual RMS above the threshold skip the render")
     ap.add_argument("--refit-every", type=int, default=5)
     ap.add_argument("--refit-steps", type=int, default=400)
+    ap.add_argument("--refit-batch", type=int, default=1024)
     ap.add_argument("--max-iter", type=int, default=5000)
     ap.add_argument("--audit", type=float, default=0.0, help="fraction of screened-out draws also evaluated exactly")
     ap.add_argument("--state-dir", default=None, help="save finished runs and checkpoints here; resume from it")
@@ -499,7 +504,7 @@ def main(argv=None) -> int:
                                                                         mocks.C4_SEED + 2), log=log,
                            audit=a.audit, state_dir=a.state_dir, deadline=deadline, trust_sigmas=a.trust_sigmas,
                            refit_every=a.refit_every, refit_steps=a.refit_steps, quantile=a.quantile,
-                           safety=a.safety)
+                           safety=a.safety, refit_batch=a.refit_batch)
     except Suspended as e:
         print(f"suspended: {e}", flush=True)
         return 3

@@ -51,7 +51,11 @@ def test_host_only_calls(lib):
 
 def test_binding_mirrors_the_struct_layout():
     from paper_1505_07674_amd.binding import LensedSystemC
-    # int32 H, W; float pixscale, cx, cy; int32 nsub, ph, pw; three pointers; int32 rule (+ tail padding)
+    # int32 H, W; float pixscale, cx, cy; int32 nsub, ph, pw; three pointers; int32 rule, amplitude;
+    # float zero_point; int32 source_position
     assert LensedSystemC.psf.offset == 32
     assert LensedSystemC.rule.offset == 8 * 4 + 3 * 8
-    assert ctypes.sizeof(LensedSystemC) == 8 * 4 + 3 * 8 + 8
+    assert LensedSystemC.amplitude.offset == 8 * 4 + 3 * 8 + 4
+    assert LensedSystemC.zero_point.offset == 8 * 4 + 3 * 8 + 8
+    assert LensedSystemC.source_position.offset == 8 * 4 + 3 * 8 + 12
+    assert ctypes.sizeof(LensedSystemC) == 8 * 4 + 3 * 8 + 16
