@@ -11,7 +11,10 @@ constexpr float LN2F = 0.693147180559945309f;
 constexpr double LOG2E = 1.44269504088896340736;
 // Source-plane radius around a cuspy source centre inside which subsamples are
 // re-traced in float64 (the float32 ray position carries ~1e-7 arcsec of rounding).
+// With an image-plane source position every point puts the source centre on one
+// of its images, where the lens magnifies that rounding; the radius doubles.
 constexpr double CUSP_RADIUS_ARCSEC = 0.03;
+constexpr double CUSP_RADIUS_IMAGE_PLANE_ARCSEC = 0.06;
 
 // Per-point constants derived once from the 17 parameters (prologue kernel).
 // Read with wave-uniform addresses, so they live in scalar registers in the

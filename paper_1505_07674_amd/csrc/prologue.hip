@@ -305,9 +305,9 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
     c.sB = (float)(bs * LOG2E);
     c.sI = (float)Is;
   }
-  // re-trace in float64 within 0.03 arcsec (source plane) of a cuspy (n > 1) source centre
+  // re-trace in float64 near a cuspy (n > 1) source centre (source-plane radius)
   {
-    const double Re = t[13], rc = CUSP_RADIUS_ARCSEC / Re;
+    const double Re = t[13], rc = (srcpos ? CUSP_RADIUS_IMAGE_PLANE_ARCSEC : CUSP_RADIUS_ARCSEC) / Re;
     c.cusp_r2 = t[14] > 1.0f ? (float)(rc * rc) : 0.0f;
   }
   for (int k = 0; k < 4; ++k) c.pad[k] = 0.0f;

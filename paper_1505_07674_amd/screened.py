@@ -302,7 +302,7 @@ class ScreenExperiment:
                  state_dir: Optional[str] = None, deadline: Optional[float] = None, chunk: int = 25,
                  local: bool = True, refit_every: int = 5, refit_steps: int = 400, band_min: float = 25.0,
                  floor: float = 0.1, trust_sigmas: float = 3.0, quantile: Optional[float] = None,
-                 safety: float = 1.25, refit_batch: int = 1024):
+                 safety: float = 1.25, refit_batch: int = 4096):
         self.spec, self.obs, self.device = spec, obs, device
         self.n_live, self.k_replace, self.seeds, self.dlogz, self.max_iter = n_live, k_replace, seeds, dlogz, max_iter
         self.train_epochs, self.train_batch = train_epochs, train_batch
@@ -481,7 +481,7 @@ def main(argv=None) -> int:
                     help="slice proposals predicted this many residual RMS above the threshold skip the render")
     ap.add_argument("--refit-every", type=int, default=5)
     ap.add_argument("--refit-steps", type=int, default=400)
-    ap.add_argument("--refit-batch", type=int, default=1024)
+    ap.add_argument("--refit-batch", type=int, default=4096)
     ap.add_argument("--max-iter", type=int, default=5000)
     ap.add_argument("--audit", type=float, default=0.0, help="fraction of screened-out draws also evaluated exactly")
     ap.add_argument("--state-dir", default=None, help="save finished runs and checkpoints here; resume from it")

@@ -86,6 +86,7 @@ def test_image_plane_loglike_and_gradient_match_the_oracle(amplitude):
     assert np.allclose(ll, lb, rtol=1e-12, atol=0)
     rll, rg = oracle_grads(osys(spec, obs, amplitude), pts)
     err = np.abs(ll - rll) / loglike_tolerance(rll, obs.weight)
+    say(f"log L errors / bar: max {err.max():.3f} at point {int(np.argmax(err))}")
     assert np.all(err <= 1.0), (err, rll)
     rel = np.linalg.norm(gr - rg, axis=1) / np.linalg.norm(rg, axis=1)
     assert rel.max() <= 1e-4, (rel.max(), int(np.argmax(rel)))
