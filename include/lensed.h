@@ -175,6 +175,36 @@ int lensed_loglike_batch(lensed_ctx* ctx, const lensed_system* systems, int n_sy
  * near a cuspy source centre that lensed_render applies. */
 int lensed_render_error(lensed_ctx* ctx, const lensed_system* sys, const float* theta, float* error, void* stream);
 
+/* ---- Composite models ---------------------------------------------------
+ * The paper's fits of real lenses (Sec. 5) add further Sersic components and a
+ * flat sky to the base model. A composite model here is K parameter points
+ * (each a full 17-parameter point: give the components the same lens
+ * parameters to describe one lens with several light components) whose pixel
+ * luminosities are summed, plus a flat sky of surface brightness `sky` (pixel
+ * luminosity sky * pixscale^2); the PSF (Eq. 15) applies to the sum. */
+
+/* Model image of one composite model.
+ *   theta         device float32 [n_components * 17], component j at theta + 17 j
+ *   n_components  1..64
+ *   sky           flat sky surface brightness (finite)
+ *   image         device float32 [height * width], written
+ * Components are summed in float64 per pixel. */
+int lensed_render_composite(lensed_ctx* ctx, const lensed_system* sys, const float* theta, int n_components,
+                            float sky, float* image, int apply_psf, void* stream);
+
+/* log L (Eq. 17) of n_models composite models of n_components points each, in
+ * one graph launch like lensed_loglike_batch.
+ *   theta            device float32 [n_models * n_components * 17]; model m is the
+ *                    n_components consecutive points starting at point m * n_components
+ *   sky              device float32 [n_models], or NULL for no sky
+ *   system_of_model  HOST int32 [n_models], indices into systems
+ *   logl             device float64 [n_models], written
+ * n_components = 1 with sky = NULL is lensed_loglike_batch. Errors as there;
+ * LENSED_INVALID_ARGUMENT for n_components < 1. */
+int lensed_loglike_composite(lensed_ctx* ctx, const lensed_system* systems, int n_systems, const float* theta,
+                             int n_components, const float* sky, const int32_t* system_of_model, int n_models,
+                             double* logl, void* stream);
+
 /* Weights of an observation that comes without a variance map (Sec. 3.3,
  * Eqs. 18-21). The photon counts k_i = g_i (d_i + b_i) (effective gain g_i =
  * electronic gain x exposure time; offset b_i = whatever was subtracted from

@@ -235,3 +235,20 @@ def loglike_grad(system, theta):
     g = np.zeros(NPAR)
     v = lib().lo_loglike_grad(system.ptr, _dp(t), _dp(g))
     return v, g
+
+
+def render_composite(system, thetas, sky=0.0, apply_psf=True):
+    """Model image of a composite model (Sec. 5: several light components and a
+    flat sky): the sum of the components' pixel luminosities (each a 17-parameter
+    point) plus the sky's, sky x pixscale^2 per pixel, then the PSF (Eq. 15)."""
+    L = sum(render(system, t, apply_psf=False) for t in np.atleast_2d(thetas))
+    L = L + float(sky) * system.pixscale ** 2
+    return psf_convolve(L, system.psf) if apply_psf else L
+
+
+def loglike_composite(system, thetas, sky=0.0):
+    """log L (Eq. 17) of a composite model: -1/2 sum_i w_i (d_i - L*_i)^2 with the
+    compensated sum."""
+    m = render_composite(system, thetas, sky).reshape(-1)
+    r = system.data - m
+    return -0.5 * sum_compensated(system.weight * r * r)

@@ -70,6 +70,8 @@ def lib():
                 "lensed_last_error": (cp, [vp]),
                 "lensed_render": (i, [vp, sp, vp, vp, i, vp]),
                 "lensed_render_error": (i, [vp, sp, vp, vp, vp]),
+                "lensed_render_composite": (i, [vp, sp, vp, i, ctypes.c_float, vp, i, vp]),
+                "lensed_loglike_composite": (i, [vp, sp, i, vp, i, vp, ctypes.POINTER(ctypes.c_int32), i, vp, vp]),
                 "lensed_weights_from_data": (i, [vp, vp, ctypes.c_int64, ctypes.c_double, vp, ctypes.c_double, vp, vp,
                                                  vp, vp]),
                 "lensed_loglike": (i, [vp, sp, vp, vp, vp]),
@@ -248,6 +250,21 @@ def render(theta: torch.Tensor, system: System, apply_psf: bool = True, *, ctx: 
     return out
 
 
+def render_composite(theta: torch.Tensor, system: System, sky: float = 0.0, apply_psf: bool = True, *,
+                     ctx: Optional[Context] = None, stream=None) -> torch.Tensor:
+    """Model image [H, W] of one composite model: the summed pixel luminosities of
+    the K points theta [K, 17] plus a flat sky (sky x pixscale^2 per pixel), then
+    the PSF (Sec. 5)."""
+    t = _theta2d(theta)
+    ctx = ctx or default_context(t.device.index)
+    out = torch.empty((system.height, system.width), dtype=torch.float32, device=t.device)
+    rc = lib().lensed_render_composite(ctx.handle, ctypes.byref(system.c_struct), ctypes.c_void_p(t.data_ptr()),
+                                       t.shape[0], float(sky), ctypes.c_void_p(out.data_ptr()), int(bool(apply_psf)),
+                                       _stream_handle(stream))
+    ctx.check(rc, "lensed_render_composite")
+    return out
+
+
 def render_error(theta: torch.Tensor, system: System, *, ctx: Optional[Context] = None,
                  stream=None) -> torch.Tensor:
     """Per-pixel |Kronrod - embedded Gauss| estimate [H, W] of a Gauss-Kronrod system (before the PSF)."""
@@ -332,6 +349,35 @@ def loglike_batch(theta: torch.Tensor, system_of_point, systems: Sequence[System
                                     sop.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), P,
                                     ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
     ctx.check(rc, "lensed_loglike_batch")
+    return out
+
+
+def loglike_composite(theta: torch.Tensor, n_components: int, system_of_model, systems: Sequence[System],
+                      sky: Optional[torch.Tensor] = None, *, out: Optional[torch.Tensor] = None,
+                      ctx: Optional[Context] = None, stream=None) -> torch.Tensor:
+    """log L of M composite models of K = n_components points each (theta [M K, 17],
+    model m = rows m K .. m K + K - 1; sky: float32 [M] device tensor or None) ->
+    float64 [M] (Sec. 5, Eq. 17)."""
+    t = _theta2d(theta)
+    K = int(n_components)
+    if K < 1 or t.shape[0] % K:
+        raise ValueError("theta must hold n_components rows per model")
+    M = t.shape[0] // K
+    som = np.ascontiguousarray(np.asarray(system_of_model, dtype=np.int32).reshape(-1))
+    if som.size != M:
+        raise ValueError("system_of_model must have one entry per model")
+    if sky is not None and (sky.dtype != torch.float32 or sky.device != t.device or sky.numel() != M or
+                            not sky.is_contiguous()):
+        raise ValueError("sky must be a contiguous float32 tensor of one value per model on theta's device")
+    ctx = ctx or default_context(t.device.index)
+    if out is None:
+        out = torch.empty(M, dtype=torch.float64, device=t.device)
+    sa = _SystemArray(systems)
+    sky_p = None if sky is None else ctypes.c_void_p(sky.data_ptr())
+    rc = lib().lensed_loglike_composite(ctx.handle, sa.arr, len(sa.systems), ctypes.c_void_p(t.data_ptr()), K, sky_p,
+                                        som.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), M,
+                                        ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+    ctx.check(rc, "lensed_loglike_composite")
     return out
 
 

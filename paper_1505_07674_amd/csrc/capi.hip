@@ -2,6 +2,7 @@
 // workspace, the plain launch sequences and the batched plans (work lists,
 // scratch layout, captured hipGraphs).
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
@@ -41,6 +42,7 @@ struct lensed_ctx {
   int stage_calls = 0;
   char* mlp_mem = nullptr;                          // surrogate scratch
   MlpScratch mlp;
+  std::vector<int32_t> composite_map;               // system of every point of a composite launch
 };
 
 namespace {
@@ -288,6 +290,52 @@ int lensed_render(lensed_ctx* c, const lensed_system* sys, const float* theta, f
   return LENSED_OK;
 }
 
+int lensed_render_composite(lensed_ctx* c, const lensed_system* sys, const float* theta, int n_components, float sky,
+                            float* image, int apply_psf, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  int rc = validate_system(c, sys, false, -1);
+  if (rc) return rc;
+  if (n_components < 1 || n_components > 64)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "n_components must be in 1..64");
+  if (!std::isfinite(sky)) return set_err(c, LENSED_INVALID_ARGUMENT, "sky must be finite");
+  if (!theta || !image) return set_err(c, LENSED_INVALID_ARGUMENT, "theta and image are required");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int K = n_components;
+  const TileShape ts = c->tiles.choose(*sys);
+  SysDesc sd = make_desc(*sys, ts);
+  const size_t npix = (size_t)sd.H * sd.W;
+  const size_t off_pc = 0;
+  const size_t off_p64 = align_up(off_pc + sizeof(PointConst) * K, 256);
+  const size_t off_psf = align_up(off_p64 + sizeof(PointConst64) * K, 256);
+  const size_t off_cc = align_up(off_psf + 3 * sizeof(float) * sd.ph * sd.pw, 256);
+  const size_t off_ce = align_up(off_cc + sizeof(int), 256);
+  const size_t off_L = align_up(off_ce + sizeof(CuspEntry) * (size_t)sd.n_rtiles * (RENDER_BLOCK / 64), 256);
+  const size_t total = align_up(off_L + sizeof(float) * npix * K, 256);
+  if ((rc = ensure_arena(c, total))) return rc;
+  PointConst* pc = (PointConst*)(c->arena + off_pc);
+  PointConst64* p64 = (PointConst64*)(c->arena + off_p64);
+  CuspList cl{(CuspEntry*)(c->arena + off_ce), (int*)(c->arena + off_cc)};
+  sd.psfn = (float*)(c->arena + off_psf);
+  float* L = (float*)(c->arena + off_L);
+  WorkArgs w;
+  std::memset(&w, 0, sizeof(w));
+  w.single = sd;
+  LENSED_HIP(c, launch_prologue(theta, K, pc, p64, nullptr, sd, nullptr, 1, cl.count, st));
+  for (int j = 0; j < K; ++j) {       // one component at a time: its cusp list starts empty
+    if (j > 0) LENSED_HIP(c, launch_zero_count(cl.count, st));
+    w.point0 = j;
+    LENSED_HIP(c, launch_render(w, pc, p64, L + (size_t)j * npix, sd.n_rtiles, cl, st));
+  }
+  const double sky_px = (double)sky * (double)sd.d * (double)sd.d;
+  LENSED_HIP(c, launch_sum_images(L, (int64_t)npix, K, sky_px, apply_psf ? L : image, st));
+  w.point0 = 0;
+  if (apply_psf)
+    LENSED_HIP(c, launch_psf(w, L, image, nullptr, 0, sd.n_ptiles, square_psf_code(sd.ph, sd.pw), sd.TW, sd.TH,
+                             sd.ph, sd.pw, st));
+  return LENSED_OK;
+}
+
 int lensed_render_error(lensed_ctx* c, const lensed_system* sys, const float* theta, float* error, void* stream) {
   if (!c) return LENSED_INVALID_ARGUMENT;
   int rc = validate_system(c, sys, false, -1);
@@ -367,25 +415,16 @@ int lensed_loglike(lensed_ctx* c, const lensed_system* sys, const float* theta, 
   return LENSED_OK;
 }
 
-int lensed_loglike_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const float* theta,
-                         const int32_t* system_of_point, int n_points, double* logl, void* stream) {
-  if (!c) return LENSED_INVALID_ARGUMENT;
-  if (n_points < 0) return set_err(c, LENSED_INVALID_ARGUMENT, "n_points must be >= 0");
-  if (n_points == 0) return LENSED_OK;
-  if (!systems || n_systems <= 0) return set_err(c, LENSED_INVALID_ARGUMENT, "at least one system is required");
-  if (!theta || !logl || !system_of_point)
-    return set_err(c, LENSED_INVALID_ARGUMENT, "theta, system_of_point and logl are required");
-  for (int s = 0; s < n_systems; ++s) {
-    const int rc = validate_system(c, &systems[s], true, s);
-    if (rc) return rc;
-  }
-  for (int p = 0; p < n_points; ++p)
-    if (system_of_point[p] < 0 || system_of_point[p] >= n_systems)
-      return set_err(c, LENSED_INVALID_ARGUMENT, "system_of_point[" + std::to_string(p) + "] out of range");
-  LENSED_HIP(c, hipSetDevice(c->device));
+namespace {
+
+// The batched log L of lensed_loglike_batch (K = 1, no sky) and of
+// lensed_loglike_composite: find or build the plan for these arguments (with
+// the autotuner on a new set of shapes), then replay its graph.
+int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const float* theta,
+              const int32_t* system_of_point, int n_points, double* logl, void* stream, int K, const float* sky) {
   BatchPlan* plan = nullptr;
   for (size_t i = 0; i < c->plans.size(); ++i) {
-    if (c->plans[i]->matches(systems, n_systems, theta, system_of_point, n_points, logl)) {
+    if (c->plans[i]->matches(systems, n_systems, theta, system_of_point, n_points, logl, nullptr, K, sky)) {
       std::unique_ptr<BatchPlan> keep = std::move(c->plans[i]);
       c->plans.erase(c->plans.begin() + i);
       c->plans.push_back(std::move(keep));
@@ -408,8 +447,8 @@ int lensed_loglike_batch(lensed_ctx* c, const lensed_system* systems, int n_syst
       for (const TileShape& t : cand) {
         BatchPlan trial;
         std::string msg;
-        if (trial.build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg, nullptr, &t) !=
-            hipSuccess) {
+        if (trial.build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg, nullptr, &t, K,
+                        sky) != hipSuccess) {
           (void)hipGetLastError();
           continue;
         }
@@ -424,7 +463,8 @@ int lensed_loglike_batch(lensed_ctx* c, const lensed_system* systems, int n_syst
     }
     std::unique_ptr<BatchPlan> np(new BatchPlan());
     std::string msg;
-    hipError_t e = np->build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg);
+    hipError_t e = np->build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg, nullptr,
+                             nullptr, K, sky);
     if (e != hipSuccess) return hip_fail(c, e, ("batch plan: " + msg).c_str());
     if (c->use_graphs) {
       e = np->capture(c->cap);
@@ -442,6 +482,53 @@ int lensed_loglike_batch(lensed_ctx* c, const lensed_system* systems, int n_syst
   }
   LENSED_HIP(c, plan->run((hipStream_t)stream));
   return LENSED_OK;
+}
+
+}  // namespace
+
+int lensed_loglike_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const float* theta,
+                         const int32_t* system_of_point, int n_points, double* logl, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  if (n_points < 0) return set_err(c, LENSED_INVALID_ARGUMENT, "n_points must be >= 0");
+  if (n_points == 0) return LENSED_OK;
+  if (!systems || n_systems <= 0) return set_err(c, LENSED_INVALID_ARGUMENT, "at least one system is required");
+  if (!theta || !logl || !system_of_point)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "theta, system_of_point and logl are required");
+  for (int s = 0; s < n_systems; ++s) {
+    const int rc = validate_system(c, &systems[s], true, s);
+    if (rc) return rc;
+  }
+  for (int p = 0; p < n_points; ++p)
+    if (system_of_point[p] < 0 || system_of_point[p] >= n_systems)
+      return set_err(c, LENSED_INVALID_ARGUMENT, "system_of_point[" + std::to_string(p) + "] out of range");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  return run_batch(c, systems, n_systems, theta, system_of_point, n_points, logl, stream, 1, nullptr);
+}
+
+int lensed_loglike_composite(lensed_ctx* c, const lensed_system* systems, int n_systems, const float* theta,
+                             int n_components, const float* sky, const int32_t* system_of_model, int n_models,
+                             double* logl, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  if (n_models < 0) return set_err(c, LENSED_INVALID_ARGUMENT, "n_models must be >= 0");
+  if (n_components < 1) return set_err(c, LENSED_INVALID_ARGUMENT, "n_components must be >= 1");
+  if (n_models == 0) return LENSED_OK;
+  if ((int64_t)n_models * n_components > INT32_MAX / NPAR)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "n_models x n_components too large");
+  if (!systems || n_systems <= 0) return set_err(c, LENSED_INVALID_ARGUMENT, "at least one system is required");
+  if (!theta || !logl || !system_of_model)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "theta, system_of_model and logl are required");
+  for (int s = 0; s < n_systems; ++s) {
+    const int rc = validate_system(c, &systems[s], true, s);
+    if (rc) return rc;
+  }
+  for (int m = 0; m < n_models; ++m)
+    if (system_of_model[m] < 0 || system_of_model[m] >= n_systems)
+      return set_err(c, LENSED_INVALID_ARGUMENT, "system_of_model[" + std::to_string(m) + "] out of range");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  const int n_points = n_models * n_components;
+  c->composite_map.resize(n_points);
+  for (int p = 0; p < n_points; ++p) c->composite_map[p] = system_of_model[p / n_components];
+  return run_batch(c, systems, n_systems, theta, c->composite_map.data(), n_points, logl, stream, n_components, sky);
 }
 
 int lensed_set_profiling(lensed_ctx* c, int enable) {

@@ -58,6 +58,19 @@ hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, Po
 hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L, int n_blocks,
                          const CuspList& cl, hipStream_t stream, hipEvent_t between = nullptr);
 
+// Composite models (K consecutive points each): L[first image of model m] =
+// sum of its K unconvolved images + sky[m] pixscale^2 (sky may be nullptr), in
+// float64 per pixel, before the PSF stage. tiles_per_model: RENDER_BLOCK-pixel
+// tiles of the largest image.
+hipError_t launch_compose(float* L, const int64_t* loff, const int* point_sys, const SysDesc* sys, int K, int n_models,
+                          const float* sky, int tiles_per_model, hipStream_t stream);
+
+// One composite model of a plain call: out = sum of the K consecutive images of
+// npix pixels in L + sky_px, in float64 (out may be L).
+hipError_t launch_sum_images(const float* L, int64_t npix, int K, double sky_px, float* out, hipStream_t stream);
+// *count = 0 by a kernel (capturable, unlike a memset node).
+hipError_t launch_zero_count(int* count, hipStream_t stream);
+
 // Weights from the data (Sec. 3.3): w = extra * g / (d + b) where g (d + b) > 0, else 0.
 // gain_map / offset_map / extra may be nullptr (scalar gain, scalar offset, 1).
 hipError_t launch_weights_from_data(const float* data, int64_t n, double gain, const float* gain_map, double offset,

@@ -53,18 +53,19 @@ class BatchPlan {
  public:
   ~BatchPlan();
   // grad == nullptr: log L only; otherwise also d log L / d theta (single system).
+  // K > 1 or sky: composite models of K consecutive points each (one log L per
+  // model, of the summed images plus sky[m] pixscale^2); map has one entry per point.
   bool matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map, int n_points,
-               const double* logl, const float* grad = nullptr) const;
+               const double* logl, const float* grad = nullptr, int K = 1, const float* sky = nullptr) const;
   // force: use this tile shape instead of the cache's choice (autotuning)
   hipError_t build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
                    int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad = nullptr,
-                   const TileShape* force = nullptr);
+                   const TileShape* force = nullptr, int K = 1, const float* sky = nullptr);
   // Runs the plan stage by stage twice on s and returns the second run's PSF + chi^2 milliseconds.
   hipError_t psf_ms(hipStream_t s, float* ms) const;
   hipError_t capture(hipStream_t cap);
   // events, when given, are LENSED_NSTAGES + 1 events recorded around the stages
-  // (prologue, render kernel, cusp corrections, PSF + chi^2, finalize)
-  // (prologue, render, PSF + chi^2, finalize)
+  // (prologue, render kernel, cusp corrections and composition, PSF + chi^2, finalize)
   hipError_t enqueue(hipStream_t s, hipEvent_t* events = nullptr) const;
   hipError_t run(hipStream_t s) const;
 
@@ -75,6 +76,12 @@ class BatchPlan {
   double* logl_ = nullptr;
   float* grad_ = nullptr;
   int n_points_ = 0;
+  int K_ = 1;                     // points per model
+  const float* sky_ = nullptr;    // [n_models] flat sky surface brightness, or nullptr
+  int n_models_ = 0;
+  int* d_mpbase_ = nullptr;       // first partial-sum slot of each model
+  int* d_mntiles_ = nullptr;      // PSF tiles of each model
+  int compose_tiles_ = 0;         // render tiles of the largest image
 
   char* mem_ = nullptr;
   SysDesc* d_sys_ = nullptr;

@@ -115,8 +115,8 @@ BatchPlan::~BatchPlan() {
 }
 
 bool BatchPlan::matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
-                        int n_points, const double* logl, const float* grad) const {
-  if (theta != theta_ || logl != logl_ || grad != grad_ || n_points != n_points_ ||
+                        int n_points, const double* logl, const float* grad, int K, const float* sky) const {
+  if (theta != theta_ || logl != logl_ || grad != grad_ || n_points != n_points_ || K != K_ || sky != sky_ ||
       (size_t)n_systems != systems_.size())
     return false;
   for (int s = 0; s < n_systems; ++s)
@@ -126,13 +126,16 @@ bool BatchPlan::matches(const lensed_system* systems, int n_systems, const float
 
 hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
                             int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad,
-                            const TileShape* force) {
+                            const TileShape* force, int K, const float* sky) {
   systems_.assign(systems, systems + n_systems);
   map_.assign(map, map + n_points);
   theta_ = theta;
   logl_ = logl;
   grad_ = grad;
   n_points_ = n_points;
+  K_ = K;
+  sky_ = sky;
+  n_models_ = n_points / K;
 
   const TileShape ts = force ? *force : tiles.choose_common(systems, n_systems);
   TW_ = ts.TW;
@@ -166,8 +169,8 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
     loff[p] = Ltot;
     Ltot += (int64_t)d.H * d.W;
     pbase[p] = ptot;
-    ntiles[p] = d.n_ptiles;
-    ptot += d.n_ptiles;
+    ntiles[p] = p % K == 0 ? d.n_ptiles : 0;
+    ptot += ntiles[p];
     gpbase[p] = gtot;
     gtot += d.n_rtiles;
     const int64_t npix = (int64_t)d.H * d.W;
@@ -175,6 +178,8 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
       const int64_t px = std::min<int64_t>(RENDER_BLOCK, npix - (int64_t)t * RENDER_BLOCK);
       ritems.push_back({px * d.N * d.N, p, t});
     }
+    compose_tiles_ = std::max(compose_tiles_, d.n_rtiles);
+    if (p % K != 0) continue;   // a composite model is blurred and compared once, on its first image
     for (int t = 0; t < d.n_ptiles; ++t) pitems.push_back({(int64_t)d.ph * d.pw, p, t});
   }
   auto by_cost = [](const Item& a, const Item& b) { return a.cost > b.cost; };
@@ -193,6 +198,8 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   const size_t o_loff = off; off = align256(off + sizeof(int64_t) * n_points);
   const size_t o_pb = off; off = align256(off + sizeof(int) * n_points);
   const size_t o_nt = off; off = align256(off + sizeof(int) * n_points);
+  const size_t o_mpb = off; off = align256(off + sizeof(int) * n_models_);
+  const size_t o_mnt = off; off = align256(off + sizeof(int) * n_models_);
   const size_t o_ri = off; off = align256(off + sizeof(int2) * n_ritems_);
   const size_t o_pi = off; off = align256(off + sizeof(int2) * n_pitems_);
   const size_t o_pc = off; off = align256(off + sizeof(PointConst) * n_points);
@@ -220,6 +227,8 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   d_loff_ = (int64_t*)(mem_ + o_loff);
   d_pbase_ = (int*)(mem_ + o_pb);
   d_ntiles_ = (int*)(mem_ + o_nt);
+  d_mpbase_ = (int*)(mem_ + o_mpb);
+  d_mntiles_ = (int*)(mem_ + o_mnt);
   d_ritems_ = (int2*)(mem_ + o_ri);
   d_pitems_ = (int2*)(mem_ + o_pi);
   d_pc_ = (PointConst*)(mem_ + o_pc);
@@ -240,11 +249,18 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   }
 
   std::vector<int> ps(map, map + n_points);
+  std::vector<int> mpbase(n_models_), mntiles(n_models_);
+  for (int m = 0; m < n_models_; ++m) {
+    mpbase[m] = pbase[(size_t)m * K];
+    mntiles[m] = ntiles[(size_t)m * K];
+  }
   if ((e = hipMemcpy(d_sys_, desc.data(), sizeof(SysDesc) * n_systems, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_point_sys_, ps.data(), sizeof(int) * n_points, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_loff_, loff.data(), sizeof(int64_t) * n_points, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_pbase_, pbase.data(), sizeof(int) * n_points, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_ntiles_, ntiles.data(), sizeof(int) * n_points, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(d_mpbase_, mpbase.data(), sizeof(int) * n_models_, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(d_mntiles_, mntiles.data(), sizeof(int) * n_models_, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_ritems_, ri.data(), sizeof(int2) * n_ritems_, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_pitems_, pi.data(), sizeof(int2) * n_pitems_, hipMemcpyHostToDevice)) != hipSuccess ||
       (g && (e = hipMemcpy(d_gpbase_, gpbase.data(), sizeof(int) * n_points, hipMemcpyHostToDevice)) != hipSuccess)) {
@@ -275,6 +291,9 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
   if ((e = launch_render(wr, d_pc_, d_p64_, d_L_, n_ritems_, cusp_, st, ev ? ev[2] : nullptr)) != hipSuccess)
     return e;
   if (ev && n_ritems_ <= 0 && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+  if ((K_ > 1 || sky_) &&
+      (e = launch_compose(d_L_, d_loff_, d_point_sys_, d_sys_, K_, n_models_, sky_, compose_tiles_, st)) != hipSuccess)
+    return e;
   if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
   WorkArgs wp = w;
   wp.items = d_pitems_;
@@ -284,7 +303,7 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
       hipSuccess)
     return e;
   if (ev && (e = hipEventRecord(ev[4], st)) != hipSuccess) return e;
-  if ((e = launch_finalize(d_part_, d_pbase_, d_ntiles_, n_points_, 0, logl_, st)) != hipSuccess) return e;
+  if ((e = launch_finalize(d_part_, d_mpbase_, d_mntiles_, n_models_, 0, logl_, st)) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[5], st)) != hipSuccess) return e;
   if (grad_) {
     // g = A^T rho overwrites the unconvolved images, which are no longer needed

@@ -158,6 +158,63 @@ hipError_t launch_rule_error(const WorkArgs& w, const PointConst* pcs, float* E,
   return hipGetLastError();
 }
 
+// Composite models (Sec. 5: extra Sersic components and a flat sky): the first
+// image of each model becomes the sum of the model's K images plus the sky's
+// pixel luminosity sky[m] pixscale^2, summed in float64. Block b walks the
+// (model, tile) items b, b + gridDim.x, ...
+__global__ __launch_bounds__(RENDER_BLOCK) void compose_kernel(float* __restrict__ L, const int64_t* __restrict__ loff,
+                                                                const int* __restrict__ point_sys,
+                                                                const SysDesc* __restrict__ sys, int K, int n_models,
+                                                                const float* __restrict__ sky, int tiles_per_model) {
+  const int64_t n_items = (int64_t)n_models * tiles_per_model;
+  for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const int m = (int)(item / tiles_per_model);
+    const int tile = (int)(item - (int64_t)m * tiles_per_model);
+    const int64_t p0 = (int64_t)m * K;
+    const SysDesc& sd = sys[point_sys ? point_sys[p0] : 0];
+    const int pix = tile * RENDER_BLOCK + (int)threadIdx.x;
+    if (pix >= sd.H * sd.W) continue;
+    double v = sky ? (double)sky[m] * (double)sd.d * (double)sd.d : 0.0;
+    for (int j = 0; j < K; ++j) v += (double)L[loff[p0 + j] + pix];
+    L[loff[p0] + pix] = (float)v;
+  }
+}
+
+// One composite model of a plain call: out = sum over j < K of L[j npix + pix],
+// plus sky_px (the sky's pixel luminosity), in float64; out may be L itself.
+__global__ __launch_bounds__(RENDER_BLOCK) void sum_images_kernel(const float* L, int64_t npix, int K, double sky_px,
+                                                                   float* out) {
+  const int64_t pix = (int64_t)blockIdx.x * RENDER_BLOCK + threadIdx.x;
+  if (pix >= npix) return;
+  double v = sky_px;
+  for (int j = 0; j < K; ++j) v += (double)L[(int64_t)j * npix + pix];
+  out[pix] = (float)v;
+}
+
+__global__ void zero_count_kernel(int* count) { *count = 0; }
+
+hipError_t launch_sum_images(const float* L, int64_t npix, int K, double sky_px, float* out, hipStream_t stream) {
+  if (npix <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sum_images_kernel, dim3((unsigned)((npix + RENDER_BLOCK - 1) / RENDER_BLOCK)), dim3(RENDER_BLOCK),
+                     0, stream, L, npix, K, sky_px, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_count(int* count, hipStream_t stream) {
+  hipLaunchKernelGGL(zero_count_kernel, dim3(1), dim3(1), 0, stream, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_compose(float* L, const int64_t* loff, const int* point_sys, const SysDesc* sys, int K, int n_models,
+                          const float* sky, int tiles_per_model, hipStream_t stream) {
+  const int64_t n_items = (int64_t)n_models * tiles_per_model;
+  if (n_items <= 0) return hipSuccess;
+  const int grid = (int)(n_items < 65536 ? n_items : 65536);
+  hipLaunchKernelGGL(compose_kernel, dim3(grid), dim3(RENDER_BLOCK), 0, stream, L, loff, point_sys, sys, K, n_models,
+                     sky, tiles_per_model);
+  return hipGetLastError();
+}
+
 hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L, int n_blocks,
                          const CuspList& cl, hipStream_t stream, hipEvent_t between) {
   if (n_blocks <= 0) return hipSuccess;

@@ -1,0 +1,109 @@
+"""GPU parity of composite models (Sec. 5: extra Sersic components and a flat
+sky on top of the base model) against the FP64 oracle: images, batched log L of
+models with 2 and 3 components and a sky over two systems, the one-component
+case against the plain batch, and the argument checks."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1505_07674_amd as lensed
+from paper_1505_07674_amd import mocks
+from paper_1505_07674_amd.binding import LensedError
+
+from helpers import f32, loglike_tolerance
+from test_gpu_grad import small_spec
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def osys(spec, data=None, weight=None):
+    return oracle.System(spec.height, spec.width, f32(spec.pixscale), spec.nsub, spec.psf.astype(np.float64), data,
+                         weight, center_x=f32(spec.center_x), center_y=f32(spec.center_y))
+
+
+def gsys(spec, data=None, weight=None):
+    t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(DEV)
+    return lensed.System(t(spec.psf), t(data), t(weight), pixscale=spec.pixscale, nsub=spec.nsub,
+                         height=spec.height, width=spec.width, center=(spec.center_x, spec.center_y))
+
+
+def components(spec, K, seed):
+    """K points sharing the lens parameters of the first: extra light components."""
+    pts = mocks.points(spec, K, seed=seed).astype(np.float32)
+    pts[1:, :5] = pts[0, :5]
+    return pts
+
+
+def test_composite_images_match_the_oracle():
+    spec = small_spec(H=44, W=40, N=3)
+    o, g = osys(spec), gsys(spec)
+    say("composite images, K = 1..3")
+    for K, sky in ((1, 0.0), (2, 0.0), (3, 0.4)):
+        th = components(spec, K, seed=90 + K)
+        for psf in (False, True):
+            img = lensed.render_composite(torch.from_numpy(th).to(DEV), g, sky=sky, apply_psf=psf)
+            ref = oracle.render_composite(o, th.astype(np.float64), sky=float(np.float32(sky)), apply_psf=psf)
+            err = np.max(np.abs(img.cpu().numpy().astype(np.float64) - ref)) / np.max(np.abs(ref))
+            assert err <= (1e-5 if psf else 3e-5), (K, psf, err)
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_composite_loglike_matches_the_oracle(K):
+    specs = [small_spec(), small_spec(H=36, W=44, N=2, center=(-0.04, 0.06))]
+    truth = components(specs[0], K, seed=100 + K)
+    systems, osystems = [], []
+    for s in specs:
+        model = oracle.render_composite(osys(s), truth.astype(np.float64), sky=0.3)
+        sigma = 0.01 * model.max()
+        rng = np.random.default_rng(s.height)
+        data = (model + sigma * rng.standard_normal(model.shape)).astype(np.float32)
+        weight = np.full(model.shape, 1.0 / sigma ** 2, np.float32)
+        systems.append(gsys(s, data, weight))
+        osystems.append(osys(s, data.astype(np.float64), weight.astype(np.float64)))
+    M = 12
+    th = np.concatenate([components(specs[0], K, seed=200 + m) for m in range(M)]).astype(np.float32)
+    sky = np.random.default_rng(5).uniform(0.0, 0.6, M).astype(np.float32)
+    som = np.arange(M, dtype=np.int32) % 2
+    say(f"composite log L, {M} models of {K} components, 2 systems")
+    ll = lensed.loglike_composite(torch.from_numpy(th).to(DEV), K, som, systems,
+                                  sky=torch.from_numpy(sky).to(DEV)).cpu().numpy()
+    ref = np.array([oracle.loglike_composite(osystems[som[m]], th[m * K:(m + 1) * K].astype(np.float64),
+                                             sky=float(sky[m])) for m in range(M)])
+    tol = np.array([loglike_tolerance(ref[m:m + 1], systems[som[m]].weight.cpu().numpy())[0] for m in range(M)])
+    err = np.abs(ll - ref) / tol
+    say(f"log L errors / bar: max {err.max():.3f}")
+    assert np.all(err <= 1.0), (err, ref)
+    # the same call again replays the cached plan and gives the same numbers
+    again = lensed.loglike_composite(torch.from_numpy(th).to(DEV), K, som, systems,
+                                     sky=torch.from_numpy(sky).to(DEV)).cpu().numpy()
+    assert np.array_equal(ll, again)
+
+
+def test_one_component_without_sky_is_the_plain_batch():
+    spec = small_spec()
+    model = oracle.render(osys(spec), spec.truth.astype(np.float64))
+    sigma = 0.01 * model.max()
+    data = (model + sigma * np.random.default_rng(1).standard_normal(model.shape)).astype(np.float32)
+    g = gsys(spec, data, np.full(model.shape, 1.0 / sigma ** 2, np.float32))
+    pts = torch.from_numpy(mocks.points(spec, 30, seed=300).astype(np.float32)).to(DEV)
+    a = lensed.loglike_composite(pts, 1, np.zeros(30, np.int32), [g]).cpu().numpy()
+    b = lensed.loglike_batch(pts, np.zeros(30, np.int32), [g]).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_composite_arguments_are_checked():
+    spec = small_spec()
+    g = gsys(spec, np.zeros((40, 36), np.float32), np.ones((40, 36), np.float32))
+    th = torch.from_numpy(components(spec, 2, seed=400)).to(DEV)
+    with pytest.raises(ValueError):
+        lensed.loglike_composite(th, 3, [0], [g])
+    with pytest.raises(LensedError):
+        lensed.loglike_composite(th, 2, [1], [g])
+    with pytest.raises(LensedError):
+        lensed.render_composite(th, g, sky=float("nan"))
