@@ -205,6 +205,21 @@ int lensed_loglike_composite(lensed_ctx* ctx, const lensed_system* systems, int 
                              int n_components, const float* sky, const int32_t* system_of_model, int n_models,
                              double* logl, void* stream);
 
+/* Simultaneous fits of several bands (Sec. 6 names the joint reconstruction of
+ * multiple bands as an extension): the bands' noise is independent, so a
+ * model's log L is the sum over its bands of Eq. 17, each band being its own
+ * system (data, weights, PSF, grid) and its own composite image.
+ *   theta        device float32 [n_models * n_bands * n_components * 17]; band b of
+ *                model m is the n_components points from point (m n_bands + b) n_components
+ *                (tie the geometry across bands by giving it the same values)
+ *   band_system  HOST int32 [n_bands], the system of each band
+ *   sky          device float32 [n_models * n_bands] (per model and band), or NULL
+ *   logl         device float64 [n_models], written: sum over the bands
+ * One graph launch, like lensed_loglike_batch. */
+int lensed_loglike_multiband(lensed_ctx* ctx, const lensed_system* systems, int n_systems, const float* theta,
+                             int n_bands, const int32_t* band_system, int n_components, const float* sky,
+                             int n_models, double* logl, void* stream);
+
 /* Weights of an observation that comes without a variance map (Sec. 3.3,
  * Eqs. 18-21). The photon counts k_i = g_i (d_i + b_i) (effective gain g_i =
  * electronic gain x exposure time; offset b_i = whatever was subtracted from

@@ -252,3 +252,11 @@ def loglike_composite(system, thetas, sky=0.0):
     m = render_composite(system, thetas, sky).reshape(-1)
     r = system.data - m
     return -0.5 * sum_compensated(system.weight * r * r)
+
+
+def loglike_multiband(band_systems, band_thetas, band_skies=None):
+    """log L of a simultaneous fit of several bands (Sec. 6 names it as an
+    extension): the bands' noise is independent, so the log-likelihoods of the
+    bands (Eq. 17, each a composite model on its own system) add."""
+    skies = [0.0] * len(band_systems) if band_skies is None else band_skies
+    return sum(loglike_composite(s, t, k) for s, t, k in zip(band_systems, band_thetas, skies))

@@ -9,8 +9,8 @@ HIP kernels for gfx950 behind the C ABI of include/lensed.h.
 """
 from .binding import (MLP_NPARAM, NPARAM, Context, LensedError, LogLikeFn, System, default_context, loglike,
                       loglike_batch, loglike_grad, mlp_adam, mlp_forward, mlp_grad, mlp_train_step, render,
-                      loglike_composite, render_composite, render_error, weights_from_data)
+                      loglike_composite, loglike_multiband, render_composite, render_error, weights_from_data)
 
 __all__ = ["MLP_NPARAM", "NPARAM", "Context", "LensedError", "LogLikeFn", "System", "default_context", "loglike",
            "loglike_batch", "loglike_grad", "mlp_adam", "mlp_forward", "mlp_grad", "mlp_train_step", "render",
-           "render_error", "weights_from_data", "loglike_composite", "render_composite"]
+           "render_error", "weights_from_data", "loglike_composite", "loglike_multiband", "render_composite"]

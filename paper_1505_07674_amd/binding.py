@@ -72,6 +72,8 @@ def lib():
                 "lensed_render_error": (i, [vp, sp, vp, vp, vp]),
                 "lensed_render_composite": (i, [vp, sp, vp, i, ctypes.c_float, vp, i, vp]),
                 "lensed_loglike_composite": (i, [vp, sp, i, vp, i, vp, ctypes.POINTER(ctypes.c_int32), i, vp, vp]),
+                "lensed_loglike_multiband": (i, [vp, sp, i, vp, i, ctypes.POINTER(ctypes.c_int32), i, vp, i, vp,
+                                                 vp]),
                 "lensed_weights_from_data": (i, [vp, vp, ctypes.c_int64, ctypes.c_double, vp, ctypes.c_double, vp, vp,
                                                  vp, vp]),
                 "lensed_loglike": (i, [vp, sp, vp, vp, vp]),
@@ -378,6 +380,33 @@ def loglike_composite(theta: torch.Tensor, n_components: int, system_of_model, s
                                         som.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), M,
                                         ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
     ctx.check(rc, "lensed_loglike_composite")
+    return out
+
+
+def loglike_multiband(theta: torch.Tensor, band_systems: Sequence[System], n_components: int = 1,
+                      sky: Optional[torch.Tensor] = None, *, out: Optional[torch.Tensor] = None,
+                      ctx: Optional[Context] = None, stream=None) -> torch.Tensor:
+    """Sum over bands of log L for M models (theta [M B K, 17]: model m, band b is
+    the K = n_components rows from (m B + b) K; band b uses band_systems[b]; sky
+    float32 [M B] or None) -> float64 [M] (independent bands, Eq. 17 each)."""
+    t = _theta2d(theta)
+    B, K = len(band_systems), int(n_components)
+    if B < 1 or K < 1 or t.shape[0] % (B * K):
+        raise ValueError("theta must hold n_bands x n_components rows per model")
+    M = t.shape[0] // (B * K)
+    if sky is not None and (sky.dtype != torch.float32 or sky.device != t.device or sky.numel() != M * B or
+                            not sky.is_contiguous()):
+        raise ValueError("sky must be a contiguous float32 tensor of one value per model and band")
+    ctx = ctx or default_context(t.device.index)
+    if out is None:
+        out = torch.empty(M, dtype=torch.float64, device=t.device)
+    sa = _SystemArray(band_systems)
+    bands = np.arange(B, dtype=np.int32)
+    sky_p = None if sky is None else ctypes.c_void_p(sky.data_ptr())
+    rc = lib().lensed_loglike_multiband(ctx.handle, sa.arr, B, ctypes.c_void_p(t.data_ptr()), B,
+                                        bands.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), K, sky_p, M,
+                                        ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+    ctx.check(rc, "lensed_loglike_multiband")
     return out
 
 

@@ -421,10 +421,11 @@ namespace {
 // lensed_loglike_composite: find or build the plan for these arguments (with
 // the autotuner on a new set of shapes), then replay its graph.
 int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const float* theta,
-              const int32_t* system_of_point, int n_points, double* logl, void* stream, int K, const float* sky) {
+              const int32_t* system_of_point, int n_points, double* logl, void* stream, int K, const float* sky,
+              int G = 1) {
   BatchPlan* plan = nullptr;
   for (size_t i = 0; i < c->plans.size(); ++i) {
-    if (c->plans[i]->matches(systems, n_systems, theta, system_of_point, n_points, logl, nullptr, K, sky)) {
+    if (c->plans[i]->matches(systems, n_systems, theta, system_of_point, n_points, logl, nullptr, K, sky, G)) {
       std::unique_ptr<BatchPlan> keep = std::move(c->plans[i]);
       c->plans.erase(c->plans.begin() + i);
       c->plans.push_back(std::move(keep));
@@ -448,7 +449,7 @@ int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const 
         BatchPlan trial;
         std::string msg;
         if (trial.build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg, nullptr, &t, K,
-                        sky) != hipSuccess) {
+                        sky, G) != hipSuccess) {
           (void)hipGetLastError();
           continue;
         }
@@ -464,7 +465,7 @@ int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const 
     std::unique_ptr<BatchPlan> np(new BatchPlan());
     std::string msg;
     hipError_t e = np->build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg, nullptr,
-                             nullptr, K, sky);
+                             nullptr, K, sky, G);
     if (e != hipSuccess) return hip_fail(c, e, ("batch plan: " + msg).c_str());
     if (c->use_graphs) {
       e = np->capture(c->cap);
@@ -529,6 +530,34 @@ int lensed_loglike_composite(lensed_ctx* c, const lensed_system* systems, int n_
   c->composite_map.resize(n_points);
   for (int p = 0; p < n_points; ++p) c->composite_map[p] = system_of_model[p / n_components];
   return run_batch(c, systems, n_systems, theta, c->composite_map.data(), n_points, logl, stream, n_components, sky);
+}
+
+int lensed_loglike_multiband(lensed_ctx* c, const lensed_system* systems, int n_systems, const float* theta,
+                             int n_bands, const int32_t* band_system, int n_components, const float* sky,
+                             int n_models, double* logl, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  if (n_models < 0) return set_err(c, LENSED_INVALID_ARGUMENT, "n_models must be >= 0");
+  if (n_bands < 1) return set_err(c, LENSED_INVALID_ARGUMENT, "n_bands must be >= 1");
+  if (n_components < 1) return set_err(c, LENSED_INVALID_ARGUMENT, "n_components must be >= 1");
+  if (n_models == 0) return LENSED_OK;
+  if ((int64_t)n_models * n_bands * n_components > INT32_MAX / NPAR)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "n_models x n_bands x n_components too large");
+  if (!systems || n_systems <= 0) return set_err(c, LENSED_INVALID_ARGUMENT, "at least one system is required");
+  if (!theta || !logl || !band_system)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "theta, band_system and logl are required");
+  for (int s = 0; s < n_systems; ++s) {
+    const int rc = validate_system(c, &systems[s], true, s);
+    if (rc) return rc;
+  }
+  for (int b = 0; b < n_bands; ++b)
+    if (band_system[b] < 0 || band_system[b] >= n_systems)
+      return set_err(c, LENSED_INVALID_ARGUMENT, "band_system[" + std::to_string(b) + "] out of range");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  const int n_points = n_models * n_bands * n_components;
+  c->composite_map.resize(n_points);
+  for (int p = 0; p < n_points; ++p) c->composite_map[p] = band_system[(p / n_components) % n_bands];
+  return run_batch(c, systems, n_systems, theta, c->composite_map.data(), n_points, logl, stream, n_components, sky,
+                   n_bands);
 }
 
 int lensed_set_profiling(lensed_ctx* c, int enable) {

@@ -53,14 +53,16 @@ class BatchPlan {
  public:
   ~BatchPlan();
   // grad == nullptr: log L only; otherwise also d log L / d theta (single system).
-  // K > 1 or sky: composite models of K consecutive points each (one log L per
-  // model, of the summed images plus sky[m] pixscale^2); map has one entry per point.
+  // K > 1 or sky: every image is the sum of K consecutive points plus sky[i]
+  // pixscale^2 (sky per image); G > 1: every log L is the sum over G consecutive
+  // images (the bands of a model). map has one entry per point.
   bool matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map, int n_points,
-               const double* logl, const float* grad = nullptr, int K = 1, const float* sky = nullptr) const;
+               const double* logl, const float* grad = nullptr, int K = 1, const float* sky = nullptr,
+               int G = 1) const;
   // force: use this tile shape instead of the cache's choice (autotuning)
   hipError_t build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
                    int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad = nullptr,
-                   const TileShape* force = nullptr, int K = 1, const float* sky = nullptr);
+                   const TileShape* force = nullptr, int K = 1, const float* sky = nullptr, int G = 1);
   // Runs the plan stage by stage twice on s and returns the second run's PSF + chi^2 milliseconds.
   hipError_t psf_ms(hipStream_t s, float* ms) const;
   hipError_t capture(hipStream_t cap);
@@ -76,11 +78,12 @@ class BatchPlan {
   double* logl_ = nullptr;
   float* grad_ = nullptr;
   int n_points_ = 0;
-  int K_ = 1;                     // points per model
-  const float* sky_ = nullptr;    // [n_models] flat sky surface brightness, or nullptr
-  int n_models_ = 0;
-  int* d_mpbase_ = nullptr;       // first partial-sum slot of each model
-  int* d_mntiles_ = nullptr;      // PSF tiles of each model
+  int K_ = 1;                     // points per image
+  int G_ = 1;                     // images per log L (bands)
+  const float* sky_ = nullptr;    // [n_images] flat sky surface brightness, or nullptr
+  int n_images_ = 0, n_models_ = 0;
+  int* d_mpbase_ = nullptr;       // first partial-sum slot of each log L
+  int* d_mntiles_ = nullptr;      // PSF tiles summed into each log L
   int compose_tiles_ = 0;         // render tiles of the largest image
 
   char* mem_ = nullptr;

@@ -115,8 +115,9 @@ BatchPlan::~BatchPlan() {
 }
 
 bool BatchPlan::matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
-                        int n_points, const double* logl, const float* grad, int K, const float* sky) const {
+                        int n_points, const double* logl, const float* grad, int K, const float* sky, int G) const {
   if (theta != theta_ || logl != logl_ || grad != grad_ || n_points != n_points_ || K != K_ || sky != sky_ ||
+      G != G_ ||
       (size_t)n_systems != systems_.size())
     return false;
   for (int s = 0; s < n_systems; ++s)
@@ -126,7 +127,7 @@ bool BatchPlan::matches(const lensed_system* systems, int n_systems, const float
 
 hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
                             int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad,
-                            const TileShape* force, int K, const float* sky) {
+                            const TileShape* force, int K, const float* sky, int G) {
   systems_.assign(systems, systems + n_systems);
   map_.assign(map, map + n_points);
   theta_ = theta;
@@ -134,8 +135,10 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   grad_ = grad;
   n_points_ = n_points;
   K_ = K;
+  G_ = G;
   sky_ = sky;
-  n_models_ = n_points / K;
+  n_images_ = n_points / K;
+  n_models_ = n_images_ / G;
 
   const TileShape ts = force ? *force : tiles.choose_common(systems, n_systems);
   TW_ = ts.TW;
@@ -250,9 +253,10 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
 
   std::vector<int> ps(map, map + n_points);
   std::vector<int> mpbase(n_models_), mntiles(n_models_);
-  for (int m = 0; m < n_models_; ++m) {
-    mpbase[m] = pbase[(size_t)m * K];
-    mntiles[m] = ntiles[(size_t)m * K];
+  for (int m = 0; m < n_models_; ++m) {   // a model's images have consecutive partial-sum slots
+    mpbase[m] = pbase[(size_t)m * G * K];
+    mntiles[m] = 0;
+    for (int b = 0; b < G; ++b) mntiles[m] += ntiles[((size_t)m * G + b) * K];
   }
   if ((e = hipMemcpy(d_sys_, desc.data(), sizeof(SysDesc) * n_systems, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_point_sys_, ps.data(), sizeof(int) * n_points, hipMemcpyHostToDevice)) != hipSuccess ||
@@ -292,7 +296,7 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
     return e;
   if (ev && n_ritems_ <= 0 && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
   if ((K_ > 1 || sky_) &&
-      (e = launch_compose(d_L_, d_loff_, d_point_sys_, d_sys_, K_, n_models_, sky_, compose_tiles_, st)) != hipSuccess)
+      (e = launch_compose(d_L_, d_loff_, d_point_sys_, d_sys_, K_, n_images_, sky_, compose_tiles_, st)) != hipSuccess)
     return e;
   if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
   WorkArgs wp = w;

@@ -107,3 +107,45 @@ def test_composite_arguments_are_checked():
         lensed.loglike_composite(th, 2, [1], [g])
     with pytest.raises(LensedError):
         lensed.render_composite(th, g, sky=float("nan"))
+
+
+def test_multiband_log_likelihoods_add_over_bands():
+    """Two bands (different grids, PSFs and noise) of composite models with
+    their own amplitudes and skies: the GPU sum of the bands' log L against the
+    oracle's, and against two single-band composite calls."""
+    bands = [small_spec(), small_spec(H=36, W=44, N=3, psf=mocks.moffat_psf(9, 0.2, 3.0, 0.08), center=(-0.04, 0.06))]
+    K, M = 2, 8
+    truth = components(bands[0], K, seed=500)
+    gs, os_ = [], []
+    for i, s in enumerate(bands):
+        model = oracle.render_composite(osys(s), truth.astype(np.float64), sky=0.1 * (i + 1))
+        sigma = 0.01 * model.max()
+        data = (model + sigma * np.random.default_rng(10 + i).standard_normal(model.shape)).astype(np.float32)
+        weight = np.full(model.shape, 1.0 / sigma ** 2, np.float32)
+        gs.append(gsys(s, data, weight))
+        os_.append(osys(s, data.astype(np.float64), weight.astype(np.float64)))
+    rows, skies = [], []
+    rng = np.random.default_rng(11)
+    for m in range(M):
+        base = components(bands[0], K, seed=600 + m)
+        for b in range(2):
+            band = base.copy()
+            band[:, [5, 12]] *= rng.uniform(0.7, 1.3, (K, 2)).astype(np.float32)   # colours differ per band
+            rows.append(band)
+            skies.append(rng.uniform(0.0, 0.3))
+    th = np.concatenate(rows).astype(np.float32)
+    sky = np.array(skies, np.float32)
+    say(f"multi-band log L: {M} models, 2 bands, {K} components")
+    ll = lensed.loglike_multiband(torch.from_numpy(th).to(DEV), gs, K, sky=torch.from_numpy(sky).to(DEV)).cpu().numpy()
+    ref = np.array([oracle.loglike_multiband(os_, [th[(2 * m + b) * K:(2 * m + b + 1) * K].astype(np.float64)
+                                                   for b in range(2)], [float(sky[2 * m + b]) for b in range(2)])
+                    for m in range(M)])
+    nw = sum(int(np.count_nonzero(g.weight.cpu().numpy())) for g in gs)
+    tol = 1e-6 * np.maximum(np.abs(ref), nw / 2.0)
+    assert np.all(np.abs(ll - ref) <= tol), (ll - ref, tol)
+    per_band = []
+    for b in range(2):
+        idx = np.concatenate([np.arange((2 * m + b) * K, (2 * m + b + 1) * K) for m in range(M)])
+        per_band.append(lensed.loglike_composite(torch.from_numpy(th[idx]).to(DEV), K, np.zeros(M, np.int32), [gs[b]],
+                                                 sky=torch.from_numpy(sky[b::2].copy()).to(DEV)).cpu().numpy())
+    assert np.allclose(ll, per_band[0] + per_band[1], rtol=1e-12, atol=0)

@@ -47,3 +47,13 @@ def test_flat_sky_stays_flat_through_the_psf():
     sw = system(d, w)
     assert oracle.loglike_composite(sw, dark[None], sky=3.0) == pytest.approx(
         -0.5 * np.sum(w * (d - 0.03) ** 2), rel=1e-13)
+
+
+def test_bands_add_their_log_likelihoods():
+    rng = np.random.default_rng(4)
+    s1 = system(rng.random(360), rng.uniform(0.5, 2.0, 360))
+    s0 = system(rng.random(360), np.zeros(360))                  # a band without weights adds nothing
+    t = T_SMALL[None]
+    one = oracle.loglike_composite(s1, t, 0.2)
+    assert oracle.loglike_multiband([s1, s1], [t, t], [0.2, 0.2]) == pytest.approx(2 * one, rel=1e-15)
+    assert oracle.loglike_multiband([s1, s0], [t, t], [0.2, 0.2]) == pytest.approx(one, rel=1e-15)
