@@ -175,6 +175,49 @@ int lensed_loglike_batch(lensed_ctx* ctx, const lensed_system* systems, int n_sy
  * near a cuspy source centre that lensed_render applies. */
 int lensed_render_error(lensed_ctx* ctx, const lensed_system* sys, const float* theta, float* error, void* stream);
 
+/* ---- General models -------------------------------------------------------
+ * The paper's fits of real lenses (Sec. 5) use several lenses (two SIEs for a
+ * lens with a companion), several Sersic components, a flat sky and, in its
+ * tests, free centres. A general model lists them; its parameters per point,
+ * in this order (float32):
+ *   per SIE          x_c, y_c, theta_E, q, phi        deflection about (x_c, y_c)
+ *   shear, if any    gamma, phi_gamma                 about the origin
+ *   per Sersic       x, y, I_e, R_e, n, q, phi        Eqs. 22-23 centred on (x, y)
+ *   sky, if any      surface brightness
+ * beta = x - sum_k alpha_SIE_k(x - c_k) - alpha_shear(x) (Eq. 1: the deflectors
+ * of one lens plane add); a Sersic with plane LENSED_LIGHT_FOREGROUND is light
+ * at x (unlensed: lens galaxies), LENSED_LIGHT_LENSED light at beta (sources).
+ * These models are evaluated in float64 and rounded once per pixel (the PSF
+ * and chi^2 stages are the common ones); the adjoint covers the 17-parameter
+ * model only. */
+#define LENSED_LIGHT_FOREGROUND 0
+#define LENSED_LIGHT_LENSED 1
+typedef struct {
+  int32_t n_sie;      /* 0..8 */
+  int32_t shear;      /* 0 or 1 */
+  int32_t n_sersic;   /* 1..8 */
+  int32_t sky;        /* 0 or 1 */
+  int32_t plane[8];   /* per Sersic: LENSED_LIGHT_FOREGROUND or LENSED_LIGHT_LENSED */
+} lensed_model;
+
+/* Parameters per point of a model (-1 for an invalid model). */
+int lensed_model_nparams(const lensed_model* model);
+
+/* Model image of one point of a general model.
+ *   theta  device float32 [lensed_model_nparams(model)]
+ *   image  device float32 [height * width], written
+ * Out-of-domain parameters (q outside (0, 1], R_e <= 0, n outside [0.2, 10],
+ * non-finite values) give a NaN image. */
+int lensed_render_model(lensed_ctx* ctx, const lensed_system* sys, const lensed_model* model, const float* theta,
+                        float* image, int apply_psf, void* stream);
+
+/* log L (Eq. 17) of n_points points of a general model over several systems,
+ * in one graph launch like lensed_loglike_batch.
+ *   theta  device float32 [n_points * lensed_model_nparams(model)] */
+int lensed_loglike_model_batch(lensed_ctx* ctx, const lensed_system* systems, int n_systems,
+                               const lensed_model* model, const float* theta, const int32_t* system_of_point,
+                               int n_points, double* logl, void* stream);
+
 /* ---- Composite models ---------------------------------------------------
  * The paper's fits of real lenses (Sec. 5) add further Sersic components and a
  * flat sky to the base model. A composite model here is K parameter points

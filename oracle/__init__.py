@@ -43,6 +43,31 @@ class LoSystem(ctypes.Structure):
     ]
 
 
+class LoModel(ctypes.Structure):
+    _fields_ = [("n_sie", ctypes.c_int32), ("shear", ctypes.c_int32), ("n_sersic", ctypes.c_int32),
+                ("sky", ctypes.c_int32), ("plane", ctypes.c_int32 * 8)]
+
+
+class Model:
+    """A general model (Sec. 5: several lenses and light components, a flat sky,
+    free centres). planes: one entry per Sersic, 'image' (unlensed light) or
+    'source' (lensed). Parameters: per SIE (x_c, y_c, theta_E, q, phi); the
+    shear (gamma, phi_gamma) if any; per Sersic (x, y, I_e, R_e, n, q, phi); the
+    sky surface brightness if any."""
+
+    def __init__(self, n_sie, planes, shear=True, sky=False):
+        planes = list(planes)
+        if not 1 <= len(planes) <= 8 or not 0 <= n_sie <= 8:
+            raise ValueError("1..8 Sersic components and 0..8 SIEs")
+        pl = (ctypes.c_int32 * 8)(*([1 if q == "source" else 0 for q in planes] + [0] * (8 - len(planes))))
+        self._m = LoModel(int(n_sie), int(bool(shear)), len(planes), int(bool(sky)), pl)
+        self.n_params = lib().lo_model_nparams(ctypes.byref(self._m))
+
+    @property
+    def ptr(self):
+        return ctypes.byref(self._m)
+
+
 def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
@@ -73,6 +98,9 @@ def lib():
             ("lo_psf_convolve", i, [i, i, dp, i, i, dp, dp]),
             ("lo_loglike", d, [sp, dp]),
             ("lo_loglike_grad", d, [sp, dp, dp]),
+            ("lo_model_nparams", i, [ctypes.c_void_p]),
+            ("lo_render_model", i, [sp, ctypes.c_void_p, dp, i, dp]),
+            ("lo_loglike_model", d, [sp, ctypes.c_void_p, dp]),
         ]:
             f = getattr(L, name)
             f.restype = res
@@ -260,3 +288,20 @@ def loglike_multiband(band_systems, band_thetas, band_skies=None):
     bands (Eq. 17, each a composite model on its own system) add."""
     skies = [0.0] * len(band_systems) if band_skies is None else band_skies
     return sum(loglike_composite(s, t, k) for s, t, k in zip(band_systems, band_thetas, skies))
+
+
+def render_model(system, model, params, apply_psf=True):
+    """Image of a general model (Model): Eqs. 1-3 with the model's deflectors and
+    light components, Eq. 14 on the system's rule, then Eq. 15."""
+    t = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1))
+    assert t.size == model.n_params
+    out = np.empty(system.height * system.width)
+    if lib().lo_render_model(system.ptr, model.ptr, _dp(t), int(bool(apply_psf)), _dp(out)) != 0:
+        raise ValueError("oracle render_model: invalid system or model")
+    return out.reshape(system.height, system.width)
+
+
+def loglike_model(system, model, params):
+    t = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1))
+    assert t.size == model.n_params
+    return lib().lo_loglike_model(system.ptr, model.ptr, _dp(t))

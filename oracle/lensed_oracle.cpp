@@ -298,6 +298,89 @@ template <class T> T surface_brightness(const Params<T>& P, T x, T y) {
   return lens + src;
 }
 
+// ---------------------------------------------------------------------------
+// General models (Sec. 5: several lenses and light components, a flat sky, free
+// centres). Parameters, in this order:
+//   per SIE        x_c, y_c, theta_E, q, phi            (deflection about its centre)
+//   shear, if any  gamma, phi_gamma                     (about the origin)
+//   per Sersic     x, y, I_e, R_e, n, q, phi            (image plane: unlensed light
+//                                                        at x; source plane: at beta)
+//   sky, if any    surface brightness
+// beta = x - sum_k alpha_SIE_k(x - c_k) - alpha_shear(x): the deflectors of one
+// lens plane add (Eq. 1).
+// ---------------------------------------------------------------------------
+}  // namespace
+extern "C" {
+typedef struct {
+  int32_t n_sie;       // 0..8
+  int32_t shear;       // 0 or 1
+  int32_t n_sersic;    // 1..8
+  int32_t sky;         // 0 or 1
+  int32_t plane[8];    // per Sersic: 0 = image plane, 1 = source plane
+} lo_model;
+}
+namespace {
+
+int model_nparams(const lo_model& M) { return 5 * M.n_sie + (M.shear ? 2 : 0) + 7 * M.n_sersic + (M.sky ? 1 : 0); }
+
+template <class T> struct GenericParams {
+  const lo_model* M;
+  std::vector<T> p;   // model_nparams values
+  std::vector<T> b;   // b_n of every Sersic
+};
+
+template <class T> GenericParams<T> make_generic(const lo_model& M, const T* th) {
+  GenericParams<T> G;
+  G.M = &M;
+  G.p.assign(th, th + model_nparams(M));
+  const int o = 5 * M.n_sie + (M.shear ? 2 : 0);
+  for (int j = 0; j < M.n_sersic; ++j) G.b.push_back(bn_of(G.p[o + 7 * j + 4]));
+  return G;
+}
+
+template <class T> T surface_brightness(const GenericParams<T>& G, T x, T y) {
+  const lo_model& M = *G.M;
+  const T* p = G.p.data();
+  int o = 0;
+  T ax(0.0), ay(0.0);
+  for (int k = 0; k < M.n_sie; ++k, o += 5) {
+    T sx, sy;
+    sie_deflection(p[o + 2], p[o + 3], p[o + 4], x - p[o], y - p[o + 1], sx, sy);
+    ax = ax + sx;
+    ay = ay + sy;
+  }
+  if (M.shear) {
+    T gx, gy;
+    shear_deflection(p[o], p[o + 1], x, y, gx, gy);
+    ax = ax + gx;
+    ay = ay + gy;
+    o += 2;
+  }
+  const T bx = x - ax, by = y - ay;
+  T I(0.0);
+  for (int j = 0; j < M.n_sersic; ++j, o += 7) {
+    const T* s = p + o;
+    I = I + (M.plane[j] ? sersic(bx, by, s[0], s[1], s[2], s[3], s[4], s[5], s[6], G.b[j])
+                        : sersic(x, y, s[0], s[1], s[2], s[3], s[4], s[5], s[6], G.b[j]));
+  }
+  if (M.sky) I = I + p[o];
+  return I;
+}
+
+bool model_valid(const lo_model* M, const double* th) {
+  if (!M || M->n_sie < 0 || M->n_sie > 8 || M->n_sersic < 1 || M->n_sersic > 8) return false;
+  if ((M->shear != 0 && M->shear != 1) || (M->sky != 0 && M->sky != 1)) return false;
+  for (int i = 0; i < model_nparams(*M); ++i) if (!std::isfinite(th[i])) return false;
+  for (int k = 0; k < M->n_sie; ++k) if (!(th[5 * k + 3] > 0.0 && th[5 * k + 3] <= 1.0)) return false;
+  const int o = 5 * M->n_sie + (M->shear ? 2 : 0);
+  for (int j = 0; j < M->n_sersic; ++j) {
+    const double* s = th + o + 7 * j;
+    if (M->plane[j] != 0 && M->plane[j] != 1) return false;
+    if (!(s[3] > 0.0) || !(s[4] >= 0.2 && s[4] <= 10.0) || !(s[5] > 0.0 && s[5] <= 1.0)) return false;
+  }
+  return true;
+}
+
 bool params_valid(const double* th) {
   for (int i = 0; i < NPAR; ++i) if (!std::isfinite(th[i])) return false;
   const double qs[3] = {th[1], th[8], th[15]};
@@ -385,8 +468,8 @@ namespace {
 // each with weight pixscale^2 / N^2.
 // The same with the Cartesian square of an explicit 1-D rule (offsets ux,
 // weights wx): L = pixscale^2 sum_{i,j} wx_i wx_j I(x_i, y_j).
-template <class T> void render_rule(const lo_system& S, const Params<T>& P, int n, const double* ux,
-                                    const double* wx, std::vector<T>& L) {
+template <class T, class Model>
+void render_rule(const lo_system& S, const Model& P, int n, const double* ux, const double* wx, std::vector<T>& L) {
   const int H = S.height, W = S.width;
   const double d = S.pixscale;
   L.assign(size_t(H) * W, T(0.0));
@@ -403,7 +486,7 @@ template <class T> void render_rule(const lo_system& S, const Params<T>& P, int 
     }
 }
 
-template <class T> void render_unconvolved(const lo_system& S, const Params<T>& P, std::vector<T>& L) {
+template <class T, class Model> void render_unconvolved(const lo_system& S, const Model& P, std::vector<T>& L) {
   if (S.rule_n > 0) {
     render_rule(S, P, S.rule_n, S.rule_x, S.rule_w, L);
     return;
@@ -457,7 +540,8 @@ bool system_valid(const lo_system* S) {
   return true;
 }
 
-template <class T> void model_image(const lo_system& S, const Params<T>& P, int apply_psf, std::vector<T>& out) {
+template <class T, class Model>
+void model_image(const lo_system& S, const Model& P, int apply_psf, std::vector<T>& out) {
   std::vector<T> L;
   render_unconvolved(S, P, L);
   if (apply_psf && S.psf) psf_convolve(S.height, S.width, L, S.psf_h, S.psf_w, S.psf, out);
@@ -547,6 +631,37 @@ double lo_loglike_grad(const lo_system* S, const double* theta, double* grad) {
     for (int k = 0; k < NPAR; ++k) g[k] += S->weight[i] * r * img[i].d[k];
   }
   for (int k = 0; k < NPAR; ++k) grad[k] = g[k];
+  return -0.5 * lo_sum_compensated(terms.data(), int64_t(terms.size()));
+}
+
+// Model image and log L of a general model (see lo_model).
+int lo_model_nparams(const lo_model* M) { return M ? model_nparams(*M) : -1; }
+
+int lo_render_model(const lo_system* S, const lo_model* M, const double* theta, int apply_psf, double* out) {
+  if (!system_valid(S) || !M || !theta || !out) return 1;
+  const size_t n = size_t(S->height) * S->width;
+  if (!model_valid(M, theta)) {
+    for (size_t i = 0; i < n; ++i) out[i] = std::numeric_limits<double>::quiet_NaN();
+    return 0;
+  }
+  const GenericParams<double> G = make_generic(*M, theta);
+  std::vector<double> img;
+  model_image(*S, G, apply_psf, img);
+  std::memcpy(out, img.data(), n * sizeof(double));
+  return 0;
+}
+
+double lo_loglike_model(const lo_system* S, const lo_model* M, const double* theta) {
+  if (!system_valid(S) || !M || !theta || !S->data || !S->weight) return std::numeric_limits<double>::quiet_NaN();
+  if (!model_valid(M, theta)) return std::numeric_limits<double>::quiet_NaN();
+  const GenericParams<double> G = make_generic(*M, theta);
+  std::vector<double> img;
+  model_image(*S, G, 1, img);
+  std::vector<double> terms(img.size());
+  for (size_t i = 0; i < img.size(); ++i) {
+    const double r = S->data[i] - img[i];
+    terms[i] = S->weight[i] * r * r;
+  }
   return -0.5 * lo_sum_compensated(terms.data(), int64_t(terms.size()));
 }
 

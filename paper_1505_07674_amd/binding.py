@@ -43,6 +43,31 @@ class LensedSystemC(ctypes.Structure):
     ]
 
 
+class LensedModelC(ctypes.Structure):
+    """Mirror of lensed_model in include/lensed.h."""
+    _fields_ = [("n_sie", ctypes.c_int32), ("shear", ctypes.c_int32), ("n_sersic", ctypes.c_int32),
+                ("sky", ctypes.c_int32), ("plane", ctypes.c_int32 * 8)]
+
+
+class Model:
+    """A general model (several SIEs with free centres, an optional shear, several
+    Sersic components, an optional flat sky; Sec. 5). planes: one entry per
+    Sersic, "foreground" (light at x: lens galaxies) or "lensed" (light at beta).
+    Parameters per point: per SIE (x_c, y_c, theta_E, q, phi); shear (gamma,
+    phi_gamma); per Sersic (x, y, I_e, R_e, n, q, phi); sky."""
+
+    def __init__(self, n_sie: int, planes: Sequence[str], shear: bool = True, sky: bool = False):
+        planes = list(planes)
+        if any(p not in ("foreground", "lensed") for p in planes):
+            raise ValueError("planes must be 'foreground' or 'lensed'")
+        codes = [1 if p == "lensed" else 0 for p in planes] + [0] * max(0, 8 - len(planes))
+        self.c_struct = LensedModelC(int(n_sie), int(bool(shear)), len(planes), int(bool(sky)),
+                                     (ctypes.c_int32 * 8)(*codes[:8]))
+        self.n_params = lib().lensed_model_nparams(ctypes.byref(self.c_struct))
+        if self.n_params < 0 or len(planes) > 8:
+            raise ValueError("a model has 0..8 SIEs and 1..8 Sersic components")
+
+
 RULES = {"sub": 0, "g3k7": 1, "g5k11": 2, "g7k15": 3}
 AMPLITUDES = {"intensity": 0, "magnitude": 1}
 SOURCE_POSITIONS = {"source": 0, "image": 1}
@@ -70,6 +95,9 @@ def lib():
                 "lensed_last_error": (cp, [vp]),
                 "lensed_render": (i, [vp, sp, vp, vp, i, vp]),
                 "lensed_render_error": (i, [vp, sp, vp, vp, vp]),
+                "lensed_model_nparams": (i, [vp]),
+                "lensed_render_model": (i, [vp, sp, vp, vp, vp, i, vp]),
+                "lensed_loglike_model_batch": (i, [vp, sp, i, vp, vp, ctypes.POINTER(ctypes.c_int32), i, vp, vp]),
                 "lensed_render_composite": (i, [vp, sp, vp, i, ctypes.c_float, vp, i, vp]),
                 "lensed_loglike_composite": (i, [vp, sp, i, vp, i, vp, ctypes.POINTER(ctypes.c_int32), i, vp, vp]),
                 "lensed_loglike_multiband": (i, [vp, sp, i, vp, i, ctypes.POINTER(ctypes.c_int32), i, vp, i, vp,
@@ -249,6 +277,51 @@ def render(theta: torch.Tensor, system: System, apply_psf: bool = True, *, ctx: 
     rc = lib().lensed_render(ctx.handle, ctypes.byref(system.c_struct), ctypes.c_void_p(t.data_ptr()),
                              ctypes.c_void_p(out.data_ptr()), int(bool(apply_psf)), _stream_handle(stream))
     ctx.check(rc, "lensed_render")
+    return out
+
+
+def _model_theta(theta: torch.Tensor, model: Model) -> torch.Tensor:
+    t = _dev_tensor(theta, torch.float32, "theta")
+    if t.dim() == 1:
+        t = t.view(1, -1)
+    if t.dim() != 2 or t.shape[1] != model.n_params:
+        raise ValueError(f"theta must be [{model.n_params}] or [P, {model.n_params}] for this model")
+    return t
+
+
+def render_model(theta: torch.Tensor, system: System, model: Model, apply_psf: bool = True, *,
+                 ctx: Optional[Context] = None, stream=None) -> torch.Tensor:
+    """Model image [H, W] of one point of a general model."""
+    t = _model_theta(theta, model)
+    if t.shape[0] != 1:
+        raise ValueError("render_model takes a single parameter point")
+    ctx = ctx or default_context(t.device.index)
+    out = torch.empty((system.height, system.width), dtype=torch.float32, device=t.device)
+    rc = lib().lensed_render_model(ctx.handle, ctypes.byref(system.c_struct), ctypes.byref(model.c_struct),
+                                   ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   int(bool(apply_psf)), _stream_handle(stream))
+    ctx.check(rc, "lensed_render_model")
+    return out
+
+
+def loglike_model_batch(theta: torch.Tensor, system_of_point, systems: Sequence[System], model: Model, *,
+                        out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None,
+                        stream=None) -> torch.Tensor:
+    """log L of P points of a general model over several systems -> float64 [P]."""
+    t = _model_theta(theta, model)
+    P = t.shape[0]
+    sop = np.ascontiguousarray(np.asarray(system_of_point, dtype=np.int32).reshape(-1))
+    if sop.size != P:
+        raise ValueError("system_of_point must have one entry per point")
+    ctx = ctx or default_context(t.device.index)
+    if out is None:
+        out = torch.empty(P, dtype=torch.float64, device=t.device)
+    sa = _SystemArray(systems)
+    rc = lib().lensed_loglike_model_batch(ctx.handle, sa.arr, len(sa.systems), ctypes.byref(model.c_struct),
+                                          ctypes.c_void_p(t.data_ptr()),
+                                          sop.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), P,
+                                          ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+    ctx.check(rc, "lensed_loglike_model_batch")
     return out
 
 

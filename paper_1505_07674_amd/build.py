@@ -17,8 +17,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblensed_hip.so")
 ARCH = "gfx950"
 
-SOURCES = ["prologue.hip", "render.hip", "psf_chi2.hip", "adjoint.hip", "variance.hip", "mlp.hip", "plan.hip",
-           "capi.hip"]
+SOURCES = ["prologue.hip", "render.hip", "model.hip", "psf_chi2.hip", "adjoint.hip", "variance.hip", "mlp.hip",
+           "plan.hip", "capi.hip"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -422,10 +422,11 @@ namespace {
 // the autotuner on a new set of shapes), then replay its graph.
 int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const float* theta,
               const int32_t* system_of_point, int n_points, double* logl, void* stream, int K, const float* sky,
-              int G = 1) {
+              int G = 1, const ModelSpec* model = nullptr, int params_per_point = NPAR) {
   BatchPlan* plan = nullptr;
   for (size_t i = 0; i < c->plans.size(); ++i) {
-    if (c->plans[i]->matches(systems, n_systems, theta, system_of_point, n_points, logl, nullptr, K, sky, G)) {
+    if (c->plans[i]->matches(systems, n_systems, theta, system_of_point, n_points, logl, nullptr, K, sky, G,
+                             model)) {
       std::unique_ptr<BatchPlan> keep = std::move(c->plans[i]);
       c->plans.erase(c->plans.begin() + i);
       c->plans.push_back(std::move(keep));
@@ -449,7 +450,7 @@ int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const 
         BatchPlan trial;
         std::string msg;
         if (trial.build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg, nullptr, &t, K,
-                        sky, G) != hipSuccess) {
+                        sky, G, model, params_per_point) != hipSuccess) {
           (void)hipGetLastError();
           continue;
         }
@@ -465,7 +466,7 @@ int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const 
     std::unique_ptr<BatchPlan> np(new BatchPlan());
     std::string msg;
     hipError_t e = np->build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg, nullptr,
-                             nullptr, K, sky, G);
+                             nullptr, K, sky, G, model, params_per_point);
     if (e != hipSuccess) return hip_fail(c, e, ("batch plan: " + msg).c_str());
     if (c->use_graphs) {
       e = np->capture(c->cap);
@@ -530,6 +531,96 @@ int lensed_loglike_composite(lensed_ctx* c, const lensed_system* systems, int n_
   c->composite_map.resize(n_points);
   for (int p = 0; p < n_points; ++p) c->composite_map[p] = system_of_model[p / n_components];
   return run_batch(c, systems, n_systems, theta, c->composite_map.data(), n_points, logl, stream, n_components, sky);
+}
+
+namespace {
+
+// The device copy of a validated lensed_model.
+int model_spec(lensed_ctx* c, const lensed_model* m, ModelSpec& spec) {
+  if (!m) return set_err(c, LENSED_INVALID_ARGUMENT, "model is NULL");
+  if (m->n_sie < 0 || m->n_sie > MAX_SIE) return set_err(c, LENSED_INVALID_ARGUMENT, "n_sie must be in 0..8");
+  if (m->n_sersic < 1 || m->n_sersic > MAX_SERSIC)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "n_sersic must be in 1..8");
+  if ((m->shear != 0 && m->shear != 1) || (m->sky != 0 && m->sky != 1))
+    return set_err(c, LENSED_INVALID_ARGUMENT, "shear and sky must be 0 or 1");
+  std::memset(&spec, 0, sizeof(spec));
+  spec.n_sie = m->n_sie;
+  spec.shear = m->shear;
+  spec.n_sersic = m->n_sersic;
+  spec.sky = m->sky;
+  for (int j = 0; j < m->n_sersic; ++j) {
+    if (m->plane[j] != LENSED_LIGHT_FOREGROUND && m->plane[j] != LENSED_LIGHT_LENSED)
+      return set_err(c, LENSED_INVALID_ARGUMENT, "plane[" + std::to_string(j) + "] must be a LENSED_LIGHT_* value");
+    spec.plane[j] = m->plane[j];
+  }
+  return LENSED_OK;
+}
+
+int spec_params(const ModelSpec& s) { return 5 * s.n_sie + (s.shear ? 2 : 0) + 7 * s.n_sersic + (s.sky ? 1 : 0); }
+
+}  // namespace
+
+int lensed_model_nparams(const lensed_model* model) {
+  ModelSpec spec;
+  if (model_spec(nullptr, model, spec) != LENSED_OK) return -1;
+  return spec_params(spec);
+}
+
+int lensed_render_model(lensed_ctx* c, const lensed_system* sys, const lensed_model* model, const float* theta,
+                        float* image, int apply_psf, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  int rc = validate_system(c, sys, false, -1);
+  if (rc) return rc;
+  ModelSpec spec;
+  if ((rc = model_spec(c, model, spec))) return rc;
+  if (!theta || !image) return set_err(c, LENSED_INVALID_ARGUMENT, "theta and image are required");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const TileShape ts = c->tiles.choose(*sys);
+  SysDesc sd = make_desc(*sys, ts);
+  const size_t npix = (size_t)sd.H * sd.W;
+  const size_t off_mc = 0;
+  const size_t off_psf = align_up(off_mc + sizeof(ModelConst), 256);
+  const size_t off_cc = align_up(off_psf + 3 * sizeof(float) * sd.ph * sd.pw, 256);
+  const size_t off_L = align_up(off_cc + sizeof(int), 256);
+  const size_t total = align_up(off_L + sizeof(float) * npix, 256);
+  if ((rc = ensure_arena(c, total))) return rc;
+  ModelConst* mc = (ModelConst*)(c->arena + off_mc);
+  sd.psfn = (float*)(c->arena + off_psf);
+  float* L = apply_psf ? (float*)(c->arena + off_L) : image;
+  WorkArgs w;
+  std::memset(&w, 0, sizeof(w));
+  w.single = sd;
+  // the 17-parameter prologue with no points normalises the PSF
+  LENSED_HIP(c, launch_prologue(theta, 0, nullptr, nullptr, nullptr, sd, nullptr, 1, (int*)(c->arena + off_cc), st));
+  LENSED_HIP(c, launch_model_prologue(theta, 1, spec_params(spec), spec, mc, st));
+  LENSED_HIP(c, launch_model_render(w, mc, L, sd.n_rtiles, st));
+  if (apply_psf)
+    LENSED_HIP(c, launch_psf(w, L, image, nullptr, 0, sd.n_ptiles, square_psf_code(sd.ph, sd.pw), sd.TW, sd.TH,
+                             sd.ph, sd.pw, st));
+  return LENSED_OK;
+}
+
+int lensed_loglike_model_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const lensed_model* model,
+                               const float* theta, const int32_t* system_of_point, int n_points, double* logl,
+                               void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  ModelSpec spec;
+  int rc = model_spec(c, model, spec);
+  if (rc) return rc;
+  if (n_points < 0) return set_err(c, LENSED_INVALID_ARGUMENT, "n_points must be >= 0");
+  if (n_points == 0) return LENSED_OK;
+  if (!systems || n_systems <= 0) return set_err(c, LENSED_INVALID_ARGUMENT, "at least one system is required");
+  if (!theta || !logl || !system_of_point)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "theta, system_of_point and logl are required");
+  for (int s = 0; s < n_systems; ++s)
+    if ((rc = validate_system(c, &systems[s], true, s))) return rc;
+  for (int p = 0; p < n_points; ++p)
+    if (system_of_point[p] < 0 || system_of_point[p] >= n_systems)
+      return set_err(c, LENSED_INVALID_ARGUMENT, "system_of_point[" + std::to_string(p) + "] out of range");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  return run_batch(c, systems, n_systems, theta, system_of_point, n_points, logl, stream, 1, nullptr, 1, &spec,
+                   spec_params(spec));
 }
 
 int lensed_loglike_multiband(lensed_ctx* c, const lensed_system* systems, int n_systems, const float* theta,

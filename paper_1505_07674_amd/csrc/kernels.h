@@ -58,6 +58,12 @@ hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, Po
 hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L, int n_blocks,
                          const CuspList& cl, hipStream_t stream, hipEvent_t between = nullptr);
 
+// General models: per-point float64 constants from the parameters (n_params
+// per point, the layout of lensed_model), and the float64 render into L.
+hipError_t launch_model_prologue(const float* theta, int n_points, int n_params, const ModelSpec& spec,
+                                 ModelConst* out, hipStream_t stream);
+hipError_t launch_model_render(const WorkArgs& w, const ModelConst* mcs, float* L, int n_blocks, hipStream_t stream);
+
 // Composite models (K consecutive points each): L[first image of model m] =
 // sum of its K unconvolved images + sky[m] pixscale^2 (sky may be nullptr), in
 // float64 per pixel, before the PSF stage. tiles_per_model: RENDER_BLOCK-pixel

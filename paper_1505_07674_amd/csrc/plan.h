@@ -56,13 +56,16 @@ class BatchPlan {
   // K > 1 or sky: every image is the sum of K consecutive points plus sky[i]
   // pixscale^2 (sky per image); G > 1: every log L is the sum over G consecutive
   // images (the bands of a model). map has one entry per point.
+  // model: a general model (ModelSpec, params_per_point values per point) instead
+  // of the 17-parameter one.
   bool matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map, int n_points,
                const double* logl, const float* grad = nullptr, int K = 1, const float* sky = nullptr,
-               int G = 1) const;
+               int G = 1, const ModelSpec* model = nullptr) const;
   // force: use this tile shape instead of the cache's choice (autotuning)
   hipError_t build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
                    int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad = nullptr,
-                   const TileShape* force = nullptr, int K = 1, const float* sky = nullptr, int G = 1);
+                   const TileShape* force = nullptr, int K = 1, const float* sky = nullptr, int G = 1,
+                   const ModelSpec* model = nullptr, int params_per_point = NPAR);
   // Runs the plan stage by stage twice on s and returns the second run's PSF + chi^2 milliseconds.
   hipError_t psf_ms(hipStream_t s, float* ms) const;
   hipError_t capture(hipStream_t cap);
@@ -85,6 +88,10 @@ class BatchPlan {
   int* d_mpbase_ = nullptr;       // first partial-sum slot of each log L
   int* d_mntiles_ = nullptr;      // PSF tiles summed into each log L
   int compose_tiles_ = 0;         // render tiles of the largest image
+  bool has_model_ = false;        // general model: model prologue and float64 render
+  ModelSpec spec_{};
+  int params_per_point_ = NPAR;
+  ModelConst* d_mc_ = nullptr;
 
   char* mem_ = nullptr;
   SysDesc* d_sys_ = nullptr;

@@ -115,9 +115,11 @@ BatchPlan::~BatchPlan() {
 }
 
 bool BatchPlan::matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
-                        int n_points, const double* logl, const float* grad, int K, const float* sky, int G) const {
+                        int n_points, const double* logl, const float* grad, int K, const float* sky, int G,
+                        const ModelSpec* model) const {
   if (theta != theta_ || logl != logl_ || grad != grad_ || n_points != n_points_ || K != K_ || sky != sky_ ||
-      G != G_ ||
+      G != G_ || (model != nullptr) != has_model_ ||
+      (model && std::memcmp(model, &spec_, sizeof(ModelSpec)) != 0) ||
       (size_t)n_systems != systems_.size())
     return false;
   for (int s = 0; s < n_systems; ++s)
@@ -127,7 +129,8 @@ bool BatchPlan::matches(const lensed_system* systems, int n_systems, const float
 
 hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
                             int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad,
-                            const TileShape* force, int K, const float* sky, int G) {
+                            const TileShape* force, int K, const float* sky, int G, const ModelSpec* model,
+                            int params_per_point) {
   systems_.assign(systems, systems + n_systems);
   map_.assign(map, map + n_points);
   theta_ = theta;
@@ -136,6 +139,9 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   n_points_ = n_points;
   K_ = K;
   G_ = G;
+  has_model_ = model != nullptr;
+  if (model) spec_ = *model;
+  params_per_point_ = params_per_point;
   sky_ = sky;
   n_images_ = n_points / K;
   n_models_ = n_images_ / G;
@@ -206,6 +212,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   const size_t o_ri = off; off = align256(off + sizeof(int2) * n_ritems_);
   const size_t o_pi = off; off = align256(off + sizeof(int2) * n_pitems_);
   const size_t o_pc = off; off = align256(off + sizeof(PointConst) * n_points);
+  const size_t o_mc = off; off = align256(off + (has_model_ ? sizeof(ModelConst) * n_points : 0));
   const size_t o_p64 = off; off = align256(off + sizeof(PointConst64) * n_points);
   const size_t o_psf = off; off = align256(off + 3 * sizeof(float) * psf_total);
   const size_t o_cc = off; off = align256(off + sizeof(int));
@@ -235,6 +242,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   d_ritems_ = (int2*)(mem_ + o_ri);
   d_pitems_ = (int2*)(mem_ + o_pi);
   d_pc_ = (PointConst*)(mem_ + o_pc);
+  d_mc_ = has_model_ ? (ModelConst*)(mem_ + o_mc) : nullptr;
   d_p64_ = (PointConst64*)(mem_ + o_p64);
   cusp_.count = (int*)(mem_ + o_cc);
   cusp_.entries = (CuspEntry*)(mem_ + o_ce);
@@ -285,16 +293,25 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
   std::memset(&none, 0, sizeof(none));
   hipError_t e;
   if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
-  if ((e = launch_prologue(theta_, n_points_, d_pc_, d_p64_, d_gc_, none, d_sys_, (int)systems_.size(), cusp_.count,
-                           st, d_gcorr_, d_point_sys_)) != hipSuccess)
+  // the 17-parameter prologue also normalises the PSFs; with a general model it does only that
+  if ((e = launch_prologue(theta_, has_model_ ? 0 : n_points_, d_pc_, d_p64_, d_gc_, none, d_sys_,
+                           (int)systems_.size(), cusp_.count, st, d_gcorr_, d_point_sys_)) != hipSuccess)
+    return e;
+  if (has_model_ &&
+      (e = launch_model_prologue(theta_, n_points_, params_per_point_, spec_, d_mc_, st)) != hipSuccess)
     return e;
   if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
   WorkArgs wr = w;
   wr.items = d_ritems_;
   wr.n_items = n_ritems_;
-  if ((e = launch_render(wr, d_pc_, d_p64_, d_L_, n_ritems_, cusp_, st, ev ? ev[2] : nullptr)) != hipSuccess)
-    return e;
-  if (ev && n_ritems_ <= 0 && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+  if (has_model_) {
+    if ((e = launch_model_render(wr, d_mc_, d_L_, n_ritems_, st)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+  } else {
+    if ((e = launch_render(wr, d_pc_, d_p64_, d_L_, n_ritems_, cusp_, st, ev ? ev[2] : nullptr)) != hipSuccess)
+      return e;
+    if (ev && n_ritems_ <= 0 && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+  }
   if ((K_ > 1 || sky_) &&
       (e = launch_compose(d_L_, d_loff_, d_point_sys_, d_sys_, K_, n_images_, sky_, compose_tiles_, st)) != hipSuccess)
     return e;

@@ -411,6 +411,76 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
 
 }  // namespace
 
+// General models: one thread per point turns its parameters (layout of
+// lensed_model: per SIE x_c, y_c, theta_E, q, phi; shear gamma, phi_gamma; per
+// Sersic x, y, I_e, R_e, n, q, phi; sky) into ModelConst, b_n by the float64
+// Newton solve. An invalid point gets sky = NaN, which makes its image NaN.
+__global__ void model_prologue_kernel(const float* __restrict__ theta, int n_points, int n_params, ModelSpec spec,
+                                      ModelConst* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_points) return;
+  const float* t = theta + (size_t)p * n_params;
+  bool valid = true;
+  for (int i = 0; i < n_params; ++i) valid = valid && isfinite(t[i]);
+  ModelConst m;
+  m.n_sie = spec.n_sie;
+  m.n_sersic = spec.n_sersic;
+  int o = 0;
+  for (int k = 0; k < MAX_SIE; ++k) {
+    for (int i = 0; i < 7; ++i) m.sie[k][i] = 0.0;
+    m.sie_sphere[k] = 0;
+    if (k >= spec.n_sie) continue;
+    const double te = t[o + 2], q = t[o + 3], ph = t[o + 4];
+    valid = valid && q > 0.0 && q <= 1.0;
+    const double s2 = (1.0 - q) * (1.0 + q), qp = sqrt(fmax(s2, 0.0));
+    m.sie[k][0] = t[o];
+    m.sie[k][1] = t[o + 1];
+    m.sie[k][2] = cos(ph);
+    m.sie[k][3] = sin(ph);
+    m.sie[k][4] = q * q;
+    m.sie[k][5] = qp;
+    m.sie_sphere[k] = s2 == 0.0;
+    m.sie[k][6] = s2 == 0.0 ? te : te * sqrt(q) / qp;
+    o += 5;
+  }
+  m.g1 = m.g2 = 0.0;
+  if (spec.shear) {
+    m.g1 = (double)t[o] * cos(2.0 * (double)t[o + 1]);
+    m.g2 = (double)t[o] * sin(2.0 * (double)t[o + 1]);
+    o += 2;
+  }
+  for (int j = 0; j < MAX_SERSIC; ++j) {
+    for (int i = 0; i < 10; ++i) m.ser[j][i] = 0.0;
+    m.plane[j] = 0;
+    if (j >= spec.n_sersic) continue;
+    const double Re = t[o + 3], n = t[o + 4], q = t[o + 5], ph = t[o + 6];
+    valid = valid && Re > 0.0 && n >= 0.2 && n <= 10.0 && q > 0.0 && q <= 1.0;
+    m.plane[j] = spec.plane[j];
+    m.ser[j][0] = t[o];
+    m.ser[j][1] = t[o + 1];
+    m.ser[j][2] = cos(ph);
+    m.ser[j][3] = sin(ph);
+    m.ser[j][4] = q;
+    m.ser[j][5] = 1.0 / q;
+    m.ser[j][6] = 1.0 / Re;
+    m.ser[j][7] = 1.0 / n;
+    m.ser[j][8] = valid ? sersic_bn(n) : 0.0;
+    m.ser[j][9] = t[o + 2];
+    o += 7;
+  }
+  m.sky = spec.sky ? (double)t[o] : 0.0;
+  if (!valid) m.sky = __builtin_nan("");
+  out[p] = m;
+}
+
+hipError_t launch_model_prologue(const float* theta, int n_points, int n_params, const ModelSpec& spec,
+                                 ModelConst* out, hipStream_t stream) {
+  if (n_points <= 0) return hipSuccess;
+  hipLaunchKernelGGL(model_prologue_kernel, dim3((n_points + 63) / 64), dim3(64), 0, stream, theta, n_points, n_params,
+                     spec, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, PointConst64* p64s, GradConst* gcs,
                            const SysDesc& single, SysDesc* table, int n_sys, int* cusp_count, hipStream_t stream,
                            double* grad_corr, const int* point_sys) {
