@@ -16,24 +16,6 @@ constexpr double LOG2E = 1.44269504088896340736;
 constexpr double CUSP_RADIUS_ARCSEC = 0.03;
 constexpr double CUSP_RADIUS_IMAGE_PLANE_ARCSEC = 0.06;
 
-// General models (several lenses and light components, a flat sky, free
-// centres): the model's shape (a copy of lensed_model) and per-point constants
-// in float64, derived by the model prologue.
-constexpr int MAX_SIE = 8, MAX_SERSIC = 8;
-struct ModelSpec {
-  int n_sie, shear, n_sersic, sky;
-  int plane[MAX_SERSIC];
-};
-struct ModelConst {
-  double sie[MAX_SIE][7];      // x_c, y_c, cos, sin, q^2, q', k = theta_E sqrt(q)/q' (theta_E when q = 1)
-  double g1, g2;               // external shear (zero without one)
-  double ser[MAX_SERSIC][10];  // x0, y0, cos, sin, q, 1/q, 1/R_e, 1/n, b_n, I_e
-  double sky;                  // flat sky surface brightness (NaN marks an invalid point)
-  int n_sie, n_sersic;
-  int sie_sphere[MAX_SIE];     // 1 where q = 1
-  int plane[MAX_SERSIC];       // 0: light at x (image plane); 1: light at beta (source plane)
-};
-
 // Per-point constants derived once from the 17 parameters (prologue kernel).
 // Read with wave-uniform addresses, so they live in scalar registers in the
 // render kernels. Invalid points carry NaN in the amplitudes and in the lens

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "internal.h"
+#include "model.h"
 
 namespace lensed {
 

@@ -1,0 +1,25 @@
+// model.h -- shape and per-point constants of general models (several lenses
+// and light components, a flat sky, free centres), evaluated in float64.
+#pragma once
+
+namespace lensed {
+
+// General models (several lenses and light components, a flat sky, free
+// centres): the model's shape (a copy of lensed_model) and per-point constants
+// in float64, derived by the model prologue.
+constexpr int MAX_SIE = 8, MAX_SERSIC = 8;
+struct ModelSpec {
+  int n_sie, shear, n_sersic, sky;
+  int plane[MAX_SERSIC];
+};
+struct ModelConst {
+  double sie[MAX_SIE][7];      // x_c, y_c, cos, sin, q^2, q', k = theta_E sqrt(q)/q' (theta_E when q = 1)
+  double g1, g2;               // external shear (zero without one)
+  double ser[MAX_SERSIC][10];  // x0, y0, cos, sin, q, 1/q, 1/R_e, 1/n, b_n, I_e
+  double sky;                  // flat sky surface brightness (NaN marks an invalid point)
+  int n_sie, n_sersic;
+  int sie_sphere[MAX_SIE];     // 1 where q = 1
+  int plane[MAX_SERSIC];       // 0: light at x (image plane); 1: light at beta (source plane)
+};
+
+}  // namespace lensed
