@@ -187,17 +187,33 @@ int lensed_render_error(lensed_ctx* ctx, const lensed_system* sys, const float* 
  * beta = x - sum_k alpha_SIE_k(x - c_k) - alpha_shear(x) (Eq. 1: the deflectors
  * of one lens plane add); a Sersic with plane LENSED_LIGHT_FOREGROUND is light
  * at x (unlensed: lens galaxies), LENSED_LIGHT_LENSED light at beta (sources).
+ *
+ * Several lens planes (the extension named in Sec. 6, in the standard form of
+ * the multi-plane lens equation): n_planes = P lens planes, ordered by
+ * distance, and the source plane P. The ray through the image-plane point x
+ * sits at x_0 = x and x_j = x - sum_{i<j} beta_ij alpha_i(x_i) (j = 1..P), with
+ * alpha_i the summed deflection of the SIEs of plane i (theta_E scaled to the
+ * source plane, as for one plane) and beta_iP = 1; the shear belongs to plane 0.
+ * A Sersic on plane j is evaluated at x_j. With P = 1 this is the one-plane
+ * model above, and sie_plane and beta are not read.
+ *
  * These models are evaluated in float64 and rounded once per pixel (the PSF
  * and chi^2 stages are the common ones); the adjoint covers the 17-parameter
  * model only. */
 #define LENSED_LIGHT_FOREGROUND 0
 #define LENSED_LIGHT_LENSED 1
 typedef struct {
-  int32_t n_sie;      /* 0..8 */
-  int32_t shear;      /* 0 or 1 */
-  int32_t n_sersic;   /* 1..8 */
-  int32_t sky;        /* 0 or 1 */
-  int32_t plane[8];   /* per Sersic: LENSED_LIGHT_FOREGROUND or LENSED_LIGHT_LENSED */
+  int32_t n_sie;        /* 0..8 */
+  int32_t shear;        /* 0 or 1 */
+  int32_t n_sersic;     /* 1..8 */
+  int32_t sky;          /* 0 or 1 */
+  int32_t plane[8];     /* per Sersic: its plane, 0..n_planes (with one lens plane:
+                           LENSED_LIGHT_FOREGROUND or LENSED_LIGHT_LENSED) */
+  int32_t n_planes;     /* lens planes P, 1..8 (0 reads as 1) */
+  int32_t sie_plane[8]; /* per SIE: its lens plane, 0..P-1 */
+  int32_t reserved;     /* 0 */
+  double beta[8][8];    /* beta[i][j], 0 <= i < j < P: distance ratio
+                           D_ij D_s / (D_j D_is), in [0, 1]; other entries unused */
 } lensed_model;
 
 /* Parameters per point of a model (-1 for an invalid model). */

@@ -45,22 +45,42 @@ class LoSystem(ctypes.Structure):
 
 class LoModel(ctypes.Structure):
     _fields_ = [("n_sie", ctypes.c_int32), ("shear", ctypes.c_int32), ("n_sersic", ctypes.c_int32),
-                ("sky", ctypes.c_int32), ("plane", ctypes.c_int32 * 8)]
+                ("sky", ctypes.c_int32), ("plane", ctypes.c_int32 * 8), ("n_planes", ctypes.c_int32),
+                ("sie_plane", ctypes.c_int32 * 8), ("reserved", ctypes.c_int32),
+                ("beta", (ctypes.c_double * 8) * 8)]
 
 
 class Model:
     """A general model (Sec. 5: several lenses and light components, a flat sky,
-    free centres). planes: one entry per Sersic, 'image' (unlensed light) or
-    'source' (lensed). Parameters: per SIE (x_c, y_c, theta_E, q, phi); the
-    shear (gamma, phi_gamma) if any; per Sersic (x, y, I_e, R_e, n, q, phi); the
-    sky surface brightness if any."""
+    free centres). planes: one entry per Sersic, 'image' (unlensed light),
+    'source' (lensed), or the index of the plane the light sits on (0..P, P the
+    source plane). Parameters: per SIE (x_c, y_c, theta_E, q, phi); the shear
+    (gamma, phi_gamma) if any; per Sersic (x, y, I_e, R_e, n, q, phi); the sky
+    surface brightness if any.
 
-    def __init__(self, n_sie, planes, shear=True, sky=False):
+    Several lens planes (the extension named in Sec. 6): beta, a P x P array whose entries
+    beta[i][j], i < j, are the distance ratios of the multi-plane lens equation,
+    and sie_planes, the lens plane of every SIE (default all on plane 0)."""
+
+    def __init__(self, n_sie, planes, shear=True, sky=False, sie_planes=None, beta=None):
         planes = list(planes)
         if not 1 <= len(planes) <= 8 or not 0 <= n_sie <= 8:
             raise ValueError("1..8 Sersic components and 0..8 SIEs")
-        pl = (ctypes.c_int32 * 8)(*([1 if q == "source" else 0 for q in planes] + [0] * (8 - len(planes))))
-        self._m = LoModel(int(n_sie), int(bool(shear)), len(planes), int(bool(sky)), pl)
+        n_planes = 1 if beta is None else len(beta)
+        codes = [0 if q == "image" else n_planes if q == "source" else int(q) for q in planes]
+        pl = (ctypes.c_int32 * 8)(*(codes + [0] * (8 - len(codes))))
+        sp = [0] * n_sie if sie_planes is None else [int(k) for k in sie_planes]
+        if len(sp) != n_sie:
+            raise ValueError("one lens plane per SIE")
+        b = ((ctypes.c_double * 8) * 8)()
+        if beta is not None:
+            beta = np.asarray(beta, np.float64)
+            for i in range(n_planes):
+                for j in range(n_planes):
+                    b[i][j] = beta[i, j]
+        self._m = LoModel(int(n_sie), int(bool(shear)), len(planes), int(bool(sky)), pl, n_planes,
+                          (ctypes.c_int32 * 8)(*(sp + [0] * (8 - len(sp)))), 0, b)
+        self.n_planes = n_planes
         self.n_params = lib().lo_model_nparams(ctypes.byref(self._m))
 
     @property
@@ -101,6 +121,7 @@ def lib():
             ("lo_model_nparams", i, [ctypes.c_void_p]),
             ("lo_render_model", i, [sp, ctypes.c_void_p, dp, i, dp]),
             ("lo_loglike_model", d, [sp, ctypes.c_void_p, dp]),
+            ("lo_model_positions", i, [ctypes.c_void_p, dp, d, d, dp, dp]),
         ]:
             f = getattr(L, name)
             f.restype = res
@@ -299,6 +320,18 @@ def render_model(system, model, params, apply_psf=True):
     if lib().lo_render_model(system.ptr, model.ptr, _dp(t), int(bool(apply_psf)), _dp(out)) != 0:
         raise ValueError("oracle render_model: invalid system or model")
     return out.reshape(system.height, system.width)
+
+
+def model_positions(model, params, x, y):
+    """Position of the ray through the image-plane point (x, y) on every plane:
+    an array [(x_0, y_0), ..., (x_P, y_P)], lens planes 0..P-1 and the source
+    plane P."""
+    t = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1))
+    assert t.size == model.n_params
+    px, py = np.empty(model.n_planes + 1), np.empty(model.n_planes + 1)
+    if lib().lo_model_positions(model.ptr, _dp(t), float(x), float(y), _dp(px), _dp(py)) != 0:
+        raise ValueError("oracle model_positions: invalid model or parameters")
+    return np.stack([px, py], axis=1)
 
 
 def loglike_model(system, model, params):

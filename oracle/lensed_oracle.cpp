@@ -303,23 +303,39 @@ template <class T> T surface_brightness(const Params<T>& P, T x, T y) {
 // centres). Parameters, in this order:
 //   per SIE        x_c, y_c, theta_E, q, phi            (deflection about its centre)
 //   shear, if any  gamma, phi_gamma                     (about the origin)
-//   per Sersic     x, y, I_e, R_e, n, q, phi            (image plane: unlensed light
-//                                                        at x; source plane: at beta)
+//   per Sersic     x, y, I_e, R_e, n, q, phi            (evaluated at the position of
+//                                                        the ray on the Sersic's plane)
 //   sky, if any    surface brightness
-// beta = x - sum_k alpha_SIE_k(x - c_k) - alpha_shear(x): the deflectors of one
-// lens plane add (Eq. 1).
+// One lens plane (Eq. 1): beta = x - sum_k alpha_SIE_k(x - c_k) - alpha_shear(x);
+// the deflectors of one plane add.
+//
+// Several lens planes (the extension named in Sec. 6, in the standard form of
+// the multi-plane lens equation): lens planes 0..P-1 ordered by distance, the
+// source plane P. The ray through the image-plane point x sits at
+//   x_0 = x,   x_j = x - sum_{i<j} beta_ij alpha_i(x_i)   (j = 1..P),
+// where alpha_i is the summed deflection of the plane-i deflectors (scaled, as
+// theta_E is, to the source plane) and beta_ij = D_ij D_s / (D_j D_is) is the
+// distance ratio of planes i < j, given with the model; beta_iP = 1. The shear
+// belongs to plane 0. A light component on plane j is evaluated at x_j: plane 0
+// is light seen unlensed, plane P the source.
 // ---------------------------------------------------------------------------
 }  // namespace
 extern "C" {
 typedef struct {
-  int32_t n_sie;       // 0..8
-  int32_t shear;       // 0 or 1
-  int32_t n_sersic;    // 1..8
-  int32_t sky;         // 0 or 1
-  int32_t plane[8];    // per Sersic: 0 = image plane, 1 = source plane
+  int32_t n_sie;        // 0..8
+  int32_t shear;        // 0 or 1
+  int32_t n_sersic;     // 1..8
+  int32_t sky;          // 0 or 1
+  int32_t plane[8];     // per Sersic: its plane, 0..n_planes (n_planes = the source plane)
+  int32_t n_planes;     // lens planes P, 1..8 (0 reads as 1)
+  int32_t sie_plane[8]; // per SIE: its lens plane, 0..P-1
+  int32_t reserved;     // 0
+  double beta[8][8];    // beta[i][j], 0 <= i < j < P: distance ratio, in [0, 1]
 } lo_model;
 }
 namespace {
+
+int lens_planes(const lo_model& M) { return M.n_planes < 1 ? 1 : M.n_planes; }
 
 int model_nparams(const lo_model& M) { return 5 * M.n_sie + (M.shear ? 2 : 0) + 7 * M.n_sersic + (M.sky ? 1 : 0); }
 
@@ -338,44 +354,88 @@ template <class T> GenericParams<T> make_generic(const lo_model& M, const T* th)
   return G;
 }
 
-template <class T> T surface_brightness(const GenericParams<T>& G, T x, T y) {
+// Summed deflection of the deflectors of lens plane `plane` at (x, y).
+template <class T> void plane_deflection(const GenericParams<T>& G, int plane, T x, T y, T& ax, T& ay) {
   const lo_model& M = *G.M;
   const T* p = G.p.data();
-  int o = 0;
-  T ax(0.0), ay(0.0);
-  for (int k = 0; k < M.n_sie; ++k, o += 5) {
+  ax = T(0.0);
+  ay = T(0.0);
+  for (int k = 0; k < M.n_sie; ++k) {
+    if ((lens_planes(M) > 1 ? M.sie_plane[k] : 0) != plane) continue;
+    const T* s = p + 5 * k;
     T sx, sy;
-    sie_deflection(p[o + 2], p[o + 3], p[o + 4], x - p[o], y - p[o + 1], sx, sy);
+    sie_deflection(s[2], s[3], s[4], x - s[0], y - s[1], sx, sy);
     ax = ax + sx;
     ay = ay + sy;
   }
-  if (M.shear) {
+  if (M.shear && plane == 0) {
     T gx, gy;
-    shear_deflection(p[o], p[o + 1], x, y, gx, gy);
+    shear_deflection(p[5 * M.n_sie], p[5 * M.n_sie + 1], x, y, gx, gy);
     ax = ax + gx;
     ay = ay + gy;
-    o += 2;
   }
-  const T bx = x - ax, by = y - ay;
+}
+
+// Position of the ray through the image-plane point (x, y) on every plane,
+// lens planes 0..P-1 and the source plane P (the multi-plane lens equation;
+// with one plane, Eq. 1).
+template <class T> void plane_positions(const GenericParams<T>& G, T x, T y, std::vector<T>& px, std::vector<T>& py) {
+  const lo_model& M = *G.M;
+  const int P = lens_planes(M);
+  std::vector<T> ax(P), ay(P);
+  px.assign(P + 1, x);
+  py.assign(P + 1, y);
+  for (int j = 0; j <= P; ++j) {
+    T sx = x, sy = y;
+    for (int i = 0; i < j; ++i) {
+      const double b = j == P ? 1.0 : M.beta[i][j];
+      sx = sx - b * ax[i];
+      sy = sy - b * ay[i];
+    }
+    px[j] = sx;
+    py[j] = sy;
+    if (j < P) plane_deflection(G, j, sx, sy, ax[j], ay[j]);
+  }
+}
+
+template <class T> T surface_brightness(const GenericParams<T>& G, T x, T y) {
+  const lo_model& M = *G.M;
+  const T* p = G.p.data();
+  std::vector<T> px, py;
+  plane_positions(G, x, y, px, py);
+  int o = 5 * M.n_sie + (M.shear ? 2 : 0);
   T I(0.0);
   for (int j = 0; j < M.n_sersic; ++j, o += 7) {
     const T* s = p + o;
-    I = I + (M.plane[j] ? sersic(bx, by, s[0], s[1], s[2], s[3], s[4], s[5], s[6], G.b[j])
-                        : sersic(x, y, s[0], s[1], s[2], s[3], s[4], s[5], s[6], G.b[j]));
+    const int k = M.plane[j];
+    I = I + sersic(px[k], py[k], s[0], s[1], s[2], s[3], s[4], s[5], s[6], G.b[j]);
   }
   if (M.sky) I = I + p[o];
   return I;
 }
 
+// The lens planes of a model: P in 1..8, every SIE on a lens plane, distance
+// ratios in [0, 1] (D_ij <= D_is for planes i < j before the source).
+bool model_shape_valid(const lo_model& M) {
+  if (M.n_planes < 0 || M.n_planes > 8) return false;
+  const int P = lens_planes(M);
+  if (P == 1) return true;
+  for (int k = 0; k < M.n_sie; ++k) if (M.sie_plane[k] < 0 || M.sie_plane[k] >= P) return false;
+  for (int i = 0; i < P; ++i)
+    for (int j = i + 1; j < P; ++j) if (!(M.beta[i][j] >= 0.0 && M.beta[i][j] <= 1.0)) return false;
+  return true;
+}
+
 bool model_valid(const lo_model* M, const double* th) {
   if (!M || M->n_sie < 0 || M->n_sie > 8 || M->n_sersic < 1 || M->n_sersic > 8) return false;
   if ((M->shear != 0 && M->shear != 1) || (M->sky != 0 && M->sky != 1)) return false;
+  if (!model_shape_valid(*M)) return false;
   for (int i = 0; i < model_nparams(*M); ++i) if (!std::isfinite(th[i])) return false;
   for (int k = 0; k < M->n_sie; ++k) if (!(th[5 * k + 3] > 0.0 && th[5 * k + 3] <= 1.0)) return false;
   const int o = 5 * M->n_sie + (M->shear ? 2 : 0);
   for (int j = 0; j < M->n_sersic; ++j) {
     const double* s = th + o + 7 * j;
-    if (M->plane[j] != 0 && M->plane[j] != 1) return false;
+    if (M->plane[j] < 0 || M->plane[j] > lens_planes(*M)) return false;
     if (!(s[3] > 0.0) || !(s[4] >= 0.2 && s[4] <= 10.0) || !(s[5] > 0.0 && s[5] <= 1.0)) return false;
   }
   return true;
@@ -636,6 +696,21 @@ double lo_loglike_grad(const lo_system* S, const double* theta, double* grad) {
 
 // Model image and log L of a general model (see lo_model).
 int lo_model_nparams(const lo_model* M) { return M ? model_nparams(*M) : -1; }
+
+// Position of the ray through the image-plane point (x, y) on the lens planes
+// 0..P-1 and the source plane P: px, py [P + 1], written. Returns 1 for an
+// invalid model or point.
+int lo_model_positions(const lo_model* M, const double* theta, double x, double y, double* px, double* py) {
+  if (!M || !theta || !px || !py || !model_valid(M, theta)) return 1;
+  const GenericParams<double> G = make_generic(*M, theta);
+  std::vector<double> vx, vy;
+  plane_positions(G, x, y, vx, vy);
+  for (size_t j = 0; j < vx.size(); ++j) {
+    px[j] = vx[j];
+    py[j] = vy[j];
+  }
+  return 0;
+}
 
 int lo_render_model(const lo_system* S, const lo_model* M, const double* theta, int apply_psf, double* out) {
   if (!system_valid(S) || !M || !theta || !out) return 1;

@@ -46,26 +46,56 @@ class LensedSystemC(ctypes.Structure):
 class LensedModelC(ctypes.Structure):
     """Mirror of lensed_model in include/lensed.h."""
     _fields_ = [("n_sie", ctypes.c_int32), ("shear", ctypes.c_int32), ("n_sersic", ctypes.c_int32),
-                ("sky", ctypes.c_int32), ("plane", ctypes.c_int32 * 8)]
+                ("sky", ctypes.c_int32), ("plane", ctypes.c_int32 * 8), ("n_planes", ctypes.c_int32),
+                ("sie_plane", ctypes.c_int32 * 8), ("reserved", ctypes.c_int32),
+                ("beta", (ctypes.c_double * 8) * 8)]
 
 
 class Model:
     """A general model (several SIEs with free centres, an optional shear, several
     Sersic components, an optional flat sky; Sec. 5). planes: one entry per
-    Sersic, "foreground" (light at x: lens galaxies) or "lensed" (light at beta).
+    Sersic, "foreground" (light at x: lens galaxies), "lensed" (light at the
+    source plane) or the index of the plane the light sits on.
     Parameters per point: per SIE (x_c, y_c, theta_E, q, phi); shear (gamma,
-    phi_gamma); per Sersic (x, y, I_e, R_e, n, q, phi); sky."""
+    phi_gamma); per Sersic (x, y, I_e, R_e, n, q, phi); sky.
 
-    def __init__(self, n_sie: int, planes: Sequence[str], shear: bool = True, sky: bool = False):
+    Lenses on several planes: beta, a P x P array of the distance ratios
+    beta[i][j] (i < j) of the multi-plane lens equation, and sie_planes, the
+    lens plane of every SIE (default: all on plane 0); "lensed" is then plane P."""
+
+    def __init__(self, n_sie: int, planes: Sequence, shear: bool = True, sky: bool = False,
+                 sie_planes: Optional[Sequence[int]] = None, beta=None):
         planes = list(planes)
-        if any(p not in ("foreground", "lensed") for p in planes):
-            raise ValueError("planes must be 'foreground' or 'lensed'")
-        codes = [1 if p == "lensed" else 0 for p in planes] + [0] * max(0, 8 - len(planes))
+        n_planes = 1 if beta is None else len(beta)
+        codes = []
+        for p in planes:
+            if p == "foreground":
+                codes.append(0)
+            elif p == "lensed":
+                codes.append(n_planes)
+            elif isinstance(p, (int, np.integer)):
+                codes.append(int(p))
+            else:
+                raise ValueError("planes must be 'foreground', 'lensed' or a plane index")
+        codes += [0] * max(0, 8 - len(codes))
+        sp = [0] * int(n_sie) if sie_planes is None else [int(k) for k in sie_planes]
+        if len(sp) != n_sie:
+            raise ValueError("sie_planes needs one lens plane per SIE")
+        b = ((ctypes.c_double * 8) * 8)()
+        if beta is not None:
+            beta = np.asarray(beta, np.float64)
+            if beta.shape != (n_planes, n_planes) or n_planes > 8:
+                raise ValueError("beta must be a square array of at most 8 x 8")
+            for i in range(n_planes):
+                for j in range(n_planes):
+                    b[i][j] = beta[i, j]
+        self.n_planes = n_planes
         self.c_struct = LensedModelC(int(n_sie), int(bool(shear)), len(planes), int(bool(sky)),
-                                     (ctypes.c_int32 * 8)(*codes[:8]))
+                                     (ctypes.c_int32 * 8)(*codes[:8]), n_planes,
+                                     (ctypes.c_int32 * 8)(*(sp + [0] * (8 - len(sp)))[:8]), 0, b)
         self.n_params = lib().lensed_model_nparams(ctypes.byref(self.c_struct))
         if self.n_params < 0 or len(planes) > 8:
-            raise ValueError("a model has 0..8 SIEs and 1..8 Sersic components")
+            raise ValueError("invalid model: 0..8 SIEs, 1..8 Sersic components, planes and ratios in range")
 
 
 RULES = {"sub": 0, "g3k7": 1, "g5k11": 2, "g7k15": 3}

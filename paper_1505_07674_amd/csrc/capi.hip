@@ -25,6 +25,9 @@ static_assert(offsetof(lensed_system, psf) == 32 && offsetof(lensed_system, rule
                   offsetof(lensed_system, amplitude) == 60 && offsetof(lensed_system, zero_point) == 64 &&
                   offsetof(lensed_system, source_position) == 68 && sizeof(lensed_system) == 72,
               "lensed_system layout");
+static_assert(offsetof(lensed_model, n_planes) == 48 && offsetof(lensed_model, beta) == 88 &&
+                  sizeof(lensed_model) == 600,
+              "lensed_model layout");
 
 struct lensed_ctx {
   int device = 0;
@@ -543,15 +546,35 @@ int model_spec(lensed_ctx* c, const lensed_model* m, ModelSpec& spec) {
     return set_err(c, LENSED_INVALID_ARGUMENT, "n_sersic must be in 1..8");
   if ((m->shear != 0 && m->shear != 1) || (m->sky != 0 && m->sky != 1))
     return set_err(c, LENSED_INVALID_ARGUMENT, "shear and sky must be 0 or 1");
+  if (m->n_planes < 0 || m->n_planes > MAX_PLANES)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "n_planes must be in 0..8");
+  const int P = m->n_planes < 1 ? 1 : m->n_planes;
   std::memset(&spec, 0, sizeof(spec));
   spec.n_sie = m->n_sie;
   spec.shear = m->shear;
   spec.n_sersic = m->n_sersic;
   spec.sky = m->sky;
+  spec.n_planes = P;
   for (int j = 0; j < m->n_sersic; ++j) {
-    if (m->plane[j] != LENSED_LIGHT_FOREGROUND && m->plane[j] != LENSED_LIGHT_LENSED)
-      return set_err(c, LENSED_INVALID_ARGUMENT, "plane[" + std::to_string(j) + "] must be a LENSED_LIGHT_* value");
+    if (m->plane[j] < 0 || m->plane[j] > P)
+      return set_err(c, LENSED_INVALID_ARGUMENT,
+                     "plane[" + std::to_string(j) + "] must be a plane index in 0..n_planes");
     spec.plane[j] = m->plane[j];
+  }
+  if (P > 1) {
+    for (int k = 0; k < m->n_sie; ++k) {
+      if (m->sie_plane[k] < 0 || m->sie_plane[k] >= P)
+        return set_err(c, LENSED_INVALID_ARGUMENT,
+                       "sie_plane[" + std::to_string(k) + "] must be a lens plane in 0..n_planes-1");
+      spec.sie_plane[k] = m->sie_plane[k];
+    }
+    for (int i = 0; i < P; ++i)
+      for (int j = i + 1; j < P; ++j) {
+        if (!(m->beta[i][j] >= 0.0 && m->beta[i][j] <= 1.0))
+          return set_err(c, LENSED_INVALID_ARGUMENT,
+                         "beta[" + std::to_string(i) + "][" + std::to_string(j) + "] must be in [0, 1]");
+        spec.beta[i][j] = m->beta[i][j];
+      }
   }
   return LENSED_OK;
 }
@@ -594,7 +617,7 @@ int lensed_render_model(lensed_ctx* c, const lensed_system* sys, const lensed_mo
   // the 17-parameter prologue with no points normalises the PSF
   LENSED_HIP(c, launch_prologue(theta, 0, nullptr, nullptr, nullptr, sd, nullptr, 1, (int*)(c->arena + off_cc), st));
   LENSED_HIP(c, launch_model_prologue(theta, 1, spec_params(spec), spec, mc, st));
-  LENSED_HIP(c, launch_model_render(w, mc, L, sd.n_rtiles, st));
+  LENSED_HIP(c, launch_model_render(w, spec, mc, L, sd.n_rtiles, st));
   if (apply_psf)
     LENSED_HIP(c, launch_psf(w, L, image, nullptr, 0, sd.n_ptiles, square_psf_code(sd.ph, sd.pw), sd.TW, sd.TH,
                              sd.ph, sd.pw, st));

@@ -63,7 +63,8 @@ hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointCo
 // per point, the layout of lensed_model), and the float64 render into L.
 hipError_t launch_model_prologue(const float* theta, int n_points, int n_params, const ModelSpec& spec,
                                  ModelConst* out, hipStream_t stream);
-hipError_t launch_model_render(const WorkArgs& w, const ModelConst* mcs, float* L, int n_blocks, hipStream_t stream);
+hipError_t launch_model_render(const WorkArgs& w, const ModelSpec& spec, const ModelConst* mcs, float* L, int n_blocks,
+                               hipStream_t stream);
 
 // Composite models (K consecutive points each): L[first image of model m] =
 // sum of its K unconvolved images + sky[m] pixscale^2 (sky may be nullptr), in

@@ -305,7 +305,7 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
   wr.items = d_ritems_;
   wr.n_items = n_ritems_;
   if (has_model_) {
-    if ((e = launch_model_render(wr, d_mc_, d_L_, n_ritems_, st)) != hipSuccess) return e;
+    if ((e = launch_model_render(wr, spec_, d_mc_, d_L_, n_ritems_, st)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
   } else {
     if ((e = launch_render(wr, d_pc_, d_p64_, d_L_, n_ritems_, cusp_, st, ev ? ev[2] : nullptr)) != hipSuccess)

@@ -1,0 +1,134 @@
+"""GPU parity of general models with lenses on several planes (the multi-plane
+extension named in Sec. 6) against the FP64 oracle: images with the midpoint
+and a Gauss-Kronrod rule, batched log L over two systems, coincident planes
+against the one-plane model, and models the library must refuse."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1505_07674_amd as lensed
+from paper_1505_07674_amd.binding import LensedError
+
+from helpers import loglike_tolerance
+from test_gpu_grad import small_spec
+from test_gpu_model import gsys, osys
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+# Three lens planes: the main lens (with the shear) on plane 0, a second lens
+# behind it on plane 1, a third on plane 2; the light of each lens on its own
+# plane, the source on plane 3, and a sky.
+BETA = np.zeros((3, 3))
+BETA[0, 1], BETA[0, 2], BETA[1, 2] = 0.45, 0.7, 0.38
+LIGHT_PLANES = [0, 1, 2, "source"]
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def models(beta=BETA):
+    gp = [p if p != "source" else "lensed" for p in LIGHT_PLANES]
+    return (lensed.Model(3, gp, shear=True, sky=True, sie_planes=[0, 1, 2], beta=beta),
+            oracle.Model(3, LIGHT_PLANES, shear=True, sky=True, sie_planes=[0, 1, 2], beta=beta))
+
+
+def three_plane_points(n, seed):
+    """46 parameters: 3 SIEs, shear, 4 Sersics, sky."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for _ in range(n):
+        p = [rng.uniform(-0.05, 0.05), rng.uniform(-0.05, 0.05), rng.uniform(0.7, 1.0), rng.uniform(0.5, 1.0),
+             rng.uniform(0, math.pi)]
+        c1 = rng.uniform(0.4, 0.8) * np.array([math.cos(a := rng.uniform(0, 6.28)), math.sin(a)])
+        c2 = rng.uniform(0.2, 0.6) * np.array([math.cos(b := rng.uniform(0, 6.28)), math.sin(b)])
+        p += [c1[0], c1[1], rng.uniform(0.2, 0.4), rng.uniform(0.6, 1.0), rng.uniform(0, math.pi)]
+        p += [c2[0], c2[1], rng.uniform(0.1, 0.3), rng.uniform(0.6, 1.0), rng.uniform(0, math.pi)]
+        p += [rng.uniform(0, 0.08), rng.uniform(0, math.pi)]
+        p += [p[0], p[1], rng.uniform(0.1, 0.3), rng.uniform(0.5, 1.2), rng.uniform(2, 5), rng.uniform(0.6, 1),
+              rng.uniform(0, math.pi)]
+        p += [c1[0], c1[1], rng.uniform(0.05, 0.2), rng.uniform(0.1, 0.4), rng.uniform(1, 4), rng.uniform(0.6, 1),
+              rng.uniform(0, math.pi)]
+        p += [c2[0], c2[1], rng.uniform(0.05, 0.2), rng.uniform(0.1, 0.3), rng.uniform(1, 4), rng.uniform(0.6, 1),
+              rng.uniform(0, math.pi)]
+        p += [rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), rng.uniform(0.5, 2), rng.uniform(0.05, 0.4),
+              rng.uniform(0.5, 4), rng.uniform(0.3, 1), rng.uniform(0, math.pi)]
+        p += [rng.uniform(0.0, 0.5)]
+        rows.append(p)
+    return np.array(rows, np.float32)
+
+
+@pytest.mark.parametrize("rule", ["sub", "g3k7"])
+def test_three_plane_images_match_the_oracle(rule):
+    spec = small_spec(H=48, W=44, N=3)
+    gm, om = models()
+    assert gm.n_params == om.n_params == 46
+    g, o = gsys(spec, rule=rule), osys(spec, rule=None if rule == "sub" else rule)
+    say(f"three-plane model images, rule {rule}")
+    for t in three_plane_points(6, seed=80):
+        for psf in (False, True):
+            img = lensed.render_model(torch.from_numpy(t).to(DEV), g, gm, apply_psf=psf).cpu().numpy()
+            ref = oracle.render_model(o, om, t.astype(np.float64), apply_psf=psf)
+            err = np.max(np.abs(img.astype(np.float64) - ref)) / np.max(np.abs(ref))
+            assert err <= 1e-6, (rule, psf, err)      # float64 throughout, rounded once
+
+
+def test_three_plane_loglike_matches_the_oracle():
+    specs = [small_spec(), small_spec(H=36, W=44, N=2, center=(-0.04, 0.06))]
+    gm, om = models()
+    truth = three_plane_points(1, seed=81)[0]
+    gs, os_ = [], []
+    for s in specs:
+        model = oracle.render_model(osys(s), om, truth.astype(np.float64))
+        sigma = 0.01 * model.max()
+        data = (model + sigma * np.random.default_rng(s.width).standard_normal(model.shape)).astype(np.float32)
+        weight = np.full(model.shape, 1.0 / sigma ** 2, np.float32)
+        gs.append(gsys(s, data, weight))
+        os_.append(osys(s, data.astype(np.float64), weight.astype(np.float64)))
+    pts = three_plane_points(16, seed=82)
+    som = np.arange(16, dtype=np.int32) % 2
+    say("three-plane log L, 16 points, 2 systems")
+    ll = lensed.loglike_model_batch(torch.from_numpy(pts).to(DEV), som, gs, gm).cpu().numpy()
+    ref = np.array([oracle.loglike_model(os_[som[i]], om, pts[i].astype(np.float64)) for i in range(16)])
+    tol = np.array([loglike_tolerance(ref[i:i + 1], gs[som[i]].weight.cpu().numpy())[0] for i in range(16)])
+    err = np.abs(ll - ref) / tol
+    say(f"log L errors / bar: max {err.max():.3f}")
+    assert np.all(err <= 1.0), (err, ref)
+
+
+def test_coincident_planes_are_the_one_plane_model():
+    """All ratios 0: every plane sees x, so the lens planes collapse into one."""
+    spec = small_spec()
+    g = gsys(spec)
+    gm0, _ = models(beta=np.zeros((3, 3)))
+    one = lensed.Model(3, ["foreground"] * 3 + ["lensed"], shear=True, sky=True)
+    say("coincident planes vs one plane")
+    for t in three_plane_points(3, seed=83):
+        a = lensed.render_model(torch.from_numpy(t).to(DEV), g, gm0).cpu().numpy().astype(np.float64)
+        b = lensed.render_model(torch.from_numpy(t).to(DEV), g, one).cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(a - b)) <= 1e-6 * np.max(np.abs(b))
+
+
+def test_invalid_plane_layouts_are_refused():
+    spec = small_spec()
+    g = gsys(spec)
+    gm, _ = models()
+    t = torch.from_numpy(three_plane_points(1, seed=84)[0]).to(DEV)
+    img = lensed.render_model(t, g, gm)
+    assert torch.isfinite(img).all()
+    for field, value in [("n_planes", 9), ("sie_plane", 3), ("beta", 1.5), ("plane", 4)]:
+        m, _ = models()
+        if field == "n_planes":
+            m.c_struct.n_planes = value
+        elif field == "sie_plane":
+            m.c_struct.sie_plane[2] = value
+        elif field == "beta":
+            m.c_struct.beta[0][2] = value
+        else:
+            m.c_struct.plane[3] = value
+        with pytest.raises(LensedError):
+            lensed.render_model(t, g, m)
