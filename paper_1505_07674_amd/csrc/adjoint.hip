@@ -43,8 +43,12 @@ __device__ __forceinline__ void resolve(const WorkArgs& w, int& point, int& tile
 // ---------------------------------------------------------------------------
 // g = A^T rho, interior pixels: g[u][v] = sum_{a,b} rho0[u+a][v+b] F[a][b].
 // ---------------------------------------------------------------------------
+// TWc = 0 with P >= 0: a wide tile (runtime width, LDS stride WIDE_STRIDE), as
+// in the forward stencil.
 template <int P, int TWc, int ROWS>
-__global__ __launch_bounds__(512) void adj_psf_kernel(WorkArgs w, const float* __restrict__ R, float* __restrict__ G) {
+__global__ __launch_bounds__(P >= 0 && TWc == 0 ? WIDE_MAX_THREADS : 512) void adj_psf_kernel(
+    WorkArgs w, const float* __restrict__ R, float* __restrict__ G) {
+  constexpr bool WIDE = P >= 0 && TWc == 0;
   extern __shared__ float S[];
   int point, tile;
   resolve(w, point, tile);
@@ -52,8 +56,9 @@ __global__ __launch_bounds__(512) void adj_psf_kernel(WorkArgs w, const float* _
   const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
   const int p = P >= 0 ? P : sd.ph / 2;
   const int q = P >= 0 ? P : sd.pw / 2;
-  const int TW = P >= 0 ? TWc : sd.TW, TH = sd.TH;
-  const int SW = TW + 2 * q, SH = TH + 2 * p;
+  const int TW = (P >= 0 && !WIDE) ? TWc : sd.TW, TH = sd.TH;
+  const int SW = TW + 2 * q, SH = TH + 2 * p;     // staged columns and rows
+  const int LS = WIDE ? WIDE_STRIDE : SW;         // LDS row stride
   const int ty = tile / sd.tiles_x, tx = tile - ty * sd.tiles_x;
   const int x0 = tx * TW, y0 = ty * TH;
   const float* __restrict__ Rp = R + loff;
@@ -64,7 +69,7 @@ __global__ __launch_bounds__(512) void adj_psf_kernel(WorkArgs w, const float* _
     const int gi = y0 + row - p;
     for (int col = jx; col < SW; col += TW) {
       const int gj = x0 + col - q;
-      S[row * SW + col] = (gi >= 0 && gi < sd.H && gj >= 0 && gj < sd.W) ? Rp[(size_t)gi * sd.W + gj] : 0.0f;
+      S[row * LS + col] = (gi >= 0 && gi < sd.H && gj >= 0 && gj < sd.W) ? Rp[(size_t)gi * sd.W + gj] : 0.0f;
     }
   }
   __syncthreads();
@@ -74,7 +79,7 @@ __global__ __launch_bounds__(512) void adj_psf_kernel(WorkArgs w, const float* _
   for (int r = 0; r < ROWS; ++r) acc[r] = 0.0f;
   if (P >= 0) {
     constexpr int K = 2 * (P > 0 ? P : 0) + 1;
-    constexpr int SWc = (TWc > 0 ? TWc : 1) + K - 1;
+    constexpr int SWc = WIDE ? WIDE_STRIDE : (TWc > 0 ? TWc : 1) + K - 1;
     // taps F[k][l] of stencil column l, contiguous in k
     stencil_columns<K, SWc, ROWS>(S + i0 * SWc + jx, uniform_const(sd.psfn + 2 * K * K), acc);
   } else {
@@ -596,9 +601,11 @@ hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n
   if (n_blocks <= 0) return hipSuccess;
   const int Rr = psf_rows(square_psf, TW, TH);
   const int threads = TW * (TH / Rr);
-  const size_t lds = sizeof(float) * (size_t)(TW + pw - 1) * (size_t)(TH + ph - 1);
+  const size_t lds = psf_lds_bytes(square_psf, TW, TH, ph, pw);
   hipError_t e;
-  if (psf_specialised(square_psf, TW)) {
+  if (psf_wide(square_psf, TW)) {
+    e = launch_adj_t<10, 0, 8>(w, R, G, n_blocks, threads, lds, st);
+  } else if (psf_specialised(square_psf, TW)) {
     if (square_psf == 21) e = Rr == 8 ? launch_adj_w<10, 8>(TW, w, R, G, n_blocks, threads, lds, st)
                                       : launch_adj_w<10, 4>(TW, w, R, G, n_blocks, threads, lds, st);
     else if (square_psf == 7) e = launch_adj_w<3, 4>(TW, w, R, G, n_blocks, threads, lds, st);

@@ -33,7 +33,7 @@ class TileCache {
   bool has_measured(const lensed_system* s, int n) const { return measured_.count(key(s, n)) != 0; }
   void set_measured(const lensed_system* s, int n, TileShape t) { measured_[key(s, n)] = t; }
   static double model_cost(int H, int W, int ph, int pw, TileShape t, int sq);
-  static std::vector<TileShape> candidates(int sq);
+  static std::vector<TileShape> candidates(int sq, const lensed_system* s = nullptr, int n = 0);
 
  private:
   static std::string key(const lensed_system* s, int n);

@@ -8,7 +8,7 @@
 
 namespace lensed {
 
-std::vector<TileShape> TileCache::candidates(int sq) {
+std::vector<TileShape> TileCache::candidates(int sq, const lensed_system* s, int n) {
   std::vector<TileShape> out;
   const int tws[] = {16, 32, 40, 48, 64};
   const int ths[] = {16, 20, 24, 32, 40, 48, 64};
@@ -16,6 +16,21 @@ std::vector<TileShape> TileCache::candidates(int sq) {
     for (int th : ths) {
       const int threads = tw * th / psf_rows(sq, tw, th);
       if (threads >= 64 && threads <= 512) out.push_back({tw, th});
+    }
+  // Wide tiles of the 21 x 21 stencil: a whole image row, or a half or a third
+  // of it, so that the tiles cover the image without ragged columns; heights
+  // whose LDS block stays within 64 KiB.
+  for (int i = 0; s && i < n; ++i)
+    for (int parts = 1; parts <= 3; ++parts) {
+      const int tw = (s[i].width + parts - 1) / parts;
+      if (!psf_wide(sq, tw)) continue;
+      for (int th : {16, 24, 32, 40}) {
+        const int threads = tw * th / psf_rows(sq, tw, th);
+        const TileShape t{tw, th};
+        if (threads < 64 || threads > WIDE_MAX_THREADS || psf_lds_bytes(sq, tw, th, 21, 21) > 65536) continue;
+        if (std::none_of(out.begin(), out.end(), [&](const TileShape& o) { return o.TW == tw && o.TH == th; }))
+          out.push_back(t);
+      }
     }
   return out;
 }
@@ -59,7 +74,7 @@ int TileCache::launch_square(const lensed_system* s, int n) {
 std::vector<TileShape> TileCache::ranked(const lensed_system* s, int n, int k) const {
   const int sq = launch_square(s, n);
   std::vector<std::pair<double, TileShape>> all;
-  for (const TileShape& t : candidates(sq)) {
+  for (const TileShape& t : candidates(sq, s, n)) {
     double cst = 0.0;
     for (int i = 0; i < n; ++i) cst += model_cost(s[i].height, s[i].width, s[i].psf_h, s[i].psf_w, t, sq);
     all.push_back({cst, t});
@@ -79,7 +94,7 @@ TileShape TileCache::choose(const lensed_system& s) {
   TileShape best{32, 32};
   double bc = 1e300;
   const int sq = square_psf_code(s.psf_h, s.psf_w);
-  for (const TileShape& t : candidates(sq)) {
+  for (const TileShape& t : candidates(sq, &s, 1)) {
     const double cst = model_cost(s.height, s.width, s.psf_h, s.psf_w, t, sq);
     if (cst < bc) {
       bc = cst;

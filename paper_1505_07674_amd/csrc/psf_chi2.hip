@@ -24,11 +24,13 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   e = (a - (s - bb)) + (b - bb);
 }
 
-// P >= 0: square (2P+1)^2 PSF, tile width TWc, ROWS outputs per thread.
+// P >= 0: square (2P+1)^2 PSF, tile width TWc, ROWS outputs per thread; with
+// TWc = 0 a wide tile: runtime width sd.TW <= WIDE_MAX_TW, LDS stride WIDE_STRIDE.
 // P = -1: any PSF and tile width, ROWS = 4.
 template <int P, int TWc, int ROWS>
-__global__ __launch_bounds__(512) void psf_kernel(WorkArgs w, const float* __restrict__ L, float* __restrict__ out,
-                                                   float2* __restrict__ partials, int mode) {
+__global__ __launch_bounds__(P >= 0 && TWc == 0 ? WIDE_MAX_THREADS : 512) void psf_kernel(
+    WorkArgs w, const float* __restrict__ L, float* __restrict__ out, float2* __restrict__ partials, int mode) {
+  constexpr bool WIDE = P >= 0 && TWc == 0;
   extern __shared__ float S[];
   __shared__ float red_hi[16], red_lo[16];
   int point, tile;
@@ -44,8 +46,9 @@ __global__ __launch_bounds__(512) void psf_kernel(WorkArgs w, const float* __res
   const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
   const int p = P >= 0 ? P : sd.ph / 2;
   const int q = P >= 0 ? P : sd.pw / 2;
-  const int TW = P >= 0 ? TWc : sd.TW, TH = sd.TH;
-  const int SW = TW + 2 * q, SH = TH + 2 * p;
+  const int TW = (P >= 0 && !WIDE) ? TWc : sd.TW, TH = sd.TH;
+  const int SW = TW + 2 * q, SH = TH + 2 * p;     // staged columns and rows
+  const int LS = WIDE ? WIDE_STRIDE : SW;         // LDS row stride
   const int ty = tile / sd.tiles_x, tx = tile - ty * sd.tiles_x;
   const int x0 = tx * TW, y0 = ty * TH;
   const float* __restrict__ Lp = L + loff;
@@ -53,12 +56,23 @@ __global__ __launch_bounds__(512) void psf_kernel(WorkArgs w, const float* __res
   const int jx = tid % TW, jy = tid / TW;
   const int rows_per_pass = blockDim.x / TW;
 
-  for (int row = jy; row < SH; row += rows_per_pass) {
-    const int gi = min(max(y0 + row - p, 0), sd.H - 1);
-    const float* __restrict__ src = Lp + (size_t)gi * sd.W;
-    for (int col = jx; col < SW; col += TW) {
-      const int gj = min(max(x0 + col - q, 0), sd.W - 1);
-      S[row * SW + col] = src[gj];
+  // Stage the tile and its halo, four rows per pass so that four loads are in
+  // flight before their LDS stores.
+  for (int col = jx; col < SW; col += TW) {
+    const int gj = min(max(x0 + col - q, 0), sd.W - 1);
+    for (int row0 = jy; row0 < SH; row0 += 4 * rows_per_pass) {
+      float v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = row0 + u * rows_per_pass;
+        const int gi = min(max(y0 + row - p, 0), sd.H - 1);
+        v[u] = row < SH ? Lp[(size_t)gi * sd.W + gj] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = row0 + u * rows_per_pass;
+        if (row < SH) S[row * LS + col] = v[u];
+      }
     }
   }
   __syncthreads();
@@ -69,7 +83,7 @@ __global__ __launch_bounds__(512) void psf_kernel(WorkArgs w, const float* __res
   for (int r = 0; r < ROWS; ++r) acc[r] = 0.0f;
   if (P >= 0) {
     constexpr int K = 2 * (P > 0 ? P : 0) + 1;
-    constexpr int SWc = (TWc > 0 ? TWc : 1) + K - 1;
+    constexpr int SWc = WIDE ? WIDE_STRIDE : (TWc > 0 ? TWc : 1) + K - 1;
     // taps F[K-1-k][K-1-l] of stencil column l, contiguous in k
     stencil_columns<K, SWc, ROWS>(S + i0 * SWc + jx, uniform_const(sd.psfn + K * K), acc);
   } else {
@@ -112,16 +126,20 @@ __global__ __launch_bounds__(512) void psf_kernel(WorkArgs w, const float* __res
     }
   }
   float hi = sum, lo = -comp;
-  // wave reduction with error-free transformations
+  // wave reduction with error-free transformations; the last wave of a block
+  // whose size is not a multiple of 64 adds only the lanes it has
+  const int lane = tid & 63, wid = tid >> 6;
+  const int nact = min(64, (int)blockDim.x - (tid & ~63));
   for (int off = 32; off > 0; off >>= 1) {
     const float h2 = __shfl_down(hi, off, 64);
     const float l2 = __shfl_down(lo, off, 64);
-    float s, e;
-    two_sum(hi, h2, s, e);
-    hi = s;
-    lo = lo + l2 + e;
+    if (lane + off < nact) {
+      float s, e;
+      two_sum(hi, h2, s, e);
+      hi = s;
+      lo = lo + l2 + e;
+    }
   }
-  const int lane = tid & 63, wid = tid >> 6;
   if (lane == 0) {
     red_hi[wid] = hi;
     red_lo[wid] = lo;
@@ -179,9 +197,11 @@ hipError_t launch_psf(const WorkArgs& w, const float* L, float* out, float2* par
   if (n_blocks <= 0) return hipSuccess;
   const int R = psf_rows(square_psf, TW, TH);
   const int threads = TW * (TH / R);
-  const size_t lds = sizeof(float) * (size_t)(TW + max_pw - 1) * (size_t)(TH + max_ph - 1);
+  const size_t lds = psf_lds_bytes(square_psf, TW, TH, max_ph, max_pw);
   // Specialised stencils for the square PSFs of the standard workloads.
   if (psf_specialised(square_psf, TW)) {
+    if (psf_wide(square_psf, TW))
+      return launch_psf_t<10, 0, 8>(w, L, out, partials, mode, n_blocks, threads, lds, stream);
     if (square_psf == 21) {
       if (R == 8) return launch_psf_w<10, 8>(TW, w, L, out, partials, mode, n_blocks, threads, lds, stream);
       return launch_psf_w<10, 4>(TW, w, L, out, partials, mode, n_blocks, threads, lds, stream);

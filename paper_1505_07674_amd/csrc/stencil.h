@@ -42,14 +42,29 @@ __device__ __forceinline__ void stencil_columns(const float* __restrict__ Sb, cf
   }
 }
 
+// Wide tiles of the 21 x 21 stencil: the tile spans up to WIDE_MAX_TW columns
+// (a whole row of a 200-pixel image) and its LDS rows are WIDE_STRIDE floats
+// apart, a multiple of 64 dwords, so the R + 20 rows a thread reads in one
+// stencil column pair up as ds_read2st64 off a single base address.
+constexpr int WIDE_STRIDE = 256;
+constexpr int WIDE_MAX_TW = WIDE_STRIDE - 20;
+constexpr int WIDE_MAX_THREADS = 1024;
+inline bool psf_wide(int square_psf, int TW) { return square_psf == 21 && TW > 64 && TW <= WIDE_MAX_TW; }
+
 // Outputs per thread of the PSF and adjoint stencil kernels for a launch; the
 // launchers, the plans and the tile model all take it from here.
 inline int psf_rows(int square_psf, int TW, int TH) {
-  return (square_psf == 21 && (TW == 32 || TW == 64) && TH % 8 == 0) ? 8 : 4;
+  return (square_psf == 21 && (TW == 32 || TW == 64 || psf_wide(square_psf, TW)) && TH % 8 == 0) ? 8 : 4;
 }
-// Whether the launch uses a specialised stencil (compile-time K and tile width).
+// Whether the launch uses a specialised stencil (compile-time K and LDS stride).
 inline bool psf_specialised(int square_psf, int TW) {
-  return (square_psf == 21 || square_psf == 7 || square_psf == 1) && (TW == 32 || TW == 64);
+  return ((square_psf == 21 || square_psf == 7 || square_psf == 1) && (TW == 32 || TW == 64)) ||
+         (psf_wide(square_psf, TW));
+}
+// LDS bytes of a PSF or adjoint stencil block.
+inline size_t psf_lds_bytes(int square_psf, int TW, int TH, int ph, int pw) {
+  const size_t stride = psf_wide(square_psf, TW) ? WIDE_STRIDE : (size_t)(TW + pw - 1);
+  return sizeof(float) * stride * (size_t)(TH + ph - 1);
 }
 
 }  // namespace lensed

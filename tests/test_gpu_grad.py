@@ -105,6 +105,17 @@ def test_gradient_isothermal_sphere_and_round_source():
     check(spec, obs, pts)
 
 
+def test_gradient_wide_tiles_with_ragged_rows():
+    """The 21x21 stencil on wide tiles (a whole row, or half of one) whose last
+    row of tiles is ragged: the adjoint's A^T on those tiles."""
+    psf = mocks.moffat_psf(21, 0.1, 3.0, 0.05)
+    spec = small_spec(H=77, W=170, N=2, psf=psf, pixscale=0.05)
+    say("gradient, 77x170 sub2, 21x21 PSF")
+    obs = small_obs(spec)
+    pts = mocks.points(spec, 6, seed=49)
+    check(spec, obs, pts)
+
+
 def test_gradient_full_c1_shape():
     """The C3 configuration: the 200x200 sub4 Moffat-21 model, 1024 points per launch,
     checked against the oracle at sampled points."""

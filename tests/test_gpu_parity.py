@@ -158,6 +158,9 @@ def _custom_spec(H, W, N, psf, pixscale=0.07, center=(0.1, -0.05)):
     (5, 129, 5, 7, 7),       # thin strip, specialised 7x7 stencil
     (90, 33, 16, 21, 21),    # largest N, specialised 21x21 stencil, ragged
     (20, 20, 9, 3, 5),       # N outside the specialised set
+    (77, 170, 2, 21, 21),    # wide 21x21 tiles, ragged rows
+    (45, 236, 2, 21, 21),    # the widest single wide tile
+    (50, 237, 2, 21, 21),    # wide tiles, two or three per row
 ])
 def test_ragged_and_generic_shapes(H, W, N, ph, pw):
     say(f"shape {H}x{W} N={N} psf {ph}x{pw}")
