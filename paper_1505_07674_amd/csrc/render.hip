@@ -95,26 +95,91 @@ __global__ __launch_bounds__(RENDER_BLOCK) void render_kernel(WorkArgs w, const 
 
 // Adds the float64 cusp corrections to the flagged pixels; a fixed grid of
 // waves walks the list written by render_kernel (each pixel appears at most
-// once), one entry per wave at a time.
+// once), one entry per wave at a time. Only a few pixels of a flagged wave, and
+// a part of their subsamples, lie inside the re-tracing radius, so the wave
+// first finds those subsamples (float32, as the render saw them) and queues
+// them in LDS, then re-traces the queue in float64 64 at a time with every lane
+// busy. Each pixel then adds its subsamples' corrections in the rule's order
+// (zero outside the radius), as a serial loop over its subsamples would.
 constexpr int CUSP_WAVES = 4;
 constexpr int CUSP_BLOCKS = 2048;
+constexpr int CUSP_CHUNK = 16;   // subsamples per pass
+
+// LDS written by some lanes of a wave and read by others: order the accesses
+// and wait for the writes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ void subsample_xy(const GkRule* R, int N, int kx, int ky, const PixelGeom& g, float& x,
+                                             float& y) {
+  y = R ? fmaf(g.uy + R->x[ky], g.d, g.cy) : fmaf(g.uy + sub_offset_rt(ky, N), g.d, g.cy);
+  x = R ? fmaf(g.ux + R->x[kx], g.d, g.cx) : fmaf(g.ux + sub_offset_rt(kx, N), g.d, g.cx);
+}
 
 __global__ __launch_bounds__(64 * CUSP_WAVES) void cusp_kernel(WorkArgs w, const PointConst* __restrict__ pcs,
                                                                const PointConst64* __restrict__ p64s,
                                                                float* __restrict__ L, CuspList cl) {
+  __shared__ float dval[CUSP_WAVES][CUSP_CHUNK * 64];             // [subsample][lane]
+  __shared__ unsigned short queue[CUSP_WAVES][CUSP_CHUNK * 64];   // lane | subsample << 6
   const int n = *cl.count;
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * CUSP_WAVES + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wave = blockIdx.x * CUSP_WAVES + wv;
+  float* __restrict__ dv = dval[wv];
+  unsigned short* __restrict__ qu = queue[wv];
   for (int i = wave; i < n; i += gridDim.x * CUSP_WAVES) {
     const CuspEntry e = cl.entries[i];
-    if (!((e.mask >> lane) & 1ull)) continue;
+    const bool mine = (e.mask >> lane) & 1ull;
     const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[e.point] : 0] : w.single;
     const int64_t loff = w.point_loff ? w.point_loff[e.point] : 0;
     const int pix = e.pix0 + lane;
     const PixelGeom g = pixel_geom(sd, pix);
     const PointConst& c = pcs[e.point];
-    const float corr = cusp_correction(c, p64s[e.point], sd.rule, sd.N, g);
-    L[loff + pix] = (float)((double)L[loff + pix] + (double)corr * sd.wgt);
+    const PointConst64& c64 = p64s[e.point];
+    const GkRule* R = sd.rule > 0 ? &kGkRules[sd.rule - 1] : nullptr;
+    const int N = sd.N, NN = N * N;
+    float acc = 0.0f;
+    for (int s0 = 0; s0 < NN; s0 += CUSP_CHUNK) {
+      const int ns = min(CUSP_CHUNK, NN - s0);
+      // the chunk's subsamples inside the radius, queued in (subsample, lane) order
+      int qn = 0;
+      for (int j = 0; j < ns; ++j) {
+        const int ky = (s0 + j) / N, kx = s0 + j - ky * N;
+        float x, y;
+        subsample_xy(R, N, kx, ky, g, x, y);
+        const bool within = mine && render_source_R2(c, x, y) < c.cusp_r2;
+        dv[j * 64 + lane] = 0.0f;
+        const unsigned long long b = __ballot(within);
+        if (within) qu[qn + __popcll(b & ((1ull << lane) - 1ull))] = (unsigned short)(lane | (j << 6));
+        qn += __popcll(b);
+      }
+      wave_lds_sync();
+      // float64 re-tracing of the queue, 64 subsamples at a time
+      for (int q0 = 0; q0 < qn; q0 += 64) {
+        if (q0 + lane < qn) {
+          const int item = qu[q0 + lane];
+          const int pl = item & 63, j = item >> 6;
+          const int ky = (s0 + j) / N, kx = s0 + j - ky * N;
+          const PixelGeom gq = pixel_geom(sd, e.pix0 + pl);
+          float x, y;
+          subsample_xy(R, N, kx, ky, gq, x, y);
+          const float sR2 = render_source_R2(c, x, y);
+          const double ox = R ? R->xd[kx] : ((double)kx + 0.5) / N - 0.5;
+          const double oy = R ? R->xd[ky] : ((double)ky + 0.5) / N - 0.5;
+          float dx, dy;
+          source_offset_f64(c64, gq, ox, oy, dx, dy);
+          const float exact = sersic_shape(source_R2(c, dx, dy), c.se, c.sB);
+          const float d = exact - sersic_shape(sR2, c.se, c.sB);
+          dv[j * 64 + pl] = R ? R->w[kx] * R->w[ky] * d : d;
+        }
+      }
+      wave_lds_sync();
+      for (int j = 0; j < ns; ++j) acc += dv[j * 64 + lane];
+      wave_lds_sync();
+    }
+    if (mine) L[loff + pix] = (float)((double)L[loff + pix] + (double)(c.sI * acc) * sd.wgt);
   }
 }
 

@@ -301,31 +301,4 @@ __device__ __forceinline__ float pixel_sum_gk(const PointConst& c, const PixelGe
   return amplitudes(c, sh, ss);
 }
 
-// Correction for one flagged pixel: for every subsample in the cusp zone, the
-// source light at the float64 re-traced offset minus the render's float32 value,
-// with the rule's weight (rule 0: N x N midpoint, weight folded into the pixel
-// weight; else the Gauss-Kronrod rule of N = 7, 11, 15 nodes).
-__device__ __forceinline__ float cusp_correction(const PointConst& c, const PointConst64& c64, int rule, int N,
-                                                 const PixelGeom& g) {
-  float acc = 0.0f;
-  const GkRule* R = rule > 0 ? &kGkRules[rule - 1] : nullptr;
-  for (int ky = 0; ky < N; ++ky) {
-    const float y = R ? fmaf(g.uy + R->x[ky], g.d, g.cy) : fmaf(g.uy + sub_offset_rt(ky, N), g.d, g.cy);
-    const double oy = R ? R->xd[ky] : ((double)ky + 0.5) / N - 0.5;
-    for (int kx = 0; kx < N; ++kx) {
-      const float x = R ? fmaf(g.ux + R->x[kx], g.d, g.cx) : fmaf(g.ux + sub_offset_rt(kx, N), g.d, g.cx);
-      const float sR2 = render_source_R2(c, x, y);
-      if (sR2 < c.cusp_r2) {
-        const double ox = R ? R->xd[kx] : ((double)kx + 0.5) / N - 0.5;
-        float dx, dy;
-        source_offset_f64(c64, g, ox, oy, dx, dy);
-        const float exact = sersic_shape(source_R2(c, dx, dy), c.se, c.sB);
-        const float d = exact - sersic_shape(sR2, c.se, c.sB);
-        acc += R ? R->w[kx] * R->w[ky] * d : d;
-      }
-    }
-  }
-  return c.sI * acc;
-}
-
 }  // namespace lensed
