@@ -51,14 +51,6 @@ __device__ double sersic_bn(double n) {
   return gamma_median(2.0 * n, b0);
 }
 
-// d b_n / dn by a central difference of the root with h = 1e-5 n (truncation
-// of order 1e-10 times the third derivative, rounding of order 1e-11), each
-// side started from the converged b_n.
-__device__ double sersic_bn_deriv(double n, double b) {
-  const double h = 1e-5 * n;
-  return (gamma_median(2.0 * (n + h), b + 2.0 * h) - gamma_median(2.0 * (n - h), b - 2.0 * h)) / (2.0 * h);
-}
-
 // Digamma psi(z), z > 0: psi(z) = psi(z + 1) - 1/z up to z >= 8, then the
 // asymptotic expansion psi(z) ~ ln z - 1/(2z) - sum_k B_2k / (2k z^2k)
 // (Abramowitz & Stegun 6.3.18) to z^-12, below 1e-15 relative there.
@@ -159,10 +151,14 @@ __device__ void lens_map_jacobian(const double (&v)[7], float (&jac)[14]) {
 __device__ bool ok_q(float q) { return q > 0.0f && q <= 1.0f; }
 __device__ bool ok_n(float n) { return n >= 0.2f && n <= 10.0f; }
 
-__global__ void prologue_kernel(const float* __restrict__ theta, int n_points, PointConst* __restrict__ pcs,
+// One block of 64 threads covers 64 / solves points: first each of a point's
+// `solves` threads finds one root of P(2n, b) = 1/2 (b_n of the lens and the
+// source light; with the adjoint also b at n +- h for db_n/dn), then one thread
+// per point derives the rest. Extra blocks normalise the systems' PSFs.
+__global__ __launch_bounds__(64) void prologue_kernel(const float* __restrict__ theta, int n_points, PointConst* __restrict__ pcs,
                                 PointConst64* __restrict__ p64s, GradConst* __restrict__ gcs, SysDesc single,
                                 SysDesc* __restrict__ table, int n_sys, int point_blocks, int* __restrict__ cusp_count,
-                                double* __restrict__ grad_corr, const int* __restrict__ point_sys) {
+                                double* __restrict__ grad_corr, const int* __restrict__ point_sys, int solves) {
   if (cusp_count && blockIdx.x == 0 && threadIdx.x == 0) *cusp_count = 0;
   if ((int)blockIdx.x >= point_blocks) {
     // PSF normalisation: one block per system, float64 sum over the array.
@@ -218,8 +214,11 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
     }
     return;
   }
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_points) return;
+  __shared__ double roots[64];
+  const int ppb = 64 / solves;
+  const int pl = threadIdx.x / solves, j = threadIdx.x - pl * solves;
+  const int p = blockIdx.x * ppb + pl;
+  if (pl >= ppb || p >= n_points) return;   // no barrier below waits for these lanes' points
   float t[NPAR];
   bool valid = true;
   for (int k = 0; k < NPAR; ++k) {
@@ -228,6 +227,20 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
   }
   valid = valid && ok_q(t[1]) && ok_q(t[8]) && ok_q(t[15]) && t[6] > 0.0f && t[13] > 0.0f && ok_n(t[7]) &&
           ok_n(t[14]);
+  // roots: j = 0, 1: b_n of lens and source light; j = 2, 3 (4, 5): the same at n + h (n - h), h = 1e-5 n
+  {
+    double r = 0.0;
+    if (valid) {
+      const double n = (j & 1) ? t[14] : t[7];
+      r = j < 2 ? sersic_bn(n) : sersic_bn(j < 4 ? n + 1e-5 * n : n - 1e-5 * n);
+    }
+    roots[threadIdx.x] = r;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  if (j != 0) return;
+  const double* rt = roots + threadIdx.x;
 
   PointConst c;
   const double te = t[0], q = t[1], phL = t[2], g = t[3], phg = t[4];
@@ -253,11 +266,7 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
   c.m12 = (float)(-g2);
   c.m22 = (float)(1.0 + g1);
 
-  double bh = 0.0, bs = 0.0;
-  if (valid) {
-    bh = sersic_bn(t[7]);
-    bs = sersic_bn(t[14]);
-  }
+  const double bh = rt[0], bs = rt[1];
   // amplitudes: I_e given, or from total magnitudes (the point's system decides)
   const SysDesc* own = table ? &table[point_sys ? point_sys[p] : 0] : &single;
   const int amp = own->amp;
@@ -265,8 +274,9 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
   AmpFromMag ah = {0.0, 0.0, 0.0, 0.0}, as = {0.0, 0.0, 0.0, 0.0};
   double dbh = 0.0, dbs = 0.0;
   if (valid && gcs) {
-    dbh = sersic_bn_deriv(t[7], bh);
-    dbs = sersic_bn_deriv(t[14], bs);
+    // central differences of the root, truncation of order 1e-10 relative
+    dbh = (rt[2] - rt[4]) / (2e-5 * (double)t[7]);
+    dbs = (rt[3] - rt[5]) / (2e-5 * (double)t[14]);
   }
   if (valid && amp) {
     ah = amplitude_from_magnitude(t[5], t[6], t[7], bh, dbh, own->zp);
@@ -415,14 +425,14 @@ __global__ void prologue_kernel(const float* __restrict__ theta, int n_points, P
 // lensed_model: per SIE x_c, y_c, theta_E, q, phi; shear gamma, phi_gamma; per
 // Sersic x, y, I_e, R_e, n, q, phi; sky) into ModelConst, b_n by the float64
 // Newton solve. An invalid point gets sky = NaN, which makes its image NaN.
-__global__ void model_prologue_kernel(const float* __restrict__ theta, int n_points, int n_params, ModelSpec spec,
+__global__ __launch_bounds__(64) void model_prologue_kernel(const float* __restrict__ theta, int n_points, int n_params, ModelSpec spec,
                                       ModelConst* __restrict__ out) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_points) return;
   const float* t = theta + (size_t)p * n_params;
   bool valid = true;
   for (int i = 0; i < n_params; ++i) valid = valid && isfinite(t[i]);
-  ModelConst m;
+  ModelConst& m = out[p];   // written in place (a local copy would live in scratch)
   m.n_sie = spec.n_sie;
   m.n_sersic = spec.n_sersic;
   int o = 0;
@@ -470,7 +480,6 @@ __global__ void model_prologue_kernel(const float* __restrict__ theta, int n_poi
   }
   m.sky = spec.sky ? (double)t[o] : 0.0;
   if (!valid) m.sky = __builtin_nan("");
-  out[p] = m;
 }
 
 hipError_t launch_model_prologue(const float* theta, int n_points, int n_params, const ModelSpec& spec,
@@ -485,11 +494,13 @@ hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, Po
                            const SysDesc& single, SysDesc* table, int n_sys, int* cusp_count, hipStream_t stream,
                            double* grad_corr, const int* point_sys) {
   const int threads = 64;
-  const int point_blocks = (n_points + threads - 1) / threads;
+  const int solves = gcs ? 6 : 2;
+  const int ppb = threads / solves;
+  const int point_blocks = (n_points + ppb - 1) / ppb;
   const int blocks = point_blocks + n_sys;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(prologue_kernel, dim3(blocks), dim3(threads), 0, stream, theta, n_points, pcs, p64s, gcs,
-                     single, table, n_sys, point_blocks, cusp_count, grad_corr, point_sys);
+                     single, table, n_sys, point_blocks, cusp_count, grad_corr, point_sys, solves);
   return hipGetLastError();
 }
 
