@@ -101,12 +101,17 @@ __global__ __launch_bounds__(P >= 0 && TWc == 0 ? WIDE_MAX_THREADS : 512) void a
   }
 }
 
-// Border pixels of g with the folded tables; blockIdx.y is the point.
+// Border pixels of g with the folded tables; blockIdx.y is the point. Eight
+// lanes share a pixel: lane `sub` takes the table rows a = -p + sub, -p + sub + 8,
+// ..., and the eight partial sums are added in a fixed order by shuffles.
+constexpr int BORDER_LANES = 8;
+
 __global__ __launch_bounds__(64) void adj_border_kernel(WorkArgs w, const float* __restrict__ R, float* __restrict__ G,
                                                          int n_border, int point_base) {
   const int point = point_base + (int)blockIdx.y;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_border) return;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = (int)(gid / BORDER_LANES), sub = (int)(gid % BORDER_LANES);
+  if (t >= n_border) return;   // the eight lanes of a pixel leave together
   const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[point] : 0] : w.single;
   const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
   const int H = sd.H, W = sd.W;
@@ -131,7 +136,7 @@ __global__ __launch_bounds__(64) void adj_border_kernel(WorkArgs w, const float*
   const float* __restrict__ K = sd.adjk + (size_t)(cr * 4 + cc) * sd.ph * sd.pw;
   const float* __restrict__ Rp = R + loff;
   float acc = 0.0f;
-  for (int a = -p; a <= p; ++a) {
+  for (int a = -p + sub; a <= p; a += BORDER_LANES) {
     const int i = u + a;
     if (i < 0 || i >= H) continue;
     for (int b = -q; b <= q; ++b) {
@@ -140,7 +145,10 @@ __global__ __launch_bounds__(64) void adj_border_kernel(WorkArgs w, const float*
       acc = fmaf(K[(a + p) * sd.pw + (b + q)], Rp[(size_t)i * W + j], acc);
     }
   }
-  G[loff + (size_t)u * W + v] = acc;
+  acc += __shfl_xor(acc, 4, BORDER_LANES);
+  acc += __shfl_xor(acc, 2, BORDER_LANES);
+  acc += __shfl_xor(acc, 1, BORDER_LANES);
+  if (sub == 0) G[loff + (size_t)u * W + v] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -435,89 +443,120 @@ __global__ __launch_bounds__(RENDER_BLOCK) void grad_kernel(WorkArgs w, const Po
 constexpr int GCUSP_WAVES = 4;
 constexpr int GCUSP_BLOCKS = 1024;
 
+// The subsamples inside the radius are first found in float32 and queued per
+// wave in LDS, then each lane takes one queued subsample at a time, so the
+// float64 re-tracing and the two sets of partials run with every lane busy.
+constexpr int GCUSP_CHUNK = 16;   // subsamples per pass
+
+__device__ __forceinline__ void gcusp_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ PixelGeom gcusp_geom(const SysDesc& sd, int pix) {
+  const int r = pix / sd.W;
+  const int col = pix - r * sd.W;
+  PixelGeom geo;
+  geo.ux = (float)col - 0.5f * (float)(sd.W - 1);
+  geo.uy = (float)r - 0.5f * (float)(sd.H - 1);
+  geo.d = sd.d;
+  geo.cx = sd.cx;
+  geo.cy = sd.cy;
+  return geo;
+}
+
 __global__ __launch_bounds__(64 * GCUSP_WAVES) void grad_cusp_kernel(WorkArgs w, const PointConst* __restrict__ pcs,
                                                                      const PointConst64* __restrict__ p64s,
                                                                      const GradConst* __restrict__ gcs,
                                                                      const float* __restrict__ G, CuspList cl,
                                                                      double* __restrict__ corr) {
+  __shared__ unsigned short queue[GCUSP_WAVES][GCUSP_CHUNK * 64];   // lane | subsample << 6
   const int n = *cl.count;
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * GCUSP_WAVES + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wave = blockIdx.x * GCUSP_WAVES + wv;
+  unsigned short* __restrict__ qu = queue[wv];
   for (int i = wave; i < n; i += gridDim.x * GCUSP_WAVES) {
     const CuspEntry e = cl.entries[i];
+    const bool mine = (e.mask >> lane) & 1ull;
+    const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[e.point] : 0] : w.single;
+    const int64_t loff = w.point_loff ? w.point_loff[e.point] : 0;
+    const PointConst& c = pcs[e.point];
+    const GradConst& gc = gcs[e.point];
+    GradUniform U;
+    U.te = gc.theta[0];
+    U.q = gc.theta[1];
+    U.sq = sqrtf(U.q);
+    U.s = (1.0f - U.q) * (1.0f + U.q);
+    U.iqp = c.sie_mode == 0 ? 0.0f : 1.0f / c.qp;
+    float s2, c2;
+    sincosf(2.0f * gc.theta[4], &s2, &c2);
+    U.c2 = c2;
+    U.s2 = s2;
+    U.gam = gc.theta[3];
+    U.RH = gc.theta[6];
+    U.RS = gc.theta[13];
+    U.qH = gc.theta[8];
+    U.qS = gc.theta[15];
+    U.bH = c.hB * LN2F;
+    U.bS = c.sB * LN2F;
+    U.dbH = gc.dB_dn_h * LN2F;
+    U.dbS = gc.dB_dn_s * LN2F;
+    const PixelGeom geo = gcusp_geom(sd, e.pix0 + lane);
+    const int N = sd.N, NN = N * N;
+    const GkRule* Rg = sd.rule > 0 ? &kGkRules[sd.rule - 1] : nullptr;
     float acc[NPAR];
 #pragma unroll
     for (int k = 0; k < NPAR; ++k) acc[k] = 0.0f;
-    if ((e.mask >> lane) & 1ull) {
-      const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[e.point] : 0] : w.single;
-      const int64_t loff = w.point_loff ? w.point_loff[e.point] : 0;
-      const int pix = e.pix0 + lane;
-      const float gp = G[loff + pix];
-      const PointConst& c = pcs[e.point];
-      const GradConst& gc = gcs[e.point];
-      GradUniform U;
-      U.te = gc.theta[0];
-      U.q = gc.theta[1];
-      U.sq = sqrtf(U.q);
-      U.s = (1.0f - U.q) * (1.0f + U.q);
-      U.iqp = c.sie_mode == 0 ? 0.0f : 1.0f / c.qp;
-      float s2, c2;
-      sincosf(2.0f * gc.theta[4], &s2, &c2);
-      U.c2 = c2;
-      U.s2 = s2;
-      U.gam = gc.theta[3];
-      U.RH = gc.theta[6];
-      U.RS = gc.theta[13];
-      U.qH = gc.theta[8];
-      U.qS = gc.theta[15];
-      U.bH = c.hB * LN2F;
-      U.bS = c.sB * LN2F;
-      U.dbH = gc.dB_dn_h * LN2F;
-      U.dbS = gc.dB_dn_s * LN2F;
-      const int r = pix / sd.W;
-      const int col = pix - r * sd.W;
-      PixelGeom geo;
-      geo.ux = (float)col - 0.5f * (float)(sd.W - 1);
-      geo.uy = (float)r - 0.5f * (float)(sd.H - 1);
-      geo.d = sd.d;
-      geo.cx = sd.cx;
-      geo.cy = sd.cy;
-      const int N = sd.N;
-      const GkRule* Rg = sd.rule > 0 ? &kGkRules[sd.rule - 1] : nullptr;
-      float a64[NPAR], a32[NPAR];
-#pragma unroll
-      for (int k = 0; k < NPAR; ++k) a64[k] = a32[k] = 0.0f;
-      for (int ky = 0; ky < N; ++ky) {
+    for (int s0 = 0; s0 < NN; s0 += GCUSP_CHUNK) {
+      const int ns = min(GCUSP_CHUNK, NN - s0);
+      int qn = 0;
+      for (int j = 0; j < ns; ++j) {
+        const int ky = (s0 + j) / N, kx = s0 + j - ky * N;
         const float y = fmaf(geo.uy + (Rg ? Rg->x[ky] : sub_offset_rt(ky, N)), geo.d, geo.cy);
-        const double oy = Rg ? Rg->xd[ky] : ((double)ky + 0.5) / N - 0.5;
-        for (int kx = 0; kx < N; ++kx) {
-          const float x = fmaf(geo.ux + (Rg ? Rg->x[kx] : sub_offset_rt(kx, N)), geo.d, geo.cx);
-          const float sR2 = render_source_R2(c, x, y);
-          if (sR2 < c.cusp_r2) {
-            const double ox = Rg ? Rg->xd[kx] : ((double)kx + 0.5) / N - 0.5;
-            const float sw = Rg ? Rg->w[kx] * Rg->w[ky] : 1.0f;
-            float dx, dy;
-            source_offset_f64(p64s[e.point], geo, ox, oy, dx, dy);
-            switch (c.sie_mode) {
-              case 0:
-                subsample_grad<0, true>(c, U, x, y, a32, false, 0.0f, 0.0f, sw);
-                subsample_grad<0, true>(c, U, x, y, a64, true, dx, dy, sw);
-                break;
-              case 1:
-                subsample_grad<1, true>(c, U, x, y, a32, false, 0.0f, 0.0f, sw);
-                subsample_grad<1, true>(c, U, x, y, a64, true, dx, dy, sw);
-                break;
-              default:
-                subsample_grad<2, true>(c, U, x, y, a32, false, 0.0f, 0.0f, sw);
-                subsample_grad<2, true>(c, U, x, y, a64, true, dx, dy, sw);
-                break;
-            }
+        const float x = fmaf(geo.ux + (Rg ? Rg->x[kx] : sub_offset_rt(kx, N)), geo.d, geo.cx);
+        const bool within = mine && render_source_R2(c, x, y) < c.cusp_r2;
+        const unsigned long long b = __ballot(within);
+        if (within) qu[qn + __popcll(b & ((1ull << lane) - 1ull))] = (unsigned short)(lane | (j << 6));
+        qn += __popcll(b);
+      }
+      gcusp_lds_sync();
+      for (int q0 = 0; q0 < qn; q0 += 64) {
+        if (q0 + lane < qn) {
+          const int item = qu[q0 + lane];
+          const int pl = item & 63, j = item >> 6;
+          const int ky = (s0 + j) / N, kx = s0 + j - ky * N;
+          const PixelGeom gq = gcusp_geom(sd, e.pix0 + pl);
+          const float y = fmaf(gq.uy + (Rg ? Rg->x[ky] : sub_offset_rt(ky, N)), gq.d, gq.cy);
+          const float x = fmaf(gq.ux + (Rg ? Rg->x[kx] : sub_offset_rt(kx, N)), gq.d, gq.cx);
+          const double oy = Rg ? Rg->xd[ky] : ((double)ky + 0.5) / N - 0.5;
+          const double ox = Rg ? Rg->xd[kx] : ((double)kx + 0.5) / N - 0.5;
+          const float sw = Rg ? Rg->w[kx] * Rg->w[ky] : 1.0f;
+          float dx, dy;
+          source_offset_f64(p64s[e.point], gq, ox, oy, dx, dy);
+          float a64[NPAR], a32[NPAR];
+#pragma unroll
+          for (int k = 0; k < NPAR; ++k) a64[k] = a32[k] = 0.0f;
+          switch (c.sie_mode) {
+            case 0:
+              subsample_grad<0, true>(c, U, x, y, a32, false, 0.0f, 0.0f, sw);
+              subsample_grad<0, true>(c, U, x, y, a64, true, dx, dy, sw);
+              break;
+            case 1:
+              subsample_grad<1, true>(c, U, x, y, a32, false, 0.0f, 0.0f, sw);
+              subsample_grad<1, true>(c, U, x, y, a64, true, dx, dy, sw);
+              break;
+            default:
+              subsample_grad<2, true>(c, U, x, y, a32, false, 0.0f, 0.0f, sw);
+              subsample_grad<2, true>(c, U, x, y, a64, true, dx, dy, sw);
+              break;
           }
+          const float wg = (float)sd.wgt * G[loff + e.pix0 + pl];
+#pragma unroll
+          for (int k = 0; k < NPAR; ++k) acc[k] = fmaf(a64[k] - a32[k], wg, acc[k]);
         }
       }
-      const float wg = (float)sd.wgt * gp;
-#pragma unroll
-      for (int k = 0; k < NPAR; ++k) acc[k] = (a64[k] - a32[k]) * wg;
+      gcusp_lds_sync();
     }
     // every lane of an entry belongs to the same point
 #pragma unroll
@@ -618,7 +657,7 @@ hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n
   // one grid row per point, at most 65535 rows per launch
   for (int p0 = 0; p0 < n_points; p0 += 65535) {
     const int np = n_points - p0 < 65535 ? n_points - p0 : 65535;
-    hipLaunchKernelGGL(adj_border_kernel, dim3((nb + 63) / 64, np), dim3(64), 0, st, w, R, G, nb, p0);
+    hipLaunchKernelGGL(adj_border_kernel, dim3((unsigned)(((int64_t)nb * BORDER_LANES + 63) / 64), np), dim3(64), 0, st, w, R, G, nb, p0);
     const hipError_t le = hipGetLastError();
     if (le != hipSuccess) return le;
   }
