@@ -444,7 +444,8 @@ int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const 
     }
     if (c->autotune && !c->tiles.has_measured(systems, n_systems)) {
       // Autotuner: time the PSF + chi^2 stage of the model's best-ranked tile
-      // shapes on this very launch (stage by stage, second of two runs) and keep
+      // shapes on this very launch (stage by stage, fastest of three runs after a
+      // warm-up) and keep
       // the fastest for every later plan over the same set of system shapes.
       const std::vector<TileShape> cand = c->tiles.ranked(systems, n_systems, 6);
       TileShape best = cand.empty() ? TileShape{32, 32} : cand[0];
