@@ -55,11 +55,7 @@ struct PointConst {
   // is derived in float64 from a magnitude: they keep the float32 rounding of
   // the amplitude from scaling every pixel of a component the same way
   float hIlo, sIlo;
-  // the lens light's (R/R_e)^2 as a quadratic form in the image plane (the lens
-  // light is centred on the lens, at the origin): (hqA x + hqB y) x + hqC y^2,
-  // two FMAs per subsample once the row terms hqB y and hqC y^2 are known
-  float hqA, hqB, hqC;
-  float pad2[4];
+  float pad2[7];
 };
 static_assert(sizeof(PointConst) == 64 * 4, "PointConst layout");
 

@@ -344,9 +344,6 @@ __global__ __launch_bounds__(64) void prologue_kernel(const float* __restrict__ 
     c.h12 = (float)(a * sn);
     c.h21 = (float)(-b * sn);
     c.h22 = (float)(b * cs);
-    c.hqA = (float)(a * a * cs * cs + b * b * sn * sn);
-    c.hqB = (float)(2.0 * cs * sn * (a * a - b * b));
-    c.hqC = (float)(a * a * sn * sn + b * b * cs * cs);
   }
   {
     const double Re = t[13], qs = t[15], ph = t[16];
@@ -371,7 +368,7 @@ __global__ __launch_bounds__(64) void prologue_kernel(const float* __restrict__ 
   }
   c.hIlo = (float)(Ih - (double)c.hI);
   c.sIlo = (float)(Is - (double)c.sI);
-  for (int k = 0; k < 4; ++k) c.pad2[k] = 0.0f;
+  for (int k = 0; k < 7; ++k) c.pad2[k] = 0.0f;
   if (!valid) {
     const float nan = __builtin_nanf("");
     c.m11 = c.m12 = c.m22 = nan;

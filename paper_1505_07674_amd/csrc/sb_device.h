@@ -86,7 +86,7 @@ __device__ __forceinline__ void source_offset_f64(const PointConst64& e, const P
 
 // ---------------------------------------------------------------------------
 // Forward render, float32, with the folded constants of PointConst (rmode,
-// tac, hqA..hqC, s11..s22, A1..cYh). Every product and sum is written out
+// tac, h11..h22, s11..s22, A1..cYh). Every product and sum is written out
 // with explicit fmaf so that the render kernel and the cusp correction, which
 // must reproduce the render's float32 value of a subsample, round identically.
 // ---------------------------------------------------------------------------
@@ -99,7 +99,7 @@ struct RowTerms {
   float sLy, cLy;     // SIE frame: x' = cL x + sL y, y' = cL y - sL x
   float rX, rY;       // B1 y + C1, B2 y + C2: row part of the source frame of beta
   float s12y, s22y;   // sphere: s12 y, s22 y
-  float hb, hc;       // lens light: hqB y, hqC y^2
+  float hx, hy;       // lens-light frame: h12 y, h22 y
 };
 
 __device__ __forceinline__ RowTerms row_terms(const PointConst& c, float y) {
@@ -112,8 +112,8 @@ __device__ __forceinline__ RowTerms row_terms(const PointConst& c, float y) {
   r.rY = fmaf(c.B2, y, c.C2);
   r.s12y = c.s12 * y;
   r.s22y = c.s22 * y;
-  r.hb = c.hqB * y;
-  r.hc = (c.hqC * y) * y;
+  r.hx = c.h12 * y;
+  r.hy = c.h22 * y;
   return r;
 }
 
@@ -177,7 +177,9 @@ __device__ __forceinline__ float sersic_shape(float R2, float e, float B) {
 template <int RM>
 __device__ __forceinline__ void subsample_light(const PointConst& c, const RowTerms& r, float x, float& h, float& s,
                                                 bool& cusp) {
-  h = sersic_shape(fmaf(fmaf(c.hqA, x, r.hb), x, r.hc), c.he, c.hB);
+  const float X = fmaf(c.h11, x, r.hx);
+  const float Y = fmaf(c.h21, x, r.hy);
+  h = sersic_shape(fmaf(X, X, Y * Y), c.he, c.hB);
   float sX, sY;
   source_frame<RM>(c, r, x, sX, sY);
   const float sR2 = fmaf(sX, sX, sY * sY);
