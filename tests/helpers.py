@@ -1,6 +1,8 @@
 """Shared helpers for the parity tests: build the same seeded observation for the
 oracle (float64 copies of float32 arrays) and for the GPU library."""
 import functools
+import importlib.util
+import os
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -44,3 +46,21 @@ def loglike_tolerance(ll_ref, weight):
     """|delta log L| bound: 1e-6 relative, floored at the expected |log L| at the truth (N_w / 2)."""
     nw = int(np.count_nonzero(weight))
     return 1e-6 * np.maximum(np.abs(ll_ref), nw / 2.0)
+
+
+def _load_golden_module():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_golden.py")
+    spec = importlib.util.spec_from_file_location("make_golden", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+# the script that wrote the stored oracle values: its point generators and digests
+golden = _load_golden_module()
+
+
+def golden_file(path):
+    """Arrays of a stored-values file (no pickles)."""
+    with np.load(path, allow_pickle=False) as f:
+        return {k: f[k] for k in f.files}

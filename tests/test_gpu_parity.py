@@ -3,10 +3,13 @@
 Bars (per point): on the model image L* (after the PSF) max |delta| <= 1e-5 x
 peak |oracle pixel|, and |delta log L| <= 1e-6 x max(|log L_oracle|, N_w/2)
 where N_w counts weighted pixels (the expected |log L| at the truth; avoids 0/0
-for noiseless data). The unconvolved intermediate L is held to 3e-5 x peak: at
-the cusp of an n ~ 4 source the float32 rounding of the ray position (~1e-7
-arcsec) alone moves single pixels by ~1e-5 of the peak before the PSF averages
-it out.
+for noiseless data). The unconvolved image L (render with apply_psf = 0) is
+held to the same 1e-5 x peak bar as L*.
+
+The full-size batches (all 4096 points of the 200x200 batch, all 8192 points of
+the 16-system mixed batch) are compared point by point with oracle values
+stored under tests/golden/ by tests/golden/make_golden.py, which calls only the
+oracle; the stored input digests prove that the test rebuilt the same inputs.
 """
 import math
 
@@ -18,7 +21,7 @@ import oracle
 import paper_1505_07674_amd as lensed
 from paper_1505_07674_amd import mocks
 
-from helpers import f32, loglike_tolerance, observation, oracle_loglikes, oracle_system
+from helpers import f32, golden, golden_file, loglike_tolerance, observation, oracle_loglikes, oracle_system
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -36,18 +39,19 @@ def gpu_system(spec, obs=None):
                          center=(spec.center_x, spec.center_y))
 
 
-def check_images(spec, thetas, apply_psf, tol=None):
-    tol = (1e-5 if apply_psf else 3e-5) if tol is None else tol
+def check_images(spec, thetas, apply_psf, tol=1e-5):
     gsys = gpu_system(spec)
     osys = oracle_system(spec)
-    worst = 0.0
+    errs = []
     for t in thetas:
         img = lensed.render(torch.from_numpy(t).to(DEV), gsys, apply_psf=apply_psf).cpu().numpy().astype(np.float64)
         ref = oracle.render(osys, t.astype(np.float64), apply_psf=apply_psf)
-        err = np.max(np.abs(img - ref)) / np.max(np.abs(ref))
-        worst = max(worst, err)
-        assert err <= tol, f"pixel error {err:.3e} x peak at theta={t.tolist()}"
-    return worst
+        errs.append(np.max(np.abs(img - ref)) / np.max(np.abs(ref)))
+    errs = np.array(errs)
+    say(f"  {spec.name} apply_psf={apply_psf}: worst pixel error {errs.max():.3e} x peak")
+    worst = int(np.argmax(errs))
+    assert errs.max() <= tol, f"pixel error {errs.max():.3e} x peak at theta={thetas[worst].tolist()}"
+    return errs.max()
 
 
 def test_c0_render_parity():
@@ -88,25 +92,28 @@ def test_c0_plain_matches_batch_and_oracle():
 def test_c1_render_parity():
     spec, _ = observation("c1")
     say("c1 render parity")
-    pts = np.concatenate([spec.truth[None, :], mocks.points(spec, 5, seed=mocks.C1_POINT_SEED)])
+    pts = np.concatenate([spec.truth[None, :], mocks.points(spec, 11, seed=mocks.C1_POINT_SEED)])
     check_images(spec, pts, True)
-    check_images(spec, pts[:2], False)
+    check_images(spec, pts, False)
 
 
-def test_c1_loglike_batch_parity_full_launch():
-    """The 4096-point batch the benchmark times; the oracle checks a spread sample."""
+def test_c1_loglike_batch_parity_every_point():
+    """The 4096-point batch the benchmark times, every point against the oracle."""
     spec, obs = observation("c1")
-    say("c1 loglike batch, 4096 points")
-    pts = mocks.points(spec, 4096, seed=mocks.C1_POINT_SEED)
-    pts[0] = spec.truth
+    say("c1 loglike batch, 4096 points, all compared")
+    pts = golden.c1_points(spec)
+    gold = golden_file(golden.C1_FILE)
+    assert str(gold["theta_sha256"]) == golden.digest(pts), "C1 points differ from those of the stored values"
+    assert str(gold["data_sha256"]) == golden.digest(obs.data), "C1 mock differs from the stored one"
+    assert str(gold["weight_sha256"]) == golden.digest(obs.weight)
+    ref = gold["loglike"]
     gsys = gpu_system(spec, obs)
-    ll = lensed.loglike_batch(torch.from_numpy(pts).to(DEV), np.zeros(4096, np.int32), [gsys]).cpu().numpy()
-    assert np.all(np.isfinite(ll))
-    idx = np.unique(np.concatenate([[0, 1, 4095], np.linspace(2, 4094, 29).astype(int)]))
-    ref = oracle_loglikes(oracle_system(spec, obs), pts[idx])
+    ll = lensed.loglike_batch(torch.from_numpy(pts).to(DEV), np.zeros(len(pts), np.int32), [gsys]).cpu().numpy()
     tol = loglike_tolerance(ref, obs.weight)
-    err = np.abs(ll[idx] - ref)
-    assert np.all(err <= tol), f"worst relative {np.max(err / tol) * 1e-6:.3e}"
+    ratio = np.abs(ll - ref) / tol
+    say(f"  worst |delta log L| / bar = {ratio.max():.3f} at point {int(np.argmax(ratio))}")
+    bad = np.nonzero(~(ratio <= 1.0))[0]
+    assert bad.size == 0, f"{bad.size} of {len(pts)} points off, e.g. {bad[:5].tolist()}"
 
 
 def test_profiled_stages_give_the_graph_result():
@@ -182,25 +189,35 @@ def test_ragged_and_generic_shapes(H, W, N, ph, pw):
     assert abs(plain - ref[0]) <= loglike_tolerance(ref[:1], obs.weight)[0]
 
 
-def test_mixed_batch_c2_sampled():
-    """16 systems of mixed size and subsampling, 512 points each, one graph launch."""
+def test_mixed_batch_c2_every_point():
+    """16 systems of mixed size and subsampling, 512 points each, one graph launch;
+    every one of the 8192 log L against the oracle."""
     specs = mocks.c2_specs()
-    say("c2 mixed batch, 16 systems x 512 points")
+    say("c2 mixed batch, 16 systems x 512 points, all compared")
+    gold = golden_file(golden.C2_FILE)
     systems, obs_all, pts_all, sop = [], [], [], []
     for s, spec in enumerate(specs):
         _, obs = observation("c2", s)
+        pts = golden.c2_points(spec, s)
+        assert str(gold["theta_sha256"][s]) == golden.digest(pts), f"C2 system {s}: points differ"
+        assert str(gold["data_sha256"][s]) == golden.digest(obs.data), f"C2 system {s}: mock differs"
+        assert str(gold["weight_sha256"][s]) == golden.digest(obs.weight)
         obs_all.append(obs)
         systems.append(gpu_system(spec, obs))
-        pts_all.append(mocks.points(spec, 512, seed=mocks.C2_BASE_SEED * 100 + s))
-        sop.append(np.full(512, s, np.int32))
+        pts_all.append(pts)
+        sop.append(np.full(len(pts), s, np.int32))
     pts = np.concatenate(pts_all)
     sop = np.concatenate(sop)
     ll = lensed.loglike_batch(torch.from_numpy(pts).to(DEV), sop, systems).cpu().numpy()
-    assert np.all(np.isfinite(ll))
+    worst = 0.0
     for s, spec in enumerate(specs):
-        idx = [s * 512, s * 512 + 511]
-        ref = oracle_loglikes(oracle_system(spec, obs_all[s]), pts[idx])
-        assert np.all(np.abs(ll[idx] - ref) <= loglike_tolerance(ref, obs_all[s].weight)), spec.name
+        sl = slice(s * 512, (s + 1) * 512)
+        ref = gold["loglike"][s]
+        ratio = np.abs(ll[sl] - ref) / loglike_tolerance(ref, obs_all[s].weight)
+        worst = max(worst, float(ratio.max()))
+        bad = np.nonzero(~(ratio <= 1.0))[0]
+        assert bad.size == 0, f"{spec.name}: {bad.size} of 512 points off (worst {ratio.max():.3f} x bar)"
+    say(f"  worst |delta log L| / bar = {worst:.3f}")
 
 
 def test_invalid_points_give_nan_only_there():

@@ -59,11 +59,12 @@ def test_gauss_kronrod_images_match_the_oracle(rule):
     spec = spec_for()
     g, o = gsys(spec, rule), osys(spec, rule)
     for t in points(spec, 4, seed=61):
-        for psf, tol in ((False, 3e-5), (True, 1e-5)):
+        for psf in (False, True):
             img = lensed.render(torch.from_numpy(t).to(DEV), g, apply_psf=psf).cpu().numpy().astype(np.float64)
             ref = oracle.render(o, t.astype(np.float64), apply_psf=psf)
             err = np.max(np.abs(img - ref)) / np.max(np.abs(ref))
-            assert err <= tol, (rule, psf, err, t.tolist())
+            say(f"  apply_psf={psf}: pixel error {err:.3e} x peak")
+            assert err <= 1e-5, (rule, psf, err, t.tolist())
 
 
 @pytest.mark.parametrize("rule", RULES)
@@ -98,7 +99,10 @@ def test_gauss_kronrod_error_estimate(rule):
         ref = oracle.render_error(o, t.astype(np.float64))
         peak = np.max(np.abs(oracle.render(o, t.astype(np.float64), apply_psf=False)))
         assert np.all(est >= 0)
-        assert np.max(np.abs(est - ref)) <= 3e-5 * peak, (rule, np.max(np.abs(est - ref)) / peak)
+        # ||K - G| - |K_o - G_o|| <= |K - K_o| + |G - G_o|: two rule sums, each held to 1e-5 x peak
+        err = np.max(np.abs(est - ref)) / peak
+        say(f"  error map: {err:.3e} x peak")
+        assert err <= 2e-5, (rule, err)
 
 
 @pytest.mark.parametrize("rule", RULES)

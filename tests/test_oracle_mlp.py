@@ -1,6 +1,8 @@
-"""Pins of the FP64 reference network (oracle/mlp.py): gradient against central
-differences, SiLU derivative, bfloat16 rounding against torch's conversion, and
-the Adam update against its closed-form first step and a convex problem."""
+"""Pins of the FP64 reference network (oracle/mlp.py): the forward pass and the
+loss gradient against torch's own float64 layers (torch.nn.functional.linear
+and silu, autograd), gradient against central differences, SiLU derivative,
+bfloat16 rounding against torch's conversion, and the Adam update against its
+closed-form first step and a convex problem."""
 import numpy as np
 import pytest
 import torch
@@ -66,3 +68,43 @@ def test_adam_first_step_and_convergence():
     for t in range(1, 3001):
         th, m, v = mlp.adam_step(th, th - target, m, v, t, lr=0.01)
     assert np.max(np.abs(th - target)) < 1e-3
+
+
+def _torch_net(theta, norm):
+    """The same network from torch's float64 layers: linear, silu, linear, silu,
+    linear, silu, linear, with the input and output normalisation."""
+    Ws, bs = mlp.unflatten(theta)
+    P = [torch.tensor(a, dtype=torch.float64, requires_grad=True) for pair in zip(Ws, bs) for a in pair]
+    nt = torch.tensor(norm, dtype=torch.float64)
+    F = torch.nn.functional
+
+    def net(x):
+        h = (torch.as_tensor(x, dtype=torch.float64) - nt[:17]) * nt[17:34]
+        for l in range(3):
+            h = F.silu(F.linear(h, P[2 * l], P[2 * l + 1]))
+        return F.linear(h, P[6], P[7])[:, 0]
+    return net, P, nt
+
+
+def test_forward_matches_torch_layers():
+    theta, norm, x, _ = _problem(B=200)
+    theta = theta + 0.3 * RNG.standard_normal(theta.size)       # non-zero biases too
+    net, _, nt = _torch_net(theta, norm)
+    ref = (nt[34] + nt[35] * net(x)).detach().numpy()
+    out = mlp.forward(theta, norm, x, emulate_bf16=False)
+    assert np.allclose(out, ref, rtol=1e-12, atol=1e-12 * np.max(np.abs(ref)))
+    # a dropped bias, a transposed weight or a missing activation would not match
+    assert np.max(np.abs(out - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+def test_loss_gradient_matches_torch_autograd():
+    theta, norm, x, y = _problem(B=96)
+    theta = theta + 0.1 * RNG.standard_normal(theta.size)
+    net, P, nt = _torch_net(theta, norm)
+    t = (torch.tensor(y, dtype=torch.float64) - nt[34]) / nt[35]
+    loss_t = torch.mean((net(x) - t) ** 2)
+    loss_t.backward()
+    gref = np.concatenate([p.grad.numpy().reshape(-1) for p in P])
+    loss, g = mlp.loss_and_grad(theta, norm, x, y, emulate_bf16=False)
+    assert loss == pytest.approx(loss_t.item(), rel=1e-12)
+    assert np.allclose(g, gref, rtol=1e-9, atol=1e-12 * np.max(np.abs(gref)))
