@@ -2,8 +2,8 @@
 
 The paper samples its posterior with nested sampling (Skilling 2004, 2006) via
 the MultiNest library (Sec. 3.2), which needs only log P(d|xi) and returns the
-posterior (Eq. 12) and the evidence (Eq. 13). This module is a plain
-single-ellipsoid nested sampler that calls the batched GPU likelihood:
+posterior (Eq. 12) and the evidence (Eq. 13). This module is a nested sampler
+that calls the batched GPU likelihood:
 
 * live points are uniform in the unit cube, mapped to parameters by the prior
   transform (independent uniform priors);
@@ -12,9 +12,12 @@ single-ellipsoid nested sampler that calls the batched GPU likelihood:
 * replacements are drawn uniformly inside the bounding ellipsoids of the live
   points (a union found by recursive 2-means splits, as MultiNest does, each
   enlarged by a volume factor, clipped to the cube) and accepted in draw order
-  when their exact log L exceeds the threshold of the removed points;
+  when their exact log L exceeds the threshold of the removed points, or come
+  from slice-sampling chains (Neal 2003) started at surviving live points, as
+  PolyChord does, whichever costs fewer exact evaluations per replacement;
 * an optional screen (a trained surrogate) may discard candidates before the
-  exact evaluation; every accepted point is evaluated exactly;
+  exact evaluation; every accepted point, and every point a slice chain moves
+  to, is evaluated exactly;
 * the run stops when the live points can no longer change log Z by more than
   `dlogz`; the evidence error is sqrt(H / n_live) (Skilling 2006).
 """
@@ -179,11 +182,15 @@ class Screen:
     """Pre-screen of candidates: predict(u) returns a log L estimate; a candidate
     is discarded when the estimate is below threshold - margin(threshold).
 
-    A slice chain also takes a proposal as inside without an exact render when
-    the estimate clears threshold + margin_in(threshold) (margin(threshold) when
-    the screen has no margin_in). Only the discards can bias the run: a chain's
-    final point is always evaluated exactly, so a smaller margin_in trades
-    fewer renders along the chains against more final points that fail."""
+    A slice chain uses the screen in two ways. While it steps its interval out,
+    a proposal whose estimate clears threshold + margin_in(threshold)
+    (margin(threshold) when the screen has no margin_in) counts as inside
+    without an exact render: the interval is then built from a fixed,
+    deterministic set, which leaves slice sampling's uniform target intact. A
+    chain only ever moves to a proposal rendered exactly above the threshold;
+    there the screen may only discard. So the screen's false discards are the
+    one way it can bias a run, in slice and rejection mode alike: both then
+    sample the contour minus the discarded region."""
     predict: Callable[[np.ndarray], np.ndarray]
     margin: Callable[[float], float]
     max_skips: int = 2000           # consecutive discards before an exact fallback batch
@@ -202,7 +209,7 @@ class NSResult:
     n_screened_out: int = 0
     n_audit: int = 0                # screened-out draws evaluated exactly to check the screen
     n_false_reject: int = 0         # of those, how many had log L above the threshold
-    n_trusted: int = 0              # slice proposals the screen classified as inside (no exact render)
+    n_trusted: int = 0              # step-out proposals the screen classified as inside (no exact render)
     n_false_accept: int = 0         # audited trusted proposals whose exact log L was below the threshold
     n_fallback: int = 0             # slice chains rerun without the screen
     history: List[tuple] = field(default_factory=list)   # (n_exact, n_accepted) per iteration
@@ -228,7 +235,7 @@ class NestedSampler:
                  candidates_per_call: int = 256, record: bool = False, audit: float = 0.0, audit_seed: int = 0,
                  multi: bool = True, record_per_iter: Optional[int] = None,
                  audit_loglike: Optional[LogLikeFn] = None, method: str = "auto", n_steps: Optional[int] = None,
-                 slice_switch: Optional[float] = None, probe_every: int = 20, max_extend: int = 8):
+                 slice_switch: Optional[float] = None, probe_every: int = 20):
         if not (1 <= k_replace < n_live):
             raise ValueError("need 1 <= k_replace < n_live")
         self.loglike = loglike
@@ -261,9 +268,6 @@ class NestedSampler:
         # budget of twice this guess of the slice cost (renders per replacement)
         self.slice_cost_guess = 1.0 / slice_switch if slice_switch is not None else 5.0 * self.n_steps
         self.probe_every = probe_every
-        # a slice chain whose final point fails its exact check takes up to this
-        # many extra slices before it is rerun without the screen
-        self.max_extend = max_extend
         # multi: bound the live points by a union of ellipsoids (else one ellipsoid)
         self.multi = multi
         self.split_rng = np.random.default_rng(seed + 1)
@@ -432,10 +436,11 @@ class NestedSampler:
                     new_l.append(logl[i])
         return np.array(new_u).reshape(-1, self.ndim), np.array(new_l)
 
-    def _classify(self, c: np.ndarray, lmin: float, screen: Optional[Screen]):
+    def _classify(self, c: np.ndarray, lmin: float, screen: Optional[Screen], trust_in: np.ndarray):
         """Inside-the-contour flags for proposals c (points outside the cube are
-        outside): by the screen where its prediction clears L_min by the margin,
-        exactly otherwise. Returns (inside, exact log L or nan)."""
+        outside): by the screen where its prediction falls below L_min by the
+        margin, or (where trust_in is set) clears it by the inside margin; exactly
+        otherwise. Returns (inside, exact log L or nan)."""
         st = self.state
         inside = np.zeros(len(c), dtype=bool)
         logl = np.full(len(c), np.nan)
@@ -445,7 +450,7 @@ class NestedSampler:
             pred = np.asarray(screen.predict(c[todo]))
             dm = screen.margin(lmin)
             dm_in = screen.margin_in(lmin) if hasattr(screen, "margin_in") else dm
-            sure_in, sure_out = pred > lmin + dm_in, pred < lmin - dm
+            sure_in, sure_out = (pred > lmin + dm_in) & trust_in[todo], pred < lmin - dm
             inside[todo[sure_in]] = True
             st["n_screened"] += int(sure_out.sum())
             st["n_trusted"] = st.get("n_trusted", 0) + int(sure_in.sum())
@@ -467,12 +472,12 @@ class NestedSampler:
         one chain per replacement from a random surviving live point, along random
         directions whitened by the live points' covariance (as PolyChord does),
         n_steps slices per chain, all chains advanced in lock-step so that every
-        round is one batched evaluation. With a screen, proposals whose predicted
-        log L clears the threshold by the margin are classified without an exact
-        render. Every final point is evaluated exactly; a chain whose final point
-        fails takes one more slice and is checked again (at most max_extend
-        times), and a chain that still fails, or whose slice shrinks to nothing,
-        is rerun without the screen."""
+        round is one batched evaluation. With a screen, step-out proposals whose
+        predicted log L clears the threshold by the margin count as inside without
+        an exact render, and any proposal predicted below it by the margin counts
+        as outside; a chain moves only to a proposal whose exact log L exceeds the
+        threshold, so every point of a chain is exactly inside. A chain whose slice
+        shrinks to nothing is rerun without the screen."""
         st = self.state
         live = st["live_u"]
         keep = np.nonzero(st["live_logl"] > lmin)[0]
@@ -502,26 +507,8 @@ class NestedSampler:
             phase[pending] = 0
             nout = np.zeros(B, dtype=int)
             nshrink = np.zeros(B, dtype=int)
-            nextend = np.zeros(B, dtype=int)
             failed = np.zeros(B, dtype=bool)
-            check = np.zeros(B, dtype=bool)          # finished, final point only screened
             while True:
-                chk = np.nonzero(check)[0]
-                if len(chk):
-                    # exact check of final points the screen took as inside
-                    check[chk] = False
-                    xl[chk] = self._exact(x[chk])
-                    for i in chk[~(xl[chk] > lmin)]:
-                        nextend[i] += 1
-                        if nextend[i] > self.max_extend:
-                            failed[i] = True
-                            continue
-                        xl[i] = np.nan               # x lies outside: take one more slice from it
-                        steps[i] = self.n_steps - 1
-                        v[i] = new_dir(np.array([i]))[0]
-                        lo[i] = -self.rng.random()
-                        hi[i] = lo[i] + 1.0
-                        phase[i], nout[i], nshrink[i] = 0, 0, 0
                 act = np.nonzero(phase < 3)[0]
                 if len(act) == 0:
                     break
@@ -529,7 +516,8 @@ class NestedSampler:
                 sh = phase[act] == 2
                 t[sh] = lo[act][sh] + self.rng.random(int(sh.sum())) * (hi[act][sh] - lo[act][sh])
                 prop = x[act] + t[:, None] * v[act]
-                inside, pl = self._classify(prop, lmin, use_screen)
+                # a move (shrinkage phase) needs the exact log L; stepping out may trust the screen
+                inside, pl = self._classify(prop, lmin, use_screen, trust_in=~sh)
                 for j, i in enumerate(act):
                     if phase[i] == 0:
                         if inside[j] and nout[i] < 20:
@@ -549,7 +537,6 @@ class NestedSampler:
                             steps[i] += 1
                             if steps[i] >= self.n_steps:
                                 phase[i] = 3
-                                check[i] = bool(np.isnan(xl[i]))
                             else:
                                 v[i] = new_dir(np.array([i]))[0]
                                 lo[i] = -self.rng.random()
