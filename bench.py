@@ -26,7 +26,25 @@ if ROOT not in sys.path:
 # function counted as one op): 84 per subsample of the model, 2 per PSF tap and
 # 5 per pixel for the chi^2.
 OPS_PER_SUBSAMPLE = 84
+# The gradient kernel's per-subsample work, counted the same way: the value and
+# its 17 closed-form partial derivatives through both Sersics, the source frame,
+# the lens equation, the SIE (q' > 1/2 branch) and the shear, and their
+# accumulation (per-point constants not counted).
+GRAD_OPS_PER_SUBSAMPLE = 211
 FP32_PEAK_TFLOPS = 157.3
+
+
+def box_any(mask, p, q):
+    """Pixels within the (2p+1) x (2q+1) box of a True pixel of mask (clipped to the image)."""
+    H, W = mask.shape
+    c = np.zeros((H + 1, W + 1), np.int64)
+    c[1:, 1:] = np.cumsum(np.cumsum(mask.astype(np.int64), 0), 1)
+    r0 = np.clip(np.arange(H) - p, 0, H)
+    r1 = np.clip(np.arange(H) + p + 1, 0, H)
+    c0 = np.clip(np.arange(W) - q, 0, W)
+    c1 = np.clip(np.arange(W) + q + 1, 0, W)
+    tot = c[r1][:, c1] - c[r0][:, c1] - c[r1][:, c0] + c[r0][:, c0]
+    return tot > 0
 
 
 def parse():
@@ -39,6 +57,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-points-per-core", type=int, default=10)
     ap.add_argument("--no-mixed", action="store_true", help="skip the 16-system mixed batch line")
+    ap.add_argument("--no-next", action="store_true", help="skip the g3k7 and general-model lines")
     ap.add_argument("--grad-points", type=int, default=1024)
     ap.add_argument("--grad-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -145,6 +164,7 @@ def mixed_batch(lensed, mocks, dev, stream, c1_ms_per_subsample, steps=5):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    schedule = ctx.batch_schedule()
     ctx.set_profiling(True)
     ctx.stage_times()
     lensed.loglike_batch(th, sop, systems, out=out, ctx=ctx)
@@ -156,7 +176,83 @@ def mixed_batch(lensed, mocks, dev, stream, c1_ms_per_subsample, steps=5):
             "subsamples_per_launch": subs, "subsample_evals_per_s": subs / (ms / 1e3),
             "render_ms": stages["render"] / calls, "psf_chi2_ms": stages["psf_chi2"] / calls,
             "render_time_per_subsample_vs_uniform": (stages["render"] / calls) / subs / c1_ms_per_subsample,
-            "shapes": [f"{sp.height}x{sp.width} N={sp.nsub}" for sp in specs]}
+            "shapes": [f"{sp.height}x{sp.width} N={sp.nsub}" for sp in specs], "schedule": schedule}
+
+
+# Work per subsample of the 41-parameter general model (two SIEs, shear, four
+# Sersics), counted as above: 28 per SIE, 8 for the shear, 2 for beta, 21 per
+# Sersic, 2 for the coordinates and 2 to accumulate.
+GENERAL41_OPS_PER_SUBSAMPLE = 2 * 28 + 8 + 2 + 4 * 21 + 2 + 2
+FP64_PEAK_TFLOPS = 78.6
+
+
+def next_rows(lensed, mocks, dev, stream, spec, obs, steps=3):
+    """Throughput of two extensions on the 200x200 grid: the paper's default
+    Gauss-Kronrod rule g3k7 (49 nodes per pixel, float32 like the midpoint
+    path) and the 41-parameter general model (float64 render)."""
+    import torch
+    out = {}
+    psf = torch.from_numpy(spec.psf).to(dev)
+    data, weight = torch.from_numpy(obs.data).to(dev), torch.from_numpy(obs.weight).to(dev)
+
+    def timed(call, n_points, ctx):
+        call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            call()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        ctx.set_profiling(True)
+        ctx.stage_times()
+        call()
+        st, calls = ctx.stage_times()
+        ctx.set_profiling(False)
+        return ms, {k: v / calls for k, v in st.items()}
+
+    # g3k7 on the C1 batch
+    P = 1024
+    ctx = lensed.Context(0)
+    gk = lensed.System(psf, data, weight, pixscale=spec.pixscale, nsub=spec.nsub, rule="g3k7")
+    th = torch.from_numpy(mocks.points(spec, P, seed=mocks.C1_POINT_SEED)).to(dev)
+    sop = np.zeros(P, np.int32)
+    res = torch.empty(P, dtype=torch.float64, device=dev)
+    log(f"g3k7: {P} points")
+    ms, st = timed(lambda: lensed.loglike_batch(th, sop, [gk], out=res, ctx=ctx), P, ctx)
+    assert torch.isfinite(res).all().item()
+    subs = spec.height * spec.width * 49 * P
+    ach = OPS_PER_SUBSAMPLE * subs / (st["render"] * 1e-3) / 1e12
+    out["g3k7"] = {"value": P / (ms / 1e3), "unit": "evals/s", "points": P, "nodes_per_pixel": 49,
+                   "stage_ms_per_step": st,
+                   "roofline": {"bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                "frac": ach / FP32_PEAK_TFLOPS, "kernel": "render",
+                                "ops_per_subsample": OPS_PER_SUBSAMPLE, "subsamples_per_launch": subs}}
+    ctx.close()
+
+    # the 41-parameter general model (two SIEs, shear, four Sersics, sky), float64 render
+    P = 256
+    ctx = lensed.Context(0)
+    model = lensed.Model(2, mocks.GENERAL_41_PLANES, shear=True, sky=True)
+    gs = lensed.System(psf, data, weight, pixscale=spec.pixscale, nsub=spec.nsub)
+    th = torch.from_numpy(mocks.general_model_points(P, seed=41)).to(dev)
+    sop = np.zeros(P, np.int32)
+    res = torch.empty(P, dtype=torch.float64, device=dev)
+    log(f"general model (41 parameters): {P} points")
+    ms, st = timed(lambda: lensed.loglike_model_batch(th, sop, [gs], model, out=res, ctx=ctx), P, ctx)
+    assert torch.isfinite(res).all().item()
+    subs = spec.height * spec.width * spec.nsub ** 2 * P
+    ach = GENERAL41_OPS_PER_SUBSAMPLE * subs / (st["render"] * 1e-3) / 1e12
+    out["general_model_41"] = {"value": P / (ms / 1e3), "unit": "evals/s", "points": P, "params": 41,
+                               "stage_ms_per_step": st,
+                               "roofline": {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+                                            "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+                                            "kernel": "model_render (float64)",
+                                            "ops_per_subsample": GENERAL41_OPS_PER_SUBSAMPLE,
+                                            "subsamples_per_launch": subs}}
+    ctx.close()
+    return out
 
 
 def main():
@@ -215,6 +311,9 @@ def main():
     ms_step = ms_total / args.steps
     value = P * args.steps / (ms_total / 1e3)
     assert torch.isfinite(out).all().item(), "non-finite log L in the timed batch"
+    schedule = ctx.batch_schedule()
+    rendered = ctx.batch_rendered()
+    assert rendered["subsamples"] == spec.height * spec.width * spec.nsub ** 2 * P
 
     # per-stage kernel durations over an equal number of profiled steps
     log("batched: per-stage hipEvent timing")
@@ -270,6 +369,40 @@ def main():
     torch.cuda.synchronize()
     grad_value = G * args.grad_steps / (g0.elapsed_time(g1) / 1e3)
     assert torch.isfinite(gg).all().item()
+    # the gradient kernel alone: stage events over profiled passes of the same launch
+    ctx.set_profiling(True)
+    ctx.stage_times()
+    for _ in range(args.grad_steps):
+        lensed.loglike_grad(gpts, gsys, ctx=ctx)
+    gstages, gcalls = ctx.stage_times()
+    ctx.set_profiling(False)
+    grad_stage_ms = {k: v / gcalls for k, v in gstages.items()}
+    # it evaluates only pixels that A^T rho reaches: the w > 0 support dilated by the PSF box
+    ph, pw = spec.psf.shape
+    vis_px = int(box_any(obs.weight > 0, ph // 2, pw // 2).sum())
+    grad_subs = vis_px * spec.nsub ** 2 * G
+    grad_achieved = GRAD_OPS_PER_SUBSAMPLE * grad_subs / (grad_stage_ms["grad"] * 1e-3) / 1e12
+
+    # masked form: only the pixels the chi^2 can see (same log L, bit for bit)
+    log("masked: same batch, visible pixels only")
+    out_m = torch.empty_like(out)
+    lensed.loglike_batch(theta, sop, [gsys], out=out_m, ctx=ctx, masked=True)
+    torch.cuda.synchronize()
+    vis = ctx.batch_rendered()
+    m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    m0.record(stream)
+    for _ in range(args.steps):
+        lensed.loglike_batch(theta, sop, [gsys], out=out_m, ctx=ctx, masked=True)
+    m1.record(stream)
+    torch.cuda.synchronize()
+    masked_ms = m0.elapsed_time(m1) / args.steps
+    assert torch.equal(out_m, out), "masked and all-pixel log L differ"
+    masked = {"value": P / (masked_ms / 1e3), "unit": "evals/s", "points": P, "ms_per_step": masked_ms,
+              "rendered_pixel_fraction": vis["pixels"] / rendered["pixels"],
+              "form": "only the pixels within the PSF footprint of w > 0 rendered, only PSF tiles with w > 0 "
+                      "convolved; log L identical bit for bit to the all-pixel batch"}
+
+    extensions = None if args.no_next else next_rows(lensed, mocks, dev, stream, spec, obs)
 
     mixed = None
     if not args.no_mixed:
@@ -298,14 +431,23 @@ def main():
                             "form": "one point per call, host sync after each (not used for the ratio)"},
         "batched_over_plain": value / plain_value,
         "adjoint": {"value": grad_value, "unit": "gradients/s", "points": G,
-                    "form": "log L and d log L/d theta (17) per point, one graph launch per step"},
+                    "form": "log L and d log L/d theta (17) per point, one graph launch per step",
+                    "stage_ms_per_step": grad_stage_ms,
+                    "roofline": {"bound": "alu", "achieved": grad_achieved, "peak": FP32_PEAK_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": grad_achieved / FP32_PEAK_TFLOPS, "kernel": "grad",
+                                 "ops_per_subsample": GRAD_OPS_PER_SUBSAMPLE, "subsamples_per_launch": grad_subs,
+                                 "pixels_per_point": vis_px}},
         "stage_ms_per_step": stage_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "render", "ops_per_subsample": OPS_PER_SUBSAMPLE,
                      "subsamples_per_launch": subs * P},
         "psf_chi2_tflops": psf_tflops,
+        "schedule": {"psf_tile": schedule["psf_tile"], "render_pixels_per_thread": schedule["render_pixels_per_thread"],
+                     "chosen_by": "autotuner (timed on this launch)"},
+        "masked": masked,
         "mixed_batch": mixed,
+        "extensions": extensions,
         "wall_s_timed": wall,
     }
     if not args.no_cpu_baseline:

@@ -155,13 +155,31 @@ int lensed_loglike(lensed_ctx* ctx, const lensed_system* sys, const float* theta
  *   logl             device float64 [n_points], written
  * The plan (work lists, scratch layout, captured graph) is cached on the context
  * keyed by the systems, the mapping and the theta/logl pointers. The first call
- * for a new set of system shapes also autotunes the PSF tile: it times the PSF +
- * chi^2 stage of the cost model's six best-ranked tile shapes on this launch
- * (synchronising `stream`) and keeps the fastest for every later plan over the
- * same shapes; LENSED_NO_AUTOTUNE=1 in the environment keeps the model's choice. */
+ * for a new set of system shapes also autotunes the schedule: it times the PSF +
+ * chi^2 stage of the cost model's six best-ranked tile shapes, then the render
+ * kernels with one and with two pixels per thread, on this launch
+ * (synchronising `stream`), and keeps the fastest for every later plan over the
+ * same shapes; LENSED_NO_AUTOTUNE=1 in the environment keeps the model's tile
+ * and one pixel per thread, LENSED_RENDER_PPT=1 or 2 (read by lensed_create)
+ * fixes the render schedule. Every schedule gives the same results bit for bit. */
 int lensed_loglike_batch(lensed_ctx* ctx, const lensed_system* systems, int n_systems,
                          const float* theta, const int32_t* system_of_point, int n_points,
                          double* logl, void* stream);
+
+/* lensed_loglike_batch restricted to the pixels that Eq. 17 can see. A pixel
+ * with w = 0 is masked (Sec. 3.2), so log L needs L* only where w > 0, and by
+ * Eq. 15 (replicate padding) L* there reads L only within the PSF's
+ * (2p+1) x (2q+1) box around it, clamped to the image. The plan renders only
+ * the pixels of that dilated support and convolves only the PSF output tiles
+ * that hold a pixel with w > 0; everything else stays zero. The result equals
+ * lensed_loglike_batch bit for bit whenever the data are finite where w = 0
+ * (a non-finite datum at a masked pixel makes the unmasked sum NaN, 0 x inf).
+ * Arguments, ownership and errors as lensed_loglike_batch; the plan reads the
+ * weights back to the host once when it is built, so the weights must not
+ * change between calls that reuse the plan (same pointers: same plan). */
+int lensed_loglike_batch_masked(lensed_ctx* ctx, const lensed_system* systems, int n_systems,
+                                const float* theta, const int32_t* system_of_point, int n_points,
+                                double* logl, void* stream);
 
 /* Per-pixel integration error estimate of a Gauss-Kronrod rule (Sec. 3.1: the
  * embedded Gauss rule estimates the error of each pixel and is saved with the
@@ -357,12 +375,31 @@ int lensed_mlp_train_step(lensed_ctx* ctx, float* params, float* m, float* v, in
  * on `stream`. lensed_stage_times waits for the recorded events and returns,
  * summed over the profiled calls since the previous query, the milliseconds of
  *   ms[0] prologue, ms[1] render kernel, ms[2] float64 cusp corrections,
- *   ms[3] PSF + chi^2, ms[4] finalize
+ *   ms[3] PSF + chi^2, ms[4] finalize,
+ * and for lensed_loglike_grad (also profiled) ms[5] A^T rho (the transposed
+ * PSF), ms[6] the per-subsample gradient kernel, ms[7] its float64 cusp
+ * corrections and the final sums (zero for calls without a gradient)
  * (ms is a HOST array of at least LENSED_NSTAGES doubles; *calls, if not NULL,
  * receives the number of calls summed), then resets the sums. */
-#define LENSED_NSTAGES 5
+#define LENSED_NSTAGES 8
 int lensed_set_profiling(lensed_ctx* ctx, int enable);
 int lensed_stage_times(lensed_ctx* ctx, double* ms, int n, int* calls);
+
+/* The schedule of the most recent batched call (the batching of Eq. 17 over
+ * points and systems): out[0], out[1] the PSF + chi^2 output tile width and
+ * height, out[2] the pixels per render thread of the midpoint rules (1, or 2
+ * horizontally adjacent pixels sharing the row terms of the subsample grid).
+ * On the first batch over a new set of image shapes the library times the
+ * best-ranked tiles and both render schedules on that launch and keeps the
+ * fastest (unless LENSED_NO_AUTOTUNE is set). out is a HOST array of 3 ints;
+ * all zero before any batched call. INVALID_ARGUMENT if out is NULL. */
+int lensed_batch_schedule(lensed_ctx* ctx, int* out);
+
+/* Work of the most recent batched call: out[0] pixels and out[1] subsamples
+ * (integration points) its render stage evaluates per launch (all pixels of
+ * every point, or only the visible ones of a masked call). out is a HOST array
+ * of 2 int64. INVALID_ARGUMENT if out is NULL. */
+int lensed_batch_rendered(lensed_ctx* ctx, int64_t* out);
 
 #ifdef __cplusplus
 }

@@ -145,6 +145,9 @@ def lib():
                                         ctypes.c_double, vp]),
                 "lensed_mlp_train_step": (i, [vp, vp, vp, vp, i, vp, vp, vp, i, ctypes.c_double, vp, vp]),
                 "lensed_stage_times": (i, [vp, ctypes.POINTER(ctypes.c_double), i, ctypes.POINTER(ctypes.c_int)]),
+                "lensed_batch_schedule": (i, [vp, ctypes.POINTER(ctypes.c_int)]),
+                "lensed_batch_rendered": (i, [vp, ctypes.POINTER(ctypes.c_int64)]),
+                "lensed_loglike_batch_masked": (i, [vp, sp, i, vp, ctypes.POINTER(ctypes.c_int32), i, vp, vp]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)
@@ -174,10 +177,10 @@ class Context:
             msg = lib().lensed_last_error(self._h)
             raise LensedError(rc, f"{what}: {msg.decode() if msg else ''}")
 
-    STAGES = ("prologue", "render", "cusp", "psf_chi2", "finalize")
+    STAGES = ("prologue", "render", "cusp", "psf_chi2", "finalize", "adjoint_psf", "grad", "grad_cusp")
 
     def set_profiling(self, enable: bool):
-        """Run batched calls stage by stage with hipEvents between the stages (no graph)."""
+        """Run batched and gradient calls stage by stage with hipEvents between the stages (no graph)."""
         self.check(lib().lensed_set_profiling(self._h, int(bool(enable))), "lensed_set_profiling")
 
     def stage_times(self):
@@ -187,6 +190,18 @@ class Context:
         self.check(lib().lensed_stage_times(self._h, ms, len(self.STAGES), ctypes.byref(calls)),
                    "lensed_stage_times")
         return dict(zip(self.STAGES, list(ms))), calls.value
+
+    def batch_schedule(self):
+        """Schedule of the most recent batched call: PSF + chi^2 tile (width, height) and render pixels per thread."""
+        out = (ctypes.c_int * 3)()
+        self.check(lib().lensed_batch_schedule(self._h, out), "lensed_batch_schedule")
+        return {"psf_tile": [out[0], out[1]], "render_pixels_per_thread": out[2]}
+
+    def batch_rendered(self):
+        """Pixels and subsamples the render stage of the most recent batched call evaluates per launch."""
+        out = (ctypes.c_int64 * 2)()
+        self.check(lib().lensed_batch_rendered(self._h, out), "lensed_batch_rendered")
+        return {"pixels": int(out[0]), "subsamples": int(out[1])}
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -439,8 +454,11 @@ class _SystemArray:
 
 
 def loglike_batch(theta: torch.Tensor, system_of_point, systems: Sequence[System], *,
-                  out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None, stream=None) -> torch.Tensor:
-    """log L of P points over several systems in one graph launch -> float64 [P]."""
+                  out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None, stream=None,
+                  masked: bool = False) -> torch.Tensor:
+    """log L of P points over several systems in one graph launch -> float64 [P].
+    masked: render only the pixels the chi^2 can see (lensed_loglike_batch_masked);
+    the same result, bit for bit, for finite data."""
     t = _theta2d(theta)
     P = t.shape[0]
     sop = np.ascontiguousarray(np.asarray(system_of_point, dtype=np.int32).reshape(-1))
@@ -450,10 +468,11 @@ def loglike_batch(theta: torch.Tensor, system_of_point, systems: Sequence[System
     if out is None:
         out = torch.empty(P, dtype=torch.float64, device=t.device)
     sa = _SystemArray(systems)
-    rc = lib().lensed_loglike_batch(ctx.handle, sa.arr, len(sa.systems), ctypes.c_void_p(t.data_ptr()),
-                                    sop.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), P,
-                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
-    ctx.check(rc, "lensed_loglike_batch")
+    fn = lib().lensed_loglike_batch_masked if masked else lib().lensed_loglike_batch
+    rc = fn(ctx.handle, sa.arr, len(sa.systems), ctypes.c_void_p(t.data_ptr()),
+            sop.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), P, ctypes.c_void_p(out.data_ptr()),
+            _stream_handle(stream))
+    ctx.check(rc, "lensed_loglike_batch_masked" if masked else "lensed_loglike_batch")
     return out
 
 

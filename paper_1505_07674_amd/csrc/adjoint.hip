@@ -502,7 +502,11 @@ __global__ __launch_bounds__(64 * GCUSP_WAVES) void grad_cusp_kernel(WorkArgs w,
     U.bS = c.sB * LN2F;
     U.dbH = gc.dB_dn_h * LN2F;
     U.dbS = gc.dB_dn_s * LN2F;
-    const PixelGeom geo = gcusp_geom(sd, e.pix0 + lane);
+    const int lpix = mine ? unit_pixel(sd, e.unit0 + lane, e.ppt) + e.half : 0;   // this lane's pixel
+    const PixelGeom geo = gcusp_geom(sd, lpix);
+    // the render constants the forward render used for this lane's pixel
+    const int prow = lpix / sd.W;
+    const RenderVariant& kv = c.rv[render_variant(prow, lpix - prow * sd.W)];
     const int N = sd.N, NN = N * N;
     const GkRule* Rg = sd.rule > 0 ? &kGkRules[sd.rule - 1] : nullptr;
     float acc[NPAR];
@@ -515,7 +519,7 @@ __global__ __launch_bounds__(64 * GCUSP_WAVES) void grad_cusp_kernel(WorkArgs w,
         const int ky = (s0 + j) / N, kx = s0 + j - ky * N;
         const float y = fmaf(geo.uy + (Rg ? Rg->x[ky] : sub_offset_rt(ky, N)), geo.d, geo.cy);
         const float x = fmaf(geo.ux + (Rg ? Rg->x[kx] : sub_offset_rt(kx, N)), geo.d, geo.cx);
-        const bool within = mine && render_source_R2(c, x, y) < c.cusp_r2;
+        const bool within = mine && render_source_R2(c, kv, x, y) < c.cusp_r2;
         const unsigned long long b = __ballot(within);
         if (within) qu[qn + __popcll(b & ((1ull << lane) - 1ull))] = (unsigned short)(lane | (j << 6));
         qn += __popcll(b);
@@ -526,7 +530,8 @@ __global__ __launch_bounds__(64 * GCUSP_WAVES) void grad_cusp_kernel(WorkArgs w,
           const int item = qu[q0 + lane];
           const int pl = item & 63, j = item >> 6;
           const int ky = (s0 + j) / N, kx = s0 + j - ky * N;
-          const PixelGeom gq = gcusp_geom(sd, e.pix0 + pl);
+          const int qpix = unit_pixel(sd, e.unit0 + pl, e.ppt) + e.half;
+          const PixelGeom gq = gcusp_geom(sd, qpix);
           const float y = fmaf(gq.uy + (Rg ? Rg->x[ky] : sub_offset_rt(ky, N)), gq.d, gq.cy);
           const float x = fmaf(gq.ux + (Rg ? Rg->x[kx] : sub_offset_rt(kx, N)), gq.d, gq.cx);
           const double oy = Rg ? Rg->xd[ky] : ((double)ky + 0.5) / N - 0.5;
@@ -551,7 +556,7 @@ __global__ __launch_bounds__(64 * GCUSP_WAVES) void grad_cusp_kernel(WorkArgs w,
               subsample_grad<2, true>(c, U, x, y, a64, true, dx, dy, sw);
               break;
           }
-          const float wg = (float)sd.wgt * G[loff + e.pix0 + pl];
+          const float wg = (float)sd.wgt * G[loff + qpix];
 #pragma unroll
           for (int k = 0; k < NPAR; ++k) acc[k] = fmaf(a64[k] - a32[k], wg, acc[k]);
         }
@@ -666,13 +671,14 @@ hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n
 
 hipError_t launch_grad(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, const GradConst* gcs,
                        const float* G, const int* gpbase, float2* gpart, int n_blocks, const CuspList& cl,
-                       double* corr, hipStream_t st) {
-  if (n_blocks <= 0) return hipSuccess;
+                       double* corr, hipStream_t st, hipEvent_t between) {
+  if (n_blocks <= 0) return between ? hipEventRecord(between, st) : hipSuccess;
   hipError_t e = for_item_parts(w, n_blocks, [&](const WorkArgs& part, int n) {
     hipLaunchKernelGGL(grad_kernel, dim3(n), dim3(RENDER_BLOCK), 0, st, part, pcs, gcs, G, gpbase, gpart);
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
+  if (between && (e = hipEventRecord(between, st)) != hipSuccess) return e;
   const int waves = n_blocks * (RENDER_BLOCK / 64);
   int grid = (waves + GCUSP_WAVES - 1) / GCUSP_WAVES;
   if (grid > GCUSP_BLOCKS) grid = GCUSP_BLOCKS;

@@ -37,11 +37,14 @@ struct lensed_ctx {
   size_t arena_bytes = 0;
   bool use_graphs = true;
   bool autotune = true;             // time the best-ranked tile shapes on the first batch of a shape set
+  int force_ppt = 0;                // 1 or 2: render pixels per thread fixed (not timed)
   std::vector<std::unique_ptr<BatchPlan>> plans;   // most recently used last
   TileCache tiles;
   bool profiling = false;                          // per-stage hipEvents, no graphs
   std::vector<std::vector<hipEvent_t>> pending;    // event sets of profiled calls
   double stage_ms[LENSED_NSTAGES] = {0};
+  int schedule[3] = {0, 0, 0};   // of the last batched plan run: PSF tile width, height; render pixels per thread
+  int64_t rendered[2] = {0, 0};  // of the last batched plan run: pixels and subsamples rendered per launch
   int stage_calls = 0;
   char* mlp_mem = nullptr;                          // surrogate scratch
   MlpScratch mlp;
@@ -241,6 +244,8 @@ int lensed_create(lensed_ctx** out, int device) {
   c->use_graphs = !(g && g[0] == '1');
   const char* t = std::getenv("LENSED_NO_AUTOTUNE");
   c->autotune = !(t && t[0] == '1');
+  const char* r = std::getenv("LENSED_RENDER_PPT");
+  c->force_ppt = (r && (r[0] == '1' || r[0] == '2') && r[1] == 0) ? r[0] - '0' : 0;
   *out = c;
   return LENSED_OK;
 }
@@ -425,11 +430,11 @@ namespace {
 // the autotuner on a new set of shapes), then replay its graph.
 int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const float* theta,
               const int32_t* system_of_point, int n_points, double* logl, void* stream, int K, const float* sky,
-              int G = 1, const ModelSpec* model = nullptr, int params_per_point = NPAR) {
+              int G = 1, const ModelSpec* model = nullptr, int params_per_point = NPAR, bool masked = false) {
   BatchPlan* plan = nullptr;
   for (size_t i = 0; i < c->plans.size(); ++i) {
     if (c->plans[i]->matches(systems, n_systems, theta, system_of_point, n_points, logl, nullptr, K, sky, G,
-                             model)) {
+                             model, masked)) {
       std::unique_ptr<BatchPlan> keep = std::move(c->plans[i]);
       c->plans.erase(c->plans.begin() + i);
       c->plans.push_back(std::move(keep));
@@ -454,7 +459,7 @@ int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const 
         BatchPlan trial;
         std::string msg;
         if (trial.build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg, nullptr, &t, K,
-                        sky, G, model, params_per_point) != hipSuccess) {
+                        sky, G, model, params_per_point, 0, masked) != hipSuccess) {
           (void)hipGetLastError();
           continue;
         }
@@ -467,10 +472,35 @@ int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const 
       }
       c->tiles.set_measured(systems, n_systems, best);
     }
+    if (c->force_ppt) {
+      c->tiles.set_render_measured(systems, n_systems, c->force_ppt);
+    } else if (c->autotune && !c->tiles.has_render_measured(systems, n_systems)) {
+      // Render schedule: one or two pixels per thread (two share the row terms
+      // of the subsample grid), timed the same way on this launch's render kernels.
+      int best = 1;
+      float best_ms = 1e30f;
+      for (int ppt = 1; ppt <= 2; ++ppt) {
+        BatchPlan trial;
+        std::string msg;
+        if (trial.build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg, nullptr, nullptr,
+                        K, sky, G, model, params_per_point, ppt, masked) != hipSuccess) {
+          (void)hipGetLastError();
+          continue;
+        }
+        if (!trial.pair_capable()) break;   // nothing to choose: every class renders one pixel per thread
+        float ms = 0.0f;
+        LENSED_HIP(c, trial.render_ms((hipStream_t)stream, &ms));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = ppt;
+        }
+      }
+      c->tiles.set_render_measured(systems, n_systems, best);
+    }
     std::unique_ptr<BatchPlan> np(new BatchPlan());
     std::string msg;
     hipError_t e = np->build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg, nullptr,
-                             nullptr, K, sky, G, model, params_per_point);
+                             nullptr, K, sky, G, model, params_per_point, 0, masked);
     if (e != hipSuccess) return hip_fail(c, e, ("batch plan: " + msg).c_str());
     if (c->use_graphs) {
       e = np->capture(c->cap);
@@ -479,6 +509,11 @@ int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const 
     c->plans.push_back(std::move(np));
     plan = c->plans.back().get();
   }
+  c->schedule[0] = plan->psf_tile().TW;
+  c->schedule[1] = plan->psf_tile().TH;
+  c->schedule[2] = plan->render_ppt();
+  c->rendered[0] = plan->rendered_pixels();
+  c->rendered[1] = plan->rendered_subsamples();
   if (c->profiling) {
     std::vector<hipEvent_t> ev(LENSED_NSTAGES + 1);
     for (auto& e : ev) LENSED_HIP(c, hipEventCreate(&e));
@@ -509,6 +544,26 @@ int lensed_loglike_batch(lensed_ctx* c, const lensed_system* systems, int n_syst
       return set_err(c, LENSED_INVALID_ARGUMENT, "system_of_point[" + std::to_string(p) + "] out of range");
   LENSED_HIP(c, hipSetDevice(c->device));
   return run_batch(c, systems, n_systems, theta, system_of_point, n_points, logl, stream, 1, nullptr);
+}
+
+int lensed_loglike_batch_masked(lensed_ctx* c, const lensed_system* systems, int n_systems, const float* theta,
+                                const int32_t* system_of_point, int n_points, double* logl, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  if (n_points < 0) return set_err(c, LENSED_INVALID_ARGUMENT, "n_points must be >= 0");
+  if (n_points == 0) return LENSED_OK;
+  if (!systems || n_systems <= 0) return set_err(c, LENSED_INVALID_ARGUMENT, "at least one system is required");
+  if (!theta || !logl || !system_of_point)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "theta, system_of_point and logl are required");
+  for (int s = 0; s < n_systems; ++s) {
+    const int rc = validate_system(c, &systems[s], true, s);
+    if (rc) return rc;
+  }
+  for (int p = 0; p < n_points; ++p)
+    if (system_of_point[p] < 0 || system_of_point[p] >= n_systems)
+      return set_err(c, LENSED_INVALID_ARGUMENT, "system_of_point[" + std::to_string(p) + "] out of range");
+  LENSED_HIP(c, hipSetDevice(c->device));
+  return run_batch(c, systems, n_systems, theta, system_of_point, n_points, logl, stream, 1, nullptr, 1, nullptr,
+                   NPAR, true);
 }
 
 int lensed_loglike_composite(lensed_ctx* c, const lensed_system* systems, int n_systems, const float* theta,
@@ -675,6 +730,21 @@ int lensed_loglike_multiband(lensed_ctx* c, const lensed_system* systems, int n_
                    n_bands);
 }
 
+int lensed_batch_schedule(lensed_ctx* c, int* out) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  if (!out) return set_err(c, LENSED_INVALID_ARGUMENT, "out is NULL");
+  for (int k = 0; k < 3; ++k) out[k] = c->schedule[k];
+  return LENSED_OK;
+}
+
+int lensed_batch_rendered(lensed_ctx* c, int64_t* out) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  if (!out) return set_err(c, LENSED_INVALID_ARGUMENT, "out is NULL");
+  out[0] = c->rendered[0];
+  out[1] = c->rendered[1];
+  return LENSED_OK;
+}
+
 int lensed_set_profiling(lensed_ctx* c, int enable) {
   if (!c) return LENSED_INVALID_ARGUMENT;
   c->profiling = enable != 0;
@@ -739,6 +809,13 @@ extern "C" int lensed_loglike_grad(lensed_ctx* c, const lensed_system* sys, cons
     }
     c->plans.push_back(std::move(np));
     plan = c->plans.back().get();
+  }
+  if (c->profiling) {
+    std::vector<hipEvent_t> ev(LENSED_NSTAGES + 1);
+    for (auto& e : ev) LENSED_HIP(c, hipEventCreate(&e));
+    LENSED_HIP(c, plan->enqueue((hipStream_t)stream, ev.data()));
+    c->pending.push_back(std::move(ev));
+    return LENSED_OK;
   }
   LENSED_HIP(c, plan->run((hipStream_t)stream));
   return LENSED_OK;

@@ -16,11 +16,51 @@ constexpr double LOG2E = 1.44269504088896340736;
 constexpr double CUSP_RADIUS_ARCSEC = 0.03;
 constexpr double CUSP_RADIUS_IMAGE_PLANE_ARCSEC = 0.06;
 
+// Float32 constants of the forward render, folded in float64 from the
+// parameters (prologue kernel) and rounded to float32. Each point carries
+// RENDER_VARIANTS roundings of them: variant v rounds every constant c to the
+// float32 neighbour below or above it, upward in a share of the variants equal
+// to c's position between its two neighbours (to 1/32 of their gap). Pixel
+// (row, col) uses the variant of its cell in an ordered-dither pattern
+// (render_variant). Every pixel thus sees each constant within one float32
+// spacing, while the mean over any 4 x 8 block of pixels is the float64
+// constant (to 1/32 of a spacing): the rounding
+// of the constants stops acting as a coherent perturbation of the model,
+// which a chi^2 far from its minimum would otherwise amplify (a relative
+// model bias eps moves log L by about 2 eps relative).
+//
+//   lens light  R^2/R_e^2 = (ha x + hb y) x + hc y^2,  I = I_e exp2(hB (1 - t)), t = exp2(he log2(R^2/R_e^2))
+//   source      the same with (se, sB) at the source frame of beta - x_S:
+//               X = A1 x + (B1 y + C1) + cXt At + cXh Ah,  Y = A2 x + (B2 y + C2) + cYt At + cYh Ah
+//   SIE frame   x' = cL x + sL y, y' = cL y - sL x, psi^2 = q2 x'^2 + y'^2; At, Ah the folded deflection terms
+//   sphere      alpha = tac (x, y)/r, X = A1 x + (B1 y + C1) - (tac/r)(s11 x + s12 y) (Y: s21, s22)
+struct RenderVariant {
+  float cL, sL, q2, iq;
+  float qp;                      // q' = sqrt(1 - q^2), the leading coefficient of the folded polynomials
+  float A1, A2, B1, B2, C1, C2;
+  float cXt, cXh, cYt, cYh;
+  float ha, hb, hc, he, hB;
+  float se, sB;
+  float tac;
+  float s11, s12, s21, s22;
+  float pad[5];
+};
+static_assert(sizeof(RenderVariant) == 32 * 4, "RenderVariant layout");
+constexpr int RENDER_VARIANTS = 16;
+
+// Variant of pixel (row, col): a 4 x 4 Bayer ordered dither over cells of two
+// horizontally adjacent pixels (so a thread that renders a pixel pair (2j, 2j+1)
+// needs one set), repeating every 4 rows and 8 columns.
+__device__ __forceinline__ int render_variant(int row, int col) {
+  return (int)((0x5D7F91B36E4CA280ull >> (4 * (((row & 3) << 2) | ((col >> 1) & 3)))) & 15ull);
+}
+
 // Per-point constants derived once from the 17 parameters (prologue kernel).
-// Read with wave-uniform addresses, so they live in scalar registers in the
-// render kernels. Invalid points carry NaN in the amplitudes and in the lens
-// matrix, which turns every result of that point into NaN.
-struct PointConst {
+// The uniform part (PointHead) is read with wave-uniform addresses, so it lives
+// in scalar registers; each render thread reads its pixel's variant of the
+// folded constants from rv. Invalid points carry NaN in the amplitudes and in
+// the lens matrix, which turns every result of that point into NaN.
+struct PointHead {
   int sie_mode;        // 0: isothermal sphere (q = 1); 1: atanh by polynomial (q' <= 1/2); 2: atanh by log
   float cL, sL;        // frame rotation of the SIE
   float q2;            // q_L^2
@@ -34,30 +74,27 @@ struct PointConst {
   float sx0, sy0, sc, ss, sqa, sqb, se, sB, sI;
   // source subsamples with R^2/R_e^2 below this are re-traced in float64 (0 = never)
   float cusp_r2;
-  float pad[4];
-  // ---- folded forms used by the forward render (the adjoint uses the fields above)
   // rmode: 0 sphere, 1 polynomials (q' <= 1/2), 2 log + half-angle atan with
   // argument <= 1/sqrt(3) (q >= 1/2), 3 log + half-angle atan on [0, 1] (q < 1/2).
   int rmode;
-  // alpha_x = tac At - ths Ah, alpha_y = tas At + thc Ah, with the factors 2
-  // (half angle) and ln 2 (log2) of modes 2 and 3 folded in; mode 0: tac = theta_E.
-  float tac, tas, thc, ths;
-  // scaled frame of the Sersic profiles: (R/R_e)^2 = X^2 + Y^2,
-  // X = a11 dx + a12 dy, Y = a21 dx + a22 dy (sqrt(q)/R_e and 1/(sqrt(q) R_e) folded in)
-  float h11, h12, h21, h22;
-  float s11, s12, s21, s22;
-  // the source frame of beta - (x_S, y_S) in one step: with S = (s11 s12; s21 s22),
-  // X = A1 x + (B1 y + C1) + cXt At + cXh Ah, Y = A2 x + (B2 y + C2) + cYt At + cYh Ah,
-  // (A1 A2) = S (m11 m12), (B1 B2) = S (m12 m22), (C1 C2) = -S (x_S y_S),
-  // cXt = -(s11 tac + s12 tas), cXh = s11 ths - s12 thc, and the same with s21, s22.
-  float A1, A2, B1, B2, C1, C2, cXt, cXh, cYt, cYh;
+  // Higher coefficients of the deflection polynomials with q' folded in, so that
+  // they take x'/psi (mode 1) or x'/(psi + r) (modes 2, 3) directly: atan
+  // (mode 1: poly[1..5]; mode 2: poly[1..5]; mode 3: poly[1..8]) and, in mode 1,
+  // atanh (poly[6..10]); coefficient k is c_k q'^(2k+1). The leading q' is per
+  // variant.
+  float poly[11];
   // low parts of the two amplitudes (I_e - float(I_e)), non-zero only when I_e
   // is derived in float64 from a magnitude: they keep the float32 rounding of
   // the amplitude from scaling every pixel of a component the same way
   float hIlo, sIlo;
-  float pad2[7];
+  float pad[22];
 };
-static_assert(sizeof(PointConst) == 64 * 4, "PointConst layout");
+static_assert(sizeof(PointHead) == 64 * 4, "PointHead layout");
+
+struct PointConst : PointHead {
+  RenderVariant rv[RENDER_VARIANTS];
+};
+static_assert(sizeof(PointConst) == sizeof(PointHead) + RENDER_VARIANTS * sizeof(RenderVariant), "PointConst layout");
 
 // Float64 lens constants for the rare re-tracing of subsamples that land next
 // to the centre of a cuspy (n > 1) source, where the float32 rounding of the
@@ -113,16 +150,36 @@ struct SysDesc {
   double wgt;             // quadrature weight pixscale^2 / N^2, in float64
   float* adjk;            // 16 folded PSF tables of the adjoint (or nullptr)
   float* adjk_pad;
+  // Render units of a masked plan: the first pixel of each unit (a pixel, or a
+  // pair of adjacent pixels) that the chi^2 can see, row-major; nullptr: every
+  // pixel, unit u starting at pixel u * ppt.
+  const int* active;
+  int n_active;           // units in `active`
+  int pad_active;
 };
+
+// First pixel of render unit u of an image rendered with ppt pixels per unit.
+__device__ __forceinline__ int unit_pixel(const SysDesc& sd, int u, int ppt) {
+  return sd.active ? sd.active[u] : u * ppt;
+}
+// Render units of an image.
+__host__ __device__ __forceinline__ int unit_count(const SysDesc& sd, int ppt) {
+  return sd.active ? sd.n_active : (sd.H * sd.W + ppt - 1) / ppt;
+}
 
 constexpr int RENDER_BLOCK = 256;
 
 // A wave of the render kernel with pixels next to a cuspy source centre: the
-// point, the first pixel of the wave and the lane mask of flagged pixels.
+// point, the lane mask of flagged pixels, and where the lanes' pixels are:
+// lane l rendered render unit unit0 + l of the point's image (unit_pixel), and
+// the entry covers pixel `half` of each unit (0, or 1 for the second pixel of
+// a pair when a thread renders ppt = 2 adjacent pixels).
 struct CuspEntry {
   int point;
-  int pix0;
+  int unit0;
   unsigned long long mask;
+  int ppt;
+  int half;
 };
 
 // Correction work list filled by the render kernel (count reset by the prologue).

@@ -59,6 +59,25 @@ hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, Po
 hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L, int n_blocks,
                          const CuspList& cl, hipStream_t stream, hipEvent_t between = nullptr);
 
+// Schedule class of a system's render: N (1..RENDER_MAX_CLASS) for the N x N
+// midpoint rule, each its own kernel with the rule unrolled; 0 for the
+// Gauss-Kronrod rules and larger N.
+constexpr int RENDER_MAX_CLASS = 8;
+int render_class(const SysDesc& sd);
+
+// A run of render items of one class: items [offset, offset + count) of w.items
+// (or, for a plain call, blocks 0..count-1 of w.single), with ppt pixels per
+// thread (2 only for classes 1..RENDER_MAX_CLASS and images of even width; an
+// item then covers 2 RENDER_BLOCK pixels).
+struct RenderSpan {
+  int klass, ppt, offset, count;
+};
+// Batched form: one launch per span, then one cusp-correction pass over all of
+// them. cl.entries needs one slot per render wave and pixel of a thread.
+hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L,
+                         const RenderSpan* spans, int n_spans, const CuspList& cl, hipStream_t stream,
+                         hipEvent_t between = nullptr);
+
 // General models: per-point float64 constants from the parameters (n_params
 // per point, the layout of lensed_model), and the float64 render into L.
 hipError_t launch_model_prologue(const float* theta, int n_points, int n_params, const ModelSpec& spec,
@@ -114,7 +133,7 @@ hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n
 // render filled) added to corr[p * 17 + k], which must start at zero.
 hipError_t launch_grad(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, const GradConst* gcs,
                        const float* G, const int* gpbase, float2* gpart, int n_blocks, const CuspList& cl,
-                       double* corr, hipStream_t st);
+                       double* corr, hipStream_t st, hipEvent_t between = nullptr);
 
 // Sums the gradient partials of every point; for points of a system with
 // magnitudes, carries d log L / d I_e over to d/dm, d/dR_e and d/dn (gcs).

@@ -32,14 +32,26 @@ class TileCache {
   std::vector<TileShape> ranked(const lensed_system* s, int n, int k) const;
   bool has_measured(const lensed_system* s, int n) const { return measured_.count(key(s, n)) != 0; }
   void set_measured(const lensed_system* s, int n, TileShape t) { measured_[key(s, n)] = t; }
+  // Render schedule (pixels per thread of the midpoint classes): the measured
+  // choice for this set of image sizes and rules, else one pixel per thread.
+  int render_ppt(const lensed_system* s, int n) const {
+    auto it = render_measured_.find(render_key(s, n));
+    return it == render_measured_.end() ? 1 : it->second;
+  }
+  bool has_render_measured(const lensed_system* s, int n) const { return render_measured_.count(render_key(s, n)) != 0; }
+  void set_render_measured(const lensed_system* s, int n, int ppt) { render_measured_[render_key(s, n)] = ppt; }
   static double model_cost(int H, int W, int ph, int pw, TileShape t, int sq);
   static std::vector<TileShape> candidates(int sq, const lensed_system* s = nullptr, int n = 0);
+  // The cost model's best tile for one system (no cache, no allocation).
+  static TileShape model_best(const lensed_system& s);
 
  private:
   static std::string key(const lensed_system* s, int n);
+  static std::string render_key(const lensed_system* s, int n);
   static int launch_square(const lensed_system* s, int n);
   std::map<std::tuple<int, int, int, int>, TileShape> cache_;
   std::map<std::string, TileShape> measured_;
+  std::map<std::string, int> render_measured_;
 };
 
 int validate_system(lensed_ctx* c, const lensed_system* s, bool need_data, int index);
@@ -60,17 +72,32 @@ class BatchPlan {
   // of the 17-parameter one.
   bool matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map, int n_points,
                const double* logl, const float* grad = nullptr, int K = 1, const float* sky = nullptr,
-               int G = 1, const ModelSpec* model = nullptr) const;
-  // force: use this tile shape instead of the cache's choice (autotuning)
+               int G = 1, const ModelSpec* model = nullptr, bool masked = false) const;
+  // force: use this tile shape instead of the cache's choice (autotuning);
+  // force_ppt > 0: render this many pixels per thread where the class allows it.
+  // masked: render only the pixels the chi^2 can see (the support of w > 0
+  // dilated by the PSF, clamped at the borders) and convolve only the PSF tiles
+  // that hold a pixel with w > 0; the other pixels and tile sums stay zero.
   hipError_t build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
                    int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad = nullptr,
                    const TileShape* force = nullptr, int K = 1, const float* sky = nullptr, int G = 1,
-                   const ModelSpec* model = nullptr, int params_per_point = NPAR);
-  // Runs the plan stage by stage twice on s and returns the second run's PSF + chi^2 milliseconds.
-  hipError_t psf_ms(hipStream_t s, float* ms) const;
+                   const ModelSpec* model = nullptr, int params_per_point = NPAR, int force_ppt = 0,
+                   bool masked = false);
+  // Runs the plan stage by stage (a warm-up, then three timed runs) and returns
+  // the fastest PSF + chi^2 stage, or the fastest render kernels, in milliseconds.
+  hipError_t psf_ms(hipStream_t s, float* ms) const { return stage_ms(s, 3, ms); }
+  hipError_t render_ms(hipStream_t s, float* ms) const { return stage_ms(s, 1, ms); }
+  // Whether a render class of this plan could take two pixels per thread.
+  bool pair_capable() const { return pair_capable_; }
+  // The schedule in use: PSF tile and pixels per thread of the midpoint classes.
+  TileShape psf_tile() const { return {TW_, TH_}; }
+  int render_ppt() const { return ppt_; }
+  int64_t rendered_pixels() const { return rendered_pixels_; }
+  int64_t rendered_subsamples() const { return rendered_subsamples_; }
   hipError_t capture(hipStream_t cap);
   // events, when given, are LENSED_NSTAGES + 1 events recorded around the stages
-  // (prologue, render kernel, cusp corrections and composition, PSF + chi^2, finalize)
+  // (prologue, render kernel, cusp corrections and composition, PSF + chi^2,
+  // finalize; with a gradient A^T rho, gradient kernel, its cusp corrections and sums)
   hipError_t enqueue(hipStream_t s, hipEvent_t* events = nullptr) const;
   hipError_t run(hipStream_t s) const;
 
@@ -113,9 +140,16 @@ class BatchPlan {
   float* d_L_ = nullptr;
   float2* d_part_ = nullptr;
   int n_ritems_ = 0, n_pitems_ = 0;
+  std::vector<RenderSpan> rspans_;   // render items by schedule class
   int square_psf_ = -1, TW_ = 32, TH_ = 32, max_ph_ = 1, max_pw_ = 1;
   hipGraph_t graph_ = nullptr;
   hipGraphExec_t exec_ = nullptr;
+  int ppt_ = 1;
+  bool pair_capable_ = false;
+  bool masked_ = false;
+  int64_t rendered_pixels_ = 0;   // pixels the render stage computes per launch
+  int64_t rendered_subsamples_ = 0;
+  hipError_t stage_ms(hipStream_t s, int stage, float* ms) const;
 };
 
 }  // namespace lensed

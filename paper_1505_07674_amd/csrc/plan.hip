@@ -8,14 +8,17 @@
 
 namespace lensed {
 
-std::vector<TileShape> TileCache::candidates(int sq, const lensed_system* s, int n) {
-  std::vector<TileShape> out;
+namespace {
+// Calls f(t) for every candidate PSF output tile of a launch over systems s
+// (sq: the launch's square-PSF code); a shape may come more than once.
+template <class F>
+void each_candidate(int sq, const lensed_system* s, int n, F f) {
   const int tws[] = {16, 32, 40, 48, 64};
   const int ths[] = {16, 20, 24, 32, 40, 48, 64};
   for (int tw : tws)
     for (int th : ths) {
       const int threads = tw * th / psf_rows(sq, tw, th);
-      if (threads >= 64 && threads <= 512) out.push_back({tw, th});
+      if (threads >= 64 && threads <= 512) f(TileShape{tw, th});
     }
   // Wide tiles of the 21 x 21 stencil: a whole image row, or a half or a third
   // of it, so that the tiles cover the image without ragged columns; heights
@@ -26,13 +29,34 @@ std::vector<TileShape> TileCache::candidates(int sq, const lensed_system* s, int
       if (!psf_wide(sq, tw)) continue;
       for (int th : {16, 24, 32, 40}) {
         const int threads = tw * th / psf_rows(sq, tw, th);
-        const TileShape t{tw, th};
         if (threads < 64 || threads > WIDE_MAX_THREADS || psf_lds_bytes(sq, tw, th, 21, 21) > 65536) continue;
-        if (std::none_of(out.begin(), out.end(), [&](const TileShape& o) { return o.TW == tw && o.TH == th; }))
-          out.push_back(t);
+        f(TileShape{tw, th});
       }
     }
+}
+}  // namespace
+
+std::vector<TileShape> TileCache::candidates(int sq, const lensed_system* s, int n) {
+  std::vector<TileShape> out;
+  each_candidate(sq, s, n, [&](TileShape t) {
+    if (std::none_of(out.begin(), out.end(), [&](const TileShape& o) { return o.TW == t.TW && o.TH == t.TH; }))
+      out.push_back(t);
+  });
   return out;
+}
+
+TileShape TileCache::model_best(const lensed_system& s) {
+  TileShape best{32, 32};
+  double bc = 1e300;
+  const int sq = square_psf_code(s.psf_h, s.psf_w);
+  each_candidate(sq, &s, 1, [&](TileShape t) {
+    const double cst = model_cost(s.height, s.width, s.psf_h, s.psf_w, t, sq);
+    if (cst < bc) {
+      bc = cst;
+      best = t;
+    }
+  });
+  return best;
 }
 
 // Lane slots of one launch: per tile, the block's lanes (whole waves) times the
@@ -57,6 +81,18 @@ std::string TileCache::key(const lensed_system* s, int n) {
   for (int i = 0; i < n; ++i)
     parts.push_back(std::to_string(s[i].height) + "x" + std::to_string(s[i].width) + "p" +
                     std::to_string(s[i].psf_h) + "x" + std::to_string(s[i].psf_w));
+  std::sort(parts.begin(), parts.end());
+  parts.erase(std::unique(parts.begin(), parts.end()), parts.end());
+  std::string k;
+  for (const auto& p : parts) k += p + ";";
+  return k;
+}
+
+std::string TileCache::render_key(const lensed_system* s, int n) {
+  std::vector<std::string> parts;
+  for (int i = 0; i < n; ++i)
+    parts.push_back(std::to_string(s[i].height) + "x" + std::to_string(s[i].width) + "n" + std::to_string(s[i].nsub) +
+                    "r" + std::to_string(s[i].rule));
   std::sort(parts.begin(), parts.end());
   parts.erase(std::unique(parts.begin(), parts.end()), parts.end());
   std::string k;
@@ -91,16 +127,7 @@ TileShape TileCache::choose(const lensed_system& s) {
   const auto shape = std::make_tuple(s.height, s.width, s.psf_h, s.psf_w);
   auto it = cache_.find(shape);
   if (it != cache_.end()) return it->second;
-  TileShape best{32, 32};
-  double bc = 1e300;
-  const int sq = square_psf_code(s.psf_h, s.psf_w);
-  for (const TileShape& t : candidates(sq, &s, 1)) {
-    const double cst = model_cost(s.height, s.width, s.psf_h, s.psf_w, t, sq);
-    if (cst < bc) {
-      bc = cst;
-      best = t;
-    }
-  }
+  const TileShape best = model_best(s);
   cache_[shape] = best;
   return best;
 }
@@ -131,7 +158,8 @@ BatchPlan::~BatchPlan() {
 
 bool BatchPlan::matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
                         int n_points, const double* logl, const float* grad, int K, const float* sky, int G,
-                        const ModelSpec* model) const {
+                        const ModelSpec* model, bool masked) const {
+  if (masked != masked_) return false;
   if (theta != theta_ || logl != logl_ || grad != grad_ || n_points != n_points_ || K != K_ || sky != sky_ ||
       G != G_ || (model != nullptr) != has_model_ ||
       (model && std::memcmp(model, &spec_, sizeof(ModelSpec)) != 0) ||
@@ -145,7 +173,7 @@ bool BatchPlan::matches(const lensed_system* systems, int n_systems, const float
 hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
                             int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad,
                             const TileShape* force, int K, const float* sky, int G, const ModelSpec* model,
-                            int params_per_point) {
+                            int params_per_point, int force_ppt, bool masked) {
   systems_.assign(systems, systems + n_systems);
   map_.assign(map, map + n_points);
   theta_ = theta;
@@ -178,6 +206,75 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
     if (square_psf_code(systems[s].psf_h, systems[s].psf_w) != square_psf_) square_psf_ = -1;
   }
 
+  // Pixels per render thread: two for a midpoint class whose images all have
+  // an even width (a pair never straddles two rows), if the schedule says so;
+  // gradient and general-model plans keep one (their kernels walk the same items).
+  ppt_ = force_ppt > 0 ? force_ppt : tiles.render_ppt(systems, n_systems);
+  if (grad || model) ppt_ = 1;
+  std::vector<char> class_pairs(RENDER_MAX_CLASS + 1, 1);
+  class_pairs[0] = 0;
+  for (int s = 0; s < n_systems; ++s)
+    if (desc[s].W % 2 != 0) class_pairs[render_class(desc[s])] = 0;
+  pair_capable_ = !grad && !model;
+  if (pair_capable_) {
+    bool any = false;
+    for (int s = 0; s < n_systems; ++s) any = any || class_pairs[render_class(desc[s])];
+    pair_capable_ = any;
+  }
+  auto class_ppt = [&](int klass) { return ppt_ == 2 && class_pairs[klass] ? 2 : 1; };
+
+  // Masked plans: per system, the render units the chi^2 can see and the PSF
+  // tiles that hold a pixel with w > 0 (from the weights, read back once here).
+  // An output pixel reads L within its (2p+1) x (2q+1) stencil, clamped at the
+  // borders, so the pixels needed are the w > 0 support dilated by that box.
+  masked_ = masked && !grad && !model;
+  std::vector<std::vector<int>> units(n_systems);
+  std::vector<std::vector<char>> ptile_on(n_systems);
+  if (masked_) {
+    for (int s = 0; s < n_systems; ++s) {
+      const SysDesc& d = desc[s];
+      const size_t npx = (size_t)d.H * d.W;
+      std::vector<float> w(npx);
+      hipError_t e = hipMemcpy(w.data(), d.weight, sizeof(float) * npx, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        msg = "reading weights";
+        return e;
+      }
+      const int p = d.ph / 2, q = d.pw / 2;
+      // separable box dilation: distance to the nearest marked pixel along rows, then along columns
+      std::vector<char> rowd(npx, 0), need(npx, 0);
+      std::vector<int> nxt(std::max(d.H, d.W) + 1);
+      for (int r = 0; r < d.H; ++r) {
+        const float* wr = &w[(size_t)r * d.W];
+        nxt[d.W] = 1 << 29;
+        for (int c = d.W - 1; c >= 0; --c) nxt[c] = wr[c] > 0.0f ? c : nxt[c + 1];
+        int last = -(1 << 29);
+        for (int c = 0; c < d.W; ++c) {
+          if (wr[c] > 0.0f) last = c;
+          rowd[(size_t)r * d.W + c] = (c - last <= q) || (nxt[c] - c <= q);
+        }
+      }
+      for (int c = 0; c < d.W; ++c) {
+        nxt[d.H] = 1 << 29;
+        for (int r = d.H - 1; r >= 0; --r) nxt[r] = rowd[(size_t)r * d.W + c] ? r : nxt[r + 1];
+        int last = -(1 << 29);
+        for (int r = 0; r < d.H; ++r) {
+          if (rowd[(size_t)r * d.W + c]) last = r;
+          need[(size_t)r * d.W + c] = (r - last <= p) || (nxt[r] - r <= p);
+        }
+      }
+      const int pp = class_ppt(render_class(d));
+      for (size_t pix = 0; pix < npx; pix += pp)
+        if (need[pix] || (pp == 2 && need[pix + 1])) units[s].push_back((int)pix);
+      ptile_on[s].assign(d.n_ptiles, 0);
+      for (int r = 0; r < d.H; ++r)
+        for (int c = 0; c < d.W; ++c)
+          if (w[(size_t)r * d.W + c] > 0.0f) ptile_on[s][(r / d.TH) * d.tiles_x + c / d.TW] = 1;
+      desc[s].n_active = (int)units[s].size();
+    }
+  }
+  rendered_pixels_ = rendered_subsamples_ = 0;
+
   std::vector<int64_t> loff(n_points);
   std::vector<int> pbase(n_points), ntiles(n_points), gpbase(n_points);
   int gtot = 0;
@@ -185,7 +282,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   int ptot = 0;
   struct Item {
     int64_t cost;
-    int point, tile;
+    int point, tile, klass;
   };
   std::vector<Item> ritems, pitems;
   for (int p = 0; p < n_points; ++p) {
@@ -197,18 +294,36 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
     ptot += ntiles[p];
     gpbase[p] = gtot;
     gtot += d.n_rtiles;
-    const int64_t npix = (int64_t)d.H * d.W;
-    for (int t = 0; t < d.n_rtiles; ++t) {
-      const int64_t px = std::min<int64_t>(RENDER_BLOCK, npix - (int64_t)t * RENDER_BLOCK);
-      ritems.push_back({px * d.N * d.N, p, t});
+    const int klass = render_class(d), pp = class_ppt(klass);
+    const int64_t nunits = masked_ ? (int64_t)units[map[p]].size() : ((int64_t)d.H * d.W + pp - 1) / pp;
+    const int64_t npix = masked_ ? nunits * pp : (int64_t)d.H * d.W;
+    rendered_pixels_ += npix;
+    rendered_subsamples_ += npix * d.N * d.N;
+    const int nrt = (int)((nunits + RENDER_BLOCK - 1) / RENDER_BLOCK);
+    for (int t = 0; t < nrt; ++t) {
+      const int64_t px = std::min<int64_t>(RENDER_BLOCK, nunits - (int64_t)t * RENDER_BLOCK) * pp;
+      ritems.push_back({px * d.N * d.N, p, t, klass});
     }
     compose_tiles_ = std::max(compose_tiles_, d.n_rtiles);
     if (p % K != 0) continue;   // a composite model is blurred and compared once, on its first image
-    for (int t = 0; t < d.n_ptiles; ++t) pitems.push_back({(int64_t)d.ph * d.pw, p, t});
+    for (int t = 0; t < d.n_ptiles; ++t)
+      if (!masked_ || ptile_on[map[p]][t]) pitems.push_back({(int64_t)d.ph * d.pw, p, t, 0});
   }
+  // render items: grouped by schedule class (one kernel each), longest first within a class
+  auto by_class_cost = [](const Item& a, const Item& b) {
+    return a.klass != b.klass ? a.klass < b.klass : a.cost > b.cost;
+  };
   auto by_cost = [](const Item& a, const Item& b) { return a.cost > b.cost; };
-  std::stable_sort(ritems.begin(), ritems.end(), by_cost);
+  std::stable_sort(ritems.begin(), ritems.end(), by_class_cost);
   std::stable_sort(pitems.begin(), pitems.end(), by_cost);
+  rspans_.clear();
+  int cusp_slots = 0;
+  for (int i = 0; i < (int)ritems.size(); ++i) {
+    const int klass = ritems[i].klass;
+    if (rspans_.empty() || rspans_.back().klass != klass) rspans_.push_back({klass, class_ppt(klass), i, 0});
+    ++rspans_.back().count;
+    cusp_slots += (RENDER_BLOCK / 64) * class_ppt(klass);
+  }
   n_ritems_ = (int)ritems.size();
   n_pitems_ = (int)pitems.size();
   std::vector<int2> ri(n_ritems_), pi(n_pitems_);
@@ -231,7 +346,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   const size_t o_p64 = off; off = align256(off + sizeof(PointConst64) * n_points);
   const size_t o_psf = off; off = align256(off + 3 * sizeof(float) * psf_total);
   const size_t o_cc = off; off = align256(off + sizeof(int));
-  const size_t o_ce = off; off = align256(off + sizeof(CuspEntry) * (size_t)n_ritems_ * (RENDER_BLOCK / 64));
+  const size_t o_ce = off; off = align256(off + sizeof(CuspEntry) * (size_t)cusp_slots);
   const size_t o_L = off; off = align256(off + sizeof(float) * (size_t)Ltot);
   const size_t o_part = off; off = align256(off + sizeof(float2) * (size_t)ptot);
   const bool g = grad != nullptr;
@@ -241,6 +356,11 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   const size_t o_gpart = off; off = align256(off + (g ? sizeof(float2) * (size_t)gtot * NPAR : 0));
   const size_t o_adjk = off; off = align256(off + (g ? sizeof(float) * 16 * psf_total : 0));
   const size_t o_gcorr = off; off = align256(off + (g ? sizeof(double) * (size_t)n_points * NPAR : 0));
+  std::vector<size_t> o_units(n_systems);
+  for (int s = 0; s < n_systems; ++s) {
+    o_units[s] = off;
+    off = align256(off + sizeof(int) * units[s].size());
+  }
   hipError_t e = hipMalloc((void**)&mem_, off);
   if (e != hipSuccess) {
     msg = "scratch of " + std::to_string(off) + " bytes";
@@ -264,6 +384,8 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   d_L_ = (float*)(mem_ + o_L);
   d_part_ = (float2*)(mem_ + o_part);
   for (int s = 0; s < n_systems; ++s) desc[s].psfn = (float*)(mem_ + o_psf) + 3 * psf_off[s];
+  if (masked_)
+    for (int s = 0; s < n_systems; ++s) desc[s].active = (const int*)(mem_ + o_units[s]);
   if (g) {
     d_gc_ = (GradConst*)(mem_ + o_gc);
     d_R_ = (float*)(mem_ + o_R);
@@ -294,6 +416,22 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
     msg = "uploading work lists";
     return e;
   }
+  if (masked_) {
+    // pixels and tile sums a masked plan never computes stay zero for every run
+    for (int s = 0; s < n_systems; ++s)
+      if (!units[s].empty() &&
+          (e = hipMemcpy((void*)desc[s].active, units[s].data(), sizeof(int) * units[s].size(),
+                         hipMemcpyHostToDevice)) != hipSuccess) {
+        msg = "uploading render units";
+        return e;
+      }
+    if ((e = hipMemset(d_L_, 0, sizeof(float) * (size_t)Ltot)) != hipSuccess ||
+        (e = hipMemset(d_part_, 0, sizeof(float2) * (size_t)ptot)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess) {
+      msg = "clearing the masked scratch";
+      return e;
+    }
+  }
   return hipSuccess;
 }
 
@@ -323,7 +461,8 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
     if ((e = launch_model_render(wr, spec_, d_mc_, d_L_, n_ritems_, st)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
   } else {
-    if ((e = launch_render(wr, d_pc_, d_p64_, d_L_, n_ritems_, cusp_, st, ev ? ev[2] : nullptr)) != hipSuccess)
+    if ((e = launch_render(wr, d_pc_, d_p64_, d_L_, rspans_.data(), (int)rspans_.size(), cusp_, st,
+                           ev ? ev[2] : nullptr)) != hipSuccess)
       return e;
     if (ev && n_ritems_ <= 0 && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
   }
@@ -347,12 +486,17 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
     if ((e = launch_adjoint_psf(wp, d_R_, d_L_, n_pitems_, square_psf_, TW_, TH_, max_ph_, max_pw_, n_points_,
                                 s0.height, s0.width, st)) != hipSuccess)
       return e;
-    if ((e = launch_grad(wr, d_pc_, d_p64_, d_gc_, d_L_, d_gpbase_, d_gpart_, n_ritems_, cusp_, d_gcorr_, st)) !=
-        hipSuccess)
+    if (ev && (e = hipEventRecord(ev[6], st)) != hipSuccess) return e;
+    if ((e = launch_grad(wr, d_pc_, d_p64_, d_gc_, d_L_, d_gpbase_, d_gpart_, n_ritems_, cusp_, d_gcorr_, st,
+                         ev ? ev[7] : nullptr)) != hipSuccess)
       return e;
     if ((e = launch_finalize_grad(d_gpart_, d_gpbase_, grad_ntiles_, n_points_, d_gcorr_, d_gc_, grad_, st)) !=
         hipSuccess)
       return e;
+    if (ev && (e = hipEventRecord(ev[8], st)) != hipSuccess) return e;
+  } else if (ev) {
+    for (int k = 6; k <= LENSED_NSTAGES; ++k)
+      if ((e = hipEventRecord(ev[k], st)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -367,7 +511,7 @@ hipError_t BatchPlan::capture(hipStream_t cap) {
   return hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0);
 }
 
-hipError_t BatchPlan::psf_ms(hipStream_t s, float* ms) const {
+hipError_t BatchPlan::stage_ms(hipStream_t s, int stage, float* ms) const {
   hipEvent_t ev[LENSED_NSTAGES + 1] = {};
   hipError_t e = hipSuccess;
   for (auto& x : ev)
@@ -380,7 +524,7 @@ hipError_t BatchPlan::psf_ms(hipStream_t s, float* ms) const {
     e = enqueue(s, ev);
     if (e == hipSuccess) e = hipEventSynchronize(ev[LENSED_NSTAGES]);
     float t = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[3], ev[4]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[stage], ev[stage + 1]);
     if (e == hipSuccess && t < *ms) *ms = t;
   }
   for (auto& x : ev)

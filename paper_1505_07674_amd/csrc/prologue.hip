@@ -11,6 +11,7 @@
 
 #include "internal.h"
 #include "kernels.h"
+#include "sie_poly.h"
 
 namespace lensed {
 namespace {
@@ -151,6 +152,26 @@ __device__ void lens_map_jacobian(const double (&v)[7], float (&jac)[14]) {
 __device__ bool ok_q(float q) { return q > 0.0f && q <= 1.0f; }
 __device__ bool ok_n(float n) { return n >= 0.2f && n <= 10.0f; }
 
+// Float32 rounding of c for render variant v: the float32 neighbour below or
+// above c, upward for a share of the RENDER_VARIANTS variants equal to c's
+// position between the two (so the mean over the variants is c to within 1/32
+// of their gap). Exactly representable and non-finite values are returned as
+// they are.
+__device__ float dither_round(double c, int v) {
+  const float f = (float)c;
+  if (!isfinite(f) || (double)f == c) return f;
+  float lo, hi;
+  if ((double)f < c) {
+    lo = f;
+    hi = nextafterf(f, __builtin_inff());
+  } else {
+    hi = f;
+    lo = nextafterf(f, -__builtin_inff());
+  }
+  const double frac = (c - (double)lo) / ((double)hi - (double)lo);
+  return frac + ((v + 0.5) / RENDER_VARIANTS - 0.5) >= 0.5 ? hi : lo;
+}
+
 // One block of 64 threads covers 64 / solves points: first each of a point's
 // `solves` threads finds one root of P(2n, b) = 1/2 (b_n of the lens and the
 // source light; with the adjoint also b at n +- h for db_n/dn), then one thread
@@ -242,7 +263,7 @@ __global__ __launch_bounds__(64) void prologue_kernel(const float* __restrict__ 
   if (j != 0) return;
   const double* rt = roots + threadIdx.x;
 
-  PointConst c;
+  PointHead c;
   const double te = t[0], q = t[1], phL = t[2], g = t[3], phg = t[4];
   c.cL = (float)cos(phL);
   c.sL = (float)sin(phL);
@@ -320,10 +341,11 @@ __global__ __launch_bounds__(64) void prologue_kernel(const float* __restrict__ 
     const double Re = t[13], rc = (srcpos ? CUSP_RADIUS_IMAGE_PLANE_ARCSEC : CUSP_RADIUS_ARCSEC) / Re;
     c.cusp_r2 = t[14] > 1.0f ? (float)(rc * rc) : 0.0f;
   }
-  for (int k = 0; k < 4; ++k) c.pad[k] = 0.0f;
-  // folded constants of the forward render
+  // folded constants of the forward render (float64), then their dithered
+  // float32 roundings, one set per variant
   double tac = te, tas = 0.0, thc = 0.0, ths = 0.0;
   c.rmode = 0;
+  for (int k = 0; k < 11; ++k) c.poly[k] = 0.0f;
   if (s2 != 0.0) {
     const double k = te * sqrt(q) / qp;
     const double fa = qp <= 0.5 ? 1.0 : 2.0, fh = qp <= 0.5 ? 1.0 : 0.693147180559945309417;
@@ -332,50 +354,76 @@ __global__ __launch_bounds__(64) void prologue_kernel(const float* __restrict__ 
     tas = fa * k * sin(phL);
     thc = fh * k * cos(phL);
     ths = fh * k * sin(phL);
+    // deflection polynomials with q' folded in: coefficient j is c_j q'^(2j+1)
+    const double qp2 = qp * qp;
+    double pw = qp * qp2;
+    if (c.rmode == 3) {
+      for (int j = 1; j <= ATAN_UNIT_POLY_DEGREE; ++j, pw *= qp2) c.poly[j] = (float)(ATAN_UNIT_POLY_D[j] * pw);
+    } else {
+      for (int j = 1; j <= ATAN_SMALL_POLY_DEGREE; ++j, pw *= qp2) c.poly[j] = (float)(ATAN_SMALL_POLY_D[j] * pw);
+    }
+    if (c.rmode == 1) {
+      pw = qp * qp2;
+      for (int j = 1; j <= ATANH_POLY_DEGREE; ++j, pw *= qp2)
+        c.poly[ATAN_SMALL_POLY_DEGREE + j] = (float)(ATANH_POLY_D[j] * pw);
+    }
   }
-  c.tac = (float)tac;
-  c.tas = (float)tas;
-  c.thc = (float)thc;
-  c.ths = (float)ths;
-  {
-    const double Re = t[6], qh = t[8], ph = t[9];
-    const double a = sqrt(qh) / Re, b = 1.0 / (sqrt(qh) * Re), cs = cos(ph), sn = sin(ph);
-    c.h11 = (float)(a * cs);
-    c.h12 = (float)(a * sn);
-    c.h21 = (float)(-b * sn);
-    c.h22 = (float)(b * cs);
-  }
+  double f[32];
+  for (int k = 0; k < 32; ++k) f[k] = 0.0;
+  f[0] = cos(phL);
+  f[1] = sin(phL);
+  f[2] = q * q;
+  f[3] = 1.0 / q;
+  f[4] = qp;
   {
     const double Re = t[13], qs = t[15], ph = t[16];
     const double a = sqrt(qs) / Re, b = 1.0 / (sqrt(qs) * Re), cs = cos(ph), sn = sin(ph);
     const double s11 = a * cs, s12 = a * sn, s21 = -b * sn, s22 = b * cs;
-    c.s11 = (float)s11;
-    c.s12 = (float)s12;
-    c.s21 = (float)s21;
-    c.s22 = (float)s22;
     // the source frame of the lens equation in one step (float64 products, one rounding each)
     const double m11 = 1.0 - g1, m12 = -g2, m22 = 1.0 + g1;
-    c.A1 = (float)(s11 * m11 + s12 * m12);
-    c.A2 = (float)(s21 * m11 + s22 * m12);
-    c.B1 = (float)(s11 * m12 + s12 * m22);
-    c.B2 = (float)(s21 * m12 + s22 * m22);
-    c.C1 = (float)(-(s11 * xs + s12 * ys));
-    c.C2 = (float)(-(s21 * xs + s22 * ys));
-    c.cXt = (float)(-(s11 * tac + s12 * tas));
-    c.cXh = (float)(s11 * ths - s12 * thc);
-    c.cYt = (float)(-(s21 * tac + s22 * tas));
-    c.cYh = (float)(s21 * ths - s22 * thc);
+    f[5] = s11 * m11 + s12 * m12;            // A1
+    f[6] = s21 * m11 + s22 * m12;            // A2
+    f[7] = s11 * m12 + s12 * m22;            // B1
+    f[8] = s21 * m12 + s22 * m22;            // B2
+    f[9] = -(s11 * xs + s12 * ys);           // C1
+    f[10] = -(s21 * xs + s22 * ys);          // C2
+    f[11] = -(s11 * tac + s12 * tas);        // cXt
+    f[12] = s11 * ths - s12 * thc;           // cXh
+    f[13] = -(s21 * tac + s22 * tas);        // cYt
+    f[14] = s21 * ths - s22 * thc;           // cYh
+    f[23] = s11;
+    f[24] = s12;
+    f[25] = s21;
+    f[26] = s22;
+  }
+  {
+    // lens light about the origin: R^2/R_e^2 = X^2 + Y^2 = (ha x + hb y) x + hc y^2
+    const double Re = t[6], qh = t[8], ph = t[9];
+    const double a = sqrt(qh) / Re, b = 1.0 / (sqrt(qh) * Re), cs = cos(ph), sn = sin(ph);
+    const double h11 = a * cs, h12 = a * sn, h21 = -b * sn, h22 = b * cs;
+    f[15] = h11 * h11 + h21 * h21;           // ha
+    f[16] = 2.0 * (h11 * h12 + h21 * h22);   // hb
+    f[17] = h12 * h12 + h22 * h22;           // hc
+  }
+  f[18] = 0.5 / (double)t[7];                // he
+  f[19] = bh * LOG2E;                        // hB
+  f[20] = 0.5 / (double)t[14];               // se
+  f[21] = bs * LOG2E;                        // sB
+  f[22] = tac;
+  if (!valid) f[5] = f[6] = __builtin_nan("");
+  for (int v = 0; v < RENDER_VARIANTS; ++v) {
+    float* o = reinterpret_cast<float*>(&pcs[p].rv[v]);
+    for (int k = 0; k < 32; ++k) o[k] = dither_round(f[k], v);
   }
   c.hIlo = (float)(Ih - (double)c.hI);
   c.sIlo = (float)(Is - (double)c.sI);
-  for (int k = 0; k < 7; ++k) c.pad2[k] = 0.0f;
+  for (int k = 0; k < 22; ++k) c.pad[k] = 0.0f;
   if (!valid) {
     const float nan = __builtin_nanf("");
     c.m11 = c.m12 = c.m22 = nan;
     c.hI = c.sI = nan;
-    c.A1 = c.A2 = nan;
   }
-  pcs[p] = c;
+  static_cast<PointHead&>(pcs[p]) = c;   // the variants are already in place
   if (p64s) {
     PointConst64 e;
     e.cL = cos(phL);

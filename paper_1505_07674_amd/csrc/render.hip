@@ -16,24 +16,17 @@
 namespace lensed {
 namespace {
 
-template <int MODE>
-__device__ float pixel_sum_dispatch(const PointConst& c, int rule, int N, const PixelGeom& g, bool& cusp) {
+// Pixel sum of schedule class NC: the N x N midpoint rule with N = NC (1..8)
+// unrolled at compile time, or (NC = 0) a Gauss-Kronrod rule or a larger N.
+template <int NC, int MODE>
+__device__ __forceinline__ float pixel_sum_class(const PointConst& c, const RenderVariant& k, int rule, int N,
+                                                 const PixelGeom& g, bool& cusp) {
+  if (NC > 0) return pixel_sum<(NC > 0 ? NC : 1), MODE>(c, k, g, cusp);
   switch (rule) {
-    case 1: return pixel_sum_gk<7, MODE>(c, g, cusp);
-    case 2: return pixel_sum_gk<11, MODE>(c, g, cusp);
-    case 3: return pixel_sum_gk<15, MODE>(c, g, cusp);
-    default: break;
-  }
-  switch (N) {
-    case 1: return pixel_sum<1, MODE>(c, g, cusp);
-    case 2: return pixel_sum<2, MODE>(c, g, cusp);
-    case 3: return pixel_sum<3, MODE>(c, g, cusp);
-    case 4: return pixel_sum<4, MODE>(c, g, cusp);
-    case 5: return pixel_sum<5, MODE>(c, g, cusp);
-    case 6: return pixel_sum<6, MODE>(c, g, cusp);
-    case 7: return pixel_sum<7, MODE>(c, g, cusp);
-    case 8: return pixel_sum<8, MODE>(c, g, cusp);
-    default: return pixel_sum_rt<MODE>(c, N, g, cusp);
+    case 1: return pixel_sum_gk<7, MODE>(c, k, g, cusp);
+    case 2: return pixel_sum_gk<11, MODE>(c, k, g, cusp);
+    case 3: return pixel_sum_gk<15, MODE>(c, k, g, cusp);
+    default: return pixel_sum_rt<MODE>(c, k, N, g, cusp);
   }
 }
 
@@ -48,9 +41,12 @@ __device__ __forceinline__ void resolve_item(const WorkArgs& w, int& point, int&
   }
 }
 
-__device__ __forceinline__ PixelGeom pixel_geom(const SysDesc& sd, int pix) {
+// Geometry of pixel pix of an image, and the variant of the render constants
+// its subsamples use.
+__device__ __forceinline__ PixelGeom pixel_geom(const SysDesc& sd, int pix, int* variant = nullptr) {
   const int r = pix / sd.W;
   const int col = pix - r * sd.W;
+  if (variant) *variant = render_variant(r, col);
   PixelGeom g;
   g.ux = (float)col - 0.5f * (float)(sd.W - 1);
   g.uy = (float)r - 0.5f * (float)(sd.H - 1);
@@ -60,37 +56,71 @@ __device__ __forceinline__ PixelGeom pixel_geom(const SysDesc& sd, int pix) {
   return g;
 }
 
+// Appends a cusp-list entry for a wave with flagged lanes (lane l renders unit
+// unit0 + l; the entry covers pixel `half` of each unit).
+__device__ __forceinline__ void push_cusp(const CuspList& cl, bool flag, int point, int unit0, int ppt, int half) {
+  const unsigned long long mask = __ballot(flag);
+  if (mask != 0ull && (threadIdx.x & 63) == 0) {
+    const int slot = atomicAdd(cl.count, 1);
+    CuspEntry e;
+    e.point = point;
+    e.unit0 = unit0;
+    e.mask = mask;
+    e.ppt = ppt;
+    e.half = half;
+    cl.entries[slot] = e;
+  }
+}
+
+// One kernel per schedule class, so that the registers of the large rules do
+// not set the occupancy of the small ones. A thread renders one unit: PPT = 1
+// pixel, or PPT = 2 horizontally adjacent pixels (2j, 2j+1) of a row, which
+// share the row terms and the constants (only for midpoint classes and images
+// of even width, so that a pair never straddles two rows). Item (point, tile)
+// covers units tile * RENDER_BLOCK .. + RENDER_BLOCK - 1: consecutive pixels,
+// or, in a masked plan, consecutive entries of the system's unit list.
+template <int NC, int PPT>
 __global__ __launch_bounds__(RENDER_BLOCK) void render_kernel(WorkArgs w, const PointConst* __restrict__ pcs,
                                                                float* __restrict__ L, CuspList cl) {
   int point, tile;
   resolve_item(w, point, tile);
   const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[point] : 0] : w.single;
   const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
-  const int pix = tile * RENDER_BLOCK + (int)threadIdx.x;
-  const bool active = pix < sd.H * sd.W;
-  bool cusp = false;
+  const int unit = tile * RENDER_BLOCK + (int)threadIdx.x;
+  const bool active = unit < unit_count(sd, PPT);
+  bool cusp = false, cusp1 = false;
   if (active) {
-    const PixelGeom g = pixel_geom(sd, pix);
+    const int pix = unit_pixel(sd, unit, PPT);
+    int v;
+    const PixelGeom g = pixel_geom(sd, pix, &v);
     const PointConst& c = pcs[point];
-    float acc;
-    switch (c.rmode) {
-      case 0: acc = pixel_sum_dispatch<0>(c, sd.rule, sd.N, g, cusp); break;
-      case 1: acc = pixel_sum_dispatch<1>(c, sd.rule, sd.N, g, cusp); break;
-      case 2: acc = pixel_sum_dispatch<2>(c, sd.rule, sd.N, g, cusp); break;
-      default: acc = pixel_sum_dispatch<3>(c, sd.rule, sd.N, g, cusp); break;
+    const RenderVariant& k = c.rv[v];
+    if (PPT == 2 && NC > 0) {
+      constexpr int N = NC > 0 ? NC : 1;
+      float a0, a1;
+      switch (c.rmode) {
+        case 0: pixel_sum_pair<N, 0>(c, k, g, a0, a1, cusp, cusp1); break;
+        case 1: pixel_sum_pair<N, 1>(c, k, g, a0, a1, cusp, cusp1); break;
+        case 2: pixel_sum_pair<N, 2>(c, k, g, a0, a1, cusp, cusp1); break;
+        default: pixel_sum_pair<N, 3>(c, k, g, a0, a1, cusp, cusp1); break;
+      }
+      L[loff + pix] = (float)((double)a0 * sd.wgt);
+      L[loff + pix + 1] = (float)((double)a1 * sd.wgt);
+    } else {
+      float acc;
+      switch (c.rmode) {
+        case 0: acc = pixel_sum_class<NC, 0>(c, k, sd.rule, sd.N, g, cusp); break;
+        case 1: acc = pixel_sum_class<NC, 1>(c, k, sd.rule, sd.N, g, cusp); break;
+        case 2: acc = pixel_sum_class<NC, 2>(c, k, sd.rule, sd.N, g, cusp); break;
+        default: acc = pixel_sum_class<NC, 3>(c, k, sd.rule, sd.N, g, cusp); break;
+      }
+      L[loff + pix] = (float)((double)acc * sd.wgt);
     }
-    L[loff + pix] = (float)((double)acc * sd.wgt);
   }
-  // one list entry per wave that has pixels next to a cuspy source centre
-  const unsigned long long mask = __ballot(cusp);
-  if (mask != 0ull && (threadIdx.x & 63) == 0) {
-    const int slot = atomicAdd(cl.count, 1);
-    CuspEntry e;
-    e.point = point;
-    e.pix0 = pix;
-    e.mask = mask;
-    cl.entries[slot] = e;
-  }
+  // one list entry per wave (and pixel of a pair) that has pixels next to a cuspy source centre
+  const int unit0 = tile * RENDER_BLOCK + (int)(threadIdx.x & ~63u);
+  push_cusp(cl, cusp, point, unit0, PPT, 0);
+  if (PPT == 2) push_cusp(cl, cusp1, point, unit0, PPT, 1);
 }
 
 // Adds the float64 cusp corrections to the flagged pixels; a fixed grid of
@@ -134,9 +164,11 @@ __global__ __launch_bounds__(64 * CUSP_WAVES) void cusp_kernel(WorkArgs w, const
     const bool mine = (e.mask >> lane) & 1ull;
     const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[e.point] : 0] : w.single;
     const int64_t loff = w.point_loff ? w.point_loff[e.point] : 0;
-    const int pix = e.pix0 + lane;
-    const PixelGeom g = pixel_geom(sd, pix);
+    const int pix = mine ? unit_pixel(sd, e.unit0 + lane, e.ppt) + e.half : 0;
+    int v;
+    const PixelGeom g = pixel_geom(sd, pix, &v);
     const PointConst& c = pcs[e.point];
+    const RenderVariant& k = c.rv[v];
     const PointConst64& c64 = p64s[e.point];
     const GkRule* R = sd.rule > 0 ? &kGkRules[sd.rule - 1] : nullptr;
     const int N = sd.N, NN = N * N;
@@ -149,7 +181,7 @@ __global__ __launch_bounds__(64 * CUSP_WAVES) void cusp_kernel(WorkArgs w, const
         const int ky = (s0 + j) / N, kx = s0 + j - ky * N;
         float x, y;
         subsample_xy(R, N, kx, ky, g, x, y);
-        const bool within = mine && render_source_R2(c, x, y) < c.cusp_r2;
+        const bool within = mine && render_source_R2(c, k, x, y) < c.cusp_r2;
         dv[j * 64 + lane] = 0.0f;
         const unsigned long long b = __ballot(within);
         if (within) qu[qn + __popcll(b & ((1ull << lane) - 1ull))] = (unsigned short)(lane | (j << 6));
@@ -162,16 +194,18 @@ __global__ __launch_bounds__(64 * CUSP_WAVES) void cusp_kernel(WorkArgs w, const
           const int item = qu[q0 + lane];
           const int pl = item & 63, j = item >> 6;
           const int ky = (s0 + j) / N, kx = s0 + j - ky * N;
-          const PixelGeom gq = pixel_geom(sd, e.pix0 + pl);
+          int vq;
+          const PixelGeom gq = pixel_geom(sd, unit_pixel(sd, e.unit0 + pl, e.ppt) + e.half, &vq);
+          const RenderVariant& kq = c.rv[vq];
           float x, y;
           subsample_xy(R, N, kx, ky, gq, x, y);
-          const float sR2 = render_source_R2(c, x, y);
+          const float sR2 = render_source_R2(c, kq, x, y);
           const double ox = R ? R->xd[kx] : ((double)kx + 0.5) / N - 0.5;
           const double oy = R ? R->xd[ky] : ((double)ky + 0.5) / N - 0.5;
           float dx, dy;
           source_offset_f64(c64, gq, ox, oy, dx, dy);
-          const float exact = sersic_shape(source_R2(c, dx, dy), c.se, c.sB);
-          const float d = exact - sersic_shape(sR2, c.se, c.sB);
+          const float exact = sersic_shape(source_R2(kq, dx, dy), kq.se, kq.sB);
+          const float d = exact - sersic_shape(sR2, kq.se, kq.sB);
           dv[j * 64 + pl] = R ? R->w[kx] * R->w[ky] * d : d;
         }
       }
@@ -187,14 +221,14 @@ __global__ __launch_bounds__(64 * CUSP_WAVES) void cusp_kernel(WorkArgs w, const
 // per-pixel integration error estimate of a Gauss-Kronrod rule), float32
 // subsample values without the cusp re-tracing.
 template <int K>
-__device__ float rule_error_pixel(const PointConst& c, const PixelGeom& g) {
+__device__ float rule_error_pixel(const PointConst& c, const RenderVariant& kv, const PixelGeom& g) {
   bool cusp = false;
   float gauss = 0.0f, k = 0.0f;
   switch (c.rmode) {
-    case 0: k = pixel_sum_gk<K, 0, true>(c, g, cusp, &gauss); break;
-    case 1: k = pixel_sum_gk<K, 1, true>(c, g, cusp, &gauss); break;
-    case 2: k = pixel_sum_gk<K, 2, true>(c, g, cusp, &gauss); break;
-    default: k = pixel_sum_gk<K, 3, true>(c, g, cusp, &gauss); break;
+    case 0: k = pixel_sum_gk<K, 0, true>(c, kv, g, cusp, &gauss); break;
+    case 1: k = pixel_sum_gk<K, 1, true>(c, kv, g, cusp, &gauss); break;
+    case 2: k = pixel_sum_gk<K, 2, true>(c, kv, g, cusp, &gauss); break;
+    default: k = pixel_sum_gk<K, 3, true>(c, kv, g, cusp, &gauss); break;
   }
   return fabsf(k - gauss);
 }
@@ -204,13 +238,15 @@ __global__ __launch_bounds__(RENDER_BLOCK) void rule_error_kernel(WorkArgs w, co
   const SysDesc sd = w.single;
   const int pix = blockIdx.x * RENDER_BLOCK + (int)threadIdx.x;
   if (pix >= sd.H * sd.W) return;
-  const PixelGeom g = pixel_geom(sd, pix);
+  int v;
+  const PixelGeom g = pixel_geom(sd, pix, &v);
   const PointConst& c = pcs[w.point0];
+  const RenderVariant& k = c.rv[v];
   float e;
   switch (sd.rule) {
-    case 1: e = rule_error_pixel<7>(c, g); break;
-    case 2: e = rule_error_pixel<11>(c, g); break;
-    default: e = rule_error_pixel<15>(c, g); break;
+    case 1: e = rule_error_pixel<7>(c, k, g); break;
+    case 2: e = rule_error_pixel<11>(c, k, g); break;
+    default: e = rule_error_pixel<15>(c, k, g); break;
   }
   E[pix] = (float)((double)e * sd.wgt);
 }
@@ -280,20 +316,57 @@ hipError_t launch_compose(float* L, const int64_t* loff, const int* point_sys, c
   return hipGetLastError();
 }
 
-hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L, int n_blocks,
-                         const CuspList& cl, hipStream_t stream, hipEvent_t between) {
-  if (n_blocks <= 0) return hipSuccess;
-  hipError_t e = for_item_parts(w, n_blocks, [&](const WorkArgs& part, int n) {
-    hipLaunchKernelGGL(render_kernel, dim3(n), dim3(RENDER_BLOCK), 0, stream, part, pcs, L, cl);
-    return hipGetLastError();
-  });
-  if (e != hipSuccess) return e;
+int render_class(const SysDesc& sd) { return sd.rule == 0 && sd.N <= RENDER_MAX_CLASS ? sd.N : 0; }
+
+hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L,
+                         const RenderSpan* spans, int n_spans, const CuspList& cl, hipStream_t stream,
+                         hipEvent_t between) {
+  int n_waves = 0;   // cusp-list capacity: one entry per wave and pixel of a thread
+  for (int i = 0; i < n_spans; ++i) n_waves += spans[i].count * (RENDER_BLOCK / 64) * (spans[i].ppt == 2 ? 2 : 1);
+  if (n_waves <= 0) return hipSuccess;
+  for (int i = 0; i < n_spans; ++i) {
+    if (spans[i].count <= 0) continue;
+    WorkArgs ws = w;
+    if (ws.items) ws.items += spans[i].offset;
+    const bool pair = spans[i].ppt == 2 && spans[i].klass > 0;
+    hipError_t e = for_item_parts(ws, spans[i].count, [&](const WorkArgs& part, int n) {
+      switch (spans[i].klass) {
+#define LENSED_RENDER_CLASS(NC)                                                                                     \
+  case NC:                                                                                                          \
+    if (pair)                                                                                                       \
+      hipLaunchKernelGGL((render_kernel<NC, 2>), dim3(n), dim3(RENDER_BLOCK), 0, stream, part, pcs, L, cl);         \
+    else                                                                                                            \
+      hipLaunchKernelGGL((render_kernel<NC, 1>), dim3(n), dim3(RENDER_BLOCK), 0, stream, part, pcs, L, cl);         \
+    break;
+        LENSED_RENDER_CLASS(1)
+        LENSED_RENDER_CLASS(2)
+        LENSED_RENDER_CLASS(3)
+        LENSED_RENDER_CLASS(4)
+        LENSED_RENDER_CLASS(5)
+        LENSED_RENDER_CLASS(6)
+        LENSED_RENDER_CLASS(7)
+        LENSED_RENDER_CLASS(8)
+#undef LENSED_RENDER_CLASS
+        default:
+          hipLaunchKernelGGL((render_kernel<0, 1>), dim3(n), dim3(RENDER_BLOCK), 0, stream, part, pcs, L, cl);
+          break;
+      }
+      return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e;
   if (between && (e = hipEventRecord(between, stream)) != hipSuccess) return e;
-  const int waves = n_blocks * (RENDER_BLOCK / 64);   // list capacity
-  int grid = (waves + CUSP_WAVES - 1) / CUSP_WAVES;
+  int grid = (n_waves + CUSP_WAVES - 1) / CUSP_WAVES;
   if (grid > CUSP_BLOCKS) grid = CUSP_BLOCKS;
   hipLaunchKernelGGL(cusp_kernel, dim3(grid), dim3(64 * CUSP_WAVES), 0, stream, w, pcs, p64s, L, cl);
   return hipGetLastError();
+}
+
+hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L, int n_blocks,
+                         const CuspList& cl, hipStream_t stream, hipEvent_t between) {
+  const RenderSpan span{render_class(w.single), 1, 0, n_blocks};
+  return launch_render(w, pcs, p64s, L, &span, 1, cl, stream, between);
 }
 
 }  // namespace lensed

@@ -85,42 +85,54 @@ __device__ __forceinline__ void source_offset_f64(const PointConst64& e, const P
 }
 
 // ---------------------------------------------------------------------------
-// Forward render, float32, with the folded constants of PointConst (rmode,
-// tac, h11..h22, s11..s22, A1..cYh). Every product and sum is written out
-// with explicit fmaf so that the render kernel and the cusp correction, which
-// must reproduce the render's float32 value of a subsample, round identically.
+// Forward render, float32, with the folded constants: the uniform part of
+// PointConst (mode, polynomial coefficients, amplitudes, cusp radius) and the
+// pixel's RenderVariant k. Every product and sum is written out with explicit
+// fmaf so that the render kernel and the cusp correction, which must reproduce
+// the render's float32 value of a subsample, round identically.
 // ---------------------------------------------------------------------------
 
 // Terms of the subsample grid that depend on the row (y) only.
 constexpr float SIE_TINY = 1e-30f;
 
 struct RowTerms {
-  float y, y2t;       // y and y^2 + SIE_TINY (sphere)
+  float y2t;          // sphere: y^2 + SIE_TINY
   float sLy, cLy;     // SIE frame: x' = cL x + sL y, y' = cL y - sL x
   float rX, rY;       // B1 y + C1, B2 y + C2: row part of the source frame of beta
   float s12y, s22y;   // sphere: s12 y, s22 y
-  float hx, hy;       // lens-light frame: h12 y, h22 y
+  float hby, hcy2;    // lens light: hb y, hc y^2
 };
 
-__device__ __forceinline__ RowTerms row_terms(const PointConst& c, float y) {
+__device__ __forceinline__ RowTerms row_terms(const RenderVariant& k, float y) {
   RowTerms r;
-  r.y = y;
   r.y2t = fmaf(y, y, SIE_TINY);
-  r.sLy = c.sL * y;
-  r.cLy = c.cL * y;
-  r.rX = fmaf(c.B1, y, c.C1);
-  r.rY = fmaf(c.B2, y, c.C2);
-  r.s12y = c.s12 * y;
-  r.s22y = c.s22 * y;
-  r.hx = c.h12 * y;
-  r.hy = c.h22 * y;
+  r.sLy = k.sL * y;
+  r.cLy = k.cL * y;
+  r.rX = fmaf(k.B1, y, k.C1);
+  r.rY = fmaf(k.B2, y, k.C2);
+  r.s12y = k.s12 * y;
+  r.s22y = k.s22 * y;
+  r.hby = k.hb * y;
+  r.hcy2 = k.hc * y * y;
   return r;
+}
+
+// p0 + s (c[1] + s (c[2] + ... + s c[D])): a deflection polynomial with q'
+// folded into its coefficients (uniform c[1..D], per-variant leading p0 = q').
+template <int D>
+__device__ __forceinline__ float folded_poly(const float* c, float p0, float s) {
+  float p = c[D];
+#pragma unroll
+  for (int j = D - 1; j >= 1; --j) p = fmaf(p, s, c[j]);
+  return fmaf(p, s, p0);
 }
 
 // Source-frame coordinates (X, Y) of beta - (x_S, y_S), (R/R_e)^2 = X^2 + Y^2,
 // for the image-plane subsample (x, row y): Eq. 1 with the SIE + external shear,
 // the shear matrix, the source centre and the source ellipse folded into
-// per-point constants.
+// per-point constants. The polynomials take w = x'/psi (mode 1) or
+// w = x'/(psi + r) (modes 2, 3) and return the folded atan (and atanh)
+// directly: atan(q' w) = w P(w^2) with P's coefficients c_k q'^(2k+1).
 //
 // The lens centre needs no branch: x'^2 carries SIE_TINY (arcsec^2), so that at
 // x' = y' = 0 exactly psi = q sqrt(SIE_TINY), r = sqrt(SIE_TINY), the atan argument
@@ -129,41 +141,44 @@ __device__ __forceinline__ RowTerms row_terms(const PointConst& c, float y) {
 // the offset changes x'^2 by a relative 1e-30 / x'^2, below float32 resolution
 // for any |x'| above 1e-11 arcsec.
 template <int RM>
-__device__ __forceinline__ void source_frame(const PointConst& c, const RowTerms& r, float x, float& X, float& Y) {
-  const float lX = fmaf(c.A1, x, r.rX);
-  const float lY = fmaf(c.A2, x, r.rY);
+__device__ __forceinline__ void source_frame(const PointConst& c, const RenderVariant& k, const RowTerms& r, float x,
+                                             float& X, float& Y) {
+  const float lX = fmaf(k.A1, x, r.rX);
+  const float lY = fmaf(k.A2, x, r.rY);
   if (RM == 0) {
-    const float s = c.tac * hw_rsq(fmaf(x, x, r.y2t));   // alpha = s (x, y)
-    X = fmaf(-s, fmaf(c.s11, x, r.s12y), lX);
-    Y = fmaf(-s, fmaf(c.s21, x, r.s22y), lY);
+    const float s = k.tac * hw_rsq(fmaf(x, x, r.y2t));   // alpha = s (x, y)
+    X = fmaf(-s, fmaf(k.s11, x, r.s12y), lX);
+    Y = fmaf(-s, fmaf(k.s21, x, r.s22y), lY);
     return;
   }
-  const float xp = fmaf(c.cL, x, r.sLy);
-  const float yp = fmaf(-c.sL, x, r.cLy);
+  const float xp = fmaf(k.cL, x, r.sLy);
+  const float yp = fmaf(-k.sL, x, r.cLy);
   const float yp2 = yp * yp;
   const float x2t = fmaf(xp, xp, SIE_TINY);
-  const float psi2 = fmaf(c.q2, x2t, yp2);
+  const float psi2 = fmaf(k.q2, x2t, yp2);
   float At, Ah;
   if (RM == 1) {
-    const float tq = c.qp * hw_rsq(psi2);
-    At = atan_small(tq * xp);
-    Ah = atanh_poly(tq * yp);
+    const float ip = hw_rsq(psi2);
+    const float w1 = ip * xp, w2 = ip * yp;
+    At = w1 * folded_poly<ATAN_SMALL_POLY_DEGREE>(c.poly, k.qp, w1 * w1);
+    Ah = w2 * folded_poly<ATANH_POLY_DEGREE>(c.poly + ATAN_SMALL_POLY_DEGREE, k.qp, w2 * w2);
   } else {
     const float r2 = x2t + yp2;
     const float psi = __builtin_amdgcn_sqrtf(psi2);
     const float ir = hw_rsq(r2);
-    const float u = c.qp * xp * hw_rcp(fmaf(r2, ir, psi));
-    At = RM == 2 ? atan_small(u) : atan_unit(u);
-    Ah = copysignf(hw_log2(fmaf(c.qp, fabsf(yp), psi) * ir * c.iq), yp);
+    const float w = xp * hw_rcp(fmaf(r2, ir, psi));
+    At = RM == 2 ? w * folded_poly<ATAN_SMALL_POLY_DEGREE>(c.poly, k.qp, w * w)
+                 : w * folded_poly<ATAN_UNIT_POLY_DEGREE>(c.poly, k.qp, w * w);
+    Ah = copysignf(hw_log2(fmaf(k.qp, fabsf(yp), psi) * ir * k.iq), yp);
   }
-  X = fmaf(c.cXt, At, fmaf(c.cXh, Ah, lX));
-  Y = fmaf(c.cYt, At, fmaf(c.cYh, Ah, lY));
+  X = fmaf(k.cXt, At, fmaf(k.cXh, Ah, lX));
+  Y = fmaf(k.cYt, At, fmaf(k.cYh, Ah, lY));
 }
 
 // (R/R_e)^2 of the source at offset (dx, dy) from its centre.
-__device__ __forceinline__ float source_R2(const PointConst& c, float dx, float dy) {
-  const float X = fmaf(c.s11, dx, c.s12 * dy);
-  const float Y = fmaf(c.s21, dx, c.s22 * dy);
+__device__ __forceinline__ float source_R2(const RenderVariant& k, float dx, float dy) {
+  const float X = fmaf(k.s11, dx, k.s12 * dy);
+  const float Y = fmaf(k.s21, dx, k.s22 * dy);
   return fmaf(X, X, Y * Y);
 }
 
@@ -175,16 +190,14 @@ __device__ __forceinline__ float sersic_shape(float R2, float e, float B) {
 
 // Lens-light and source shapes at one subsample, and the cusp flag.
 template <int RM>
-__device__ __forceinline__ void subsample_light(const PointConst& c, const RowTerms& r, float x, float& h, float& s,
-                                                bool& cusp) {
-  const float X = fmaf(c.h11, x, r.hx);
-  const float Y = fmaf(c.h21, x, r.hy);
-  h = sersic_shape(fmaf(X, X, Y * Y), c.he, c.hB);
+__device__ __forceinline__ void subsample_light(const PointConst& c, const RenderVariant& k, const RowTerms& r,
+                                                float x, float& h, float& s, bool& cusp) {
+  h = sersic_shape(fmaf(fmaf(k.ha, x, r.hby), x, r.hcy2), k.he, k.hB);
   float sX, sY;
-  source_frame<RM>(c, r, x, sX, sY);
+  source_frame<RM>(c, k, r, x, sX, sY);
   const float sR2 = fmaf(sX, sX, sY * sY);
   cusp = cusp || (sR2 < c.cusp_r2);
-  s = sersic_shape(sR2, c.se, c.sB);
+  s = sersic_shape(sR2, k.se, k.sB);
 }
 
 // Lens-light and source sums times their amplitudes, the low parts first (they
@@ -196,33 +209,77 @@ __device__ __forceinline__ float amplitudes(const PointConst& c, float sh, float
 
 // Sum of the surface brightness over the N x N midpoint abscissae of a pixel.
 template <int N, int RM>
-__device__ __forceinline__ float pixel_sum(const PointConst& c, const PixelGeom& g, bool& cusp) {
+__device__ __forceinline__ float pixel_sum(const PointConst& c, const RenderVariant& k, const PixelGeom& g,
+                                           bool& cusp) {
   float sh = 0.0f, ss = 0.0f;
   float xs[N];
 #pragma unroll
   for (int kx = 0; kx < N; ++kx) xs[kx] = fmaf(g.ux + sub_offset<N>(kx), g.d, g.cx);
 #pragma unroll
   for (int ky = 0; ky < N; ++ky) {
-    const RowTerms r = row_terms(c, fmaf(g.uy + sub_offset<N>(ky), g.d, g.cy));
+    const RowTerms r = row_terms(k, fmaf(g.uy + sub_offset<N>(ky), g.d, g.cy));
 #pragma unroll
     for (int kx = 0; kx < N; ++kx) {
       float h, s;
-      subsample_light<RM>(c, r, xs[kx], h, s, cusp);
-      sh += h;
-      ss += s;
+      subsample_light<RM>(c, k, r, xs[kx], h, s, cusp);
+      if (ky == 0 && kx == 0) {
+        sh = h;
+        ss = s;
+      } else {
+        sh += h;
+        ss += s;
+      }
     }
   }
   return amplitudes(c, sh, ss);
 }
 
+// The same for two horizontally adjacent pixels of one row (the second one
+// pixel to the right): the row terms are computed once for both.
+template <int N, int RM>
+__device__ __forceinline__ void pixel_sum_pair(const PointConst& c, const RenderVariant& k, const PixelGeom& g,
+                                               float& acc0, float& acc1, bool& cusp0, bool& cusp1) {
+  float sh0 = 0.0f, ss0 = 0.0f, sh1 = 0.0f, ss1 = 0.0f;
+  float xs0[N], xs1[N];
+#pragma unroll
+  for (int kx = 0; kx < N; ++kx) {
+    xs0[kx] = fmaf(g.ux + sub_offset<N>(kx), g.d, g.cx);
+    xs1[kx] = fmaf((g.ux + 1.0f) + sub_offset<N>(kx), g.d, g.cx);
+  }
+#pragma unroll
+  for (int ky = 0; ky < N; ++ky) {
+    const RowTerms r = row_terms(k, fmaf(g.uy + sub_offset<N>(ky), g.d, g.cy));
+#pragma unroll
+    for (int kx = 0; kx < N; ++kx) {
+      float h0, s0, h1, s1;
+      subsample_light<RM>(c, k, r, xs0[kx], h0, s0, cusp0);
+      subsample_light<RM>(c, k, r, xs1[kx], h1, s1, cusp1);
+      if (ky == 0 && kx == 0) {
+        sh0 = h0;
+        ss0 = s0;
+        sh1 = h1;
+        ss1 = s1;
+      } else {
+        sh0 += h0;
+        ss0 += s0;
+        sh1 += h1;
+        ss1 += s1;
+      }
+    }
+  }
+  acc0 = amplitudes(c, sh0, ss0);
+  acc1 = amplitudes(c, sh1, ss1);
+}
+
 template <int RM>
-__device__ __forceinline__ float pixel_sum_rt(const PointConst& c, int N, const PixelGeom& g, bool& cusp) {
+__device__ __forceinline__ float pixel_sum_rt(const PointConst& c, const RenderVariant& k, int N, const PixelGeom& g,
+                                              bool& cusp) {
   float sh = 0.0f, ss = 0.0f;
   for (int ky = 0; ky < N; ++ky) {
-    const RowTerms r = row_terms(c, fmaf(g.uy + sub_offset_rt(ky, N), g.d, g.cy));
+    const RowTerms r = row_terms(k, fmaf(g.uy + sub_offset_rt(ky, N), g.d, g.cy));
     for (int kx = 0; kx < N; ++kx) {
       float h, s;
-      subsample_light<RM>(c, r, fmaf(g.ux + sub_offset_rt(kx, N), g.d, g.cx), h, s, cusp);
+      subsample_light<RM>(c, k, r, fmaf(g.ux + sub_offset_rt(kx, N), g.d, g.cx), h, s, cusp);
       sh += h;
       ss += s;
     }
@@ -231,14 +288,14 @@ __device__ __forceinline__ float pixel_sum_rt(const PointConst& c, int N, const 
 }
 
 // (R/R_e)^2 of the source seen by the float32 render at subsample (x, y).
-__device__ __forceinline__ float render_source_R2(const PointConst& c, float x, float y) {
-  const RowTerms r = row_terms(c, y);
+__device__ __forceinline__ float render_source_R2(const PointConst& c, const RenderVariant& k, float x, float y) {
+  const RowTerms r = row_terms(k, y);
   float X, Y;
   switch (c.rmode) {
-    case 0: source_frame<0>(c, r, x, X, Y); break;
-    case 1: source_frame<1>(c, r, x, X, Y); break;
-    case 2: source_frame<2>(c, r, x, X, Y); break;
-    default: source_frame<3>(c, r, x, X, Y); break;
+    case 0: source_frame<0>(c, k, r, x, X, Y); break;
+    case 1: source_frame<1>(c, k, r, x, X, Y); break;
+    case 2: source_frame<2>(c, k, r, x, X, Y); break;
+    default: source_frame<3>(c, k, r, x, X, Y); break;
   }
   return fmaf(X, X, Y * Y);
 }
@@ -268,8 +325,8 @@ static __constant__ GkRule kGkRules[3] = {
 // Kronrod-weighted sum over the K x K nodes of a pixel (rows rolled, columns
 // unrolled); with ERR also the embedded Gauss sum, returned in gauss.
 template <int K, int RM, bool ERR = false>
-__device__ __forceinline__ float pixel_sum_gk(const PointConst& c, const PixelGeom& g, bool& cusp,
-                                              float* gauss = nullptr) {
+__device__ __forceinline__ float pixel_sum_gk(const PointConst& c, const RenderVariant& kv, const PixelGeom& g,
+                                              bool& cusp, float* gauss = nullptr) {
   const GkRule& R = kGkRules[(K - 7) / 4];
   float xs[K];
 #pragma unroll
@@ -277,12 +334,12 @@ __device__ __forceinline__ float pixel_sum_gk(const PointConst& c, const PixelGe
   float sh = 0.0f, ss = 0.0f, gh = 0.0f, gs = 0.0f;
 #pragma unroll 1
   for (int ky = 0; ky < K; ++ky) {
-    const RowTerms r = row_terms(c, fmaf(g.uy + R.x[ky], g.d, g.cy));
+    const RowTerms r = row_terms(kv, fmaf(g.uy + R.x[ky], g.d, g.cy));
     float rh = 0.0f, rs = 0.0f, qh = 0.0f, qs = 0.0f;
 #pragma unroll
     for (int kx = 0; kx < K; ++kx) {
       float h, s;
-      subsample_light<RM>(c, r, xs[kx], h, s, cusp);
+      subsample_light<RM>(c, kv, r, xs[kx], h, s, cusp);
       rh = fmaf(R.w[kx], h, rh);
       rs = fmaf(R.w[kx], s, rs);
       if (ERR) {

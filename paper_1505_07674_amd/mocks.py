@@ -206,3 +206,38 @@ def make_observation(spec: SystemSpec, render_noiseless: Callable[[np.ndarray], 
     data = (model + sigma * eps).astype(np.float32)
     weight = np.where(spec.mask, 1.0 / (sigma * sigma), 0.0).astype(np.float32)
     return Observation(spec, data, weight, sigma)
+
+
+# General model of Sec. 5 (a lens with a companion): two SIEs with free centres,
+# an external shear, two host components, the companion's light, a lensed
+# source and a flat sky: 41 parameters, layout of lensed_model (per SIE
+# x, y, theta_E, q, phi; shear gamma, phi; per Sersic x, y, I_e, R_e, n, q, phi;
+# sky). Planes: three foreground components, then the lensed source.
+GENERAL_41_PLANES = ["foreground", "foreground", "foreground", "lensed"]
+
+
+def general_model_points(n: int, seed: int) -> np.ndarray:
+    """n parameter points (float32 [n, 41]) of the companion model, uniform in
+    ranges around a main lens of theta_E ~ 1.1 arcsec and a companion 0.6-1.0
+    arcsec away."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for _ in range(n):
+        p = [rng.uniform(-0.05, 0.05), rng.uniform(-0.05, 0.05), rng.uniform(0.9, 1.3), rng.uniform(0.5, 1.0),
+             rng.uniform(0, math.pi)]                                              # main SIE
+        a = rng.uniform(0, 2 * math.pi)
+        r = rng.uniform(0.6, 1.0)
+        cx, cy = r * math.cos(a), r * math.sin(a)
+        p += [cx, cy, rng.uniform(0.1, 0.4), rng.uniform(0.6, 1.0), rng.uniform(0, math.pi)]   # companion SIE
+        p += [rng.uniform(0, 0.08), rng.uniform(0, math.pi)]                                  # shear
+        p += [p[0], p[1], rng.uniform(0.05, 0.2), rng.uniform(0.5, 1.5), rng.uniform(2, 5), rng.uniform(0.6, 1),
+              rng.uniform(0, math.pi)]                                                         # host, extended
+        p += [p[0], p[1], rng.uniform(0.2, 0.6), rng.uniform(0.1, 0.3), rng.uniform(0.5, 1.5), rng.uniform(0.6, 1),
+              rng.uniform(0, math.pi)]                                                         # host, compact
+        p += [cx, cy, rng.uniform(0.05, 0.2), rng.uniform(0.1, 0.4), rng.uniform(1, 4), rng.uniform(0.6, 1),
+              rng.uniform(0, math.pi)]                                                         # companion light
+        p += [rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), rng.uniform(0.5, 2), rng.uniform(0.05, 0.4),
+              rng.uniform(0.5, 4), rng.uniform(0.3, 1), rng.uniform(0, math.pi)]               # source
+        p += [rng.uniform(0.0, 0.5)]                                                           # sky
+        rows.append(p)
+    return np.array(rows, np.float32)

@@ -393,16 +393,20 @@ class ScreenExperiment:
             self._sur = (sur, fit)
         return self._sur
 
+    def _make_screen(self, sur, seed):
+        ra, _ = self.plain()
+        return SurrogateScreen(
+            sur, sigmas=self.sigmas, pool=(ra.evaluated_u, ra.evaluated_logl) if self.local else None,
+            seed=seed, refit_every=self.refit_every, refit_steps=self.refit_steps,
+            band_min=self.band_min, floor=self.floor, trust_sigmas=self.trust_sigmas, quantile=self.quantile,
+            safety=self.safety, refit_batch=self.refit_batch)
+
     def screened(self):
         """Run C, screened by the network (refitted locally when ``local``)."""
         if "c" not in self._runs:
             ra, _ = self.plain()
             sur, _ = self.surrogate()
-            self._screen = SurrogateScreen(
-                sur, sigmas=self.sigmas, pool=(ra.evaluated_u, ra.evaluated_logl) if self.local else None,
-                seed=self.seeds[2], refit_every=self.refit_every, refit_steps=self.refit_steps,
-                band_min=self.band_min, floor=self.floor, trust_sigmas=self.trust_sigmas, quantile=self.quantile,
-                safety=self.safety, refit_batch=self.refit_batch)
+            self._screen = self._make_screen(sur, self.seeds[2])
             self.log(f"screened run C, seed {self.seeds[2]}" +
                      (f" (network refitted locally every {self.refit_every} iterations)" if self.local else ""))
             rc, wc = self._runs["c"] = self._run("screened_c", self.seeds[2], screen=self._screen,
@@ -446,6 +450,61 @@ class ScreenExperiment:
         return out
 
 
+    def study(self, null_seeds, screened_seeds) -> dict:
+        """The sampler's own spread and the screen's effect over several seeds.
+
+        Plain runs with ``null_seeds`` give the null: how far a plain posterior
+        mean lands from run A's by sampling noise alone. Screened runs with
+        ``screened_seeds`` each start from the same network trained on run A's
+        pairs (refits are undone between runs). Shifts are |mean - mean_A| in
+        units of run A's posterior sigma, per parameter; each run is summarised
+        by its largest shift. The render ratio of a screened run is the mean
+        exact renders per accepted point of all plain runs (A and the nulls)
+        over its own."""
+        ra, wa = self.plain()
+        sur, fit = self.surrogate()
+        snap = sur.snapshot()
+        ll = self.ll
+        to_theta = lambda u: ll.theta(u)[:, ll.free].astype(np.float64)
+        ma, sa = ra.posterior_moments(to_theta)
+
+        def shifts(r):
+            m, _ = r.posterior_moments(to_theta)
+            return np.abs(m - ma) / sa
+
+        nulls, screened = [], []
+        for sd in null_seeds:
+            self.log(f"plain run, seed {sd}")
+            r, w = self._run(f"plain_s{sd}", sd)
+            d = shifts(r)
+            nulls.append(dict(_summary(r, w), seed=sd, shift_sigma=d.tolist(), max_shift_sigma=float(d.max())))
+            self.log(f"  {r.n_exact} exact, log Z {r.logz:.2f}, largest shift {d.max():.3f} sigma, {w:.0f} s")
+        plain_rpa = float(np.mean([ra.renders_per_accepted] + [n["renders_per_accepted"] for n in nulls]))
+        for sd in screened_seeds:
+            sur.restore(snap)
+            screen = self._make_screen(sur, sd)
+            self.log(f"screened run, seed {sd}")
+            r, w = self._run(f"screened_s{sd}", sd, screen=screen, fn=_Observed(self.ll, screen))
+            d = shifts(r)
+            screened.append(dict(_summary(r, w), seed=sd, shift_sigma=d.tolist(), max_shift_sigma=float(d.max()),
+                                 renders_per_accepted_ratio=plain_rpa / r.renders_per_accepted))
+            self.log(f"  {r.n_exact} exact, ratio {plain_rpa / r.renders_per_accepted:.2f}, log Z {r.logz:.2f}, "
+                     f"largest shift {d.max():.3f} sigma, {w:.0f} s")
+        sur.restore(snap)
+        null_max = [n["max_shift_sigma"] for n in nulls]
+        scr_max = [c["max_shift_sigma"] for c in screened]
+        ratios = [c["renders_per_accepted_ratio"] for c in screened]
+        return {"system": self.spec.name, "n_live": self.n_live, "k_replace": self.k_replace, "ndim": self.ndim,
+                "plain_a": dict(_summary(ra, wa), seed=self.seeds[0]), "fit": fit,
+                "plain_renders_per_accepted_mean": plain_rpa, "null": nulls, "screened": screened,
+                "null_max_shift_sigma": null_max, "screened_max_shift_sigma": scr_max,
+                "renders_per_accepted_ratio": ratios, "ratio_mean": float(np.mean(ratios)) if ratios else None,
+                "settings": {"sigmas": self.sigmas, "trust_sigmas": self.trust_sigmas, "quantile": self.quantile,
+                             "safety": self.safety, "floor": self.floor, "refit_every": self.refit_every,
+                             "refit_steps": self.refit_steps, "refit_batch": self.refit_batch,
+                             "band_min": self.band_min, "local": self.local}}
+
+
 def compare_runs(spec: SystemSpec, obs: Observation, device: torch.device, null: bool = True, **settings) -> dict:
     """The whole experiment in one call (ScreenExperiment's settings as keywords)."""
     return ScreenExperiment(spec, obs, device, **settings).summary(null=null)
@@ -487,6 +546,10 @@ def main(argv=None) -> int:
     ap.add_argument("--state-dir", default=None, help="save finished runs and checkpoints here; resume from it")
     ap.add_argument("--time-limit", type=float, default=None, help="seconds before the running stage is suspended")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--null-seeds", type=int, nargs="*", default=None,
+                    help="seed study: plain runs with these seeds (the null spread about run A)")
+    ap.add_argument("--screened-seeds", type=int, nargs="*", default=None,
+                    help="seed study: screened runs with these seeds, each from the network trained on run A")
     a = ap.parse_args(argv)
     if not torch.cuda.is_available():
         print("a GPU is required", file=sys.stderr)
@@ -498,13 +561,16 @@ def main(argv=None) -> int:
     if a.state_dir:
         os.makedirs(a.state_dir, exist_ok=True)
     deadline = time.monotonic() + a.time_limit if a.time_limit else None
+    settings = dict(n_live=a.n_live, k_replace=a.k_replace, train_epochs=a.epochs, sigmas=a.sigmas,
+                    max_iter=a.max_iter, seeds=(mocks.C4_SEED, mocks.C4_SEED + 1, mocks.C4_SEED + 2), log=log,
+                    audit=a.audit, state_dir=a.state_dir, deadline=deadline, trust_sigmas=a.trust_sigmas,
+                    refit_every=a.refit_every, refit_steps=a.refit_steps, quantile=a.quantile, safety=a.safety,
+                    refit_batch=a.refit_batch)
     try:
-        res = compare_runs(spec, obs, dev, n_live=a.n_live, k_replace=a.k_replace, train_epochs=a.epochs,
-                           sigmas=a.sigmas, max_iter=a.max_iter, seeds=(mocks.C4_SEED, mocks.C4_SEED + 1,
-                                                                        mocks.C4_SEED + 2), log=log,
-                           audit=a.audit, state_dir=a.state_dir, deadline=deadline, trust_sigmas=a.trust_sigmas,
-                           refit_every=a.refit_every, refit_steps=a.refit_steps, quantile=a.quantile,
-                           safety=a.safety, refit_batch=a.refit_batch)
+        if a.null_seeds is not None or a.screened_seeds is not None:
+            res = ScreenExperiment(spec, obs, dev, **settings).study(a.null_seeds or [], a.screened_seeds or [])
+        else:
+            res = compare_runs(spec, obs, dev, **settings)
     except Suspended as e:
         print(f"suspended: {e}", flush=True)
         return 3

@@ -188,6 +188,22 @@ class Surrogate:
         window = res[lo:hi] if hi > lo else res
         return max(sigmas * float(np.sqrt(np.mean(window ** 2))), floor)
 
+    def snapshot(self) -> dict:
+        """An in-memory copy of the trained state (weights, maps, calibration)."""
+        return {"params": self.params.clone(), "norm": None if self.norm is None else self.norm.clone(),
+                "l_ref": self.l_ref, "mu": self.mu.copy(), "P": self.P.copy(),
+                "margin_table": None if self.margin_table is None else tuple(a.copy() for a in self.margin_table),
+                "history": list(self.history)}
+
+    def restore(self, snap: dict) -> None:
+        """Back to a snapshot (so that several screened runs start from the same network)."""
+        self.params = snap["params"].clone()
+        self.norm = None if snap["norm"] is None else snap["norm"].clone()
+        self.l_ref = snap["l_ref"]
+        self.mu, self.P = snap["mu"].copy(), snap["P"].copy()
+        self.margin_table = None if snap["margin_table"] is None else tuple(a.copy() for a in snap["margin_table"])
+        self.history = list(snap["history"])
+
     def save(self, path: str, fit: dict) -> None:
         """Weights, normalisation, reference log L, calibration table and fit summary (npz)."""
         import json

@@ -41,10 +41,12 @@ def oracle_grads(osys, pts):
 
 
 def check(spec, obs, pts, tol=1e-4, truth_rows=()):
-    """Gradient bar at every point; the log L bar against the oracle away from the
-    truth rows (on a ~1e3-pixel image the float32 model noise at the truth, about
-    2 sqrt(N_w) |dL*/sigma|, reaches the N_w/2 x 1e-6 floor), and everywhere the
-    log L of the gradient plan equals the batched log L of the same points."""
+    """Gradient bar at every point (1e-3 at the truth rows, where the gradient is
+    noise-driven; see the module docstring); the log L bar against the oracle
+    away from the truth rows (on a ~1e3-pixel image the float32 model noise at
+    the truth, about 2 sqrt(N_w) |dL*/sigma|, reaches the N_w/2 x 1e-6 floor),
+    and everywhere the log L of the gradient plan equals the batched log L of
+    the same points."""
     gsys = gpu_system(spec, obs)
     tp = torch.from_numpy(np.ascontiguousarray(pts)).to(DEV)
     ll, g = lensed.loglike_grad(tp, gsys)
@@ -55,9 +57,13 @@ def check(spec, obs, pts, tol=1e-4, truth_rows=()):
     far = np.setdiff1d(np.arange(len(pts)), truth_rows)
     assert np.all(np.abs(ll[far] - rll[far]) <= loglike_tolerance(rll[far], obs.weight))
     rel = np.linalg.norm(g - rg, axis=1) / np.linalg.norm(rg, axis=1)
-    worst = int(np.argmax(rel))
-    assert rel.max() <= tol, (f"worst relative gradient error {rel.max():.3e} at point {worst}: "
-                              f"gpu {g[worst]} oracle {rg[worst]}")
+    bar = np.full(len(pts), tol)
+    bar[list(truth_rows)] = 1e-3
+    say(f"  relative gradient error: worst {rel[far].max():.2e} away from the truth"
+        + (f", {rel[list(truth_rows)].max():.2e} at the truth" if len(truth_rows) else ""))
+    worst = int(np.argmax(rel / bar))
+    assert np.all(rel <= bar), (f"relative gradient error {rel[worst]:.3e} at point {worst} (bar {bar[worst]:.0e}): "
+                                f"gpu {g[worst]} oracle {rg[worst]}")
     return rel
 
 
