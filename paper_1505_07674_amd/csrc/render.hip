@@ -80,7 +80,7 @@ __device__ __forceinline__ void push_cusp(const CuspList& cl, bool flag, int poi
 // covers units tile * RENDER_BLOCK .. + RENDER_BLOCK - 1: consecutive pixels,
 // or, in a masked plan, consecutive entries of the system's unit list.
 template <int NC, int PPT>
-__global__ __launch_bounds__(RENDER_BLOCK) void render_kernel(WorkArgs w, const PointConst* __restrict__ pcs,
+__global__ __launch_bounds__(RENDER_BLOCK, NC > 0 && NC <= 4 ? 8 : 1) void render_kernel(WorkArgs w, const PointConst* __restrict__ pcs,
                                                                float* __restrict__ L, CuspList cl) {
   int point, tile;
   resolve_item(w, point, tile);
@@ -126,11 +126,12 @@ __global__ __launch_bounds__(RENDER_BLOCK) void render_kernel(WorkArgs w, const 
 // Adds the float64 cusp corrections to the flagged pixels; a fixed grid of
 // waves walks the list written by render_kernel (each pixel appears at most
 // once), one entry per wave at a time. Only a few pixels of a flagged wave, and
-// a part of their subsamples, lie inside the re-tracing radius, so the wave
-// first finds those subsamples (float32, as the render saw them) and queues
-// them in LDS, then re-traces the queue in float64 64 at a time with every lane
-// busy. Each pixel then adds its subsamples' corrections in the rule's order
-// (zero outside the radius), as a serial loop over its subsamples would.
+// a part of their subsamples, lie inside the re-tracing radius. The wave lists
+// the entry's F flagged pixels in LDS and tests the F x (subsamples) pairs 64
+// at a time (float32, as the render saw them), queueing those inside the
+// radius; then it re-traces the queue in float64 64 at a time with every lane
+// busy. Lane f < F then adds its pixel's corrections in the rule's order (zero
+// outside the radius), as a serial loop over its subsamples would.
 constexpr int CUSP_WAVES = 4;
 constexpr int CUSP_BLOCKS = 2048;
 constexpr int CUSP_CHUNK = 16;   // subsamples per pass
@@ -152,50 +153,61 @@ __device__ __forceinline__ void subsample_xy(const GkRule* R, int N, int kx, int
 __global__ __launch_bounds__(64 * CUSP_WAVES) void cusp_kernel(WorkArgs w, const PointConst* __restrict__ pcs,
                                                                const PointConst64* __restrict__ p64s,
                                                                float* __restrict__ L, CuspList cl) {
-  __shared__ float dval[CUSP_WAVES][CUSP_CHUNK * 64];             // [subsample][lane]
-  __shared__ unsigned short queue[CUSP_WAVES][CUSP_CHUNK * 64];   // lane | subsample << 6
+  __shared__ float dval[CUSP_WAVES][CUSP_CHUNK * 64];             // [subsample][flagged pixel]
+  __shared__ unsigned short queue[CUSP_WAVES][CUSP_CHUNK * 64];   // flagged pixel | subsample << 6
+  __shared__ int fpix[CUSP_WAVES][64];                            // the entry's flagged pixels
   const int n = *cl.count;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wave = blockIdx.x * CUSP_WAVES + wv;
   float* __restrict__ dv = dval[wv];
   unsigned short* __restrict__ qu = queue[wv];
+  int* __restrict__ fp = fpix[wv];
   for (int i = wave; i < n; i += gridDim.x * CUSP_WAVES) {
     const CuspEntry e = cl.entries[i];
     const bool mine = (e.mask >> lane) & 1ull;
+    const int F = __popcll(e.mask);
     const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[e.point] : 0] : w.single;
     const int64_t loff = w.point_loff ? w.point_loff[e.point] : 0;
-    const int pix = mine ? unit_pixel(sd, e.unit0 + lane, e.ppt) + e.half : 0;
-    int v;
-    const PixelGeom g = pixel_geom(sd, pix, &v);
+    if (mine) fp[__popcll(e.mask & ((1ull << lane) - 1ull))] = unit_pixel(sd, e.unit0 + lane, e.ppt) + e.half;
+    wave_lds_sync();
     const PointConst& c = pcs[e.point];
-    const RenderVariant& k = c.rv[v];
     const PointConst64& c64 = p64s[e.point];
     const GkRule* R = sd.rule > 0 ? &kGkRules[sd.rule - 1] : nullptr;
     const int N = sd.N, NN = N * N;
+    const int pix = lane < F ? fp[lane] : 0;   // the flagged pixel whose sum this lane keeps
     float acc = 0.0f;
     for (int s0 = 0; s0 < NN; s0 += CUSP_CHUNK) {
       const int ns = min(CUSP_CHUNK, NN - s0);
-      // the chunk's subsamples inside the radius, queued in (subsample, lane) order
+      for (int j = 0; j < ns; ++j) dv[j * 64 + lane] = 0.0f;
+      // the (flagged pixel, subsample) pairs of the chunk inside the radius, queued in pair order
       int qn = 0;
-      for (int j = 0; j < ns; ++j) {
-        const int ky = (s0 + j) / N, kx = s0 + j - ky * N;
-        float x, y;
-        subsample_xy(R, N, kx, ky, g, x, y);
-        const bool within = mine && render_source_R2(c, k, x, y) < c.cusp_r2;
-        dv[j * 64 + lane] = 0.0f;
-        const unsigned long long b = __ballot(within);
-        if (within) qu[qn + __popcll(b & ((1ull << lane) - 1ull))] = (unsigned short)(lane | (j << 6));
-        qn += __popcll(b);
+      for (int b = 0; b < F * ns; b += 64) {
+        const int item = b + lane;
+        bool within = false;
+        int f = 0, j = 0;
+        if (item < F * ns) {
+          f = item / ns;
+          j = item - f * ns;
+          const int ky = (s0 + j) / N, kx = s0 + j - ky * N;
+          int v;
+          const PixelGeom g = pixel_geom(sd, fp[f], &v);
+          float x, y;
+          subsample_xy(R, N, kx, ky, g, x, y);
+          within = render_source_R2(c, c.rv[v], x, y) < c.cusp_r2;
+        }
+        const unsigned long long bal = __ballot(within);
+        if (within) qu[qn + __popcll(bal & ((1ull << lane) - 1ull))] = (unsigned short)(f | (j << 6));
+        qn += __popcll(bal);
       }
       wave_lds_sync();
       // float64 re-tracing of the queue, 64 subsamples at a time
       for (int q0 = 0; q0 < qn; q0 += 64) {
         if (q0 + lane < qn) {
-          const int item = qu[q0 + lane];
-          const int pl = item & 63, j = item >> 6;
+          const int it = qu[q0 + lane];
+          const int f = it & 63, j = it >> 6;
           const int ky = (s0 + j) / N, kx = s0 + j - ky * N;
           int vq;
-          const PixelGeom gq = pixel_geom(sd, unit_pixel(sd, e.unit0 + pl, e.ppt) + e.half, &vq);
+          const PixelGeom gq = pixel_geom(sd, fp[f], &vq);
           const RenderVariant& kq = c.rv[vq];
           float x, y;
           subsample_xy(R, N, kx, ky, gq, x, y);
@@ -206,14 +218,15 @@ __global__ __launch_bounds__(64 * CUSP_WAVES) void cusp_kernel(WorkArgs w, const
           source_offset_f64(c64, gq, ox, oy, dx, dy);
           const float exact = sersic_shape(source_R2(kq, dx, dy), kq.se, kq.sB);
           const float d = exact - sersic_shape(sR2, kq.se, kq.sB);
-          dv[j * 64 + pl] = R ? R->w[kx] * R->w[ky] * d : d;
+          dv[j * 64 + f] = R ? R->w[kx] * R->w[ky] * d : d;
         }
       }
       wave_lds_sync();
-      for (int j = 0; j < ns; ++j) acc += dv[j * 64 + lane];
+      if (lane < F)
+        for (int j = 0; j < ns; ++j) acc += dv[j * 64 + lane];
       wave_lds_sync();
     }
-    if (mine) L[loff + pix] = (float)((double)L[loff + pix] + (double)(c.sI * acc) * sd.wgt);
+    if (lane < F) L[loff + pix] = (float)((double)L[loff + pix] + (double)(c.sI * acc) * sd.wgt);
   }
 }
 

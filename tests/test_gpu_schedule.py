@@ -27,15 +27,20 @@ def say(msg):
 
 
 def context_with(ppt):
-    old = os.environ.get("LENSED_RENDER_PPT")
-    os.environ["LENSED_RENDER_PPT"] = str(ppt)
+    """A context with the render schedule fixed and the PSF tile left to the
+    cost model: two contexts autotuning by timing could pick different PSF
+    tiles, whose chi^2 partial sums group the pixels differently."""
+    env = {"LENSED_RENDER_PPT": str(ppt), "LENSED_NO_AUTOTUNE": "1"}
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
     try:
         return Context(0)
     finally:
-        if old is None:
-            del os.environ["LENSED_RENDER_PPT"]
-        else:
-            os.environ["LENSED_RENDER_PPT"] = old
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
 
 
 def mixed_systems():
