@@ -66,8 +66,12 @@ enum {
                                   nsub outside 1..16, bad system index, ...     */
   LENSED_HIP_ERROR = 2,        /* a HIP runtime call failed; see lensed_last_error */
   LENSED_OUT_OF_MEMORY = 3,    /* workspace allocation failed                   */
-  LENSED_NOT_SUPPORTED = 4     /* no usable gfx950 device                       */
+  LENSED_NOT_SUPPORTED = 4,    /* no usable gfx950 device                       */
+  LENSED_TOO_LARGE = 5         /* input exceeds the static workspace of lensed_loglike_noalloc */
 };
+
+/* Bytes of the static device workspace of lensed_loglike_noalloc (per device). */
+#define LENSED_NOALLOC_SCRATCH_BYTES (6u << 20)
 
 typedef struct lensed_ctx lensed_ctx;
 
@@ -145,6 +149,29 @@ int lensed_render(lensed_ctx* ctx, const lensed_system* sys, const float* theta,
  * This is the plain form: one launch sequence per call. */
 int lensed_loglike(lensed_ctx* ctx, const lensed_system* sys, const float* theta,
                    double* logl, void* stream);
+
+/* lensed_loglike without a context and without any allocation, for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc. Every intermediate (per-point
+ * constants, normalised PSF copies, the unconvolved image, cusp work list,
+ * per-tile chi^2 sums) lives in one static device array of
+ * LENSED_NOALLOC_SCRATCH_BYTES per device, which the library holds until the
+ * process ends; its device address is looked up once per device. The call
+ * runs on the calling thread's current HIP device, asynchronously on `stream`
+ * (a stream of that device), and gives the same log L as lensed_loglike, bit
+ * for bit.
+ *   sys    as for lensed_loglike (data and weight required)
+ *   theta  device float32 [17]
+ *   logl   device float64 [1], written
+ * Returns LENSED_TOO_LARGE, before any launch, when the image and PSF need
+ * more than the workspace (about 4.4 bytes per pixel plus 52 KB: images up to
+ * about 1.4 million pixels, 1180 x 1180), INVALID_ARGUMENT as lensed_loglike,
+ * HIP_ERROR if a launch fails. Every call on a device shares its workspace, and
+ * each call leaves its contents behind: calls that may overlap on one device
+ * (on different streams, or from several threads) race and must be ordered by
+ * the caller. Nothing here needs zeroed memory: the prologue kernel clears the
+ * one counter it uses. */
+int lensed_loglike_noalloc(const lensed_system* sys, const float* theta, double* logl, void* stream);
 
 /* Log-likelihoods of many points over many systems in one graph launch
  * (Eq. 17 for every point). Work is split into (point, tile) items, ordered

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "liblensed_hip.so")
 ARCH = "gfx950"
 
 SOURCES = ["prologue.hip", "render.hip", "model.hip", "psf_chi2.hip", "adjoint.hip", "variance.hip", "mlp.hip",
-           "plan.hip", "capi.hip"]
+           "plan.hip", "capi.hip", "noalloc.hip"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -218,6 +218,7 @@ const char* lensed_status_string(int status) {
     case LENSED_HIP_ERROR: return "HIP runtime error";
     case LENSED_OUT_OF_MEMORY: return "out of device memory";
     case LENSED_NOT_SUPPORTED: return "not supported";
+    case LENSED_TOO_LARGE: return "input exceeds the static workspace";
     default: return "unknown status";
   }
 }
