@@ -27,10 +27,10 @@ if ROOT not in sys.path:
 # 5 per pixel for the chi^2.
 OPS_PER_SUBSAMPLE = 84
 # The gradient kernel's per-subsample work, counted the same way: the value and
-# its 17 closed-form partial derivatives through both Sersics, the source frame,
-# the lens equation, the SIE (q' > 1/2 branch) and the shear, and their
-# accumulation (per-point constants not counted).
-GRAD_OPS_PER_SUBSAMPLE = 211
+# the derivatives through both Sersics, the source frame, the lens equation and
+# the SIE (q' > 1/2 branch), and the 17 moments they feed (per-point constants
+# and the per-point map from moments to partials not counted).
+GRAD_OPS_PER_SUBSAMPLE = 159
 FP32_PEAK_TFLOPS = 157.3
 
 
@@ -189,7 +189,8 @@ FP64_PEAK_TFLOPS = 78.6
 def next_rows(lensed, mocks, dev, stream, spec, obs, steps=3):
     """Throughput of two extensions on the 200x200 grid: the paper's default
     Gauss-Kronrod rule g3k7 (49 nodes per pixel, float32 like the midpoint
-    path) and the 41-parameter general model (float64 render)."""
+    path) and the 41-parameter general model (float64 render), with its
+    gradient."""
     import torch
     out = {}
     psf = torch.from_numpy(spec.psf).to(dev)
@@ -251,6 +252,13 @@ def next_rows(lensed, mocks, dev, stream, spec, obs, steps=3):
                                             "kernel": "model_render (float64)",
                                             "ops_per_subsample": GENERAL41_OPS_PER_SUBSAMPLE,
                                             "subsamples_per_launch": subs}}
+    # and its adjoint (one component per pass, float64 dual numbers)
+    P = 64
+    th = th[:P].contiguous()
+    log(f"general model (41 parameters) gradients: {P} points")
+    ms, st = timed(lambda: lensed.loglike_model_grad(th, gs, model, ctx=ctx), P, ctx)
+    out["general_model_41_grad"] = {"value": P / (ms / 1e3), "unit": "gradients/s", "points": P, "params": 41,
+                                    "passes": 2 + 4 + 1, "stage_ms_per_step": st}
     ctx.close()
     return out
 

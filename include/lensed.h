@@ -243,8 +243,8 @@ int lensed_render_error(lensed_ctx* ctx, const lensed_system* sys, const float* 
  * model above, and sie_plane and beta are not read.
  *
  * These models are evaluated in float64 and rounded once per pixel (the PSF
- * and chi^2 stages are the common ones); the adjoint covers the 17-parameter
- * model only. */
+ * and chi^2 stages are the common ones); lensed_loglike_model_grad gives the
+ * adjoint of the models with one lens plane. */
 #define LENSED_LIGHT_FOREGROUND 0
 #define LENSED_LIGHT_LENSED 1
 typedef struct {
@@ -278,6 +278,20 @@ int lensed_render_model(lensed_ctx* ctx, const lensed_system* sys, const lensed_
 int lensed_loglike_model_batch(lensed_ctx* ctx, const lensed_system* systems, int n_systems,
                                const lensed_model* model, const float* theta, const int32_t* system_of_point,
                                int n_points, double* logl, void* stream);
+
+/* log L and its gradient with respect to every parameter of a general model
+ * with one lens plane (the paper's real-lens models, Sec. 5: several SIEs with
+ * free centres, the shear, several Sersic components, the sky), for n_points
+ * points of one system: the derivative of Eq. 17 through Eqs. 15, 14, 2, 1 and
+ * 22, by the transposed PSF of lensed_loglike_grad and float64 partial
+ * derivatives per subsample (forward-mode dual numbers, one component at a time).
+ *   theta  device float32 [n_points * P], P = lensed_model_nparams(model)
+ *   logl   device float64 [n_points], written
+ *   grad   device float32 [n_points * P], written (d log L / d theta, in the
+ *          parameter order of the model)
+ * A model with n_planes > 1 is rejected with LENSED_INVALID_ARGUMENT. */
+int lensed_loglike_model_grad(lensed_ctx* ctx, const lensed_system* sys, const lensed_model* model,
+                              const float* theta, int n_points, double* logl, float* grad, void* stream);
 
 /* ---- Composite models ---------------------------------------------------
  * The paper's fits of real lenses (Sec. 5) add further Sersic components and a

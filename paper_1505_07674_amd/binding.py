@@ -137,6 +137,7 @@ def lib():
                 "lensed_loglike": (i, [vp, sp, vp, vp, vp]),
                 "lensed_loglike_batch": (i, [vp, sp, i, vp, ctypes.POINTER(ctypes.c_int32), i, vp, vp]),
                 "lensed_loglike_grad": (i, [vp, sp, vp, i, vp, vp, vp]),
+                "lensed_loglike_model_grad": (i, [vp, sp, vp, vp, i, vp, vp, vp]),
                 "lensed_set_profiling": (i, [vp, i]),
                 "lensed_mlp_param_count": (i, []),
                 "lensed_mlp_forward": (i, [vp, vp, vp, vp, vp, i, vp]),
@@ -544,6 +545,22 @@ def loglike_grad(theta: torch.Tensor, system: System, *, ctx: Optional[Context] 
                                    ctypes.c_void_p(ll.data_ptr()), ctypes.c_void_p(g.data_ptr()),
                                    _stream_handle(stream))
     ctx.check(rc, "lensed_loglike_grad")
+    return ll, g
+
+
+def loglike_model_grad(theta: torch.Tensor, system: System, model: Model, *, ctx: Optional[Context] = None,
+                       stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """log L and d log L / d theta for P points of a general model (one lens
+    plane) on one system -> (float64 [P], float32 [P, model.n_params])."""
+    t = _model_theta(theta, model)
+    P = t.shape[0]
+    ctx = ctx or default_context(t.device.index)
+    ll = torch.empty(P, dtype=torch.float64, device=t.device)
+    g = torch.empty((P, model.n_params), dtype=torch.float32, device=t.device)
+    rc = lib().lensed_loglike_model_grad(ctx.handle, ctypes.byref(system.c_struct), ctypes.byref(model.c_struct),
+                                         ctypes.c_void_p(t.data_ptr()), P, ctypes.c_void_p(ll.data_ptr()),
+                                         ctypes.c_void_p(g.data_ptr()), _stream_handle(stream))
+    ctx.check(rc, "lensed_loglike_model_grad")
     return ll, g
 
 

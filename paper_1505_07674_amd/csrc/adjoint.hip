@@ -11,8 +11,11 @@
 // through the Sersic profiles (Eqs. 22-23, with db_n/dn), and for the lens
 // parameters through beta = x - alpha(x) (Eq. 1) using the SIE Jacobian
 //   d alpha'/d x' = theta_E sqrt(q)/(psi r^2) [[y'^2, -x'y'], [-x'y', x'^2]].
-// Sums are float32 per thread, combined across the block with TwoSum and
-// across tiles in float64.
+// Each partial is a fixed per-point linear combination of 17 moments (sums
+// over subsamples of products that vary per subsample, e.g. sum D h'_x^2),
+// so the kernels accumulate the moments and the final pass maps them to the
+// 17 partials in float64 (grad_from_moments). Sums are float32 per thread,
+// combined across the block with TwoSum and across tiles in float64.
 #include <math.h>
 
 #include "internal.h"
@@ -101,54 +104,90 @@ __global__ __launch_bounds__(P >= 0 && TWc == 0 ? WIDE_MAX_THREADS : 512) void a
   }
 }
 
-// Border pixels of g with the folded tables; blockIdx.y is the point. Eight
-// lanes share a pixel: lane `sub` takes the table rows a = -p + sub, -p + sub + 8,
-// ..., and the eight partial sums are added in a fixed order by shuffles.
-constexpr int BORDER_LANES = 8;
+// Border pixels of g with the folded tables. A block takes a segment of up to
+// BORDER_SEG consecutive pixels on one side of the image (top row, bottom row,
+// then the left and right columns without their corners; blockIdx.y is the
+// point) and stages the window of rho they read in LDS, zero outside the image,
+// so every table row is a full PW-tap dot product (a zero tap adds exactly
+// nothing). Each pixel has BORDER_SUB lanes: lane `sub` takes the table rows
+// a = a_lo + sub, a_lo + sub + BORDER_SUB, ... of the rows that fall inside the
+// image, and the partial sums are added in a fixed order by shuffles. PW = 0:
+// the table width is a runtime value.
+constexpr int BORDER_SEG = 64;
+constexpr int BORDER_SUB = 4;
 
-__global__ __launch_bounds__(64) void adj_border_kernel(WorkArgs w, const float* __restrict__ R, float* __restrict__ G,
-                                                         int n_border, int point_base) {
+__host__ __device__ inline int border_row_segments(int W) { return (W + BORDER_SEG - 1) / BORDER_SEG; }
+__host__ __device__ inline int border_side_segments(int H) { return H > 2 ? (H - 2 + BORDER_SEG - 1) / BORDER_SEG : 0; }
+// Segments of an H x W image: every pixel on the first or last row or column
+// lies in exactly one (the bottom row is absent when H = 1, the right column
+// when W = 1).
+__host__ __device__ inline int border_segments(int H, int W) {
+  return border_row_segments(W) * (H > 1 ? 2 : 1) + border_side_segments(H) * (W > 1 ? 2 : 1);
+}
+// LDS floats of the largest window for a PSF of ph x pw.
+inline size_t border_lds_floats(int ph, int pw) {
+  const size_t row = (size_t)ph * (BORDER_SEG + pw - 1), col = (size_t)(BORDER_SEG + ph - 1) * pw;
+  return row > col ? row : col;
+}
+
+template <int PW>
+__global__ __launch_bounds__(BORDER_SEG* BORDER_SUB) void adj_border_kernel(WorkArgs w, const float* __restrict__ R,
+                                                                             float* __restrict__ G, int point_base) {
+  extern __shared__ float S[];
   const int point = point_base + (int)blockIdx.y;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int t = (int)(gid / BORDER_LANES), sub = (int)(gid % BORDER_LANES);
-  if (t >= n_border) return;   // the eight lanes of a pixel leave together
   const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[point] : 0] : w.single;
   const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
-  const int H = sd.H, W = sd.W;
-  int u, v;
-  if (H <= 2 || W <= 2) {   // every pixel touches a border
-    u = t / W;
-    v = t - u * W;
-  } else if (t < W) {
-    u = 0;
-    v = t;
-  } else if (t < 2 * W) {
-    u = H - 1;
-    v = t - W;
+  const int H = sd.H, W = sd.W, p = sd.ph / 2, q = sd.pw / 2;
+  const int pw = PW > 0 ? PW : sd.pw;
+  const int nrow = border_row_segments(W), nbot = H > 1 ? nrow : 0;
+  const int nside = border_side_segments(H), nright = W > 1 ? nside : 0;
+  int seg = (int)blockIdx.x;
+  bool is_row;
+  int u0, v0;
+  if (seg < nrow) {
+    is_row = true, u0 = 0, v0 = seg * BORDER_SEG;
+  } else if ((seg -= nrow) < nbot) {
+    is_row = true, u0 = H - 1, v0 = seg * BORDER_SEG;
+  } else if ((seg -= nbot) < nside) {
+    is_row = false, u0 = 1 + seg * BORDER_SEG, v0 = 0;
+  } else if ((seg -= nside) < nright) {
+    is_row = false, u0 = 1 + seg * BORDER_SEG, v0 = W - 1;
   } else {
-    const int k = t - 2 * W;
-    u = 1 + (k >> 1);
-    v = (k & 1) ? W - 1 : 0;
+    return;   // uniform over the block, before any barrier
   }
-  const int cr = (H == 1) ? 3 : (u == 0 ? 1 : (u == H - 1 ? 2 : 0));
-  const int cc = (W == 1) ? 3 : (v == 0 ? 1 : (v == W - 1 ? 2 : 0));
-  const int p = sd.ph / 2, q = sd.pw / 2;
-  const float* __restrict__ K = sd.adjk + (size_t)(cr * 4 + cc) * sd.ph * sd.pw;
+  const int len = is_row ? min(BORDER_SEG, W - v0) : min(BORDER_SEG, H - 1 - u0);
+  const int u1 = is_row ? u0 : u0 + len - 1, v1 = is_row ? v0 + len - 1 : v0;
+  // window of rho: rows u0 - p .. u1 + p, columns v0 - q .. v1 + q
+  const int wr0 = u0 - p, wc0 = v0 - q;
+  const int WC = v1 - v0 + 1 + 2 * q, n_win = (u1 - u0 + 1 + 2 * p) * WC;
   const float* __restrict__ Rp = R + loff;
+  for (int i = (int)threadIdx.x; i < n_win; i += (int)blockDim.x) {
+    const int r = i / WC, gi = wr0 + r, gj = wc0 + (i - r * WC);
+    S[i] = (gi >= 0 && gi < H && gj >= 0 && gj < W) ? Rp[(size_t)gi * W + gj] : 0.0f;
+  }
+  __syncthreads();
+  const int j = (int)threadIdx.x / BORDER_SUB, sub = (int)threadIdx.x % BORDER_SUB;
   float acc = 0.0f;
-  for (int a = -p + sub; a <= p; a += BORDER_LANES) {
-    const int i = u + a;
-    if (i < 0 || i >= H) continue;
-    for (int b = -q; b <= q; ++b) {
-      const int j = v + b;
-      if (j < 0 || j >= W) continue;
-      acc = fmaf(K[(a + p) * sd.pw + (b + q)], Rp[(size_t)i * W + j], acc);
+  const int u = is_row ? u0 : u0 + j, v = is_row ? v0 + j : v0;
+  if (j < len) {
+    const int cr = (H == 1) ? 3 : (u == 0 ? 1 : (u == H - 1 ? 2 : 0));
+    const int cc = (W == 1) ? 3 : (v == 0 ? 1 : (v == W - 1 ? 2 : 0));
+    const float* __restrict__ K = sd.adjk + (size_t)(cr * 4 + cc) * sd.ph * pw;
+    const int a_lo = max(-p, -u), a_hi = min(p, H - 1 - u);
+    for (int a = a_lo + sub; a <= a_hi; a += BORDER_SUB) {
+      const float* __restrict__ Kr = K + (a + p) * pw;
+      const float* __restrict__ Sr = S + (u + a - wr0) * WC + (v - q - wc0);
+      if (PW > 0) {
+#pragma unroll
+        for (int b = 0; b < PW; ++b) acc = fmaf(Kr[b], Sr[b], acc);
+      } else {
+        for (int b = 0; b < pw; ++b) acc = fmaf(Kr[b], Sr[b], acc);
+      }
     }
   }
-  acc += __shfl_xor(acc, 4, BORDER_LANES);
-  acc += __shfl_xor(acc, 2, BORDER_LANES);
-  acc += __shfl_xor(acc, 1, BORDER_LANES);
-  if (sub == 0) G[loff + (size_t)u * W + v] = acc;
+  acc += __shfl_xor(acc, 2, BORDER_SUB);
+  acc += __shfl_xor(acc, 1, BORDER_SUB);
+  if (j < len && sub == 0) G[loff + (size_t)u * W + v] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -163,7 +202,45 @@ struct GradUniform {
   float qH, qS;              // Sersic axis ratios
   float bH, bS;              // natural-log Sersic constants b = B ln 2
   float dbH, dbS;            // db/dn
+  // reciprocals of the per-point divisors, so that no subsample divides:
+  float hs, iq, iq2, hsq;    // 1/(2s), 1/q, 1/q^2, 1/(2 sqrt q)
+  float m2iRH, m2iRS;        // -2/R_H, -2/R_S
+  float iqH, iqS;            // 1/q_H, 1/q_S
+  float kS1, kS2;            // cos, sin (phi_S - phi_L): source-frame gradient into the SIE frame
 };
+
+__device__ __forceinline__ GradUniform grad_uniform(const PointConst& c, const GradConst& gc) {
+  GradUniform U;
+  U.te = gc.theta[0];
+  U.q = gc.theta[1];
+  U.sq = sqrtf(U.q);
+  U.s = (1.0f - U.q) * (1.0f + U.q);
+  U.iqp = c.sie_mode == 0 ? 0.0f : 1.0f / c.qp;
+  float s2, c2;
+  sincosf(2.0f * gc.theta[4], &s2, &c2);
+  U.c2 = c2;
+  U.s2 = s2;
+  U.gam = gc.theta[3];
+  U.RH = gc.theta[6];
+  U.RS = gc.theta[13];
+  U.qH = gc.theta[8];
+  U.qS = gc.theta[15];
+  U.bH = c.hB * LN2F;
+  U.bS = c.sB * LN2F;
+  U.dbH = gc.dB_dn_h * LN2F;
+  U.dbS = gc.dB_dn_s * LN2F;
+  U.hs = 0.5f / U.s;
+  U.iq = 1.0f / U.q;
+  U.iq2 = 1.0f / (U.q * U.q);
+  U.hsq = 0.5f / U.sq;
+  U.m2iRH = -2.0f / U.RH;
+  U.m2iRS = -2.0f / U.RS;
+  U.iqH = 1.0f / U.qH;
+  U.iqS = 1.0f / U.qS;
+  U.kS1 = c.sc * c.cL + c.ss * c.sL;
+  U.kS2 = c.ss * c.cL - c.sc * c.sL;
+  return U;
+}
 
 // Sersic value and derivatives at scaled squared radius rho2.
 struct SersicD {
@@ -178,7 +255,7 @@ __device__ __forceinline__ SersicD sersic_d(float rho2, float e, float B, float 
   r.E = hw_exp2(fmaf(-B, t, B));
   r.I = Ie * r.E;
   const bool pos = rho2 > 0.0f;
-  r.D = pos ? -r.I * b * t * e / rho2 : 0.0f;
+  r.D = pos ? -r.I * b * t * e * hw_rcp(rho2) : 0.0f;
   // dI/dn = I [b'(1 - t) + b t ln(rho2) / (2 n^2)],  1/(2n^2) = 2 e^2
   const float tl = pos ? t * (L2 * LN2F) : 0.0f;
   r.dn = r.I * fmaf(db, 1.0f - t, b * tl * 2.0f * e * e);
@@ -244,72 +321,105 @@ __device__ __forceinline__ void subsample_grad(const PointConst& c, const GradUn
     db = datanh_ds_series(U.s, v0);
   } else {
     const float pr = live ? psi2 * hw_rcp(r2) : 0.0f;   // psi^2 / r^2
-    da = (u0 * pr - a) * (0.5f / U.s);
-    db = (v0 * pr * (1.0f / (U.q * U.q)) - b) * (0.5f / U.s);
+    da = (u0 * pr - a) * U.hs;
+    db = (v0 * pr * U.iq2 - b) * U.hs;
   }
   const float pr2 = live ? psi2 * hw_rcp(r2) : 0.0f;
-  // frame derivatives
-  const float dte_x = U.sq * a, dte_y = U.sq * b;
-  const float dphi_x = U.te * U.sq * (v0 - b), dphi_y = U.te * U.sq * (a - u0);
-  const float dq_x = U.te * (a * (0.5f / U.sq) + U.sq * (-2.0f * U.q * da - U.q * u0 * u0 * u0 * pr2));
-  const float dq_y = U.te * (b * (0.5f / U.sq) + U.sq * (-2.0f * U.q * db - v0 * u0 * u0 * pr2 / U.q));
   // back to the image frame
-  auto rot_x = [&](float fx, float fy) { return fmaf(c.cL, fx, -c.sL * fy); };
-  auto rot_y = [&](float fx, float fy) { return fmaf(c.sL, fx, c.cL * fy); };
-  const float ax = rot_x(apx, apy), ay = rot_y(apx, apy);
+  const float ax = fmaf(c.cL, apx, -c.sL * apy), ay = fmaf(c.sL, apx, c.cL * apy);
   // ---- lens equation and source
   const float bx = fmaf(c.m11, x, fmaf(c.m12, y, -ax));
   const float by = fmaf(c.m12, x, fmaf(c.m22, y, -ay));
   const float dx = override ? odx : bx - c.sx0, dy = override ? ody : by - c.sy0;
   const float sxp = fmaf(c.sc, dx, c.ss * dy);
   const float syp = fmaf(c.sc, dy, -c.ss * dx);
-  const float srho2 = fmaf(c.sqa * sxp, sxp, c.sqb * syp * syp);
+  const float sx2 = sxp * sxp, sy2 = syp * syp;
+  const float srho2 = fmaf(c.sqa, sx2, c.sqb * sy2);
   SersicD Sd = sersic_d(srho2, c.se, c.sB, c.sI, U.bS, U.dbS);
   if (WT) {
     Sd.E *= sw;
     Sd.D *= sw;
     Sd.dn *= sw;
   }
-  const float gxp = 2.0f * c.sqa * sxp, gyp = 2.0f * c.sqb * syp;   // d rho2 / d(x', y') of the source frame
-  const float Gx = Sd.D * fmaf(gxp, c.sc, -gyp * c.ss);
-  const float Gy = Sd.D * fmaf(gxp, c.ss, gyp * c.sc);
+  // dI/dbeta in the SIE frame: D times the source-frame gradient of rho^2,
+  // rotated by phi_S - phi_L
+  const float gxp = 2.0f * c.sqa * sxp, gyp = 2.0f * c.sqb * syp;
+  const float Gx = Sd.D * fmaf(gxp, U.kS1, -gyp * U.kS2);
+  const float Gy = Sd.D * fmaf(gxp, U.kS2, gyp * U.kS1);
   // ---- lens light
   const float hxp = fmaf(c.hc, x, c.hs * y);
   const float hyp = fmaf(c.hc, y, -c.hs * x);
-  const float hrho2 = fmaf(c.hqa * hxp, hxp, c.hqb * hyp * hyp);
+  const float hx2 = hxp * hxp, hy2 = hyp * hyp;
+  const float hrho2 = fmaf(c.hqa, hx2, c.hqb * hy2);
   SersicD Hd = sersic_d(hrho2, c.he, c.hB, c.hI, U.bH, U.dbH);
   if (WT) {
     Hd.E *= sw;
     Hd.D *= sw;
     Hd.dn *= sw;
   }
-  // ---- accumulate
-  acc[0] -= Gx * rot_x(dte_x, dte_y) + Gy * rot_y(dte_x, dte_y);
-  acc[1] -= Gx * rot_x(dq_x, dq_y) + Gy * rot_y(dq_x, dq_y);
-  acc[2] -= Gx * rot_x(dphi_x, dphi_y) + Gy * rot_y(dphi_x, dphi_y);
-  acc[3] -= Gx * fmaf(U.c2, x, U.s2 * y) + Gy * fmaf(U.s2, x, -U.c2 * y);
-  acc[4] -= 2.0f * U.gam * (Gx * fmaf(-U.s2, x, U.c2 * y) + Gy * fmaf(U.c2, x, U.s2 * y));
+  // ---- accumulate the moments (grad_from_moments maps them to the partials)
+  const float u2pr = u0 * u0 * pr2;
+  acc[0] += fmaf(a, Gx, b * Gy);
+  acc[1] += fmaf(Gx, fmaf(2.0f, da, u0 * u2pr), Gy * fmaf(2.0f, db, v0 * u2pr * U.iq2));
+  acc[2] += fmaf(v0 - b, Gx, (a - u0) * Gy);
+  acc[3] += fmaf(Gx, xp, -Gy * yp);
+  acc[4] += fmaf(Gx, yp, Gy * xp);
   acc[5] += Hd.E;
-  acc[6] += -2.0f * hrho2 * Hd.D / U.RH;
+  acc[6] += Hd.D * hx2;
   acc[7] += Hd.dn;
-  acc[8] += Hd.D * (c.hqa * hxp * hxp - c.hqb * hyp * hyp) / U.qH;
-  acc[9] += Hd.D * 2.0f * hxp * hyp * (c.hqa - c.hqb);
-  acc[10] -= Gx;
-  acc[11] -= Gy;
+  acc[8] += Hd.D * hy2;
+  acc[9] += Hd.D * (hxp * hyp);
+  acc[10] += Gx;
+  acc[11] += Gy;
   acc[12] += Sd.E;
-  acc[13] += -2.0f * srho2 * Sd.D / U.RS;
+  acc[13] += Sd.D * sx2;
   acc[14] += Sd.dn;
-  acc[15] += Sd.D * (c.sqa * sxp * sxp - c.sqb * syp * syp) / U.qS;
-  acc[16] += Sd.D * 2.0f * sxp * syp * (c.sqa - c.sqb);
+  acc[15] += Sd.D * sy2;
+  acc[16] += Sd.D * (sxp * syp);
 }
 
+// The 17 partials from the moments, for one point, in float64:
+//   M0 = sum a G'x + b G'y,  M1 = sum G'x (2 da + u0^3 pr) + G'y (2 db + v0 u0^2 pr / q^2),
+//   M2 = sum (v0 - b) G'x + (a - u0) G'y,  M3 = sum G'x x' - G'y y',  M4 = sum G'x y' + G'y x'
+// (G' = dI/dbeta in the SIE frame, x' the SIE frame), M10, M11 = sum G', and
+// per Sersic the value, dI/dn and D times x'^2, y'^2, x'y' in its own frame.
+__device__ void grad_from_moments(const double (&M)[NPAR], const PointConst& c, const GradConst& gc, double (&g)[NPAR]) {
+  const double te = gc.theta[0], q = gc.theta[1], sq = sqrt(q), gam = gc.theta[3];
+  const double cL = c.cL, sL = c.sL;
+  // the shear angle relative to the SIE frame
+  const double ph = 2.0 * ((double)gc.theta[4] - (double)gc.theta[2]);
+  const double c2 = cos(ph), s2 = sin(ph);
+  g[0] = -sq * M[0];
+  g[1] = -te * (0.5 / sq * M[0] - sq * q * M[1]);
+  g[2] = -te * sq * M[2];
+  g[3] = -(c2 * M[3] + s2 * M[4]);
+  g[4] = -2.0 * gam * (c2 * M[4] - s2 * M[3]);
+  const double hqa = c.hqa, hqb = c.hqb, sqa = c.sqa, sqb = c.sqb;
+  g[5] = M[5];
+  g[6] = -2.0 / gc.theta[6] * (hqa * M[6] + hqb * M[8]);
+  g[7] = M[7];
+  g[8] = (hqa * M[6] - hqb * M[8]) / gc.theta[8];
+  g[9] = 2.0 * (hqa - hqb) * M[9];
+  g[10] = -(cL * M[10] - sL * M[11]);
+  g[11] = -(sL * M[10] + cL * M[11]);
+  g[12] = M[12];
+  g[13] = -2.0 / gc.theta[13] * (sqa * M[13] + sqb * M[15]);
+  g[14] = M[14];
+  g[15] = (sqa * M[13] - sqb * M[15]) / gc.theta[15];
+  g[16] = 2.0 * (sqa - sqb) * M[16];
+}
+
+// The subsample offsets (k + 1/2)/N - 1/2 by a multiply with 1/N (to a float32
+// rounding of the quotient: the gradient needs the abscissae to float32
+// accuracy, not bit for bit those of the render).
 template <int MODE>
 __device__ __forceinline__ void pixel_grad(const PointConst& c, const GradUniform& U, int N, const PixelGeom& g,
                                            float (&acc)[NPAR]) {
+  const float iN = 1.0f / (float)N;
   for (int ky = 0; ky < N; ++ky) {
-    const float y = fmaf(g.uy + sub_offset_rt(ky, N), g.d, g.cy);
+    const float y = fmaf(g.uy + fmaf((float)ky + 0.5f, iN, -0.5f), g.d, g.cy);
     for (int kx = 0; kx < N; ++kx) {
-      const float x = fmaf(g.ux + sub_offset_rt(kx, N), g.d, g.cx);
+      const float x = fmaf(g.ux + fmaf((float)kx + 0.5f, iN, -0.5f), g.d, g.cx);
       subsample_grad<MODE>(c, U, x, y, acc);
     }
   }
@@ -332,7 +442,9 @@ __device__ __forceinline__ void pixel_grad_gk(const PointConst& c, const GradUni
 
 // One thread per pixel, one block per (point, render tile): sums
 // g_pix * d^2/N^2 * dI/dtheta over the pixel's subsamples, then over the block.
-__global__ __launch_bounds__(RENDER_BLOCK) void grad_kernel(WorkArgs w, const PointConst* __restrict__ pcs,
+// Six waves per SIMD (at most 80 VGPRs, no spills) hide the latency of the
+// transcendental chains better than the five the registers would otherwise allow.
+__global__ __launch_bounds__(RENDER_BLOCK, 6) void grad_kernel(WorkArgs w, const PointConst* __restrict__ pcs,
                                                              const GradConst* __restrict__ gcs,
                                                              const float* __restrict__ G,
                                                              const int* __restrict__ gpbase,
@@ -344,25 +456,7 @@ __global__ __launch_bounds__(RENDER_BLOCK) void grad_kernel(WorkArgs w, const Po
   const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
   const PointConst& c = pcs[point];
   const GradConst& gc = gcs[point];
-  GradUniform U;
-  U.te = gc.theta[0];
-  U.q = gc.theta[1];
-  U.sq = sqrtf(U.q);
-  U.s = (1.0f - U.q) * (1.0f + U.q);
-  U.iqp = c.sie_mode == 0 ? 0.0f : 1.0f / c.qp;
-  float s2, c2;
-  sincosf(2.0f * gc.theta[4], &s2, &c2);
-  U.c2 = c2;
-  U.s2 = s2;
-  U.gam = gc.theta[3];
-  U.RH = gc.theta[6];
-  U.RS = gc.theta[13];
-  U.qH = gc.theta[8];
-  U.qS = gc.theta[15];
-  U.bH = c.hB * LN2F;
-  U.bS = c.sB * LN2F;
-  U.dbH = gc.dB_dn_h * LN2F;
-  U.dbS = gc.dB_dn_s * LN2F;
+  const GradUniform U = grad_uniform(c, gc);
 
   float acc[NPAR];
 #pragma unroll
@@ -371,7 +465,7 @@ __global__ __launch_bounds__(RENDER_BLOCK) void grad_kernel(WorkArgs w, const Po
   if (pix < sd.H * sd.W) {
     const float gp = G[loff + pix];
     if (gp != 0.0f) {   // pixels outside the reach of any weighted residual add nothing
-      const int r = pix / sd.W;
+      const int r = row_of(sd, pix);
       const int col = pix - r * sd.W;
       PixelGeom geo;
       geo.ux = (float)col - 0.5f * (float)(sd.W - 1);
@@ -455,7 +549,7 @@ __device__ __forceinline__ void gcusp_lds_sync() {
 }
 
 __device__ __forceinline__ PixelGeom gcusp_geom(const SysDesc& sd, int pix) {
-  const int r = pix / sd.W;
+  const int r = row_of(sd, pix);
   const int col = pix - r * sd.W;
   PixelGeom geo;
   geo.ux = (float)col - 0.5f * (float)(sd.W - 1);
@@ -483,29 +577,11 @@ __global__ __launch_bounds__(64 * GCUSP_WAVES) void grad_cusp_kernel(WorkArgs w,
     const int64_t loff = w.point_loff ? w.point_loff[e.point] : 0;
     const PointConst& c = pcs[e.point];
     const GradConst& gc = gcs[e.point];
-    GradUniform U;
-    U.te = gc.theta[0];
-    U.q = gc.theta[1];
-    U.sq = sqrtf(U.q);
-    U.s = (1.0f - U.q) * (1.0f + U.q);
-    U.iqp = c.sie_mode == 0 ? 0.0f : 1.0f / c.qp;
-    float s2, c2;
-    sincosf(2.0f * gc.theta[4], &s2, &c2);
-    U.c2 = c2;
-    U.s2 = s2;
-    U.gam = gc.theta[3];
-    U.RH = gc.theta[6];
-    U.RS = gc.theta[13];
-    U.qH = gc.theta[8];
-    U.qS = gc.theta[15];
-    U.bH = c.hB * LN2F;
-    U.bS = c.sB * LN2F;
-    U.dbH = gc.dB_dn_h * LN2F;
-    U.dbS = gc.dB_dn_s * LN2F;
+    const GradUniform U = grad_uniform(c, gc);
     const int lpix = mine ? unit_pixel(sd, e.unit0 + lane, e.ppt) + e.half : 0;   // this lane's pixel
     const PixelGeom geo = gcusp_geom(sd, lpix);
     // the render constants the forward render used for this lane's pixel
-    const int prow = lpix / sd.W;
+    const int prow = row_of(sd, lpix);
     const RenderVariant& kv = c.rv[render_variant(prow, lpix - prow * sd.W)];
     const int N = sd.N, NN = N * N;
     const GkRule* Rg = sd.rule > 0 ? &kGkRules[sd.rule - 1] : nullptr;
@@ -573,18 +649,10 @@ __global__ __launch_bounds__(64 * GCUSP_WAVES) void grad_cusp_kernel(WorkArgs w,
   }
 }
 
-// grad[p][k] = sum over the point's render tiles of (hi + lo) plus the cusp
-// correction, in float64.
-// Sum of one gradient entry k of point p over its tiles (and its cusp term).
-__device__ double grad_entry(const float2* __restrict__ gpart, int base, int ntiles, const double* __restrict__ corr,
-                             int p, int k) {
-  double s = corr ? corr[(size_t)p * NPAR + k] : 0.0;
-  for (int i = 0; i < ntiles; ++i) {
-    const float2 v = gpart[(size_t)(base + i) * NPAR + k];
-    s += (double)v.x + (double)v.y;
-  }
-  return s;
-}
+// One block per point: wave w sums the moments k = w, w + 4, ... over the
+// point's render tiles (hi + lo, float64, lanes striding over the tiles, then
+// a fixed shuffle tree) and adds the cusp correction.
+constexpr int FGRAD_THREADS = 256;
 
 // With magnitudes, slots 5 and 12 of the sums hold d log L / d I_e and slots
 // 6, 7 and 13, 14 the derivatives at fixed I_e; the chain rule through
@@ -593,33 +661,44 @@ __device__ double grad_entry(const float2* __restrict__ gpart, int base, int nti
 // position, slots 10 and 11 hold d log L / d beta; the chain rule through
 // beta(x_I, y_I, theta_E, q_L, phi_L, gamma, phi_gamma) gives d/dx_I, d/dy_I and
 // adds g_beta . d beta / d theta_k to the five lens entries.
-__global__ void finalize_grad_kernel(const float2* __restrict__ gpart, const int* __restrict__ gpbase, int ntiles,
-                                     int n_points, const double* __restrict__ corr,
-                                     const GradConst* __restrict__ gcs, float* __restrict__ grad) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_points * NPAR) return;
-  const int p = t / NPAR, k = t - p * NPAR;
+__global__ __launch_bounds__(FGRAD_THREADS) void finalize_grad_kernel(
+    const float2* __restrict__ gpart, const int* __restrict__ gpbase, int ntiles, const double* __restrict__ corr,
+    const PointConst* __restrict__ pcs, const GradConst* __restrict__ gcs, float* __restrict__ grad, int point_base) {
+  __shared__ double M[NPAR];
+  const int p = point_base + (int)blockIdx.x;
   const int base = gpbase ? gpbase[p] : 0;
-  double s = grad_entry(gpart, base, ntiles, corr, p, k);
-  if (gcs && gcs[p].srcpos && (k <= 4 || k == 10 || k == 11)) {
-    const float* J = gcs[p].src_jac;
-    const double gx = k == 10 ? s : grad_entry(gpart, base, ntiles, corr, p, 10);
-    const double gy = k == 11 ? s : grad_entry(gpart, base, ntiles, corr, p, 11);
-    const int col = k <= 4 ? k + 2 : k - 10;
-    const double chain = gx * (double)J[col] + gy * (double)J[7 + col];
-    s = k <= 4 ? s + chain : chain;
-  }
-  if (gcs && gcs[p].amp) {
-    const GradConst& gc = gcs[p];
-    if (k >= 5 && k <= 7) {
-      const double gI = k == 5 ? s : grad_entry(gpart, base, ntiles, corr, p, 5);
-      s = k == 5 ? gI * (double)gc.amp_chain[0] : s + gI * (double)gc.amp_chain[k - 5];
-    } else if (k >= 12 && k <= 14) {
-      const double gI = k == 12 ? s : grad_entry(gpart, base, ntiles, corr, p, 12);
-      s = k == 12 ? gI * (double)gc.amp_chain[3] : s + gI * (double)gc.amp_chain[k - 9];
+  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+  for (int k = wv; k < NPAR; k += FGRAD_THREADS / 64) {
+    double s = 0.0;
+    for (int i = lane; i < ntiles; i += 64) {
+      const float2 v = gpart[(size_t)(base + i) * NPAR + k];
+      s += (double)v.x + (double)v.y;
     }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) M[k] = s + (corr ? corr[(size_t)p * NPAR + k] : 0.0);
   }
-  grad[t] = (float)s;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double g[NPAR];
+  const GradConst& gc = gcs[p];
+  grad_from_moments(M, pcs[p], gc, g);
+  if (gc.srcpos) {
+    const float* J = gc.src_jac;
+    const double gx = g[10], gy = g[11];
+    for (int k = 0; k <= 4; ++k) g[k] += gx * (double)J[k + 2] + gy * (double)J[7 + k + 2];
+    g[10] = gx * (double)J[0] + gy * (double)J[7];
+    g[11] = gx * (double)J[1] + gy * (double)J[8];
+  }
+  if (gc.amp) {
+    const double gIh = g[5], gIs = g[12];
+    g[5] = gIh * (double)gc.amp_chain[0];
+    g[6] += gIh * (double)gc.amp_chain[1];
+    g[7] += gIh * (double)gc.amp_chain[2];
+    g[12] = gIs * (double)gc.amp_chain[3];
+    g[13] += gIs * (double)gc.amp_chain[4];
+    g[14] += gIs * (double)gc.amp_chain[5];
+  }
+  for (int k = 0; k < NPAR; ++k) grad[(size_t)p * NPAR + k] = (float)g[k];
 }
 
 template <int P, int TWc, int R>
@@ -658,11 +737,17 @@ hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n
     e = launch_adj_t<-1, 0, 4>(w, R, G, n_blocks, threads, lds, st);
   }
   if (e != hipSuccess) return e;
-  const int nb = (H <= 2 || W <= 2) ? H * W : 2 * W + 2 * (H - 2);
+  const int nseg = border_segments(H, W);
+  const size_t blds = border_lds_floats(ph, pw) * sizeof(float);
   // one grid row per point, at most 65535 rows per launch
   for (int p0 = 0; p0 < n_points; p0 += 65535) {
     const int np = n_points - p0 < 65535 ? n_points - p0 : 65535;
-    hipLaunchKernelGGL(adj_border_kernel, dim3((unsigned)(((int64_t)nb * BORDER_LANES + 63) / 64), np), dim3(64), 0, st, w, R, G, nb, p0);
+    if (pw == 21)
+      hipLaunchKernelGGL(adj_border_kernel<21>, dim3((unsigned)nseg, np), dim3(BORDER_SEG * BORDER_SUB), blds, st, w,
+                         R, G, p0);
+    else
+      hipLaunchKernelGGL(adj_border_kernel<0>, dim3((unsigned)nseg, np), dim3(BORDER_SEG * BORDER_SUB), blds, st, w,
+                         R, G, p0);
     const hipError_t le = hipGetLastError();
     if (le != hipSuccess) return le;
   }
@@ -687,12 +772,17 @@ hipError_t launch_grad(const WorkArgs& w, const PointConst* pcs, const PointCons
 }
 
 hipError_t launch_finalize_grad(const float2* gpart, const int* gpbase, int ntiles, int n_points, const double* corr,
-                                const GradConst* gcs, float* grad, hipStream_t st) {
+                                const PointConst* pcs, const GradConst* gcs, float* grad, hipStream_t st) {
   if (n_points <= 0) return hipSuccess;
-  const int n = n_points * NPAR;
-  hipLaunchKernelGGL(finalize_grad_kernel, dim3((n + 127) / 128), dim3(128), 0, st, gpart, gpbase, ntiles, n_points,
-                     corr, gcs, grad);
-  return hipGetLastError();
+  // at most 2^20 blocks per launch (the grid stays far below 2^32 work-items)
+  for (int p0 = 0; p0 < n_points; p0 += 1 << 20) {
+    const int np = n_points - p0 < (1 << 20) ? n_points - p0 : (1 << 20);
+    hipLaunchKernelGGL(finalize_grad_kernel, dim3((unsigned)np), dim3(FGRAD_THREADS), 0, st, gpart, gpbase, ntiles,
+                       corr, pcs, gcs, grad, p0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace lensed

@@ -197,6 +197,7 @@ SysDesc make_desc(const lensed_system& s, const TileShape& t) {
   // the midpoint weights 1/N^2 are folded here; the Gauss-Kronrod weights (summing to 1) multiply in the kernel
   d.wgt = (double)s.pixscale * (double)s.pixscale /
           (s.rule == LENSED_RULE_MIDPOINT ? (double)s.nsub * (double)s.nsub : 1.0);
+  set_row_divisor(d);
   return d;
 }
 
@@ -488,7 +489,7 @@ int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const 
           (void)hipGetLastError();
           continue;
         }
-        if (!trial.pair_capable()) break;   // nothing to choose: every class renders one pixel per thread
+        if (trial.max_ppt() < 2) break;   // nothing to choose: every class renders one pixel per thread
         float ms = 0.0f;
         LENSED_HIP(c, trial.render_ms((hipStream_t)stream, &ms));
         if (ms < best_ms) {
@@ -775,19 +776,14 @@ int lensed_stage_times(lensed_ctx* c, double* ms, int n, int* calls) {
 
 }  // extern "C"
 
-extern "C" int lensed_loglike_grad(lensed_ctx* c, const lensed_system* sys, const float* theta, int n_points,
-                                   double* logl, float* grad, void* stream) {
-  if (!c) return LENSED_INVALID_ARGUMENT;
-  if (n_points < 0) return set_err(c, LENSED_INVALID_ARGUMENT, "n_points must be >= 0");
-  if (n_points == 0) return LENSED_OK;
-  int rc = validate_system(c, sys, true, -1);
-  if (rc) return rc;
-  if (!theta || !logl || !grad) return set_err(c, LENSED_INVALID_ARGUMENT, "theta, logl and grad are required");
+// The gradient plans of one system (17-parameter model, or a general model).
+static int run_grad(lensed_ctx* c, const lensed_system* sys, const float* theta, int n_points, double* logl,
+                    float* grad, void* stream, const ModelSpec* spec, int params_per_point) {
   LENSED_HIP(c, hipSetDevice(c->device));
   std::vector<int32_t> map(n_points, 0);
   BatchPlan* plan = nullptr;
   for (size_t i = 0; i < c->plans.size(); ++i) {
-    if (c->plans[i]->matches(sys, 1, theta, map.data(), n_points, logl, grad)) {
+    if (c->plans[i]->matches(sys, 1, theta, map.data(), n_points, logl, grad, 1, nullptr, 1, spec)) {
       std::unique_ptr<BatchPlan> keep = std::move(c->plans[i]);
       c->plans.erase(c->plans.begin() + i);
       c->plans.push_back(std::move(keep));
@@ -802,7 +798,8 @@ extern "C" int lensed_loglike_grad(lensed_ctx* c, const lensed_system* sys, cons
     }
     std::unique_ptr<BatchPlan> np(new BatchPlan());
     std::string msg;
-    hipError_t e = np->build(sys, 1, theta, map.data(), n_points, logl, c->tiles, msg, grad);
+    hipError_t e = np->build(sys, 1, theta, map.data(), n_points, logl, c->tiles, msg, grad, nullptr, 1, nullptr, 1,
+                             spec, params_per_point);
     if (e != hipSuccess) return hip_fail(c, e, ("gradient plan: " + msg).c_str());
     if (c->use_graphs) {
       e = np->capture(c->cap);
@@ -820,6 +817,34 @@ extern "C" int lensed_loglike_grad(lensed_ctx* c, const lensed_system* sys, cons
   }
   LENSED_HIP(c, plan->run((hipStream_t)stream));
   return LENSED_OK;
+}
+
+extern "C" int lensed_loglike_grad(lensed_ctx* c, const lensed_system* sys, const float* theta, int n_points,
+                                   double* logl, float* grad, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  if (n_points < 0) return set_err(c, LENSED_INVALID_ARGUMENT, "n_points must be >= 0");
+  if (n_points == 0) return LENSED_OK;
+  int rc = validate_system(c, sys, true, -1);
+  if (rc) return rc;
+  if (!theta || !logl || !grad) return set_err(c, LENSED_INVALID_ARGUMENT, "theta, logl and grad are required");
+  return run_grad(c, sys, theta, n_points, logl, grad, stream, nullptr, NPAR);
+}
+
+extern "C" int lensed_loglike_model_grad(lensed_ctx* c, const lensed_system* sys, const lensed_model* model,
+                                         const float* theta, int n_points, double* logl, float* grad, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  ModelSpec spec;
+  int rc = model_spec(c, model, spec);
+  if (rc) return rc;
+  if (spec.n_planes > 1)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "the adjoint of general models covers one lens plane only");
+  if (n_points < 0) return set_err(c, LENSED_INVALID_ARGUMENT, "n_points must be >= 0");
+  if (n_points == 0) return LENSED_OK;
+  if ((int64_t)n_points * spec_params(spec) > INT32_MAX)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "n_points x parameters too large");
+  if ((rc = validate_system(c, sys, true, -1))) return rc;
+  if (!theta || !logl || !grad) return set_err(c, LENSED_INVALID_ARGUMENT, "theta, logl and grad are required");
+  return run_grad(c, sys, theta, n_points, logl, grad, stream, &spec, spec_params(spec));
 }
 
 extern "C" {

@@ -156,7 +156,23 @@ struct SysDesc {
   const int* active;
   int n_active;           // units in `active`
   int pad_active;
+  unsigned int wdiv_m;    // row of pixel n: (n wdiv_m) >> wdiv_s (row_of)
+  int wdiv_s;
 };
+
+// floor(n / W) for 0 <= n < 2^28 (every pixel index: H W <= 2^28) by one
+// 32 x 32 -> 64-bit product and a shift instead of an integer division
+// (Granlund & Montgomery 1994, Thm. 4.2): with 2^(l-1) < W <= 2^l the
+// multiplier m = floor(2^(28+l) / W) + 1 satisfies 2^(28+l) < m W <= 2^(28+l) + 2^l.
+__host__ __device__ __forceinline__ int row_of(const SysDesc& sd, int n) {
+  return (int)(((unsigned long long)(unsigned)n * sd.wdiv_m) >> sd.wdiv_s);
+}
+inline void set_row_divisor(SysDesc& d) {
+  int l = 0;
+  while ((1ll << l) < (long long)d.W) ++l;
+  d.wdiv_s = 28 + l;
+  d.wdiv_m = (unsigned int)((1ull << (28 + l)) / (unsigned long long)d.W + 1ull);
+}
 
 // First pixel of render unit u of an image rendered with ppt pixels per unit.
 __device__ __forceinline__ int unit_pixel(const SysDesc& sd, int u, int ppt) {

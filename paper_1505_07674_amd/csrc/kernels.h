@@ -80,10 +80,20 @@ hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointCo
 
 // General models: per-point float64 constants from the parameters (n_params
 // per point, the layout of lensed_model), and the float64 render into L.
+// with_db: also db_n/dn of every Sersic (the adjoint needs it).
 hipError_t launch_model_prologue(const float* theta, int n_points, int n_params, const ModelSpec& spec,
-                                 ModelConst* out, hipStream_t stream);
+                                 ModelConst* out, hipStream_t stream, bool with_db = false);
 hipError_t launch_model_render(const WorkArgs& w, const ModelSpec& spec, const ModelConst* mcs, float* L, int n_blocks,
                                hipStream_t stream);
+// Adjoint of a general model with one lens plane: per (point, render tile) and
+// model parameter, g d^2 w dI/dtheta summed over the tile's pixels and
+// subsamples in float64 (gpart[(gpbase[point] + tile) P + k], P parameters per
+// point; g = A^T rho in G), then their sums over the tiles into grad (float32,
+// [n_points][P]).
+hipError_t launch_model_grad(const WorkArgs& w, const ModelSpec& spec, const ModelConst* mcs, const float* G,
+                             const int* gpbase, double* gpart, int P, int n_blocks, hipStream_t stream);
+hipError_t launch_model_finalize_grad(const double* gpart, const int* gpbase, int ntiles, int P, int n_points,
+                                      float* grad, hipStream_t stream);
 
 // Composite models (K consecutive points each): L[first image of model m] =
 // sum of its K unconvolved images + sky[m] pixscale^2 (sky may be nullptr), in
@@ -128,16 +138,20 @@ hipError_t launch_finalize(const float2* partials, const int* point_pbase, const
 hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n_blocks, int square_psf, int TW,
                               int TH, int ph, int pw, int n_points, int H, int W, hipStream_t st);
 
-// Per-(point, render tile) sums of g d^2/N^2 dI/dtheta: gpart[(gpbase[p] + tile) * 17 + k],
+// Per-(point, render tile) sums of g d^2/N^2 times the 17 gradient moments of
+// the subsamples (each partial dI/dtheta is a fixed per-point combination of
+// them): gpart[(gpbase[p] + tile) * 17 + k],
 // then the float64 cusp corrections of the waves in cl (the list the forward
 // render filled) added to corr[p * 17 + k], which must start at zero.
 hipError_t launch_grad(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, const GradConst* gcs,
                        const float* G, const int* gpbase, float2* gpart, int n_blocks, const CuspList& cl,
                        double* corr, hipStream_t st, hipEvent_t between = nullptr);
 
-// Sums the gradient partials of every point; for points of a system with
-// magnitudes, carries d log L / d I_e over to d/dm, d/dR_e and d/dn (gcs).
+// Sums the gradient moments of every point (tiles and cusp corrections), maps
+// them to the 17 partials, and for points of a system with magnitudes carries
+// d log L / d I_e over to d/dm, d/dR_e and d/dn, with an image-plane source
+// position d/dbeta over to the image-plane point and the lens (gcs).
 hipError_t launch_finalize_grad(const float2* gpart, const int* gpbase, int ntiles, int n_points, const double* corr,
-                                const GradConst* gcs, float* grad, hipStream_t st);
+                                const PointConst* pcs, const GradConst* gcs, float* grad, hipStream_t st);
 
 }  // namespace lensed

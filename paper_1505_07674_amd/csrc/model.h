@@ -16,9 +16,11 @@ struct ModelSpec {
   double beta[MAX_PLANES][MAX_PLANES];  // distance ratios beta_ij, i < j < n_planes (0 with one plane)
 };
 struct ModelConst {
-  double sie[MAX_SIE][7];      // x_c, y_c, cos, sin, q^2, q', k = theta_E sqrt(q)/q' (theta_E when q = 1)
+  double sie[MAX_SIE][9];      // x_c, y_c, cos, sin, q^2, q', k = theta_E sqrt(q)/q' (theta_E when q = 1),
+                               // theta_E, q
   double g1, g2;               // external shear (zero without one)
-  double ser[MAX_SERSIC][10];  // x0, y0, cos, sin, q, 1/q, 1/R_e, 1/n, b_n, I_e
+  double gam, c2g, s2g;        // gamma, cos 2 phi_gamma, sin 2 phi_gamma
+  double ser[MAX_SERSIC][11];  // x0, y0, cos, sin, q, 1/q, 1/R_e, 1/n, b_n, I_e, db_n/dn (0 unless asked for)
   double sky;                  // flat sky surface brightness (NaN marks an invalid point)
   int n_sie, n_sersic;
   int sie_sphere[MAX_SIE];     // 1 where q = 1

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(RENDER_BLOCK) void model_render_kernel(WorkArgs w, 
   const int pix = tile * RENDER_BLOCK + (int)threadIdx.x;
   if (pix >= sd.H * sd.W) return;
   const ModelConst& m = mcs[point];
-  const int r = pix / sd.W, c = pix - r * sd.W;
+  const int r = row_of(sd, pix), c = pix - r * sd.W;
   const double ux = (double)c - 0.5 * (double)(sd.W - 1), uy = (double)r - 0.5 * (double)(sd.H - 1);
   const double d = sd.d, cx = sd.cx, cy = sd.cy;
   const int N = sd.N;
@@ -133,6 +133,330 @@ __global__ __launch_bounds__(RENDER_BLOCK) void model_render_kernel(WorkArgs w, 
   L[loff + pix] = (float)(acc * sd.wgt);
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of general models with one lens plane: d log L / d theta =
+// sum_j g_j wgt sum_k w_k dI(x_jk)/d theta, g = A^T rho (the common adjoint PSF
+// stage), the derivative of Eq. 17 through Eqs. 15, 14, 2, 1 and 22. The
+// partials of I at a subsample come from forward-mode dual numbers in float64,
+// one component per pass (an SIE, a Sersic, or the shear and the sky
+// together; blockIdx.y is the pass), so that a thread keeps at most 7 sums:
+//   SIE k        dI/dtheta_k = -G . d alpha_k/d theta_k  (x_c, y_c, theta_E, q, phi)
+//   Sersic j     dS_j/d(x, y, I_e, R_e, n, q, phi) at x (foreground) or beta
+//   shear, sky   G . d beta/d(gamma, phi_gamma), 1
+// with G = sum over the lensed Sersics of grad S_j(beta).
+// ---------------------------------------------------------------------------
+
+// Value and M partial derivatives.
+template <int M>
+struct Dl {
+  double v;
+  double d[M];
+};
+
+template <int M>
+__device__ inline Dl<M> dconst(double v) {
+  Dl<M> r;
+  r.v = v;
+#pragma unroll
+  for (int i = 0; i < M; ++i) r.d[i] = 0.0;
+  return r;
+}
+template <int M>
+__device__ inline Dl<M> dvar(double v, int k) {
+  Dl<M> r = dconst<M>(v);
+  r.d[k] = 1.0;
+  return r;
+}
+// f(a) with f'(a) = fp
+template <int M>
+__device__ inline Dl<M> dchain(const Dl<M>& a, double f, double fp) {
+  Dl<M> r;
+  r.v = f;
+#pragma unroll
+  for (int i = 0; i < M; ++i) r.d[i] = fp * a.d[i];
+  return r;
+}
+template <int M>
+__device__ inline Dl<M> operator+(const Dl<M>& a, const Dl<M>& b) {
+  Dl<M> r;
+  r.v = a.v + b.v;
+#pragma unroll
+  for (int i = 0; i < M; ++i) r.d[i] = a.d[i] + b.d[i];
+  return r;
+}
+template <int M>
+__device__ inline Dl<M> operator-(const Dl<M>& a, const Dl<M>& b) {
+  Dl<M> r;
+  r.v = a.v - b.v;
+#pragma unroll
+  for (int i = 0; i < M; ++i) r.d[i] = a.d[i] - b.d[i];
+  return r;
+}
+template <int M>
+__device__ inline Dl<M> operator-(const Dl<M>& a) {
+  return dchain(a, -a.v, -1.0);
+}
+template <int M>
+__device__ inline Dl<M> operator*(const Dl<M>& a, const Dl<M>& b) {
+  Dl<M> r;
+  r.v = a.v * b.v;
+#pragma unroll
+  for (int i = 0; i < M; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+  return r;
+}
+template <int M>
+__device__ inline Dl<M> operator*(const Dl<M>& a, double b) {
+  return dchain(a, a.v * b, b);
+}
+template <int M>
+__device__ inline Dl<M> operator+(const Dl<M>& a, double b) {
+  return dchain(a, a.v + b, 1.0);
+}
+template <int M>
+__device__ inline Dl<M> operator/(const Dl<M>& a, const Dl<M>& b) {
+  Dl<M> r;
+  r.v = a.v / b.v;
+  const double ib = 1.0 / b.v;
+#pragma unroll
+  for (int i = 0; i < M; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) * ib;
+  return r;
+}
+template <int M>
+__device__ inline Dl<M> dsqrt(const Dl<M>& a) {
+  const double s = sqrt(a.v);
+  return dchain(a, s, 0.5 / s);
+}
+template <int M>
+__device__ inline Dl<M> dexp(const Dl<M>& a) {
+  const double e = exp(a.v);
+  return dchain(a, e, e);
+}
+template <int M>
+__device__ inline Dl<M> dlog(const Dl<M>& a) {
+  return dchain(a, log(a.v), 1.0 / a.v);
+}
+template <int M>
+__device__ inline Dl<M> datan(const Dl<M>& a) {
+  return dchain(a, atan(a.v), 1.0 / (1.0 + a.v * a.v));
+}
+template <int M>
+__device__ inline Dl<M> datanh(const Dl<M>& a) {
+  return dchain(a, atanh(a.v), 1.0 / (1.0 - a.v * a.v));
+}
+
+// atan(sqrt(s) u) / sqrt(s) (HYP false) or atanh(sqrt(s) u) / sqrt(s) (HYP
+// true), s = 1 - q^2 >= 0: below SIE_SERIES_S by the series
+// u sum_k (-+1)^k (s u^2)^k / (2k + 1), which also gives the round limit s = 0
+// and its derivative in s. The SIE keeps |u| <= 1/q for the atan and |u| <= 1
+// for the atanh, so s u^2 < 0.053 there and 15 terms reach 1e-19.
+constexpr double SIE_SERIES_S = 0.05;
+
+template <bool HYP, int M>
+__device__ inline Dl<M> atan_over_root(const Dl<M>& s, const Dl<M>& u) {
+  if (s.v < SIE_SERIES_S) {
+    const Dl<M> z = s * u * u;
+    constexpr int K = 14;
+    Dl<M> p = dconst<M>((HYP || K % 2 == 0 ? 1.0 : -1.0) / (2 * K + 1));
+    for (int k = K - 1; k >= 0; --k) p = p * z + (HYP || k % 2 == 0 ? 1.0 : -1.0) / (2 * k + 1);
+    return u * p;
+  }
+  const Dl<M> r = dsqrt(s);
+  return (HYP ? datanh(r * u) : datan(r * u)) / r;
+}
+
+// Deflection of SIE k at (x, y) with its derivatives in (x_c, y_c, theta_E, q,
+// phi): alpha' = theta_E sqrt(q) (atan(q' u)/q', atanh(q' v)/q'), u = x'/psi,
+// v = y'/psi, rotated back by phi (the same deflection as add_sie).
+__device__ inline void sie_deflection_d(const ModelConst& m, int k, double x, double y, Dl<5>& ax, Dl<5>& ay) {
+  const double* s = m.sie[k];
+  Dl<5> dx = dconst<5>(x - s[0]), dy = dconst<5>(y - s[1]);
+  dx.d[0] = -1.0;
+  dy.d[1] = -1.0;
+  Dl<5> c = dconst<5>(s[2]), sn = dconst<5>(s[3]);
+  c.d[4] = -s[3];
+  sn.d[4] = s[2];
+  const Dl<5> te = dvar<5>(s[7], 2), q = dvar<5>(s[8], 3);
+  const Dl<5> xp = c * dx + sn * dy, yp = c * dy - sn * dx;
+  const Dl<5> psi2 = q * q * xp * xp + yp * yp;
+  if (!(psi2.v > 0.0)) {   // the centre itself: no deflection
+    ax = ay = dconst<5>(0.0);
+    return;
+  }
+  const Dl<5> psi = dsqrt(psi2);
+  const Dl<5> ss = -(q * q) + 1.0;
+  const Dl<5> f = te * dsqrt(q);
+  const Dl<5> a1 = f * atan_over_root<false>(ss, xp / psi), a2 = f * atan_over_root<true>(ss, yp / psi);
+  ax = c * a1 - sn * a2;
+  ay = sn * a1 + c * a2;
+}
+
+// Sersic j at (px, py) and its gradient in (px, py).
+__device__ inline double sersic_and_grad(const ModelConst& m, int j, double px, double py, double& gx, double& gy) {
+  const double* s = m.ser[j];
+  const double dx = px - s[0], dy = py - s[1];
+  const double xp = s[2] * dx + s[3] * dy, yp = s[2] * dy - s[3] * dx;
+  const double R2 = s[4] * xp * xp + s[5] * yp * yp;
+  if (!(R2 > 0.0)) {
+    gx = gy = 0.0;
+    return s[9] * exp(s[8]);
+  }
+  const double t = exp(0.5 * s[7] * log(R2 * s[6] * s[6]));
+  const double S = s[9] * exp(-s[8] * (t - 1.0));
+  const double D = -s[8] * S * t * 0.5 * s[7] / R2;   // dS/dR^2
+  const double ex = 2.0 * s[4] * xp, ey = 2.0 * s[5] * yp;   // dR^2/dx', dR^2/dy'
+  gx = D * (ex * s[2] - ey * s[3]);
+  gy = D * (ex * s[3] + ey * s[2]);
+  return S;
+}
+
+// Sersic j at (px, py) with its derivatives in (x, y, I_e, R_e, n, q, phi).
+__device__ inline Dl<7> sersic_d(const ModelConst& m, int j, double px, double py) {
+  const double* s = m.ser[j];
+  Dl<7> dx = dconst<7>(px - s[0]), dy = dconst<7>(py - s[1]);
+  dx.d[0] = -1.0;
+  dy.d[1] = -1.0;
+  const Dl<7> Ie = dvar<7>(s[9], 2), Re = dvar<7>(1.0 / s[6], 3), n = dvar<7>(1.0 / s[7], 4), q = dvar<7>(s[4], 5);
+  Dl<7> c = dconst<7>(s[2]), sn = dconst<7>(s[3]), b = dconst<7>(s[8]);
+  c.d[6] = -s[3];
+  sn.d[6] = s[2];
+  b.d[4] = s[10];
+  const Dl<7> xp = c * dx + sn * dy, yp = c * dy - sn * dx;
+  const Dl<7> R2 = q * xp * xp + yp * yp / q;
+  const Dl<7> t = R2.v > 0.0 ? dexp(dlog(R2 / (Re * Re)) * (dconst<7>(0.5) / n)) : dconst<7>(0.0);
+  return Ie * dexp(-(b * (t + -1.0)));
+}
+
+// beta at (x, y) (every SIE, the shear), with SIE `skip` left out, and G.
+__device__ inline void source_side(const ModelConst& m, double x, double y, int skip, double& ax, double& ay) {
+  ax = m.g1 * x + m.g2 * y;
+  ay = m.g2 * x - m.g1 * y;
+  for (int k = 0; k < m.n_sie; ++k)
+    if (k != skip) add_sie(m, k, x, y, ax, ay);
+}
+__device__ inline void lensed_gradient(const ModelConst& m, double bx, double by, double& Gx, double& Gy) {
+  Gx = Gy = 0.0;
+  for (int j = 0; j < m.n_sersic; ++j)
+    if (m.plane[j]) {
+      double gx, gy;
+      sersic_and_grad(m, j, bx, by, gx, gy);
+      Gx += gx;
+      Gy += gy;
+    }
+}
+
+__global__ __launch_bounds__(RENDER_BLOCK) void model_grad_kernel(WorkArgs w, ModelSpec spec,
+                                                                   const ModelConst* __restrict__ mcs,
+                                                                   const float* __restrict__ G,
+                                                                   const int* __restrict__ gpbase,
+                                                                   double* __restrict__ gpart, int P) {
+  __shared__ double red[RENDER_BLOCK / 64][7];
+  int point, tile;
+  if (w.items) {
+    const int2 it = w.items[blockIdx.x];
+    point = it.x;
+    tile = it.y;
+  } else {
+    point = w.point0;
+    tile = blockIdx.x;
+  }
+  const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[point] : 0] : w.single;
+  const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
+  const ModelConst& m = mcs[point];
+  // the pass: SIE k, Sersic j, or the shear and the sky
+  const int pass = (int)blockIdx.y;
+  const int kind = pass < spec.n_sie ? 0 : (pass < spec.n_sie + spec.n_sersic ? 1 : 2);
+  const int comp = kind == 0 ? pass : pass - spec.n_sie;
+  const int off = kind == 0 ? 5 * comp : (kind == 1 ? 5 * spec.n_sie + (spec.shear ? 2 : 0) + 7 * comp : 5 * spec.n_sie);
+  const int npar = kind == 0 ? 5 : (kind == 1 ? 7 : (spec.shear ? 2 : 0) + (spec.sky ? 1 : 0));
+  double acc[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) acc[i] = 0.0;
+  const int pix = tile * RENDER_BLOCK + (int)threadIdx.x;
+  const float gp = pix < sd.H * sd.W ? G[loff + pix] : 0.0f;
+  if (gp != 0.0f) {   // pixels outside the reach of any weighted residual add nothing
+    const int r = row_of(sd, pix), c = pix - r * sd.W;
+    const double ux = (double)c - 0.5 * (double)(sd.W - 1), uy = (double)r - 0.5 * (double)(sd.H - 1);
+    const double d = sd.d, cx = sd.cx, cy = sd.cy;
+    const int N = sd.N;
+    const GkRule* R = sd.rule > 0 ? &kGkRules[sd.rule - 1] : nullptr;
+    for (int ky = 0; ky < N; ++ky) {
+      const double oy = R ? R->xd[ky] : ((double)ky + 0.5) / N - 0.5;
+      const double y = cy + (uy + oy) * d;
+      for (int kx = 0; kx < N; ++kx) {
+        const double ox = R ? R->xd[kx] : ((double)kx + 0.5) / N - 0.5;
+        const double wq = R ? (double)R->w[kx] * (double)R->w[ky] : 1.0;
+        const double x = cx + (ux + ox) * d;
+        if (kind == 0) {
+          double ax, ay, Gx, Gy;
+          source_side(m, x, y, comp, ax, ay);
+          Dl<5> akx, aky;
+          sie_deflection_d(m, comp, x, y, akx, aky);
+          lensed_gradient(m, x - ax - akx.v, y - ay - aky.v, Gx, Gy);
+#pragma unroll
+          for (int i = 0; i < 5; ++i) acc[i] -= wq * (Gx * akx.d[i] + Gy * aky.d[i]);
+        } else if (kind == 1) {
+          double px = x, py = y;
+          if (m.plane[comp]) {
+            double ax, ay;
+            source_side(m, x, y, -1, ax, ay);
+            px = x - ax;
+            py = y - ay;
+          }
+          const Dl<7> S = sersic_d(m, comp, px, py);
+#pragma unroll
+          for (int i = 0; i < 7; ++i) acc[i] += wq * S.d[i];
+        } else {
+          int i = 0;
+          if (spec.shear) {
+            double ax, ay, Gx, Gy;
+            source_side(m, x, y, -1, ax, ay);
+            lensed_gradient(m, x - ax, y - ay, Gx, Gy);
+            const double c2 = m.c2g, s2 = m.s2g;
+            // beta = x - alpha_SIE - Gamma x, Gamma = gamma [[c2, s2], [s2, -c2]]
+            acc[0] -= wq * (Gx * (c2 * x + s2 * y) + Gy * (s2 * x - c2 * y));
+            acc[1] -= wq * 2.0 * m.gam * (Gx * (c2 * y - s2 * x) + Gy * (c2 * x + s2 * y));
+            i = 2;
+          }
+          if (spec.sky) acc[i] += wq;
+        }
+      }
+    }
+    const double scale = (double)gp * sd.wgt;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) acc[i] *= scale;
+  }
+  // block sums in float64, in a fixed order
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    double v = acc[i];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0) red[wid][i] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < npar) {
+    const int i = threadIdx.x;
+    double v = red[0][i];
+    for (int k = 1; k < RENDER_BLOCK / 64; ++k) v += red[k][i];
+    // the sky is the model's last parameter; the other slots of a pass are consecutive
+    const int slot = kind == 2 && spec.sky && i == npar - 1 ? P - 1 : off + i;
+    gpart[(size_t)(gpbase[point] + tile) * P + slot] = v;
+  }
+}
+
+// grad[p][k] = sum over the point's render tiles, float64, rounded once.
+__global__ __launch_bounds__(64) void model_finalize_grad_kernel(const double* __restrict__ gpart,
+                                                                  const int* __restrict__ gpbase, int ntiles, int P,
+                                                                  float* __restrict__ grad, int point_base) {
+  const int p = point_base + (int)blockIdx.x;
+  const int base = gpbase[p];
+  for (int k = threadIdx.x; k < P; k += blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < ntiles; ++i) s += gpart[(size_t)(base + i) * P + k];
+    grad[(size_t)p * P + k] = (float)s;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_model_render(const WorkArgs& w, const ModelSpec& spec, const ModelConst* mcs, float* L, int n_blocks,
@@ -142,6 +466,29 @@ hipError_t launch_model_render(const WorkArgs& w, const ModelSpec& spec, const M
     hipLaunchKernelGGL(model_render_kernel, dim3(n), dim3(RENDER_BLOCK), 0, stream, part, spec, mcs, L);
     return hipGetLastError();
   });
+}
+
+hipError_t launch_model_grad(const WorkArgs& w, const ModelSpec& spec, const ModelConst* mcs, const float* G,
+                            const int* gpbase, double* gpart, int P, int n_blocks, hipStream_t stream) {
+  if (n_blocks <= 0) return hipSuccess;
+  const int passes = spec.n_sie + spec.n_sersic + ((spec.shear || spec.sky) ? 1 : 0);
+  return for_item_parts(w, n_blocks, [&](const WorkArgs& part, int n) {
+    hipLaunchKernelGGL(model_grad_kernel, dim3(n, passes), dim3(RENDER_BLOCK), 0, stream, part, spec, mcs, G, gpbase,
+                       gpart, P);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_model_finalize_grad(const double* gpart, const int* gpbase, int ntiles, int P, int n_points,
+                                      float* grad, hipStream_t stream) {
+  for (int p0 = 0; p0 < n_points; p0 += 1 << 20) {
+    const int np = n_points - p0 < (1 << 20) ? n_points - p0 : (1 << 20);
+    hipLaunchKernelGGL(model_finalize_grad_kernel, dim3((unsigned)np), dim3(64), 0, stream, gpart, gpbase, ntiles, P,
+                       grad, p0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace lensed

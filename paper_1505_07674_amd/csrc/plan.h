@@ -64,7 +64,8 @@ int square_psf_code(int ph, int pw);
 class BatchPlan {
  public:
   ~BatchPlan();
-  // grad == nullptr: log L only; otherwise also d log L / d theta (single system).
+  // grad == nullptr: log L only; otherwise also d log L / d theta (single system;
+  // with a general model, one lens plane).
   // K > 1 or sky: every image is the sum of K consecutive points plus sky[i]
   // pixscale^2 (sky per image); G > 1: every log L is the sum over G consecutive
   // images (the bands of a model). map has one entry per point.
@@ -87,8 +88,8 @@ class BatchPlan {
   // the fastest PSF + chi^2 stage, or the fastest render kernels, in milliseconds.
   hipError_t psf_ms(hipStream_t s, float* ms) const { return stage_ms(s, 3, ms); }
   hipError_t render_ms(hipStream_t s, float* ms) const { return stage_ms(s, 1, ms); }
-  // Whether a render class of this plan could take two pixels per thread.
-  bool pair_capable() const { return pair_capable_; }
+  // The most pixels per thread a render class of this plan could take (1 or 2).
+  int max_ppt() const { return max_ppt_; }
   // The schedule in use: PSF tile and pixels per thread of the midpoint classes.
   TileShape psf_tile() const { return {TW_, TH_}; }
   int render_ppt() const { return ppt_; }
@@ -136,6 +137,7 @@ class BatchPlan {
   int* d_gpbase_ = nullptr;       // first gradient-partial tile of each point
   float2* d_gpart_ = nullptr;     // [tiles][17] (hi, lo)
   double* d_gcorr_ = nullptr;     // [points][17] float64 cusp corrections
+  double* d_mgpart_ = nullptr;    // general-model gradients: [tiles][params per point]
   int grad_ntiles_ = 0;
   float* d_L_ = nullptr;
   float2* d_part_ = nullptr;
@@ -145,7 +147,7 @@ class BatchPlan {
   hipGraph_t graph_ = nullptr;
   hipGraphExec_t exec_ = nullptr;
   int ppt_ = 1;
-  bool pair_capable_ = false;
+  int max_ppt_ = 1;
   bool masked_ = false;
   int64_t rendered_pixels_ = 0;   // pixels the render stage computes per launch
   int64_t rendered_subsamples_ = 0;

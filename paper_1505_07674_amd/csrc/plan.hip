@@ -211,17 +211,14 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   // gradient and general-model plans keep one (their kernels walk the same items).
   ppt_ = force_ppt > 0 ? force_ppt : tiles.render_ppt(systems, n_systems);
   if (grad || model) ppt_ = 1;
-  std::vector<char> class_pairs(RENDER_MAX_CLASS + 1, 1);
-  class_pairs[0] = 0;
+  std::vector<int> class_div(RENDER_MAX_CLASS + 1, 2);   // pixels per thread each class allows
+  class_div[0] = 1;
   for (int s = 0; s < n_systems; ++s)
-    if (desc[s].W % 2 != 0) class_pairs[render_class(desc[s])] = 0;
-  pair_capable_ = !grad && !model;
-  if (pair_capable_) {
-    bool any = false;
-    for (int s = 0; s < n_systems; ++s) any = any || class_pairs[render_class(desc[s])];
-    pair_capable_ = any;
-  }
-  auto class_ppt = [&](int klass) { return ppt_ == 2 && class_pairs[klass] ? 2 : 1; };
+    if (desc[s].W % 2 != 0) class_div[render_class(desc[s])] = 1;
+  max_ppt_ = 1;
+  if (!grad && !model)
+    for (int s = 0; s < n_systems; ++s) max_ppt_ = std::max(max_ppt_, class_div[render_class(desc[s])]);
+  auto class_ppt = [&](int klass) { return std::min(ppt_, class_div[klass]); };
 
   // Masked plans: per system, the render units the chi^2 can see and the PSF
   // tiles that hold a pixel with w > 0 (from the weights, read back once here).
@@ -350,12 +347,15 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   const size_t o_L = off; off = align256(off + sizeof(float) * (size_t)Ltot);
   const size_t o_part = off; off = align256(off + sizeof(float2) * (size_t)ptot);
   const bool g = grad != nullptr;
-  const size_t o_gc = off; off = align256(off + (g ? sizeof(GradConst) * n_points : 0));
+  const bool g17 = g && !has_model_;   // the 17-parameter adjoint (else the general-model one)
+  const size_t o_gc = off; off = align256(off + (g17 ? sizeof(GradConst) * n_points : 0));
   const size_t o_R = off; off = align256(off + (g ? sizeof(float) * (size_t)Ltot : 0));
   const size_t o_gpb = off; off = align256(off + (g ? sizeof(int) * n_points : 0));
-  const size_t o_gpart = off; off = align256(off + (g ? sizeof(float2) * (size_t)gtot * NPAR : 0));
+  const size_t o_gpart = off; off = align256(off + (g17 ? sizeof(float2) * (size_t)gtot * NPAR : 0));
+  const size_t o_mgpart = off;
+  off = align256(off + (g && has_model_ ? sizeof(double) * (size_t)gtot * params_per_point : 0));
   const size_t o_adjk = off; off = align256(off + (g ? sizeof(float) * 16 * psf_total : 0));
-  const size_t o_gcorr = off; off = align256(off + (g ? sizeof(double) * (size_t)n_points * NPAR : 0));
+  const size_t o_gcorr = off; off = align256(off + (g17 ? sizeof(double) * (size_t)n_points * NPAR : 0));
   std::vector<size_t> o_units(n_systems);
   for (int s = 0; s < n_systems; ++s) {
     o_units[s] = off;
@@ -387,11 +387,12 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   if (masked_)
     for (int s = 0; s < n_systems; ++s) desc[s].active = (const int*)(mem_ + o_units[s]);
   if (g) {
-    d_gc_ = (GradConst*)(mem_ + o_gc);
+    d_gc_ = g17 ? (GradConst*)(mem_ + o_gc) : nullptr;
     d_R_ = (float*)(mem_ + o_R);
     d_gpbase_ = (int*)(mem_ + o_gpb);
-    d_gpart_ = (float2*)(mem_ + o_gpart);
-    d_gcorr_ = (double*)(mem_ + o_gcorr);
+    d_gpart_ = g17 ? (float2*)(mem_ + o_gpart) : nullptr;
+    d_mgpart_ = g17 ? nullptr : (double*)(mem_ + o_mgpart);
+    d_gcorr_ = g17 ? (double*)(mem_ + o_gcorr) : nullptr;
     grad_ntiles_ = desc[0].n_rtiles;
     for (int s = 0; s < n_systems; ++s) desc[s].adjk = (float*)(mem_ + o_adjk) + 16 * psf_off[s];
   }
@@ -450,8 +451,8 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
   if ((e = launch_prologue(theta_, has_model_ ? 0 : n_points_, d_pc_, d_p64_, d_gc_, none, d_sys_,
                            (int)systems_.size(), cusp_.count, st, d_gcorr_, d_point_sys_)) != hipSuccess)
     return e;
-  if (has_model_ &&
-      (e = launch_model_prologue(theta_, n_points_, params_per_point_, spec_, d_mc_, st)) != hipSuccess)
+  if (has_model_ && (e = launch_model_prologue(theta_, n_points_, params_per_point_, spec_, d_mc_, st,
+                                                grad_ != nullptr)) != hipSuccess)
     return e;
   if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
   WorkArgs wr = w;
@@ -487,12 +488,22 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
                                 s0.height, s0.width, st)) != hipSuccess)
       return e;
     if (ev && (e = hipEventRecord(ev[6], st)) != hipSuccess) return e;
-    if ((e = launch_grad(wr, d_pc_, d_p64_, d_gc_, d_L_, d_gpbase_, d_gpart_, n_ritems_, cusp_, d_gcorr_, st,
-                         ev ? ev[7] : nullptr)) != hipSuccess)
-      return e;
-    if ((e = launch_finalize_grad(d_gpart_, d_gpbase_, grad_ntiles_, n_points_, d_gcorr_, d_gc_, grad_, st)) !=
-        hipSuccess)
-      return e;
+    if (has_model_) {
+      if ((e = launch_model_grad(wr, spec_, d_mc_, d_L_, d_gpbase_, d_mgpart_, params_per_point_, n_ritems_, st)) !=
+          hipSuccess)
+        return e;
+      if (ev && (e = hipEventRecord(ev[7], st)) != hipSuccess) return e;
+      if ((e = launch_model_finalize_grad(d_mgpart_, d_gpbase_, grad_ntiles_, params_per_point_, n_points_, grad_,
+                                          st)) != hipSuccess)
+        return e;
+    } else {
+      if ((e = launch_grad(wr, d_pc_, d_p64_, d_gc_, d_L_, d_gpbase_, d_gpart_, n_ritems_, cusp_, d_gcorr_, st,
+                           ev ? ev[7] : nullptr)) != hipSuccess)
+        return e;
+      if ((e = launch_finalize_grad(d_gpart_, d_gpbase_, grad_ntiles_, n_points_, d_gcorr_, d_pc_, d_gc_, grad_,
+                                    st)) != hipSuccess)
+        return e;
+    }
     if (ev && (e = hipEventRecord(ev[8], st)) != hipSuccess) return e;
   } else if (ev) {
     for (int k = 6; k <= LENSED_NSTAGES; ++k)

@@ -474,7 +474,7 @@ __global__ __launch_bounds__(64) void prologue_kernel(const float* __restrict__ 
 // Sersic x, y, I_e, R_e, n, q, phi; sky) into ModelConst, b_n by the float64
 // Newton solve. An invalid point gets sky = NaN, which makes its image NaN.
 __global__ __launch_bounds__(64) void model_prologue_kernel(const float* __restrict__ theta, int n_points, int n_params, ModelSpec spec,
-                                      ModelConst* __restrict__ out) {
+                                      ModelConst* __restrict__ out, int with_db) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_points) return;
   const float* t = theta + (size_t)p * n_params;
@@ -485,7 +485,7 @@ __global__ __launch_bounds__(64) void model_prologue_kernel(const float* __restr
   m.n_sersic = spec.n_sersic;
   int o = 0;
   for (int k = 0; k < MAX_SIE; ++k) {
-    for (int i = 0; i < 7; ++i) m.sie[k][i] = 0.0;
+    for (int i = 0; i < 9; ++i) m.sie[k][i] = 0.0;
     m.sie_sphere[k] = 0;
     if (k >= spec.n_sie) continue;
     const double te = t[o + 2], q = t[o + 3], ph = t[o + 4];
@@ -499,16 +499,21 @@ __global__ __launch_bounds__(64) void model_prologue_kernel(const float* __restr
     m.sie[k][5] = qp;
     m.sie_sphere[k] = s2 == 0.0;
     m.sie[k][6] = s2 == 0.0 ? te : te * sqrt(q) / qp;
+    m.sie[k][7] = te;
+    m.sie[k][8] = q;
     o += 5;
   }
-  m.g1 = m.g2 = 0.0;
+  m.g1 = m.g2 = m.gam = m.c2g = m.s2g = 0.0;
   if (spec.shear) {
-    m.g1 = (double)t[o] * cos(2.0 * (double)t[o + 1]);
-    m.g2 = (double)t[o] * sin(2.0 * (double)t[o + 1]);
+    m.gam = t[o];
+    m.c2g = cos(2.0 * (double)t[o + 1]);
+    m.s2g = sin(2.0 * (double)t[o + 1]);
+    m.g1 = m.gam * m.c2g;
+    m.g2 = m.gam * m.s2g;
     o += 2;
   }
   for (int j = 0; j < MAX_SERSIC; ++j) {
-    for (int i = 0; i < 10; ++i) m.ser[j][i] = 0.0;
+    for (int i = 0; i < 11; ++i) m.ser[j][i] = 0.0;
     m.plane[j] = 0;
     if (j >= spec.n_sersic) continue;
     const double Re = t[o + 3], n = t[o + 4], q = t[o + 5], ph = t[o + 6];
@@ -524,6 +529,8 @@ __global__ __launch_bounds__(64) void model_prologue_kernel(const float* __restr
     m.ser[j][7] = 1.0 / n;
     m.ser[j][8] = valid ? sersic_bn(n) : 0.0;
     m.ser[j][9] = t[o + 2];
+    // db_n/dn by central differences of the root (truncation of order 1e-10 relative)
+    if (with_db && valid) m.ser[j][10] = (sersic_bn(n + 1e-5 * n) - sersic_bn(n - 1e-5 * n)) / (2e-5 * n);
     o += 7;
   }
   m.sky = spec.sky ? (double)t[o] : 0.0;
@@ -531,10 +538,10 @@ __global__ __launch_bounds__(64) void model_prologue_kernel(const float* __restr
 }
 
 hipError_t launch_model_prologue(const float* theta, int n_points, int n_params, const ModelSpec& spec,
-                                 ModelConst* out, hipStream_t stream) {
+                                 ModelConst* out, hipStream_t stream, bool with_db) {
   if (n_points <= 0) return hipSuccess;
   hipLaunchKernelGGL(model_prologue_kernel, dim3((n_points + 63) / 64), dim3(64), 0, stream, theta, n_points, n_params,
-                     spec, out);
+                     spec, out, with_db ? 1 : 0);
   return hipGetLastError();
 }
 
