@@ -15,7 +15,7 @@
 // over subsamples of products that vary per subsample, e.g. sum D h'_x^2),
 // so the kernels accumulate the moments and the final pass maps them to the
 // 17 partials in float64 (grad_from_moments). Sums are float32 per thread,
-// combined across the block with TwoSum and across tiles in float64.
+// combined across the block and across tiles in float64.
 #include <math.h>
 
 #include "internal.h"
@@ -25,12 +25,6 @@
 
 namespace lensed {
 namespace {
-
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
-  s = a + b;
-  const float bb = s - a;
-  e = (a - (s - bb)) + (b - bb);
-}
 
 __device__ __forceinline__ void resolve(const WorkArgs& w, int& point, int& tile) {
   if (w.items) {
@@ -125,8 +119,8 @@ __host__ __device__ inline int border_segments(int H, int W) {
   return border_row_segments(W) * (H > 1 ? 2 : 1) + border_side_segments(H) * (W > 1 ? 2 : 1);
 }
 // LDS floats of the largest window for a PSF of ph x pw.
-inline size_t border_lds_floats(int ph, int pw) {
-  const size_t row = (size_t)ph * (BORDER_SEG + pw - 1), col = (size_t)(BORDER_SEG + ph - 1) * pw;
+__host__ __device__ inline int border_lds_floats(int ph, int pw) {
+  const int row = ph * (BORDER_SEG + pw - 1), col = (BORDER_SEG + ph - 1) * pw;
   return row > col ? row : col;
 }
 
@@ -165,6 +159,13 @@ __global__ __launch_bounds__(BORDER_SEG* BORDER_SUB) void adj_border_kernel(Work
     const int r = i / WC, gi = wr0 + r, gj = wc0 + (i - r * WC);
     S[i] = (gi >= 0 && gi < H && gj >= 0 && gj < W) ? Rp[(size_t)gi * W + gj] : 0.0f;
   }
+  // PW > 0: the four folded tables the segment's pixels use (one row class,
+  // every column class; the side columns are all of row class 0) go to LDS too
+  const int ntab = sd.ph * pw;
+  float* __restrict__ SK = S + border_lds_floats(sd.ph, pw);
+  const int t0 = is_row ? 4 * ((H == 1) ? 3 : (u0 == 0 ? 1 : 2)) : 0;
+  if (PW > 0)
+    for (int i = (int)threadIdx.x; i < 4 * ntab; i += (int)blockDim.x) SK[i] = sd.adjk[(size_t)t0 * ntab + i];
   __syncthreads();
   const int j = (int)threadIdx.x / BORDER_SUB, sub = (int)threadIdx.x % BORDER_SUB;
   float acc = 0.0f;
@@ -172,7 +173,8 @@ __global__ __launch_bounds__(BORDER_SEG* BORDER_SUB) void adj_border_kernel(Work
   if (j < len) {
     const int cr = (H == 1) ? 3 : (u == 0 ? 1 : (u == H - 1 ? 2 : 0));
     const int cc = (W == 1) ? 3 : (v == 0 ? 1 : (v == W - 1 ? 2 : 0));
-    const float* __restrict__ K = sd.adjk + (size_t)(cr * 4 + cc) * sd.ph * pw;
+    const float* __restrict__ K =
+        PW > 0 ? SK + (size_t)(cr * 4 + cc - t0) * ntab : sd.adjk + (size_t)(cr * 4 + cc) * ntab;
     const int a_lo = max(-p, -u), a_hi = min(p, H - 1 - u);
     for (int a = a_lo + sub; a <= a_hi; a += BORDER_SUB) {
       const float* __restrict__ Kr = K + (a + p) * pw;
@@ -449,7 +451,8 @@ __global__ __launch_bounds__(RENDER_BLOCK, 6) void grad_kernel(WorkArgs w, const
                                                              const float* __restrict__ G,
                                                              const int* __restrict__ gpbase,
                                                              float2* __restrict__ gpart) {
-  __shared__ float red_hi[RENDER_BLOCK / 64][NPAR], red_lo[RENDER_BLOCK / 64][NPAR];
+  static_assert(RENDER_BLOCK == 256, "the block sums read four entries per lane");
+  __shared__ float part[NPAR][RENDER_BLOCK];
   int point, tile;
   resolve(w, point, tile);
   const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[point] : 0] : w.single;
@@ -491,41 +494,23 @@ __global__ __launch_bounds__(RENDER_BLOCK, 6) void grad_kernel(WorkArgs w, const
       for (int k = 0; k < NPAR; ++k) acc[k] *= wgt;
     }
   }
-  // block reduction of the 17 sums with error-free transformations
-  float lo[NPAR];
+  // block sums of the 17 moments: the threads' float32 sums go to LDS, wave w
+  // adds moments w, w + 4, ... in float64 (four entries per lane, then a fixed
+  // shuffle tree; float64 holds the sum of 256 float32 values exactly enough
+  // that no cancellation is lost), stored as a float32 pair hi + lo
 #pragma unroll
-  for (int k = 0; k < NPAR; ++k) lo[k] = 0.0f;
-  for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-    for (int k = 0; k < NPAR; ++k) {
-      const float h2 = __shfl_down(acc[k], off, 64);
-      const float l2 = __shfl_down(lo[k], off, 64);
-      float s, e;
-      two_sum(acc[k], h2, s, e);
-      acc[k] = s;
-      lo[k] = lo[k] + l2 + e;
-    }
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < NPAR; ++k) {
-      red_hi[wid][k] = acc[k];
-      red_lo[wid][k] = lo[k];
-    }
-  }
+  for (int k = 0; k < NPAR; ++k) part[k][threadIdx.x] = acc[k];
   __syncthreads();
-  if (threadIdx.x < NPAR) {
-    const int k = threadIdx.x;
-    float h = red_hi[0][k], l = red_lo[0][k];
-    for (int i = 1; i < RENDER_BLOCK / 64; ++i) {
-      float s, e;
-      two_sum(h, red_hi[i][k], s, e);
-      h = s;
-      l = l + red_lo[i][k] + e;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int base = gpbase ? gpbase[point] : 0;
+  for (int k = wid; k < NPAR; k += RENDER_BLOCK / 64) {
+    double v = ((double)part[k][lane] + (double)part[k][lane + 64]) +
+               ((double)part[k][lane + 128] + (double)part[k][lane + 192]);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) {
+      const float hi = (float)v;
+      gpart[(size_t)(base + tile) * NPAR + k] = make_float2(hi, (float)(v - (double)hi));
     }
-    const int base = gpbase ? gpbase[point] : 0;
-    gpart[(size_t)(base + tile) * NPAR + k] = make_float2(h, l);
   }
 }
 
@@ -738,7 +723,8 @@ hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n
   }
   if (e != hipSuccess) return e;
   const int nseg = border_segments(H, W);
-  const size_t blds = border_lds_floats(ph, pw) * sizeof(float);
+  // the window, and with 21-wide tables also the four tables of a segment
+  const size_t blds = (size_t)(border_lds_floats(ph, pw) + (pw == 21 ? 4 * ph * pw : 0)) * sizeof(float);
   // one grid row per point, at most 65535 rows per launch
   for (int p0 = 0; p0 < n_points; p0 += 65535) {
     const int np = n_points - p0 < 65535 ? n_points - p0 : 65535;
