@@ -796,6 +796,9 @@ static int run_grad(lensed_ctx* c, const lensed_system* sys, const float* theta,
       LENSED_HIP(c, hipDeviceSynchronize());
       c->plans.erase(c->plans.begin());
     }
+    // the render schedule: as fixed by LENSED_RENDER_PPT, else as measured for
+    // these shapes by a batched call (one pixel per thread when none was)
+    if (c->force_ppt) c->tiles.set_render_measured(sys, 1, c->force_ppt);
     std::unique_ptr<BatchPlan> np(new BatchPlan());
     std::string msg;
     hipError_t e = np->build(sys, 1, theta, map.data(), n_points, logl, c->tiles, msg, grad, nullptr, 1, nullptr, 1,

@@ -208,15 +208,16 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
 
   // Pixels per render thread: two for a midpoint class whose images all have
   // an even width (a pair never straddles two rows), if the schedule says so;
-  // gradient and general-model plans keep one (their kernels walk the same items).
+  // general-model plans keep one (their kernel walks one pixel per thread). The
+  // gradient kernels have item lists of their own.
   ppt_ = force_ppt > 0 ? force_ppt : tiles.render_ppt(systems, n_systems);
-  if (grad || model) ppt_ = 1;
+  if (model) ppt_ = 1;
   std::vector<int> class_div(RENDER_MAX_CLASS + 1, 2);   // pixels per thread each class allows
   class_div[0] = 1;
   for (int s = 0; s < n_systems; ++s)
     if (desc[s].W % 2 != 0) class_div[render_class(desc[s])] = 1;
   max_ppt_ = 1;
-  if (!grad && !model)
+  if (!model)
     for (int s = 0; s < n_systems; ++s) max_ppt_ = std::max(max_ppt_, class_div[render_class(desc[s])]);
   auto class_ppt = [&](int klass) { return std::min(ppt_, class_div[klass]); };
 
@@ -325,6 +326,12 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   n_pitems_ = (int)pitems.size();
   std::vector<int2> ri(n_ritems_), pi(n_pitems_);
   for (int i = 0; i < n_ritems_; ++i) ri[i] = make_int2(ritems[i].point, ritems[i].tile);
+  // the gradient kernels take one pixel per thread: (point, 256-pixel tile) items
+  std::vector<int2> gi;
+  if (grad)
+    for (int p = 0; p < n_points; ++p)
+      for (int t = 0; t < desc[map[p]].n_rtiles; ++t) gi.push_back(make_int2(p, t));
+  n_gitems_ = (int)gi.size();
   for (int i = 0; i < n_pitems_; ++i) pi[i] = make_int2(pitems[i].point, pitems[i].tile);
 
   // one device allocation for every table and scratch buffer of the plan
@@ -337,6 +344,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   const size_t o_mpb = off; off = align256(off + sizeof(int) * n_models_);
   const size_t o_mnt = off; off = align256(off + sizeof(int) * n_models_);
   const size_t o_ri = off; off = align256(off + sizeof(int2) * n_ritems_);
+  const size_t o_gi = off; off = align256(off + sizeof(int2) * n_gitems_);
   const size_t o_pi = off; off = align256(off + sizeof(int2) * n_pitems_);
   const size_t o_pc = off; off = align256(off + sizeof(PointConst) * n_points);
   const size_t o_mc = off; off = align256(off + (has_model_ ? sizeof(ModelConst) * n_points : 0));
@@ -375,6 +383,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   d_mpbase_ = (int*)(mem_ + o_mpb);
   d_mntiles_ = (int*)(mem_ + o_mnt);
   d_ritems_ = (int2*)(mem_ + o_ri);
+  d_gitems_ = n_gitems_ ? (int2*)(mem_ + o_gi) : nullptr;
   d_pitems_ = (int2*)(mem_ + o_pi);
   d_pc_ = (PointConst*)(mem_ + o_pc);
   d_mc_ = has_model_ ? (ModelConst*)(mem_ + o_mc) : nullptr;
@@ -412,6 +421,8 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
       (e = hipMemcpy(d_mpbase_, mpbase.data(), sizeof(int) * n_models_, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_mntiles_, mntiles.data(), sizeof(int) * n_models_, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_ritems_, ri.data(), sizeof(int2) * n_ritems_, hipMemcpyHostToDevice)) != hipSuccess ||
+      (n_gitems_ &&
+       (e = hipMemcpy(d_gitems_, gi.data(), sizeof(int2) * n_gitems_, hipMemcpyHostToDevice)) != hipSuccess) ||
       (e = hipMemcpy(d_pitems_, pi.data(), sizeof(int2) * n_pitems_, hipMemcpyHostToDevice)) != hipSuccess ||
       (g && (e = hipMemcpy(d_gpbase_, gpbase.data(), sizeof(int) * n_points, hipMemcpyHostToDevice)) != hipSuccess)) {
     msg = "uploading work lists";
@@ -482,6 +493,9 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
   if ((e = launch_finalize(d_part_, d_mpbase_, d_mntiles_, n_models_, 0, logl_, st)) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[5], st)) != hipSuccess) return e;
   if (grad_) {
+    WorkArgs wg = w;
+    wg.items = d_gitems_;
+    wg.n_items = n_gitems_;
     // g = A^T rho overwrites the unconvolved images, which are no longer needed
     const lensed_system& s0 = systems_[0];
     if ((e = launch_adjoint_psf(wp, d_R_, d_L_, n_pitems_, square_psf_, TW_, TH_, max_ph_, max_pw_, n_points_,
@@ -489,7 +503,7 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
       return e;
     if (ev && (e = hipEventRecord(ev[6], st)) != hipSuccess) return e;
     if (has_model_) {
-      if ((e = launch_model_grad(wr, spec_, d_mc_, d_L_, d_gpbase_, d_mgpart_, params_per_point_, n_ritems_, st)) !=
+      if ((e = launch_model_grad(wg, spec_, d_mc_, d_L_, d_gpbase_, d_mgpart_, params_per_point_, n_gitems_, st)) !=
           hipSuccess)
         return e;
       if (ev && (e = hipEventRecord(ev[7], st)) != hipSuccess) return e;
@@ -497,7 +511,7 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
                                           st)) != hipSuccess)
         return e;
     } else {
-      if ((e = launch_grad(wr, d_pc_, d_p64_, d_gc_, d_L_, d_gpbase_, d_gpart_, n_ritems_, cusp_, d_gcorr_, st,
+      if ((e = launch_grad(wg, d_pc_, d_p64_, d_gc_, d_L_, d_gpbase_, d_gpart_, n_gitems_, cusp_, d_gcorr_, st,
                            ev ? ev[7] : nullptr)) != hipSuccess)
         return e;
       if ((e = launch_finalize_grad(d_gpart_, d_gpbase_, grad_ntiles_, n_points_, d_gcorr_, d_pc_, d_gc_, grad_,

@@ -117,3 +117,23 @@ def test_autotuner_records_a_render_schedule():
     assert sched["psf_tile"][0] > 0 and sched["psf_tile"][1] > 0
     assert torch.all(torch.isfinite(ll))
     ctx.close()
+
+
+def test_gradient_plans_take_the_render_schedule():
+    """A gradient plan renders with the schedule's pixels per thread while its
+    gradient kernels keep their own one-pixel items: log L and gradient agree
+    bit for bit between the schedules."""
+    from test_gpu_grad import gpu_system as grad_system, small_obs, small_spec
+    spec = small_spec(H=40, W=36, N=4)
+    obs = small_obs(spec)
+    gs = grad_system(spec, obs)
+    pts = torch.from_numpy(mocks.points(spec, 12, seed=61)).to(DEV)
+    out = {}
+    for ppt in (1, 2):
+        ctx = context_with(ppt)
+        ll, g = lensed.loglike_grad(pts, gs, ctx=ctx)
+        out[ppt] = (ll.cpu().numpy(), g.cpu().numpy())
+        ctx.close()
+    assert np.all(np.isfinite(out[1][1]))
+    assert np.array_equal(out[1][0], out[2][0])
+    assert np.array_equal(out[1][1], out[2][1])
