@@ -196,54 +196,6 @@ __global__ __launch_bounds__(BORDER_SEG* BORDER_SUB) void adj_border_kernel(Work
 // Per-subsample partial derivatives.
 // ---------------------------------------------------------------------------
 
-// Uniform per-point values used by the gradient kernel.
-struct GradUniform {
-  float te, sq, q, s, iqp;   // theta_E, sqrt(q), q, s = 1 - q^2, 1/q' (0 when q = 1)
-  float c2, s2, gam;         // shear: cos 2phi, sin 2phi, gamma
-  float RH, RS;              // half-light radii
-  float qH, qS;              // Sersic axis ratios
-  float bH, bS;              // natural-log Sersic constants b = B ln 2
-  float dbH, dbS;            // db/dn
-  // reciprocals of the per-point divisors, so that no subsample divides:
-  float hs, iq, iq2, hsq;    // 1/(2s), 1/q, 1/q^2, 1/(2 sqrt q)
-  float m2iRH, m2iRS;        // -2/R_H, -2/R_S
-  float iqH, iqS;            // 1/q_H, 1/q_S
-  float kS1, kS2;            // cos, sin (phi_S - phi_L): source-frame gradient into the SIE frame
-};
-
-__device__ __forceinline__ GradUniform grad_uniform(const PointConst& c, const GradConst& gc) {
-  GradUniform U;
-  U.te = gc.theta[0];
-  U.q = gc.theta[1];
-  U.sq = sqrtf(U.q);
-  U.s = (1.0f - U.q) * (1.0f + U.q);
-  U.iqp = c.sie_mode == 0 ? 0.0f : 1.0f / c.qp;
-  float s2, c2;
-  sincosf(2.0f * gc.theta[4], &s2, &c2);
-  U.c2 = c2;
-  U.s2 = s2;
-  U.gam = gc.theta[3];
-  U.RH = gc.theta[6];
-  U.RS = gc.theta[13];
-  U.qH = gc.theta[8];
-  U.qS = gc.theta[15];
-  U.bH = c.hB * LN2F;
-  U.bS = c.sB * LN2F;
-  U.dbH = gc.dB_dn_h * LN2F;
-  U.dbS = gc.dB_dn_s * LN2F;
-  U.hs = 0.5f / U.s;
-  U.iq = 1.0f / U.q;
-  U.iq2 = 1.0f / (U.q * U.q);
-  U.hsq = 0.5f / U.sq;
-  U.m2iRH = -2.0f / U.RH;
-  U.m2iRS = -2.0f / U.RS;
-  U.iqH = 1.0f / U.qH;
-  U.iqS = 1.0f / U.qS;
-  U.kS1 = c.sc * c.cL + c.ss * c.sL;
-  U.kS2 = c.ss * c.cL - c.sc * c.sL;
-  return U;
-}
-
 // Sersic value and derivatives at scaled squared radius rho2.
 struct SersicD {
   float I, E, D;     // value, I/I_e, dI/drho2
@@ -287,7 +239,9 @@ constexpr float S_SERIES = 0.0625f;   // use the series for 1 - q^2 below this
 // quadrature weight sw when WT (a Gauss-Kronrod node). With `override`, the
 // offset of beta from the source centre is (odx, ody) instead of the float32
 // lens equation (the float64 re-traced value near a cuspy source).
-template <int MODE, bool WT = false>
+// SER: 1 the series in s, 0 the closed form, -1 chosen here by s (a per-point
+// choice that a caller may take once outside its subsample loop).
+template <int MODE, bool WT = false, int SER = -1>
 __device__ __forceinline__ void subsample_grad(const PointConst& c, const GradUniform& U, float x, float y,
                                                float (&acc)[NPAR], bool override = false, float odx = 0.0f,
                                                float ody = 0.0f, float sw = 1.0f) {
@@ -315,10 +269,10 @@ __device__ __forceinline__ void subsample_grad(const PointConst& c, const GradUn
     const float num = fmaf(c.qp, fabsf(yp), psi);
     b = live ? copysignf(LN2F * hw_log2(num * ir * c.iq), yp) * U.iqp : 0.0f;
   }
-  const float apx = U.te * U.sq * a, apy = U.te * U.sq * b;   // alpha' in the frame
+  const float apx = U.tesq * a, apy = U.tesq * b;   // alpha' in the frame
   // d/ds of a and b
   float da, db;
-  if (U.s < S_SERIES) {
+  if (SER == 1 || (SER < 0 && U.s < S_SERIES)) {
     da = datan_ds_series(U.s, u0);
     db = datanh_ds_series(U.s, v0);
   } else {
@@ -414,7 +368,7 @@ __device__ void grad_from_moments(const double (&M)[NPAR], const PointConst& c, 
 // The subsample offsets (k + 1/2)/N - 1/2 by a multiply with 1/N (to a float32
 // rounding of the quotient: the gradient needs the abscissae to float32
 // accuracy, not bit for bit those of the render).
-template <int MODE>
+template <int MODE, int SER>
 __device__ __forceinline__ void pixel_grad(const PointConst& c, const GradUniform& U, int N, const PixelGeom& g,
                                            float (&acc)[NPAR]) {
   const float iN = 1.0f / (float)N;
@@ -422,7 +376,7 @@ __device__ __forceinline__ void pixel_grad(const PointConst& c, const GradUnifor
     const float y = fmaf(g.uy + fmaf((float)ky + 0.5f, iN, -0.5f), g.d, g.cy);
     for (int kx = 0; kx < N; ++kx) {
       const float x = fmaf(g.ux + fmaf((float)kx + 0.5f, iN, -0.5f), g.d, g.cx);
-      subsample_grad<MODE>(c, U, x, y, acc);
+      subsample_grad<MODE, false, SER>(c, U, x, y, acc);
     }
   }
 }
@@ -444,8 +398,11 @@ __device__ __forceinline__ void pixel_grad_gk(const PointConst& c, const GradUni
 
 // One thread per pixel, one block per (point, render tile): sums
 // g_pix * d^2/N^2 * dI/dtheta over the pixel's subsamples, then over the block.
-// Six waves per SIMD (at most 80 VGPRs, no spills) hide the latency of the
-// transcendental chains better than the five the registers would otherwise allow.
+// The series-or-closed-form choice of the SIE's d/ds is per point, taken once
+// outside the subsample loops. Six waves per SIMD (at most 80 VGPRs, no
+// spills) hide the latency of the transcendental chains better than five.
+// (A kernel per N with the midpoint loops unrolled issued 7 % fewer
+// instructions but needed 96 VGPRs, and five waves ran 6 % slower.)
 __global__ __launch_bounds__(RENDER_BLOCK, 6) void grad_kernel(WorkArgs w, const PointConst* __restrict__ pcs,
                                                              const GradConst* __restrict__ gcs,
                                                              const float* __restrict__ G,
@@ -459,7 +416,7 @@ __global__ __launch_bounds__(RENDER_BLOCK, 6) void grad_kernel(WorkArgs w, const
   const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
   const PointConst& c = pcs[point];
   const GradConst& gc = gcs[point];
-  const GradUniform U = grad_uniform(c, gc);
+  const GradUniform& U = gc.u;
 
   float acc[NPAR];
 #pragma unroll
@@ -477,10 +434,17 @@ __global__ __launch_bounds__(RENDER_BLOCK, 6) void grad_kernel(WorkArgs w, const
       geo.cx = sd.cx;
       geo.cy = sd.cy;
       if (sd.rule == 0) {
+        const bool ser = U.s < S_SERIES;
         switch (c.sie_mode) {
-          case 0: pixel_grad<0>(c, U, sd.N, geo, acc); break;
-          case 1: pixel_grad<1>(c, U, sd.N, geo, acc); break;
-          default: pixel_grad<2>(c, U, sd.N, geo, acc); break;
+          case 0: pixel_grad<0, 1>(c, U, sd.N, geo, acc); break;   // q = 1: s = 0
+          case 1:
+            if (ser) pixel_grad<1, 1>(c, U, sd.N, geo, acc);
+            else pixel_grad<1, 0>(c, U, sd.N, geo, acc);
+            break;
+          default:
+            if (ser) pixel_grad<2, 1>(c, U, sd.N, geo, acc);
+            else pixel_grad<2, 0>(c, U, sd.N, geo, acc);
+            break;
         }
       } else {
         switch (c.sie_mode) {
@@ -562,7 +526,7 @@ __global__ __launch_bounds__(64 * GCUSP_WAVES) void grad_cusp_kernel(WorkArgs w,
     const int64_t loff = w.point_loff ? w.point_loff[e.point] : 0;
     const PointConst& c = pcs[e.point];
     const GradConst& gc = gcs[e.point];
-    const GradUniform U = grad_uniform(c, gc);
+    const GradUniform& U = gc.u;
     const int lpix = mine ? unit_pixel(sd, e.unit0 + lane, e.ppt) + e.half : 0;   // this lane's pixel
     const PixelGeom geo = gcusp_geom(sd, lpix);
     // the render constants the forward render used for this lane's pixel

@@ -109,6 +109,19 @@ struct PointConst64 {
 };
 static_assert(sizeof(PointConst64) == 16 * 8, "PointConst64 layout");
 
+// Per-point values of the gradient's per-subsample arithmetic, derived in
+// float64 by the prologue and read with uniform addresses (scalar registers).
+struct GradUniform {
+  float tesq;          // theta_E sqrt(q)
+  float iqp;           // 1/q' (0 when q = 1)
+  float s;             // 1 - q^2
+  float hs;            // 1/(2 s) (0 when s = 0)
+  float iq2;           // 1/q^2
+  float bH, bS;        // natural-log Sersic constants b_n of the lens light and the source
+  float dbH, dbS;      // db_n/dn
+  float kS1, kS2;      // cos, sin (phi_S - phi_L): source-frame gradient into the SIE frame
+};
+
 // Extra per-point values needed by the adjoint.
 struct GradConst {
   float theta[NPAR];   // raw parameters
@@ -126,9 +139,10 @@ struct GradConst {
   // phi_gamma), row-major.
   float src_jac[14];
   int srcpos;
-  float pad[5];
+  GradUniform u;
+  float pad[10];
 };
-static_assert(sizeof(GradConst) == 48 * 4, "GradConst layout");
+static_assert(sizeof(GradConst) == 64 * 4, "GradConst layout");
 
 // Geometry and schedule of one system (one observation).
 struct SysDesc {

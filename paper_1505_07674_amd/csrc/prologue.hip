@@ -462,7 +462,19 @@ __global__ __launch_bounds__(64) void prologue_kernel(const float* __restrict__ 
     gc.amp = amp;
     for (int k = 0; k < 14; ++k) gc.src_jac[k] = jac[k];
     gc.srcpos = srcpos;
-    for (int k = 0; k < 5; ++k) gc.pad[k] = 0.0f;
+    GradUniform& u = gc.u;
+    u.tesq = (float)(te * sqrt(q));
+    u.iqp = s2 == 0.0 ? 0.0f : (float)(1.0 / qp);
+    u.s = (float)s2;
+    u.hs = s2 == 0.0 ? 0.0f : (float)(0.5 / s2);
+    u.iq2 = (float)(1.0 / (q * q));
+    u.bH = (float)bh;
+    u.bS = (float)bs;
+    u.dbH = (float)dbh;
+    u.dbS = (float)dbs;
+    u.kS1 = (float)cos((double)t[16] - phL);
+    u.kS2 = (float)sin((double)t[16] - phL);
+    for (int k = 0; k < 10; ++k) gc.pad[k] = 0.0f;
     gcs[p] = gc;
   }
 }
