@@ -101,6 +101,19 @@ def test_gradient_when_the_signal_reaches_the_border():
     check(spec, obs, pts)
 
 
+@pytest.mark.parametrize("H,W,P", [(1, 9, 5), (2, 11, 21), (9, 1, 5), (13, 2, 21), (3, 70, 21), (66, 3, 7)])
+def test_gradient_on_degenerate_image_shapes(H, W, P):
+    """Images one to three pixels high or wide: every pixel touches the border,
+    the first and last rows (columns) coincide when H = 1 (W = 1), and the
+    border segments of A^T rho are ragged (their window staged with zeros)."""
+    psf = mocks.moffat_psf(P, 0.3, 3.0, 0.2)
+    spec = small_spec(H=H, W=W, N=2, psf=psf, pixscale=0.2, center=(0.1, -0.05))
+    say(f"gradient, {H}x{W} sub2, {P}x{P} PSF")
+    obs = small_obs(spec)
+    pts = mocks.points(spec, 6, seed=59 + H + W)
+    check(spec, obs, pts)
+
+
 def test_gradient_isothermal_sphere_and_round_source():
     spec = small_spec(H=32, W=32, N=4)
     say("gradient, q = 1 lens")
