@@ -452,7 +452,10 @@ def main():
                      "subsamples_per_launch": subs * P},
         "psf_chi2_tflops": psf_tflops,
         "schedule": {"psf_tile": schedule["psf_tile"], "render_pixels_per_thread": schedule["render_pixels_per_thread"],
-                     "chosen_by": "autotuner (timed on this launch)"},
+                     "render_block": schedule["render_block"],
+                     "chosen_by": ("fixed by LENSED_RENDER_PPT / LENSED_RENDER_BLOCK"
+                                   if os.environ.get("LENSED_RENDER_PPT") or os.environ.get("LENSED_RENDER_BLOCK")
+                                   else "autotuner (timed on this launch)")},
         "masked": masked,
         "mixed_batch": mixed,
         "extensions": extensions,

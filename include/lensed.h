@@ -184,11 +184,13 @@ int lensed_loglike_noalloc(const lensed_system* sys, const float* theta, double*
  * keyed by the systems, the mapping and the theta/logl pointers. The first call
  * for a new set of system shapes also autotunes the schedule: it times the PSF +
  * chi^2 stage of the cost model's six best-ranked tile shapes, then the render
- * kernels with one and with two pixels per thread, on this launch
- * (synchronising `stream`), and keeps the fastest for every later plan over the
- * same shapes; LENSED_NO_AUTOTUNE=1 in the environment keeps the model's tile
- * and one pixel per thread, LENSED_RENDER_PPT=1 or 2 (read by lensed_create)
- * fixes the render schedule. Every schedule gives the same results bit for bit. */
+ * kernels with one and with two pixels per thread in blocks of 128, 256 and
+ * 512 threads, on this launch (synchronising `stream`), and keeps the fastest
+ * for every later plan over the same shapes; LENSED_NO_AUTOTUNE=1 in the
+ * environment keeps the model's tile and one pixel per thread in 256-thread
+ * blocks, LENSED_RENDER_PPT=1 or 2 and LENSED_RENDER_BLOCK=128, 256 or 512
+ * (read by lensed_create) fix the render schedule. Every schedule gives the
+ * same results bit for bit. */
 int lensed_loglike_batch(lensed_ctx* ctx, const lensed_system* systems, int n_systems,
                          const float* theta, const int32_t* system_of_point, int n_points,
                          double* logl, void* stream);
@@ -435,6 +437,11 @@ int lensed_stage_times(lensed_ctx* ctx, double* ms, int n, int* calls);
  * fastest (unless LENSED_NO_AUTOTUNE is set). out is a HOST array of 3 ints;
  * all zero before any batched call. INVALID_ARGUMENT if out is NULL. */
 int lensed_batch_schedule(lensed_ctx* ctx, int* out);
+
+/* Threads per block of the render kernels in the most recent batched call
+ * (128, 256 or 512; chosen with the pixels per thread, as above). out is a
+ * HOST int, zero before any batched call. INVALID_ARGUMENT if out is NULL. */
+int lensed_batch_render_block(lensed_ctx* ctx, int* out);
 
 /* Work of the most recent batched call: out[0] pixels and out[1] subsamples
  * (integration points) its render stage evaluates per launch (all pixels of

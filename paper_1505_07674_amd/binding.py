@@ -147,6 +147,7 @@ def lib():
                 "lensed_mlp_train_step": (i, [vp, vp, vp, vp, i, vp, vp, vp, i, ctypes.c_double, vp, vp]),
                 "lensed_stage_times": (i, [vp, ctypes.POINTER(ctypes.c_double), i, ctypes.POINTER(ctypes.c_int)]),
                 "lensed_batch_schedule": (i, [vp, ctypes.POINTER(ctypes.c_int)]),
+                "lensed_batch_render_block": (i, [vp, ctypes.POINTER(ctypes.c_int)]),
                 "lensed_batch_rendered": (i, [vp, ctypes.POINTER(ctypes.c_int64)]),
                 "lensed_loglike_batch_masked": (i, [vp, sp, i, vp, ctypes.POINTER(ctypes.c_int32), i, vp, vp]),
             }
@@ -193,10 +194,13 @@ class Context:
         return dict(zip(self.STAGES, list(ms))), calls.value
 
     def batch_schedule(self):
-        """Schedule of the most recent batched call: PSF + chi^2 tile (width, height) and render pixels per thread."""
+        """Schedule of the most recent batched call: PSF + chi^2 tile (width, height), render pixels per thread
+        and render threads per block."""
         out = (ctypes.c_int * 3)()
         self.check(lib().lensed_batch_schedule(self._h, out), "lensed_batch_schedule")
-        return {"psf_tile": [out[0], out[1]], "render_pixels_per_thread": out[2]}
+        block = ctypes.c_int()
+        self.check(lib().lensed_batch_render_block(self._h, ctypes.byref(block)), "lensed_batch_render_block")
+        return {"psf_tile": [out[0], out[1]], "render_pixels_per_thread": out[2], "render_block": block.value}
 
     def batch_rendered(self):
         """Pixels and subsamples the render stage of the most recent batched call evaluates per launch."""

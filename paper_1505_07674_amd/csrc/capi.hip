@@ -38,12 +38,14 @@ struct lensed_ctx {
   bool use_graphs = true;
   bool autotune = true;             // time the best-ranked tile shapes on the first batch of a shape set
   int force_ppt = 0;                // 1 or 2: render pixels per thread fixed (not timed)
+  int force_block = 0;              // 128, 256 or 512: render threads per block fixed (not timed)
   std::vector<std::unique_ptr<BatchPlan>> plans;   // most recently used last
   TileCache tiles;
   bool profiling = false;                          // per-stage hipEvents, no graphs
   std::vector<std::vector<hipEvent_t>> pending;    // event sets of profiled calls
   double stage_ms[LENSED_NSTAGES] = {0};
-  int schedule[3] = {0, 0, 0};   // of the last batched plan run: PSF tile width, height; render pixels per thread
+  int schedule[4] = {0, 0, 0, 0};   // of the last batched plan run: PSF tile width, height; render pixels per
+                                    // thread, threads per render block
   int64_t rendered[2] = {0, 0};  // of the last batched plan run: pixels and subsamples rendered per launch
   int stage_calls = 0;
   char* mlp_mem = nullptr;                          // surrogate scratch
@@ -248,6 +250,9 @@ int lensed_create(lensed_ctx** out, int device) {
   c->autotune = !(t && t[0] == '1');
   const char* r = std::getenv("LENSED_RENDER_PPT");
   c->force_ppt = (r && (r[0] == '1' || r[0] == '2') && r[1] == 0) ? r[0] - '0' : 0;
+  const char* rb = std::getenv("LENSED_RENDER_BLOCK");
+  const int fb = rb ? std::atoi(rb) : 0;
+  c->force_block = (fb == 128 || fb == 256 || fb == 512) ? fb : 0;
   *out = c;
   return LENSED_OK;
 }
@@ -474,27 +479,40 @@ int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const 
       }
       c->tiles.set_measured(systems, n_systems, best);
     }
-    if (c->force_ppt) {
-      c->tiles.set_render_measured(systems, n_systems, c->force_ppt);
+    if (model) {
+      // the general-model render takes one pixel per thread in 256-thread blocks
+      c->tiles.set_render_measured(systems, n_systems, RenderSchedule{1, RENDER_BLOCK});
+    } else if (c->force_ppt || c->force_block) {
+      c->tiles.set_render_measured(systems, n_systems,
+                                   RenderSchedule{c->force_ppt ? c->force_ppt : 1,
+                                                  c->force_block ? c->force_block : RENDER_BLOCK});
     } else if (c->autotune && !c->tiles.has_render_measured(systems, n_systems)) {
       // Render schedule: one or two pixels per thread (two share the row terms
-      // of the subsample grid), timed the same way on this launch's render kernels.
-      int best = 1;
+      // of the subsample grid) in blocks of 128, 256 or 512 threads, timed the
+      // same way on this launch's render kernels.
+      RenderSchedule best{1, RENDER_BLOCK};
       float best_ms = 1e30f;
-      for (int ppt = 1; ppt <= 2; ++ppt) {
-        BatchPlan trial;
-        std::string msg;
-        if (trial.build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg, nullptr, nullptr,
-                        K, sky, G, model, params_per_point, ppt, masked) != hipSuccess) {
-          (void)hipGetLastError();
-          continue;
-        }
-        if (trial.max_ppt() < 2) break;   // nothing to choose: every class renders one pixel per thread
-        float ms = 0.0f;
-        LENSED_HIP(c, trial.render_ms((hipStream_t)stream, &ms));
-        if (ms < best_ms) {
-          best_ms = ms;
-          best = ppt;
+      bool pairs = true;
+      for (int ppt = 1; ppt <= 2 && pairs; ++ppt) {
+        for (const int bs : {128, 256, 512}) {
+          const RenderSchedule cand{ppt, bs};
+          BatchPlan trial;
+          std::string msg;
+          if (trial.build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg, nullptr, nullptr,
+                          K, sky, G, model, params_per_point, &cand, masked) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+          }
+          if (ppt == 2 && trial.max_ppt() < 2) {   // no class of this launch takes two pixels
+            pairs = false;
+            break;
+          }
+          float ms = 0.0f;
+          LENSED_HIP(c, trial.render_ms((hipStream_t)stream, &ms));
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = cand;
+          }
         }
       }
       c->tiles.set_render_measured(systems, n_systems, best);
@@ -502,7 +520,7 @@ int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const 
     std::unique_ptr<BatchPlan> np(new BatchPlan());
     std::string msg;
     hipError_t e = np->build(systems, n_systems, theta, system_of_point, n_points, logl, c->tiles, msg, nullptr,
-                             nullptr, K, sky, G, model, params_per_point, 0, masked);
+                             nullptr, K, sky, G, model, params_per_point, nullptr, masked);
     if (e != hipSuccess) return hip_fail(c, e, ("batch plan: " + msg).c_str());
     if (c->use_graphs) {
       e = np->capture(c->cap);
@@ -514,6 +532,7 @@ int run_batch(lensed_ctx* c, const lensed_system* systems, int n_systems, const 
   c->schedule[0] = plan->psf_tile().TW;
   c->schedule[1] = plan->psf_tile().TH;
   c->schedule[2] = plan->render_ppt();
+  c->schedule[3] = plan->render_block();
   c->rendered[0] = plan->rendered_pixels();
   c->rendered[1] = plan->rendered_subsamples();
   if (c->profiling) {
@@ -739,6 +758,13 @@ int lensed_batch_schedule(lensed_ctx* c, int* out) {
   return LENSED_OK;
 }
 
+int lensed_batch_render_block(lensed_ctx* c, int* out) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  if (!out) return set_err(c, LENSED_INVALID_ARGUMENT, "out is NULL");
+  out[0] = c->schedule[3];
+  return LENSED_OK;
+}
+
 int lensed_batch_rendered(lensed_ctx* c, int64_t* out) {
   if (!c) return LENSED_INVALID_ARGUMENT;
   if (!out) return set_err(c, LENSED_INVALID_ARGUMENT, "out is NULL");
@@ -798,7 +824,9 @@ static int run_grad(lensed_ctx* c, const lensed_system* sys, const float* theta,
     }
     // the render schedule: as fixed by LENSED_RENDER_PPT, else as measured for
     // these shapes by a batched call (one pixel per thread when none was)
-    if (c->force_ppt) c->tiles.set_render_measured(sys, 1, c->force_ppt);
+    if (c->force_ppt || c->force_block)
+      c->tiles.set_render_measured(sys, 1, RenderSchedule{c->force_ppt ? c->force_ppt : 1,
+                                                         c->force_block ? c->force_block : RENDER_BLOCK});
     std::unique_ptr<BatchPlan> np(new BatchPlan());
     std::string msg;
     hipError_t e = np->build(sys, 1, theta, map.data(), n_points, logl, c->tiles, msg, grad, nullptr, 1, nullptr, 1,

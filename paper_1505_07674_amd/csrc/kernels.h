@@ -67,10 +67,16 @@ int render_class(const SysDesc& sd);
 
 // A run of render items of one class: items [offset, offset + count) of w.items
 // (or, for a plain call, blocks 0..count-1 of w.single), with ppt pixels per
-// thread (2 only for classes 1..RENDER_MAX_CLASS and images of even width; an
-// item then covers 2 RENDER_BLOCK pixels).
+// thread (2 only for classes 1..RENDER_MAX_CLASS and images of even width) and
+// block threads per block (64 <= block <= RENDER_BLOCK_MAX, a multiple of 64):
+// an item covers block render units of ppt pixels.
 struct RenderSpan {
-  int klass, ppt, offset, count;
+  int klass, ppt, offset, count, block;
+};
+constexpr int RENDER_BLOCK_MAX = 512;
+// A render schedule: pixels per thread and threads per block.
+struct RenderSchedule {
+  int ppt, block;
 };
 // Batched form: one launch per span, then one cusp-correction pass over all of
 // them. cl.entries needs one slot per render wave and pixel of a thread.

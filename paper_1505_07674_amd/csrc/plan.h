@@ -32,14 +32,15 @@ class TileCache {
   std::vector<TileShape> ranked(const lensed_system* s, int n, int k) const;
   bool has_measured(const lensed_system* s, int n) const { return measured_.count(key(s, n)) != 0; }
   void set_measured(const lensed_system* s, int n, TileShape t) { measured_[key(s, n)] = t; }
-  // Render schedule (pixels per thread of the midpoint classes): the measured
-  // choice for this set of image sizes and rules, else one pixel per thread.
-  int render_ppt(const lensed_system* s, int n) const {
+  // Render schedule (pixels per thread of the midpoint classes, threads per
+  // block): the measured choice for this set of image sizes and rules, else one
+  // pixel per thread in RENDER_BLOCK-thread blocks.
+  RenderSchedule render_schedule(const lensed_system* s, int n) const {
     auto it = render_measured_.find(render_key(s, n));
-    return it == render_measured_.end() ? 1 : it->second;
+    return it == render_measured_.end() ? RenderSchedule{1, RENDER_BLOCK} : it->second;
   }
   bool has_render_measured(const lensed_system* s, int n) const { return render_measured_.count(render_key(s, n)) != 0; }
-  void set_render_measured(const lensed_system* s, int n, int ppt) { render_measured_[render_key(s, n)] = ppt; }
+  void set_render_measured(const lensed_system* s, int n, RenderSchedule r) { render_measured_[render_key(s, n)] = r; }
   static double model_cost(int H, int W, int ph, int pw, TileShape t, int sq);
   static std::vector<TileShape> candidates(int sq, const lensed_system* s = nullptr, int n = 0);
   // The cost model's best tile for one system (no cache, no allocation).
@@ -51,7 +52,7 @@ class TileCache {
   static int launch_square(const lensed_system* s, int n);
   std::map<std::tuple<int, int, int, int>, TileShape> cache_;
   std::map<std::string, TileShape> measured_;
-  std::map<std::string, int> render_measured_;
+  std::map<std::string, RenderSchedule> render_measured_;
 };
 
 int validate_system(lensed_ctx* c, const lensed_system* s, bool need_data, int index);
@@ -75,24 +76,27 @@ class BatchPlan {
                const double* logl, const float* grad = nullptr, int K = 1, const float* sky = nullptr,
                int G = 1, const ModelSpec* model = nullptr, bool masked = false) const;
   // force: use this tile shape instead of the cache's choice (autotuning);
-  // force_ppt > 0: render this many pixels per thread where the class allows it.
+  // force_render: use this render schedule (pixels per thread where the class
+  // allows it, threads per block) instead of the cache's.
   // masked: render only the pixels the chi^2 can see (the support of w > 0
   // dilated by the PSF, clamped at the borders) and convolve only the PSF tiles
   // that hold a pixel with w > 0; the other pixels and tile sums stay zero.
   hipError_t build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
                    int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad = nullptr,
                    const TileShape* force = nullptr, int K = 1, const float* sky = nullptr, int G = 1,
-                   const ModelSpec* model = nullptr, int params_per_point = NPAR, int force_ppt = 0,
-                   bool masked = false);
+                   const ModelSpec* model = nullptr, int params_per_point = NPAR,
+                   const RenderSchedule* force_render = nullptr, bool masked = false);
   // Runs the plan stage by stage (a warm-up, then three timed runs) and returns
   // the fastest PSF + chi^2 stage, or the fastest render kernels, in milliseconds.
   hipError_t psf_ms(hipStream_t s, float* ms) const { return stage_ms(s, 3, ms); }
   hipError_t render_ms(hipStream_t s, float* ms) const { return stage_ms(s, 1, ms); }
   // The most pixels per thread a render class of this plan could take (1 or 2).
   int max_ppt() const { return max_ppt_; }
-  // The schedule in use: PSF tile and pixels per thread of the midpoint classes.
+  // The schedule in use: PSF tile, pixels per thread of the midpoint classes and
+  // threads per render block.
   TileShape psf_tile() const { return {TW_, TH_}; }
   int render_ppt() const { return ppt_; }
+  int render_block() const { return rbs_; }
   int64_t rendered_pixels() const { return rendered_pixels_; }
   int64_t rendered_subsamples() const { return rendered_subsamples_; }
   hipError_t capture(hipStream_t cap);
@@ -149,6 +153,7 @@ class BatchPlan {
   hipGraph_t graph_ = nullptr;
   hipGraphExec_t exec_ = nullptr;
   int ppt_ = 1;
+  int rbs_ = RENDER_BLOCK;        // threads (render units) per render block
   int max_ppt_ = 1;
   bool masked_ = false;
   int64_t rendered_pixels_ = 0;   // pixels the render stage computes per launch

@@ -173,7 +173,7 @@ bool BatchPlan::matches(const lensed_system* systems, int n_systems, const float
 hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
                             int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad,
                             const TileShape* force, int K, const float* sky, int G, const ModelSpec* model,
-                            int params_per_point, int force_ppt, bool masked) {
+                            int params_per_point, const RenderSchedule* force_render, bool masked) {
   systems_.assign(systems, systems + n_systems);
   map_.assign(map, map + n_points);
   theta_ = theta;
@@ -210,8 +210,10 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   // an even width (a pair never straddles two rows), if the schedule says so;
   // general-model plans keep one (their kernel walks one pixel per thread). The
   // gradient kernels have item lists of their own.
-  ppt_ = force_ppt > 0 ? force_ppt : tiles.render_ppt(systems, n_systems);
-  if (model) ppt_ = 1;
+  const RenderSchedule rs = force_render ? *force_render : tiles.render_schedule(systems, n_systems);
+  ppt_ = rs.ppt == 2 ? 2 : 1;
+  rbs_ = rs.block >= 64 && rs.block <= RENDER_BLOCK_MAX && rs.block % 64 == 0 ? rs.block : RENDER_BLOCK;
+  if (model) ppt_ = 1, rbs_ = RENDER_BLOCK;   // the general-model render walks 256-pixel tiles
   std::vector<int> class_div(RENDER_MAX_CLASS + 1, 2);   // pixels per thread each class allows
   class_div[0] = 1;
   for (int s = 0; s < n_systems; ++s)
@@ -297,9 +299,9 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
     const int64_t npix = masked_ ? nunits * pp : (int64_t)d.H * d.W;
     rendered_pixels_ += npix;
     rendered_subsamples_ += npix * d.N * d.N;
-    const int nrt = (int)((nunits + RENDER_BLOCK - 1) / RENDER_BLOCK);
+    const int nrt = (int)((nunits + rbs_ - 1) / rbs_);
     for (int t = 0; t < nrt; ++t) {
-      const int64_t px = std::min<int64_t>(RENDER_BLOCK, nunits - (int64_t)t * RENDER_BLOCK) * pp;
+      const int64_t px = std::min<int64_t>(rbs_, nunits - (int64_t)t * rbs_) * pp;
       ritems.push_back({px * d.N * d.N, p, t, klass});
     }
     compose_tiles_ = std::max(compose_tiles_, d.n_rtiles);
@@ -318,9 +320,9 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   int cusp_slots = 0;
   for (int i = 0; i < (int)ritems.size(); ++i) {
     const int klass = ritems[i].klass;
-    if (rspans_.empty() || rspans_.back().klass != klass) rspans_.push_back({klass, class_ppt(klass), i, 0});
+    if (rspans_.empty() || rspans_.back().klass != klass) rspans_.push_back({klass, class_ppt(klass), i, 0, rbs_});
     ++rspans_.back().count;
-    cusp_slots += (RENDER_BLOCK / 64) * class_ppt(klass);
+    cusp_slots += (rbs_ / 64) * class_ppt(klass);
   }
   n_ritems_ = (int)ritems.size();
   n_pitems_ = (int)pitems.size();

@@ -77,16 +77,17 @@ __device__ __forceinline__ void push_cusp(const CuspList& cl, bool flag, int poi
 // pixel, or PPT = 2 horizontally adjacent pixels (2j, 2j+1) of a row, which
 // share the row terms and the constants (only for midpoint classes and images
 // of even width, so that a pair never straddles two rows). Item (point, tile)
-// covers units tile * RENDER_BLOCK .. + RENDER_BLOCK - 1: consecutive pixels,
-// or, in a masked plan, consecutive entries of the system's unit list.
+// covers units tile * B .. + B - 1 (B = blockDim.x, up to RENDER_BLOCK_MAX):
+// consecutive pixels, or, in a masked plan, consecutive entries of the
+// system's unit list.
 template <int NC, int PPT>
-__global__ __launch_bounds__(RENDER_BLOCK, NC > 0 && NC <= 4 ? 8 : 1) void render_kernel(WorkArgs w, const PointConst* __restrict__ pcs,
-                                                               float* __restrict__ L, CuspList cl) {
+__global__ __launch_bounds__(RENDER_BLOCK_MAX, NC > 0 && NC <= 4 ? 8 : 1) void render_kernel(
+    WorkArgs w, const PointConst* __restrict__ pcs, float* __restrict__ L, CuspList cl) {
   int point, tile;
   resolve_item(w, point, tile);
   const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[point] : 0] : w.single;
   const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
-  const int unit = tile * RENDER_BLOCK + (int)threadIdx.x;
+  const int unit = tile * (int)blockDim.x + (int)threadIdx.x;
   const bool active = unit < unit_count(sd, PPT);
   bool cusp = false, cusp1 = false;
   if (active) {
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(RENDER_BLOCK, NC > 0 && NC <= 4 ? 8 : 1) void rende
     }
   }
   // one list entry per wave (and pixel of a pair) that has pixels next to a cuspy source centre
-  const int unit0 = tile * RENDER_BLOCK + (int)(threadIdx.x & ~63u);
+  const int unit0 = tile * (int)blockDim.x + (int)(threadIdx.x & ~63u);
   push_cusp(cl, cusp, point, unit0, PPT, 0);
   if (PPT == 2) push_cusp(cl, cusp1, point, unit0, PPT, 1);
 }
@@ -335,21 +336,23 @@ hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointCo
                          const RenderSpan* spans, int n_spans, const CuspList& cl, hipStream_t stream,
                          hipEvent_t between) {
   int n_waves = 0;   // cusp-list capacity: one entry per wave and pixel of a thread
-  for (int i = 0; i < n_spans; ++i) n_waves += spans[i].count * (RENDER_BLOCK / 64) * (spans[i].ppt == 2 ? 2 : 1);
+  for (int i = 0; i < n_spans; ++i) n_waves += spans[i].count * (spans[i].block / 64) * (spans[i].ppt == 2 ? 2 : 1);
   if (n_waves <= 0) return hipSuccess;
   for (int i = 0; i < n_spans; ++i) {
     if (spans[i].count <= 0) continue;
     WorkArgs ws = w;
     if (ws.items) ws.items += spans[i].offset;
     const bool pair = spans[i].ppt == 2 && spans[i].klass > 0;
+    const int bs = spans[i].block;
+    if (bs < 64 || bs > RENDER_BLOCK_MAX || bs % 64 != 0) return hipErrorInvalidValue;
     hipError_t e = for_item_parts(ws, spans[i].count, [&](const WorkArgs& part, int n) {
       switch (spans[i].klass) {
 #define LENSED_RENDER_CLASS(NC)                                                                                     \
   case NC:                                                                                                          \
     if (pair)                                                                                                       \
-      hipLaunchKernelGGL((render_kernel<NC, 2>), dim3(n), dim3(RENDER_BLOCK), 0, stream, part, pcs, L, cl);         \
+      hipLaunchKernelGGL((render_kernel<NC, 2>), dim3(n), dim3(bs), 0, stream, part, pcs, L, cl);                   \
     else                                                                                                            \
-      hipLaunchKernelGGL((render_kernel<NC, 1>), dim3(n), dim3(RENDER_BLOCK), 0, stream, part, pcs, L, cl);         \
+      hipLaunchKernelGGL((render_kernel<NC, 1>), dim3(n), dim3(bs), 0, stream, part, pcs, L, cl);                   \
     break;
         LENSED_RENDER_CLASS(1)
         LENSED_RENDER_CLASS(2)
@@ -361,7 +364,7 @@ hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointCo
         LENSED_RENDER_CLASS(8)
 #undef LENSED_RENDER_CLASS
         default:
-          hipLaunchKernelGGL((render_kernel<0, 1>), dim3(n), dim3(RENDER_BLOCK), 0, stream, part, pcs, L, cl);
+          hipLaunchKernelGGL((render_kernel<0, 1>), dim3(n), dim3(bs), 0, stream, part, pcs, L, cl);
           break;
       }
       return hipGetLastError();
@@ -378,7 +381,7 @@ hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointCo
 
 hipError_t launch_render(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, float* L, int n_blocks,
                          const CuspList& cl, hipStream_t stream, hipEvent_t between) {
-  const RenderSpan span{render_class(w.single), 1, 0, n_blocks};
+  const RenderSpan span{render_class(w.single), 1, 0, n_blocks, RENDER_BLOCK};
   return launch_render(w, pcs, p64s, L, &span, 1, cl, stream, between);
 }
 

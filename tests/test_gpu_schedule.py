@@ -1,6 +1,7 @@
 """Render schedules of the batch engine (the batching of Eq. 17 over points and
 systems): one pixel per thread, or two horizontally adjacent pixels per thread
-sharing the row terms of the subsample grid. Each pixel is computed by the same
+sharing the row terms of the subsample grid, in blocks of 128, 256 or 512
+threads. Each pixel is computed by the same
 operations on the same constants either way, so the batched log L must agree
 bit for bit between the schedules, and with the FP64 oracle to the usual bar.
 Systems of odd width, and the Gauss-Kronrod classes, keep one pixel per thread
@@ -26,11 +27,11 @@ def say(msg):
     print(msg, flush=True)
 
 
-def context_with(ppt):
+def context_with(ppt, block=256):
     """A context with the render schedule fixed and the PSF tile left to the
     cost model: two contexts autotuning by timing could pick different PSF
     tiles, whose chi^2 partial sums group the pixels differently."""
-    env = {"LENSED_RENDER_PPT": str(ppt), "LENSED_NO_AUTOTUNE": "1"}
+    env = {"LENSED_RENDER_PPT": str(ppt), "LENSED_RENDER_BLOCK": str(block), "LENSED_NO_AUTOTUNE": "1"}
     old = {k: os.environ.get(k) for k in env}
     os.environ.update(env)
     try:
@@ -103,6 +104,31 @@ def test_c1_pair_schedule_matches_single_pixel_schedule():
     assert np.array_equal(out[1], out[2])
 
 
+@pytest.mark.parametrize("ppt", [1, 2])
+def test_render_block_sizes_are_bitwise_identical(ppt):
+    """Blocks of 128, 256 and 512 render threads cover the same units with the
+    same arithmetic, so log L agrees bit for bit; the cusp list holds one entry
+    per wave whatever the block, so the cusp-heavy mixed systems check it too."""
+    systems = mixed_systems()
+    per = 20
+    pts = np.concatenate([mocks.points(spec, per, seed=80 + i) for i, (spec, _, _, _) in enumerate(systems)])
+    sop = np.repeat(np.arange(len(systems), dtype=np.int32), per)
+    tp = torch.from_numpy(pts).to(DEV)
+    gsys = [g for _, _, g, _ in systems]
+    out = {}
+    for block in (128, 256, 512):
+        ctx = context_with(ppt, block)
+        out[block] = lensed.loglike_batch(tp, sop, gsys, ctx=ctx).cpu().numpy()
+        sched = ctx.batch_schedule()
+        say(f"ppt {ppt} block {block}: schedule {sched}")
+        assert sched["render_block"] == block and sched["render_pixels_per_thread"] == ppt
+        masked = lensed.loglike_batch(tp, sop, gsys, ctx=ctx, masked=True).cpu().numpy()
+        assert np.array_equal(masked, out[block]), block
+        ctx.close()
+    assert np.all(np.isfinite(out[256]))
+    assert np.array_equal(out[128], out[256]) and np.array_equal(out[512], out[256])
+
+
 def test_autotuner_records_a_render_schedule():
     from helpers import observation
     spec, obs = observation("c0")
@@ -114,6 +140,7 @@ def test_autotuner_records_a_render_schedule():
     sched = ctx.batch_schedule()
     say(f"autotuned schedule for 64x64 N=2: {sched}")
     assert sched["render_pixels_per_thread"] in (1, 2)
+    assert sched["render_block"] in (128, 256, 512)
     assert sched["psf_tile"][0] > 0 and sched["psf_tile"][1] > 0
     assert torch.all(torch.isfinite(ll))
     ctx.close()
@@ -129,11 +156,12 @@ def test_gradient_plans_take_the_render_schedule():
     gs = grad_system(spec, obs)
     pts = torch.from_numpy(mocks.points(spec, 12, seed=61)).to(DEV)
     out = {}
-    for ppt in (1, 2):
-        ctx = context_with(ppt)
+    for ppt, block in ((1, 256), (2, 256), (2, 512), (1, 128)):
+        ctx = context_with(ppt, block)
         ll, g = lensed.loglike_grad(pts, gs, ctx=ctx)
-        out[ppt] = (ll.cpu().numpy(), g.cpu().numpy())
+        out[ppt, block] = (ll.cpu().numpy(), g.cpu().numpy())
         ctx.close()
-    assert np.all(np.isfinite(out[1][1]))
-    assert np.array_equal(out[1][0], out[2][0])
-    assert np.array_equal(out[1][1], out[2][1])
+    assert np.all(np.isfinite(out[1, 256][1]))
+    for key in out:
+        assert np.array_equal(out[1, 256][0], out[key][0]), key
+        assert np.array_equal(out[1, 256][1], out[key][1]), key
