@@ -3,11 +3,14 @@
 // sky (the models of the paper's fits of real lenses, Sec. 5), and lenses on
 // several planes (the multi-plane extension named in Sec. 6).
 //
-// Evaluated in float64 throughout (the float32 folding of the 17-parameter
-// render does not carry over to an arbitrary number of components), then
-// rounded once per pixel; the PSF and chi^2 stages are the common ones. On
-// gfx950 the float64 vector rate equals the unpacked float32 one; the cost is
-// the float64 transcendentals.
+// Coordinates, deflections and radii are float64 (the float32 folding of the
+// 17-parameter render does not carry over to an arbitrary number of
+// components), and so are the SIE's atan and atanh, whose errors would move
+// rays near a cuspy source centre. The Sersic profiles take their powers of
+// two as an exact integer part and a float32 fraction (exp2_split,
+// log2_split): errors of a few 1e-7 of each subsample's light that vary with
+// the argument, at a fraction of the float64 library functions' cost. Each
+// pixel is rounded once; the PSF and chi^2 stages are the common ones.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -37,15 +40,38 @@ __device__ inline void add_sie(const ModelConst& m, int k, double x, double y, d
   }
 }
 
-// Sersic component j (Eq. 22) at (px, py).
+constexpr double LN2 = 0.693147180559945309417;
+
+// 2^a for float64 a: the integer part exact (ldexp), the fraction in [0, 1)
+// by the float32 hardware exp2 (relative error about 1e-7).
+__device__ inline double exp2_split(double a) {
+  a = fmax(a, -1100.0);
+  const double k = floor(a);
+  return ldexp((double)__builtin_amdgcn_exp2f((float)(a - k)), (int)k);
+}
+
+// log2 u for finite u > 0: the binary exponent exact, the mantissa in [1/2, 1)
+// by the float32 hardware log2 (absolute error about 1e-7).
+__device__ inline double log2_split(double u) {
+  int k;
+  const double f = frexp(u, &k);
+  return (double)k + (double)__builtin_amdgcn_logf((float)f);
+}
+
+// Sersic component j (Eq. 22) at (px, py): the offset, rotation and radius in
+// float64; the profile exp(-b ((R/R_e)^{1/n} - 1)) as powers of two, whose
+// exponents are float64 and whose fractional parts go through the hardware
+// float32 exp2 / log2 (per-subsample relative errors of a few 1e-7 that
+// vary with the argument, against the float64 library functions' many
+// instructions each).
 __device__ inline double sersic_at(const ModelConst& m, int j, double px, double py) {
   const double* s = m.ser[j];
   const double dx = px - s[0], dy = py - s[1];
   const double xp = s[2] * dx + s[3] * dy, yp = s[2] * dy - s[3] * dx;
   const double R2 = s[4] * xp * xp + s[5] * yp * yp;
-  // (R/R_e)^{1/n} = exp(ln(R^2 / R_e^2) / (2n))
-  const double t = R2 > 0.0 ? exp(0.5 * s[7] * log(R2 * s[6] * s[6])) : 0.0;
-  return s[9] * exp(-s[8] * (t - 1.0));
+  // (R/R_e)^{1/n} = 2^(log2(R^2 / R_e^2) / (2n))
+  const double t = R2 > 0.0 ? exp2_split(0.5 * s[7] * log2_split(R2 * s[6] * s[6])) : 0.0;
+  return s[9] * exp2_split(s[8] * LOG2E * (1.0 - t));
 }
 
 // Surface brightness of a general model with one lens plane at (x, y) (Eqs.
@@ -226,14 +252,16 @@ __device__ inline Dl<M> dsqrt(const Dl<M>& a) {
   const double s = sqrt(a.v);
   return dchain(a, s, 0.5 / s);
 }
+// exp and log of a Sersic argument, as in sersic_at (relative errors of a few
+// 1e-7 in the value and the derivatives).
 template <int M>
 __device__ inline Dl<M> dexp(const Dl<M>& a) {
-  const double e = exp(a.v);
+  const double e = exp2_split(a.v * LOG2E);
   return dchain(a, e, e);
 }
 template <int M>
 __device__ inline Dl<M> dlog(const Dl<M>& a) {
-  return dchain(a, log(a.v), 1.0 / a.v);
+  return dchain(a, log2_split(a.v) * LN2, 1.0 / a.v);
 }
 template <int M>
 __device__ inline Dl<M> datan(const Dl<M>& a) {
@@ -298,10 +326,10 @@ __device__ inline double sersic_and_grad(const ModelConst& m, int j, double px, 
   const double R2 = s[4] * xp * xp + s[5] * yp * yp;
   if (!(R2 > 0.0)) {
     gx = gy = 0.0;
-    return s[9] * exp(s[8]);
+    return s[9] * exp2_split(s[8] * LOG2E);
   }
-  const double t = exp(0.5 * s[7] * log(R2 * s[6] * s[6]));
-  const double S = s[9] * exp(-s[8] * (t - 1.0));
+  const double t = exp2_split(0.5 * s[7] * log2_split(R2 * s[6] * s[6]));
+  const double S = s[9] * exp2_split(s[8] * LOG2E * (1.0 - t));
   const double D = -s[8] * S * t * 0.5 * s[7] / R2;   // dS/dR^2
   const double ex = 2.0 * s[4] * xp, ey = 2.0 * s[5] * yp;   // dR^2/dx', dR^2/dy'
   gx = D * (ex * s[2] - ey * s[3]);

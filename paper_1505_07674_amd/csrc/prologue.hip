@@ -483,10 +483,11 @@ __global__ __launch_bounds__(64) void prologue_kernel(const float* __restrict__ 
 
 // General models: one thread per point turns its parameters (layout of
 // lensed_model: per SIE x_c, y_c, theta_E, q, phi; shear gamma, phi_gamma; per
-// Sersic x, y, I_e, R_e, n, q, phi; sky) into ModelConst, b_n by the float64
-// Newton solve. An invalid point gets sky = NaN, which makes its image NaN.
+// Sersic x, y, I_e, R_e, n, q, phi; sky) into ModelConst; model_bn_kernel
+// then adds the b_n roots. An invalid point gets sky = NaN, which makes its
+// image NaN.
 __global__ __launch_bounds__(64) void model_prologue_kernel(const float* __restrict__ theta, int n_points, int n_params, ModelSpec spec,
-                                      ModelConst* __restrict__ out, int with_db) {
+                                      ModelConst* __restrict__ out) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_points) return;
   const float* t = theta + (size_t)p * n_params;
@@ -539,21 +540,47 @@ __global__ __launch_bounds__(64) void model_prologue_kernel(const float* __restr
     m.ser[j][5] = 1.0 / q;
     m.ser[j][6] = 1.0 / Re;
     m.ser[j][7] = 1.0 / n;
-    m.ser[j][8] = valid ? sersic_bn(n) : 0.0;
-    m.ser[j][9] = t[o + 2];
-    // db_n/dn by central differences of the root (truncation of order 1e-10 relative)
-    if (with_db && valid) m.ser[j][10] = (sersic_bn(n + 1e-5 * n) - sersic_bn(n - 1e-5 * n)) / (2e-5 * n);
+    m.ser[j][9] = t[o + 2];   // b_n (slot 8) and db_n/dn (slot 10): model_bn_kernel
     o += 7;
   }
   m.sky = spec.sky ? (double)t[o] : 0.0;
   if (!valid) m.sky = __builtin_nan("");
 }
 
+// b_n of every Sersic of every valid point, one Newton solve per thread: lane
+// c of a block is a (point, component) pair, and with with_db the block's
+// second and third waves solve at n (1 +- 1e-5) for db_n/dn by central
+// differences (truncation of order 1e-10 relative). Runs after
+// model_prologue_kernel, whose NaN sky marks the invalid points.
+constexpr int MODEL_BN_PAIRS = 64;
+__global__ __launch_bounds__(3 * MODEL_BN_PAIRS) void model_bn_kernel(const float* __restrict__ theta, int n_points,
+                                                                     int n_params, ModelSpec spec,
+                                                                     ModelConst* __restrict__ out) {
+  __shared__ double root[3][MODEL_BN_PAIRS];
+  const int c = (int)(threadIdx.x % MODEL_BN_PAIRS), v = (int)(threadIdx.x / MODEL_BN_PAIRS);
+  const int64_t pair = (int64_t)blockIdx.x * MODEL_BN_PAIRS + c;
+  const bool live = pair < (int64_t)n_points * spec.n_sersic;
+  const int p = live ? (int)(pair / spec.n_sersic) : 0, j = live ? (int)(pair % spec.n_sersic) : 0;
+  const bool valid = live && !isnan(out[p].sky);
+  const int o = 5 * spec.n_sie + (spec.shear ? 2 : 0) + 7 * j;
+  const double n = valid ? (double)theta[(size_t)p * n_params + o + 4] : 1.0;
+  if (valid) root[v][c] = sersic_bn(v == 0 ? n : (v == 1 ? n + 1e-5 * n : n - 1e-5 * n));
+  __syncthreads();
+  if (!valid || v != 0) return;
+  out[p].ser[j][8] = root[0][c];
+  if (blockDim.x == 3 * MODEL_BN_PAIRS) out[p].ser[j][10] = (root[1][c] - root[2][c]) / (2e-5 * n);
+}
+
 hipError_t launch_model_prologue(const float* theta, int n_points, int n_params, const ModelSpec& spec,
                                  ModelConst* out, hipStream_t stream, bool with_db) {
   if (n_points <= 0) return hipSuccess;
   hipLaunchKernelGGL(model_prologue_kernel, dim3((n_points + 63) / 64), dim3(64), 0, stream, theta, n_points, n_params,
-                     spec, out, with_db ? 1 : 0);
+                     spec, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || spec.n_sersic <= 0) return e;
+  const int64_t pairs = (int64_t)n_points * spec.n_sersic;
+  hipLaunchKernelGGL(model_bn_kernel, dim3((unsigned)((pairs + MODEL_BN_PAIRS - 1) / MODEL_BN_PAIRS)),
+                     dim3(with_db ? 3 * MODEL_BN_PAIRS : MODEL_BN_PAIRS), 0, stream, theta, n_points, n_params, spec, out);
   return hipGetLastError();
 }
 

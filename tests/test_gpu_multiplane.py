@@ -74,7 +74,9 @@ def test_three_plane_images_match_the_oracle(rule):
             img = lensed.render_model(torch.from_numpy(t).to(DEV), g, gm, apply_psf=psf).cpu().numpy()
             ref = oracle.render_model(o, om, t.astype(np.float64), apply_psf=psf)
             err = np.max(np.abs(img.astype(np.float64) - ref)) / np.max(np.abs(ref))
-            assert err <= 1e-6, (rule, psf, err)      # float64 throughout, rounded once
+            say(f"  rule {rule} psf {psf}: max error / peak {err:.2e}")
+            # float64 rays; the Sersic profiles' fractional powers of two in float32
+            assert err <= 1e-6, (rule, psf, err)
 
 
 def test_three_plane_loglike_matches_the_oracle():
