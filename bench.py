@@ -249,7 +249,7 @@ def next_rows(lensed, mocks, dev, stream, spec, obs, steps=3):
                                "stage_ms_per_step": st,
                                "roofline": {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
                                             "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
-                                            "kernel": "model_render (float64)",
+                                            "kernel": "model_render (float64 rays, float32 profile fractions)",
                                             "ops_per_subsample": GENERAL41_OPS_PER_SUBSAMPLE,
                                             "subsamples_per_launch": subs}}
     # and its adjoint (one component per pass, float64 dual numbers)

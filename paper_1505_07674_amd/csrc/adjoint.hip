@@ -418,11 +418,18 @@ __global__ __launch_bounds__(RENDER_BLOCK, 6) void grad_kernel(WorkArgs w, const
   const GradConst& gc = gcs[point];
   const GradUniform& U = gc.u;
 
+  const int base = gpbase ? gpbase[point] : 0;
+  const int n_sup = grad_support_count(sd);
+  if (tile * RENDER_BLOCK >= n_sup) {   // past the support's last pixel: zero sums
+    if ((int)threadIdx.x < NPAR) gpart[(size_t)(base + tile) * NPAR + threadIdx.x] = make_float2(0.0f, 0.0f);
+    return;
+  }
   float acc[NPAR];
 #pragma unroll
   for (int k = 0; k < NPAR; ++k) acc[k] = 0.0f;
-  const int pix = tile * RENDER_BLOCK + (int)threadIdx.x;
-  if (pix < sd.H * sd.W) {
+  const int unit = tile * RENDER_BLOCK + (int)threadIdx.x;
+  if (unit < n_sup) {
+    const int pix = grad_support_pixel(sd, unit);
     const float gp = G[loff + pix];
     if (gp != 0.0f) {   // pixels outside the reach of any weighted residual add nothing
       const int r = row_of(sd, pix);
@@ -466,7 +473,6 @@ __global__ __launch_bounds__(RENDER_BLOCK, 6) void grad_kernel(WorkArgs w, const
   for (int k = 0; k < NPAR; ++k) part[k][threadIdx.x] = acc[k];
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int base = gpbase ? gpbase[point] : 0;
   for (int k = wid; k < NPAR; k += RENDER_BLOCK / 64) {
     double v = ((double)part[k][lane] + (double)part[k][lane + 64]) +
                ((double)part[k][lane + 128] + (double)part[k][lane + 192]);
@@ -702,6 +708,72 @@ hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n
     if (le != hipSuccess) return le;
   }
   return hipSuccess;
+}
+
+// The adjoint's support, rebuilt from the weights on every launch so that a
+// plan stays right when the caller changes the weights in place. Row pass:
+// any w > 0 within q = pw/2 columns (clamped to the row).
+__global__ __launch_bounds__(256) void grad_support_rows_kernel(const SysDesc* __restrict__ sys) {
+  const SysDesc& sd = sys[blockIdx.y];
+  const int pix = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (!sd.gsup || pix >= sd.H * sd.W) return;
+  const int r = row_of(sd, pix), c = pix - r * sd.W, q = sd.pw / 2;
+  const float* wr = sd.weight + (size_t)r * sd.W;
+  const int c1 = min(c + q, sd.W - 1);
+  bool any = false;
+  for (int cc = max(c - q, 0); cc <= c1; ++cc) any = any || wr[cc] > 0.0f;
+  sd.gflags[pix] = any ? 1 : 0;
+}
+
+// Column pass: any row-pass flag within p = ph/2 rows (clamped to the column).
+__global__ __launch_bounds__(256) void grad_support_cols_kernel(const SysDesc* __restrict__ sys) {
+  const SysDesc& sd = sys[blockIdx.y];
+  const int npix = sd.H * sd.W;
+  const int pix = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (!sd.gsup || pix >= npix) return;
+  const int r = row_of(sd, pix), c = pix - r * sd.W, p = sd.ph / 2;
+  const int r1 = min(r + p, sd.H - 1);
+  bool any = false;
+  for (int rr = max(r - p, 0); rr <= r1; ++rr) any = any || sd.gflags[(size_t)rr * sd.W + c] != 0;
+  sd.gflags[npix + pix] = any ? 1 : 0;
+}
+
+// Compaction, one block per system: each thread counts the flags of a chunk of
+// consecutive pixels, a block scan gives each chunk its first slot, and the
+// chunks write their pixels in row-major order.
+constexpr int GSUP_THREADS = 1024;
+__global__ __launch_bounds__(GSUP_THREADS) void grad_support_compact_kernel(const SysDesc* __restrict__ sys) {
+  __shared__ int scan[GSUP_THREADS];
+  const SysDesc& sd = sys[blockIdx.x];
+  if (!sd.gsup) return;   // uniform over the block
+  const int npix = sd.H * sd.W;
+  const unsigned char* f = sd.gflags + npix;
+  const int chunk = (npix + GSUP_THREADS - 1) / GSUP_THREADS;
+  const int t = (int)threadIdx.x;
+  const int b = min(t * chunk, npix), e = min(b + chunk, npix);
+  int cnt = 0;
+  for (int i = b; i < e; ++i) cnt += f[i];
+  scan[t] = cnt;
+  __syncthreads();
+  for (int off = 1; off < GSUP_THREADS; off <<= 1) {   // inclusive Hillis-Steele scan
+    const int v = t >= off ? scan[t - off] : 0;
+    __syncthreads();
+    scan[t] += v;
+    __syncthreads();
+  }
+  int pos = scan[t] - cnt;
+  for (int i = b; i < e; ++i)
+    if (f[i]) sd.gsup[pos++] = i;
+  if (t == GSUP_THREADS - 1) *sd.gsup_n = scan[t];
+}
+
+hipError_t launch_grad_support(const SysDesc* sys, int n_sys, int max_pixels, hipStream_t st) {
+  if (n_sys <= 0 || max_pixels <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((max_pixels + 255) / 256), (unsigned)n_sys);
+  hipLaunchKernelGGL(grad_support_rows_kernel, grid, dim3(256), 0, st, sys);
+  hipLaunchKernelGGL(grad_support_cols_kernel, grid, dim3(256), 0, st, sys);
+  hipLaunchKernelGGL(grad_support_compact_kernel, dim3((unsigned)n_sys), dim3(GSUP_THREADS), 0, st, sys);
+  return hipGetLastError();
 }
 
 hipError_t launch_grad(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, const GradConst* gcs,

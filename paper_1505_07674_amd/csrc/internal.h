@@ -172,6 +172,15 @@ struct SysDesc {
   int pad_active;
   unsigned int wdiv_m;    // row of pixel n: (n wdiv_m) >> wdiv_s (row_of)
   int wdiv_s;
+  // Support of the adjoint's g = A^T rho in a gradient plan: every pixel within
+  // the PSF box of a pixel with w > 0 (replicate padding only moves a tap
+  // towards the image, so the clamped border taps stay inside that box).
+  // Rebuilt from the weights by every gradient launch (grad_support_*
+  // kernels): gsup[0 .. *gsup_n) its pixels in row-major order, gflags 2 H W
+  // bytes of scratch. nullptr: every pixel.
+  int* gsup;
+  int* gsup_n;
+  unsigned char* gflags;
 };
 
 // floor(n / W) for 0 <= n < 2^28 (every pixel index: H W <= 2^28) by one
@@ -196,6 +205,9 @@ __device__ __forceinline__ int unit_pixel(const SysDesc& sd, int u, int ppt) {
 __host__ __device__ __forceinline__ int unit_count(const SysDesc& sd, int ppt) {
   return sd.active ? sd.n_active : (sd.H * sd.W + ppt - 1) / ppt;
 }
+// Pixels of the adjoint's support, and pixel u of it.
+__device__ __forceinline__ int grad_support_count(const SysDesc& sd) { return sd.gsup ? *sd.gsup_n : sd.H * sd.W; }
+__device__ __forceinline__ int grad_support_pixel(const SysDesc& sd, int u) { return sd.gsup ? sd.gsup[u] : u; }
 
 constexpr int RENDER_BLOCK = 256;
 

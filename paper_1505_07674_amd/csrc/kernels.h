@@ -144,9 +144,16 @@ hipError_t launch_finalize(const float2* partials, const int* point_pbase, const
 hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n_blocks, int square_psf, int TW,
                               int TH, int ph, int pw, int n_points, int H, int W, hipStream_t st);
 
+// Rebuilds the adjoint's support (SysDesc::gsup) of every system in the device
+// table sys[0 .. n_sys) whose gsup is set, from its weights: a row pass and a
+// column pass of the PSF-box dilation of w > 0 into gflags, then one block per
+// system compacts the flags into the pixel list. max_pixels bounds H W.
+hipError_t launch_grad_support(const SysDesc* sys, int n_sys, int max_pixels, hipStream_t st);
+
 // Per-(point, render tile) sums of g d^2/N^2 times the 17 gradient moments of
 // the subsamples (each partial dI/dtheta is a fixed per-point combination of
-// them): gpart[(gpbase[p] + tile) * 17 + k],
+// them): gpart[(gpbase[p] + tile) * 17 + k], tile t covering pixels
+// 256 t .. 256 t + 255 of the support (zero past its end),
 // then the float64 cusp corrections of the waves in cl (the list the forward
 // render filled) added to corr[p * 17 + k], which must start at zero.
 hipError_t launch_grad(const WorkArgs& w, const PointConst* pcs, const PointConst64* p64s, const GradConst* gcs,

@@ -396,11 +396,21 @@ __global__ __launch_bounds__(RENDER_BLOCK) void model_grad_kernel(WorkArgs w, Mo
   const int comp = kind == 0 ? pass : pass - spec.n_sie;
   const int off = kind == 0 ? 5 * comp : (kind == 1 ? 5 * spec.n_sie + (spec.shear ? 2 : 0) + 7 * comp : 5 * spec.n_sie);
   const int npar = kind == 0 ? 5 : (kind == 1 ? 7 : (spec.shear ? 2 : 0) + (spec.sky ? 1 : 0));
+  const int n_sup = grad_support_count(sd);
+  if (tile * RENDER_BLOCK >= n_sup) {   // past the support's last pixel: zero sums
+    if ((int)threadIdx.x < npar) {
+      const int i = threadIdx.x;
+      const int slot = kind == 2 && spec.sky && i == npar - 1 ? P - 1 : off + i;
+      gpart[(size_t)(gpbase[point] + tile) * P + slot] = 0.0;
+    }
+    return;
+  }
   double acc[7];
 #pragma unroll
   for (int i = 0; i < 7; ++i) acc[i] = 0.0;
-  const int pix = tile * RENDER_BLOCK + (int)threadIdx.x;
-  const float gp = pix < sd.H * sd.W ? G[loff + pix] : 0.0f;
+  const int unit = tile * RENDER_BLOCK + (int)threadIdx.x;
+  const int pix = unit < n_sup ? grad_support_pixel(sd, unit) : 0;
+  const float gp = unit < n_sup ? G[loff + pix] : 0.0f;
   if (gp != 0.0f) {   // pixels outside the reach of any weighted residual add nothing
     const int r = row_of(sd, pix), c = pix - r * sd.W;
     const double ux = (double)c - 0.5 * (double)(sd.W - 1), uy = (double)r - 0.5 * (double)(sd.H - 1);

@@ -154,6 +154,7 @@ class BatchPlan {
   hipGraphExec_t exec_ = nullptr;
   int ppt_ = 1;
   int rbs_ = RENDER_BLOCK;        // threads (render units) per render block
+  int64_t max_pixels_ = 0;        // largest image of the plan (pixels)
   int max_ppt_ = 1;
   bool masked_ = false;
   int64_t rendered_pixels_ = 0;   // pixels the render stage computes per launch

@@ -366,10 +366,17 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   off = align256(off + (g && has_model_ ? sizeof(double) * (size_t)gtot * params_per_point : 0));
   const size_t o_adjk = off; off = align256(off + (g ? sizeof(float) * 16 * psf_total : 0));
   const size_t o_gcorr = off; off = align256(off + (g17 ? sizeof(double) * (size_t)n_points * NPAR : 0));
-  std::vector<size_t> o_units(n_systems);
+  std::vector<size_t> o_units(n_systems), o_gsup(n_systems);
   for (int s = 0; s < n_systems; ++s) {
     o_units[s] = off;
     off = align256(off + sizeof(int) * units[s].size());
+  }
+  max_pixels_ = 0;
+  for (int s = 0; s < n_systems; ++s) {   // the adjoint's support: count, pixel list, two flag planes
+    const size_t npix = (size_t)desc[s].H * desc[s].W;
+    max_pixels_ = std::max<int64_t>(max_pixels_, (int64_t)npix);
+    o_gsup[s] = off;
+    if (g) off = align256(off + 256 + sizeof(int) * npix + 2 * npix);
   }
   hipError_t e = hipMalloc((void**)&mem_, off);
   if (e != hipSuccess) {
@@ -405,7 +412,13 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
     d_mgpart_ = g17 ? nullptr : (double*)(mem_ + o_mgpart);
     d_gcorr_ = g17 ? (double*)(mem_ + o_gcorr) : nullptr;
     grad_ntiles_ = desc[0].n_rtiles;
-    for (int s = 0; s < n_systems; ++s) desc[s].adjk = (float*)(mem_ + o_adjk) + 16 * psf_off[s];
+    for (int s = 0; s < n_systems; ++s) {
+      desc[s].adjk = (float*)(mem_ + o_adjk) + 16 * psf_off[s];
+      const size_t npix = (size_t)desc[s].H * desc[s].W;
+      desc[s].gsup_n = (int*)(mem_ + o_gsup[s]);
+      desc[s].gsup = (int*)(mem_ + o_gsup[s] + 256);
+      desc[s].gflags = (unsigned char*)(mem_ + o_gsup[s] + 256 + sizeof(int) * npix);
+    }
   }
 
   std::vector<int> ps(map, map + n_points);
@@ -498,6 +511,8 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
     WorkArgs wg = w;
     wg.items = d_gitems_;
     wg.n_items = n_gitems_;
+    // the pixels g can reach, from the weights as they are now
+    if ((e = launch_grad_support(d_sys_, (int)systems_.size(), (int)max_pixels_, st)) != hipSuccess) return e;
     // g = A^T rho overwrites the unconvolved images, which are no longer needed
     const lensed_system& s0 = systems_[0];
     if ((e = launch_adjoint_psf(wp, d_R_, d_L_, n_pitems_, square_psf_, TW_, TH_, max_ph_, max_pw_, n_points_,
