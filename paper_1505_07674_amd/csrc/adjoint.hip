@@ -738,21 +738,19 @@ __global__ __launch_bounds__(256) void grad_support_cols_kernel(const SysDesc* _
   sd.gflags[npix + pix] = any ? 1 : 0;
 }
 
-// Compaction, one block per system: each thread counts the flags of a chunk of
-// consecutive pixels, a block scan gives each chunk its first slot, and the
-// chunks write their pixels in row-major order.
+// Compaction of the flags f[0 .. n) of units of `ppt` pixels (a unit is
+// flagged if any of its pixels is) into out[], the first pixel of each flagged
+// unit in order; returns their number to every thread. Each thread counts a
+// chunk of consecutive units, a block scan gives each chunk its first slot.
 constexpr int GSUP_THREADS = 1024;
-__global__ __launch_bounds__(GSUP_THREADS) void grad_support_compact_kernel(const SysDesc* __restrict__ sys) {
-  __shared__ int scan[GSUP_THREADS];
-  const SysDesc& sd = sys[blockIdx.x];
-  if (!sd.gsup) return;   // uniform over the block
-  const int npix = sd.H * sd.W;
-  const unsigned char* f = sd.gflags + npix;
-  const int chunk = (npix + GSUP_THREADS - 1) / GSUP_THREADS;
+__device__ int compact_units(const unsigned char* f, int npix, int ppt, int* out, int* scan) {
+  const int n = npix / ppt;
+  const int chunk = (n + GSUP_THREADS - 1) / GSUP_THREADS;
   const int t = (int)threadIdx.x;
-  const int b = min(t * chunk, npix), e = min(b + chunk, npix);
+  const int b = min(t * chunk, n), e = min(b + chunk, n);
+  auto flag = [&](int u) { return ppt == 1 ? f[u] != 0 : (f[2 * u] | f[2 * u + 1]) != 0; };
   int cnt = 0;
-  for (int i = b; i < e; ++i) cnt += f[i];
+  for (int u = b; u < e; ++u) cnt += flag(u);
   scan[t] = cnt;
   __syncthreads();
   for (int off = 1; off < GSUP_THREADS; off <<= 1) {   // inclusive Hillis-Steele scan
@@ -762,12 +760,53 @@ __global__ __launch_bounds__(GSUP_THREADS) void grad_support_compact_kernel(cons
     __syncthreads();
   }
   int pos = scan[t] - cnt;
-  for (int i = b; i < e; ++i)
-    if (f[i]) sd.gsup[pos++] = i;
-  if (t == GSUP_THREADS - 1) *sd.gsup_n = scan[t];
+  for (int u = b; u < e; ++u)
+    if (flag(u)) out[pos++] = u * ppt;
+  const int total = scan[GSUP_THREADS - 1];
+  __syncthreads();   // scan[] is reused by the next call
+  return total;
 }
 
-hipError_t launch_grad_support(const SysDesc* sys, int n_sys, int max_pixels, hipStream_t st) {
+// One block per system: the support's pixels, and with uact its render units.
+__global__ __launch_bounds__(GSUP_THREADS) void grad_support_compact_kernel(SysDesc* __restrict__ sys) {
+  __shared__ int scan[GSUP_THREADS];
+  SysDesc& sd = sys[blockIdx.x];
+  if (!sd.gsup) return;   // uniform over the block
+  const int npix = sd.H * sd.W;
+  const unsigned char* f = sd.gflags + npix;
+  const int n = compact_units(f, npix, 1, sd.gsup, scan);
+  if (threadIdx.x == 0) *sd.gsup_n = n;
+  if (!sd.uact) return;
+  const int nu = compact_units(f, npix, sd.uppt == 2 ? 2 : 1, sd.uact, scan);
+  if (threadIdx.x == 0) sd.n_active = nu;
+}
+
+// Zeroes the unconvolved image of every point outside its system's support
+// (one block per point): a gradient plan renders only the support, and the
+// PSF stage, which multiplies w = 0 by its outputs there, must read finite
+// values, not what an earlier launch left (a NaN point's image, or g).
+__global__ __launch_bounds__(256) void grad_support_clear_kernel(WorkArgs w, float* __restrict__ L, int point_base) {
+  const int point = point_base + (int)blockIdx.x;
+  const SysDesc& sd = w.sys_table[w.point_sys ? w.point_sys[point] : 0];
+  if (!sd.uact) return;
+  const int npix = sd.H * sd.W;
+  const unsigned char* need = sd.gflags + npix;
+  float* img = L + w.point_loff[point];
+  for (int pix = (int)threadIdx.x; pix < npix; pix += 256)
+    if (!need[pix]) img[pix] = 0.0f;
+}
+
+hipError_t launch_grad_clear(const WorkArgs& w, float* L, int n_points, hipStream_t st) {
+  for (int p0 = 0; p0 < n_points; p0 += 1 << 20) {   // at most 2^20 blocks per launch
+    const int np = n_points - p0 < (1 << 20) ? n_points - p0 : (1 << 20);
+    hipLaunchKernelGGL(grad_support_clear_kernel, dim3((unsigned)np), dim3(256), 0, st, w, L, p0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_grad_support(SysDesc* sys, int n_sys, int max_pixels, hipStream_t st) {
   if (n_sys <= 0 || max_pixels <= 0) return hipSuccess;
   const dim3 grid((unsigned)((max_pixels + 255) / 256), (unsigned)n_sys);
   hipLaunchKernelGGL(grad_support_rows_kernel, grid, dim3(256), 0, st, sys);

@@ -181,6 +181,12 @@ struct SysDesc {
   int* gsup;
   int* gsup_n;
   unsigned char* gflags;
+  // Render units over the same support (a 17-parameter gradient plan renders
+  // only these): the support kernels write the first pixel of each unit of
+  // uppt pixels to uact, which `active` also points to, and their number to
+  // n_active of the device copy of this descriptor. nullptr: not rebuilt.
+  int* uact;
+  int uppt;
 };
 
 // floor(n / W) for 0 <= n < 2^28 (every pixel index: H W <= 2^28) by one

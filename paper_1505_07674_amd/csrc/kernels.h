@@ -147,8 +147,14 @@ hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n
 // Rebuilds the adjoint's support (SysDesc::gsup) of every system in the device
 // table sys[0 .. n_sys) whose gsup is set, from its weights: a row pass and a
 // column pass of the PSF-box dilation of w > 0 into gflags, then one block per
-// system compacts the flags into the pixel list. max_pixels bounds H W.
-hipError_t launch_grad_support(const SysDesc* sys, int n_sys, int max_pixels, hipStream_t st);
+// system compacts the flags into the pixel list and, where uact is set, into
+// the render units (writing n_active of the table entry). max_pixels bounds H W.
+hipError_t launch_grad_support(SysDesc* sys, int n_sys, int max_pixels, hipStream_t st);
+
+// Zeroes each point's unconvolved image L outside its system's support, for the
+// systems whose render units are rebuilt with it (uact set); w carries the
+// device system table, the point-to-system map and the image offsets.
+hipError_t launch_grad_clear(const WorkArgs& w, float* L, int n_points, hipStream_t st);
 
 // Per-(point, render tile) sums of g d^2/N^2 times the 17 gradient moments of
 // the subsamples (each partial dI/dtheta is a fixed per-point combination of

@@ -377,6 +377,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
     max_pixels_ = std::max<int64_t>(max_pixels_, (int64_t)npix);
     o_gsup[s] = off;
     if (g) off = align256(off + 256 + sizeof(int) * npix + 2 * npix);
+    if (g17) off = align256(off + sizeof(int) * npix);   // render units over the support
   }
   hipError_t e = hipMalloc((void**)&mem_, off);
   if (e != hipSuccess) {
@@ -418,6 +419,12 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
       desc[s].gsup_n = (int*)(mem_ + o_gsup[s]);
       desc[s].gsup = (int*)(mem_ + o_gsup[s] + 256);
       desc[s].gflags = (unsigned char*)(mem_ + o_gsup[s] + 256 + sizeof(int) * npix);
+      if (g17) {   // the forward render covers only the support too (rebuilt with it)
+        desc[s].uact = (int*)(mem_ + align256(o_gsup[s] + 256 + sizeof(int) * npix + 2 * npix));
+        desc[s].active = desc[s].uact;
+        desc[s].uppt = class_ppt(render_class(desc[s]));
+        desc[s].n_active = 0;   // written by the support kernels before each render
+      }
     }
   }
 
@@ -480,6 +487,10 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
   if (has_model_ && (e = launch_model_prologue(theta_, n_points_, params_per_point_, spec_, d_mc_, st,
                                                 grad_ != nullptr)) != hipSuccess)
     return e;
+  // a gradient plan's support (the pixels g can reach, which are also the only
+  // pixels its forward render needs), from the weights as they are now
+  if (grad_ && (e = launch_grad_support(d_sys_, (int)systems_.size(), (int)max_pixels_, st)) != hipSuccess) return e;
+  if (grad_ && !has_model_ && (e = launch_grad_clear(w, d_L_, n_points_, st)) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
   WorkArgs wr = w;
   wr.items = d_ritems_;
@@ -511,8 +522,6 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
     WorkArgs wg = w;
     wg.items = d_gitems_;
     wg.n_items = n_gitems_;
-    // the pixels g can reach, from the weights as they are now
-    if ((e = launch_grad_support(d_sys_, (int)systems_.size(), (int)max_pixels_, st)) != hipSuccess) return e;
     // g = A^T rho overwrites the unconvolved images, which are no longer needed
     const lensed_system& s0 = systems_[0];
     if ((e = launch_adjoint_psf(wp, d_R_, d_L_, n_pitems_, square_psf_, TW_, TH_, max_ph_, max_pw_, n_points_,

@@ -208,6 +208,20 @@ def test_autograd_function_backward():
     assert torch.allclose(pts.grad, (w[:, None].float() * g), rtol=1e-6, atol=0)
 
 
+
+def grad_into(ctx, theta, system, ll, g):
+    """lensed_loglike_grad through the C ABI into fixed output buffers, so that
+    calls with the same buffers reuse the context's cached plan."""
+    import ctypes
+    from paper_1505_07674_amd.binding import _stream_handle, lib
+    rc = lib().lensed_loglike_grad(ctx.handle, ctypes.byref(system.c_struct), ctypes.c_void_p(theta.data_ptr()),
+                                   theta.shape[0], ctypes.c_void_p(ll.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                   _stream_handle(None))
+    ctx.check(rc, "lensed_loglike_grad")
+    torch.cuda.synchronize()
+    return ll.cpu().numpy().copy(), g.cpu().numpy().copy()
+
+
 def test_gradient_follows_weights_changed_in_place():
     """The gradient kernels visit only the pixels within the PSF box of a w > 0
     pixel, a support rebuilt from the weights by every launch: a cached plan
@@ -221,6 +235,8 @@ def test_gradient_follows_weights_changed_in_place():
     tp = torch.from_numpy(pts).to(DEV)
     gs = gpu_system(spec, obs)
     full = gs.weight.clone()
+    ll_buf = torch.empty(len(pts), dtype=torch.float64, device=DEV)
+    g_buf = torch.empty((len(pts), 17), dtype=torch.float32, device=DEV)
     ctx = Context(0)
     results = []
     for label, cut in (("left half masked", slice(0, 18)), ("all weights", None), ("right third masked", slice(24, 36))):
@@ -228,13 +244,13 @@ def test_gradient_follows_weights_changed_in_place():
         if cut is not None:
             gs.weight[:, cut] = 0.0
         say(f"weights in place: {label}")
-        ll, g = lensed.loglike_grad(tp, gs, ctx=ctx)
+        ll, g = grad_into(ctx, tp, gs, ll_buf, g_buf)
         fresh = Context(0)
-        ll_f, g_f = lensed.loglike_grad(tp, gs, ctx=fresh)
+        ll_f, g_f = grad_into(fresh, tp, gs, torch.empty_like(ll_buf), torch.empty_like(g_buf))
         fresh.close()
-        assert np.array_equal(ll.cpu().numpy(), ll_f.cpu().numpy()), label
-        assert np.array_equal(g.cpu().numpy(), g_f.cpu().numpy()), label
-        results.append((label, gs.weight.cpu().numpy().copy(), g.cpu().numpy()))
+        assert np.array_equal(ll, ll_f), label
+        assert np.array_equal(g, g_f), label
+        results.append((label, gs.weight.cpu().numpy().copy(), g))
     ctx.close()
     for label, w, g in results[::2]:   # the two masked states against the oracle
         osys = oracle_system(spec, mocks.Observation(spec, obs.data, w, obs.sigma))
@@ -242,3 +258,32 @@ def test_gradient_follows_weights_changed_in_place():
         rel = np.linalg.norm(g - ref, axis=1) / np.linalg.norm(ref, axis=1)
         say(f"  {label}: worst relative gradient error {rel.max():.2e}")
         assert np.all(rel <= 1e-4), (label, rel)
+
+
+def test_gradient_plan_reused_after_an_invalid_point():
+    """A gradient plan renders only the support of g and zeroes the rest of each
+    image per launch, so a NaN point in one call (its image and g are NaN)
+    leaves nothing behind for the valid point that takes its slot next."""
+    from paper_1505_07674_amd.binding import Context
+    spec = small_spec(H=40, W=36, N=2)
+    obs = small_obs(spec)
+    pts = mocks.points(spec, 6, seed=44)
+    gs = gpu_system(spec, obs)
+    gs.weight[:, 0:14] = 0.0   # a support well inside the image
+    tp = torch.from_numpy(pts).to(DEV)
+    slot = tp.clone()
+    slot[2, 0] = float("nan")
+    ll_buf = torch.empty(len(pts), dtype=torch.float64, device=DEV)
+    g_buf = torch.empty((len(pts), 17), dtype=torch.float32, device=DEV)
+    ctx = Context(0)
+    ll_bad, _ = grad_into(ctx, slot, gs, ll_buf, g_buf)
+    assert np.isnan(ll_bad[2]) and np.all(np.isfinite(ll_bad[[0, 1, 3, 4, 5]]))
+    slot.copy_(tp)   # same buffers, same plan
+    ll, g = grad_into(ctx, slot, gs, ll_buf, g_buf)
+    ctx.close()
+    fresh = Context(0)
+    ll_f, g_f = grad_into(fresh, tp, gs, torch.empty_like(ll_buf), torch.empty_like(g_buf))
+    fresh.close()
+    say(f"after a NaN point: log L {ll[2]:.6g} (fresh {ll_f[2]:.6g})")
+    assert np.array_equal(ll, ll_f)
+    assert np.array_equal(g, g_f)
