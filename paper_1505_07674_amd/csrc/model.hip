@@ -137,8 +137,11 @@ __global__ __launch_bounds__(RENDER_BLOCK) void model_render_kernel(WorkArgs w, 
   }
   const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[point] : 0] : w.single;
   const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
-  const int pix = tile * RENDER_BLOCK + (int)threadIdx.x;
-  if (pix >= sd.H * sd.W) return;
+  // render units are single pixels: the whole image, or in a gradient plan the
+  // support of g (the only pixels the PSF outputs with w > 0 read)
+  const int unit = tile * RENDER_BLOCK + (int)threadIdx.x;
+  if (unit >= unit_count(sd, 1)) return;
+  const int pix = unit_pixel(sd, unit, 1);
   const ModelConst& m = mcs[point];
   const int r = row_of(sd, pix), c = pix - r * sd.W;
   const double ux = (double)c - 0.5 * (double)(sd.W - 1), uy = (double)r - 0.5 * (double)(sd.H - 1);

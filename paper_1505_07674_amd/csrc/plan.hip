@@ -377,7 +377,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
     max_pixels_ = std::max<int64_t>(max_pixels_, (int64_t)npix);
     o_gsup[s] = off;
     if (g) off = align256(off + 256 + sizeof(int) * npix + 2 * npix);
-    if (g17) off = align256(off + sizeof(int) * npix);   // render units over the support
+    if (g) off = align256(off + sizeof(int) * npix);   // render units over the support
   }
   hipError_t e = hipMalloc((void**)&mem_, off);
   if (e != hipSuccess) {
@@ -419,10 +419,10 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
       desc[s].gsup_n = (int*)(mem_ + o_gsup[s]);
       desc[s].gsup = (int*)(mem_ + o_gsup[s] + 256);
       desc[s].gflags = (unsigned char*)(mem_ + o_gsup[s] + 256 + sizeof(int) * npix);
-      if (g17) {   // the forward render covers only the support too (rebuilt with it)
+      {   // the forward render covers only the support too (rebuilt with it)
         desc[s].uact = (int*)(mem_ + align256(o_gsup[s] + 256 + sizeof(int) * npix + 2 * npix));
         desc[s].active = desc[s].uact;
-        desc[s].uppt = class_ppt(render_class(desc[s]));
+        desc[s].uppt = has_model_ ? 1 : class_ppt(render_class(desc[s]));
         desc[s].n_active = 0;   // written by the support kernels before each render
       }
     }
@@ -490,7 +490,7 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
   // a gradient plan's support (the pixels g can reach, which are also the only
   // pixels its forward render needs), from the weights as they are now
   if (grad_ && (e = launch_grad_support(d_sys_, (int)systems_.size(), (int)max_pixels_, st)) != hipSuccess) return e;
-  if (grad_ && !has_model_ && (e = launch_grad_clear(w, d_L_, n_points_, st)) != hipSuccess) return e;
+  if (grad_ && (e = launch_grad_clear(w, d_L_, n_points_, st)) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
   WorkArgs wr = w;
   wr.items = d_ritems_;
