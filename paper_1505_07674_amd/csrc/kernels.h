@@ -9,6 +9,8 @@
 
 namespace lensed {
 
+constexpr int MAX_PSF = 63;   // largest PSF side accepted (LDS staging bound)
+
 // Work description shared by the render, PSF/chi^2 and adjoint kernels.
 // Plain calls use `single` and `point0` with implicit item = (point0, blockIdx.x);
 // batched calls pass device tables and an explicit (point, tile) item list.

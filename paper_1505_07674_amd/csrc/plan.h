@@ -14,7 +14,6 @@ struct lensed_ctx;
 
 namespace lensed {
 
-constexpr int MAX_PSF = 63;   // largest PSF side accepted (LDS staging bound)
 
 struct TileShape {
   int TW, TH;

@@ -19,10 +19,17 @@ namespace {
 // Root of P(a, b) = 1/2 by Newton's method, safeguarded by bisection, from the
 // start b0. P(a, x) = x^a e^{-x} / Gamma(a+1) * (1 + x/(a+1) + x^2/((a+1)(a+2)) + ...)
 // and dP/dx = x^{a-1} e^{-x} / Gamma(a) = (x^a e^{-x} / Gamma(a+1)) a / x.
+// Stopping: once a Newton step is below 1e-6 of b, one more step brings the
+// error, quadratically, below rounding, and the loop ends there. (Waiting for
+// a step below 4e-16 of b instead lets rounding noise in f keep the iteration
+// going, and an f that rounds to exactly 0 made the bracket send b off by a
+// bisection step: dozens of extra iterations for some n, and a wave waits for
+// its slowest lane.)
 __device__ double gamma_median(double a, double b0) {
   const double lga1 = lgamma(a + 1.0);
   double lo = 0.0, hi = a + 40.0;
   double b = (b0 > lo && b0 < hi) ? b0 : 0.5 * a + 1e-3;
+  bool last = false;
   for (int it = 0; it < 100; ++it) {
     const double pref = exp(a * log(b) - b - lga1);
     double term = 1.0, sum = 1.0;
@@ -32,12 +39,15 @@ __device__ double gamma_median(double a, double b0) {
       if (term <= 1e-17 * sum) break;
     }
     const double f = pref * sum - 0.5;
+    if (f == 0.0) break;
     if (f > 0.0) hi = b; else lo = b;
     double nb = b - f * b / (pref * a);
-    if (!(nb > lo && nb < hi)) nb = 0.5 * (lo + hi);
+    const bool newton = nb >= lo && nb <= hi;
+    if (!newton) nb = 0.5 * (lo + hi);
     const double step = fabs(nb - b);
     b = nb;
-    if (step <= 4e-16 * b) break;
+    if (last || step <= 4e-16 * b) break;
+    if (newton && step <= 1e-6 * b) last = true;
   }
   return b;
 }
@@ -172,74 +182,105 @@ __device__ float dither_round(double c, int v) {
   return frac + ((v + 0.5) / RENDER_VARIANTS - 0.5) >= 0.5 ? hi : lo;
 }
 
-// One block of 64 threads covers 64 / solves points: first each of a point's
-// `solves` threads finds one root of P(2n, b) = 1/2 (b_n of the lens and the
-// source light; with the adjoint also b at n +- h for db_n/dn), then one thread
-// per point derives the rest. Extra blocks normalise the systems' PSFs.
-__global__ __launch_bounds__(64) void prologue_kernel(const float* __restrict__ theta, int n_points, PointConst* __restrict__ pcs,
-                                PointConst64* __restrict__ p64s, GradConst* __restrict__ gcs, SysDesc single,
-                                SysDesc* __restrict__ table, int n_sys, int point_blocks, int* __restrict__ cusp_count,
-                                double* __restrict__ grad_corr, const int* __restrict__ point_sys, int solves) {
-  if (cusp_count && blockIdx.x == 0 && threadIdx.x == 0) *cusp_count = 0;
-  if ((int)blockIdx.x >= point_blocks) {
-    // PSF normalisation: one block per system, float64 sum over the array.
-    const int s = blockIdx.x - point_blocks;
-    const SysDesc sd = table ? table[s] : single;
-    const int n = sd.ph * sd.pw;
-    __shared__ double part[64];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += (double)sd.psf[i];
-    part[threadIdx.x] = acc;
+// Per system (one block each): the PSF normalised to unit sum in float64 and
+// stored three ways (row-major; column-major flipped, the convolution's taps;
+// column-major, the transpose's taps), and for the adjoint the 16 folded
+// tables of the transposed convolution. For border class (cr, cc) (0 interior,
+// 1 first, 2 last, 3 both, per axis) the entry at offset (a, b) sums the
+// kernel over the offsets the replicate padding maps there: first -> offsets
+// a..p, last -> -p..a, both -> all (only a = 0). Each such sum is a rectangle
+// of a float64 summed-area table of the PSF.
+constexpr int PSF_PREP_THREADS = 256;
+__global__ __launch_bounds__(PSF_PREP_THREADS) void psf_prepare_kernel(SysDesc single, SysDesc* __restrict__ table) {
+  __shared__ double part[PSF_PREP_THREADS];
+  __shared__ double sat[(MAX_PSF + 1) * (MAX_PSF + 1)];
+  const SysDesc sd = table ? table[blockIdx.x] : single;
+  const int n = sd.ph * sd.pw, t = (int)threadIdx.x;
+  double acc = 0.0;
+  for (int i = t; i < n; i += PSF_PREP_THREADS) acc += (double)sd.psf[i];
+  part[t] = acc;
+  __syncthreads();
+  for (int w = PSF_PREP_THREADS / 2; w > 0; w >>= 1) {
+    if (t < w) part[t] += part[t + w];
     __syncthreads();
-    for (int w = 32; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-      __syncthreads();
+  }
+  const double inv = 1.0 / part[0];
+  for (int i = t; i < n; i += PSF_PREP_THREADS) {
+    sd.psfn[i] = (float)((double)sd.psf[i] * inv);
+    const int l = i / sd.ph, k = i - l * sd.ph;
+    sd.psfn[n + i] = (float)((double)sd.psf[(sd.ph - 1 - k) * sd.pw + (sd.pw - 1 - l)] * inv);
+    sd.psfn[2 * n + i] = (float)((double)sd.psf[k * sd.pw + l] * inv);
+  }
+  if (!sd.adjk) return;   // uniform over the block
+  // summed-area table S[i][j] = sum of psf[a][b] over a < i, b < j: row sums, then column sums
+  const int SW = sd.pw + 1;
+  for (int i = t; i <= sd.ph; i += PSF_PREP_THREADS) {
+    double r = 0.0;
+    sat[i * SW] = 0.0;
+    for (int j = 0; j < sd.pw; ++j) {
+      if (i > 0) r += (double)sd.psf[(i - 1) * sd.pw + j];
+      sat[i * SW + j + 1] = r;
     }
-    const double inv = 1.0 / part[0];
-    // three copies: row-major; column-major flipped (the convolution's taps, column
-    // l = KW-1-b, row k = KH-1-a for entry (a, b)); column-major (the transpose's taps)
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      sd.psfn[i] = (float)((double)sd.psf[i] * inv);
-      const int l = i / sd.ph, k = i - l * sd.ph;
-      sd.psfn[n + i] = (float)((double)sd.psf[(sd.ph - 1 - k) * sd.pw + (sd.pw - 1 - l)] * inv);
-      sd.psfn[2 * n + i] = (float)((double)sd.psf[k * sd.pw + l] * inv);
+  }
+  __syncthreads();
+  for (int j = t; j <= sd.pw; j += PSF_PREP_THREADS) {
+    double c = 0.0;
+    for (int i = 0; i <= sd.ph; ++i) {
+      c += sat[i * SW + j];
+      sat[i * SW + j] = c;
     }
-    if (sd.adjk) {
-      // Folded tables of the transposed convolution: for border class (cr, cc)
-      // (0 interior, 1 first, 2 last, 3 both, per axis) the entry at offset (a, b)
-      // sums the normalised kernel over the offsets the replicate padding maps
-      // there: first -> offsets a..p, last -> -p..a, both -> all (only a = 0).
-      const int p = sd.ph / 2, q = sd.pw / 2;
-      for (int i = threadIdx.x; i < 16 * n; i += blockDim.x) {
-        const int cls = i / n, e = i - cls * n;
-        const int cr = cls >> 2, cc = cls & 3;
-        const int a = e / sd.pw - p, b = e % sd.pw - q;
-        int a0, a1, b0, b1;
-        switch (cr) {
-          case 0: a0 = a; a1 = a; break;
-          case 1: a0 = a; a1 = a >= 0 ? p : a - 1; break;
-          case 2: a0 = -p; a1 = a <= 0 ? a : -p - 1; break;
-          default: a0 = -p; a1 = a == 0 ? p : -p - 1; break;
-        }
-        switch (cc) {
-          case 0: b0 = b; b1 = b; break;
-          case 1: b0 = b; b1 = b >= 0 ? q : b - 1; break;
-          case 2: b0 = -q; b1 = b <= 0 ? b : -q - 1; break;
-          default: b0 = -q; b1 = b == 0 ? q : -q - 1; break;
-        }
-        double acc = 0.0;
-        for (int aa = a0; aa <= a1; ++aa)
-          for (int bb = b0; bb <= b1; ++bb) acc += (double)sd.psf[(aa + p) * sd.pw + (bb + q)];
-        sd.adjk[i] = (float)(acc * inv);
+  }
+  __syncthreads();
+  const int p = sd.ph / 2, q = sd.pw / 2;
+  for (int i = t; i < 16 * n; i += PSF_PREP_THREADS) {
+    const int cls = i / n, e = i - cls * n;
+    const int cr = cls >> 2, cc = cls & 3;
+    const int a = e / sd.pw - p, b = e % sd.pw - q;
+    int a0, a1, b0, b1;
+    switch (cr) {
+      case 0: a0 = a; a1 = a; break;
+      case 1: a0 = a; a1 = a >= 0 ? p : a - 1; break;
+      case 2: a0 = -p; a1 = a <= 0 ? a : -p - 1; break;
+      default: a0 = -p; a1 = a == 0 ? p : -p - 1; break;
+    }
+    switch (cc) {
+      case 0: b0 = b; b1 = b; break;
+      case 1: b0 = b; b1 = b >= 0 ? q : b - 1; break;
+      case 2: b0 = -q; b1 = b <= 0 ? b : -q - 1; break;
+      default: b0 = -q; b1 = b == 0 ? q : -q - 1; break;
+    }
+    double sum = 0.0;
+    if (a1 >= a0 && b1 >= b0) {
+      if (a0 == a1 && b0 == b1) {
+        sum = (double)sd.psf[(a0 + p) * sd.pw + (b0 + q)];   // a single tap, exactly
+      } else {
+        const int r0 = a0 + p, r1 = a1 + p + 1, c0 = b0 + q, c1 = b1 + q + 1;
+        sum = (sat[r1 * SW + c1] - sat[r0 * SW + c1]) - (sat[r1 * SW + c0] - sat[r0 * SW + c0]);
       }
     }
-    return;
+    sd.adjk[i] = (float)(sum * inv);
   }
+}
+
+// One block of 64 threads covers PROLOGUE_POINTS points, PROLOGUE_LANES lanes
+// each: first `solves` lanes of a point each find one root of P(2n, b) = 1/2
+// (b_n of the lens and the source light; with the adjoint also b at n +- h for
+// db_n/dn), then one lane derives the rest, and all the point's lanes share the
+// 16 x 32 dithered roundings of the render variants. Extra blocks normalise
+// the systems' PSFs.
+constexpr int PROLOGUE_LANES = 16;
+constexpr int PROLOGUE_POINTS = 64 / PROLOGUE_LANES;
+__global__ __launch_bounds__(64) void prologue_kernel(const float* __restrict__ theta, int n_points,
+                                                      PointConst* __restrict__ pcs, PointConst64* __restrict__ p64s,
+                                                      GradConst* __restrict__ gcs, const SysDesc* __restrict__ table,
+                                                      const int* __restrict__ point_sys, int* __restrict__ cusp_count,
+                                                      double* __restrict__ grad_corr, SysDesc single, int solves) {
+  if (cusp_count && blockIdx.x == 0 && threadIdx.x == 0) *cusp_count = 0;
   __shared__ double roots[64];
-  const int ppb = 64 / solves;
-  const int pl = threadIdx.x / solves, j = threadIdx.x - pl * solves;
-  const int p = blockIdx.x * ppb + pl;
-  if (pl >= ppb || p >= n_points) return;   // no barrier below waits for these lanes' points
+  __shared__ double folded[PROLOGUE_POINTS][32];
+  const int pl = threadIdx.x / PROLOGUE_LANES, j = threadIdx.x % PROLOGUE_LANES;
+  const int p = blockIdx.x * PROLOGUE_POINTS + pl;
+  if (p >= n_points) return;   // no barrier below waits for these lanes' points
   float t[NPAR];
   bool valid = true;
   for (int k = 0; k < NPAR; ++k) {
@@ -251,7 +292,7 @@ __global__ __launch_bounds__(64) void prologue_kernel(const float* __restrict__ 
   // roots: j = 0, 1: b_n of lens and source light; j = 2, 3 (4, 5): the same at n + h (n - h), h = 1e-5 n
   {
     double r = 0.0;
-    if (valid) {
+    if (valid && j < solves) {
       const double n = (j & 1) ? t[14] : t[7];
       r = j < 2 ? sersic_bn(n) : sersic_bn(j < 4 ? n + 1e-5 * n : n - 1e-5 * n);
     }
@@ -260,222 +301,228 @@ __global__ __launch_bounds__(64) void prologue_kernel(const float* __restrict__ 
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  if (j != 0) return;
-  const double* rt = roots + threadIdx.x;
-
-  PointHead c;
-  const double te = t[0], q = t[1], phL = t[2], g = t[3], phg = t[4];
-  c.cL = (float)cos(phL);
-  c.sL = (float)sin(phL);
-  const double s2 = (1.0 - q) * (1.0 + q);
-  const double qp = sqrt(s2);
-  c.q2 = (float)(q * q);
-  c.qp = (float)qp;
-  c.iq = (float)(1.0 / q);
-  if (s2 == 0.0) {
-    c.sie_mode = 0;
-    c.kc = (float)te;
-    c.ks = 0.0f;
-  } else {
-    c.sie_mode = qp <= 0.5 ? 1 : 2;
-    const double k = te * sqrt(q) / qp;
-    c.kc = (float)(k * cos(phL));
-    c.ks = (float)(k * sin(phL));
-  }
-  const double g1 = g * cos(2.0 * phg), g2 = g * sin(2.0 * phg);
-  c.m11 = (float)(1.0 - g1);
-  c.m12 = (float)(-g2);
-  c.m22 = (float)(1.0 + g1);
-
-  const double bh = rt[0], bs = rt[1];
-  // amplitudes: I_e given, or from total magnitudes (the point's system decides)
-  const SysDesc* own = table ? &table[point_sys ? point_sys[p] : 0] : &single;
-  const int amp = own->amp;
-  double Ih = t[5], Is = t[12];
-  AmpFromMag ah = {0.0, 0.0, 0.0, 0.0}, as = {0.0, 0.0, 0.0, 0.0};
-  double dbh = 0.0, dbs = 0.0;
-  if (valid && gcs) {
-    // central differences of the root, truncation of order 1e-10 relative
-    dbh = (rt[2] - rt[4]) / (2e-5 * (double)t[7]);
-    dbs = (rt[3] - rt[5]) / (2e-5 * (double)t[14]);
-  }
-  if (valid && amp) {
-    ah = amplitude_from_magnitude(t[5], t[6], t[7], bh, dbh, own->zp);
-    as = amplitude_from_magnitude(t[12], t[13], t[14], bs, dbs, own->zp);
-    Ih = ah.I;
-    Is = as.I;
-  }
-  // source centre: given, or the image of an image-plane point (Sec. 5)
-  const int srcpos = own->srcpos;
-  double xs = t[10], ys = t[11];
-  float jac[14] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  if (valid && srcpos) {
-    const double v[7] = {t[10], t[11], t[0], t[1], t[2], t[3], t[4]};
-    lens_map_f64(v, xs, ys);
-    if (gcs) lens_map_jacobian(v, jac);
-  }
-  {
-    const double Re = t[6], qh = t[8], ph = t[9];
-    c.hc = (float)cos(ph);
-    c.hs = (float)sin(ph);
-    c.hqa = (float)(qh / (Re * Re));
-    c.hqb = (float)(1.0 / (qh * Re * Re));
-    c.he = (float)(0.5 / (double)t[7]);
-    c.hB = (float)(bh * LOG2E);
-    c.hI = (float)Ih;
-  }
-  {
-    const double Re = t[13], qs = t[15], ph = t[16];
-    c.sx0 = (float)xs;
-    c.sy0 = (float)ys;
-    c.sc = (float)cos(ph);
-    c.ss = (float)sin(ph);
-    c.sqa = (float)(qs / (Re * Re));
-    c.sqb = (float)(1.0 / (qs * Re * Re));
-    c.se = (float)(0.5 / (double)t[14]);
-    c.sB = (float)(bs * LOG2E);
-    c.sI = (float)Is;
-  }
-  // re-trace in float64 near a cuspy (n > 1) source centre (source-plane radius)
-  {
-    const double Re = t[13], rc = (srcpos ? CUSP_RADIUS_IMAGE_PLANE_ARCSEC : CUSP_RADIUS_ARCSEC) / Re;
-    c.cusp_r2 = t[14] > 1.0f ? (float)(rc * rc) : 0.0f;
-  }
-  // folded constants of the forward render (float64), then their dithered
-  // float32 roundings, one set per variant
-  double tac = te, tas = 0.0, thc = 0.0, ths = 0.0;
-  c.rmode = 0;
-  for (int k = 0; k < 11; ++k) c.poly[k] = 0.0f;
-  if (s2 != 0.0) {
-    const double k = te * sqrt(q) / qp;
-    const double fa = qp <= 0.5 ? 1.0 : 2.0, fh = qp <= 0.5 ? 1.0 : 0.693147180559945309417;
-    c.rmode = qp <= 0.5 ? 1 : (q >= 0.5 ? 2 : 3);
-    tac = fa * k * cos(phL);
-    tas = fa * k * sin(phL);
-    thc = fh * k * cos(phL);
-    ths = fh * k * sin(phL);
-    // deflection polynomials with q' folded in: coefficient j is c_j q'^(2j+1)
-    const double qp2 = qp * qp;
-    double pw = qp * qp2;
-    if (c.rmode == 3) {
-      for (int j = 1; j <= ATAN_UNIT_POLY_DEGREE; ++j, pw *= qp2) c.poly[j] = (float)(ATAN_UNIT_POLY_D[j] * pw);
+  const double* rt = roots + pl * PROLOGUE_LANES;
+  if (j == 0) {   // the point's head, its float64 folded constants (to LDS) and the adjoint's constants
+    PointHead c;
+    const double te = t[0], q = t[1], phL = t[2], g = t[3], phg = t[4];
+    c.cL = (float)cos(phL);
+    c.sL = (float)sin(phL);
+    const double s2 = (1.0 - q) * (1.0 + q);
+    const double qp = sqrt(s2);
+    c.q2 = (float)(q * q);
+    c.qp = (float)qp;
+    c.iq = (float)(1.0 / q);
+    if (s2 == 0.0) {
+      c.sie_mode = 0;
+      c.kc = (float)te;
+      c.ks = 0.0f;
     } else {
-      for (int j = 1; j <= ATAN_SMALL_POLY_DEGREE; ++j, pw *= qp2) c.poly[j] = (float)(ATAN_SMALL_POLY_D[j] * pw);
+      c.sie_mode = qp <= 0.5 ? 1 : 2;
+      const double k = te * sqrt(q) / qp;
+      c.kc = (float)(k * cos(phL));
+      c.ks = (float)(k * sin(phL));
     }
-    if (c.rmode == 1) {
-      pw = qp * qp2;
-      for (int j = 1; j <= ATANH_POLY_DEGREE; ++j, pw *= qp2)
-        c.poly[ATAN_SMALL_POLY_DEGREE + j] = (float)(ATANH_POLY_D[j] * pw);
-    }
-  }
-  double f[32];
-  for (int k = 0; k < 32; ++k) f[k] = 0.0;
-  f[0] = cos(phL);
-  f[1] = sin(phL);
-  f[2] = q * q;
-  f[3] = 1.0 / q;
-  f[4] = qp;
-  {
-    const double Re = t[13], qs = t[15], ph = t[16];
-    const double a = sqrt(qs) / Re, b = 1.0 / (sqrt(qs) * Re), cs = cos(ph), sn = sin(ph);
-    const double s11 = a * cs, s12 = a * sn, s21 = -b * sn, s22 = b * cs;
-    // the source frame of the lens equation in one step (float64 products, one rounding each)
-    const double m11 = 1.0 - g1, m12 = -g2, m22 = 1.0 + g1;
-    f[5] = s11 * m11 + s12 * m12;            // A1
-    f[6] = s21 * m11 + s22 * m12;            // A2
-    f[7] = s11 * m12 + s12 * m22;            // B1
-    f[8] = s21 * m12 + s22 * m22;            // B2
-    f[9] = -(s11 * xs + s12 * ys);           // C1
-    f[10] = -(s21 * xs + s22 * ys);          // C2
-    f[11] = -(s11 * tac + s12 * tas);        // cXt
-    f[12] = s11 * ths - s12 * thc;           // cXh
-    f[13] = -(s21 * tac + s22 * tas);        // cYt
-    f[14] = s21 * ths - s22 * thc;           // cYh
-    f[23] = s11;
-    f[24] = s12;
-    f[25] = s21;
-    f[26] = s22;
-  }
-  {
-    // lens light about the origin: R^2/R_e^2 = X^2 + Y^2 = (ha x + hb y) x + hc y^2
-    const double Re = t[6], qh = t[8], ph = t[9];
-    const double a = sqrt(qh) / Re, b = 1.0 / (sqrt(qh) * Re), cs = cos(ph), sn = sin(ph);
-    const double h11 = a * cs, h12 = a * sn, h21 = -b * sn, h22 = b * cs;
-    f[15] = h11 * h11 + h21 * h21;           // ha
-    f[16] = 2.0 * (h11 * h12 + h21 * h22);   // hb
-    f[17] = h12 * h12 + h22 * h22;           // hc
-  }
-  f[18] = 0.5 / (double)t[7];                // he
-  f[19] = bh * LOG2E;                        // hB
-  f[20] = 0.5 / (double)t[14];               // se
-  f[21] = bs * LOG2E;                        // sB
-  f[22] = tac;
-  if (!valid) f[5] = f[6] = __builtin_nan("");
-  for (int v = 0; v < RENDER_VARIANTS; ++v) {
-    float* o = reinterpret_cast<float*>(&pcs[p].rv[v]);
-    for (int k = 0; k < 32; ++k) o[k] = dither_round(f[k], v);
-  }
-  c.hIlo = (float)(Ih - (double)c.hI);
-  c.sIlo = (float)(Is - (double)c.sI);
-  for (int k = 0; k < 22; ++k) c.pad[k] = 0.0f;
-  if (!valid) {
-    const float nan = __builtin_nanf("");
-    c.m11 = c.m12 = c.m22 = nan;
-    c.hI = c.sI = nan;
-  }
-  static_cast<PointHead&>(pcs[p]) = c;   // the variants are already in place
-  if (p64s) {
-    PointConst64 e;
-    e.cL = cos(phL);
-    e.sL = sin(phL);
-    e.q2 = q * q;
-    e.qp = qp;
-    e.te = te;
-    e.k = s2 == 0.0 ? te : te * sqrt(q) / qp;
-    e.mode = s2 == 0.0 ? 0 : 1;
-    e.pad0 = 0;
-    e.m11 = 1.0 - g1;
-    e.m12 = -g2;
-    e.m22 = 1.0 + g1;
-    e.sx0 = xs;
-    e.sy0 = ys;
-    for (int k = 0; k < 4; ++k) e.pad[k] = 0.0;
-    if (!valid) e.m11 = e.m12 = e.m22 = __builtin_nan("");
-    p64s[p] = e;
-  }
+    const double g1 = g * cos(2.0 * phg), g2 = g * sin(2.0 * phg);
+    c.m11 = (float)(1.0 - g1);
+    c.m12 = (float)(-g2);
+    c.m22 = (float)(1.0 + g1);
 
-  if (grad_corr)
-    for (int k = 0; k < NPAR; ++k) grad_corr[(size_t)p * NPAR + k] = 0.0;
-  if (gcs) {
-    GradConst gc;
-    for (int k = 0; k < NPAR; ++k) gc.theta[k] = t[k];
-    gc.bh = (float)bh;
-    gc.bs = (float)bs;
-    gc.dB_dn_h = valid ? (float)(dbh * LOG2E) : __builtin_nanf("");
-    gc.dB_dn_s = valid ? (float)(dbs * LOG2E) : __builtin_nanf("");
-    gc.amp_chain[0] = (float)ah.dm;
-    gc.amp_chain[1] = (float)ah.dR;
-    gc.amp_chain[2] = (float)ah.dn;
-    gc.amp_chain[3] = (float)as.dm;
-    gc.amp_chain[4] = (float)as.dR;
-    gc.amp_chain[5] = (float)as.dn;
-    gc.amp = amp;
-    for (int k = 0; k < 14; ++k) gc.src_jac[k] = jac[k];
-    gc.srcpos = srcpos;
-    GradUniform& u = gc.u;
-    u.tesq = (float)(te * sqrt(q));
-    u.iqp = s2 == 0.0 ? 0.0f : (float)(1.0 / qp);
-    u.s = (float)s2;
-    u.hs = s2 == 0.0 ? 0.0f : (float)(0.5 / s2);
-    u.iq2 = (float)(1.0 / (q * q));
-    u.bH = (float)bh;
-    u.bS = (float)bs;
-    u.dbH = (float)dbh;
-    u.dbS = (float)dbs;
-    u.kS1 = (float)cos((double)t[16] - phL);
-    u.kS2 = (float)sin((double)t[16] - phL);
-    for (int k = 0; k < 10; ++k) gc.pad[k] = 0.0f;
-    gcs[p] = gc;
+    const double bh = rt[0], bs = rt[1];
+    // amplitudes: I_e given, or from total magnitudes (the point's system decides)
+    const SysDesc* own = table ? &table[point_sys ? point_sys[p] : 0] : &single;
+    const int amp = own->amp;
+    double Ih = t[5], Is = t[12];
+    AmpFromMag ah = {0.0, 0.0, 0.0, 0.0}, as = {0.0, 0.0, 0.0, 0.0};
+    double dbh = 0.0, dbs = 0.0;
+    if (valid && gcs) {
+      // central differences of the root, truncation of order 1e-10 relative
+      dbh = (rt[2] - rt[4]) / (2e-5 * (double)t[7]);
+      dbs = (rt[3] - rt[5]) / (2e-5 * (double)t[14]);
+    }
+    if (valid && amp) {
+      ah = amplitude_from_magnitude(t[5], t[6], t[7], bh, dbh, own->zp);
+      as = amplitude_from_magnitude(t[12], t[13], t[14], bs, dbs, own->zp);
+      Ih = ah.I;
+      Is = as.I;
+    }
+    // source centre: given, or the image of an image-plane point (Sec. 5)
+    const int srcpos = own->srcpos;
+    double xs = t[10], ys = t[11];
+    float jac[14] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (valid && srcpos) {
+      const double v[7] = {t[10], t[11], t[0], t[1], t[2], t[3], t[4]};
+      lens_map_f64(v, xs, ys);
+      if (gcs) lens_map_jacobian(v, jac);
+    }
+    {
+      const double Re = t[6], qh = t[8], ph = t[9];
+      c.hc = (float)cos(ph);
+      c.hs = (float)sin(ph);
+      c.hqa = (float)(qh / (Re * Re));
+      c.hqb = (float)(1.0 / (qh * Re * Re));
+      c.he = (float)(0.5 / (double)t[7]);
+      c.hB = (float)(bh * LOG2E);
+      c.hI = (float)Ih;
+    }
+    {
+      const double Re = t[13], qs = t[15], ph = t[16];
+      c.sx0 = (float)xs;
+      c.sy0 = (float)ys;
+      c.sc = (float)cos(ph);
+      c.ss = (float)sin(ph);
+      c.sqa = (float)(qs / (Re * Re));
+      c.sqb = (float)(1.0 / (qs * Re * Re));
+      c.se = (float)(0.5 / (double)t[14]);
+      c.sB = (float)(bs * LOG2E);
+      c.sI = (float)Is;
+    }
+    // re-trace in float64 near a cuspy (n > 1) source centre (source-plane radius)
+    {
+      const double Re = t[13], rc = (srcpos ? CUSP_RADIUS_IMAGE_PLANE_ARCSEC : CUSP_RADIUS_ARCSEC) / Re;
+      c.cusp_r2 = t[14] > 1.0f ? (float)(rc * rc) : 0.0f;
+    }
+    // folded constants of the forward render (float64), then their dithered
+    // float32 roundings, one set per variant
+    double tac = te, tas = 0.0, thc = 0.0, ths = 0.0;
+    c.rmode = 0;
+    for (int k = 0; k < 11; ++k) c.poly[k] = 0.0f;
+    if (s2 != 0.0) {
+      const double k = te * sqrt(q) / qp;
+      const double fa = qp <= 0.5 ? 1.0 : 2.0, fh = qp <= 0.5 ? 1.0 : 0.693147180559945309417;
+      c.rmode = qp <= 0.5 ? 1 : (q >= 0.5 ? 2 : 3);
+      tac = fa * k * cos(phL);
+      tas = fa * k * sin(phL);
+      thc = fh * k * cos(phL);
+      ths = fh * k * sin(phL);
+      // deflection polynomials with q' folded in: coefficient j is c_j q'^(2j+1)
+      const double qp2 = qp * qp;
+      double pw = qp * qp2;
+      if (c.rmode == 3) {
+        for (int j = 1; j <= ATAN_UNIT_POLY_DEGREE; ++j, pw *= qp2) c.poly[j] = (float)(ATAN_UNIT_POLY_D[j] * pw);
+      } else {
+        for (int j = 1; j <= ATAN_SMALL_POLY_DEGREE; ++j, pw *= qp2) c.poly[j] = (float)(ATAN_SMALL_POLY_D[j] * pw);
+      }
+      if (c.rmode == 1) {
+        pw = qp * qp2;
+        for (int j = 1; j <= ATANH_POLY_DEGREE; ++j, pw *= qp2)
+          c.poly[ATAN_SMALL_POLY_DEGREE + j] = (float)(ATANH_POLY_D[j] * pw);
+      }
+    }
+    double f[32];
+    for (int k = 0; k < 32; ++k) f[k] = 0.0;
+    f[0] = cos(phL);
+    f[1] = sin(phL);
+    f[2] = q * q;
+    f[3] = 1.0 / q;
+    f[4] = qp;
+    {
+      const double Re = t[13], qs = t[15], ph = t[16];
+      const double a = sqrt(qs) / Re, b = 1.0 / (sqrt(qs) * Re), cs = cos(ph), sn = sin(ph);
+      const double s11 = a * cs, s12 = a * sn, s21 = -b * sn, s22 = b * cs;
+      // the source frame of the lens equation in one step (float64 products, one rounding each)
+      const double m11 = 1.0 - g1, m12 = -g2, m22 = 1.0 + g1;
+      f[5] = s11 * m11 + s12 * m12;            // A1
+      f[6] = s21 * m11 + s22 * m12;            // A2
+      f[7] = s11 * m12 + s12 * m22;            // B1
+      f[8] = s21 * m12 + s22 * m22;            // B2
+      f[9] = -(s11 * xs + s12 * ys);           // C1
+      f[10] = -(s21 * xs + s22 * ys);          // C2
+      f[11] = -(s11 * tac + s12 * tas);        // cXt
+      f[12] = s11 * ths - s12 * thc;           // cXh
+      f[13] = -(s21 * tac + s22 * tas);        // cYt
+      f[14] = s21 * ths - s22 * thc;           // cYh
+      f[23] = s11;
+      f[24] = s12;
+      f[25] = s21;
+      f[26] = s22;
+    }
+    {
+      // lens light about the origin: R^2/R_e^2 = X^2 + Y^2 = (ha x + hb y) x + hc y^2
+      const double Re = t[6], qh = t[8], ph = t[9];
+      const double a = sqrt(qh) / Re, b = 1.0 / (sqrt(qh) * Re), cs = cos(ph), sn = sin(ph);
+      const double h11 = a * cs, h12 = a * sn, h21 = -b * sn, h22 = b * cs;
+      f[15] = h11 * h11 + h21 * h21;           // ha
+      f[16] = 2.0 * (h11 * h12 + h21 * h22);   // hb
+      f[17] = h12 * h12 + h22 * h22;           // hc
+    }
+    f[18] = 0.5 / (double)t[7];                // he
+    f[19] = bh * LOG2E;                        // hB
+    f[20] = 0.5 / (double)t[14];               // se
+    f[21] = bs * LOG2E;                        // sB
+    f[22] = tac;
+    if (!valid) f[5] = f[6] = __builtin_nan("");
+    for (int k = 0; k < 32; ++k) folded[pl][k] = f[k];
+    c.hIlo = (float)(Ih - (double)c.hI);
+    c.sIlo = (float)(Is - (double)c.sI);
+    for (int k = 0; k < 22; ++k) c.pad[k] = 0.0f;
+    if (!valid) {
+      const float nan = __builtin_nanf("");
+      c.m11 = c.m12 = c.m22 = nan;
+      c.hI = c.sI = nan;
+    }
+    static_cast<PointHead&>(pcs[p]) = c;   // the variants are already in place
+    if (p64s) {
+      PointConst64 e;
+      e.cL = cos(phL);
+      e.sL = sin(phL);
+      e.q2 = q * q;
+      e.qp = qp;
+      e.te = te;
+      e.k = s2 == 0.0 ? te : te * sqrt(q) / qp;
+      e.mode = s2 == 0.0 ? 0 : 1;
+      e.pad0 = 0;
+      e.m11 = 1.0 - g1;
+      e.m12 = -g2;
+      e.m22 = 1.0 + g1;
+      e.sx0 = xs;
+      e.sy0 = ys;
+      for (int k = 0; k < 4; ++k) e.pad[k] = 0.0;
+      if (!valid) e.m11 = e.m12 = e.m22 = __builtin_nan("");
+      p64s[p] = e;
+    }
+
+    if (grad_corr)
+      for (int k = 0; k < NPAR; ++k) grad_corr[(size_t)p * NPAR + k] = 0.0;
+    if (gcs) {
+      GradConst gc;
+      for (int k = 0; k < NPAR; ++k) gc.theta[k] = t[k];
+      gc.bh = (float)bh;
+      gc.bs = (float)bs;
+      gc.dB_dn_h = valid ? (float)(dbh * LOG2E) : __builtin_nanf("");
+      gc.dB_dn_s = valid ? (float)(dbs * LOG2E) : __builtin_nanf("");
+      gc.amp_chain[0] = (float)ah.dm;
+      gc.amp_chain[1] = (float)ah.dR;
+      gc.amp_chain[2] = (float)ah.dn;
+      gc.amp_chain[3] = (float)as.dm;
+      gc.amp_chain[4] = (float)as.dR;
+      gc.amp_chain[5] = (float)as.dn;
+      gc.amp = amp;
+      for (int k = 0; k < 14; ++k) gc.src_jac[k] = jac[k];
+      gc.srcpos = srcpos;
+      GradUniform& u = gc.u;
+      u.tesq = (float)(te * sqrt(q));
+      u.iqp = s2 == 0.0 ? 0.0f : (float)(1.0 / qp);
+      u.s = (float)s2;
+      u.hs = s2 == 0.0 ? 0.0f : (float)(0.5 / s2);
+      u.iq2 = (float)(1.0 / (q * q));
+      u.bH = (float)bh;
+      u.bS = (float)bs;
+      u.dbH = (float)dbh;
+      u.dbS = (float)dbs;
+      u.kS1 = (float)cos((double)t[16] - phL);
+      u.kS2 = (float)sin((double)t[16] - phL);
+      for (int k = 0; k < 10; ++k) gc.pad[k] = 0.0f;
+      gcs[p] = gc;
+    }
+  }
+  // the dithered float32 roundings of the folded constants, one set per render
+  // variant: lane j of the point rounds constants j and j + 16
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  for (int k = j; k < 32; k += PROLOGUE_LANES) {
+    const double fk = folded[pl][k];
+    for (int v = 0; v < RENDER_VARIANTS; ++v) reinterpret_cast<float*>(&pcs[p].rv[v])[k] = dither_round(fk, v);
   }
 }
 
@@ -589,12 +636,16 @@ hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, Po
                            double* grad_corr, const int* point_sys) {
   const int threads = 64;
   const int solves = gcs ? 6 : 2;
-  const int ppb = threads / solves;
+  const int ppb = PROLOGUE_POINTS;
   const int point_blocks = (n_points + ppb - 1) / ppb;
-  const int blocks = point_blocks + n_sys;
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(prologue_kernel, dim3(blocks), dim3(threads), 0, stream, theta, n_points, pcs, p64s, gcs,
-                     single, table, n_sys, point_blocks, cusp_count, grad_corr, point_sys, solves);
+  if (n_sys > 0) {
+    hipLaunchKernelGGL(psf_prepare_kernel, dim3(n_sys), dim3(PSF_PREP_THREADS), 0, stream, single, table);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (point_blocks == 0 && !cusp_count) return hipSuccess;
+  hipLaunchKernelGGL(prologue_kernel, dim3(point_blocks > 0 ? point_blocks : 1), dim3(threads), 0, stream, theta,
+                     n_points, pcs, p64s, gcs, table, point_sys, cusp_count, grad_corr, single, solves);
   return hipGetLastError();
 }
 
