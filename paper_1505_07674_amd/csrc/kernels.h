@@ -48,10 +48,11 @@ hipError_t for_item_parts(const WorkArgs& w, int n_blocks, F launch) {
 // cusp-correction accumulators of every point in grad_corr. The system of
 // point p is table[point_sys[p]] (table[0] without point_sys; single without
 // table); its amplitude mode decides whether theta[5] and theta[12] are I_e or
-// total magnitudes.
+// total magnitudes. adjoint_tables: the systems' adjk tables (set in their
+// descriptors) are filled too, as every gradient plan needs.
 hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, PointConst64* p64s, GradConst* gcs,
                            const SysDesc& single, SysDesc* table, int n_sys, int* cusp_count, hipStream_t stream,
-                           double* grad_corr = nullptr, const int* point_sys = nullptr);
+                           double* grad_corr = nullptr, const int* point_sys = nullptr, bool adjoint_tables = false);
 
 // Unconvolved pixel luminosities into L (scratch or the caller's image): the
 // float32 render kernel, then the float64 cusp corrections of the pixels it

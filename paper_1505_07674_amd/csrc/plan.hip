@@ -482,7 +482,8 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
   if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
   // the 17-parameter prologue also normalises the PSFs; with a general model it does only that
   if ((e = launch_prologue(theta_, has_model_ ? 0 : n_points_, d_pc_, d_p64_, d_gc_, none, d_sys_,
-                           (int)systems_.size(), cusp_.count, st, d_gcorr_, d_point_sys_)) != hipSuccess)
+                           (int)systems_.size(), cusp_.count, st, d_gcorr_, d_point_sys_, grad_ != nullptr)) !=
+      hipSuccess)
     return e;
   if (has_model_ && (e = launch_model_prologue(theta_, n_points_, params_per_point_, spec_, d_mc_, st,
                                                 grad_ != nullptr)) != hipSuccess)

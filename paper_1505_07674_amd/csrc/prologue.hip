@@ -190,27 +190,39 @@ __device__ float dither_round(double c, int v) {
 // kernel over the offsets the replicate padding maps there: first -> offsets
 // a..p, last -> -p..a, both -> all (only a = 0). Each such sum is a rectangle
 // of a float64 summed-area table of the PSF.
+// The normalisation by a block of T threads (part: T doubles of LDS); returns
+// 1 / sum.
+template <int T>
+__device__ double psf_normalise(const SysDesc& sd, double* part) {
+  const int n = sd.ph * sd.pw, t = (int)threadIdx.x;
+  double acc = 0.0;
+  for (int i = t; i < n; i += T) acc += (double)sd.psf[i];
+  part[t] = acc;
+  __syncthreads();
+  for (int w = T / 2; w > 0; w >>= 1) {
+    if (t < w) part[t] += part[t + w];
+    __syncthreads();
+  }
+  const double inv = 1.0 / part[0];
+  for (int i = t; i < n; i += T) {
+    sd.psfn[i] = (float)((double)sd.psf[i] * inv);
+    const int l = i / sd.ph, k = i - l * sd.ph;
+    sd.psfn[n + i] = (float)((double)sd.psf[(sd.ph - 1 - k) * sd.pw + (sd.pw - 1 - l)] * inv);
+    sd.psfn[2 * n + i] = (float)((double)sd.psf[k * sd.pw + l] * inv);
+  }
+  return inv;
+}
+
+// Launched before the prologue when the plan has the adjoint (the forward
+// plans normalise in extra blocks of the prologue kernel instead, one launch
+// fewer per call).
 constexpr int PSF_PREP_THREADS = 256;
 __global__ __launch_bounds__(PSF_PREP_THREADS) void psf_prepare_kernel(SysDesc single, SysDesc* __restrict__ table) {
   __shared__ double part[PSF_PREP_THREADS];
   __shared__ double sat[(MAX_PSF + 1) * (MAX_PSF + 1)];
   const SysDesc sd = table ? table[blockIdx.x] : single;
   const int n = sd.ph * sd.pw, t = (int)threadIdx.x;
-  double acc = 0.0;
-  for (int i = t; i < n; i += PSF_PREP_THREADS) acc += (double)sd.psf[i];
-  part[t] = acc;
-  __syncthreads();
-  for (int w = PSF_PREP_THREADS / 2; w > 0; w >>= 1) {
-    if (t < w) part[t] += part[t + w];
-    __syncthreads();
-  }
-  const double inv = 1.0 / part[0];
-  for (int i = t; i < n; i += PSF_PREP_THREADS) {
-    sd.psfn[i] = (float)((double)sd.psf[i] * inv);
-    const int l = i / sd.ph, k = i - l * sd.ph;
-    sd.psfn[n + i] = (float)((double)sd.psf[(sd.ph - 1 - k) * sd.pw + (sd.pw - 1 - l)] * inv);
-    sd.psfn[2 * n + i] = (float)((double)sd.psf[k * sd.pw + l] * inv);
-  }
+  const double inv = psf_normalise<PSF_PREP_THREADS>(sd, part);
   if (!sd.adjk) return;   // uniform over the block
   // summed-area table S[i][j] = sum of psf[a][b] over a < i, b < j: row sums, then column sums
   const int SW = sd.pw + 1;
@@ -274,8 +286,15 @@ __global__ __launch_bounds__(64) void prologue_kernel(const float* __restrict__ 
                                                       PointConst* __restrict__ pcs, PointConst64* __restrict__ p64s,
                                                       GradConst* __restrict__ gcs, const SysDesc* __restrict__ table,
                                                       const int* __restrict__ point_sys, int* __restrict__ cusp_count,
-                                                      double* __restrict__ grad_corr, SysDesc single, int solves) {
+                                                      double* __restrict__ grad_corr, SysDesc single, int solves,
+                                                      int point_blocks) {
   if (cusp_count && blockIdx.x == 0 && threadIdx.x == 0) *cusp_count = 0;
+  if ((int)blockIdx.x >= point_blocks) {   // PSF normalisation, one block per system
+    __shared__ double part[64];
+    const int s = blockIdx.x - point_blocks;
+    psf_normalise<64>(table ? table[s] : single, part);
+    return;
+  }
   __shared__ double roots[64];
   __shared__ double folded[PROLOGUE_POINTS][32];
   const int pl = threadIdx.x / PROLOGUE_LANES, j = threadIdx.x % PROLOGUE_LANES;
@@ -633,19 +652,22 @@ hipError_t launch_model_prologue(const float* theta, int n_points, int n_params,
 
 hipError_t launch_prologue(const float* theta, int n_points, PointConst* pcs, PointConst64* p64s, GradConst* gcs,
                            const SysDesc& single, SysDesc* table, int n_sys, int* cusp_count, hipStream_t stream,
-                           double* grad_corr, const int* point_sys) {
+                           double* grad_corr, const int* point_sys, bool adjoint_tables) {
   const int threads = 64;
   const int solves = gcs ? 6 : 2;
   const int ppb = PROLOGUE_POINTS;
   const int point_blocks = (n_points + ppb - 1) / ppb;
-  if (n_sys > 0) {
+  // with the adjoint the PSF also gets its folded tables, in a kernel of its own
+  const bool prep = adjoint_tables && n_sys > 0;
+  if (prep) {
     hipLaunchKernelGGL(psf_prepare_kernel, dim3(n_sys), dim3(PSF_PREP_THREADS), 0, stream, single, table);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (point_blocks == 0 && !cusp_count) return hipSuccess;
-  hipLaunchKernelGGL(prologue_kernel, dim3(point_blocks > 0 ? point_blocks : 1), dim3(threads), 0, stream, theta,
-                     n_points, pcs, p64s, gcs, table, point_sys, cusp_count, grad_corr, single, solves);
+  const int blocks = point_blocks + (prep ? 0 : n_sys);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(prologue_kernel, dim3(blocks), dim3(threads), 0, stream, theta, n_points, pcs,
+                     p64s, gcs, table, point_sys, cusp_count, grad_corr, single, solves, point_blocks);
   return hipGetLastError();
 }
 
