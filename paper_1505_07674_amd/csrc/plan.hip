@@ -371,13 +371,15 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
     o_units[s] = off;
     off = align256(off + sizeof(int) * units[s].size());
   }
+  // the adjoint's support per system: its count (a 256-byte slot), pixel list
+  // and two flag planes, then the render units over it (aligned)
+  auto gsup_units_offset = [](size_t npix) { return align256(256 + sizeof(int) * npix + 2 * npix); };
   max_pixels_ = 0;
-  for (int s = 0; s < n_systems; ++s) {   // the adjoint's support: count, pixel list, two flag planes
+  for (int s = 0; s < n_systems; ++s) {
     const size_t npix = (size_t)desc[s].H * desc[s].W;
     max_pixels_ = std::max<int64_t>(max_pixels_, (int64_t)npix);
     o_gsup[s] = off;
-    if (g) off = align256(off + 256 + sizeof(int) * npix + 2 * npix);
-    if (g) off = align256(off + sizeof(int) * npix);   // render units over the support
+    if (g) off = align256(off + gsup_units_offset(npix) + sizeof(int) * npix);
   }
   hipError_t e = hipMalloc((void**)&mem_, off);
   if (e != hipSuccess) {
@@ -419,12 +421,11 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
       desc[s].gsup_n = (int*)(mem_ + o_gsup[s]);
       desc[s].gsup = (int*)(mem_ + o_gsup[s] + 256);
       desc[s].gflags = (unsigned char*)(mem_ + o_gsup[s] + 256 + sizeof(int) * npix);
-      {   // the forward render covers only the support too (rebuilt with it)
-        desc[s].uact = (int*)(mem_ + align256(o_gsup[s] + 256 + sizeof(int) * npix + 2 * npix));
-        desc[s].active = desc[s].uact;
-        desc[s].uppt = has_model_ ? 1 : class_ppt(render_class(desc[s]));
-        desc[s].n_active = 0;   // written by the support kernels before each render
-      }
+      // the forward render covers only the support too, in units rebuilt with it
+      desc[s].uact = (int*)(mem_ + o_gsup[s] + gsup_units_offset(npix));
+      desc[s].active = desc[s].uact;
+      desc[s].uppt = has_model_ ? 1 : class_ppt(render_class(desc[s]));
+      desc[s].n_active = 0;   // written by the support kernels before each render
     }
   }
 
