@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--points", type=int, default=4096)
-    ap.add_argument("--plain-points", type=int, default=1024)
+    ap.add_argument("--plain-points", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-points-per-core", type=int, default=10)
     ap.add_argument("--no-mixed", action="store_true", help="skip the 16-system mixed batch line")
