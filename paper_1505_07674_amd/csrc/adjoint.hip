@@ -712,7 +712,8 @@ hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n
 
 // The adjoint's support, rebuilt from the weights on every launch so that a
 // plan stays right when the caller changes the weights in place. Row pass:
-// any w > 0 within q = pw/2 columns (clamped to the row).
+// any w > 0 within q = pw/2 columns (clamped to the row); it also marks the
+// PSF tiles that hold a pixel with w > 0.
 __global__ __launch_bounds__(256) void grad_support_rows_kernel(const SysDesc* __restrict__ sys) {
   const SysDesc& sd = sys[blockIdx.y];
   const int pix = (int)blockIdx.x * 256 + (int)threadIdx.x;
@@ -723,6 +724,7 @@ __global__ __launch_bounds__(256) void grad_support_rows_kernel(const SysDesc* _
   bool any = false;
   for (int cc = max(c - q, 0); cc <= c1; ++cc) any = any || wr[cc] > 0.0f;
   sd.gflags[pix] = any ? 1 : 0;
+  if (sd.ptile_w && wr[c] > 0.0f) sd.ptile_w[(r / sd.TH) * sd.tiles_x + c / sd.TW] = 1;
 }
 
 // Column pass: any row-pass flag within p = ph/2 rows (clamped to the column).

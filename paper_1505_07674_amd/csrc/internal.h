@@ -164,9 +164,10 @@ struct SysDesc {
   double wgt;             // quadrature weight pixscale^2 / N^2, in float64
   float* adjk;            // 16 folded PSF tables of the adjoint (or nullptr)
   float* adjk_pad;
-  // Render units of a masked plan: the first pixel of each unit (a pixel, or a
-  // pair of adjacent pixels) that the chi^2 can see, row-major; nullptr: every
-  // pixel, unit u starting at pixel u * ppt.
+  // Render units of a masked plan (built on the host) or of a gradient plan
+  // (uact below, rebuilt on the device): the first pixel of each unit (a
+  // pixel, or a pair of adjacent pixels) that the chi^2 can see, row-major;
+  // nullptr: every pixel, unit u starting at pixel u * ppt.
   const int* active;
   int n_active;           // units in `active`
   int pad_active;
@@ -187,6 +188,11 @@ struct SysDesc {
   // n_active of the device copy of this descriptor. nullptr: not rebuilt.
   int* uact;
   int uppt;
+  // Per PSF output tile of a gradient plan: 1 if it holds a pixel with w > 0
+  // (set by the support kernels each launch, cleared by the PSF preparation);
+  // the PSF stage skips the others, whose chi^2 terms and rho are all zero.
+  // nullptr: every tile is convolved.
+  unsigned char* ptile_w;
 };
 
 // floor(n / W) for 0 <= n < 2^28 (every pixel index: H W <= 2^28) by one

@@ -379,7 +379,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
     const size_t npix = (size_t)desc[s].H * desc[s].W;
     max_pixels_ = std::max<int64_t>(max_pixels_, (int64_t)npix);
     o_gsup[s] = off;
-    if (g) off = align256(off + gsup_units_offset(npix) + sizeof(int) * npix);
+    if (g) off = align256(align256(off + gsup_units_offset(npix) + sizeof(int) * npix) + desc[s].n_ptiles);
   }
   hipError_t e = hipMalloc((void**)&mem_, off);
   if (e != hipSuccess) {
@@ -426,6 +426,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
       desc[s].active = desc[s].uact;
       desc[s].uppt = has_model_ ? 1 : class_ppt(render_class(desc[s]));
       desc[s].n_active = 0;   // written by the support kernels before each render
+      desc[s].ptile_w = (unsigned char*)(mem_ + align256(o_gsup[s] + gsup_units_offset(npix) + sizeof(int) * npix));
     }
   }
 

@@ -222,6 +222,8 @@ __global__ __launch_bounds__(PSF_PREP_THREADS) void psf_prepare_kernel(SysDesc s
   __shared__ double sat[(MAX_PSF + 1) * (MAX_PSF + 1)];
   const SysDesc sd = table ? table[blockIdx.x] : single;
   const int n = sd.ph * sd.pw, t = (int)threadIdx.x;
+  if (sd.ptile_w)   // the support kernels, which run next, mark the tiles with w > 0
+    for (int i = t; i < sd.n_ptiles; i += PSF_PREP_THREADS) sd.ptile_w[i] = 0;
   const double inv = psf_normalise<PSF_PREP_THREADS>(sd, part);
   if (!sd.adjk) return;   // uniform over the block
   // summed-area table S[i][j] = sum of psf[a][b] over a < i, b < j: row sums, then column sums

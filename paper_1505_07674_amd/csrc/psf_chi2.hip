@@ -55,6 +55,15 @@ __global__ __launch_bounds__(P >= 0 && TWc == 0 ? WIDE_MAX_THREADS : 512) void p
   const int tid = threadIdx.x;
   const int jx = tid % TW, jy = tid / TW;
   const int rows_per_pass = blockDim.x / TW;
+  if (sd.ptile_w && !sd.ptile_w[tile]) {   // no pixel with w > 0 (gradient plans): zero chi^2, zero rho
+    if (mode == 2)
+      for (int k = tid; k < TW * TH; k += blockDim.x) {
+        const int gi = y0 + k / TW, gj = x0 + k % TW;
+        if (gi < sd.H && gj < sd.W) out[loff + (size_t)gi * sd.W + gj] = 0.0f;
+      }
+    if (tid == 0) partials[(w.point_pbase ? w.point_pbase[point] : 0) + tile] = make_float2(0.0f, 0.0f);
+    return;
+  }
 
   // Stage the tile and its halo, four rows per pass so that four loads are in
   // flight before their LDS stores.
