@@ -131,7 +131,7 @@ class BatchPlan {
   int* d_pbase_ = nullptr;
   int* d_ntiles_ = nullptr;
   int2* d_ritems_ = nullptr;
-  int2* d_gitems_ = nullptr;      // gradient plans: (point, 256-pixel tile) items
+  int2* d_gitems_ = nullptr;      // gradient plans: (point, 256-pixel tile of the support of g) items
   int n_gitems_ = 0;
   int2* d_pitems_ = nullptr;
   PointConst* d_pc_ = nullptr;

@@ -328,7 +328,9 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   n_pitems_ = (int)pitems.size();
   std::vector<int2> ri(n_ritems_), pi(n_pitems_);
   for (int i = 0; i < n_ritems_; ++i) ri[i] = make_int2(ritems[i].point, ritems[i].tile);
-  // the gradient kernels take one pixel per thread: (point, 256-pixel tile) items
+  // the gradient kernels take one pixel per thread: (point, tile) items, tile t
+  // covering pixels 256 t .. 256 t + 255 of the support of g (tiles past the
+  // support's end write zero sums)
   std::vector<int2> gi;
   if (grad)
     for (int p = 0; p < n_points; ++p)
