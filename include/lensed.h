@@ -291,6 +291,8 @@ int lensed_loglike_model_batch(lensed_ctx* ctx, const lensed_system* systems, in
  *   logl   device float64 [n_points], written
  *   grad   device float32 [n_points * P], written (d log L / d theta, in the
  *          parameter order of the model)
+ * Like lensed_loglike_grad, each call renders and differentiates only the
+ * pixels within the PSF box of a weighted pixel, from the weights as they are.
  * A model with n_planes > 1 is rejected with LENSED_INVALID_ARGUMENT. */
 int lensed_loglike_model_grad(lensed_ctx* ctx, const lensed_system* sys, const lensed_model* model,
                               const float* theta, int n_points, double* logl, float* grad, void* stream);
@@ -368,7 +370,12 @@ int lensed_weights_from_data(lensed_ctx* ctx, const float* data, int64_t n, doub
  *   logl   device float64 [n_points], written
  *   grad   device float32 [n_points * 17], written (d log L / d theta)
  * Any integration rule of the system (midpoint or Gauss-Kronrod) and either
- * amplitude parametrisation (the entries 5 and 12 are then d/dm). */
+ * amplitude parametrisation (the entries 5 and 12 are then d/dm). Each call
+ * derives from the weights as they are then the pixels within the PSF box of
+ * a pixel with w > 0 (the only pixels log L and g = A^T rho depend on) and
+ * renders and differentiates only those; PSF output tiles without a weighted
+ * pixel are skipped, so non-finite data there does not reach log L (the
+ * weights may change between calls that reuse the cached plan). */
 int lensed_loglike_grad(lensed_ctx* ctx, const lensed_system* sys, const float* theta,
                         int n_points, double* logl, float* grad, void* stream);
 
