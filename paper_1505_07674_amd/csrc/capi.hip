@@ -278,7 +278,7 @@ int lensed_render(lensed_ctx* c, const lensed_system* sys, const float* theta, f
   if (!theta || !image) return set_err(c, LENSED_INVALID_ARGUMENT, "theta and image are required");
   LENSED_HIP(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
-  const TileShape ts = c->tiles.choose(*sys);
+  const TileShape ts = TileCache::latency_best(*sys);   // one image: a latency-ranked tile
   SysDesc sd = make_desc(*sys, ts);
   const size_t npix = (size_t)sd.H * sd.W;
   const size_t off_pc = 0;
@@ -317,7 +317,7 @@ int lensed_render_composite(lensed_ctx* c, const lensed_system* sys, const float
   LENSED_HIP(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   const int K = n_components;
-  const TileShape ts = c->tiles.choose(*sys);
+  const TileShape ts = TileCache::latency_best(*sys);   // one image: a latency-ranked tile
   SysDesc sd = make_desc(*sys, ts);
   const size_t npix = (size_t)sd.H * sd.W;
   const size_t off_pc = 0;
@@ -360,7 +360,7 @@ int lensed_render_error(lensed_ctx* c, const lensed_system* sys, const float* th
   if (!theta || !error) return set_err(c, LENSED_INVALID_ARGUMENT, "theta and error are required");
   LENSED_HIP(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
-  const TileShape ts = c->tiles.choose(*sys);
+  const TileShape ts = TileCache::latency_best(*sys);   // one image: a latency-ranked tile
   SysDesc sd = make_desc(*sys, ts);
   const size_t off_pc = 0;
   const size_t off_p64 = align_up(off_pc + sizeof(PointConst), 256);
@@ -401,7 +401,7 @@ int lensed_loglike(lensed_ctx* c, const lensed_system* sys, const float* theta, 
   if (!theta || !logl) return set_err(c, LENSED_INVALID_ARGUMENT, "theta and logl are required");
   LENSED_HIP(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
-  const TileShape ts = c->tiles.choose(*sys);
+  const TileShape ts = TileCache::latency_best(*sys);   // one image: a latency-ranked tile
   SysDesc sd = make_desc(*sys, ts);
   const size_t npix = (size_t)sd.H * sd.W;
   const size_t off_pc = 0;
@@ -676,7 +676,7 @@ int lensed_render_model(lensed_ctx* c, const lensed_system* sys, const lensed_mo
   if (!theta || !image) return set_err(c, LENSED_INVALID_ARGUMENT, "theta and image are required");
   LENSED_HIP(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
-  const TileShape ts = c->tiles.choose(*sys);
+  const TileShape ts = TileCache::latency_best(*sys);   // one image: a latency-ranked tile
   SysDesc sd = make_desc(*sys, ts);
   const size_t npix = (size_t)sd.H * sd.W;
   const size_t off_mc = 0;

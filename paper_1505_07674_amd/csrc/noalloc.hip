@@ -40,7 +40,7 @@ extern "C" int lensed_loglike_noalloc(const lensed_system* sys, const float* the
   if (scratch_err[dev] != hipSuccess || !scratch_ptr[dev]) return LENSED_HIP_ERROR;
 
   // the layout of lensed_loglike's workspace, inside the static array
-  const TileShape ts = TileCache::model_best(*sys);
+  const TileShape ts = TileCache::latency_best(*sys);   // the tile lensed_loglike uses
   SysDesc sd = make_desc(*sys, ts);
   const size_t npix = (size_t)sd.H * sd.W;
   const size_t off_pc = 0;

@@ -26,6 +26,9 @@ struct TileShape {
 // fastest per set of system shapes, which then overrides the model.
 class TileCache {
  public:
+  // The tile for one image (the single-point entry points): the specialised
+  // 32- or 64-wide tiles, ranked by latency, not by throughput.
+  static TileShape latency_best(const lensed_system& s);
   TileShape choose(const lensed_system& s);
   TileShape choose_common(const lensed_system* s, int n);
   std::vector<TileShape> ranked(const lensed_system* s, int n, int k) const;

@@ -1,5 +1,6 @@
 // plan.hip -- tile-shape model and batched plans with captured hipGraphs.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 
@@ -74,6 +75,33 @@ double TileCache::model_cost(int H, int W, int ph, int pw, TileShape t, int sq) 
   const double per_lane = tap * (double)R * ph * pw + 0.5 * (double)pw * (R + ph - 1);
   const double staging = 6.0 * (double)(t.TW + pw - 1) * (double)(t.TH + ph - 1);
   return ntiles * (lanes * per_lane + staging + 2000.0);
+}
+
+// One image runs on a few blocks, so what counts is how long a block takes:
+// its waves share the CU's four SIMDs, and each thread applies R ph pw taps.
+// Cost: (waves per SIMD, from the block's own waves or from the whole launch
+// spread over 1024 SIMDs, whichever is larger) x the taps per thread, plus
+// the block's LDS staging per thread.
+TileShape TileCache::latency_best(const lensed_system& s) {
+  const int sq = square_psf_code(s.psf_h, s.psf_w);
+  TileShape best{32, 32};
+  double bc = 1e300;
+  each_candidate(sq, &s, 1, [&](TileShape t) {
+    if (t.TW != 32 && t.TW != 64) return;
+    const int R = psf_rows(sq, t.TW, t.TH);
+    const int threads = t.TW * t.TH / R;
+    const double waves = (double)((threads + 63) / 64);
+    const double ntiles = (double)((s.width + t.TW - 1) / t.TW) * (double)((s.height + t.TH - 1) / t.TH);
+    const double per_simd = std::max(std::ceil(waves / 4.0), std::ceil(ntiles * waves / 1024.0));
+    const double tap = psf_specialised(sq, t.TW) ? 1.0 : 2.0;
+    const double cst = per_simd * tap * R * s.psf_h * s.psf_w +
+                       6.0 * (double)(t.TW + s.psf_w - 1) * (double)(t.TH + s.psf_h - 1) / threads;
+    if (cst < bc) {
+      bc = cst;
+      best = t;
+    }
+  });
+  return best;
 }
 
 std::string TileCache::key(const lensed_system* s, int n) {
