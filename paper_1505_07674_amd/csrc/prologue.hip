@@ -4,7 +4,7 @@
 // wave-uniform constants the render kernels consume (trigonometry, the shear
 // matrix, reciprocal radii and the Sersic b_n). b_n is the root of
 // P(2n, b) = 1/2 (R_e is the half-light radius, Sec. 4.1 Eq. 22), solved here in
-// float64 by a bracketed Newton iteration on the power series of the
+// float64 by a bracketed Halley iteration on the power series of the
 // regularised incomplete gamma function. Extra blocks normalise each system's
 // PSF to unit sum (Sec. 3.1).
 #include <math.h>
@@ -16,11 +16,12 @@
 namespace lensed {
 namespace {
 
-// Root of P(a, b) = 1/2 by Newton's method, safeguarded by bisection, from the
-// start b0. P(a, x) = x^a e^{-x} / Gamma(a+1) * (1 + x/(a+1) + x^2/((a+1)(a+2)) + ...)
-// and dP/dx = x^{a-1} e^{-x} / Gamma(a) = (x^a e^{-x} / Gamma(a+1)) a / x.
-// Stopping: once a Newton step is below 1e-6 of b, one more step brings the
-// error, quadratically, below rounding, and the loop ends there. (Waiting for
+// Root of P(a, b) = 1/2 by Halley's method, safeguarded by bisection, from the
+// start b0. P(a, x) = x^a e^{-x} / Gamma(a+1) * (1 + x/(a+1) + x^2/((a+1)(a+2)) + ...),
+// dP/dx = x^{a-1} e^{-x} / Gamma(a) = (x^a e^{-x} / Gamma(a+1)) a / x and
+// d2P/dx2 = dP/dx ((a - 1)/x - 1). Stopping: once a step is below 1e-4 of b,
+// one more step brings the error, cubically, below rounding, and the loop ends
+// there. (Waiting for
 // a step below 4e-16 of b instead lets rounding noise in f keep the iteration
 // going, and an f that rounds to exactly 0 made the bracket send b off by a
 // bisection step: dozens of extra iterations for some n, and a wave waits for
@@ -41,20 +42,21 @@ __device__ double gamma_median(double a, double b0) {
     const double f = pref * sum - 0.5;
     if (f == 0.0) break;
     if (f > 0.0) hi = b; else lo = b;
-    double nb = b - f * b / (pref * a);
-    const bool newton = nb >= lo && nb <= hi;
-    if (!newton) nb = 0.5 * (lo + hi);
+    const double d1 = pref * a / b, d2 = d1 * ((a - 1.0) / b - 1.0);
+    double nb = b - 2.0 * f * d1 / (2.0 * d1 * d1 - f * d2);
+    const bool inside = nb >= lo && nb <= hi;
+    if (!inside) nb = 0.5 * (lo + hi);
     const double step = fabs(nb - b);
     b = nb;
     if (last || step <= 4e-16 * b) break;
-    if (newton && step <= 1e-6 * b) last = true;
+    if (inside && step <= 1e-4 * b) last = true;
   }
   return b;
 }
 
 // b_n (R_e is the half-light radius, Sec. 4.1 Eq. 22), started from the
 // asymptotic expansion of Ciotti & Bertin (1999): within 4e-4 for n >= 0.5 and
-// within 2e-3 at n = 0.3, so Newton needs two or three steps.
+// within 2e-3 at n = 0.3, so Halley needs two or three steps.
 __device__ double sersic_bn(double n) {
   const double in = 1.0 / n;
   const double b0 = 2.0 * n - 1.0 / 3.0 +
@@ -178,7 +180,8 @@ __device__ float dither_round(double c, int v) {
     hi = f;
     lo = nextafterf(f, -__builtin_inff());
   }
-  const double frac = (c - (double)lo) / ((double)hi - (double)lo);
+  // hi - lo is a power of two, so the quotient is an exact scaling
+  const double frac = ldexp(c - (double)lo, -ilogb((double)hi - (double)lo));
   return frac + ((v + 0.5) / RENDER_VARIANTS - 0.5) >= 0.5 ? hi : lo;
 }
 
@@ -615,7 +618,7 @@ __global__ __launch_bounds__(64) void model_prologue_kernel(const float* __restr
   if (!valid) m.sky = __builtin_nan("");
 }
 
-// b_n of every Sersic of every valid point, one Newton solve per thread: lane
+// b_n of every Sersic of every valid point, one root solve per thread: lane
 // c of a block is a (point, component) pair, and with with_db the block's
 // second and third waves solve at n (1 +- 1e-5) for db_n/dn by central
 // differences (truncation of order 1e-10 relative). Runs after
