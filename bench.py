@@ -266,8 +266,8 @@ def next_rows(lensed, mocks, dev, stream, spec, obs, steps=3):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(the path shards by points across GPUs, but no multi-GPU run is part of it)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path would shard by points across GPUs; this benchmark runs one GPU's share)", file=sys.stderr)
         sys.exit(2)
     import torch
 
