@@ -327,6 +327,27 @@ int lensed_loglike_composite(lensed_ctx* ctx, const lensed_system* systems, int 
                              int n_components, const float* sky, const int32_t* system_of_model, int n_models,
                              double* logl, void* stream);
 
+/* log L of composite models (as lensed_loglike_composite, one system) and its
+ * gradient with respect to every component's 17 parameters and the sky: the
+ * components share the model's residual, so component k's gradient is that of
+ * Eq. 17 through Eqs. 15, 14, 2 and 1 with g = A^T rho of the model, and the
+ * sky, which adds sky x pixscale^2 to every pixel, has d log L / d sky =
+ * pixscale^2 x sum of rho (the PSF keeps a constant image constant).
+ *   theta     device float32 [n_models * n_components * 17], as in
+ *             lensed_loglike_composite
+ *   sky       device float32 [n_models], or NULL for no sky
+ *   logl      device float64 [n_models], written
+ *   grad      device float32 [n_models * n_components * 17], written
+ *   grad_sky  device float32 [n_models], written; NULL exactly when sky is NULL
+ * n_components = 1 without a sky is lensed_loglike_grad. A multi-band fit
+ * (lensed_loglike_multiband) sums the bands' log L, so its gradient is the
+ * sum over its bands of this one, band by band. Errors as
+ * lensed_loglike_composite; LENSED_INVALID_ARGUMENT when only one of sky and
+ * grad_sky is given. */
+int lensed_loglike_composite_grad(lensed_ctx* ctx, const lensed_system* sys, const float* theta, int n_components,
+                                  const float* sky, int n_models, double* logl, float* grad, float* grad_sky,
+                                  void* stream);
+
 /* Simultaneous fits of several bands (Sec. 6 names the joint reconstruction of
  * multiple bands as an extension): the bands' noise is independent, so a
  * model's log L is the sum over its bands of Eq. 17, each band being its own

@@ -138,6 +138,7 @@ def lib():
                 "lensed_loglike_batch": (i, [vp, sp, i, vp, ctypes.POINTER(ctypes.c_int32), i, vp, vp]),
                 "lensed_loglike_grad": (i, [vp, sp, vp, i, vp, vp, vp]),
                 "lensed_loglike_model_grad": (i, [vp, sp, vp, vp, i, vp, vp, vp]),
+                "lensed_loglike_composite_grad": (i, [vp, sp, vp, i, vp, i, vp, vp, vp, vp]),
                 "lensed_set_profiling": (i, [vp, i]),
                 "lensed_mlp_param_count": (i, []),
                 "lensed_mlp_forward": (i, [vp, vp, vp, vp, vp, i, vp]),
@@ -550,6 +551,35 @@ def loglike_grad(theta: torch.Tensor, system: System, *, ctx: Optional[Context] 
                                    _stream_handle(stream))
     ctx.check(rc, "lensed_loglike_grad")
     return ll, g
+
+
+def loglike_composite_grad(theta: torch.Tensor, n_components: int, system: System, *,
+                           sky: Optional[torch.Tensor] = None, ctx: Optional[Context] = None,
+                           stream=None):
+    """log L and its gradient for composite models of n_components points on one
+    system -> (float64 [n_models], float32 [n_models * n_components, 17],
+    float32 [n_models] d log L / d sky or None without a sky)."""
+    t = _theta2d(theta)
+    n_points = t.shape[0]
+    if n_components < 1 or n_points % n_components:
+        raise ValueError("theta must hold n_models x n_components points")
+    n_models = n_points // n_components
+    ctx = ctx or default_context(t.device.index)
+    ll = torch.empty(n_models, dtype=torch.float64, device=t.device)
+    g = torch.empty((n_points, NPARAM), dtype=torch.float32, device=t.device)
+    sk = gs = None
+    if sky is not None:
+        sk = sky.to(device=t.device, dtype=torch.float32).contiguous()
+        if sk.numel() != n_models:
+            raise ValueError("sky must hold one value per model")
+        gs = torch.empty(n_models, dtype=torch.float32, device=t.device)
+    rc = lib().lensed_loglike_composite_grad(ctx.handle, ctypes.byref(system.c_struct), ctypes.c_void_p(t.data_ptr()),
+                                             int(n_components), ctypes.c_void_p(sk.data_ptr() if sk is not None else None),
+                                             n_models, ctypes.c_void_p(ll.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                             ctypes.c_void_p(gs.data_ptr() if gs is not None else None),
+                                             _stream_handle(stream))
+    ctx.check(rc, "lensed_loglike_composite_grad")
+    return ll, g, gs
 
 
 def loglike_model_grad(theta: torch.Tensor, system: System, model: Model, *, ctx: Optional[Context] = None,

@@ -131,6 +131,7 @@ __global__ __launch_bounds__(BORDER_SEG* BORDER_SUB) void adj_border_kernel(Work
   const int point = point_base + (int)blockIdx.y;
   const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[point] : 0] : w.single;
   const int64_t loff = w.point_loff ? w.point_loff[point] : 0;
+  if (w.point_goff && w.point_goff[point] != loff) return;   // a composite model's later component: no rho of its own
   const int H = sd.H, W = sd.W, p = sd.ph / 2, q = sd.pw / 2;
   const int pw = PW > 0 ? PW : sd.pw;
   const int nrow = border_row_segments(W), nbot = H > 1 ? nrow : 0;
@@ -428,9 +429,10 @@ __global__ __launch_bounds__(RENDER_BLOCK, 6) void grad_kernel(WorkArgs w, const
 #pragma unroll
   for (int k = 0; k < NPAR; ++k) acc[k] = 0.0f;
   const int unit = tile * RENDER_BLOCK + (int)threadIdx.x;
+  const int64_t goff = w.point_goff ? w.point_goff[point] : loff;   // the composite model's g
   if (unit < n_sup) {
     const int pix = grad_support_pixel(sd, unit);
-    const float gp = G[loff + pix];
+    const float gp = G[goff + pix];
     if (gp != 0.0f) {   // pixels outside the reach of any weighted residual add nothing
       const int r = row_of(sd, pix);
       const int col = pix - r * sd.W;
@@ -530,6 +532,7 @@ __global__ __launch_bounds__(64 * GCUSP_WAVES) void grad_cusp_kernel(WorkArgs w,
     const bool mine = (e.mask >> lane) & 1ull;
     const SysDesc sd = w.sys_table ? w.sys_table[w.point_sys ? w.point_sys[e.point] : 0] : w.single;
     const int64_t loff = w.point_loff ? w.point_loff[e.point] : 0;
+    const int64_t goff = w.point_goff ? w.point_goff[e.point] : loff;   // the composite model's g
     const PointConst& c = pcs[e.point];
     const GradConst& gc = gcs[e.point];
     const GradUniform& U = gc.u;
@@ -587,7 +590,7 @@ __global__ __launch_bounds__(64 * GCUSP_WAVES) void grad_cusp_kernel(WorkArgs w,
               subsample_grad<2, true>(c, U, x, y, a64, true, dx, dy, sw);
               break;
           }
-          const float wg = (float)sd.wgt * G[loff + qpix];
+          const float wg = (float)sd.wgt * G[goff + qpix];
 #pragma unroll
           for (int k = 0; k < NPAR; ++k) acc[k] = fmaf(a64[k] - a32[k], wg, acc[k]);
         }
@@ -802,6 +805,39 @@ hipError_t launch_grad_clear(const WorkArgs& w, float* L, int n_points, hipStrea
   for (int p0 = 0; p0 < n_points; p0 += 1 << 20) {   // at most 2^20 blocks per launch
     const int np = n_points - p0 < (1 << 20) ? n_points - p0 : (1 << 20);
     hipLaunchKernelGGL(grad_support_clear_kernel, dim3((unsigned)np), dim3(256), 0, st, w, L, p0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+__global__ __launch_bounds__(256) void grad_sky_kernel(const float* __restrict__ R, const int64_t* __restrict__ loff,
+                                                        const int* __restrict__ point_sys,
+                                                        const SysDesc* __restrict__ sys, int K,
+                                                        float* __restrict__ grad_sky, int model_base) {
+  __shared__ double part[256];
+  const int m = model_base + (int)blockIdx.x;
+  const int64_t p0 = (int64_t)m * K;
+  const SysDesc& sd = sys[point_sys ? point_sys[p0] : 0];
+  const int npix = sd.H * sd.W;
+  const float* rho = R + loff[p0];
+  double acc = 0.0;
+  for (int i = (int)threadIdx.x; i < npix; i += 256) acc += (double)rho[i];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad_sky[m] = (float)(part[0] * (double)sd.d * (double)sd.d);
+}
+
+hipError_t launch_grad_sky(const float* R, const int64_t* loff, const int* point_sys, const SysDesc* sys, int K,
+                           int n_models, float* grad_sky, hipStream_t st) {
+  for (int m0 = 0; m0 < n_models; m0 += 1 << 20) {   // at most 2^20 blocks per launch
+    const int nm = n_models - m0 < (1 << 20) ? n_models - m0 : (1 << 20);
+    hipLaunchKernelGGL(grad_sky_kernel, dim3((unsigned)nm), dim3(256), 0, st, R, loff, point_sys, sys, K, grad_sky,
+                       m0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -804,12 +804,13 @@ int lensed_stage_times(lensed_ctx* c, double* ms, int n, int* calls) {
 
 // The gradient plans of one system (17-parameter model, or a general model).
 static int run_grad(lensed_ctx* c, const lensed_system* sys, const float* theta, int n_points, double* logl,
-                    float* grad, void* stream, const ModelSpec* spec, int params_per_point) {
+                    float* grad, void* stream, const ModelSpec* spec, int params_per_point, int K = 1,
+                    const float* sky = nullptr, float* grad_sky = nullptr) {
   LENSED_HIP(c, hipSetDevice(c->device));
   std::vector<int32_t> map(n_points, 0);
   BatchPlan* plan = nullptr;
   for (size_t i = 0; i < c->plans.size(); ++i) {
-    if (c->plans[i]->matches(sys, 1, theta, map.data(), n_points, logl, grad, 1, nullptr, 1, spec)) {
+    if (c->plans[i]->matches(sys, 1, theta, map.data(), n_points, logl, grad, K, sky, 1, spec, false, grad_sky)) {
       std::unique_ptr<BatchPlan> keep = std::move(c->plans[i]);
       c->plans.erase(c->plans.begin() + i);
       c->plans.push_back(std::move(keep));
@@ -829,8 +830,8 @@ static int run_grad(lensed_ctx* c, const lensed_system* sys, const float* theta,
                                                          c->force_block ? c->force_block : RENDER_BLOCK});
     std::unique_ptr<BatchPlan> np(new BatchPlan());
     std::string msg;
-    hipError_t e = np->build(sys, 1, theta, map.data(), n_points, logl, c->tiles, msg, grad, nullptr, 1, nullptr, 1,
-                             spec, params_per_point);
+    hipError_t e = np->build(sys, 1, theta, map.data(), n_points, logl, c->tiles, msg, grad, nullptr, K, sky, 1,
+                             spec, params_per_point, nullptr, false, grad_sky);
     if (e != hipSuccess) return hip_fail(c, e, ("gradient plan: " + msg).c_str());
     if (c->use_graphs) {
       e = np->capture(c->cap);
@@ -859,6 +860,24 @@ extern "C" int lensed_loglike_grad(lensed_ctx* c, const lensed_system* sys, cons
   if (rc) return rc;
   if (!theta || !logl || !grad) return set_err(c, LENSED_INVALID_ARGUMENT, "theta, logl and grad are required");
   return run_grad(c, sys, theta, n_points, logl, grad, stream, nullptr, NPAR);
+}
+
+extern "C" int lensed_loglike_composite_grad(lensed_ctx* c, const lensed_system* sys, const float* theta,
+                                             int n_components, const float* sky, int n_models, double* logl,
+                                             float* grad, float* grad_sky, void* stream) {
+  if (!c) return LENSED_INVALID_ARGUMENT;
+  if (n_models < 0) return set_err(c, LENSED_INVALID_ARGUMENT, "n_models must be >= 0");
+  if (n_components < 1) return set_err(c, LENSED_INVALID_ARGUMENT, "n_components must be >= 1");
+  if (n_models == 0) return LENSED_OK;
+  if ((int64_t)n_models * n_components > INT32_MAX / NPAR)
+    return set_err(c, LENSED_INVALID_ARGUMENT, "n_models x n_components too large");
+  int rc = validate_system(c, sys, true, -1);
+  if (rc) return rc;
+  if (!theta || !logl || !grad) return set_err(c, LENSED_INVALID_ARGUMENT, "theta, logl and grad are required");
+  if ((sky == nullptr) != (grad_sky == nullptr))
+    return set_err(c, LENSED_INVALID_ARGUMENT, "sky and grad_sky are given together or not at all");
+  return run_grad(c, sys, theta, n_models * n_components, logl, grad, stream, nullptr, NPAR, n_components, sky,
+                  grad_sky);
 }
 
 extern "C" int lensed_loglike_model_grad(lensed_ctx* c, const lensed_system* sys, const lensed_model* model,

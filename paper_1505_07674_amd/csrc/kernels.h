@@ -19,6 +19,8 @@ struct WorkArgs {
   const SysDesc* sys_table;     // [n_systems] or nullptr
   const int* point_sys;         // [n_points] system of each point, or nullptr (system 0)
   const int64_t* point_loff;    // [n_points] offset of the point's image in the scratch, or nullptr (0)
+  const int64_t* point_goff;    // [n_points] offset of the image whose g = A^T rho the point's gradient
+                                // reads (the first image of its composite model), or nullptr (point_loff)
   const int* point_pbase;       // [n_points] first partial-sum slot of the point, or nullptr (0)
   const int2* items;            // [n_items] (point, tile), or nullptr
   int n_items;                  // grid size when items is given
@@ -146,6 +148,13 @@ hipError_t launch_finalize(const float2* partials, const int* point_pbase, const
 // kernel, border pixels by the folded tables); R and G use the image offsets.
 hipError_t launch_adjoint_psf(const WorkArgs& w, const float* R, float* G, int n_blocks, int square_psf, int TW,
                               int TH, int ph, int pw, int n_points, int H, int W, hipStream_t st);
+
+// d log L / d sky of every composite model m (its points m K .. m K + K - 1,
+// its rho in R at the offset of its first image): the sky adds sky d^2 to
+// every pixel of L, the PSF keeps a constant image constant, so the
+// derivative is d^2 times the sum of rho over the image. One block per model.
+hipError_t launch_grad_sky(const float* R, const int64_t* loff, const int* point_sys, const SysDesc* sys, int K,
+                           int n_models, float* grad_sky, hipStream_t st);
 
 // Rebuilds the adjoint's support (SysDesc::gsup) of every system in the device
 // table sys[0 .. n_sys) whose gsup is set, from its weights: a row pass and a

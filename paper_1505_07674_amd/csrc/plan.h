@@ -76,7 +76,8 @@ class BatchPlan {
   // of the 17-parameter one.
   bool matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map, int n_points,
                const double* logl, const float* grad = nullptr, int K = 1, const float* sky = nullptr,
-               int G = 1, const ModelSpec* model = nullptr, bool masked = false) const;
+               int G = 1, const ModelSpec* model = nullptr, bool masked = false,
+               const float* grad_sky = nullptr) const;
   // force: use this tile shape instead of the cache's choice (autotuning);
   // force_render: use this render schedule (pixels per thread where the class
   // allows it, threads per block) instead of the cache's.
@@ -87,7 +88,8 @@ class BatchPlan {
                    int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad = nullptr,
                    const TileShape* force = nullptr, int K = 1, const float* sky = nullptr, int G = 1,
                    const ModelSpec* model = nullptr, int params_per_point = NPAR,
-                   const RenderSchedule* force_render = nullptr, bool masked = false);
+                   const RenderSchedule* force_render = nullptr, bool masked = false,
+                   float* grad_sky = nullptr);
   // Runs the plan stage by stage (a warm-up, then three timed runs) and returns
   // the fastest PSF + chi^2 stage, or the fastest render kernels, in milliseconds.
   hipError_t psf_ms(hipStream_t s, float* ms) const { return stage_ms(s, 3, ms); }
@@ -118,6 +120,8 @@ class BatchPlan {
   int K_ = 1;                     // points per image
   int G_ = 1;                     // images per log L (bands)
   const float* sky_ = nullptr;    // [n_images] flat sky surface brightness, or nullptr
+  float* grad_sky_ = nullptr;     // gradient plans with a sky: d log L / d sky per model, or nullptr
+  int64_t* d_goff_ = nullptr;     // gradient plans with K > 1: offset of each point's model image (g)
   int n_images_ = 0, n_models_ = 0;
   int* d_mpbase_ = nullptr;       // first partial-sum slot of each log L
   int* d_mntiles_ = nullptr;      // PSF tiles summed into each log L

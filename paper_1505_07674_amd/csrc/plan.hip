@@ -186,8 +186,8 @@ BatchPlan::~BatchPlan() {
 
 bool BatchPlan::matches(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
                         int n_points, const double* logl, const float* grad, int K, const float* sky, int G,
-                        const ModelSpec* model, bool masked) const {
-  if (masked != masked_) return false;
+                        const ModelSpec* model, bool masked, const float* grad_sky) const {
+  if (masked != masked_ || grad_sky != grad_sky_) return false;
   if (theta != theta_ || logl != logl_ || grad != grad_ || n_points != n_points_ || K != K_ || sky != sky_ ||
       G != G_ || (model != nullptr) != has_model_ ||
       (model && std::memcmp(model, &spec_, sizeof(ModelSpec)) != 0) ||
@@ -201,7 +201,7 @@ bool BatchPlan::matches(const lensed_system* systems, int n_systems, const float
 hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const float* theta, const int32_t* map,
                             int n_points, double* logl, TileCache& tiles, std::string& msg, float* grad,
                             const TileShape* force, int K, const float* sky, int G, const ModelSpec* model,
-                            int params_per_point, const RenderSchedule* force_render, bool masked) {
+                            int params_per_point, const RenderSchedule* force_render, bool masked, float* grad_sky) {
   systems_.assign(systems, systems + n_systems);
   map_.assign(map, map + n_points);
   theta_ = theta;
@@ -214,6 +214,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   if (model) spec_ = *model;
   params_per_point_ = params_per_point;
   sky_ = sky;
+  grad_sky_ = grad && sky ? grad_sky : nullptr;
   n_images_ = n_points / K;
   n_models_ = n_images_ / G;
 
@@ -396,6 +397,8 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
   off = align256(off + (g && has_model_ ? sizeof(double) * (size_t)gtot * params_per_point : 0));
   const size_t o_adjk = off; off = align256(off + (g ? sizeof(float) * 16 * psf_total : 0));
   const size_t o_gcorr = off; off = align256(off + (g17 ? sizeof(double) * (size_t)n_points * NPAR : 0));
+  const bool composite_grad = g && K > 1;   // a component's gradient reads its model's g
+  const size_t o_goff = off; off = align256(off + (composite_grad ? sizeof(int64_t) * n_points : 0));
   std::vector<size_t> o_units(n_systems), o_gsup(n_systems);
   for (int s = 0; s < n_systems; ++s) {
     o_units[s] = off;
@@ -444,6 +447,7 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
     d_gpart_ = g17 ? (float2*)(mem_ + o_gpart) : nullptr;
     d_mgpart_ = g17 ? nullptr : (double*)(mem_ + o_mgpart);
     d_gcorr_ = g17 ? (double*)(mem_ + o_gcorr) : nullptr;
+    d_goff_ = composite_grad ? (int64_t*)(mem_ + o_goff) : nullptr;
     grad_ntiles_ = desc[0].n_rtiles;
     for (int s = 0; s < n_systems; ++s) {
       desc[s].adjk = (float*)(mem_ + o_adjk) + 16 * psf_off[s];
@@ -481,6 +485,14 @@ hipError_t BatchPlan::build(const lensed_system* systems, int n_systems, const f
       (g && (e = hipMemcpy(d_gpbase_, gpbase.data(), sizeof(int) * n_points, hipMemcpyHostToDevice)) != hipSuccess)) {
     msg = "uploading work lists";
     return e;
+  }
+  if (d_goff_) {
+    std::vector<int64_t> goff(n_points);
+    for (int p = 0; p < n_points; ++p) goff[p] = loff[p - p % K];
+    if ((e = hipMemcpy(d_goff_, goff.data(), sizeof(int64_t) * n_points, hipMemcpyHostToDevice)) != hipSuccess) {
+      msg = "uploading the model image offsets";
+      return e;
+    }
   }
   if (masked_) {
     // pixels and tile sums a masked plan never computes stay zero for every run
@@ -555,9 +567,15 @@ hipError_t BatchPlan::enqueue(hipStream_t st, hipEvent_t* ev) const {
     WorkArgs wg = w;
     wg.items = d_gitems_;
     wg.n_items = n_gitems_;
+    wg.point_goff = d_goff_;
+    WorkArgs wa = wp;   // the adjoint PSF: the border pass skips a model's later components
+    wa.point_goff = d_goff_;
+    if (grad_sky_ && (e = launch_grad_sky(d_R_, d_loff_, d_point_sys_, d_sys_, K_, n_models_, grad_sky_, st)) !=
+        hipSuccess)
+      return e;
     // g = A^T rho overwrites the unconvolved images, which are no longer needed
     const lensed_system& s0 = systems_[0];
-    if ((e = launch_adjoint_psf(wp, d_R_, d_L_, n_pitems_, square_psf_, TW_, TH_, max_ph_, max_pw_, n_points_,
+    if ((e = launch_adjoint_psf(wa, d_R_, d_L_, n_pitems_, square_psf_, TW_, TH_, max_ph_, max_pw_, n_points_,
                                 s0.height, s0.width, st)) != hipSuccess)
       return e;
     if (ev && (e = hipEventRecord(ev[6], st)) != hipSuccess) return e;

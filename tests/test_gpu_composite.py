@@ -150,3 +150,85 @@ def test_multiband_log_likelihoods_add_over_bands():
         per_band.append(lensed.loglike_composite(torch.from_numpy(th[idx]).to(DEV), K, np.zeros(M, np.int32), [gs[b]],
                                                  sky=torch.from_numpy(sky[b::2].copy()).to(DEV)).cpu().numpy())
     assert np.allclose(ll, per_band[0] + per_band[1], rtol=1e-12, atol=0)
+
+
+def _composite_case(K, n_models, seed):
+    spec = small_spec(H=40, W=36, N=2)
+    truth = components(spec, K, seed=seed)
+    sky_true = 0.3
+    o = osys(spec)
+    model = oracle.render_composite(o, truth.astype(np.float64), sky=float(np.float32(sky_true)))
+    sigma = 0.01 * model.max()
+    rng = np.random.default_rng(seed)
+    data = (model + sigma * rng.standard_normal(model.shape)).astype(np.float32)
+    weight = ((rng.random(model.shape) < 0.85) / sigma ** 2).astype(np.float32)
+    pts = np.concatenate([components(spec, K, seed=seed + 1 + m) for m in range(n_models)])
+    skies = (sky_true + 0.2 * rng.standard_normal(n_models)).astype(np.float32)
+    return spec, data, weight, pts, skies
+
+
+def test_composite_gradient_with_one_component_is_the_17_parameter_gradient():
+    spec, data, weight, pts, _ = _composite_case(1, 6, seed=310)
+    g = gsys(spec, data, weight)
+    tp = torch.from_numpy(pts).to(DEV)
+    say("composite gradient, one component, no sky, against lensed_loglike_grad")
+    ll, gr, gs = lensed.loglike_composite_grad(tp, 1, g)
+    ll1, gr1 = lensed.loglike_grad(tp, g)
+    assert gs is None
+    assert np.array_equal(ll.cpu().numpy(), ll1.cpu().numpy())
+    assert np.array_equal(gr.cpu().numpy(), gr1.cpu().numpy())
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_composite_gradient_matches_the_oracle(K):
+    """Component k's gradient is the 17-parameter gradient of the oracle on the
+    data minus the other components and the sky (the residual is the same); the
+    sky's is a Richardson difference of the oracle's composite log L."""
+    n_models = 3
+    spec, data, weight, pts, skies = _composite_case(K, n_models, seed=320 + K)
+    g = gsys(spec, data, weight)
+    tp = torch.from_numpy(pts).to(DEV)
+    say(f"composite gradient, K = {K}, {n_models} models with a sky")
+    ll, gr, gs = lensed.loglike_composite_grad(tp, K, g, sky=torch.from_numpy(skies).to(DEV))
+    ll, gr, gs = ll.cpu().numpy(), gr.cpu().numpy().astype(np.float64), gs.cpu().numpy().astype(np.float64)
+    o = osys(spec, data.astype(np.float64), weight.astype(np.float64))
+    px2 = float(o.pixscale) ** 2
+    for m in range(n_models):
+        th = pts[m * K:(m + 1) * K].astype(np.float64)
+        sky = float(skies[m])
+        ref_ll = oracle.loglike_composite(o, th, sky=sky)
+        assert abs(ll[m] - ref_ll) <= loglike_tolerance(np.array([ref_ll]), weight)[0], (m, ll[m], ref_ll)
+        for k in range(K):
+            others = sum(oracle.render(o, th[j]) for j in range(K) if j != k) + sky * px2
+            ok = osys(spec, (data.astype(np.float64) - others).reshape(-1), weight.astype(np.float64))
+            _, ref_g = oracle.loglike_grad(ok, th[k])
+            got = gr[m * K + k]
+            rel = np.linalg.norm(got - ref_g) / np.linalg.norm(ref_g)
+            say(f"  model {m} component {k}: relative gradient error {rel:.2e}")
+            assert rel <= 1e-4, (m, k, rel)
+        h = 1e-3 * max(abs(sky), 1.0)
+        f = lambda s: oracle.loglike_composite(o, th, sky=s)
+        d1 = (f(sky + h) - f(sky - h)) / (2 * h)
+        d2 = (f(sky + h / 2) - f(sky - h / 2)) / h
+        ref_sky = (4 * d2 - d1) / 3
+        # bar: 1e-4 of the sum of the terms' magnitudes, px^2 sum |w (d - L*)|
+        resid = data.astype(np.float64) - oracle.render_composite(o, th, sky=sky)
+        scale = px2 * np.sum(np.abs(weight.astype(np.float64) * resid))
+        say(f"  model {m} sky: {gs[m]:.6g} vs {ref_sky:.6g} (scale {scale:.3g})")
+        assert abs(gs[m] - ref_sky) <= 1e-4 * scale, (m, gs[m], ref_sky, scale)
+
+
+def test_composite_gradient_arguments():
+    spec, data, weight, pts, skies = _composite_case(2, 2, seed=330)
+    g = gsys(spec, data, weight)
+    tp = torch.from_numpy(pts).to(DEV)
+    with pytest.raises(ValueError):
+        lensed.loglike_composite_grad(tp[:3], 2, g)
+    from paper_1505_07674_amd.binding import lib
+    import ctypes
+    rc = lib().lensed_loglike_composite_grad(lensed.default_context(0).handle, ctypes.byref(g.c_struct),
+                                             ctypes.c_void_p(tp.data_ptr()), 2,
+                                             ctypes.c_void_p(torch.from_numpy(skies).to(DEV).data_ptr()), 2,
+                                             ctypes.c_void_p(torch.empty(2, dtype=torch.float64, device=DEV).data_ptr()),
+                                             ctypes.c_void_p(torch.empty(4 * 17, device=DEV).data_ptr()), None, None)
+    assert rc == 1   # LENSED_INVALID_ARGUMENT: a sky without grad_sky
