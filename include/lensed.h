@@ -282,18 +282,18 @@ int lensed_loglike_model_batch(lensed_ctx* ctx, const lensed_system* systems, in
                                int n_points, double* logl, void* stream);
 
 /* log L and its gradient with respect to every parameter of a general model
- * with one lens plane (the paper's real-lens models, Sec. 5: several SIEs with
- * free centres, the shear, several Sersic components, the sky), for n_points
- * points of one system: the derivative of Eq. 17 through Eqs. 15, 14, 2, 1 and
- * 22, by the transposed PSF of lensed_loglike_grad and float64 partial
- * derivatives per subsample (forward-mode dual numbers, one component at a time).
+ * (the paper's real-lens models, Sec. 5: several SIEs with free centres, the
+ * shear, several Sersic components, the sky; lenses on several planes, Sec. 6),
+ * for n_points points of one system: the derivative of Eq. 17 through Eqs. 15,
+ * 14, 2, 1 and 22, by the transposed PSF of lensed_loglike_grad and float64
+ * partial derivatives per subsample (forward-mode dual numbers, one component
+ * at a time; with several planes the duals follow the ray plane by plane).
  *   theta  device float32 [n_points * P], P = lensed_model_nparams(model)
  *   logl   device float64 [n_points], written
  *   grad   device float32 [n_points * P], written (d log L / d theta, in the
  *          parameter order of the model)
  * Like lensed_loglike_grad, each call renders and differentiates only the
- * pixels within the PSF box of a weighted pixel, from the weights as they are.
- * A model with n_planes > 1 is rejected with LENSED_INVALID_ARGUMENT. */
+ * pixels within the PSF box of a weighted pixel, from the weights as they are. */
 int lensed_loglike_model_grad(lensed_ctx* ctx, const lensed_system* sys, const lensed_model* model,
                               const float* theta, int n_points, double* logl, float* grad, void* stream);
 

@@ -886,8 +886,6 @@ extern "C" int lensed_loglike_model_grad(lensed_ctx* c, const lensed_system* sys
   ModelSpec spec;
   int rc = model_spec(c, model, spec);
   if (rc) return rc;
-  if (spec.n_planes > 1)
-    return set_err(c, LENSED_INVALID_ARGUMENT, "the adjoint of general models covers one lens plane only");
   if (n_points < 0) return set_err(c, LENSED_INVALID_ARGUMENT, "n_points must be >= 0");
   if (n_points == 0) return LENSED_OK;
   if ((int64_t)n_points * spec_params(spec) > INT32_MAX)

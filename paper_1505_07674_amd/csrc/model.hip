@@ -357,6 +357,118 @@ __device__ inline Dl<7> sersic_d(const ModelConst& m, int j, double px, double p
   return Ie * dexp(-(b * (t + -1.0)));
 }
 
+// ---- Several lens planes: the ray's positions in dual numbers --------------
+// With lenses on several planes a deflector's parameters move the rays of every
+// later plane, so the pass carries derivatives through the whole chain: the
+// position on plane j is x - sum_{i<j} beta_ij alpha_i(x_i) in dual numbers
+// whose variables are the pass's own parameters (those of SIE comp, of Sersic
+// comp, or the shear), and every deflector and Sersic is evaluated at dual
+// positions.
+
+// SIE k at the dual position (x, y); own: its (x_c, y_c, theta_E, q, phi) are
+// the variables 0..4.
+__device__ inline void sie_alpha_dual(const ModelConst& m, int k, const Dl<7>& x, const Dl<7>& y, bool own,
+                                      Dl<7>& ax, Dl<7>& ay) {
+  const double* s = m.sie[k];
+  Dl<7> xc = dconst<7>(s[0]), yc = dconst<7>(s[1]), c = dconst<7>(s[2]), sn = dconst<7>(s[3]);
+  Dl<7> te = dconst<7>(s[7]), q = dconst<7>(s[8]);
+  if (own) {
+    xc.d[0] = 1.0;
+    yc.d[1] = 1.0;
+    te.d[2] = 1.0;
+    q.d[3] = 1.0;
+    c.d[4] = -s[3];
+    sn.d[4] = s[2];
+  }
+  const Dl<7> dx = x - xc, dy = y - yc;
+  const Dl<7> xp = c * dx + sn * dy, yp = c * dy - sn * dx;
+  const Dl<7> psi2 = q * q * xp * xp + yp * yp;
+  if (!(psi2.v > 0.0)) {   // the centre itself: no deflection
+    ax = ay = dconst<7>(0.0);
+    return;
+  }
+  const Dl<7> psi = dsqrt(psi2);
+  const Dl<7> ss = -(q * q) + 1.0;
+  const Dl<7> f = te * dsqrt(q);
+  const Dl<7> a1 = f * atan_over_root<false>(ss, xp / psi), a2 = f * atan_over_root<true>(ss, yp / psi);
+  ax = c * a1 - sn * a2;
+  ay = sn * a1 + c * a2;
+}
+
+// The external shear's deflection at (x, y) added to (ax, ay); own: (gamma,
+// phi_gamma) are the variables 0, 1.
+__device__ inline void shear_alpha_dual(const ModelConst& m, const Dl<7>& x, const Dl<7>& y, bool own, Dl<7>& ax,
+                                        Dl<7>& ay) {
+  Dl<7> gam = dconst<7>(m.gam), c2 = dconst<7>(m.c2g), s2 = dconst<7>(m.s2g);
+  if (own) {
+    gam.d[0] = 1.0;
+    c2.d[1] = -2.0 * m.s2g;
+    s2.d[1] = 2.0 * m.c2g;
+  }
+  const Dl<7> g1 = gam * c2, g2 = gam * s2;
+  ax = ax + g1 * x + g2 * y;
+  ay = ay + g2 * x - g1 * y;
+}
+
+// Sersic j at the dual position (px, py); own: its (x, y, I_e, R_e, n, q, phi)
+// are the variables 0..6.
+__device__ inline Dl<7> sersic_at_dual(const ModelConst& m, int j, const Dl<7>& px, const Dl<7>& py,
+                                               bool own) {
+  const double* s = m.ser[j];
+  Dl<7> x0 = dconst<7>(s[0]), y0 = dconst<7>(s[1]), Ie = dconst<7>(s[9]), Re = dconst<7>(1.0 / s[6]);
+  Dl<7> n = dconst<7>(1.0 / s[7]), q = dconst<7>(s[4]), c = dconst<7>(s[2]), sn = dconst<7>(s[3]);
+  Dl<7> b = dconst<7>(s[8]);
+  if (own) {
+    x0.d[0] = 1.0;
+    y0.d[1] = 1.0;
+    Ie.d[2] = 1.0;
+    Re.d[3] = 1.0;
+    n.d[4] = 1.0;
+    b.d[4] = s[10];
+    q.d[5] = 1.0;
+    c.d[6] = -s[3];
+    sn.d[6] = s[2];
+  }
+  const Dl<7> dx = px - x0, dy = py - y0;
+  const Dl<7> xp = c * dx + sn * dy, yp = c * dy - sn * dx;
+  const Dl<7> R2 = q * xp * xp + yp * yp / q;
+  const Dl<7> t = R2.v > 0.0 ? dexp(dlog(R2 / (Re * Re)) * (dconst<7>(0.5) / n)) : dconst<7>(0.0);
+  return Ie * dexp(-(b * (t + -1.0)));
+}
+
+// I at the subsample (x, y) of a model with spec.n_planes > 1 (the sky left
+// out), with its derivatives in the pass's parameters (kind 0: SIE comp, 1:
+// Sersic comp, 2: the shear).
+__device__ Dl<7> planes_dual(const ModelConst& m, const ModelSpec& spec, double x, double y, int kind, int comp) {
+  const int P = spec.n_planes;
+  Dl<7> ax[MAX_PLANES], ay[MAX_PLANES];
+  Dl<7> I = dconst<7>(0.0);
+  for (int j = 0; j <= P; ++j) {
+    Dl<7> px = dconst<7>(x), py = dconst<7>(y);
+    for (int i = 0; i < j; ++i) {
+      const double b = j == P ? 1.0 : spec.beta[i][j];
+      px = px - ax[i] * b;
+      py = py - ay[i] * b;
+    }
+    for (int k = 0; k < m.n_sersic; ++k)
+      if (m.plane[k] == j) I = I + sersic_at_dual(m, k, px, py, kind == 1 && comp == k);
+    if (j < P) {
+      Dl<7> dx = dconst<7>(0.0), dy = dconst<7>(0.0);
+      for (int k = 0; k < m.n_sie; ++k)
+        if (spec.sie_plane[k] == j) {
+          Dl<7> a, b;
+          sie_alpha_dual(m, k, px, py, kind == 0 && comp == k, a, b);
+          dx = dx + a;
+          dy = dy + b;
+        }
+      if (j == 0 && spec.shear) shear_alpha_dual(m, px, py, kind == 2, dx, dy);
+      ax[j] = dx;
+      ay[j] = dy;
+    }
+  }
+  return I;
+}
+
 // beta at (x, y) (every SIE, the shear), with SIE `skip` left out, and G.
 __device__ inline void source_side(const ModelConst& m, double x, double y, int skip, double& ax, double& ay) {
   ax = m.g1 * x + m.g2 * y;
@@ -375,6 +487,8 @@ __device__ inline void lensed_gradient(const ModelConst& m, double bx, double by
     }
 }
 
+// PLANES: the model has several lens planes (planes_dual per subsample).
+template <bool PLANES>
 __global__ __launch_bounds__(RENDER_BLOCK) void model_grad_kernel(WorkArgs w, ModelSpec spec,
                                                                    const ModelConst* __restrict__ mcs,
                                                                    const float* __restrict__ G,
@@ -427,7 +541,14 @@ __global__ __launch_bounds__(RENDER_BLOCK) void model_grad_kernel(WorkArgs w, Mo
         const double ox = R ? R->xd[kx] : ((double)kx + 0.5) / N - 0.5;
         const double wq = R ? (double)R->w[kx] * (double)R->w[ky] : 1.0;
         const double x = cx + (ux + ox) * d;
-        if (kind == 0) {
+        if (PLANES) {
+          if (kind < 2 || spec.shear) {
+            const Dl<7> I = planes_dual(m, spec, x, y, kind, comp);
+            const int nd = kind == 0 ? 5 : (kind == 1 ? 7 : 2);
+            for (int i = 0; i < nd; ++i) acc[i] += wq * I.d[i];
+          }
+          if (kind == 2 && spec.sky) acc[spec.shear ? 2 : 0] += wq;
+        } else if (kind == 0) {
           double ax, ay, Gx, Gy;
           source_side(m, x, y, comp, ax, ay);
           Dl<5> akx, aky;
@@ -514,8 +635,12 @@ hipError_t launch_model_grad(const WorkArgs& w, const ModelSpec& spec, const Mod
   if (n_blocks <= 0) return hipSuccess;
   const int passes = spec.n_sie + spec.n_sersic + ((spec.shear || spec.sky) ? 1 : 0);
   return for_item_parts(w, n_blocks, [&](const WorkArgs& part, int n) {
-    hipLaunchKernelGGL(model_grad_kernel, dim3(n, passes), dim3(RENDER_BLOCK), 0, stream, part, spec, mcs, G, gpbase,
-                       gpart, P);
+    if (spec.n_planes > 1)
+      hipLaunchKernelGGL(model_grad_kernel<true>, dim3(n, passes), dim3(RENDER_BLOCK), 0, stream, part, spec, mcs, G,
+                         gpbase, gpart, P);
+    else
+      hipLaunchKernelGGL(model_grad_kernel<false>, dim3(n, passes), dim3(RENDER_BLOCK), 0, stream, part, spec, mcs, G,
+                         gpbase, gpart, P);
     return hipGetLastError();
   });
 }
