@@ -244,9 +244,10 @@ int lensed_render_error(lensed_ctx* ctx, const lensed_system* sys, const float* 
  * A Sersic on plane j is evaluated at x_j. With P = 1 this is the one-plane
  * model above, and sie_plane and beta are not read.
  *
- * These models are evaluated in float64 and rounded once per pixel (the PSF
- * and chi^2 stages are the common ones); lensed_loglike_model_grad gives the
- * adjoint of the models with one lens plane. */
+ * These models trace rays in float64 (the Sersic profiles take the fractional
+ * parts of their powers of two in float32) and round once per pixel (the PSF
+ * and chi^2 stages are the common ones); lensed_loglike_model_grad gives their
+ * adjoint, with one or several lens planes. */
 #define LENSED_LIGHT_FOREGROUND 0
 #define LENSED_LIGHT_LENSED 1
 typedef struct {
