@@ -675,3 +675,19 @@ class LogLikeFn(torch.autograd.Function):
     def backward(ctx_, grad_out: torch.Tensor):
         (g,) = ctx_.saved_tensors
         return (grad_out.to(g.dtype)[:, None] * g), None
+
+
+class LogLikeModelFn(torch.autograd.Function):
+    """log L(theta) for [P, n_params] points of a general model on one system,
+    with the library's adjoint (lensed_loglike_model_grad) as backward."""
+
+    @staticmethod
+    def forward(ctx_, theta: torch.Tensor, system: System, model: Model):
+        ll, g = loglike_model_grad(theta.detach(), system, model)
+        ctx_.save_for_backward(g)
+        return ll
+
+    @staticmethod
+    def backward(ctx_, grad_out: torch.Tensor):
+        (g,) = ctx_.saved_tensors
+        return (grad_out.to(g.dtype)[:, None] * g), None, None

@@ -152,3 +152,18 @@ def test_three_plane_gradient_matches_oracle_differences(rule):
         say(f"  point {i}: relative error {rel:.2e} (largest at parameter {worst}: {gg[i][worst]:.6g} vs "
             f"{ref[worst]:.6g})")
         assert rel <= 1e-4, (i, rel, gg[i], ref)
+
+
+def test_autograd_function_backward_is_the_adjoint():
+    """LogLikeModelFn: torch's backward of sum(c * log L) is c times the adjoint's gradient."""
+    spec = small_spec(H=40, W=36, N=2)
+    gm, om = models(2, PLANES_41, sky=True)
+    truth = companion_points(1, seed=71)[0]
+    data, weight = mock(spec, om, truth)
+    g = gsys(spec, data, weight)
+    pts = torch.from_numpy(companion_points(3, seed=79)).to(DEV).requires_grad_(True)
+    coef = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64, device=DEV)
+    ll = lensed.LogLikeModelFn.apply(pts, g, gm)
+    (coef * ll).sum().backward()
+    _, ref = lensed.loglike_model_grad(pts.detach(), g, gm)
+    assert torch.equal(pts.grad, coef.to(torch.float32)[:, None] * ref)
