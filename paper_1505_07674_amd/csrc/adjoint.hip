@@ -746,35 +746,46 @@ __global__ __launch_bounds__(256) void grad_support_cols_kernel(const SysDesc* _
 // Compaction of the flags f[0 .. n) of units of `ppt` pixels (a unit is
 // flagged if any of its pixels is) into out[], the first pixel of each flagged
 // unit in order; returns their number to every thread. Each thread counts a
-// chunk of consecutive units, a block scan gives each chunk its first slot.
+// chunk of consecutive units; the chunks' first slots come from a wave-level
+// prefix sum (shuffles) and a scan of the 16 wave totals in LDS.
 constexpr int GSUP_THREADS = 1024;
-__device__ int compact_units(const unsigned char* f, int npix, int ppt, int* out, int* scan) {
+__device__ int compact_units(const unsigned char* f, int npix, int ppt, int* out, int* wsum) {
   const int n = npix / ppt;
   const int chunk = (n + GSUP_THREADS - 1) / GSUP_THREADS;
-  const int t = (int)threadIdx.x;
+  const int t = (int)threadIdx.x, lane = t & 63, wv = t >> 6;
   const int b = min(t * chunk, n), e = min(b + chunk, n);
   auto flag = [&](int u) { return ppt == 1 ? f[u] != 0 : (f[2 * u] | f[2 * u + 1]) != 0; };
   int cnt = 0;
+#pragma unroll 4
   for (int u = b; u < e; ++u) cnt += flag(u);
-  scan[t] = cnt;
-  __syncthreads();
-  for (int off = 1; off < GSUP_THREADS; off <<= 1) {   // inclusive Hillis-Steele scan
-    const int v = t >= off ? scan[t - off] : 0;
-    __syncthreads();
-    scan[t] += v;
-    __syncthreads();
+  int incl = cnt;   // inclusive prefix over the wave
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
   }
-  int pos = scan[t] - cnt;
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  if (t == 0) {   // exclusive prefix of the wave totals, and the total in wsum[16]
+    int acc = 0;
+    for (int k = 0; k < GSUP_THREADS / 64; ++k) {
+      const int v = wsum[k];
+      wsum[k] = acc;
+      acc += v;
+    }
+    wsum[GSUP_THREADS / 64] = acc;
+  }
+  __syncthreads();
+  int pos = wsum[wv] + incl - cnt;
   for (int u = b; u < e; ++u)
     if (flag(u)) out[pos++] = u * ppt;
-  const int total = scan[GSUP_THREADS - 1];
-  __syncthreads();   // scan[] is reused by the next call
+  const int total = wsum[GSUP_THREADS / 64];
+  __syncthreads();   // wsum[] is reused by the next call
   return total;
 }
 
 // One block per system: the support's pixels, and with uact its render units.
 __global__ __launch_bounds__(GSUP_THREADS) void grad_support_compact_kernel(SysDesc* __restrict__ sys) {
-  __shared__ int scan[GSUP_THREADS];
+  __shared__ int scan[GSUP_THREADS / 64 + 1];
   SysDesc& sd = sys[blockIdx.x];
   if (!sd.gsup) return;   // uniform over the block
   const int npix = sd.H * sd.W;
